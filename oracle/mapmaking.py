@@ -1,0 +1,473 @@
+"""Oracle implementation (FP64, numpy).  Test infrastructure only.
+
+Notation follows the paper: d = P s + n (Eqs. probl, datamod); a polarised
+sample is d_t = I + Q cos 2phi_t + U sin 2phi_t + n_t (Eq. datamodel); the GLS
+estimate solves A x = b with A = P^T W P, b = P^T W d (Eqs. estimator,
+linearsystem); here W = N^-1 is a banded Toeplitz matrix per stationary
+interval.  Preconditioners: M_BD (Eq. mbd) and M_2l (Eq. m2l) with E = Z^T A Z.
+The deflation space comes from Ritz vectors of an Arnoldi run on B = M_BD A
+(Sect. 5 and Appendix A, Alg. arnoldi, Eqs. factoriz and ritz).  The solver is
+PCG (Eq. pcg) with the relative residual of the metric in Sect. 6.1.
+
+Readings where the paper is silent or garbled (each is listed in the design doc):
+  * residual: the stop test and the reported residual use the
+    unpreconditioned ||b - A x|| / ||b|| (Eq. residuals mixes in M_P);
+  * N^-1 is block diagonal over intervals, each block the principal section of
+    the banded Toeplitz matrix (no wrap-around, nothing couples intervals);
+  * flagged samples are masked out of both P and d (W = M N^-1 M);
+  * M_BD uses the zero-lag coefficient c_0 of the sample's interval as
+    diag(N^-1);
+  * PCG uses beta = rho_new / rho for both preconditioners (M_2l is not
+    symmetric; Sect. 3.2);
+  * Arnoldi starts from r_0 = M_BD b (x_0 = 0), orthogonalises by classical
+    Gram-Schmidt applied twice, stops when h_{j+1,j} <= eps_Arn or j = m_max;
+  * Ritz values are ordered by real part; a complex pair is never split; the
+    real and imaginary parts of a pair's vector both enter Z.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = [
+    "Pointing", "Noise", "OracleError", "pointing_build", "apply_P", "apply_PT",
+    "noise_build", "noise_apply_direct", "noise_apply_fft", "noise_apply",
+    "apply_A", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
+    "m2l_apply", "arnoldi", "ritz_select", "defl_build", "pcg", "SolveInfo",
+    "dense_P", "dense_Ninv",
+]
+
+
+COARSE_PIVOT_TOL = 1e-13
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: str, msg: str):
+        super().__init__(f"{code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# O1  pointing  (Eqs. probl, datamodel; observed-pixel selection, Sect. 4)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Pointing:
+    n_samp: int
+    n_pix_total: int
+    hits: np.ndarray      # int32[n_pix_total] samples per global pixel (unflagged)
+    obs_pix: np.ndarray   # int32[n_obs] observed global ids, ascending
+    cidx: np.ndarray      # int32[n_pix_total] compact index or -1
+    j: np.ndarray         # int32[n_samp] compact pixel per sample, -1 = flagged
+    perm: np.ndarray      # int32[n_valid] samples sorted by (j, t)
+    off: np.ndarray       # int32[n_obs+1] segment offsets into perm
+    cos2: np.ndarray      # f64[n_samp]
+    sin2: np.ndarray      # f64[n_samp]
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_pix.shape[0])
+
+    @property
+    def n(self) -> int:
+        return 3 * self.n_obs
+
+
+def pointing_build(pix, psi, n_pix_total: int, min_hits: int = 3) -> Pointing:
+    """P has three non-zeros per row, (1, cos 2phi_t, sin 2phi_t) at the
+    sample's pixel (Eq. datamodel).  Pixels seen fewer than min_hits times are
+    dropped and their samples flagged (the paper discards samples of pixels
+    observed without enough redundancy, Sect. 4)."""
+    pix = np.asarray(pix, dtype=np.int32)
+    psi = np.asarray(psi, dtype=np.float64)
+    if pix.shape != psi.shape:
+        raise OracleError("INVALID", "pix and psi differ in length")
+    if np.any(pix < -1) or np.any(pix >= n_pix_total):
+        raise OracleError("INVALID", "pixel index out of range")
+    valid = pix >= 0
+    hits = np.bincount(pix[valid], minlength=n_pix_total).astype(np.int32)
+    obs_pix = np.nonzero(hits >= min_hits)[0].astype(np.int32)
+    cidx = np.full(n_pix_total, -1, dtype=np.int32)
+    cidx[obs_pix] = np.arange(obs_pix.shape[0], dtype=np.int32)
+    j = np.full(pix.shape[0], -1, dtype=np.int32)
+    j[valid] = cidx[pix[valid]]
+    t_keep = np.nonzero(j >= 0)[0]
+    perm = t_keep[np.argsort(j[t_keep], kind="stable")].astype(np.int32)
+    off = np.zeros(obs_pix.shape[0] + 1, dtype=np.int32)
+    off[1:] = np.cumsum(hits[obs_pix])
+    return Pointing(n_samp=pix.shape[0], n_pix_total=n_pix_total, hits=hits,
+                    obs_pix=obs_pix, cidx=cidx, j=j, perm=perm, off=off,
+                    cos2=np.cos(2.0 * psi), sin2=np.sin(2.0 * psi))
+
+
+def apply_P(pt: Pointing, x) -> np.ndarray:
+    """y_t = I_j + Q_j cos 2phi_t + U_j sin 2phi_t at j = j_t; 0 if flagged
+    (Eq. datamodel).  x is the map, [n_obs][3] interleaved."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    y = np.zeros(pt.n_samp)
+    m = pt.j >= 0
+    jj = pt.j[m]
+    y[m] = x[jj, 0] + pt.cos2[m] * x[jj, 1] + pt.sin2[m] * x[jj, 2]
+    return y
+
+
+def apply_PT(pt: Pointing, z) -> np.ndarray:
+    """(P^T z)_{j,a} = sum over samples t with j_t = j of w_t[a] z_t, with
+    w_t = (1, cos 2phi_t, sin 2phi_t); samples summed in time order."""
+    z = np.asarray(z, dtype=np.float64)
+    m = pt.j >= 0
+    jj = pt.j[m]
+    out = np.empty((pt.n_obs, 3))
+    out[:, 0] = np.bincount(jj, weights=z[m], minlength=pt.n_obs)
+    out[:, 1] = np.bincount(jj, weights=pt.cos2[m] * z[m], minlength=pt.n_obs)
+    out[:, 2] = np.bincount(jj, weights=pt.sin2[m] * z[m], minlength=pt.n_obs)
+    return out.reshape(-1)
+
+
+def dense_P(pt: Pointing) -> np.ndarray:
+    """The N_t x 3 n_obs pointing matrix written out (tiny inputs only)."""
+    P = np.zeros((pt.n_samp, pt.n))
+    for t in range(pt.n_samp):
+        j = pt.j[t]
+        if j >= 0:
+            P[t, 3 * j] = 1.0
+            P[t, 3 * j + 1] = pt.cos2[t]
+            P[t, 3 * j + 2] = pt.sin2[t]
+    return P
+
+
+# ---------------------------------------------------------------------------
+# O2  N^-1: banded Toeplitz per stationary interval (W = N^-1, Sect. 2)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Noise:
+    interval_start: np.ndarray  # int64[n_int+1]
+    filter_id: np.ndarray       # int32[n_int]
+    band: np.ndarray            # f64[n_filters, half_bw+1]
+    half_bw: int
+
+    @property
+    def n_samp(self) -> int:
+        return int(self.interval_start[-1])
+
+
+def noise_build(interval_start, filter_id, band, half_bw: int) -> Noise:
+    istart = np.asarray(interval_start, dtype=np.int64)
+    fid = np.asarray(filter_id, dtype=np.int32)
+    band = np.asarray(band, dtype=np.float64).reshape(-1, half_bw + 1)
+    if istart[0] != 0 or np.any(np.diff(istart) <= 0):
+        raise OracleError("INVALID", "intervals must tile [0, n_samp)")
+    if np.any(np.diff(istart) <= 2 * half_bw):
+        raise OracleError("INVALID", "half bandwidth must be < L_min/2")
+    if np.any(fid < 0) or np.any(fid >= band.shape[0]):
+        raise OracleError("INVALID", "filter id out of range")
+    return Noise(istart, fid, band, half_bw)
+
+
+def noise_apply_direct(nz: Noise, y) -> np.ndarray:
+    """z_t = sum_{u in I(t), |t-u| <= lambda} c^f_{|t-u|} y_u: the definition,
+    one lag at a time, truncated at interval edges."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.empty_like(y)
+    lam = nz.half_bw
+    for i in range(nz.filter_id.shape[0]):
+        a, b = int(nz.interval_start[i]), int(nz.interval_start[i + 1])
+        c = nz.band[nz.filter_id[i]]
+        yi = y[a:b]
+        zi = c[0] * yi
+        for d in range(1, min(lam, b - a - 1) + 1):
+            zi[d:] += c[d] * yi[:-d]
+            zi[:-d] += c[d] * yi[d:]
+        z[a:b] = zi
+    return z
+
+
+def noise_apply_fft(nz: Noise, y) -> np.ndarray:
+    """Same operator by zero-padded FFT convolution: per interval of length L,
+    a circular convolution of length n_f >= L + lambda with the symmetric
+    kernel reproduces the truncated band exactly (no wrap-around reaches an
+    output).  numpy's FFT is the library step."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.empty_like(y)
+    lam = nz.half_bw
+    cache = {}
+    for i in range(nz.filter_id.shape[0]):
+        a, b = int(nz.interval_start[i]), int(nz.interval_start[i + 1])
+        L = b - a
+        nf = 1 << int(np.ceil(np.log2(L + lam)))
+        key = (nf, int(nz.filter_id[i]))
+        if key not in cache:
+            c = nz.band[nz.filter_id[i]]
+            h = np.zeros(nf)
+            h[0] = c[0]
+            h[1:lam + 1] = c[1:]
+            h[nf - lam:] = c[1:][::-1]
+            cache[key] = np.fft.rfft(h)
+        yp = np.zeros(nf)
+        yp[:L] = y[a:b]
+        z[a:b] = np.fft.irfft(np.fft.rfft(yp) * cache[key], n=nf)[:L]
+    return z
+
+
+def noise_apply(nz: Noise, y, method: str = "direct") -> np.ndarray:
+    return noise_apply_fft(nz, y) if method == "fft" else noise_apply_direct(nz, y)
+
+
+def dense_Ninv(nz: Noise) -> np.ndarray:
+    """N^-1 written out as a block-diagonal matrix of Toeplitz sections."""
+    n = nz.n_samp
+    N = np.zeros((n, n))
+    for i in range(nz.filter_id.shape[0]):
+        a, b = int(nz.interval_start[i]), int(nz.interval_start[i + 1])
+        c = nz.band[nz.filter_id[i]]
+        for t in range(a, b):
+            for u in range(max(a, t - nz.half_bw), min(b, t + nz.half_bw + 1)):
+                N[t, u] = c[abs(t - u)]
+    return N
+
+
+# ---------------------------------------------------------------------------
+# O5/O6  A x = P^T N^-1 P x ;  b = P^T N^-1 (mask * d)   (Eq. linearsystem)
+# ---------------------------------------------------------------------------
+
+def apply_A(pt: Pointing, nz: Noise, x, method: str = "direct") -> np.ndarray:
+    return apply_PT(pt, noise_apply(nz, apply_P(pt, x), method))
+
+
+def rhs(pt: Pointing, nz: Noise, d, method: str = "direct") -> np.ndarray:
+    """Samples of unobserved or off-patch pixels are zeroed before weighting,
+    so W = M N^-1 M with M the 0/1 mask (keeps W semi-definite, P M = P)."""
+    d = np.where(pt.j >= 0, np.asarray(d, dtype=np.float64), 0.0)
+    return apply_PT(pt, noise_apply(nz, d, method))
+
+
+# ---------------------------------------------------------------------------
+# O7  M_BD^-1 = P^T diag(N^-1) P   (Eq. mbd)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Mbd:
+    blocks: np.ndarray      # f64[n_obs, 3, 3]  B_j
+    inv: np.ndarray         # f64[n_obs, 3, 3]  B_j^-1
+    rcond_min: float
+
+
+def _diag_weight(pt: Pointing, nz: Noise) -> np.ndarray:
+    """diag(N^-1)_t = c_0 of the sample's interval filter."""
+    c0 = np.empty(pt.n_samp)
+    for i in range(nz.filter_id.shape[0]):
+        a, b = int(nz.interval_start[i]), int(nz.interval_start[i + 1])
+        c0[a:b] = nz.band[nz.filter_id[i], 0]
+    return c0
+
+
+def mbd_build(pt: Pointing, nz: Noise, rcond_tol: float = 1e-12) -> Mbd:
+    """B_j = sum_{t: j_t = j} c_0 w_t w_t^T with w_t = (1, cos 2phi, sin 2phi);
+    M_BD is the block-diagonal matrix of the B_j^-1."""
+    c0 = _diag_weight(pt, nz)
+    m = pt.j >= 0
+    jj = pt.j[m]
+    w = np.stack([np.ones(pt.n_samp), pt.cos2, pt.sin2], axis=1)[m]
+    cw = c0[m]
+    B = np.zeros((pt.n_obs, 3, 3))
+    for a in range(3):
+        for b in range(3):
+            B[:, a, b] = np.bincount(jj, weights=cw * w[:, a] * w[:, b], minlength=pt.n_obs)
+    try:
+        np.linalg.cholesky(B)
+    except np.linalg.LinAlgError as e:
+        raise OracleError("SINGULAR_BLOCK", "a 3x3 block is not positive definite") from e
+    inv = np.linalg.inv(B)
+    rc = 1.0 / (np.abs(B).sum(axis=1).max(axis=1) * np.abs(inv).sum(axis=1).max(axis=1))
+    if pt.n_obs and rc.min() < rcond_tol:
+        raise OracleError("SINGULAR_BLOCK", f"3x3 block rcond {rc.min():.3e}")
+    return Mbd(B, inv, float(rc.min()) if pt.n_obs else 1.0)
+
+
+def mbd_apply(M: Mbd, v) -> np.ndarray:
+    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    return np.einsum("jab,jb->ja", M.inv, v).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# O8  M_2l = M_BD (1 - A Z E^-1 Z^T) + Z E^-1 Z^T,  E = Z^T A Z   (Eq. m2l)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class M2l:
+    mbd: Mbd
+    Z: np.ndarray      # f64[n, k]
+    AZ: np.ndarray     # f64[n, k]
+    E: np.ndarray      # f64[k, k] symmetrised
+    L: np.ndarray      # Cholesky factor of E
+
+
+def m2l_from_Z(pt: Pointing, nz: Noise, mbd: Mbd, Z, method: str = "direct") -> M2l:
+    Z = np.asarray(Z, dtype=np.float64).reshape(pt.n, -1)
+    k = Z.shape[1]
+    AZ = np.empty_like(Z)
+    for c in range(k):
+        AZ[:, c] = apply_A(pt, nz, Z[:, c], method)
+    E = Z.T @ AZ
+    E = 0.5 * (E + E.T)
+    # E must be SPD (Sect. 3.2).  A pivot below 1e-13 of the largest diagonal
+    # entry is treated as a failure: E is numerically singular (Z rank deficient).
+    try:
+        L = np.linalg.cholesky(E) if k else np.zeros((0, 0))
+    except np.linalg.LinAlgError as e:
+        raise OracleError("COARSE_NOT_SPD", "E = Z^T A Z is not positive definite") from e
+    if k and np.min(np.diag(L)) ** 2 <= COARSE_PIVOT_TOL * np.max(np.diag(E)):
+        raise OracleError("COARSE_NOT_SPD", "E = Z^T A Z is numerically singular")
+    return M2l(mbd, Z, AZ, E, L)
+
+
+def m2l_apply(M: M2l, v) -> np.ndarray:
+    """c = E^-1 Z^T v ; out = M_BD (v - A Z c) + Z c."""
+    v = np.asarray(v, dtype=np.float64)
+    if M.Z.shape[1] == 0:
+        return mbd_apply(M.mbd, v)
+    g = M.Z.T @ v
+    c = np.linalg.solve(M.L.T, np.linalg.solve(M.L, g))
+    return mbd_apply(M.mbd, v - M.AZ @ c) + M.Z @ c
+
+
+# ---------------------------------------------------------------------------
+# O9  Arnoldi on B = M_BD A (Alg. arnoldi), Ritz pairs (Eq. ritz), Z
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ArnoldiResult:
+    W: np.ndarray      # f64[n, m+1] orthonormal Krylov basis (last column w_{m+1})
+    H: np.ndarray      # f64[m+1, m] Hessenberg matrix incl. h_{m+1,m}
+    m: int
+    h_last: float
+
+
+def arnoldi(apply_B, r0, m_max: int, eps_arn: float, reorth: bool = True) -> ArnoldiResult:
+    """w_1 = r0/||r0||; for j: v = B w_j; h_ij = (v, w_i) for all i <= j from
+    the same v (classical Gram-Schmidt); v -= sum h_ij w_i; with reorth the
+    projection is repeated once and added into h (CGS2); h_{j+1,j} = ||v||;
+    stop when h_{j+1,j} <= eps_arn, else w_{j+1} = v / h_{j+1,j}."""
+    n = r0.shape[0]
+    W = np.zeros((n, m_max + 1))
+    H = np.zeros((m_max + 1, m_max))
+    W[:, 0] = r0 / np.linalg.norm(r0)
+    m = 0
+    h_last = 0.0
+    for j in range(m_max):
+        v = apply_B(W[:, j])
+        h = W[:, :j + 1].T @ v
+        v = v - W[:, :j + 1] @ h
+        if reorth:
+            h2 = W[:, :j + 1].T @ v
+            v = v - W[:, :j + 1] @ h2
+            h = h + h2
+        H[:j + 1, j] = h
+        hn = np.linalg.norm(v)
+        H[j + 1, j] = hn
+        m = j + 1
+        h_last = hn
+        if hn <= eps_arn:
+            break
+        W[:, j + 1] = v / hn
+    return ArnoldiResult(W[:, :m + 1], H[:m + 1, :m], m, h_last)
+
+
+def ritz_select(H_m: np.ndarray, k: int, eps_lambda: float = 0.0):
+    """Eigenpairs of the m x m Hessenberg matrix (numpy's LAPACK eig), ordered
+    by real part ascending.  Keep the k smallest (k+1 if that would split a
+    conjugate pair) or, with eps_lambda > 0, all with Re(theta) < eps_lambda.
+    Returns (theta_sorted, Y) with Y real: a complex pair contributes the real
+    and imaginary parts of one of its vectors."""
+    theta, Yc = np.linalg.eig(H_m)
+    order = np.lexsort((theta.imag, theta.real))
+    theta, Yc = theta[order], Yc[:, order]
+    m = theta.shape[0]
+    if eps_lambda > 0:
+        keep = int(np.sum(theta.real < eps_lambda))
+    else:
+        keep = min(k, m)
+    if 0 < keep < m and theta[keep - 1].imag != 0 and np.conj(theta[keep - 1]) == theta[keep]:
+        keep += 1
+    cols = []
+    i = 0
+    while i < keep:
+        if theta[i].imag != 0 and i + 1 < m and np.conj(theta[i]) == theta[i + 1]:
+            cols.append(Yc[:, i].real)
+            cols.append(Yc[:, i].imag)
+            i += 2
+        else:
+            cols.append(Yc[:, i].real)
+            i += 1
+    Y = np.stack(cols, axis=1) if cols else np.zeros((m, 0))
+    return theta, Y
+
+
+def defl_build(pt: Pointing, nz: Noise, mbd: Mbd, b_seed, k: int, eps_arn: float,
+               m_max: int, eps_lambda: float = 0.0, method: str = "direct",
+               reorth: bool = True):
+    """Deflation space from Ritz vectors of B = M_BD A (Sect. 5): Arnoldi from
+    r_0 = M_BD b_seed, Ritz selection, V = W_m Y, Z = Q of a Householder QR
+    of V (numpy's QR).  Returns (M2l, ArnoldiResult, theta)."""
+    r0 = mbd_apply(mbd, b_seed)
+    res = arnoldi(lambda w: mbd_apply(mbd, apply_A(pt, nz, w, method)), r0, m_max,
+                  eps_arn, reorth)
+    theta, Y = ritz_select(res.H[:res.m, :res.m], k, eps_lambda)
+    V = res.W[:, :res.m] @ Y
+    Z = np.linalg.qr(V)[0] if V.shape[1] else V
+    return m2l_from_Z(pt, nz, mbd, Z, method), res, theta
+
+
+# ---------------------------------------------------------------------------
+# O10  PCG (Eq. pcg; stop on ||b - A x|| / ||b|| <= tol, Sect. 6.1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SolveInfo:
+    iters: int
+    rel_res_recursive: float
+    rel_res_true: float
+    history: np.ndarray
+    breakdown: bool = False
+    converged: bool = False
+
+
+def pcg(apply_A_fn, apply_M_fn, b, tol: float, max_iter: int, x0=None):
+    """Textbook preconditioned conjugate gradients:
+        r = b - A x; z = M r; p = z; rho = r.z
+        repeat: q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q;
+                z = M r; rho' = r.z; beta = rho'/rho; p = z + beta p
+    until ||r|| / ||b|| <= tol or max_iter iterations."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply_A_fn(x)
+    z = apply_M_fn(r)
+    p = z.copy()
+    rho = float(r @ z)
+    bnorm = float(np.linalg.norm(b))
+    if bnorm == 0.0:
+        return x, SolveInfo(0, 0.0, 0.0, np.zeros(1), converged=True)
+    hist = [float(np.linalg.norm(r)) / bnorm]
+    k = 0
+    breakdown = False
+    while hist[-1] > tol and k < max_iter:
+        q = apply_A_fn(p)
+        pq = float(p @ q)
+        if not pq > 0.0:
+            breakdown = True
+            break
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        z = apply_M_fn(r)
+        rho_new = float(r @ z)
+        beta = rho_new / rho
+        p = z + beta * p
+        rho = rho_new
+        k += 1
+        hist.append(float(np.linalg.norm(r)) / bnorm)
+    true_res = float(np.linalg.norm(b - apply_A_fn(x))) / bnorm
+    return x, SolveInfo(k, hist[-1], true_res, np.array(hist), breakdown,
+                        converged=hist[-1] <= tol)

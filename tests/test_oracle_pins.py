@@ -1,0 +1,460 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself -- brute force on tiny inputs, a library routine for a special case,
+a closed form, a hand-derived value or an identity the paper states.
+
+Sizes are tiny so the whole file runs in seconds on the CPU.
+"""
+import json
+import math
+import os
+from collections import defaultdict
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _setup(seed=0, **kw):
+    p = synth.random_problem(seed, **kw)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    return p, pt, nz
+
+
+def _dense_P_test(pix, psi, cidx):
+    """P written from Eq. datamodel with math.cos/math.sin, independent of the
+    oracle's vectorised gather."""
+    n_obs = int(cidx.max()) + 1 if cidx.size and cidx.max() >= 0 else 0
+    P = np.zeros((len(pix), 3 * n_obs))
+    for t, (p, ph) in enumerate(zip(pix, psi)):
+        if p >= 0 and cidx[p] >= 0:
+            j = cidx[p]
+            P[t, 3 * j: 3 * j + 3] = (1.0, math.cos(2 * ph), math.sin(2 * ph))
+    return P
+
+
+def _dense_N_scipy(p):
+    """Block-diagonal N^-1 from scipy.linalg.toeplitz, one block per interval."""
+    blocks = []
+    for i in range(p.n_intervals):
+        L = int(p.interval_start[i + 1] - p.interval_start[i])
+        col = np.zeros(L)
+        c = p.band[p.filter_id[i]]
+        m = min(L, p.half_bw + 1)
+        col[:m] = c[:m]
+        blocks.append(scipy.linalg.toeplitz(col))
+    return scipy.linalg.block_diag(*blocks)
+
+
+# ---------------------------------------------------------------- pointing (O1)
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pointing_bruteforce(seed):
+    p = synth.random_problem(seed, n_side=5, n_samp=700, flag_frac=0.1, min_hits=30)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    hits = defaultdict(int)
+    for q in p.pix:
+        if q >= 0:
+            hits[int(q)] += 1
+    assert [hits[q] for q in range(p.n_pix_total)] == pt.hits.tolist()
+    obs = sorted(q for q in range(p.n_pix_total) if hits[q] >= p.min_hits)
+    assert obs == pt.obs_pix.tolist()
+    assert len(obs) < p.n_pix_total  # the threshold actually dropped pixels here
+    pairs = sorted((obs.index(int(q)), t) for t, q in enumerate(p.pix) if q >= 0 and int(q) in obs)
+    assert [t for _, t in pairs] == pt.perm.tolist()
+    off = [0]
+    for q in obs:
+        off.append(off[-1] + hits[q])
+    assert off == pt.off.tolist()
+    assert pt.off[-1] == pt.perm.shape[0] == int(np.sum(pt.j >= 0))
+    for t, q in enumerate(p.pix):
+        exp = obs.index(int(q)) if q >= 0 and int(q) in obs else -1
+        assert pt.j[t] == exp
+
+
+def test_pointing_rejects_bad_pixels():
+    with pytest.raises(O.OracleError):
+        O.pointing_build(np.array([0, 5]), np.zeros(2), 4)
+    with pytest.raises(O.OracleError):
+        O.pointing_build(np.array([0, -2]), np.zeros(2), 4)
+
+
+# ---------------------------------------------------------------- P, P^T (O3, O4)
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_P_PT_dense(seed):
+    p, pt, nz = _setup(seed, n_side=4, n_samp=400, n_int=3, half_bw=4)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(pt.n)
+    y = rng.standard_normal(pt.n_samp)
+    np.testing.assert_allclose(O.apply_P(pt, x), P @ x, rtol=1e-14, atol=1e-13)
+    np.testing.assert_allclose(O.apply_PT(pt, y), P.T @ y, rtol=1e-13, atol=1e-12)
+
+
+def test_P_PT_adjoint():
+    p, pt, nz = _setup(4, n_side=6, n_samp=3000)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(pt.n)
+    y = rng.standard_normal(pt.n_samp)
+    lhs = O.apply_P(pt, x) @ y
+    rhs = x @ O.apply_PT(pt, y)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + np.linalg.norm(x) * np.linalg.norm(y))
+
+
+def test_P_matches_generator_data_model():
+    """Noiseless TOD from the generator's own data model equals P s."""
+    p = synth.config1(noiseless=True)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    s = p.signal[pt.obs_pix].reshape(-1)
+    np.testing.assert_allclose(O.apply_P(pt, s), p.tod, rtol=0, atol=1e-12)
+
+
+def test_golden_one_pixel():
+    g = _golden("one_pixel_binned_map.json")
+    pt = O.pointing_build(np.array(g["pix"]), np.array(g["psi"]), 1, 1)
+    nz = O.noise_build([0, 4], [0], [[1.0]], 0)
+    np.testing.assert_allclose(O.apply_P(pt, g["iqu"]), g["tod"], atol=1e-13)
+    np.testing.assert_allclose(O.apply_PT(pt, g["tod"]), g["PT_d"], atol=1e-13)
+    M = O.mbd_build(pt, nz)
+    np.testing.assert_allclose(M.blocks[0], g["block"], atol=1e-14)
+    b = O.rhs(pt, nz, g["tod"])
+    np.testing.assert_allclose(O.mbd_apply(M, b), g["binned"], atol=1e-13)
+
+
+# ---------------------------------------------------------------- N^-1 (O2)
+
+def test_golden_toeplitz():
+    g = _golden("toeplitz_band_3x.json")
+    nz = O.noise_build(g["interval_start"], g["filter_id"], g["band"], g["half_bw"])
+    np.testing.assert_allclose(O.noise_apply_direct(nz, g["y"]), g["z"], atol=1e-15)
+    np.testing.assert_allclose(O.noise_apply_fft(nz, g["y"]), g["z"], atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_noise_vs_scipy_toeplitz(seed):
+    p, pt, nz = _setup(seed, n_samp=600, n_int=4, half_bw=20, n_filters=3)
+    N = _dense_N_scipy(p)
+    y = np.random.default_rng(seed).standard_normal(p.n_samp)
+    ref = N @ y
+    np.testing.assert_allclose(O.noise_apply_direct(nz, y), ref, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(O.noise_apply_fft(nz, y), ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(O.dense_Ninv(nz), N)
+
+
+def test_noise_fft_vs_direct_large_band():
+    p = synth.config2(n_side=32, grid=(2, 2), samp_per_det=1 << 12, L=1 << 11, half_bw=512)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    y = np.random.default_rng(0).standard_normal(p.n_samp)
+    a = O.noise_apply_direct(nz, y)
+    b = O.noise_apply_fft(nz, y)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_noise_symmetric_and_positive_symbol():
+    p = synth.config1()
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    rng = np.random.default_rng(2)
+    u, v = rng.standard_normal((2, p.n_samp))
+    a = O.noise_apply_direct(nz, u) @ v
+    b = u @ O.noise_apply_direct(nz, v)
+    assert abs(a - b) <= 1e-12 * abs(a)
+    c = p.band[0]
+    lam = p.half_bw
+    w = np.linspace(0, np.pi, 8 * lam + 1)
+    sym = c[0] + 2 * np.sum(c[1:, None] * np.cos(np.arange(1, lam + 1)[:, None] * w[None, :]), axis=0)
+    assert sym.min() > 0
+    # a section's eigenvalues lie within the symbol's range
+    T = scipy.linalg.toeplitz(np.concatenate([c, np.zeros(400 - lam - 1)]))
+    ev = np.linalg.eigvalsh(T)
+    assert ev.min() >= sym.min() * (1 - 1e-9) and ev.max() <= sym.max() * (1 + 1e-9)
+
+
+def test_noise_rejects_bad_intervals():
+    with pytest.raises(O.OracleError):
+        O.noise_build([0, 5, 4], [0, 0], [[1.0, 0.1]], 1)
+    with pytest.raises(O.OracleError):
+        O.noise_build([0, 4, 8], [0, 0], [[1.0, 0.1, 0.1]], 2)
+
+
+# ---------------------------------------------------------------- A, b (O5, O6)
+
+def test_A_dense_spd():
+    p, pt, nz = _setup(6, n_side=3, n_samp=480, n_int=3, half_bw=10)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    N = _dense_N_scipy(p)
+    A = P.T @ N @ P
+    cols = np.stack([O.apply_A(pt, nz, e) for e in np.eye(pt.n)], axis=1)
+    np.testing.assert_allclose(cols, A, rtol=1e-12, atol=1e-11 * np.abs(A).max())
+    np.testing.assert_allclose(cols, cols.T, rtol=0, atol=1e-12 * np.abs(A).max())
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+
+
+def test_b_noiseless_equals_A_s():
+    p = synth.config1(noiseless=True)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    s = p.signal[pt.obs_pix].reshape(-1)
+    b = O.rhs(pt, nz, p.tod)
+    As = O.apply_A(pt, nz, s)
+    assert np.linalg.norm(b - As) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_rhs_masks_flagged_samples():
+    p, pt, nz = _setup(7, n_side=4, n_samp=500, flag_frac=0.2, n_int=2, half_bw=5)
+    d = p.tod.copy()
+    d[pt.j < 0] = 1e6  # garbage on flagged samples must not leak into b
+    b1 = O.rhs(pt, nz, d)
+    d[pt.j < 0] = 0.0
+    np.testing.assert_array_equal(b1, O.rhs(pt, nz, d))
+
+
+# ---------------------------------------------------------------- M_BD (O7)
+
+def test_mbd_inverse_and_white_noise_closed_form():
+    """With lambda = 0 (white noise) A = M_BD^-1, so PCG with M_BD stops after
+    one iteration at the binned map B_j^-1 sum_t c0 w_t d_t (noiseless: s)."""
+    p = synth.random_problem(8, n_side=4, n_samp=800, half_bw=0, n_int=2, noiseless=True)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band[:, :1], 0)
+    M = O.mbd_build(pt, nz)
+    for j in range(pt.n_obs):
+        np.testing.assert_allclose(M.blocks[j] @ M.inv[j], np.eye(3), atol=1e-12)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    c0 = np.concatenate([np.full(int(p.interval_start[i + 1] - p.interval_start[i]),
+                                 p.band[p.filter_id[i], 0]) for i in range(p.n_intervals)])
+    A_dense = P.T @ (c0[:, None] * P)
+    Minv_dense = scipy.linalg.block_diag(*M.blocks)
+    np.testing.assert_allclose(A_dense, Minv_dense, rtol=1e-12, atol=1e-12)
+    b = O.rhs(pt, nz, p.tod)
+    x, info = O.pcg(lambda v: O.apply_A(pt, nz, v), lambda v: O.mbd_apply(M, v), b, 1e-12, 50)
+    assert info.iters == 1
+    np.testing.assert_allclose(x, p.signal[pt.obs_pix].reshape(-1), rtol=1e-10, atol=1e-10)
+
+
+def test_mbd_singular_block_detected():
+    # three hits at the same angle: rank-1 block
+    pix = np.array([0, 0, 0, 1, 1, 1, 1])
+    psi = np.array([0.3, 0.3, 0.3, 0.0, 0.5, 1.0, 1.5])
+    pt = O.pointing_build(pix, psi, 2, 3)
+    nz = O.noise_build([0, 7], [0], [[1.0]], 0)
+    with pytest.raises(O.OracleError) as e:
+        O.mbd_build(pt, nz)
+    assert e.value.code == "SINGULAR_BLOCK"
+
+
+# ---------------------------------------------------------------- M_2l (O8)
+
+def _small_c1_like():
+    p = synth.config2(n_side=16, grid=(2, 2), samp_per_det=1 << 10, L=1 << 9, half_bw=32)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    return p, pt, nz
+
+
+def test_m2l_identities():
+    p, pt, nz = _small_c1_like()
+    M = O.mbd_build(pt, nz)
+    rng = np.random.default_rng(3)
+    k = 6
+    Z = rng.standard_normal((pt.n, k))
+    M2 = O.m2l_from_Z(pt, nz, M, Z)
+    # Eq. ident: M_2l A Z = Z
+    for c in range(k):
+        out = O.m2l_apply(M2, O.apply_A(pt, nz, Z[:, c]))
+        assert np.linalg.norm(out - Z[:, c]) <= 1e-9 * np.linalg.norm(Z[:, c])
+    # R A Z = 0 with R = 1 - A Z E^-1 Z^T
+    AZ = M2.AZ
+    RAZ = AZ - AZ @ np.linalg.solve(M2.E, Z.T @ AZ)
+    assert np.linalg.norm(RAZ) <= 1e-10 * np.linalg.norm(AZ)
+    # M_2l A y = M_BD A y for y with Z^T A y = 0
+    y = rng.standard_normal(pt.n)
+    y = y - Z @ np.linalg.solve(M2.E, Z.T @ O.apply_A(pt, nz, y))
+    Ay = O.apply_A(pt, nz, y)
+    assert np.linalg.norm(Z.T @ Ay) <= 1e-9 * np.linalg.norm(Z) * np.linalg.norm(Ay)
+    np.testing.assert_allclose(O.m2l_apply(M2, Ay), O.mbd_apply(M, Ay),
+                               rtol=1e-8, atol=1e-9 * np.abs(O.mbd_apply(M, Ay)).max())
+    # invariance under Z -> Z G
+    G = rng.standard_normal((k, k)) + 3 * np.eye(k)
+    M3 = O.m2l_from_Z(pt, nz, M, Z @ G)
+    v = rng.standard_normal(pt.n)
+    a, b = O.m2l_apply(M2, v), O.m2l_apply(M3, v)
+    assert np.linalg.norm(a - b) <= 1e-8 * np.linalg.norm(a)
+    # k = 0 is M_BD
+    M0 = O.m2l_from_Z(pt, nz, M, np.zeros((pt.n, 0)))
+    np.testing.assert_array_equal(O.m2l_apply(M0, v), O.mbd_apply(M, v))
+
+
+def test_m2l_exact_eigvecs_deflate_to_one():
+    """With Z = exact eigenvectors of M_BD A, the deflated eigenvalues of
+    M_2l A become 1 and the rest are unchanged."""
+    p, pt, nz = _setup(9, n_side=3, n_samp=600, n_int=2, half_bw=12)
+    M = O.mbd_build(pt, nz)
+    B = np.stack([O.mbd_apply(M, O.apply_A(pt, nz, e)) for e in np.eye(pt.n)], axis=1)
+    ev, V = np.linalg.eig(B)
+    order = np.argsort(ev.real)
+    ev, V = ev.real[order], V.real[:, order]
+    k = 4
+    M2 = O.m2l_from_Z(pt, nz, M, V[:, :k])
+    C = np.stack([O.m2l_apply(M2, O.apply_A(pt, nz, e)) for e in np.eye(pt.n)], axis=1)
+    ev2 = np.sort(np.linalg.eigvals(C).real)
+    exp = np.sort(np.concatenate([np.ones(k), ev[k:]]))
+    np.testing.assert_allclose(ev2, exp, rtol=1e-8, atol=1e-8)
+
+
+def test_coarse_not_spd_detected():
+    p, pt, nz = _small_c1_like()
+    M = O.mbd_build(pt, nz)
+    z = np.random.default_rng(0).standard_normal(pt.n)
+    with pytest.raises(O.OracleError) as e:
+        O.m2l_from_Z(pt, nz, M, np.stack([z, z], axis=1))
+    assert e.value.code == "COARSE_NOT_SPD"
+
+
+# ---------------------------------------------------------------- Arnoldi (O9)
+
+def test_arnoldi_relations_and_full_spectrum():
+    p, pt, nz = _setup(10, n_side=3, n_samp=600, n_int=2, half_bw=12)
+    M = O.mbd_build(pt, nz)
+    Bop = lambda w: O.mbd_apply(M, O.apply_A(pt, nz, w))
+    Bd = np.stack([Bop(e) for e in np.eye(pt.n)], axis=1)
+    b = O.rhs(pt, nz, p.tod)
+    r0 = O.mbd_apply(M, b)
+    res = O.arnoldi(Bop, r0, pt.n, 1e-300)
+    m = res.m
+    W = res.W
+    # orthonormal basis
+    G = W[:, :m].T @ W[:, :m]
+    assert np.abs(G - np.eye(m)).max() <= 1e-12
+    # Eq. factoriz: B W_m = W_m H_m + h_{m+1,m} w_{m+1} e_m^T
+    H = res.H
+    lhs = Bd @ W[:, :m]
+    rhs_ = W[:, :m] @ H[:m, :m]
+    if W.shape[1] > m:
+        rhs_[:, m - 1] += H[m, m - 1] * W[:, m]
+    assert np.abs(lhs - rhs_).max() <= 1e-12 * np.abs(Bd).max()
+    # full Arnoldi: Ritz values = eigenvalues of M_BD A
+    if m == pt.n:
+        th = np.sort(np.linalg.eigvals(H[:m, :m]).real)
+        ev = np.sort(np.linalg.eigvals(Bd).real)
+        np.testing.assert_allclose(th, ev, rtol=1e-9)
+
+
+def test_ritz_residual_identity():
+    """||B v_i - theta_i v_i|| = |h_{m+1,m}| |e_m^T y_i| (Eq. ritz, read with
+    y_i in place of v_i on the right)."""
+    p, pt, nz = _small_c1_like()
+    M = O.mbd_build(pt, nz)
+    Bop = lambda w: O.mbd_apply(M, O.apply_A(pt, nz, w))
+    b = O.rhs(pt, nz, p.tod)
+    res = O.arnoldi(Bop, O.mbd_apply(M, b), 30, 1e-14)
+    m = res.m
+    theta, Y = np.linalg.eig(res.H[:m, :m])
+    for i in range(0, m, 5):
+        v = res.W[:, :m] @ Y[:, i]
+        lhs = np.linalg.norm(np.array([Bop(v.real), Bop(v.imag)]).T @ np.array([1, 1j]) - theta[i] * v)
+        rhs_ = abs(res.H[m, m - 1]) * abs(Y[m - 1, i])
+        assert abs(lhs - rhs_) <= 1e-9 * max(1.0, np.linalg.norm(v))
+
+
+def test_ritz_select_keeps_pairs():
+    H = np.array([[1.0, -2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.0, 3.0]])
+    theta, Y = O.ritz_select(H, 1)
+    assert Y.shape[1] == 2   # the complex pair at Re = 1 is kept whole
+    theta, Y = O.ritz_select(H, 3)
+    assert Y.shape[1] == 3
+    theta, Y = O.ritz_select(H, 0, eps_lambda=2.0)
+    assert Y.shape[1] == 2
+
+
+def test_defl_build_smallest_ritz_span():
+    """With the Arnoldi run to exhaustion the selected Z spans the invariant
+    subspace of the k smallest eigenvalues of M_BD A."""
+    p, pt, nz = _setup(11, n_side=3, n_samp=600, n_int=2, half_bw=12)
+    M = O.mbd_build(pt, nz)
+    b = O.rhs(pt, nz, p.tod)
+    k = 5
+    M2, res, theta = O.defl_build(pt, nz, M, b, k, 1e-300, pt.n)
+    Bd = np.stack([O.mbd_apply(M, O.apply_A(pt, nz, e)) for e in np.eye(pt.n)], axis=1)
+    ev, V = np.linalg.eig(Bd)
+    order = np.argsort(ev.real)
+    Vk = np.linalg.qr(V[:, order[:k]].real)[0]
+    s = scipy.linalg.subspace_angles(M2.Z, Vk)
+    assert np.max(np.sin(s)) <= 1e-7
+
+
+# ---------------------------------------------------------------- PCG (O10)
+
+def test_pcg_vs_cholesky_direct():
+    p, pt, nz = _setup(12, n_side=3, n_samp=600, n_int=3, half_bw=12)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    A = P.T @ _dense_N_scipy(p) @ P
+    b = O.rhs(pt, nz, p.tod)
+    M = O.mbd_build(pt, nz)
+    x, info = O.pcg(lambda v: O.apply_A(pt, nz, v), lambda v: O.mbd_apply(M, v), b, 1e-13, 500)
+    xd = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), b)
+    kappa = np.linalg.cond(A)
+    assert info.converged
+    assert np.linalg.norm(x - xd) <= kappa * 1e-13 * np.linalg.norm(xd) * 10
+    # exact inverse as preconditioner: one iteration
+    Ainv = np.linalg.inv(A)
+    x1, info1 = O.pcg(lambda v: A @ v, lambda v: Ainv @ v, b, 1e-10, 10)
+    assert info1.iters == 1
+
+
+def test_pcg_errnorm_bound_each_iteration():
+    p, pt, nz = _setup(13, n_side=3, n_samp=600, n_int=3, half_bw=12)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    A = P.T @ _dense_N_scipy(p) @ P
+    b = O.rhs(pt, nz, p.tod)
+    xd = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), b)
+    M = O.mbd_build(pt, nz)
+    Md = scipy.linalg.block_diag(*M.inv)
+    kap = np.linalg.cond(Md @ A)
+    kapA = np.linalg.cond(A)
+    for it in range(1, 12):
+        x, info = O.pcg(lambda v: A @ v, lambda v: Md @ v, b, 0.0, it)
+        err = np.linalg.norm(xd - x) / np.linalg.norm(xd)
+        # unpreconditioned residual: ||e|| <= kappa(A) ||r||/||b||
+        assert err <= kapA * info.rel_res_true * (1 + 1e-8)
+        # preconditioned residual of Eq. residuals: ||e|| <= kappa(MA) ||M r||/||M b||
+        r = b - A @ x
+        assert err <= kap * np.linalg.norm(Md @ r) / np.linalg.norm(Md @ b) * (1 + 1e-8)
+
+
+def test_noiseless_recovery_config1():
+    """Signal-only TOD: the solution is the input map (error-norm analogue)."""
+    p = synth.config1(noiseless=True)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    M = O.mbd_build(pt, nz)
+    b = O.rhs(pt, nz, p.tod)
+    x, info = O.pcg(lambda v: O.apply_A(pt, nz, v), lambda v: O.mbd_apply(M, v), b, 1e-10, 500)
+    s = p.signal[pt.obs_pix].reshape(-1)
+    assert info.converged and info.rel_res_true <= 1e-9
+    assert np.linalg.norm(x - s) / np.linalg.norm(s) <= 1e-6
+
+
+def test_m2l_fewer_iterations_than_mbd():
+    p = synth.config1()
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    M = O.mbd_build(pt, nz)
+    b = O.rhs(pt, nz, p.tod)
+    A = lambda v: O.apply_A(pt, nz, v)
+    _, i1 = O.pcg(A, lambda v: O.mbd_apply(M, v), b, 1e-8, 1000)
+    M2, res, th = O.defl_build(pt, nz, M, b, 32, 1e-8, 256)
+    _, i2 = O.pcg(A, lambda v: O.m2l_apply(M2, v), b, 1e-8, 1000)
+    assert i1.converged and i2.converged
+    assert i2.iters <= i1.iters
+    assert i2.rel_res_true <= 1e-8 * 1.5
