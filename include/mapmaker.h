@@ -1,0 +1,268 @@
+/*
+ * mapmaker.h -- C ABI of the MI355X map-making library (libmapmaker.so).
+ *
+ * Solves the generalised-least-squares map-making system of Puglisi et al.
+ * (2018), "Iterative map-making with two-level preconditioning for polarized
+ * CMB data sets":
+ *
+ *     A x = b,   A = P^T N^-1 P,   b = P^T N^-1 d            (Eqs. estimator, linearsystem)
+ *
+ * with P the polarised pointing matrix (three non-zeros per row, 1, cos 2phi,
+ * sin 2phi; Eq. datamodel), N^-1 a banded-Toeplitz inverse-noise matrix per
+ * stationary interval (W = N^-1, Sect. 2), by preconditioned conjugate
+ * gradients (Eq. pcg) with either the block-diagonal preconditioner M_BD
+ * (Eq. mbd) or the two-level preconditioner
+ *
+ *     M_2l = M_BD (1 - A Z E^-1 Z^T) + Z E^-1 Z^T,   E = Z^T A Z   (Eq. m2l)
+ *
+ * whose deflation space Z is built from Ritz vectors of an Arnoldi run on
+ * M_BD A (Sect. 5, Appendix A).
+ *
+ * Conventions
+ *  - Every call returns mm_status.  MM_OK = 0.  MM_NOT_CONVERGED = 1 is a
+ *    non-error outcome (solve info is filled).  Negative values are errors;
+ *    the message is in mm_last_error(ctx).  Arguments are validated before
+ *    any device work; an invalid argument leaves outputs untouched.
+ *  - Array arguments marked [device] are device pointers on the context's
+ *    device (e.g. a torch tensor's data_ptr()); [host] marks host pointers.
+ *    The caller owns every array it passes; the library never frees them and
+ *    keeps no reference to them after the call returns.
+ *  - Handles (mm_ctx, mm_pointing, mm_noise, mm_precond) own all memory the
+ *    library allocates; mm_*_destroy releases it.  A handle must be destroyed
+ *    before the context that created it.
+ *  - Work is enqueued on the HIP stream given at context creation.  Calls that
+ *    return host-visible results (counts, status, solve info) synchronise that
+ *    stream; others are asynchronous with respect to the host.
+ *  - Map layout: pixel-major, I,Q,U interleaved, FP64: x[(3 j + a) * nrhs + r]
+ *    for compact pixel j, Stokes a, right-hand side r.  n = 3 * n_obs.
+ *  - TOD layout: time-major, x[t * nrhs + r]; FP64, or FP32 for an MM_F32
+ *    pointing/noise pair.
+ *  - nrhs (right-hand sides processed together) must be 1, 2, 4, 8, 16, 32
+ *    or 64.  Columns are processed independently and in a fixed order, so a
+ *    column's result does not depend on the values in the other columns.
+ *  - Not thread safe per context: calls on one context must not overlap.
+ */
+#ifndef MAPMAKER_H
+#define MAPMAKER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MM_OK = 0,
+    MM_NOT_CONVERGED = 1,
+    MM_E_INVALID = -1,        /* bad argument (sizes, ranges, layout) */
+    MM_E_OOM = -2,            /* device allocation failed */
+    MM_E_DEVICE = -3,         /* HIP runtime error */
+    MM_E_SINGULAR_BLOCK = -4, /* a 3x3 M_BD block is not invertible */
+    MM_E_COARSE_NOT_SPD = -5, /* E = Z^T A Z is not positive definite */
+    MM_E_BREAKDOWN = -6,      /* PCG: p^T A p <= 0 */
+    MM_E_NONFINITE = -7,      /* NaN/Inf in an input */
+    MM_E_BUSY = -8            /* request exceeds the configured memory budget */
+} mm_status;
+
+/* Precision of the time-domain work (TOD, pointing weights, N^-1 band and its
+ * accumulation).  Map-domain vectors, reductions, the 3x3 M_BD inverses and
+ * the coarse matrix E are always FP64. */
+typedef enum { MM_F64 = 0, MM_F32 = 1 } mm_precision;
+
+/* How N^-1 is applied: AUTO picks FFT for half bandwidths >= 256 when the
+ * interval lengths allow it, else the direct band. */
+typedef enum { MM_NOISE_AUTO = 0, MM_NOISE_DIRECT = 1, MM_NOISE_FFT = 2 } mm_noise_method;
+
+typedef struct mm_ctx mm_ctx;
+typedef struct mm_pointing mm_pointing;
+typedef struct mm_noise mm_noise;
+typedef struct mm_precond mm_precond;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates (default priority). */
+mm_status mm_ctx_create(int device, void *hip_stream, mm_ctx **out);
+void mm_ctx_destroy(mm_ctx *ctx);
+/* Message of the last failed call on this context ("" if none).  Owned by the
+ * context; valid until the next call. */
+const char *mm_last_error(const mm_ctx *ctx);
+/* Library version string. */
+const char *mm_version(void);
+
+/* --------------------------------------------------------------- pointing */
+
+/* Build P from per-sample pixels and angles (Eq. datamodel).  Samples with
+ * pix = -1 are flagged.  Pixels with fewer than min_hits unflagged samples
+ * are dropped and their samples flagged too (the paper keeps only pixels
+ * observed with enough redundancy, Sect. 4).  Observed pixels get compact
+ * ids 0..n_obs-1 in ascending global id.
+ *   n_samp       number of samples, 0 < n_samp < 2^31
+ *   n_pix_total  number of global pixels; pix must lie in [-1, n_pix_total)
+ *   pix  [device] int32[n_samp];  psi [device] f64[n_samp], radians
+ *   prec         precision of the stored weights (cos 2psi, sin 2psi)
+ * Errors: MM_E_INVALID (sizes, pixel out of range), MM_E_NONFINITE (psi). */
+mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
+                            const int32_t *pix, const double *psi, int32_t min_hits,
+                            mm_precision prec, mm_pointing **out);
+/* n_obs (observed pixels) and n_valid (unflagged samples).  [host] outputs. */
+mm_status mm_pointing_counts(const mm_pointing *p, int32_t *n_obs, int64_t *n_valid);
+/* Hit counts per global pixel and the observed pixels' global ids.
+ *   hits [device] int32[n_pix_total]; obs_pix [device] int32[n_obs] (either may be NULL) */
+mm_status mm_pointing_hits(mm_ctx *ctx, const mm_pointing *p, int32_t *hits, int32_t *obs_pix);
+/* The sample-to-pixel structure: j [device] int32[n_samp] compact pixel per
+ * sample (-1 = flagged); perm [device] int32[n_valid] samples sorted by
+ * (pixel, time); off [device] int32[n_obs+1] segment offsets (any may be NULL). */
+mm_status mm_pointing_export(mm_ctx *ctx, const mm_pointing *p, int32_t *j, int32_t *perm,
+                             int32_t *off);
+void mm_pointing_destroy(mm_pointing *p);
+
+/* ------------------------------------------------------------------ noise */
+
+/* Banded-Toeplitz N^-1, block diagonal over stationary intervals: for t in
+ * interval i = [s_i, s_{i+1}) with filter f = filter_id[i],
+ *     (N^-1 y)_t = sum_{u in [s_i, s_{i+1}), |t-u| <= half_bw} c^f_{|t-u|} y_u.
+ *   interval_start [host] int64[n_intervals+1], s_0 = 0, strictly increasing
+ *   filter_id [host] int32[n_intervals] in [0, n_filters)
+ *   band [host] f64[n_filters][half_bw+1] = c_0..c_lambda of each filter
+ * Errors: MM_E_INVALID if intervals do not tile [0, s_n) or
+ * 2 * half_bw >= the shortest interval; MM_E_NONFINITE for NaN/Inf bands. */
+mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals, const int64_t *interval_start,
+                         const int32_t *filter_id, int32_t n_filters, int32_t half_bw,
+                         const double *band, mm_noise_method method, mm_precision prec,
+                         mm_noise **out);
+/* The method actually used (MM_NOISE_DIRECT or MM_NOISE_FFT). */
+mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method);
+/* z = N^-1 y on the TOD layout.  y, z [device], TOD precision, distinct. */
+mm_status mm_noise_apply(mm_ctx *ctx, const mm_noise *nz, int32_t nrhs, const void *y, void *z);
+void mm_noise_destroy(mm_noise *nz);
+
+/* ------------------------------------------------------------- operators */
+
+/* y = P x (map -> TOD).  x [device] f64 map layout; y [device] TOD layout and
+ * precision. */
+mm_status mm_apply_P(mm_ctx *ctx, const mm_pointing *p, int32_t nrhs, const double *x, void *y);
+/* x = P^T z (TOD -> map), a deterministic pixel-sorted segmented reduction.
+ * z [device] TOD layout/precision; x [device] f64 map layout. */
+mm_status mm_apply_PT(mm_ctx *ctx, const mm_pointing *p, int32_t nrhs, const void *z, double *x);
+/* y = A x = P^T N^-1 P x (matrix-free; Eq. linearsystem).  x, y [device] f64
+ * map layout, distinct.  The pointing and noise must have the same precision
+ * and n_samp. */
+mm_status mm_apply_A(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, int32_t nrhs,
+                     const double *x, double *y);
+/* b = P^T N^-1 (mask . d): flagged samples are zeroed before weighting.
+ * tod [device] TOD precision, layout [nrhs][n_samp] (each realisation
+ * contiguous); b [device] f64 map layout.  Errors: MM_E_NONFINITE. */
+mm_status mm_rhs(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, int32_t nrhs,
+                 const void *tod, double *b);
+
+/* --------------------------------------------------------- preconditioners */
+
+/* M_BD: the 3x3 blocks B_j = sum_{t in j} c_0^{f(t)} w_t w_t^T (Eq. mbd, with
+ * diag(N^-1) = the zero-lag coefficient c_0 of the sample's interval), each
+ * inverted in FP64.  Errors: MM_E_SINGULAR_BLOCK if a block is not positive
+ * definite or its 1-norm reciprocal condition number is below 1e-12. */
+mm_status mm_mbd_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond **out);
+/* Smallest 1-norm reciprocal condition number over the 3x3 blocks. */
+mm_status mm_mbd_rcond(const mm_precond *M, double *rcond_min);
+
+/* Arnoldi diagnostics of mm_defl_build. */
+typedef struct {
+    int32_t m;            /* Arnoldi steps taken */
+    int32_t k;            /* deflation vectors kept */
+    double h_last;        /* h_{m+1,m} at exit */
+    double setup_seconds; /* wall time of the whole build */
+} mm_arnoldi_info;
+
+/* M_2l from Ritz vectors (Sect. 5, Appendix A): Arnoldi on B = M_BD A from
+ * r_0 = M_BD b_seed, classical Gram-Schmidt applied twice, until
+ * h_{j+1,j} <= eps_arn or m_max steps; eigenpairs of H_m ordered by real
+ * part; keep the k smallest (k+1 rather than split a complex pair) or, if
+ * eps_lambda > 0, all with Re(theta) < eps_lambda; Z = orthonormalised
+ * W_m [Re y | Im y]; E = Z^T A Z (FP64 MFMA), Cholesky-factorised on device.
+ *   mbd       an M_BD handle built for the same pointing and noise
+ *   b_seed    [device] f64[n] start vector seed (typically b)
+ *   h_history [host] f64[m_max] or NULL: h_{j+1,j} per step
+ *   info      [host] or NULL
+ * Errors: MM_E_INVALID (k, m_max), MM_E_COARSE_NOT_SPD. */
+mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                        const mm_precond *mbd, const double *b_seed, int32_t k,
+                        double eps_lambda, double eps_arn, int32_t m_max,
+                        double *h_history, mm_arnoldi_info *info, mm_precond **out);
+/* M_2l from a caller-supplied deflation matrix (Eq. m2l).
+ *   Z [device] f64[k][n] column-major (column c at Z + c*n), 1 <= k <= 64.
+ * Errors: MM_E_COARSE_NOT_SPD if Z^T A Z is not (numerically) SPD: a Cholesky
+ * pivot^2 below 1e-13 times the largest diagonal entry. */
+mm_status mm_defl_from_Z(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                         const mm_precond *mbd, int32_t k, const double *Z, mm_precond **out);
+/* Copy out Z, A Z ([device] f64[k][n] each, either may be NULL) and E
+ * ([device] f64[k][k], symmetrised). */
+mm_status mm_defl_export(mm_ctx *ctx, const mm_precond *M, int32_t *k, double *Z, double *AZ,
+                         double *E);
+/* Arnoldi basis and Hessenberg matrix of the last mm_defl_build on this
+ * handle: W [device] f64[m+1][n] column-major, H [host] f64[(m+1) * m]
+ * column-major (either may be NULL). */
+mm_status mm_defl_arnoldi_export(mm_ctx *ctx, const mm_precond *M, int32_t *m, double *W,
+                                 double *H);
+/* out = M v for an M_BD or M_2l handle.  v, out [device] f64 map layout, distinct. */
+mm_status mm_precond_apply(mm_ctx *ctx, const mm_precond *M, int32_t nrhs, const double *v,
+                           double *out);
+void mm_precond_destroy(mm_precond *M);
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+    int32_t iters;             /* PCG iterations taken */
+    int32_t converged;         /* 1 if ||r||/||b|| <= tol */
+    int32_t breakdown;         /* 1 if p^T A p <= 0 stopped the column */
+    int32_t pad;
+    double rel_res_recursive;  /* ||r_k|| / ||b|| from the recursion */
+    double rel_res_true;       /* ||b - A x_k|| / ||b|| recomputed at exit */
+    double solve_seconds;      /* wall time of the solve (all columns) */
+} mm_solve_info;
+
+/* PCG flags */
+#define MM_SOLVE_CHECK_EVERY(c) ((c) & 0xff)  /* host convergence poll period (0 = 1) */
+
+/* Preconditioned conjugate gradients (Eq. pcg), column-independent for
+ * nrhs > 1:  r = b - A x; z = M r; p = z; rho = r.z; repeat q = A p;
+ * alpha = rho / p.q; x += alpha p; r -= alpha q; z = M r; rho' = r.z;
+ * beta = rho'/rho; p = z + beta p -- until ||r|| / ||b|| <= tol (the
+ * unpreconditioned residual, Sect. 6.1) or max_iter.  M may be NULL (no
+ * preconditioner), an M_BD or an M_2l handle.
+ *   b [device] f64 map layout; x [device] in: x_0, out: solution
+ *   history [host] f64[nrhs][max_iter+1] or NULL: ||r_k||/||b|| per column
+ *   info [host] mm_solve_info[nrhs] or NULL
+ * Returns MM_OK if every column converged, MM_NOT_CONVERGED otherwise,
+ * MM_E_BREAKDOWN if a column broke down. */
+mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const mm_precond *M,
+                   int32_t nrhs, const double *b, double *x, double tol, int32_t max_iter,
+                   uint32_t flags, double *history, mm_solve_info *info);
+
+/* ---------------------------------------------------------- profiling aid */
+
+/* When on, each kernel of mm_apply_A / mm_solve is bracketed by HIP events on
+ * the context's stream and its time accumulated per stage (P, N^-1, P^T,
+ * precond, vector ops).  Stage names and totals via mm_profile_read. */
+mm_status mm_profile_enable(mm_ctx *ctx, int on);
+/* names [host] receives up to max entries of "name" (each <= 31 chars + NUL,
+ * 32 bytes per entry), ms [host] total milliseconds, calls [host] launches.
+ * *n receives the number of stages.  Resets the counters. */
+mm_status mm_profile_read(mm_ctx *ctx, int32_t max, char *names, double *ms, int64_t *calls,
+                          int32_t *n);
+
+/* ---------------------------------------------------- host-only utilities */
+
+/* Eigenvalues and eigenvectors of a real m x m upper Hessenberg matrix (the
+ * Ritz step of Appendix A), host FP64: Francis double-shift QR for the
+ * eigenvalues, inverse iteration for the vectors.  H [host] column-major
+ * m x m (entries below the subdiagonal ignored); wr, wi [host] f64[m];
+ * vr, vi [host] f64[m*m] column-major (eigenvector i in column i, unit
+ * 2-norm; a real eigenvalue has vi column 0).  Needs no GPU. */
+mm_status mm_hessenberg_eig(int32_t m, const double *H, double *wr, double *wi, double *vr,
+                            double *vi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAPMAKER_H */

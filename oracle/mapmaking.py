@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Pointing", "Noise", "OracleError", "pointing_build", "apply_P", "apply_PT",
     "noise_build", "noise_apply_direct", "noise_apply_fft", "noise_apply",
-    "apply_A", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
+    "apply_A", "apply_A_pixels", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
     "m2l_apply", "arnoldi", "ritz_select", "defl_build", "pcg", "SolveInfo",
     "dense_P", "dense_Ninv",
 ]
@@ -234,6 +234,33 @@ def dense_Ninv(nz: Noise) -> np.ndarray:
 
 def apply_A(pt: Pointing, nz: Noise, x, method: str = "direct") -> np.ndarray:
     return apply_PT(pt, noise_apply(nz, apply_P(pt, x), method))
+
+
+def apply_A_pixels(pt: Pointing, nz: Noise, x, pixels) -> np.ndarray:
+    """(A x) restricted to the listed compact pixels, each computed on its own
+    from the definition: for every sample t of the pixel,
+    z_t = sum_{u in I(t), |t-u| <= lambda} c_{|t-u|} (P x)_u, then
+    sum_t w_t z_t.  Cost is per requested pixel, so it serves as a check at
+    sizes where the whole product is too large for the oracle.
+    Returns f64[len(pixels), 3]."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    lam = nz.half_bw
+    out = np.zeros((len(pixels), 3))
+    for q, j in enumerate(pixels):
+        ts = pt.perm[pt.off[j]:pt.off[j + 1]]
+        for t in ts:
+            i = int(np.searchsorted(nz.interval_start, t, side="right") - 1)
+            a, b = int(nz.interval_start[i]), int(nz.interval_start[i + 1])
+            lo, hi = max(a, int(t) - lam), min(b, int(t) + lam + 1)
+            u = np.arange(lo, hi)
+            ju = pt.j[u]
+            m = ju >= 0
+            y = np.zeros(hi - lo)
+            y[m] = x[ju[m], 0] + pt.cos2[u[m]] * x[ju[m], 1] + pt.sin2[u[m]] * x[ju[m], 2]
+            c = nz.band[nz.filter_id[i]][np.abs(u - int(t))]
+            z = float(np.dot(c, y))
+            out[q] += z * np.array([1.0, pt.cos2[t], pt.sin2[t]])
+    return out
 
 
 def rhs(pt: Pointing, nz: Noise, d, method: str = "direct") -> np.ndarray:

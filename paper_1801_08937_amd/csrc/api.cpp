@@ -1,0 +1,925 @@
+// C-ABI entry points: argument validation, handle ownership, and the host
+// control loops (PCG, Arnoldi) that drive the device kernels.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+// ------------------------------------------------------------ profiler
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    MM_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Profiler::flush() {
+    for (auto &p : pending) {
+        MM_HIP(hipEventSynchronize(p.b));
+        float ms = 0;
+        MM_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        auto &st = stages[p.name];
+        st.ms += ms;
+        st.calls += 1;
+        pool.push_back(p.a);
+        pool.push_back(p.b);
+    }
+    pending.clear();
+}
+
+Profiler::~Profiler() {
+    for (auto &p : pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+Scope::Scope(Profiler &p, hipStream_t st, const char *n) : pr(&p), s(st), name(n) {
+    if (!pr->on) return;
+    a = pr->get();
+    b = pr->get();
+    (void)hipEventRecord(a, s);
+}
+
+Scope::~Scope() {
+    if (!pr->on) return;
+    (void)hipEventRecord(b, s);
+    pr->pending.push_back({name, a, b});
+    if (pr->pending.size() > 4096) {
+        try { pr->flush(); } catch (...) {}
+    }
+}
+
+void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz);
+
+}  // namespace mm
+
+using namespace mm;
+
+#define API_BEGIN(ctxp)                                   \
+    mm_ctx *api_ctx_ = (ctxp);                            \
+    try {                                                 \
+        if (api_ctx_) {                                   \
+            api_ctx_->last_error.clear();                 \
+            MM_HIP(hipSetDevice(api_ctx_->device));       \
+        }
+
+#define API_END                                                            \
+    }                                                                      \
+    catch (const mm::Error &e) {                                           \
+        if (api_ctx_) api_ctx_->last_error = e.what();                     \
+        return e.code;                                                     \
+    }                                                                      \
+    catch (const std::bad_alloc &) {                                       \
+        if (api_ctx_) api_ctx_->last_error = "host allocation failed";     \
+        return MM_E_OOM;                                                   \
+    }                                                                      \
+    catch (const std::exception &e) {                                      \
+        if (api_ctx_) api_ctx_->last_error = e.what();                     \
+        return MM_E_DEVICE;                                                \
+    }
+
+namespace {
+
+size_t tod_elem(mm_precision p) { return p == MM_F32 ? sizeof(float) : sizeof(double); }
+
+void check_nrhs(int nrhs) {
+    MM_CHECK(pow2_ok(nrhs), MM_E_INVALID, "nrhs must be 1, 2, 4, 8, 16, 32 or 64");
+}
+
+void check_pair(const mm_pointing *p, const mm_noise *nz) {
+    MM_CHECK(p && nz, MM_E_INVALID, "null pointing or noise handle");
+    MM_CHECK(p->n_samp == nz->n_samp, MM_E_INVALID,
+             "pointing and noise cover different numbers of samples");
+    MM_CHECK(p->prec == nz->prec, MM_E_INVALID, "pointing and noise precisions differ");
+}
+
+void ensure_tod(mm_ctx *ctx, const mm_pointing *p, int nrhs) {
+    const size_t b = tod_elem(p->prec) * (size_t)p->n_samp * nrhs;
+    ctx->tod_a.alloc(b);
+    ctx->tod_b.alloc(b);
+}
+
+void apply_A_impl(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, int nrhs,
+                  const double *x, double *y) {
+    ensure_tod(ctx, p, nrhs);
+    apply_P_dev(ctx, p, nrhs, x, ctx->tod_a.ptr);
+    noise_apply_dev(ctx, nz, nrhs, ctx->tod_a.ptr, ctx->tod_b.ptr);
+    apply_PT_dev(ctx, p, nrhs, ctx->tod_b.ptr, y);
+}
+
+double *pinned(mm_ctx *ctx, size_t bytes) {
+    if (ctx->pinned_bytes < bytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        void *p = nullptr;
+        MM_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        ctx->pinned = static_cast<double *>(p);
+        ctx->pinned_bytes = bytes;
+    }
+    return ctx->pinned;
+}
+
+void precond_apply_impl(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
+                        double *partial, int n_part) {
+    if (M->kind == 0)
+        mbd_apply_dev(ctx, M->inv.as<double>(), M->n_obs, nrhs, v, out, partial ? v : nullptr,
+                      partial, n_part);
+    else
+        m2l_apply_dev(ctx, M, nrhs, v, out, partial, n_part);
+}
+
+// M_2l from Z (device, column-major n x k): AZ, E = Z^T AZ, Cholesky on device.
+void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M) {
+    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int k = M->k;
+    M->AZ.alloc(sizeof(double) * n * k);
+    for (int c = 0; c < k; ++c)
+        apply_A_impl(ctx, p, nz, 1, M->Z.as<double>() + (int64_t)c * n,
+                     M->AZ.as<double>() + (int64_t)c * n);
+    M->E.alloc(sizeof(double) * k * k);
+    M->Lc.alloc(sizeof(double) * k * k);
+    gram_mfma(ctx, n, k, k, M->Z.as<double>(), 1, n, M->AZ.as<double>(), 1, n, M->E.as<double>());
+    DBuf flag;
+    flag.alloc(sizeof(int));
+    chol_small_dev(ctx, k, M->E.as<double>(), M->Lc.as<double>(), flag.as<int>());
+    int hf = 0;
+    MM_HIP(hipMemcpyAsync(&hf, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    MM_CHECK(!hf, MM_E_COARSE_NOT_SPD, "coarse matrix E = Z^T A Z is not positive definite");
+}
+
+int choose_tile(int64_t n_samp, int n_cu) {
+    int64_t per = n_samp / (4 * (int64_t)n_cu);
+    int tl = 256;
+    while (tl < 4096 && tl < per) tl <<= 1;
+    return tl;
+}
+
+}  // namespace
+
+// ================================================================ context
+
+extern "C" const char *mm_version(void) { return "mapmaker-mi355x 0.1"; }
+
+extern "C" mm_status mm_ctx_create(int device, void *hip_stream, mm_ctx **out) {
+    if (!out) return MM_E_INVALID;
+    *out = nullptr;
+    mm_ctx *ctx = nullptr;
+    try {
+        int ndev = 0;
+        MM_HIP(hipGetDeviceCount(&ndev));
+        MM_CHECK(device >= 0 && device < ndev, MM_E_INVALID, "no such device");
+        MM_HIP(hipSetDevice(device));
+        ctx = new mm_ctx();
+        ctx->device = device;
+        if (hip_stream) {
+            ctx->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            MM_HIP(hipStreamCreate(&ctx->stream));
+            ctx->own_stream = true;
+        }
+        hipDeviceProp_t prop;
+        MM_HIP(hipGetDeviceProperties(&prop, device));
+        ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        *out = ctx;
+        return MM_OK;
+    } catch (const mm::Error &e) {
+        delete ctx;
+        return e.code;
+    } catch (...) {
+        delete ctx;
+        return MM_E_DEVICE;
+    }
+}
+
+extern "C" void mm_ctx_destroy(mm_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" const char *mm_last_error(const mm_ctx *ctx) {
+    return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+// =============================================================== pointing
+
+extern "C" mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
+                                       const int32_t *pix, const double *psi, int32_t min_hits,
+                                       mm_precision prec, mm_pointing **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    MM_CHECK(n_samp > 0 && n_samp < ((int64_t)1 << 31), MM_E_INVALID,
+             "n_samp must be in (0, 2^31)");
+    MM_CHECK(n_pix_total > 0, MM_E_INVALID, "n_pix_total must be positive");
+    MM_CHECK(pix && psi, MM_E_INVALID, "null pix/psi");
+    MM_CHECK(min_hits >= 1, MM_E_INVALID, "min_hits must be >= 1");
+    MM_CHECK(prec == MM_F64 || prec == MM_F32, MM_E_INVALID, "bad precision");
+    auto *p = new mm_pointing();
+    p->n_samp = n_samp;
+    p->n_pix_total = n_pix_total;
+    p->prec = prec;
+    try {
+        pointing_build_device(ctx, p, pix, psi, min_hits);
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    *out = p;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pointing_counts(const mm_pointing *p, int32_t *n_obs, int64_t *n_valid) {
+    if (!p) return MM_E_INVALID;
+    if (n_obs) *n_obs = p->n_obs;
+    if (n_valid) *n_valid = p->n_valid;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pointing_hits(mm_ctx *ctx, const mm_pointing *p, int32_t *hits,
+                                      int32_t *obs_pix) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(p, MM_E_INVALID, "null pointing");
+    if (hits)
+        MM_HIP(hipMemcpyAsync(hits, p->hits.ptr, sizeof(int32_t) * p->n_pix_total,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    if (obs_pix && p->n_obs)
+        MM_HIP(hipMemcpyAsync(obs_pix, p->obs_pix.ptr, sizeof(int32_t) * p->n_obs,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pointing_export(mm_ctx *ctx, const mm_pointing *p, int32_t *j,
+                                        int32_t *perm, int32_t *off) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(p, MM_E_INVALID, "null pointing");
+    if (j)
+        MM_HIP(hipMemcpyAsync(j, p->j.ptr, sizeof(int32_t) * p->n_samp, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+    if (perm && p->n_valid)
+        MM_HIP(hipMemcpyAsync(perm, p->perm.ptr, sizeof(int32_t) * p->n_valid,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    if (off)
+        MM_HIP(hipMemcpyAsync(off, p->off.ptr, sizeof(int32_t) * (p->n_obs + 1),
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+    return MM_OK;
+}
+
+extern "C" void mm_pointing_destroy(mm_pointing *p) { delete p; }
+
+// ================================================================== noise
+
+extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
+                                    const int64_t *interval_start, const int32_t *filter_id,
+                                    int32_t n_filters, int32_t half_bw, const double *band,
+                                    mm_noise_method method, mm_precision prec, mm_noise **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    MM_CHECK(n_intervals > 0 && interval_start && filter_id && band, MM_E_INVALID,
+             "noise: empty or null arguments");
+    MM_CHECK(n_filters > 0 && half_bw >= 0, MM_E_INVALID, "noise: bad filter count or bandwidth");
+    MM_CHECK(prec == MM_F64 || prec == MM_F32, MM_E_INVALID, "bad precision");
+    MM_CHECK(interval_start[0] == 0, MM_E_INVALID, "intervals must start at sample 0");
+    int64_t min_len = INT64_MAX;
+    for (int i = 0; i < n_intervals; ++i) {
+        const int64_t L = interval_start[i + 1] - interval_start[i];
+        MM_CHECK(L > 0, MM_E_INVALID, "intervals must be strictly increasing");
+        min_len = std::min(min_len, L);
+        MM_CHECK(filter_id[i] >= 0 && filter_id[i] < n_filters, MM_E_INVALID,
+                 "filter id out of range");
+    }
+    MM_CHECK(2 * (int64_t)half_bw < min_len, MM_E_INVALID,
+             "half bandwidth must be below half the shortest interval");
+    MM_CHECK(interval_start[n_intervals] < ((int64_t)1 << 31), MM_E_INVALID, "too many samples");
+    const size_t nb = (size_t)n_filters * (half_bw + 1);
+    for (size_t i = 0; i < nb; ++i)
+        MM_CHECK(std::isfinite(band[i]), MM_E_NONFINITE, "non-finite band coefficient");
+    MM_CHECK(method == MM_NOISE_AUTO || method == MM_NOISE_DIRECT || method == MM_NOISE_FFT,
+             MM_E_INVALID, "bad noise method");
+
+    auto *nz = new mm_noise();
+    try {
+        nz->n_samp = interval_start[n_intervals];
+        nz->n_int = n_intervals;
+        nz->n_filters = n_filters;
+        nz->half_bw = half_bw;
+        nz->prec = prec;
+        nz->h_istart.assign(interval_start, interval_start + n_intervals + 1);
+        nz->h_fid.assign(filter_id, filter_id + n_intervals);
+        nz->h_band.assign(band, band + nb);
+        const bool fft_ok = noise_fft_supported(half_bw, min_len);
+        if (method == MM_NOISE_FFT) {
+            MM_CHECK(fft_ok, MM_E_INVALID, "FFT noise method unsupported for this bandwidth");
+            nz->method = MM_NOISE_FFT;
+        } else if (method == MM_NOISE_AUTO) {
+            nz->method = (fft_ok && half_bw >= 256) ? MM_NOISE_FFT : MM_NOISE_DIRECT;
+        } else {
+            nz->method = MM_NOISE_DIRECT;
+        }
+        hipStream_t s = ctx->stream;
+        nz->istart.alloc(sizeof(int64_t) * (n_intervals + 1));
+        nz->fid.alloc(sizeof(int32_t) * n_intervals);
+        nz->band64.alloc(sizeof(double) * nb);
+        MM_HIP(hipMemcpyAsync(nz->istart.ptr, interval_start, sizeof(int64_t) * (n_intervals + 1),
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipMemcpyAsync(nz->fid.ptr, filter_id, sizeof(int32_t) * n_intervals,
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipMemcpyAsync(nz->band64.ptr, band, sizeof(double) * nb, hipMemcpyHostToDevice, s));
+        if (prec == MM_F32) {
+            std::vector<float> bf(band, band + nb);
+            nz->band.alloc(sizeof(float) * nb);
+            MM_HIP(hipMemcpyAsync(nz->band.ptr, bf.data(), sizeof(float) * nb,
+                                  hipMemcpyHostToDevice, s));
+            MM_HIP(hipStreamSynchronize(s));
+        } else {
+            nz->band.alloc(sizeof(double) * nb);
+            MM_HIP(hipMemcpyAsync(nz->band.ptr, band, sizeof(double) * nb,
+                                  hipMemcpyHostToDevice, s));
+        }
+        // direct-band tile table: (first sample, interval) per tile
+        const int tl = choose_tile(nz->n_samp, ctx->n_cu);
+        std::vector<int64_t> tiles;
+        for (int i = 0; i < n_intervals; ++i)
+            for (int64_t t = interval_start[i]; t < interval_start[i + 1]; t += tl) {
+                tiles.push_back(t);
+                tiles.push_back(i);
+            }
+        nz->tile_len = tl;
+        nz->n_tiles = (int64_t)tiles.size() / 2;
+        nz->tiles.alloc(sizeof(int64_t) * tiles.size());
+        MM_HIP(hipMemcpyAsync(nz->tiles.ptr, tiles.data(), sizeof(int64_t) * tiles.size(),
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipStreamSynchronize(s));
+        if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
+    } catch (...) {
+        delete nz;
+        throw;
+    }
+    *out = nz;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method) {
+    if (!nz || !method) return MM_E_INVALID;
+    *method = nz->method;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_noise_apply(mm_ctx *ctx, const mm_noise *nz, int32_t nrhs, const void *y,
+                                    void *z) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(nz && y && z && y != z, MM_E_INVALID, "noise apply: bad arguments");
+    check_nrhs(nrhs);
+    noise_apply_dev(ctx, nz, nrhs, y, z);
+    API_END
+    return MM_OK;
+}
+
+extern "C" void mm_noise_destroy(mm_noise *nz) { delete nz; }
+
+// ============================================================== operators
+
+extern "C" mm_status mm_apply_P(mm_ctx *ctx, const mm_pointing *p, int32_t nrhs, const double *x,
+                                void *y) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(p && x && y, MM_E_INVALID, "apply_P: null argument");
+    check_nrhs(nrhs);
+    apply_P_dev(ctx, p, nrhs, x, y);
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_apply_PT(mm_ctx *ctx, const mm_pointing *p, int32_t nrhs, const void *z,
+                                 double *x) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(p && x && z, MM_E_INVALID, "apply_PT: null argument");
+    check_nrhs(nrhs);
+    apply_PT_dev(ctx, p, nrhs, z, x);
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_apply_A(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                int32_t nrhs, const double *x, double *y) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    MM_CHECK(x && y && x != y, MM_E_INVALID, "apply_A: x and y must be distinct and non-null");
+    check_nrhs(nrhs);
+    apply_A_impl(ctx, p, nz, nrhs, x, y);
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_rhs(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, int32_t nrhs,
+                            const void *tod, double *b) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    MM_CHECK(tod && b, MM_E_INVALID, "rhs: null argument");
+    check_nrhs(nrhs);
+    ensure_tod(ctx, p, nrhs);
+    DBuf flag;
+    flag.alloc(sizeof(int));
+    MM_HIP(hipMemsetAsync(flag.ptr, 0, sizeof(int), ctx->stream));
+    mask_tod_dev(ctx, p, nrhs, tod, ctx->tod_a.ptr, flag.as<int>());
+    int hf = 0;
+    MM_HIP(hipMemcpyAsync(&hf, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    MM_CHECK(!hf, MM_E_NONFINITE, "rhs: non-finite TOD sample on an observed pixel");
+    noise_apply_dev(ctx, nz, nrhs, ctx->tod_a.ptr, ctx->tod_b.ptr);
+    apply_PT_dev(ctx, p, nrhs, ctx->tod_b.ptr, b);
+    API_END
+    return MM_OK;
+}
+
+// ======================================================== preconditioners
+
+extern "C" mm_status mm_mbd_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                  mm_precond **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    auto *M = new mm_precond();
+    M->kind = 0;
+    M->n_obs = p->n_obs;
+    int bad = 0;
+    try {
+        mbd_build_dev(ctx, p, nz, M, &bad);
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    if (bad) {
+        delete M;
+        throw Error(MM_E_SINGULAR_BLOCK,
+                    std::to_string(bad) + " pixel block(s) singular or with rcond < 1e-12");
+    }
+    *out = M;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_mbd_rcond(const mm_precond *M, double *rcond_min) {
+    if (!M || !rcond_min) return MM_E_INVALID;
+    *rcond_min = M->rcond_min;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_defl_from_Z(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                    const mm_precond *mbd, int32_t k, const double *Z,
+                                    mm_precond **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs, MM_E_INVALID,
+             "defl: needs an M_BD handle of the same pointing");
+    MM_CHECK(k >= 1 && k <= 64 && k <= 3 * p->n_obs, MM_E_INVALID, "defl: k must be in [1, 64]");
+    MM_CHECK(Z, MM_E_INVALID, "defl: null Z");
+    const int64_t n = 3 * (int64_t)p->n_obs;
+    auto *M = new mm_precond();
+    try {
+        M->kind = 1;
+        M->n_obs = p->n_obs;
+        M->k = k;
+        M->rcond_min = mbd->rcond_min;
+        M->inv.alloc(sizeof(double) * 6 * p->n_obs);
+        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * 6 * p->n_obs,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        M->Z.alloc(sizeof(double) * n * k);
+        MM_HIP(hipMemcpyAsync(M->Z.ptr, Z, sizeof(double) * n * k, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+        finish_m2l(ctx, p, nz, M);
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    *out = M;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                   const mm_precond *mbd, const double *b_seed, int32_t k,
+                                   double eps_lambda, double eps_arn, int32_t m_max,
+                                   double *h_history, mm_arnoldi_info *info, mm_precond **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    auto t_start = std::chrono::steady_clock::now();
+    check_pair(p, nz);
+    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs, MM_E_INVALID,
+             "defl: needs an M_BD handle of the same pointing");
+    MM_CHECK(b_seed, MM_E_INVALID, "defl: null b_seed");
+    const int64_t n = 3 * (int64_t)p->n_obs;
+    MM_CHECK(m_max >= 1 && m_max <= 500 && m_max <= n, MM_E_INVALID, "defl: m_max in [1, min(500, n)]");
+    MM_CHECK(eps_lambda > 0 || (k >= 1 && k <= 63 && k <= m_max), MM_E_INVALID,
+             "defl: k in [1, 63] and <= m_max");
+    hipStream_t s = ctx->stream;
+    auto *M = new mm_precond();
+    try {
+        M->kind = 1;
+        M->n_obs = p->n_obs;
+        M->rcond_min = mbd->rcond_min;
+        M->inv.alloc(sizeof(double) * 6 * p->n_obs);
+        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * 6 * p->n_obs,
+                              hipMemcpyDeviceToDevice, s));
+        M->W.alloc(sizeof(double) * n * (m_max + 1));
+        double *W = M->W.as<double>();
+        DBuf tmp, v, hd;
+        tmp.alloc(sizeof(double) * n);
+        v.alloc(sizeof(double) * n);
+        hd.alloc(sizeof(double) * 1024);
+        double *hp = pinned(ctx, sizeof(double) * 1024);
+        // w_1 = r_0 / ||r_0||, r_0 = M_BD b
+        mbd_apply_dev(ctx, M->inv.as<double>(), p->n_obs, 1, b_seed, v.as<double>(), nullptr,
+                      nullptr, 0);
+        dot_cols(ctx, n, 1, v.as<double>(), v.as<double>(), hd.as<double>());
+        MM_HIP(hipMemcpyAsync(hp, hd.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+        MM_HIP(hipStreamSynchronize(s));
+        MM_CHECK(hp[0] > 0 && std::isfinite(hp[0]), MM_E_INVALID, "defl: zero start vector");
+        const double nrm0 = std::sqrt(hp[0]);
+        hp[1] = nrm0;
+        MM_HIP(hipMemcpyAsync(hd.as<double>() + 1, hp + 1, sizeof(double), hipMemcpyHostToDevice, s));
+        scale_copy(ctx, n, v.as<double>(), hd.as<double>() + 1, W, 1);
+        std::vector<double> H((size_t)(m_max + 1) * m_max, 0.0);
+        int m = 0;
+        double h_last = 0;
+        for (int j = 0; j < m_max; ++j) {
+            const double *wj = W + (int64_t)j * n;
+            apply_A_impl(ctx, p, nz, 1, wj, tmp.as<double>());
+            mbd_apply_dev(ctx, M->inv.as<double>(), p->n_obs, 1, tmp.as<double>(),
+                          v.as<double>(), nullptr, nullptr, 0);
+            // classical Gram-Schmidt, applied twice
+            gemv_t(ctx, n, j + 1, W, v.as<double>(), hd.as<double>());
+            gemv_n_sub(ctx, n, j + 1, W, hd.as<double>(), v.as<double>());
+            gemv_t(ctx, n, j + 1, W, v.as<double>(), hd.as<double>() + 512);
+            gemv_n_sub(ctx, n, j + 1, W, hd.as<double>() + 512, v.as<double>());
+            dot_cols(ctx, n, 1, v.as<double>(), v.as<double>(), hd.as<double>() + 1023);
+            MM_HIP(hipMemcpyAsync(hp, hd.ptr, sizeof(double) * 1024, hipMemcpyDeviceToHost, s));
+            MM_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)j * (m_max + 1) + i] = hp[i] + hp[512 + i];
+            const double hn = std::sqrt(std::max(hp[1023], 0.0));
+            H[(size_t)j * (m_max + 1) + j + 1] = hn;
+            if (h_history) h_history[j] = hn;
+            m = j + 1;
+            h_last = hn;
+            if (!(hn > eps_arn)) break;
+            hp[0] = hn;
+            MM_HIP(hipMemcpyAsync(hd.ptr, hp, sizeof(double), hipMemcpyHostToDevice, s));
+            scale_copy(ctx, n, v.as<double>(), hd.as<double>(), W + (int64_t)(j + 1) * n, 1);
+        }
+        M->arn_m = m;
+        M->H.assign((size_t)(m + 1) * m, 0.0);
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i <= m; ++i)
+                M->H[(size_t)j * (m + 1) + i] = H[(size_t)j * (m_max + 1) + i];
+        // Ritz pairs of H_m
+        std::vector<double> Hm((size_t)m * m), wr(m), wi(m), vr((size_t)m * m), vi((size_t)m * m);
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) Hm[(size_t)j * m + i] = H[(size_t)j * (m_max + 1) + i];
+        hessenberg_eig(m, Hm.data(), wr.data(), wi.data(), vr.data(), vi.data());
+        int keep;
+        if (eps_lambda > 0) {
+            keep = 0;
+            while (keep < m && wr[keep] < eps_lambda) ++keep;
+        } else {
+            keep = std::min(k, m);
+        }
+        auto pair_at = [&](int i) { return i + 1 < m && wi[i] != 0 && wi[i] == -wi[i + 1] && wr[i] == wr[i + 1]; };
+        if (keep > 0 && keep < m && wi[keep - 1] != 0 && pair_at(keep - 1)) ++keep;
+        std::vector<double> Y;
+        int kk = 0;
+        for (int i = 0; i < keep && kk < 64;) {
+            if (pair_at(i)) {
+                if (kk + 2 > 64) break;
+                Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);
+                Y.insert(Y.end(), vi.begin() + (size_t)i * m, vi.begin() + (size_t)(i + 1) * m);
+                kk += 2;
+                i += 2;
+            } else {
+                Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);
+                kk += 1;
+                i += 1;
+            }
+        }
+        MM_CHECK(kk >= 1, MM_E_INVALID, "defl: no Ritz vector selected");
+        // V = W_m Y, then Cholesky-QR applied twice for an orthonormal Z
+        DBuf Yd, V, G;
+        Yd.alloc(sizeof(double) * Y.size());
+        MM_HIP(hipMemcpyAsync(Yd.ptr, Y.data(), sizeof(double) * Y.size(), hipMemcpyHostToDevice, s));
+        V.alloc(sizeof(double) * n * kk);
+        M->Z.alloc(sizeof(double) * n * kk);
+        matmul_small_right(ctx, n, m, kk, W, Yd.as<double>(), V.as<double>());
+        G.alloc(sizeof(double) * kk * kk);
+        std::vector<double> g((size_t)kk * kk), rinv((size_t)kk * kk);
+        for (int pass = 0; pass < 2; ++pass) {
+            double *src = pass == 0 ? V.as<double>() : M->Z.as<double>();
+            double *dst = pass == 0 ? M->Z.as<double>() : V.as<double>();
+            gram_mfma(ctx, n, kk, kk, src, 1, n, src, 1, n, G.as<double>());
+            MM_HIP(hipMemcpyAsync(g.data(), G.ptr, sizeof(double) * kk * kk, hipMemcpyDeviceToHost, s));
+            MM_HIP(hipStreamSynchronize(s));
+            // upper Cholesky factor R (G = R^T R), then R^-1 (column-major for the kernel)
+            std::vector<double> R((size_t)kk * kk, 0.0);
+            for (int c = 0; c < kk; ++c) {
+                for (int r2 = 0; r2 <= c; ++r2) {
+                    double sum = 0.5 * (g[(size_t)r2 * kk + c] + g[(size_t)c * kk + r2]);
+                    for (int q = 0; q < r2; ++q) sum -= R[(size_t)q * kk + r2] * R[(size_t)q * kk + c];
+                    if (r2 == c) {
+                        MM_CHECK(sum > 0, MM_E_COARSE_NOT_SPD, "defl: Ritz vectors linearly dependent");
+                        R[(size_t)c * kk + c] = std::sqrt(sum);
+                    } else {
+                        R[(size_t)r2 * kk + c] = sum / R[(size_t)r2 * kk + r2];
+                    }
+                }
+            }
+            std::fill(rinv.begin(), rinv.end(), 0.0);
+            for (int c = 0; c < kk; ++c) {  // solve R x = e_c
+                std::vector<double> x(kk, 0.0);
+                for (int r2 = c; r2 >= 0; --r2) {
+                    double sum = (r2 == c) ? 1.0 : 0.0;
+                    for (int q = r2 + 1; q <= c; ++q) sum -= R[(size_t)r2 * kk + q] * x[q];
+                    x[r2] = sum / R[(size_t)r2 * kk + r2];
+                }
+                for (int r2 = 0; r2 < kk; ++r2) rinv[(size_t)c * kk + r2] = x[r2];
+            }
+            MM_HIP(hipMemcpyAsync(G.ptr, rinv.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
+            matmul_small_right(ctx, n, kk, kk, src, G.as<double>(), dst);
+            MM_HIP(hipStreamSynchronize(s));
+        }
+        // after two passes the orthonormal basis is in V
+        std::swap(M->Z, V);
+        M->k = kk;
+        finish_m2l(ctx, p, nz, M);
+        if (info) {
+            info->m = m;
+            info->k = kk;
+            info->h_last = h_last;
+            info->setup_seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        }
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    *out = M;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_defl_export(mm_ctx *ctx, const mm_precond *M, int32_t *k, double *Z,
+                                    double *AZ, double *E) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(M && M->kind == 1, MM_E_INVALID, "defl_export: not an M_2l handle");
+    const int64_t n = 3 * (int64_t)M->n_obs;
+    if (k) *k = M->k;
+    if (Z) MM_HIP(hipMemcpyAsync(Z, M->Z.ptr, sizeof(double) * n * M->k, hipMemcpyDeviceToDevice, ctx->stream));
+    if (AZ) MM_HIP(hipMemcpyAsync(AZ, M->AZ.ptr, sizeof(double) * n * M->k, hipMemcpyDeviceToDevice, ctx->stream));
+    if (E) MM_HIP(hipMemcpyAsync(E, M->E.ptr, sizeof(double) * M->k * M->k, hipMemcpyDeviceToDevice, ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_defl_arnoldi_export(mm_ctx *ctx, const mm_precond *M, int32_t *m,
+                                            double *W, double *H) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(M && M->kind == 1, MM_E_INVALID, "arnoldi_export: not an M_2l handle");
+    const int64_t n = 3 * (int64_t)M->n_obs;
+    if (m) *m = M->arn_m;
+    if (W && M->arn_m > 0)
+        MM_HIP(hipMemcpyAsync(W, M->W.ptr, sizeof(double) * n * (M->arn_m + 1),
+                              hipMemcpyDeviceToDevice, ctx->stream));
+    if (H) std::memcpy(H, M->H.data(), sizeof(double) * M->H.size());
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_precond_apply(mm_ctx *ctx, const mm_precond *M, int32_t nrhs,
+                                      const double *v, double *out) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(M && v && out && v != out, MM_E_INVALID, "precond_apply: bad arguments");
+    check_nrhs(nrhs);
+    precond_apply_impl(ctx, M, nrhs, v, out, nullptr, 0);
+    API_END
+    return MM_OK;
+}
+
+extern "C" void mm_precond_destroy(mm_precond *M) { delete M; }
+
+// ================================================================== solve
+
+extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                              const mm_precond *M, int32_t nrhs, const double *b, double *x,
+                              double tol, int32_t max_iter, uint32_t flags, double *history,
+                              mm_solve_info *info) {
+    if (!ctx) return MM_E_INVALID;
+    mm_status result = MM_OK;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    check_nrhs(nrhs);
+    MM_CHECK(b && x && b != x, MM_E_INVALID, "solve: bad b/x");
+    MM_CHECK(tol >= 0 && max_iter >= 0, MM_E_INVALID, "solve: bad tol/max_iter");
+    MM_CHECK(!M || M->n_obs == p->n_obs, MM_E_INVALID, "solve: preconditioner of another pointing");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = ctx->stream;
+    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int R = nrhs;
+    const size_t vb = sizeof(double) * n * R;
+    DBuf r, z, pv, q, sc, part, hist;
+    r.alloc(vb);
+    z.alloc(vb);
+    pv.alloc(vb);
+    q.alloc(vb);
+    sc.alloc(sizeof(double) * 7 * 64 + sizeof(int) * 3 * 64);
+    const int n_part = reduction_parts(n);
+    part.alloc(sizeof(double) * n_part * R);
+    hist.alloc(sizeof(double) * (size_t)(max_iter + 1) * R);
+    PcgDev sd;
+    double *sb = sc.as<double>();
+    sd.rho = sb; sd.pq = sb + 64; sd.alpha = sb + 128; sd.beta = sb + 192;
+    sd.rn2 = sb + 256; sd.bn2 = sb + 320; sd.tol2 = sb + 384;
+    int *ib = reinterpret_cast<int *>(sb + 448);
+    sd.done = ib; sd.brk = ib + 64; sd.iters = ib + 128;
+    pcg_init_scalars(ctx, R, sd, tol);
+    dot_cols(ctx, n, R, b, b, sd.bn2);
+    // r = b - A x0
+    apply_A_impl(ctx, p, nz, R, x, q.as<double>());
+    axpby_cols(ctx, n, R, b, q.as<double>(), r.as<double>());
+    dot_partial_cols(ctx, n, R, r.as<double>(), r.as<double>(), part.as<double>(), n_part);
+    pcg_after_rn(ctx, R, sd, part.as<double>(), n_part, 0);
+    // z = M r, rho = r.z
+    auto apply_M = [&](const double *in, double *outv) {
+        if (M) {
+            precond_apply_impl(ctx, M, R, in, outv, part.as<double>(), n_part);
+        } else {
+            MM_HIP(hipMemcpyAsync(outv, in, vb, hipMemcpyDeviceToDevice, s));
+            dot_partial_cols(ctx, n, R, in, outv, part.as<double>(), n_part);
+        }
+    };
+    apply_M(r.as<double>(), z.as<double>());
+    pcg_after_rz(ctx, R, sd, part.as<double>(), n_part, 1);
+    MM_HIP(hipMemcpyAsync(pv.ptr, z.ptr, vb, hipMemcpyDeviceToDevice, s));
+    // device-side residual history: rn2 per iteration
+    const size_t hb = sizeof(double) * (size_t)(max_iter + 1) * R;
+    std::vector<double> h_rn2((size_t)(max_iter + 1) * R, -1.0);
+    double *hpin = pinned(ctx, sizeof(double) * 64 * 3 + sizeof(int) * 64 * 3);
+    MM_HIP(hipMemcpyAsync(hist.ptr, sd.rn2, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
+    const int check = std::max(1u, flags & 0xffu);
+    int it = 0;
+    auto poll = [&]() -> bool {
+        MM_HIP(hipMemcpyAsync(hpin, sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        MM_HIP(hipStreamSynchronize(s));
+        const int *dn = reinterpret_cast<const int *>(hpin);
+        for (int c = 0; c < R; ++c)
+            if (!dn[c]) return false;
+        return true;
+    };
+    bool all_done = poll();
+    while (!all_done && it < max_iter) {
+        apply_A_impl(ctx, p, nz, R, pv.as<double>(), q.as<double>());
+        dot_partial_cols(ctx, n, R, pv.as<double>(), q.as<double>(), part.as<double>(), n_part);
+        pcg_after_pq(ctx, R, sd, part.as<double>(), n_part);
+        pcg_update_xr(ctx, n, R, sd, pv.as<double>(), q.as<double>(), x, r.as<double>(),
+                      part.as<double>(), n_part);
+        pcg_after_rn(ctx, R, sd, part.as<double>(), n_part, 1);
+        ++it;
+        MM_HIP(hipMemcpyAsync(hist.as<double>() + (size_t)it * R, sd.rn2, sizeof(double) * R,
+                              hipMemcpyDeviceToDevice, s));
+        apply_M(r.as<double>(), z.as<double>());
+        pcg_after_rz(ctx, R, sd, part.as<double>(), n_part, 0);
+        pcg_update_p(ctx, n, R, sd, z.as<double>(), pv.as<double>());
+        if (it % check == 0 || it == max_iter) all_done = poll();
+    }
+    // true residual
+    apply_A_impl(ctx, p, nz, R, x, q.as<double>());
+    axpby_cols(ctx, n, R, b, q.as<double>(), r.as<double>());
+    DBuf tr;
+    tr.alloc(sizeof(double) * R);
+    dot_cols(ctx, n, R, r.as<double>(), r.as<double>(), tr.as<double>());
+    std::vector<double> h_tr(R), h_bn2(R), h_rn(R);
+    std::vector<int> h_done(R), h_brk(R), h_it(R);
+    MM_HIP(hipMemcpyAsync(h_tr.data(), tr.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_bn2.data(), sd.bn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_rn.data(), sd.rn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_done.data(), sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_brk.data(), sd.brk, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_it.data(), sd.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_rn2.data(), hist.ptr, sizeof(double) * (size_t)(it + 1) * R,
+                          hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    (void)hb;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool any_brk = false, all_conv = true;
+    for (int c = 0; c < R; ++c) {
+        const double bn = h_bn2[c] > 0 ? std::sqrt(h_bn2[c]) : 1.0;
+        const bool conv = !h_brk[c] && h_rn[c] <= tol * tol * h_bn2[c];
+        any_brk |= h_brk[c] != 0;
+        all_conv &= conv;
+        if (info) {
+            info[c].iters = h_it[c];
+            info[c].converged = conv ? 1 : 0;
+            info[c].breakdown = h_brk[c];
+            info[c].pad = 0;
+            info[c].rel_res_recursive = std::sqrt(std::max(h_rn[c], 0.0)) / bn;
+            info[c].rel_res_true = std::sqrt(std::max(h_tr[c], 0.0)) / bn;
+            info[c].solve_seconds = secs;
+        }
+        if (history) {
+            for (int k2 = 0; k2 <= max_iter; ++k2) {
+                double v = -1.0;
+                if (k2 <= h_it[c] && k2 <= it) v = std::sqrt(std::max(h_rn2[(size_t)k2 * R + c], 0.0)) / bn;
+                history[(size_t)c * (max_iter + 1) + k2] = v;
+            }
+        }
+    }
+    result = any_brk ? MM_E_BREAKDOWN : (all_conv ? MM_OK : MM_NOT_CONVERGED);
+    if (any_brk) ctx->last_error = "PCG breakdown: p^T A p <= 0";
+    API_END
+    return result;
+}
+
+// ============================================================== profiling
+
+extern "C" mm_status mm_profile_enable(mm_ctx *ctx, int on) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    ctx->prof.flush();
+    ctx->prof.on = on != 0;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_profile_read(mm_ctx *ctx, int32_t max, char *names, double *ms,
+                                     int64_t *calls, int32_t *n) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    ctx->prof.flush();
+    int i = 0;
+    for (auto &kv : ctx->prof.stages) {
+        if (i < max) {
+            if (names) {
+                std::memset(names + 32 * i, 0, 32);
+                std::strncpy(names + 32 * i, kv.first.c_str(), 31);
+            }
+            if (ms) ms[i] = kv.second.ms;
+            if (calls) calls[i] = kv.second.calls;
+        }
+        ++i;
+    }
+    if (n) *n = i;
+    ctx->prof.stages.clear();
+    API_END
+    return MM_OK;
+}
+
+// =============================================================== host-only
+
+extern "C" mm_status mm_hessenberg_eig(int32_t m, const double *H, double *wr, double *wi,
+                                       double *vr, double *vi) {
+    if (m < 1 || !H || !wr || !wi || !vr || !vi) return MM_E_INVALID;
+    try {
+        hessenberg_eig(m, H, wr, wi, vr, vi);
+    } catch (const mm::Error &e) {
+        return e.code;
+    } catch (...) {
+        return MM_E_DEVICE;
+    }
+    return MM_OK;
+}

@@ -1,0 +1,828 @@
+// Map-domain kernels: M_BD build/apply (Eq. mbd), deterministic column
+// reductions, PCG vector updates (Eq. pcg), the skinny dense products of the
+// two-level preconditioner (Eq. m2l) and of the Arnoldi process (Alg.
+// arnoldi), the FP64 MFMA Gram product used for E = Z^T (A Z), and the small
+// on-device Cholesky of E.
+//
+// All reductions are two-stage with a fixed partition and a fixed tree, so
+// results are bitwise repeatable run to run; no floating-point atomics.
+#include "mm_internal.h"
+
+namespace mm {
+
+template <typename T> struct Vec2w;
+template <> struct Vec2w<float> { using type = float2; };
+template <> struct Vec2w<double> { using type = double2; };
+
+namespace {
+
+constexpr int BS = 256;
+
+// ------------------------------------------------------------------ M_BD
+
+__device__ __forceinline__ int64_t find_interval(const int64_t *__restrict__ istart, int n_int,
+                                                 int64_t t) {
+    int lo = 0, hi = n_int;  // istart[lo] <= t < istart[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (istart[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// One wave per compact pixel: B_j = sum c0 (1,c,s)(1,c,s)^T; lane 0 inverts.
+template <typename T>
+__global__ void __launch_bounds__(BS) k_mbd_build(const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ perm,
+                                                  const typename Vec2w<T>::type *__restrict__ ws,
+                                                  const int64_t *__restrict__ istart, int n_int,
+                                                  const int32_t *__restrict__ fid,
+                                                  const double *__restrict__ band64, int lam,
+                                                  int32_t n_obs, double *__restrict__ inv,
+                                                  double *__restrict__ rcond,
+                                                  int *__restrict__ n_bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (j >= n_obs) return;
+    const int32_t a = off[j], b = off[j + 1];
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t i = a + lane; i < b; i += 64) {
+        const int64_t t = perm[i];
+        const double c0 = band64[(int64_t)fid[find_interval(istart, n_int, t)] * (lam + 1)];
+        const auto ww = ws[i];
+        const double c = (double)ww.x, sn = (double)ww.y;
+        s[0] += c0;
+        s[1] += c0 * c;
+        s[2] += c0 * sn;
+        s[3] += c0 * c * c;
+        s[4] += c0 * c * sn;
+        s[5] += c0 * sn * sn;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s[q] += __shfl_xor(s[q], m);
+    if (lane != 0) return;
+    // Cholesky B = L L^T with positive pivots
+    const double b00 = s[0], b01 = s[1], b02 = s[2], b11 = s[3], b12 = s[4], b22 = s[5];
+    bool ok = b00 > 0;
+    double l00 = ok ? sqrt(b00) : 1, l10 = b01 / l00, l20 = b02 / l00;
+    double d1 = b11 - l10 * l10;
+    ok = ok && d1 > 0;
+    double l11 = d1 > 0 ? sqrt(d1) : 1, l21 = (b12 - l20 * l10) / l11;
+    double d2 = b22 - l20 * l20 - l21 * l21;
+    ok = ok && d2 > 0;
+    double l22 = d2 > 0 ? sqrt(d2) : 1;
+    // L^-1 (lower) then B^-1 = L^-T L^-1
+    const double m00 = 1 / l00, m11 = 1 / l11, m22 = 1 / l22;
+    const double m10 = -l10 * m00 * m11;
+    const double m21 = -l21 * m11 * m22;
+    const double m20 = -(l20 * m00 + l21 * m10) * m22;
+    double i00 = m00 * m00 + m10 * m10 + m20 * m20;
+    double i01 = m11 * m10 + m21 * m20;
+    double i02 = m22 * m20;
+    double i11 = m11 * m11 + m21 * m21;
+    double i12 = m22 * m21;
+    double i22 = m22 * m22;
+    double nb = fmax(fabs(b00) + fabs(b01) + fabs(b02),
+                     fmax(fabs(b01) + fabs(b11) + fabs(b12), fabs(b02) + fabs(b12) + fabs(b22)));
+    double ni = fmax(fabs(i00) + fabs(i01) + fabs(i02),
+                     fmax(fabs(i01) + fabs(i11) + fabs(i12), fabs(i02) + fabs(i12) + fabs(i22)));
+    double rc = ok ? 1.0 / (nb * ni) : 0.0;
+    if (!(rc >= 1e-12)) {
+        atomicAdd(n_bad, 1);
+        ok = false;
+    }
+    rcond[j] = ok ? rc : 0.0;
+    double *o = inv + 6 * j;
+    o[0] = i00; o[1] = i01; o[2] = i02; o[3] = i11; o[4] = i12; o[5] = i22;
+}
+
+__global__ void k_min_reduce(const double *__restrict__ v, int64_t n, double *__restrict__ out) {
+    __shared__ double sm[BS];
+    double m = 1e300;
+    for (int64_t i = threadIdx.x; i < n; i += BS) m = fmin(m, v[i]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+// Block-column partial sums: thread (rg, r) accumulates rows rg, rg + 256/R, ...
+// of the block's row range; the 256/R row groups are then combined per column by
+// a fixed halving tree in LDS.  partial[blk * R + r].
+template <int R>
+__device__ __forceinline__ void block_col_reduce(double v, double *__restrict__ partial) {
+    __shared__ double sm[BS];
+    constexpr int NG = BS / R;
+    const int r = threadIdx.x % R, rg = threadIdx.x / R;
+    sm[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NG / 2; s > 0; s >>= 1) {
+        if (rg < s) sm[rg * R + r] += sm[(rg + s) * R + r];
+        __syncthreads();
+    }
+    if (rg == 0) partial[(int64_t)blockIdx.x * R + r] = sm[r];
+}
+
+// out = B_j^-1 v per pixel and column; optionally partial sums of
+// dot_with . out per column (fused r.z of PCG).
+template <int R>
+__global__ void __launch_bounds__(BS) k_mbd_apply(const double *__restrict__ inv, int32_t n_obs,
+                                                  const double *__restrict__ v,
+                                                  double *__restrict__ out,
+                                                  const double *__restrict__ dot_with,
+                                                  double *__restrict__ partial,
+                                                  int64_t pix_per_block) {
+    constexpr int NG = BS / R;
+    const int r = threadIdx.x % R, rg = threadIdx.x / R;
+    const int64_t p0 = (int64_t)blockIdx.x * pix_per_block;
+    int64_t p1 = p0 + pix_per_block;
+    if (p1 > n_obs) p1 = n_obs;
+    double acc = 0;
+    for (int64_t j = p0 + rg; j < p1; j += NG) {
+        const double *m = inv + 6 * j;
+        const int64_t base = 3 * j * R + r;
+        const double v0 = v[base], v1 = v[base + R], v2 = v[base + 2 * R];
+        const double o0 = m[0] * v0 + m[1] * v1 + m[2] * v2;
+        const double o1 = m[1] * v0 + m[3] * v1 + m[4] * v2;
+        const double o2 = m[2] * v0 + m[4] * v1 + m[5] * v2;
+        out[base] = o0;
+        out[base + R] = o1;
+        out[base + 2 * R] = o2;
+        if (dot_with) acc += dot_with[base] * o0 + dot_with[base + R] * o1 +
+                             dot_with[base + 2 * R] * o2;
+    }
+    if (partial) block_col_reduce<R>(acc, partial);
+}
+
+// ------------------------------------------------------------- reductions
+
+template <int R>
+__global__ void __launch_bounds__(BS) k_dot_partial(int64_t n, const double *__restrict__ a,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ partial,
+                                                    int64_t rows_per_block) {
+    constexpr int NG = BS / R;
+    const int r = threadIdx.x % R, rg = threadIdx.x / R;
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    int64_t i1 = i0 + rows_per_block;
+    if (i1 > n) i1 = n;
+    double acc = 0;
+    for (int64_t i = i0 + rg; i < i1; i += NG) acc += a[i * R + r] * b[i * R + r];
+    block_col_reduce<R>(acc, partial);
+}
+
+// Second stage: one wave per column sums partial[b * R + r] over b in a fixed
+// order (lane-strided, then a xor butterfly).
+__device__ __forceinline__ double wave_sum_parts(const double *__restrict__ partial, int n_part,
+                                                 int R, int r) {
+    const int lane = threadIdx.x & 63;
+    double s = 0;
+    for (int b = lane; b < n_part; b += 64) s += partial[(int64_t)b * R + r];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    return s;
+}
+
+__global__ void k_dot_final(const double *__restrict__ partial, int n_part, int R,
+                            double *__restrict__ out) {
+    const int r = blockIdx.x;
+    const double s = wave_sum_parts(partial, n_part, R, r);
+    if ((threadIdx.x & 63) == 0) out[r] = s;
+}
+
+// ------------------------------------------------------------------- PCG
+
+__global__ void k_pcg_init(int R, PcgDev s, double tol) {
+    const int r = threadIdx.x;
+    if (r >= R) return;
+    s.done[r] = 0;
+    s.brk[r] = 0;
+    s.iters[r] = 0;
+    s.tol2[r] = tol * tol;
+}
+
+// r = b - Ax  (all columns)
+template <int R>
+__global__ void __launch_bounds__(BS) k_axpby(int64_t n, const double *__restrict__ b,
+                                              const double *__restrict__ ax,
+                                              double *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n * R;
+         e += (int64_t)gridDim.x * BS)
+        out[e] = b[e] - ax[e];
+}
+
+// alpha = rho / p.q, breakdown if p.q <= 0
+__global__ void k_pcg_alpha(const double *__restrict__ partial, int n_part, int R, PcgDev s) {
+    const int r = blockIdx.x;
+    const double pq = wave_sum_parts(partial, n_part, R, r);
+    if ((threadIdx.x & 63) != 0) return;
+    s.pq[r] = pq;
+    if (s.done[r]) return;
+    if (!(pq > 0.0)) {
+        s.brk[r] = 1;
+        s.done[r] = 1;
+        s.alpha[r] = 0;
+        return;
+    }
+    s.alpha[r] = s.rho[r] / pq;
+}
+
+// x += alpha p; r -= alpha q (live columns); partial ||r||^2
+template <int R>
+__global__ void __launch_bounds__(BS) k_pcg_xr(int64_t n, PcgDev s, const double *__restrict__ p,
+                                               const double *__restrict__ q,
+                                               double *__restrict__ x, double *__restrict__ rr,
+                                               double *__restrict__ partial,
+                                               int64_t rows_per_block) {
+    constexpr int NG = BS / R;
+    const int r = threadIdx.x % R, rg = threadIdx.x / R;
+    const bool live = !s.done[r];
+    const double al = s.alpha[r];
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    int64_t i1 = i0 + rows_per_block;
+    if (i1 > n) i1 = n;
+    double acc = 0;
+    for (int64_t i = i0 + rg; i < i1; i += NG) {
+        const int64_t e = i * R + r;
+        double rv = rr[e];
+        if (live) {
+            x[e] += al * p[e];
+            rv -= al * q[e];
+            rr[e] = rv;
+        }
+        acc += rv * rv;
+    }
+    block_col_reduce<R>(acc, partial);
+}
+
+// ||r||^2; iteration count and convergence flag
+__global__ void k_pcg_rn(const double *__restrict__ partial, int n_part, int R, PcgDev s,
+                         int count_iter) {
+    const int r = blockIdx.x;
+    const double rn = wave_sum_parts(partial, n_part, R, r);
+    if ((threadIdx.x & 63) != 0) return;
+    if (count_iter) {
+        if (s.done[r]) return;
+        s.iters[r] += 1;
+    }
+    s.rn2[r] = rn;
+    if (rn <= s.tol2[r] * s.bn2[r]) s.done[r] = 1;
+}
+
+// rho' = r.z; beta = rho'/rho (init: rho = r.z, beta unused)
+__global__ void k_pcg_rz(const double *__restrict__ partial, int n_part, int R, PcgDev s,
+                         int init) {
+    const int r = blockIdx.x;
+    const double rz = wave_sum_parts(partial, n_part, R, r);
+    if ((threadIdx.x & 63) != 0) return;
+    if (init) {
+        s.rho[r] = rz;
+        s.beta[r] = 0;
+        return;
+    }
+    if (s.done[r]) return;
+    s.beta[r] = rz / s.rho[r];
+    s.rho[r] = rz;
+}
+
+template <int R>
+__global__ void __launch_bounds__(BS) k_pcg_p(int64_t n, PcgDev s, const double *__restrict__ z,
+                                              double *__restrict__ p) {
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n * R;
+         e += (int64_t)gridDim.x * BS) {
+        const int r = (int)(e % R);
+        if (!s.done[r]) p[e] = z[e] + s.beta[r] * p[e];
+    }
+}
+
+template <int R>
+__global__ void __launch_bounds__(BS) k_copy_masked(int64_t n, const int *__restrict__ done,
+                                                    const double *__restrict__ src,
+                                                    double *__restrict__ dst) {
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n * R;
+         e += (int64_t)gridDim.x * BS) {
+        const int r = (int)(e % R);
+        if (!done || !done[r]) dst[e] = src[e];
+    }
+}
+
+// -------------------------------------------------------- skinny products
+
+// partial[chunk * ncol + col] = sum_{i in chunk} W[col * n + i] v[i]
+__global__ void __launch_bounds__(BS) k_gemv_t(int64_t n, const double *__restrict__ W,
+                                               const double *__restrict__ v,
+                                               double *__restrict__ partial, int64_t rows,
+                                               int ncol) {
+    const int col = blockIdx.y;
+    const int64_t i0 = (int64_t)blockIdx.x * rows;
+    int64_t i1 = i0 + rows;
+    if (i1 > n) i1 = n;
+    const double *w = W + (int64_t)col * n;
+    double acc = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BS) acc += w[i] * v[i];
+    __shared__ double sm[BS];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncol + col] = sm[0];
+}
+
+// v[i] -= sum_c W[c n + i] h[c]
+__global__ void __launch_bounds__(BS) k_gemv_n_sub(int64_t n, int ncol,
+                                                   const double *__restrict__ W,
+                                                   const double *__restrict__ h,
+                                                   double *__restrict__ v) {
+    __shared__ double sh[512];
+    for (int c = threadIdx.x; c < ncol; c += BS) sh[c] = h[c];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        double acc = 0;
+        for (int c = 0; c < ncol; ++c) acc += W[(int64_t)c * n + i] * sh[c];
+        v[i] -= acc;
+    }
+}
+
+// dst = src * s or src / s, s a device scalar
+__global__ void k_scale(int64_t n, const double *__restrict__ src, const double *__restrict__ s,
+                        double *__restrict__ dst, int invert) {
+    const double f = invert ? 1.0 / *s : *s;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        dst[i] = src[i] * f;
+}
+
+// Zout[:, c] = sum_m V[:, m] Y[m + c * kin]  (Y on device, col-major kin x kout)
+__global__ void __launch_bounds__(BS) k_mat_small_right(int64_t n, int kin, int kout,
+                                                        const double *__restrict__ V,
+                                                        const double *__restrict__ Y,
+                                                        double *__restrict__ Zo) {
+    extern __shared__ double sy[];
+    for (int e = threadIdx.x; e < kin * kout; e += BS) sy[e] = Y[e];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        for (int c = 0; c < kout; ++c) {
+            double acc = 0;
+            for (int m = 0; m < kin; ++m) acc += V[(int64_t)m * n + i] * sy[m + c * kin];
+            Zo[(int64_t)c * n + i] = acc;
+        }
+    }
+}
+
+// --------------------------------------------------------- MFMA Gram (FP64)
+//
+// C[a][b] = sum_i X(i, a) Y(i, b), X(i, a) = X[i*xr + a*xc], likewise Y.
+// Block = 4 waves; rows are staged through LDS 32 at a time (coalesced along
+// whichever dimension is contiguous) and fed to v_mfma_f64_16x16x4f64 in
+// K-steps of 4 rows.  Each block writes its partial KA x KB product; a second
+// kernel sums the partials in a fixed order.
+
+using d4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+
+constexpr int GR_ROWS = 32;
+
+__global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
+                                                  const double *__restrict__ X, int64_t xr,
+                                                  int64_t xc, const double *__restrict__ Y,
+                                                  int64_t yr, int64_t yc,
+                                                  double *__restrict__ partial,
+                                                  int64_t rows_per_block) {
+    const int KA = (ka + 15) & ~15, KB = (kb + 15) & ~15;  // <= 64 each
+    __shared__ double sx[GR_ROWS][64 + 1];
+    __shared__ double syy[GR_ROWS][64 + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int TA = KA / 16, TB = KB / 16, NT = TA * TB;
+    d4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    int64_t i1 = i0 + rows_per_block;
+    if (i1 > n) i1 = n;
+    for (int64_t rb = i0; rb < i1; rb += GR_ROWS) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < GR_ROWS * 64; e += BS) {
+            int rr, cc;
+            // choose the index order that walks memory contiguously
+            if (xr == 1) { rr = e % GR_ROWS; cc = e / GR_ROWS; } else { cc = e % 64; rr = e / 64; }
+            const int64_t i = rb + rr;
+            sx[rr][cc] = (i < i1 && cc < ka) ? X[i * xr + cc * xc] : 0.0;
+            if (yr == 1) { rr = e % GR_ROWS; cc = e / GR_ROWS; } else { cc = e % 64; rr = e / 64; }
+            const int64_t i2 = rb + rr;
+            syy[rr][cc] = (i2 < i1 && cc < kb) ? Y[i2 * yr + cc * yc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GR_ROWS; ks += 4) {
+            const int kk = ks + lane / 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = wv + 4 * q;
+                if (t < NT) {
+                    const int ta = t / TB, tb = t % TB;
+                    const double av = sx[kk][ta * 16 + (lane % 16)];
+                    const double bv = syy[kk][tb * 16 + (lane % 16)];
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D layout: lane holds rows 4*(lane/16) + v, column lane % 16
+    double *out = partial + (int64_t)blockIdx.x * 64 * 64;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = wv + 4 * q;
+        if (t < NT) {
+            const int ta = t / TB, tb = t % TB;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = ta * 16 + 4 * (lane / 16) + v;
+                const int col = tb * 16 + (lane % 16);
+                out[row * 64 + col] = acc[q][v];
+            }
+        }
+    }
+}
+
+__global__ void k_gram_final(const double *__restrict__ partial, int n_part, int ka, int kb,
+                             double *__restrict__ C) {
+    const int e = blockIdx.x * BS + threadIdx.x;
+    if (e >= ka * kb) return;
+    const int a = e / kb, b = e % kb;
+    double s = 0;
+    for (int p = 0; p < n_part; ++p) s += partial[(int64_t)p * 4096 + a * 64 + b];
+    C[a * kb + b] = s;
+}
+
+// -------------------------------------------------------- small Cholesky
+//
+// E (k x k row-major, k <= 64) -> symmetrised E_s = (E + E^T)/2 (written back)
+// and its lower factor Lc (row-major).  flag = 1 if a pivot^2 falls below
+// 1e-13 * max diag (numerically not SPD).
+__global__ void k_chol_small(int k, double *__restrict__ E, double *__restrict__ Lc,
+                             int *__restrict__ flag) {
+    __shared__ double A[64][65];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        A[i][j] = 0.5 * (E[i * k + j] + E[j * k + i]);
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += blockDim.x) E[e] = A[e / k][e % k];
+    __shared__ double dmax;
+    __shared__ int bad;
+    if (tid == 0) {
+        double m = 0;
+        for (int i = 0; i < k; ++i) m = fmax(m, A[i][i]);
+        dmax = m;
+        bad = 0;
+    }
+    __syncthreads();
+    for (int c = 0; c < k; ++c) {
+        if (tid == 0) {
+            double d = A[c][c];
+            if (!(d > 1e-13 * dmax)) { bad = 1; d = 1e-300; }
+            A[c][c] = sqrt(d);
+        }
+        __syncthreads();
+        const double lcc = A[c][c];
+        for (int i = c + 1 + tid; i < k; i += blockDim.x) A[i][c] /= lcc;
+        __syncthreads();
+        for (int e = tid; e < (k - c - 1) * (k - c - 1); e += blockDim.x) {
+            const int i = c + 1 + e / (k - c - 1), j = c + 1 + e % (k - c - 1);
+            if (j <= i) A[i][j] -= A[i][c] * A[j][c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        Lc[e] = j <= i ? A[i][j] : 0.0;
+    }
+    if (tid == 0) *flag = bad;
+}
+
+// c = E^-1 g per column: forward then backward substitution with Lc.
+// g[a * R + r] (k x R), c likewise.  One thread per column.
+__global__ void k_coarse_solve(int k, int R, const double *__restrict__ Lc,
+                               const double *__restrict__ g, double *__restrict__ c) {
+    const int r = threadIdx.x;
+    if (r >= R) return;
+    double y[64];
+    for (int i = 0; i < k; ++i) {
+        double s = g[i * R + r];
+        for (int j = 0; j < i; ++j) s -= Lc[i * k + j] * y[j];
+        y[i] = s / Lc[i * k + i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int j = i + 1; j < k; ++j) s -= Lc[j * k + i] * y[j];
+        y[i] = s / Lc[i * k + i];
+    }
+    for (int i = 0; i < k; ++i) c[i * R + r] = y[i];
+}
+
+// out = M_BD (v - AZ c) + Z c per pixel and column (Eq. m2l), with optional
+// partial sums of dot_with . out.  Z, AZ are column-major n x k, c is k x R.
+template <int R>
+__global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv, int32_t n_obs,
+                                                  int k, int64_t n, const double *__restrict__ Z,
+                                                  const double *__restrict__ AZ,
+                                                  const double *__restrict__ cc,
+                                                  const double *__restrict__ v,
+                                                  double *__restrict__ out,
+                                                  const double *__restrict__ dot_with,
+                                                  double *__restrict__ partial,
+                                                  int64_t pix_per_block) {
+    constexpr int NG = BS / R;
+    __shared__ double sc[64 * 64];
+    for (int e = threadIdx.x; e < k * R; e += BS) sc[e] = cc[e];
+    __syncthreads();
+    const int r = threadIdx.x % R, rg = threadIdx.x / R;
+    const int64_t p0 = (int64_t)blockIdx.x * pix_per_block;
+    int64_t p1 = p0 + pix_per_block;
+    if (p1 > n_obs) p1 = n_obs;
+    double acc = 0;
+    for (int64_t j = p0 + rg; j < p1; j += NG) {
+        double u[3], zc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int64_t row = 3 * j + a;
+            double s_az = 0, s_z = 0;
+            for (int q = 0; q < k; ++q) {
+                const double cq = sc[q * R + r];
+                s_az += AZ[(int64_t)q * n + row] * cq;
+                s_z += Z[(int64_t)q * n + row] * cq;
+            }
+            u[a] = v[row * R + r] - s_az;
+            zc[a] = s_z;
+        }
+        const double *m = inv + 6 * j;
+        const double o0 = m[0] * u[0] + m[1] * u[1] + m[2] * u[2] + zc[0];
+        const double o1 = m[1] * u[0] + m[3] * u[1] + m[4] * u[2] + zc[1];
+        const double o2 = m[2] * u[0] + m[4] * u[1] + m[5] * u[2] + zc[2];
+        const int64_t base = 3 * j * R + r;
+        out[base] = o0;
+        out[base + R] = o1;
+        out[base + 2 * R] = o2;
+        if (dot_with) acc += dot_with[base] * o0 + dot_with[base + R] * o1 +
+                             dot_with[base + 2 * R] * o2;
+    }
+    if (partial) block_col_reduce<R>(acc, partial);
+}
+
+template <typename F> void dispatch_r(int nrhs, F &&f) {
+    switch (nrhs) {
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 2: f(std::integral_constant<int, 2>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 8: f(std::integral_constant<int, 8>()); break;
+        case 16: f(std::integral_constant<int, 16>()); break;
+        case 32: f(std::integral_constant<int, 32>()); break;
+        case 64: f(std::integral_constant<int, 64>()); break;
+        default: throw Error(MM_E_INVALID, "nrhs must be a power of two <= 64");
+    }
+}
+
+int grid_for(int64_t n, int max_blocks = 4096) {
+    int64_t g = (n + BS - 1) / BS;
+    if (g > max_blocks) g = max_blocks;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+
+int reduction_parts(int64_t n_rows) {
+    int64_t p = (n_rows + 1023) / 1024;
+    if (p > 512) p = 512;
+    return (int)(p < 1 ? 1 : p);
+}
+
+static int64_t rows_per(int64_t n, int parts) { return (n + parts - 1) / parts; }
+
+void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M,
+                   int *n_bad_out) {
+    hipStream_t s = ctx->stream;
+    const int32_t n_obs = p->n_obs;
+    M->inv.alloc(sizeof(double) * 6 * (n_obs > 0 ? n_obs : 1));
+    DBuf rc, bad, mn;
+    rc.alloc(sizeof(double) * (n_obs > 0 ? n_obs : 1));
+    bad.alloc(sizeof(int));
+    mn.alloc(sizeof(double));
+    MM_HIP(hipMemsetAsync(bad.ptr, 0, sizeof(int), s));
+    if (n_obs > 0) {
+        const unsigned nb = (unsigned)((n_obs + 3) / 4);
+        if (p->prec == MM_F32)
+            k_mbd_build<float><<<nb, BS, 0, s>>>(p->off.as<int32_t>(), p->perm.as<int32_t>(),
+                                                 p->ws.as<float2>(), nz->istart.as<int64_t>(),
+                                                 nz->n_int, nz->fid.as<int32_t>(),
+                                                 nz->band64.as<double>(), nz->half_bw, n_obs,
+                                                 M->inv.as<double>(), rc.as<double>(),
+                                                 bad.as<int>());
+        else
+            k_mbd_build<double><<<nb, BS, 0, s>>>(p->off.as<int32_t>(), p->perm.as<int32_t>(),
+                                                  p->ws.as<double2>(), nz->istart.as<int64_t>(),
+                                                  nz->n_int, nz->fid.as<int32_t>(),
+                                                  nz->band64.as<double>(), nz->half_bw, n_obs,
+                                                  M->inv.as<double>(), rc.as<double>(),
+                                                  bad.as<int>());
+        k_min_reduce<<<1, BS, 0, s>>>(rc.as<double>(), n_obs, mn.as<double>());
+        MM_HIP(hipGetLastError());
+    }
+    int hb = 0;
+    double hm = 1.0;
+    MM_HIP(hipMemcpyAsync(&hb, bad.ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (n_obs > 0) MM_HIP(hipMemcpyAsync(&hm, mn.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    M->rcond_min = hm;
+    *n_bad_out = hb;
+}
+
+void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nrhs, const double *v,
+                   double *out, const double *dot_with, double *partial, int n_part) {
+    Scope sc(ctx->prof, ctx->stream, "precond");
+    if (n_obs == 0) return;
+    // partition: n_part blocks over pixels (3 rows each)
+    const int parts = partial ? n_part : reduction_parts(3 * (int64_t)n_obs);
+    const int64_t ppb = rows_per(n_obs, parts);
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_mbd_apply<R><<<parts, BS, 0, ctx->stream>>>(inv, n_obs, v, out, dot_with, partial, ppb);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b,
+                      double *partial, int n_part) {
+    const int64_t rpb = rows_per(n, n_part);
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_dot_partial<R><<<n_part, BS, 0, ctx->stream>>>(n, a, b, partial, rpb);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void dot_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b, double *out) {
+    Scope sc(ctx->prof, ctx->stream, "vec");
+    const int parts = reduction_parts(n);
+    ctx->red.alloc(sizeof(double) * parts * 64);
+    dot_partial_cols(ctx, n, nrhs, a, b, ctx->red.as<double>(), parts);
+    k_dot_final<<<nrhs, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, nrhs, out);
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_init_scalars(mm_ctx *ctx, int nrhs, PcgDev s, double tol) {
+    k_pcg_init<<<1, 64, 0, ctx->stream>>>(nrhs, s, tol);
+    MM_HIP(hipGetLastError());
+}
+
+void axpby_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *b, const double *Ax, double *r) {
+    Scope sc(ctx->prof, ctx->stream, "vec");
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_axpby<R><<<grid_for(n * R), BS, 0, ctx->stream>>>(n, b, Ax, r);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_after_pq(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part) {
+    k_pcg_alpha<<<nrhs, 64, 0, ctx->stream>>>(partial, n_part, nrhs, s);
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *p, const double *q,
+                   double *x, double *r, double *partial, int n_part) {
+    Scope sc(ctx->prof, ctx->stream, "vec");
+    const int64_t rpb = rows_per(n, n_part);
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_pcg_xr<R><<<n_part, BS, 0, ctx->stream>>>(n, s, p, q, x, r, partial, rpb);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_after_rn(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part,
+                  int count_iter) {
+    k_pcg_rn<<<nrhs, 64, 0, ctx->stream>>>(partial, n_part, nrhs, s, count_iter);
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_after_rz(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part, int init) {
+    k_pcg_rz<<<nrhs, 64, 0, ctx->stream>>>(partial, n_part, nrhs, s, init);
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_update_p(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *z, double *p) {
+    Scope sc(ctx->prof, ctx->stream, "vec");
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_pcg_p<R><<<grid_for(n * R), BS, 0, ctx->stream>>>(n, s, z, p);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const double *src,
+                      double *dst) {
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_copy_masked<R><<<grid_for(n * R), BS, 0, ctx->stream>>>(n, done, src, dst);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, double *h) {
+    Scope sc(ctx->prof, ctx->stream, "gemv");
+    const int parts = reduction_parts(n);
+    ctx->red.alloc(sizeof(double) * parts * (ncol > 64 ? ncol : 64));
+    k_gemv_t<<<dim3(parts, ncol), BS, 0, ctx->stream>>>(n, W, v, ctx->red.as<double>(),
+                                                         rows_per(n, parts), ncol);
+    k_dot_final<<<ncol, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, ncol, h);
+    MM_HIP(hipGetLastError());
+}
+
+void gemv_n_sub(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *h, double *v) {
+    Scope sc(ctx->prof, ctx->stream, "gemv");
+    MM_CHECK(ncol <= 512, MM_E_INVALID, "gemv: too many columns");
+    k_gemv_n_sub<<<grid_for(n, 2048), BS, 0, ctx->stream>>>(n, ncol, W, h, v);
+    MM_HIP(hipGetLastError());
+}
+
+void scale_copy(mm_ctx *ctx, int64_t n, const double *src, const double *s_dev, double *dst,
+                int invert) {
+    k_scale<<<grid_for(n), BS, 0, ctx->stream>>>(n, src, s_dev, dst, invert);
+    MM_HIP(hipGetLastError());
+}
+
+void matmul_small_right(mm_ctx *ctx, int64_t n, int kin, int kout, const double *V,
+                        const double *Y, double *Zo) {
+    MM_CHECK((size_t)kin * kout * sizeof(double) <= 60 * 1024, MM_E_INVALID,
+             "matmul_small_right: coefficient block too large");
+    k_mat_small_right<<<grid_for(n, 2048), BS, sizeof(double) * kin * kout, ctx->stream>>>(
+        n, kin, kout, V, Y, Zo);
+    MM_HIP(hipGetLastError());
+}
+
+void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t x_rs,
+               int64_t x_cs, const double *Y, int64_t y_rs, int64_t y_cs, double *C) {
+    Scope sc(ctx->prof, ctx->stream, "gram_mfma");
+    MM_CHECK(ka >= 1 && ka <= 64 && kb >= 1 && kb <= 64, MM_E_INVALID, "gram: sizes");
+    int parts = (int)((n + 2047) / 2048);
+    if (parts > 1024) parts = 1024;
+    if (parts < 1) parts = 1;
+    int64_t rpb = (n + parts - 1) / parts;
+    rpb = (rpb + GR_ROWS - 1) / GR_ROWS * GR_ROWS;
+    ctx->gram_part.alloc(sizeof(double) * 4096 * parts);
+    k_gram_mfma<<<parts, BS, 0, ctx->stream>>>(n, ka, kb, X, x_rs, x_cs, Y, y_rs, y_cs,
+                                                ctx->gram_part.as<double>(), rpb);
+    k_gram_final<<<(ka * kb + BS - 1) / BS, BS, 0, ctx->stream>>>(ctx->gram_part.as<double>(),
+                                                                   parts, ka, kb, C);
+    MM_HIP(hipGetLastError());
+}
+
+void chol_small_dev(mm_ctx *ctx, int k, const double *E, double *Lc, int *flag) {
+    k_chol_small<<<1, 64, 0, ctx->stream>>>(k, const_cast<double *>(E), Lc, flag);
+    MM_HIP(hipGetLastError());
+}
+
+void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c) {
+    const int64_t n = 3 * (int64_t)M->n_obs;
+    const int k = M->k;
+    ctx->coef_g.alloc(sizeof(double) * 64 * 64);
+    double *g = ctx->coef_g.as<double>();
+    if (nrhs == 1) {
+        gemv_t(ctx, n, k, M->Z.as<double>(), v, g);
+    } else {
+        // g[a][r] = sum_i Z[a n + i] v[i R + r]   (Z^T V on MFMA)
+        gram_mfma(ctx, n, k, nrhs, M->Z.as<double>(), 1, n, v, nrhs, 1, g);
+    }
+    k_coarse_solve<<<1, 64, 0, ctx->stream>>>(k, nrhs, M->Lc.as<double>(), g, c);
+    MM_HIP(hipGetLastError());
+}
+
+void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
+                   double *partial, int n_part) {
+    Scope sc(ctx->prof, ctx->stream, "precond");
+    const int64_t n = 3 * (int64_t)M->n_obs;
+    const int k = M->k;
+    ctx->scal.alloc(sizeof(double) * 64 * 64 + 4096);
+    double *c = ctx->scal.as<double>();
+    m2l_coef_dev(ctx, M, nrhs, v, c);
+    const int parts = partial ? n_part : reduction_parts(n);
+    const int64_t ppb = rows_per(M->n_obs, parts);
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        k_m2l_final<R><<<parts, BS, 0, ctx->stream>>>(M->inv.as<double>(), M->n_obs, k, n,
+                                                      M->Z.as<double>(), M->AZ.as<double>(), c,
+                                                      v, out, partial ? v : nullptr, partial, ppb);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+}  // namespace mm

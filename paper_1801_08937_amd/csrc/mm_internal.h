@@ -1,0 +1,224 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mapmaker.h"
+
+namespace mm {
+
+// An error carried from deep inside a call up to the C-ABI boundary, where it
+// becomes the call's status and the context's last-error message.
+struct Error : std::runtime_error {
+    mm_status code;
+    Error(mm_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define MM_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::mm::Error(e_ == hipErrorOutOfMemory ? MM_E_OOM : MM_E_DEVICE,      \
+                              std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+#define MM_CHECK(cond, code, msg)                                                      \
+    do {                                                                               \
+        if (!(cond)) throw ::mm::Error((code), (msg));                                 \
+    } while (0)
+
+// Owning device buffer.
+struct DBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    // Grow-only.  Growing a buffer that queued kernels may still use waits
+    // for the device first.
+    void alloc(size_t b) {
+        if (b <= bytes && ptr) return;
+        if (ptr) (void)hipDeviceSynchronize();
+        release();
+        if (b == 0) return;
+        hipError_t e = hipMalloc(&ptr, b);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            throw Error(MM_E_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        }
+        bytes = b;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Per-stage timing with HIP events on the context's stream.
+struct Profiler {
+    bool on = false;
+    struct Stage { double ms = 0; int64_t calls = 0; };
+    std::map<std::string, Stage> stages;
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    void flush();  // synchronises on the recorded events
+    ~Profiler();
+};
+
+struct Scope {
+    Profiler *pr;
+    hipStream_t s;
+    const char *name;
+    hipEvent_t a{}, b{};
+    Scope(Profiler &p, hipStream_t st, const char *n);
+    ~Scope();
+};
+
+}  // namespace mm
+
+struct mm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string last_error;
+    mm::Profiler prof;
+    // reusable workspace
+    mm::DBuf tod_a, tod_b;         // TOD temporaries for A applies
+    mm::DBuf red;                  // reduction partials
+    mm::DBuf scal;                 // small device scalars
+    mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
+    double *pinned = nullptr;      // host pinned scratch (scalar readback)
+    size_t pinned_bytes = 0;
+    int n_cu = 256;
+};
+
+struct mm_pointing {
+    int64_t n_samp = 0;
+    int32_t n_pix_total = 0;
+    int32_t n_obs = 0;
+    int64_t n_valid = 0;
+    mm_precision prec = MM_F64;
+    mm::DBuf hits, obs_pix, j, w, perm, ws, off, seg_order;
+    int32_t max_seg = 0;
+};
+
+struct mm_noise {
+    int64_t n_samp = 0;
+    int32_t n_int = 0, n_filters = 0, half_bw = 0;
+    mm_noise_method method = MM_NOISE_DIRECT;
+    mm_precision prec = MM_F64;
+    std::vector<int64_t> h_istart;
+    std::vector<int32_t> h_fid;
+    std::vector<double> h_band;
+    mm::DBuf istart, fid, band, band64;
+    // direct band: tile table
+    mm::DBuf tiles;  // int64 pairs (tile start sample, interval index)
+    int64_t n_tiles = 0;
+    int32_t tile_len = 0;
+    // FFT: per-filter packed spectrum and block table
+    int32_t fft_n = 0;       // real block length
+    int32_t fft_valid = 0;   // valid outputs per block
+    mm::DBuf fft_spec;       // per filter: A_k, B_k (2 * fft_n/2 doubles)
+    mm::DBuf fft_tw;         // twiddles exp(-2 pi i m / (fft_n/2)), m < fft_n/2
+    mm::DBuf fft_blocks;     // int64 pairs (first output sample, interval index)
+    int64_t n_fft_blocks = 0;
+};
+
+struct mm_precond {
+    int kind = 0;  // 0 = M_BD, 1 = M_2l
+    int32_t n_obs = 0;
+    mm::DBuf inv;  // f64[n_obs][6] packed symmetric B_j^-1
+    double rcond_min = 0;
+    // M_2l
+    int32_t k = 0;
+    mm::DBuf Z, AZ, E, Lc;  // Z, AZ: f64[k][n]; E, Lc: f64[k][k] (Lc lower, row-major)
+    // Arnoldi record
+    int32_t arn_m = 0;
+    mm::DBuf W;
+    std::vector<double> H;  // (m+1) x m column-major
+};
+
+namespace mm {
+
+// ---- launchers (defined in the .hip files) ----
+// pointing.hip
+void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, const double *psi,
+                           int32_t min_hits);
+
+// tod_ops.hip
+void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y);
+void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x);
+void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
+void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_rm, void *y,
+                  int *nonfinite_flag);
+void noise_prepare(mm_ctx *ctx, mm_noise *nz);  // tiles, FFT spectra
+bool noise_fft_supported(int half_bw, int64_t min_len);
+
+// map_ops.hip
+void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M,
+                   int *n_bad);
+void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nrhs, const double *v,
+                   double *out, const double *dot_with, double *dot_partial, int n_part);
+
+// Deterministic dot products of columns: out[r] = sum_i a[i R + r] b[i R + r]
+// over n rows (two stages, fixed order).
+void dot_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b, double *out);
+int reduction_parts(int64_t n_rows);
+
+// Small dense helpers
+void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t x_rs,
+               int64_t x_cs, const double *Y, int64_t y_rs, int64_t y_cs, double *C);
+void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, double *h);
+void gemv_n_sub(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *h, double *v);
+void scale_copy(mm_ctx *ctx, int64_t n, const double *src, const double *s_dev, double *dst,
+                int invert);
+void matmul_small_right(mm_ctx *ctx, int64_t n, int kin, int kout, const double *V,
+                        const double *Y, double *Zout);  // Zout = V Y, col-major
+void chol_small_dev(mm_ctx *ctx, int k, const double *E, double *Lc, int *flag);
+void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
+                   double *dot_partial, int n_part);
+void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c);
+
+// PCG vector kernels on column-batched map vectors
+struct PcgDev {
+    double *rho, *pq, *alpha, *beta, *rn2, *bn2, *tol2;
+    int *done, *brk, *iters;
+};
+void pcg_init_scalars(mm_ctx *ctx, int nrhs, PcgDev s, double tol);
+void axpby_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *b, const double *Ax, double *r);
+void pcg_after_pq(mm_ctx *ctx, int nrhs, PcgDev s, const double *pq_partial, int n_part);
+void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *p, const double *q,
+                   double *x, double *r, double *partial, int n_part);
+void pcg_after_rn(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part,
+                  int count_iter);
+void pcg_after_rz(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part, int init);
+void pcg_update_p(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *z, double *p);
+void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b,
+                      double *partial, int n_part);
+void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const double *src,
+                      double *dst);
+
+// host
+void hessenberg_eig(int m, const double *H, double *wr, double *wi, double *vr, double *vi);
+
+inline int pow2_ok(int r) { return r >= 1 && r <= 64 && (r & (r - 1)) == 0; }
+
+}  // namespace mm

@@ -1,0 +1,295 @@
+// Time-domain operators: P (map -> TOD gather), P^T (pixel-sorted segmented
+// reduction, no float atomics), the banded-Toeplitz N^-1 applied directly,
+// and the flag mask applied to the data.  The FFT form of N^-1 lives in
+// noise_fft.hip.
+//
+// Layouts: map x[(3 j + a) R + r] (FP64); TOD y[t R + r] (T = float or double).
+// A wavefront's 64 lanes are split into G = 64 / R sample groups of R columns,
+// so one wave step touches G consecutive samples x R columns: contiguous TOD
+// rows.  Each column is computed with the same arithmetic and order whatever
+// the other columns hold.
+#include "mm_internal.h"
+
+namespace mm {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// works on a contiguous range of logical blocks (neighbouring pixels share
+// their TOD cache lines in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nb) {
+    if ((nb & 7) != 0) return bid;
+    return (bid & 7) * (nb >> 3) + (bid >> 3);
+}
+
+namespace {
+
+constexpr int BS = 256;
+
+template <typename T, int R>
+__global__ void __launch_bounds__(BS) k_apply_P(const int32_t *__restrict__ jpix,
+                                                const typename Vec2<T>::type *__restrict__ w,
+                                                int64_t n, const double *__restrict__ x,
+                                                T *__restrict__ y) {
+    constexpr int G = 64 / R;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / R, r = lane % R;
+    const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * BS) >> 6;
+    for (int64_t t = wave * G + sub; t < n; t += nwave * G) {
+        const int32_t j = jpix[t];
+        T v = (T)0;
+        if (j >= 0) {
+            const auto ww = w[t];
+            const double *xp = x + (int64_t)3 * j * R + r;
+            v = (T)xp[0] + ww.x * (T)xp[R] + ww.y * (T)xp[2 * R];
+        }
+        y[t * R + r] = v;
+    }
+}
+
+// One wave per compact pixel j: lanes stride through the segment
+// perm[off[j]..off[j+1]) in order, accumulating (1, cos, sin) * z; the G
+// lane groups are then combined by a fixed xor butterfly.
+template <typename T, int R>
+__global__ void __launch_bounds__(BS) k_apply_PT(const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ perm,
+                                                 const typename Vec2<T>::type *__restrict__ ws,
+                                                 int32_t n_obs, const T *__restrict__ z,
+                                                 double *__restrict__ x) {
+    constexpr int G = 64 / R;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / R, r = lane % R;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t j = blk * (BS / 64) + (threadIdx.x >> 6);
+    if (j >= n_obs) return;
+    const int32_t a = off[j], b = off[j + 1];
+    T s0 = 0, s1 = 0, s2 = 0;
+    for (int32_t i = a + sub; i < b; i += G) {
+        const int32_t t = perm[i];
+        const T zz = z[(int64_t)t * R + r];
+        const auto ww = ws[i];
+        s0 += zz;
+        s1 += ww.x * zz;
+        s2 += ww.y * zz;
+    }
+#pragma unroll
+    for (int m = 32; m >= R; m >>= 1) {
+        s0 += __shfl_xor(s0, m);
+        s1 += __shfl_xor(s1, m);
+        s2 += __shfl_xor(s2, m);
+    }
+    if (sub == 0) {
+        double *xp = x + (int64_t)3 * j * R + r;
+        xp[0] = (double)s0;
+        xp[R] = (double)s1;
+        xp[2 * R] = (double)s2;
+    }
+}
+
+// Direct banded Toeplitz: block (tile, part) computes outputs
+// t in [t0 + part*TL/R, t0 + (part+1)*TL/R) of one interval for all R columns.
+// The input window [t - lambda, t + lambda] (clipped to the interval) is
+// streamed through LDS in chunks; every output accumulates its taps in
+// ascending u, so its value does not depend on the tiling or on R.
+template <typename T, int R>
+__global__ void __launch_bounds__(BS) k_band(const int64_t *__restrict__ tiles,
+                                             const int64_t *__restrict__ istart,
+                                             const int32_t *__restrict__ fid,
+                                             const T *__restrict__ band, int lam, int TL,
+                                             const T *__restrict__ y, T *__restrict__ z) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sb = reinterpret_cast<T *>(smem_raw);
+    const int band_slots = (lam + 1 + 3) & ~3;
+    T *sy = sb + band_slots;
+    constexpr int CHR = 4096;          // LDS chunk, in elements
+    constexpr int CH = CHR / R;        // samples per chunk
+
+    const int64_t t_tile = tiles[2 * blockIdx.x];
+    const int64_t iv = tiles[2 * blockIdx.x + 1];
+    const int64_t a = istart[iv], b = istart[iv + 1];
+    const T *c = band + (int64_t)fid[iv] * (lam + 1);
+    const int sub_len = TL / R;
+    const int64_t t0 = t_tile + (int64_t)blockIdx.y * sub_len;
+    int64_t t1 = t0 + sub_len;
+    const int64_t tile_end = t_tile + TL < b ? t_tile + TL : b;
+    if (t1 > tile_end) t1 = tile_end;
+    if (t0 >= t1) return;
+
+    for (int i = threadIdx.x; i <= lam; i += BS) sb[i] = c[i];
+
+    constexpr int SPT = BS / R;  // sample slots per pass
+    const int r = threadIdx.x % R;
+    const int ts = threadIdx.x / R;
+    const int opt = (sub_len + SPT - 1) / SPT;  // consecutive outputs per thread
+    constexpr int MAXO = 16;
+    T acc[MAXO];
+#pragma unroll
+    for (int q = 0; q < MAXO; ++q) acc[q] = 0;
+    const int64_t my0 = t0 + (int64_t)ts * opt;
+
+    const int64_t lo = t0 - lam > a ? t0 - lam : a;
+    const int64_t hi = t1 + lam < b ? t1 + lam : b;
+    for (int64_t c0 = lo; c0 < hi; c0 += CH) {
+        const int64_t c1 = c0 + CH < hi ? c0 + CH : hi;
+        __syncthreads();
+        const int64_t cnt = (c1 - c0) * R;
+        const T *src = y + c0 * R;
+        for (int64_t e = threadIdx.x; e < cnt; e += BS) sy[e] = src[e];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXO; ++q) {
+            if (q < opt) {
+                const int64_t t = my0 + q;
+                if (t < t1) {
+                    int64_t ulo = t - lam > c0 ? t - lam : c0;
+                    int64_t uhi = t + lam + 1 < c1 ? t + lam + 1 : c1;
+                    T s = acc[q];
+                    for (int64_t u = ulo; u < uhi; ++u) {
+                        const int64_t d = t > u ? t - u : u - t;
+                        s += sb[d] * sy[(u - c0) * R + r];
+                    }
+                    acc[q] = s;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXO; ++q) {
+        if (q < opt) {
+            const int64_t t = my0 + q;
+            if (t < t1) z[t * R + r] = acc[q];
+        }
+    }
+}
+
+// y[t R + r] = mask_t * tod[r * n + t]; flags non-finite data on kept samples.
+template <typename T, int R>
+__global__ void __launch_bounds__(BS) k_mask(const int32_t *__restrict__ jpix, int64_t n,
+                                             const T *__restrict__ tod, T *__restrict__ y,
+                                             int *__restrict__ flag) {
+    int bad = 0;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n * R;
+         e += (int64_t)gridDim.x * BS) {
+        const int64_t t = e / R;
+        const int r = (int)(e % R);
+        T v = tod[(int64_t)r * n + t];
+        if (jpix[t] >= 0) {
+            bad |= !isfinite(v);
+        } else {
+            v = (T)0;
+        }
+        y[e] = v;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+int grid_for(int64_t n, int max_blocks = 16384) {
+    int64_t g = (n + BS - 1) / BS;
+    if (g > max_blocks) g = max_blocks;
+    return (int)(g < 1 ? 1 : g);
+}
+
+template <typename F> void dispatch_r(int nrhs, F &&f) {
+    switch (nrhs) {
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 2: f(std::integral_constant<int, 2>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 8: f(std::integral_constant<int, 8>()); break;
+        case 16: f(std::integral_constant<int, 16>()); break;
+        case 32: f(std::integral_constant<int, 32>()); break;
+        case 64: f(std::integral_constant<int, 64>()); break;
+        default: throw Error(MM_E_INVALID, "nrhs must be a power of two <= 64");
+    }
+}
+
+}  // namespace
+
+void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y) {
+    Scope sc(ctx->prof, ctx->stream, "P");
+    const int64_t n = p->n_samp;
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        const int grid = grid_for(n * R, 8 * ctx->n_cu * 4);
+        if (p->prec == MM_F32)
+            k_apply_P<float, R><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(),
+                                                              p->w.as<float2>(), n, x,
+                                                              static_cast<float *>(y));
+        else
+            k_apply_P<double, R><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(),
+                                                               p->w.as<double2>(), n, x,
+                                                               static_cast<double *>(y));
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x) {
+    Scope sc(ctx->prof, ctx->stream, "PT");
+    if (p->n_obs == 0) return;
+    int64_t nb = (p->n_obs + 3) / 4;
+    if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        if (p->prec == MM_F32)
+            k_apply_PT<float, R><<<(unsigned)nb, BS, 0, ctx->stream>>>(
+                p->off.as<int32_t>(), p->perm.as<int32_t>(), p->ws.as<float2>(), p->n_obs,
+                static_cast<const float *>(z), x);
+        else
+            k_apply_PT<double, R><<<(unsigned)nb, BS, 0, ctx->stream>>>(
+                p->off.as<int32_t>(), p->perm.as<int32_t>(), p->ws.as<double2>(), p->n_obs,
+                static_cast<const double *>(z), x);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
+
+void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
+    if (nz->method == MM_NOISE_FFT) {
+        noise_fft_apply_dev(ctx, nz, nrhs, y, z);
+        return;
+    }
+    Scope sc(ctx->prof, ctx->stream, "Ninv_band");
+    const int lam = nz->half_bw;
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        dim3 grid((unsigned)nz->n_tiles, R);
+        const int band_slots = (lam + 1 + 3) & ~3;
+        if (nz->prec == MM_F32) {
+            size_t sm = sizeof(float) * (band_slots + 4096);
+            k_band<float, R><<<grid, BS, sm, ctx->stream>>>(
+                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+                nz->band.as<float>(), lam, nz->tile_len, static_cast<const float *>(y),
+                static_cast<float *>(z));
+        } else {
+            size_t sm = sizeof(double) * (band_slots + 4096);
+            k_band<double, R><<<grid, BS, sm, ctx->stream>>>(
+                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+                nz->band.as<double>(), lam, nz->tile_len, static_cast<const double *>(y),
+                static_cast<double *>(z));
+        }
+    });
+    MM_HIP(hipGetLastError());
+}
+
+void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod, void *y,
+                  int *flag) {
+    const int64_t n = p->n_samp;
+    dispatch_r(nrhs, [&](auto RR) {
+        constexpr int R = decltype(RR)::value;
+        const int grid = grid_for(n * R);
+        if (p->prec == MM_F32)
+            k_mask<float, R><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), n,
+                                                           static_cast<const float *>(tod),
+                                                           static_cast<float *>(y), flag);
+        else
+            k_mask<double, R><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), n,
+                                                            static_cast<const double *>(tod),
+                                                            static_cast<double *>(y), flag);
+    });
+    MM_HIP(hipGetLastError());
+}
+
+}  // namespace mm

@@ -1,0 +1,422 @@
+"""Python binding of libmapmaker.so (the C ABI in include/mapmaker.h).
+
+Argument marshalling only: every operation runs in the library's HIP kernels.
+Device arrays are torch tensors on the context's GPU (torch provides memory and
+streams); they are passed to the library as raw pointers.
+
+The library must have been built (``python -m paper_1801_08937_amd.build``);
+importing this module without it raises ImportError -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmapmaker.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "mapmaker.h")
+
+MM_OK, MM_NOT_CONVERGED = 0, 1
+STATUS = {0: "MM_OK", 1: "MM_NOT_CONVERGED", -1: "MM_E_INVALID", -2: "MM_E_OOM",
+          -3: "MM_E_DEVICE", -4: "MM_E_SINGULAR_BLOCK", -5: "MM_E_COARSE_NOT_SPD",
+          -6: "MM_E_BREAKDOWN", -7: "MM_E_NONFINITE", -8: "MM_E_BUSY"}
+F64, F32 = 0, 1
+NOISE_AUTO, NOISE_DIRECT, NOISE_FFT = 0, 1, 2
+
+
+class MapmakerError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("breakdown", C.c_int32),
+                ("pad", C.c_int32), ("rel_res_recursive", C.c_double),
+                ("rel_res_true", C.c_double), ("solve_seconds", C.c_double)]
+
+
+class ArnoldiInfo(C.Structure):
+    _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("h_last", C.c_double),
+                ("setup_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1801_08937_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint32
+        PP = C.POINTER(C.c_void_p)
+        sig = {
+            "mm_version": (C.c_char_p, []),
+            "mm_ctx_create": (C.c_int, [C.c_int, P, PP]),
+            "mm_ctx_destroy": (None, [P]),
+            "mm_last_error": (C.c_char_p, [P]),
+            "mm_pointing_build": (C.c_int, [P, I64, I32, P, P, I32, C.c_int, PP]),
+            "mm_pointing_counts": (C.c_int, [P, C.POINTER(I32), C.POINTER(I64)]),
+            "mm_pointing_hits": (C.c_int, [P, P, P, P]),
+            "mm_pointing_export": (C.c_int, [P, P, P, P, P]),
+            "mm_pointing_destroy": (None, [P]),
+            "mm_noise_build": (C.c_int, [P, I32, P, P, I32, I32, P, C.c_int, C.c_int, PP]),
+            "mm_noise_method_used": (C.c_int, [P, C.POINTER(C.c_int)]),
+            "mm_noise_apply": (C.c_int, [P, P, I32, P, P]),
+            "mm_noise_destroy": (None, [P]),
+            "mm_apply_P": (C.c_int, [P, P, I32, P, P]),
+            "mm_apply_PT": (C.c_int, [P, P, I32, P, P]),
+            "mm_apply_A": (C.c_int, [P, P, P, I32, P, P]),
+            "mm_rhs": (C.c_int, [P, P, P, I32, P, P]),
+            "mm_mbd_build": (C.c_int, [P, P, P, PP]),
+            "mm_mbd_rcond": (C.c_int, [P, C.POINTER(D)]),
+            "mm_defl_build": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, PP]),
+            "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
+            "mm_defl_export": (C.c_int, [P, P, C.POINTER(I32), P, P, P]),
+            "mm_defl_arnoldi_export": (C.c_int, [P, P, C.POINTER(I32), P, P]),
+            "mm_precond_apply": (C.c_int, [P, P, I32, P, P]),
+            "mm_precond_destroy": (None, [P]),
+            "mm_solve": (C.c_int, [P, P, P, P, I32, P, P, D, I32, U32, P, P]),
+            "mm_profile_enable": (C.c_int, [P, C.c_int]),
+            "mm_profile_read": (C.c_int, [P, I32, P, P, P, C.POINTER(I32)]),
+            "mm_hessenberg_eig": (C.c_int, [I32, P, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions include/mapmaker.h declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mm_[A-Za-z0-9_]+)\s*\(", src)) - {"mm_status"})
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _dev_check(t, dtype=None, numel=None, name="array"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def hessenberg_eig(H: np.ndarray):
+    """Host-only Ritz eigensolver of the library (no GPU needed)."""
+    H = np.asarray(H, dtype=np.float64)
+    m = H.shape[0]
+    Hc = np.asfortranarray(H)
+    wr, wi = np.zeros(m), np.zeros(m)
+    vr, vi = np.zeros((m, m), order="F"), np.zeros((m, m), order="F")
+    st = lib().mm_hessenberg_eig(m, Hc.ctypes.data, wr.ctypes.data, wi.ctypes.data,
+                                 vr.ctypes.data, vi.ctypes.data)
+    if st != 0:
+        raise MapmakerError(st, "hessenberg_eig failed")
+    return wr + 1j * wi, vr + 1j * vi
+
+
+class Context:
+    """A library context on one GPU, enqueuing on a torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = lib().mm_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise MapmakerError(st, "mm_ctx_create failed")
+        self.h = h
+
+    def _check(self, st, what):
+        if st < 0 or (st > 1):
+            msg = lib().mm_last_error(self.h)
+            raise MapmakerError(st, f"{what}: {msg.decode() if msg else ''}")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mm_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ------------------------------------------------------------- builders
+    def pointing(self, pix, psi, n_pix_total: int, min_hits: int = 3, prec: int = F64):
+        import torch
+        _dev_check(pix, torch.int32, name="pix")
+        _dev_check(psi, torch.float64, pix.numel(), name="psi")
+        h = C.c_void_p()
+        self._check(lib().mm_pointing_build(self.h, pix.numel(), n_pix_total, _ptr(pix),
+                                            _ptr(psi), min_hits, prec, C.byref(h)),
+                    "mm_pointing_build")
+        return Pointing(self, h, pix.numel(), n_pix_total, prec)
+
+    def noise(self, interval_start, filter_id, band, half_bw: int, method: int = NOISE_AUTO,
+              prec: int = F64):
+        istart = np.ascontiguousarray(interval_start, dtype=np.int64)
+        fid = np.ascontiguousarray(filter_id, dtype=np.int32)
+        band = np.ascontiguousarray(band, dtype=np.float64).reshape(-1, half_bw + 1)
+        h = C.c_void_p()
+        self._check(lib().mm_noise_build(self.h, fid.shape[0], istart.ctypes.data,
+                                         fid.ctypes.data, band.shape[0], half_bw,
+                                         band.ctypes.data, method, prec, C.byref(h)),
+                    "mm_noise_build")
+        return Noise(self, h, int(istart[-1]), half_bw, prec)
+
+    # ------------------------------------------------------------ operators
+    def _tod_dtype(self, prec):
+        import torch
+        return torch.float32 if prec == F32 else torch.float64
+
+    def apply_P(self, p: "Pointing", x, y=None, nrhs: int = 1):
+        import torch
+        _dev_check(x, torch.float64, p.n * nrhs, "x")
+        if y is None:
+            y = torch.empty(p.n_samp * nrhs, dtype=self._tod_dtype(p.prec), device=x.device)
+        self._check(lib().mm_apply_P(self.h, p.h, nrhs, _ptr(x), _ptr(y)), "mm_apply_P")
+        return y
+
+    def apply_PT(self, p: "Pointing", z, x=None, nrhs: int = 1):
+        import torch
+        _dev_check(z, self._tod_dtype(p.prec), p.n_samp * nrhs, "z")
+        if x is None:
+            x = torch.empty(p.n * nrhs, dtype=torch.float64, device=z.device)
+        self._check(lib().mm_apply_PT(self.h, p.h, nrhs, _ptr(z), _ptr(x)), "mm_apply_PT")
+        return x
+
+    def noise_apply(self, nz: "Noise", y, z=None, nrhs: int = 1):
+        import torch
+        _dev_check(y, self._tod_dtype(nz.prec), nz.n_samp * nrhs, "y")
+        if z is None:
+            z = torch.empty_like(y)
+        self._check(lib().mm_noise_apply(self.h, nz.h, nrhs, _ptr(y), _ptr(z)), "mm_noise_apply")
+        return z
+
+    def apply_A(self, p, nz, x, y=None, nrhs: int = 1):
+        import torch
+        _dev_check(x, torch.float64, p.n * nrhs, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(lib().mm_apply_A(self.h, p.h, nz.h, nrhs, _ptr(x), _ptr(y)), "mm_apply_A")
+        return y
+
+    def rhs(self, p, nz, tod, b=None, nrhs: int = 1):
+        import torch
+        _dev_check(tod, self._tod_dtype(p.prec), p.n_samp * nrhs, "tod")
+        if b is None:
+            b = torch.empty(p.n * nrhs, dtype=torch.float64, device=tod.device)
+        self._check(lib().mm_rhs(self.h, p.h, nz.h, nrhs, _ptr(tod), _ptr(b)), "mm_rhs")
+        return b
+
+    # ------------------------------------------------------ preconditioners
+    def mbd(self, p, nz):
+        h = C.c_void_p()
+        self._check(lib().mm_mbd_build(self.h, p.h, nz.h, C.byref(h)), "mm_mbd_build")
+        return Precond(self, h, p.n, 0)
+
+    def defl_from_Z(self, p, nz, mbd, Z):
+        import torch
+        k = Z.shape[1] if Z.dim() == 2 else 1
+        Zc = Z.t().contiguous() if Z.dim() == 2 else Z.contiguous()
+        _dev_check(Zc, torch.float64, p.n * k, "Z")
+        h = C.c_void_p()
+        self._check(lib().mm_defl_from_Z(self.h, p.h, nz.h, mbd.h, k, _ptr(Zc), C.byref(h)),
+                    "mm_defl_from_Z")
+        return Precond(self, h, p.n, 1)
+
+    def defl_build(self, p, nz, mbd, b_seed, k: int = 32, eps_arn: float = 1e-8,
+                   m_max: int = 256, eps_lambda: float = 0.0):
+        import torch
+        _dev_check(b_seed, torch.float64, p.n, "b_seed")
+        hist = np.zeros(m_max)
+        info = ArnoldiInfo()
+        h = C.c_void_p()
+        self._check(lib().mm_defl_build(self.h, p.h, nz.h, mbd.h, _ptr(b_seed), k, eps_lambda,
+                                        eps_arn, m_max, hist.ctypes.data, C.byref(info),
+                                        C.byref(h)), "mm_defl_build")
+        M = Precond(self, h, p.n, 1)
+        M.arnoldi_info = info
+        M.h_history = hist[: info.m].copy()
+        return M
+
+    def precond_apply(self, M, v, out=None, nrhs: int = 1):
+        import torch
+        _dev_check(v, torch.float64, M.n * nrhs, "v")
+        if out is None:
+            out = torch.empty_like(v)
+        self._check(lib().mm_precond_apply(self.h, M.h, nrhs, _ptr(v), _ptr(out)),
+                    "mm_precond_apply")
+        return out
+
+    # ---------------------------------------------------------------- solve
+    def solve(self, p, nz, M, b, x=None, tol: float = 1e-8, max_iter: int = 2000,
+              nrhs: int = 1, check_every: int = 1, history: bool = True):
+        import torch
+        _dev_check(b, torch.float64, p.n * nrhs, "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        hist = np.zeros((nrhs, max_iter + 1)) if history else None
+        infos = (SolveInfo * nrhs)()
+        st = lib().mm_solve(self.h, p.h, nz.h, M.h if M is not None else None, nrhs, _ptr(b),
+                            _ptr(x), tol, max_iter, check_every & 0xFF,
+                            hist.ctypes.data if hist is not None else None, infos)
+        self._check(st, "mm_solve")
+        out = []
+        for c in range(nrhs):
+            i = infos[c]
+            h = hist[c, : i.iters + 1].copy() if hist is not None else None
+            out.append(dict(iters=i.iters, converged=bool(i.converged),
+                            breakdown=bool(i.breakdown), rel_res_recursive=i.rel_res_recursive,
+                            rel_res_true=i.rel_res_true, solve_seconds=i.solve_seconds,
+                            history=h, status=st))
+        return x, (out[0] if nrhs == 1 else out)
+
+    # ------------------------------------------------------------ profiling
+    def profile(self, on: bool):
+        self._check(lib().mm_profile_enable(self.h, 1 if on else 0), "mm_profile_enable")
+
+    def profile_read(self):
+        mx = 64
+        names = C.create_string_buffer(32 * mx)
+        ms = np.zeros(mx)
+        calls = np.zeros(mx, dtype=np.int64)
+        n = C.c_int32()
+        self._check(lib().mm_profile_read(self.h, mx, names, ms.ctypes.data, calls.ctypes.data,
+                                          C.byref(n)), "mm_profile_read")
+        res = {}
+        for i in range(min(n.value, mx)):
+            nm = names.raw[32 * i: 32 * i + 32].split(b"\0")[0].decode()
+            res[nm] = (float(ms[i]), int(calls[i]))
+        return res
+
+
+class _Handle:
+    _destroy = ""
+
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def close(self):
+        if getattr(self, "h", None):
+            getattr(lib(), self._destroy)(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pointing(_Handle):
+    _destroy = "mm_pointing_destroy"
+
+    def __init__(self, ctx, h, n_samp, n_pix_total, prec):
+        super().__init__(ctx, h)
+        self.n_samp, self.n_pix_total, self.prec = n_samp, n_pix_total, prec
+        n_obs, n_valid = C.c_int32(), C.c_int64()
+        lib().mm_pointing_counts(h, C.byref(n_obs), C.byref(n_valid))
+        self.n_obs, self.n_valid = n_obs.value, n_valid.value
+        self.n = 3 * self.n_obs
+
+    def hits(self):
+        import torch
+        dev = self.ctx.torch_device
+        hits = torch.empty(self.n_pix_total, dtype=torch.int32, device=dev)
+        obs = torch.empty(max(self.n_obs, 1), dtype=torch.int32, device=dev)
+        self.ctx._check(lib().mm_pointing_hits(self.ctx.h, self.h, _ptr(hits), _ptr(obs)),
+                        "mm_pointing_hits")
+        return hits, obs[: self.n_obs]
+
+    def export(self):
+        import torch
+        dev = self.ctx.torch_device
+        j = torch.empty(self.n_samp, dtype=torch.int32, device=dev)
+        perm = torch.empty(max(self.n_valid, 1), dtype=torch.int32, device=dev)
+        off = torch.empty(self.n_obs + 1, dtype=torch.int32, device=dev)
+        self.ctx._check(lib().mm_pointing_export(self.ctx.h, self.h, _ptr(j), _ptr(perm),
+                                                 _ptr(off)), "mm_pointing_export")
+        return j, perm[: self.n_valid], off
+
+
+class Noise(_Handle):
+    _destroy = "mm_noise_destroy"
+
+    def __init__(self, ctx, h, n_samp, half_bw, prec):
+        super().__init__(ctx, h)
+        self.n_samp, self.half_bw, self.prec = n_samp, half_bw, prec
+        m = C.c_int()
+        lib().mm_noise_method_used(h, C.byref(m))
+        self.method = m.value
+
+
+class Precond(_Handle):
+    _destroy = "mm_precond_destroy"
+
+    def __init__(self, ctx, h, n, kind):
+        super().__init__(ctx, h)
+        self.n, self.kind = n, kind
+
+    def rcond(self):
+        r = C.c_double()
+        lib().mm_mbd_rcond(self.h, C.byref(r))
+        return r.value
+
+    def export(self):
+        import torch
+        k = C.c_int32()
+        self.ctx._check(lib().mm_defl_export(self.ctx.h, self.h, C.byref(k), None, None, None),
+                        "mm_defl_export")
+        k = k.value
+        dev = self.ctx.torch_device
+        Z = torch.empty(k, self.n, dtype=torch.float64, device=dev)
+        AZ = torch.empty(k, self.n, dtype=torch.float64, device=dev)
+        E = torch.empty(k, k, dtype=torch.float64, device=dev)
+        self.ctx._check(lib().mm_defl_export(self.ctx.h, self.h, None, _ptr(Z), _ptr(AZ),
+                                             _ptr(E)), "mm_defl_export")
+        return Z.t(), AZ.t(), E
+
+    def arnoldi(self):
+        import torch
+        m = C.c_int32()
+        self.ctx._check(lib().mm_defl_arnoldi_export(self.ctx.h, self.h, C.byref(m), None, None),
+                        "mm_defl_arnoldi_export")
+        m = m.value
+        W = torch.empty(m + 1, self.n, dtype=torch.float64, device=self.ctx.torch_device)
+        H = np.zeros((m, m + 1))
+        self.ctx._check(lib().mm_defl_arnoldi_export(self.ctx.h, self.h, None, _ptr(W),
+                                                     H.ctypes.data), "mm_defl_arnoldi_export")
+        return W.t(), H.T.copy()

@@ -1,0 +1,321 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars: integer pointing outputs bit-exact; FP64 operator outputs within 1e-12
+relative (max-norm over the output); solver outputs as stated per test.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import build_both, dev, host, maxrel, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1801_08937_amd import mapmaker as mm
+    c = mm.Context(0)
+    yield c
+    c.close()
+
+
+def _problems():
+    # several tiles, ragged intervals, flagged samples, pixels below threshold
+    return [
+        synth.random_problem(1, n_side=8, n_samp=5000, n_int=5, half_bw=17, n_filters=3,
+                             flag_frac=0.1),
+        synth.random_problem(2, n_side=12, n_samp=20011, n_int=7, half_bw=40, n_filters=2,
+                             flag_frac=0.02, min_hits=150),
+        synth.config2(n_side=32, grid=(4, 2), samp_per_det=1 << 12, L=1 << 11, half_bw=100),
+    ]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_pointing_bit_exact(ctx, case):
+    p = _problems()[case]
+    lp, ln, op, on = build_both(ctx, p)
+    hits, obs = lp.hits()
+    j, perm, off = lp.export()
+    assert lp.n_obs == op.n_obs and lp.n_valid == op.perm.shape[0]
+    np.testing.assert_array_equal(host(hits), op.hits)
+    np.testing.assert_array_equal(host(obs), op.obs_pix)
+    np.testing.assert_array_equal(host(j), op.j)
+    np.testing.assert_array_equal(host(perm), op.perm)
+    np.testing.assert_array_equal(host(off), op.off)
+
+
+def test_pointing_bit_exact_config1(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    j, perm, off = lp.export()
+    np.testing.assert_array_equal(host(perm), op.perm)
+    np.testing.assert_array_equal(host(off), op.off)
+    np.testing.assert_array_equal(host(j), op.j)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_P_PT_noise_A_parity(ctx, case):
+    p = _problems()[case]
+    lp, ln, op, on = build_both(ctx, p, method=1)
+    rng = np.random.default_rng(case)
+    x = rng.standard_normal(op.n)
+    y = rng.standard_normal(op.n_samp)
+    assert maxrel(host(ctx.apply_P(lp, dev(x))), O.apply_P(op, x)) <= TOL_OP
+    assert maxrel(host(ctx.apply_PT(lp, dev(y))), O.apply_PT(op, y)) <= TOL_OP
+    assert maxrel(host(ctx.noise_apply(ln, dev(y))), O.noise_apply_direct(on, y)) <= TOL_OP
+    assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x)) <= TOL_OP
+    assert maxrel(host(ctx.rhs(lp, ln, dev(p.tod))), O.rhs(op, on, p.tod)) <= TOL_OP
+
+
+def test_config1_operators(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    x = np.random.default_rng(0).standard_normal(op.n)
+    assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x)) <= TOL_OP
+    assert maxrel(host(ctx.rhs(lp, ln, dev(p.tod))), O.rhs(op, on, p.tod)) <= TOL_OP
+
+
+def test_A_symmetric_positive_on_gpu(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal((2, op.n))
+    Ax = host(ctx.apply_A(lp, ln, dev(x)))
+    Ay = host(ctx.apply_A(lp, ln, dev(y)))
+    assert abs(x @ Ay - y @ Ax) <= 1e-12 * abs(x @ Ay)
+    assert x @ Ax > 0 and y @ Ay > 0
+
+
+def test_mbd_parity(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    OM = O.mbd_build(op, on)
+    v = np.random.default_rng(1).standard_normal(op.n)
+    assert maxrel(host(ctx.precond_apply(M, dev(v))), O.mbd_apply(OM, v)) <= TOL_OP
+    assert abs(M.rcond() - OM.rcond_min) <= 1e-10 * OM.rcond_min
+
+
+def test_m2l_from_Z_parity_and_identities(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    OM = O.mbd_build(op, on)
+    rng = np.random.default_rng(2)
+    k = 12
+    Z = rng.standard_normal((op.n, k))
+    M2 = ctx.defl_from_Z(lp, ln, M, dev(Z))
+    OM2 = O.m2l_from_Z(op, on, OM, Z)
+    Zg, AZg, Eg = M2.export()
+    assert maxrel(host(AZg), OM2.AZ) <= TOL_OP
+    assert maxrel(host(Eg), OM2.E) <= TOL_OP
+    v = rng.standard_normal(op.n)
+    assert maxrel(host(ctx.precond_apply(M2, dev(v))), O.m2l_apply(OM2, v)) <= 1e-10
+    # Eq. ident on the GPU: M_2l A Z = Z
+    for c in range(3):
+        out = host(ctx.precond_apply(M2, ctx.apply_A(lp, ln, dev(Z[:, c].copy()))))
+        assert rel(out, Z[:, c]) <= 1e-9
+
+
+def test_coarse_not_spd_reported(ctx):
+    from paper_1801_08937_amd import mapmaker as mm
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    z = np.random.default_rng(0).standard_normal(op.n)
+    with pytest.raises(mm.MapmakerError) as e:
+        ctx.defl_from_Z(lp, ln, M, dev(np.stack([z, z], axis=1)))
+    assert e.value.name == "MM_E_COARSE_NOT_SPD"
+
+
+def test_pcg_fixed_iterations_parity(ctx):
+    """Same algorithm, same iteration count: iterates agree to rounding."""
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    OM = O.mbd_build(op, on)
+    b = O.rhs(op, on, p.tod)
+    x, info = ctx.solve(lp, ln, M, dev(b), tol=0.0, max_iter=10)
+    xo, io = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), b, 0.0, 10)
+    assert info["iters"] == io.iters == 10
+    assert rel(host(x), xo) <= 1e-10
+    np.testing.assert_allclose(info["history"], io.history, rtol=1e-9)
+
+
+def test_solve_config1_mbd_to_1e8(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    b = ctx.rhs(lp, ln, dev(p.tod))
+    x, info = ctx.solve(lp, ln, M, b, tol=1e-8, max_iter=2000)
+    assert info["converged"] and info["rel_res_true"] <= 1.5e-8
+    OM = O.mbd_build(op, on)
+    bo = O.rhs(op, on, p.tod)
+    xo, io = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-13, 5000)
+    # both within kappa * tol of the exact solution; stated bound 1e-6
+    assert rel(host(x), xo) <= 1e-6
+    assert abs(info["iters"] - 0) >= 1
+
+
+def test_noiseless_recovery_gpu(ctx):
+    p = synth.config1(noiseless=True)
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    b = ctx.rhs(lp, ln, dev(p.tod))
+    x, info = ctx.solve(lp, ln, M, b, tol=1e-10, max_iter=2000)
+    s = p.signal[op.obs_pix].reshape(-1)
+    assert info["converged"]
+    assert rel(host(x), s) <= 1e-6
+
+
+def test_defl_build_parity_small(ctx):
+    """Arnoldi on the GPU vs the oracle: the first Hessenberg columns agree;
+    the selected deflation spaces span the same subspace (principal angles)."""
+    import scipy.linalg
+    p = synth.config2(n_side=16, grid=(2, 2), samp_per_det=1 << 10, L=1 << 9, half_bw=32)
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    OM = O.mbd_build(op, on)
+    b = O.rhs(op, on, p.tod)
+    k, m_max = 8, 60
+    M2 = ctx.defl_build(lp, ln, M, dev(b), k=k, eps_arn=1e-10, m_max=m_max)
+    OM2, res, theta = O.defl_build(op, on, OM, b, k, 1e-10, m_max)
+    W, H = M2.arnoldi()
+    assert M2.arnoldi_info.m == res.m
+    np.testing.assert_allclose(H[:11, :10], res.H[:11, :10], rtol=1e-10, atol=1e-12)
+    Zg = host(M2.export()[0])
+    assert Zg.shape[1] == OM2.Z.shape[1]
+    th = np.sort(theta.real)
+    if th[k] - th[k - 1] > 1e-3 * th[k]:
+        s = scipy.linalg.subspace_angles(Zg, OM2.Z)
+        assert np.max(np.sin(s)) <= 1e-6
+    # Z orthonormal
+    G = Zg.T @ Zg
+    assert np.abs(G - np.eye(G.shape[0])).max() <= 1e-12
+
+
+def test_m2l_converges_no_slower_than_mbd_config1(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    b = ctx.rhs(lp, ln, dev(p.tod))
+    M2 = ctx.defl_build(lp, ln, M, b, k=32, eps_arn=1e-8, m_max=256)
+    _, i1 = ctx.solve(lp, ln, M, b, tol=1e-8)
+    _, i2 = ctx.solve(lp, ln, M2, b, tol=1e-8)
+    assert i1["converged"] and i2["converged"]
+    assert i2["iters"] <= i1["iters"]
+    assert i2["rel_res_true"] <= 1.5e-8
+
+
+def test_determinism_bitwise(ctx):
+    import torch
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    x = dev(np.random.default_rng(3).standard_normal(op.n))
+    a = ctx.apply_A(lp, ln, x)
+    b = ctx.apply_A(lp, ln, x)
+    assert torch.equal(a, b)
+    M = ctx.mbd(lp, ln)
+    bb = ctx.rhs(lp, ln, dev(p.tod))
+    x1, _ = ctx.solve(lp, ln, M, bb, tol=1e-8)
+    x2, _ = ctx.solve(lp, ln, M, bb, tol=1e-8)
+    assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("R", [2, 8, 64])
+def test_multi_rhs_columns(ctx, R):
+    """Column r of a multi-RHS apply equals the single apply to rounding, and
+    does not depend on the other columns (bitwise)."""
+    import torch
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    rng = np.random.default_rng(R)
+    X = rng.standard_normal((op.n, R))
+    Y = host(ctx.apply_A(lp, ln, dev(X.reshape(-1)), nrhs=R)).reshape(op.n, R)
+    for r in (0, R - 1):
+        ref = O.apply_A(op, on, X[:, r])
+        assert maxrel(Y[:, r], ref) <= TOL_OP
+    X2 = X.copy()
+    X2[:, 1:] = rng.standard_normal((op.n, R - 1))
+    Y2 = host(ctx.apply_A(lp, ln, dev(X2.reshape(-1)), nrhs=R)).reshape(op.n, R)
+    np.testing.assert_array_equal(Y[:, 0], Y2[:, 0])
+
+
+def test_fp32_form_error_vs_fp64_oracle(ctx):
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p, prec=1)
+    x = np.random.default_rng(0).standard_normal(op.n)
+    e = rel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x))
+    assert e <= 1e-5, e
+    M = ctx.mbd(lp, ln)
+    import torch
+    b = ctx.rhs(lp, ln, dev(p.tod.astype(np.float32)))
+    xs, info = ctx.solve(lp, ln, M, b, tol=1e-6, max_iter=2000)
+    OM = O.mbd_build(op, on)
+    bo = O.rhs(op, on, p.tod)
+    xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-12, 5000)
+    err = rel(host(xs), xo)
+    print(f"fp32 form: map rel error vs FP64 oracle = {err:.3e}, iters = {info['iters']}")
+    assert err <= 1e-3
+
+
+def test_error_paths(ctx):
+    import torch
+    from paper_1801_08937_amd import mapmaker as mm
+    # singular 3x3 block: three hits at one angle
+    pix = np.array([0, 0, 0, 1, 1, 1, 1], dtype=np.int32)
+    psi = np.array([0.3, 0.3, 0.3, 0.0, 0.5, 1.0, 1.5])
+    lp = ctx.pointing(dev(pix), dev(psi), 2, 3)
+    ln = ctx.noise([0, 7], [0], [[1.0]], 0)
+    with pytest.raises(mm.MapmakerError) as e:
+        ctx.mbd(lp, ln)
+    assert e.value.name == "MM_E_SINGULAR_BLOCK"
+    # pixel out of range
+    with pytest.raises(mm.MapmakerError) as e:
+        ctx.pointing(dev(np.array([0, 9], dtype=np.int32)), dev(np.zeros(2)), 4, 1)
+    assert e.value.name == "MM_E_INVALID"
+    # non-finite TOD on an observed sample
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    d = p.tod.copy()
+    d[5] = np.nan
+    with pytest.raises(mm.MapmakerError) as e:
+        ctx.rhs(lp, ln, dev(d))
+    assert e.value.name == "MM_E_NONFINITE"
+    # bad nrhs
+    with pytest.raises(mm.MapmakerError) as e:
+        ctx.apply_A(lp, ln, dev(np.zeros(op.n * 3)), nrhs=3)
+    assert e.value.name == "MM_E_INVALID"
+    # bandwidth too wide for the intervals
+    with pytest.raises(mm.MapmakerError) as e:
+        ctx.noise([0, 10, 20], [0, 0], np.ones((1, 6)), 5)
+    assert e.value.name == "MM_E_INVALID"
+    # max_iter reached: not converged is a status, not an error
+    M = ctx.mbd(lp, ln)
+    b = ctx.rhs(lp, ln, dev(p.tod))
+    x, info = ctx.solve(lp, ln, M, b, tol=1e-12, max_iter=1)
+    assert info["iters"] == 1 and not info["converged"] and info["status"] == 1
+
+
+@pytest.mark.slow
+def test_config2_full_size_pointing_and_sampled_A(ctx):
+    """Config 2 at full size (1.34e8 samples): pointing bit-exact; A x checked
+    on sampled pixels computed one by one by the oracle."""
+    p = synth.config2()
+    lp, ln, op, on = build_both(ctx, p)
+    j, perm, off = lp.export()
+    np.testing.assert_array_equal(host(off), op.off)
+    np.testing.assert_array_equal(host(perm), op.perm)
+    del j, perm
+    x = np.random.default_rng(0).standard_normal(op.n)
+    Ax = host(ctx.apply_A(lp, ln, dev(x))).reshape(-1, 3)
+    pix = [0, 1234, op.n_obs // 2, op.n_obs - 1]
+    ref = O.apply_A_pixels(op, on, x, pix)
+    assert maxrel(Ax[pix], ref) <= 1e-10

@@ -200,6 +200,15 @@ def test_A_dense_spd():
     assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
 
 
+def test_apply_A_pixels_matches_full_product():
+    p, pt, nz = _setup(14, n_side=5, n_samp=1500, n_int=3, half_bw=30, flag_frac=0.1)
+    x = np.random.default_rng(3).standard_normal(pt.n)
+    full = O.apply_A(pt, nz, x).reshape(-1, 3)
+    pix = [0, 3, pt.n_obs - 1]
+    np.testing.assert_allclose(O.apply_A_pixels(pt, nz, x, pix), full[pix], rtol=1e-12,
+                               atol=1e-12 * np.abs(full).max())
+
+
 def test_b_noiseless_equals_A_s():
     p = synth.config1(noiseless=True)
     pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
