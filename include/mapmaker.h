@@ -239,6 +239,33 @@ mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const 
                    int32_t nrhs, const double *b, double *x, double tol, int32_t max_iter,
                    uint32_t flags, double *history, mm_solve_info *info);
 
+/* ------------------------------------------------- step-wise PCG sessions */
+
+/* A PCG session holds nrhs column slots that iterate in lockstep with the
+ * same pointing, noise and preconditioner; each slot carries its own
+ * right-hand side, tolerance and iteration budget.  A slot can be (re)started
+ * while other slots are mid-solve: this is the continuous-batching primitive
+ * of the serving layer.  Column results do not depend on what the other
+ * slots hold.  Iterations are Eq. pcg exactly as in mm_solve. */
+typedef struct mm_pcg mm_pcg;
+
+mm_status mm_pcg_create(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                        const mm_precond *M, int32_t nrhs, mm_pcg **out);
+/* Start slot from x_0 = 0: r = b, z = M r, p = z.  b [device] f64[n]
+ * (contiguous, one column).  tol: relative residual target; max_iter: budget. */
+mm_status mm_pcg_start(mm_ctx *ctx, mm_pcg *s, int32_t slot, const double *b, double tol,
+                       int32_t max_iter);
+/* Run n_iter lockstep iterations over the live slots (finished and free slots
+ * are skipped). */
+mm_status mm_pcg_iterate(mm_ctx *ctx, mm_pcg *s, int32_t n_iter);
+/* Per-slot state [host] arrays of nrhs (any may be NULL): state 0 = free,
+ * 1 = running, 2 = converged, 3 = iteration budget spent, 4 = breakdown;
+ * iterations taken; recursive relative residual. */
+mm_status mm_pcg_poll(mm_ctx *ctx, mm_pcg *s, int32_t *state, int32_t *iters, double *rel_res);
+/* Copy a slot's current solution to x [device] f64[n] and free the slot. */
+mm_status mm_pcg_finish(mm_ctx *ctx, mm_pcg *s, int32_t slot, double *x);
+void mm_pcg_destroy(mm_pcg *s);
+
 /* ---------------------------------------------------------- profiling aid */
 
 /* When on, each kernel of mm_apply_A / mm_solve is bracketed by HIP events on

@@ -161,6 +161,61 @@ void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precon
     MM_CHECK(!hf, MM_E_COARSE_NOT_SPD, "coarse matrix E = Z^T A Z is not positive definite");
 }
 
+// Device vectors and scalars of a column-batched PCG (Eq. pcg).
+struct PcgWork {
+    int R = 1;
+    int64_t n = 0;
+    int n_part = 1;
+    DBuf r, z, pv, q, part, sc;
+    PcgDev sd{};
+    void alloc(int64_t n_, int R_) {
+        n = n_;
+        R = R_;
+        n_part = reduction_parts(n);
+        const size_t vb = sizeof(double) * n * R;
+        r.alloc(vb);
+        z.alloc(vb);
+        pv.alloc(vb);
+        q.alloc(vb);
+        part.alloc(sizeof(double) * n_part * R);
+        sc.alloc(sizeof(double) * 7 * 64 + sizeof(int) * 3 * 64);
+        double *sb = sc.as<double>();
+        sd.rho = sb; sd.pq = sb + 64; sd.alpha = sb + 128; sd.beta = sb + 192;
+        sd.rn2 = sb + 256; sd.bn2 = sb + 320; sd.tol2 = sb + 384;
+        int *ib = reinterpret_cast<int *>(sb + 448);
+        sd.done = ib; sd.brk = ib + 64; sd.iters = ib + 128;
+    }
+};
+
+// z = M r on all columns with the fused partial sums of r.z.
+void pcg_apply_M(mm_ctx *ctx, const mm_precond *M, PcgWork &w, const double *in, double *out) {
+    if (M) {
+        precond_apply_impl(ctx, M, w.R, in, out, w.part.as<double>(), w.n_part);
+    } else {
+        MM_HIP(hipMemcpyAsync(out, in, sizeof(double) * w.n * w.R, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+        dot_partial_cols(ctx, w.n, w.R, in, out, w.part.as<double>(), w.n_part);
+    }
+}
+
+// One lockstep iteration over the live columns:
+//   q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q; ||r||^2;
+//   z = M r; rho' = r.z; beta = rho'/rho; p = z + beta p.
+void pcg_iteration(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const mm_precond *M,
+                   PcgWork &w, double *x) {
+    const int R = w.R;
+    apply_A_impl(ctx, p, nz, R, w.pv.as<double>(), w.q.as<double>());
+    dot_partial_cols(ctx, w.n, R, w.pv.as<double>(), w.q.as<double>(), w.part.as<double>(),
+                     w.n_part);
+    pcg_after_pq(ctx, R, w.sd, w.part.as<double>(), w.n_part);
+    pcg_update_xr(ctx, w.n, R, w.sd, w.pv.as<double>(), w.q.as<double>(), x, w.r.as<double>(),
+                  w.part.as<double>(), w.n_part);
+    pcg_after_rn(ctx, R, w.sd, w.part.as<double>(), w.n_part, 1);
+    pcg_apply_M(ctx, M, w, w.r.as<double>(), w.z.as<double>());
+    pcg_after_rz(ctx, R, w.sd, w.part.as<double>(), w.n_part, 0);
+    pcg_update_p(ctx, w.n, R, w.sd, w.z.as<double>(), w.pv.as<double>());
+}
+
 int choose_tile(int64_t n_samp, int n_cu) {
     int64_t per = n_samp / (4 * (int64_t)n_cu);
     int tl = 256;
@@ -760,90 +815,57 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     hipStream_t s = ctx->stream;
     const int64_t n = 3 * (int64_t)p->n_obs;
     const int R = nrhs;
-    const size_t vb = sizeof(double) * n * R;
-    DBuf r, z, pv, q, sc, part, hist;
-    r.alloc(vb);
-    z.alloc(vb);
-    pv.alloc(vb);
-    q.alloc(vb);
-    sc.alloc(sizeof(double) * 7 * 64 + sizeof(int) * 3 * 64);
-    const int n_part = reduction_parts(n);
-    part.alloc(sizeof(double) * n_part * R);
+    PcgWork w;
+    w.alloc(n, R);
+    DBuf hist;
     hist.alloc(sizeof(double) * (size_t)(max_iter + 1) * R);
-    PcgDev sd;
-    double *sb = sc.as<double>();
-    sd.rho = sb; sd.pq = sb + 64; sd.alpha = sb + 128; sd.beta = sb + 192;
-    sd.rn2 = sb + 256; sd.bn2 = sb + 320; sd.tol2 = sb + 384;
-    int *ib = reinterpret_cast<int *>(sb + 448);
-    sd.done = ib; sd.brk = ib + 64; sd.iters = ib + 128;
-    pcg_init_scalars(ctx, R, sd, tol);
-    dot_cols(ctx, n, R, b, b, sd.bn2);
+    pcg_init_scalars(ctx, R, w.sd, tol);
+    dot_cols(ctx, n, R, b, b, w.sd.bn2);
     // r = b - A x0
-    apply_A_impl(ctx, p, nz, R, x, q.as<double>());
-    axpby_cols(ctx, n, R, b, q.as<double>(), r.as<double>());
-    dot_partial_cols(ctx, n, R, r.as<double>(), r.as<double>(), part.as<double>(), n_part);
-    pcg_after_rn(ctx, R, sd, part.as<double>(), n_part, 0);
-    // z = M r, rho = r.z
-    auto apply_M = [&](const double *in, double *outv) {
-        if (M) {
-            precond_apply_impl(ctx, M, R, in, outv, part.as<double>(), n_part);
-        } else {
-            MM_HIP(hipMemcpyAsync(outv, in, vb, hipMemcpyDeviceToDevice, s));
-            dot_partial_cols(ctx, n, R, in, outv, part.as<double>(), n_part);
-        }
-    };
-    apply_M(r.as<double>(), z.as<double>());
-    pcg_after_rz(ctx, R, sd, part.as<double>(), n_part, 1);
-    MM_HIP(hipMemcpyAsync(pv.ptr, z.ptr, vb, hipMemcpyDeviceToDevice, s));
-    // device-side residual history: rn2 per iteration
-    const size_t hb = sizeof(double) * (size_t)(max_iter + 1) * R;
+    apply_A_impl(ctx, p, nz, R, x, w.q.as<double>());
+    axpby_cols(ctx, n, R, b, w.q.as<double>(), w.r.as<double>());
+    dot_partial_cols(ctx, n, R, w.r.as<double>(), w.r.as<double>(), w.part.as<double>(), w.n_part);
+    pcg_after_rn(ctx, R, w.sd, w.part.as<double>(), w.n_part, 0);
+    // z = M r, rho = r.z, p = z
+    pcg_apply_M(ctx, M, w, w.r.as<double>(), w.z.as<double>());
+    pcg_after_rz(ctx, R, w.sd, w.part.as<double>(), w.n_part, 1);
+    MM_HIP(hipMemcpyAsync(w.pv.ptr, w.z.ptr, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
     std::vector<double> h_rn2((size_t)(max_iter + 1) * R, -1.0);
-    double *hpin = pinned(ctx, sizeof(double) * 64 * 3 + sizeof(int) * 64 * 3);
-    MM_HIP(hipMemcpyAsync(hist.ptr, sd.rn2, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
+    int *hpin = reinterpret_cast<int *>(pinned(ctx, sizeof(int) * 64));
+    MM_HIP(hipMemcpyAsync(hist.ptr, w.sd.rn2, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
     const int check = std::max(1u, flags & 0xffu);
     int it = 0;
     auto poll = [&]() -> bool {
-        MM_HIP(hipMemcpyAsync(hpin, sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        MM_HIP(hipMemcpyAsync(hpin, w.sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
         MM_HIP(hipStreamSynchronize(s));
-        const int *dn = reinterpret_cast<const int *>(hpin);
         for (int c = 0; c < R; ++c)
-            if (!dn[c]) return false;
+            if (!hpin[c]) return false;
         return true;
     };
     bool all_done = poll();
     while (!all_done && it < max_iter) {
-        apply_A_impl(ctx, p, nz, R, pv.as<double>(), q.as<double>());
-        dot_partial_cols(ctx, n, R, pv.as<double>(), q.as<double>(), part.as<double>(), n_part);
-        pcg_after_pq(ctx, R, sd, part.as<double>(), n_part);
-        pcg_update_xr(ctx, n, R, sd, pv.as<double>(), q.as<double>(), x, r.as<double>(),
-                      part.as<double>(), n_part);
-        pcg_after_rn(ctx, R, sd, part.as<double>(), n_part, 1);
+        pcg_iteration(ctx, p, nz, M, w, x);
         ++it;
-        MM_HIP(hipMemcpyAsync(hist.as<double>() + (size_t)it * R, sd.rn2, sizeof(double) * R,
+        MM_HIP(hipMemcpyAsync(hist.as<double>() + (size_t)it * R, w.sd.rn2, sizeof(double) * R,
                               hipMemcpyDeviceToDevice, s));
-        apply_M(r.as<double>(), z.as<double>());
-        pcg_after_rz(ctx, R, sd, part.as<double>(), n_part, 0);
-        pcg_update_p(ctx, n, R, sd, z.as<double>(), pv.as<double>());
         if (it % check == 0 || it == max_iter) all_done = poll();
     }
     // true residual
-    apply_A_impl(ctx, p, nz, R, x, q.as<double>());
-    axpby_cols(ctx, n, R, b, q.as<double>(), r.as<double>());
+    apply_A_impl(ctx, p, nz, R, x, w.q.as<double>());
+    axpby_cols(ctx, n, R, b, w.q.as<double>(), w.r.as<double>());
     DBuf tr;
     tr.alloc(sizeof(double) * R);
-    dot_cols(ctx, n, R, r.as<double>(), r.as<double>(), tr.as<double>());
+    dot_cols(ctx, n, R, w.r.as<double>(), w.r.as<double>(), tr.as<double>());
     std::vector<double> h_tr(R), h_bn2(R), h_rn(R);
-    std::vector<int> h_done(R), h_brk(R), h_it(R);
+    std::vector<int> h_brk(R), h_it(R);
     MM_HIP(hipMemcpyAsync(h_tr.data(), tr.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-    MM_HIP(hipMemcpyAsync(h_bn2.data(), sd.bn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-    MM_HIP(hipMemcpyAsync(h_rn.data(), sd.rn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-    MM_HIP(hipMemcpyAsync(h_done.data(), sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
-    MM_HIP(hipMemcpyAsync(h_brk.data(), sd.brk, sizeof(int) * R, hipMemcpyDeviceToHost, s));
-    MM_HIP(hipMemcpyAsync(h_it.data(), sd.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_bn2.data(), w.sd.bn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_rn.data(), w.sd.rn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_brk.data(), w.sd.brk, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_it.data(), w.sd.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
     MM_HIP(hipMemcpyAsync(h_rn2.data(), hist.ptr, sizeof(double) * (size_t)(it + 1) * R,
                           hipMemcpyDeviceToHost, s));
     MM_HIP(hipStreamSynchronize(s));
-    (void)hb;
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool any_brk = false, all_conv = true;
@@ -864,7 +886,8 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
         if (history) {
             for (int k2 = 0; k2 <= max_iter; ++k2) {
                 double v = -1.0;
-                if (k2 <= h_it[c] && k2 <= it) v = std::sqrt(std::max(h_rn2[(size_t)k2 * R + c], 0.0)) / bn;
+                if (k2 <= h_it[c] && k2 <= it)
+                    v = std::sqrt(std::max(h_rn2[(size_t)k2 * R + c], 0.0)) / bn;
                 history[(size_t)c * (max_iter + 1) + k2] = v;
             }
         }
@@ -874,6 +897,165 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     API_END
     return result;
 }
+
+// ========================================================== PCG sessions
+
+struct mm_pcg {
+    const mm_pointing *p = nullptr;
+    const mm_noise *nz = nullptr;
+    const mm_precond *M = nullptr;
+    PcgWork w;
+    DBuf x, tb;
+    std::vector<int> state, host_iters, max_iter;
+    std::vector<double> tol;
+};
+
+extern "C" mm_status mm_pcg_create(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                   const mm_precond *M, int32_t nrhs, mm_pcg **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    check_nrhs(nrhs);
+    MM_CHECK(!M || M->n_obs == p->n_obs, MM_E_INVALID, "pcg: preconditioner of another pointing");
+    auto *S = new mm_pcg();
+    try {
+        S->p = p;
+        S->nz = nz;
+        S->M = M;
+        const int64_t n = 3 * (int64_t)p->n_obs;
+        S->w.alloc(n, nrhs);
+        S->x.alloc(sizeof(double) * n * nrhs);
+        S->tb.alloc(sizeof(double) * n);
+        MM_HIP(hipMemsetAsync(S->x.ptr, 0, sizeof(double) * n * nrhs, ctx->stream));
+        MM_HIP(hipMemsetAsync(S->w.r.ptr, 0, sizeof(double) * n * nrhs, ctx->stream));
+        MM_HIP(hipMemsetAsync(S->w.pv.ptr, 0, sizeof(double) * n * nrhs, ctx->stream));
+        pcg_init_scalars(ctx, nrhs, S->w.sd, 0.0);
+        for (int c = 0; c < nrhs; ++c) slot_ctl(ctx, S->w.sd, c, 0, 0.0);
+        S->state.assign(nrhs, 0);
+        S->host_iters.assign(nrhs, 0);
+        S->max_iter.assign(nrhs, 0);
+        S->tol.assign(nrhs, 0.0);
+        MM_HIP(hipStreamSynchronize(ctx->stream));
+    } catch (...) {
+        delete S;
+        throw;
+    }
+    *out = S;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pcg_start(mm_ctx *ctx, mm_pcg *S, int32_t slot, const double *b,
+                                  double tol, int32_t max_iter) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(S && b, MM_E_INVALID, "pcg_start: null argument");
+    MM_CHECK(slot >= 0 && slot < S->w.R, MM_E_INVALID, "pcg_start: slot out of range");
+    MM_CHECK(tol >= 0 && max_iter >= 0, MM_E_INVALID, "pcg_start: bad tol/max_iter");
+    PcgWork &w = S->w;
+    const int64_t n = w.n;
+    double *z1 = S->tb.as<double>();
+    // x = 0, r = b, z = M b, p = z
+    col_set(ctx, n, w.R, slot, nullptr, S->x.as<double>());
+    col_set(ctx, n, w.R, slot, b, w.r.as<double>());
+    if (S->M)
+        precond_apply_impl(ctx, S->M, 1, b, z1, nullptr, 0);
+    else
+        MM_HIP(hipMemcpyAsync(z1, b, sizeof(double) * n, hipMemcpyDeviceToDevice, ctx->stream));
+    col_set(ctx, n, w.R, slot, z1, w.pv.as<double>());
+    dot_cols(ctx, n, 1, b, b, w.sd.bn2 + slot);
+    dot_cols(ctx, n, 1, b, z1, w.sd.rho + slot);
+    slot_ctl(ctx, w.sd, slot, 1, tol);
+    S->state[slot] = 1;
+    S->host_iters[slot] = 0;
+    S->max_iter[slot] = max_iter;
+    S->tol[slot] = tol;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pcg_iterate(mm_ctx *ctx, mm_pcg *S, int32_t n_iter) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(S && n_iter >= 0, MM_E_INVALID, "pcg_iterate: bad arguments");
+    int left = n_iter;
+    while (left > 0) {
+        int chunk = left;
+        bool any = false;
+        for (int c = 0; c < S->w.R; ++c)
+            if (S->state[c] == 1) {
+                const int rem = S->max_iter[c] - S->host_iters[c];
+                if (rem <= 0) {
+                    slot_ctl(ctx, S->w.sd, c, 0, 0.0);
+                    S->state[c] = 5;  // budget spent; classified at the next poll
+                    continue;
+                }
+                any = true;
+                chunk = std::min(chunk, rem);
+            }
+        if (!any) break;
+        for (int i = 0; i < chunk; ++i) pcg_iteration(ctx, S->p, S->nz, S->M, S->w, S->x.as<double>());
+        for (int c = 0; c < S->w.R; ++c)
+            if (S->state[c] == 1) {
+                S->host_iters[c] += chunk;
+                if (S->host_iters[c] >= S->max_iter[c]) {
+                    slot_ctl(ctx, S->w.sd, c, 0, 0.0);
+                    S->state[c] = 5;
+                }
+            }
+        left -= chunk;
+    }
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pcg_poll(mm_ctx *ctx, mm_pcg *S, int32_t *state, int32_t *iters,
+                                 double *rel_res) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(S, MM_E_INVALID, "pcg_poll: null session");
+    const int R = S->w.R;
+    std::vector<int> dn(R), br(R), it(R);
+    std::vector<double> rn(R), bn(R);
+    hipStream_t s = ctx->stream;
+    MM_HIP(hipMemcpyAsync(dn.data(), S->w.sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(br.data(), S->w.sd.brk, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(it.data(), S->w.sd.iters, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(rn.data(), S->w.sd.rn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(bn.data(), S->w.sd.bn2, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < R; ++c) {
+        if (S->state[c] == 1 || S->state[c] == 5) {
+            if (dn[c] || S->state[c] == 5) {
+                const double t2 = S->tol[c] * S->tol[c];
+                S->state[c] = br[c] ? 4 : (rn[c] <= t2 * bn[c] ? 2 : 3);
+            }
+        }
+        if (state) state[c] = S->state[c];
+        if (iters) iters[c] = S->state[c] == 0 ? 0 : it[c];
+        if (rel_res)
+            rel_res[c] = (S->state[c] == 0) ? 0.0
+                         : std::sqrt(std::max(rn[c], 0.0)) / (bn[c] > 0 ? std::sqrt(bn[c]) : 1.0);
+    }
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pcg_finish(mm_ctx *ctx, mm_pcg *S, int32_t slot, double *x) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(S && x, MM_E_INVALID, "pcg_finish: null argument");
+    MM_CHECK(slot >= 0 && slot < S->w.R, MM_E_INVALID, "pcg_finish: slot out of range");
+    col_get(ctx, S->w.n, S->w.R, slot, S->x.as<double>(), x);
+    slot_ctl(ctx, S->w.sd, slot, 0, 0.0);
+    S->state[slot] = 0;
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+    return MM_OK;
+}
+
+extern "C" void mm_pcg_destroy(mm_pcg *S) { delete S; }
 
 // ============================================================== profiling
 

@@ -359,19 +359,47 @@ __global__ void k_scale(int64_t n, const double *__restrict__ src, const double 
         dst[i] = src[i] * f;
 }
 
-// Zout[:, c] = sum_m V[:, m] Y[m + c * kin]  (Y on device, col-major kin x kout)
-__global__ void __launch_bounds__(BS) k_mat_small_right(int64_t n, int kin, int kout,
+// Zout = V Y for tall V (n x kin, column-major) and small Y (kin x kout,
+// column-major, kout <= 64) on FP64 MFMA: each wave owns 16 output rows and
+// all kout columns (up to four 16 x 16 accumulators), stepping through kin four
+// columns of V at a time.
+using d4m = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+
+__global__ void __launch_bounds__(BS) k_gemm_tall_small(int64_t n, int kin, int kout,
                                                         const double *__restrict__ V,
                                                         const double *__restrict__ Y,
                                                         double *__restrict__ Zo) {
-    extern __shared__ double sy[];
-    for (int e = threadIdx.x; e < kin * kout; e += BS) sy[e] = Y[e];
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-        for (int c = 0; c < kout; ++c) {
-            double acc = 0;
-            for (int m = 0; m < kin; ++m) acc += V[(int64_t)m * n + i] * sy[m + c * kin];
-            Zo[(int64_t)c * n + i] = acc;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+    if (row0 >= n) return;
+    const int i16 = lane % 16, k4 = lane / 16;
+    const int64_t arow = row0 + i16;
+    const int TB = (kout + 15) / 16;
+    d4m acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4m{0, 0, 0, 0};
+    for (int m = 0; m < kin; m += 4) {
+        const int mm = m + k4;
+        const double av = (arow < n && mm < kin) ? V[(int64_t)mm * n + arow] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < TB) {
+                const int col = q * 16 + i16;
+                const double bv = (mm < kin && col < kout) ? Y[(int64_t)col * kin + mm] : 0.0;
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    // item v of lane l holds row l/16 + 4 v, column l % 16
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < TB) {
+            const int col = q * 16 + i16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + k4 + 4 * v;
+                if (row < n && col < kout) Zo[(int64_t)col * n + row] = acc[q][v];
+            }
         }
     }
 }
@@ -433,7 +461,8 @@ __global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
             }
         }
     }
-    // D layout: lane holds rows 4*(lane/16) + v, column lane % 16
+    // D layout of v_mfma_f64_16x16x4f64 (checked on gfx950): item v of lane l
+    // holds row l/16 + 4 v, column l % 16.
     double *out = partial + (int64_t)blockIdx.x * 64 * 64;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -442,7 +471,7 @@ __global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
             const int ta = t / TB, tb = t % TB;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = ta * 16 + 4 * (lane / 16) + v;
+                const int row = ta * 16 + (lane / 16) + 4 * v;
                 const int col = tb * 16 + (lane % 16);
                 out[row * 64 + col] = acc[q][v];
             }
@@ -574,6 +603,37 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
                              dot_with[base + 2 * R] * o2;
     }
     if (partial) block_col_reduce<R>(acc, partial);
+}
+
+// ----------------------------------------------------- session slot helpers
+
+// dst[i R + slot] = src ? src[i] : 0
+__global__ void k_col_set(int64_t n, int R, int slot, const double *__restrict__ src,
+                          double *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        dst[i * R + slot] = src ? src[i] : 0.0;
+}
+
+// dst[i] = src[i R + slot]
+__global__ void k_col_get(int64_t n, int R, int slot, const double *__restrict__ src,
+                          double *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        dst[i] = src[i * R + slot];
+}
+
+// mode 0: slot becomes free/stopped (done = 1); mode 1: (re)start with
+// tolerance tol (rn2 = bn2, already written), done if already converged.
+__global__ void k_slot_ctl(PcgDev s, int slot, int mode, double tol) {
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        s.done[slot] = 1;
+        return;
+    }
+    s.tol2[slot] = tol * tol;
+    s.iters[slot] = 0;
+    s.brk[slot] = 0;
+    s.rn2[slot] = s.bn2[slot];
+    s.done[slot] = (s.rn2[slot] <= s.tol2[slot] * s.bn2[slot]) ? 1 : 0;
 }
 
 template <typename F> void dispatch_r(int nrhs, F &&f) {
@@ -737,6 +797,21 @@ void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const d
     MM_HIP(hipGetLastError());
 }
 
+void col_set(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst) {
+    k_col_set<<<grid_for(n), BS, 0, ctx->stream>>>(n, R, slot, src, dst);
+    MM_HIP(hipGetLastError());
+}
+
+void col_get(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst) {
+    k_col_get<<<grid_for(n), BS, 0, ctx->stream>>>(n, R, slot, src, dst);
+    MM_HIP(hipGetLastError());
+}
+
+void slot_ctl(mm_ctx *ctx, PcgDev s, int slot, int mode, double tol) {
+    k_slot_ctl<<<1, 64, 0, ctx->stream>>>(s, slot, mode, tol);
+    MM_HIP(hipGetLastError());
+}
+
 void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, double *h) {
     Scope sc(ctx->prof, ctx->stream, "gemv");
     const int parts = reduction_parts(n);
@@ -762,10 +837,10 @@ void scale_copy(mm_ctx *ctx, int64_t n, const double *src, const double *s_dev, 
 
 void matmul_small_right(mm_ctx *ctx, int64_t n, int kin, int kout, const double *V,
                         const double *Y, double *Zo) {
-    MM_CHECK((size_t)kin * kout * sizeof(double) <= 60 * 1024, MM_E_INVALID,
-             "matmul_small_right: coefficient block too large");
-    k_mat_small_right<<<grid_for(n, 2048), BS, sizeof(double) * kin * kout, ctx->stream>>>(
-        n, kin, kout, V, Y, Zo);
+    Scope sc(ctx->prof, ctx->stream, "gemm_mfma");
+    MM_CHECK(kout >= 1 && kout <= 64 && kin >= 1, MM_E_INVALID, "matmul_small_right: sizes");
+    const int64_t blocks = (n + 63) / 64;
+    k_gemm_tall_small<<<(unsigned)blocks, BS, 0, ctx->stream>>>(n, kin, kout, V, Y, Zo);
     MM_HIP(hipGetLastError());
 }
 

@@ -213,11 +213,18 @@ void pcg_after_rz(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_
 void pcg_update_p(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *z, double *p);
 void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b,
                       double *partial, int n_part);
+void col_set(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst);
+void col_get(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst);
+void slot_ctl(mm_ctx *ctx, PcgDev s, int slot, int mode, double tol);
 void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const double *src,
                       double *dst);
 
 // host
 void hessenberg_eig(int m, const double *H, double *wr, double *wi, double *vr, double *vi);
+
+template <typename T> struct Vec2T;
+template <> struct Vec2T<float> { using type = float2; };
+template <> struct Vec2T<double> { using type = double2; };
 
 inline int pow2_ok(int r) { return r >= 1 && r <= 64 && (r & (r - 1)) == 0; }
 

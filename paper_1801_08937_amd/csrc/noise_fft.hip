@@ -1,25 +1,330 @@
-// N^-1 by FFT (overlap-save per stationary interval).  Placeholder until the
-// LDS-resident FFT kernel lands: reports itself unsupported so AUTO picks the
-// direct band.
+// N^-1 by FFT: overlap-save convolution per stationary interval.
+//
+// For an interval [a, e) with half bandwidth lambda, the outputs
+// t in [t0, t0 + V) need the inputs u in [t0 - lambda, t0 - lambda + N)
+// (zero outside the interval), N = 2 NC real samples, V = N - 2 lambda.  A
+// circular convolution of length N with the symmetric kernel
+// h = (c_0, c_1 .. c_lambda, 0 .., c_lambda .. c_1) is then exact on those V
+// outputs: no wrapped-around term reaches them.  The banded matrix is never
+// formed; its spectrum H_k = c_0 + 2 sum_d c_d cos(2 pi k d / N) is real.
+//
+// One workgroup per block: the N real inputs are packed as NC complex values
+// z_m = y_{2m} + i y_{2m+1}, transformed by an NC-point complex FFT held in
+// LDS (Stockham, radices 16 x 8 x 8 x 8, data exchanged through LDS between
+// passes), multiplied by the spectrum in the packed domain
+//     Z'_k = A_k Z_k + B_k (W^k O_k + i W^-k E_k),
+//     E_k = (Z_k + conj Z_{NC-k}) / 2,  O_k = (Z_k - conj Z_{NC-k}) / 2i,
+//     A_k = (H_k + H_{k+NC}) / 2NC,     B_k = (H_k - H_{k+NC}) / 2NC,  W = e^{-2 pi i / N},
+// and transformed back; the real and imaginary parts of the result are the
+// even and odd outputs.
+#include <cmath>
+
 #include "mm_internal.h"
 
 namespace mm {
+namespace {
+
+constexpr int FFT_NC = 8192;       // complex points per block
+constexpr int FFT_N = 2 * FFT_NC;  // real samples per block
+constexpr int FFT_THREADS = 512;
+constexpr int FFT_MAX_LAMBDA = 6144;
+
+// e^{2 pi i m / 16}
+__device__ constexpr double C16[16] = {
+    1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898,
+    0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
+    -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898,
+    0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
+__device__ constexpr double S16[16] = {
+    0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867,
+    1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898,
+    0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
+    -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+
+constexpr int ilog2(int r) { return r <= 1 ? 0 : 1 + ilog2(r / 2); }
+constexpr int bitrev(int i, int bits) {
+    int o = 0;
+    for (int b = 0; b < bits; ++b) o |= ((i >> b) & 1) << (bits - 1 - b);
+    return o;
+}
+
+// In-register R-point DFT, DIR = -1 forward, +1 inverse (radix-2, decimation
+// in time).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_small(T (&re)[R], T (&im)[R]) {
+    constexpr int B = ilog2(R);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int j = bitrev(i, B);
+        if (i < j) {
+            T t = re[i]; re[i] = re[j]; re[j] = t;
+            t = im[i]; im[i] = im[j]; im[j] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len *= 2) {
+        const int half = len / 2;
+        const int step = 16 / len;
+#pragma unroll
+        for (int i = 0; i < R; i += len) {
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                const T wr = (T)C16[k * step];
+                const T wi = (T)(DIR * S16[k * step]);
+                const T xr = re[i + k + half], xi = im[i + k + half];
+                const T tr = wr * xr - wi * xi;
+                const T ti = wr * xi + wi * xr;
+                re[i + k + half] = re[i + k] - tr;
+                im[i + k + half] = im[i + k] - ti;
+                re[i + k] += tr;
+                im[i + k] += ti;
+            }
+        }
+    }
+}
+
+// One Stockham pass of radix R at sub-transform size NS over the NC points in
+// LDS.  tw[m] = e^{-2 pi i m / NC}.
+template <typename T, int R, int NS, int DIR>
+__device__ __forceinline__ void stockham_pass(T *__restrict__ sre, T *__restrict__ sim,
+                                              const typename Vec2T<T>::type *__restrict__ tw) {
+    constexpr int NB = FFT_NC / R;
+    constexpr int PER = NB / FFT_THREADS;
+    T re[PER][R], im[PER][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int j = tid + p * FFT_THREADS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            re[p][r] = sre[j + r * NB];
+            im[p][r] = sim[j + r * NB];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int j = tid + p * FFT_THREADS;
+        const int jm = j % NS;
+        if (NS > 1) {
+            constexpr int SCALE = FFT_NC / (NS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const auto w = tw[jm * r * SCALE];
+                const T wr = w.x, wi = DIR < 0 ? w.y : -w.y;
+                const T xr = re[p][r], xi = im[p][r];
+                re[p][r] = wr * xr - wi * xi;
+                im[p][r] = wr * xi + wi * xr;
+            }
+        }
+        dft_small<T, R, DIR>(re[p], im[p]);
+        const int idx = (j / NS) * NS * R + jm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sre[idx + r * NS] = re[p][r];
+            sim[idx + r * NS] = im[p][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int DIR>
+__device__ __forceinline__ void fft8192(T *sre, T *sim, const typename Vec2T<T>::type *tw) {
+    stockham_pass<T, 16, 1, DIR>(sre, sim, tw);
+    stockham_pass<T, 8, 16, DIR>(sre, sim, tw);
+    stockham_pass<T, 8, 128, DIR>(sre, sim, tw);
+    stockham_pass<T, 8, 1024, DIR>(sre, sim, tw);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FFT_THREADS)
+    k_noise_fft(const int64_t *__restrict__ blocks, const int64_t *__restrict__ istart,
+                const int32_t *__restrict__ fid, const typename Vec2T<T>::type *__restrict__ ab,
+                const typename Vec2T<T>::type *__restrict__ tw,
+                const typename Vec2T<T>::type *__restrict__ twN, int lam, int V, int R,
+                const T *__restrict__ y, T *__restrict__ z) {
+    __shared__ T sre[FFT_NC];
+    __shared__ T sim[FFT_NC];
+    const int tid = threadIdx.x;
+    const int r = blockIdx.y;
+    const int64_t t0 = blocks[2 * blockIdx.x];
+    const int64_t iv = blocks[2 * blockIdx.x + 1];
+    const int64_t a = istart[iv], e = istart[iv + 1];
+    const int64_t base = t0 - lam;
+    for (int m = tid; m < FFT_NC; m += FFT_THREADS) {
+        const int64_t u0 = base + 2 * m, u1 = u0 + 1;
+        sre[m] = (u0 >= a && u0 < e) ? y[u0 * R + r] : (T)0;
+        sim[m] = (u1 >= a && u1 < e) ? y[u1 * R + r] : (T)0;
+    }
+    __syncthreads();
+    fft8192<T, -1>(sre, sim, tw);
+    // spectrum in the packed domain, one (k, NC-k) pair per thread step
+    const auto *abf = ab + (int64_t)fid[iv] * FFT_NC;
+    for (int k = tid; k <= FFT_NC / 2; k += FFT_THREADS) {
+        const int kp = (FFT_NC - k) & (FFT_NC - 1);
+        const T zr = sre[k], zi = sim[k], pr = sre[kp], pi = sim[kp];
+        // pair member k
+        {
+            const T er = (zr + pr) * (T)0.5, ei = (zi - pi) * (T)0.5;   // E = (Z + conj Zp)/2
+            const T orr = (zi + pi) * (T)0.5, oi = -(zr - pr) * (T)0.5; // O = (Z - conj Zp)/2i
+            const auto w = twN[k];
+            const T wr = w.x, wi = w.y;                                 // W^k
+            // W^k O + i W^-k E
+            const T a1r = wr * orr - wi * oi, a1i = wr * oi + wi * orr;
+            const T b1r = wr * er + wi * ei, b1i = wr * ei - wi * er;   // W^-k E
+            const T sr = a1r - b1i, si = a1i + b1r;
+            const auto c = abf[k];
+            sre[k] = c.x * zr + c.y * sr;
+            sim[k] = c.x * zi + c.y * si;
+        }
+        if (kp != k) {
+            const T er = (pr + zr) * (T)0.5, ei = (pi - zi) * (T)0.5;
+            const T orr = (pi + zi) * (T)0.5, oi = -(pr - zr) * (T)0.5;
+            const auto w = twN[kp];
+            const T wr = w.x, wi = w.y;
+            const T a1r = wr * orr - wi * oi, a1i = wr * oi + wi * orr;
+            const T b1r = wr * er + wi * ei, b1i = wr * ei - wi * er;
+            const T sr = a1r - b1i, si = a1i + b1r;
+            const auto c = abf[kp];
+            sre[kp] = c.x * pr + c.y * sr;
+            sim[kp] = c.x * pi + c.y * si;
+        }
+    }
+    __syncthreads();
+    fft8192<T, 1>(sre, sim, tw);
+    int64_t nvalid = e - t0;
+    if (nvalid > V) nvalid = V;
+    for (int q = tid; q < nvalid; q += FFT_THREADS) {
+        const int np = lam + q;
+        const T v = (np & 1) ? sim[np >> 1] : sre[np >> 1];
+        z[(t0 + q) * R + r] = v;
+    }
+}
+
+// H_k = c_0 + 2 sum_d c_d cos(2 pi k d / N) for k in [0, NC], with the cosine
+// table cos(2 pi m / N), m < N, staged in LDS (exact argument reduction by
+// integer arithmetic on k d mod N).
+__global__ void __launch_bounds__(256)
+    k_fft_spectrum(const double *__restrict__ band, int lam, const double *__restrict__ ctab,
+                   double *__restrict__ H) {
+    __shared__ double sc[FFT_N];
+    for (int m = threadIdx.x; m < FFT_N; m += 256) sc[m] = ctab[m];
+    __syncthreads();
+    const int f = blockIdx.y;
+    const double *c = band + (int64_t)f * (lam + 1);
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k > FFT_NC) return;
+    double s = 0;
+    for (int d = 1; d <= lam; ++d) s += c[d] * sc[(int)(((int64_t)k * d) & (FFT_N - 1))];
+    H[(int64_t)f * (FFT_NC + 1) + k] = c[0] + 2.0 * s;
+}
+
+template <typename T>
+__global__ void k_fft_ab(const double *__restrict__ H, int n_filters,
+                         typename Vec2T<T>::type *__restrict__ ab) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)n_filters * FFT_NC) return;
+    const int64_t f = e / FFT_NC;
+    const int k = (int)(e % FFT_NC);
+    const double hk = H[f * (FFT_NC + 1) + k];
+    const double hc = H[f * (FFT_NC + 1) + (FFT_NC - k)];  // H_{k+NC} = H_{NC-k}
+    typename Vec2T<T>::type v;
+    v.x = (T)((hk + hc) / (2.0 * FFT_NC));
+    v.y = (T)((hk - hc) / (2.0 * FFT_NC));
+    ab[e] = v;
+}
+
+}  // namespace
 
 bool noise_fft_supported(int half_bw, int64_t min_len) {
-    (void)half_bw;
     (void)min_len;
-    return false;
+    return half_bw >= 1 && half_bw <= FFT_MAX_LAMBDA;
 }
 
 void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz) {
-    (void)ctx;
-    (void)nz;
-    throw Error(MM_E_INVALID, "FFT noise method not available");
+    hipStream_t s = ctx->stream;
+    const int lam = nz->half_bw;
+    MM_CHECK(noise_fft_supported(lam, 0), MM_E_INVALID, "FFT: bandwidth unsupported");
+    nz->fft_n = FFT_N;
+    nz->fft_valid = FFT_N - 2 * lam;
+    const bool f32 = nz->prec == MM_F32;
+    const size_t e2 = f32 ? sizeof(float2) : sizeof(double2);
+    // twiddle tables (long double on the host, rounded once)
+    std::vector<double> ctab(FFT_N);
+    std::vector<double> tw(2 * FFT_NC), twN(2 * FFT_NC);
+    const long double pi2 = 6.283185307179586476925286766559L;
+    for (int m = 0; m < FFT_N; ++m) ctab[m] = (double)cosl(pi2 * m / FFT_N);
+    for (int m = 0; m < FFT_NC; ++m) {
+        tw[2 * m] = (double)cosl(pi2 * m / FFT_NC);
+        tw[2 * m + 1] = (double)-sinl(pi2 * m / FFT_NC);
+        twN[2 * m] = (double)cosl(pi2 * m / FFT_N);
+        twN[2 * m + 1] = (double)-sinl(pi2 * m / FFT_N);
+    }
+    nz->fft_tw.alloc(2 * e2 * FFT_NC);  // tw then twN
+    if (f32) {
+        std::vector<float> a(4 * FFT_NC);
+        for (int i = 0; i < 2 * FFT_NC; ++i) {
+            a[i] = (float)tw[i];
+            a[2 * FFT_NC + i] = (float)twN[i];
+        }
+        MM_HIP(hipMemcpyAsync(nz->fft_tw.ptr, a.data(), sizeof(float) * a.size(),
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipStreamSynchronize(s));
+    } else {
+        MM_HIP(hipMemcpyAsync(nz->fft_tw.ptr, tw.data(), sizeof(double) * tw.size(),
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipMemcpyAsync(nz->fft_tw.as<double>() + 2 * FFT_NC, twN.data(),
+                              sizeof(double) * twN.size(), hipMemcpyHostToDevice, s));
+        MM_HIP(hipStreamSynchronize(s));
+    }
+    // spectra
+    DBuf dctab, H;
+    dctab.alloc(sizeof(double) * FFT_N);
+    H.alloc(sizeof(double) * (size_t)nz->n_filters * (FFT_NC + 1));
+    MM_HIP(hipMemcpyAsync(dctab.ptr, ctab.data(), sizeof(double) * FFT_N, hipMemcpyHostToDevice, s));
+    dim3 g((FFT_NC + 1 + 255) / 256, nz->n_filters);
+    k_fft_spectrum<<<g, 256, 0, s>>>(nz->band64.as<double>(), lam,
+                                                           dctab.as<double>(), H.as<double>());
+    nz->fft_spec.alloc(e2 * (size_t)nz->n_filters * FFT_NC);
+    const int64_t tot = (int64_t)nz->n_filters * FFT_NC;
+    if (f32)
+        k_fft_ab<float><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(H.as<double>(), nz->n_filters,
+                                                                   nz->fft_spec.as<float2>());
+    else
+        k_fft_ab<double><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(H.as<double>(), nz->n_filters,
+                                                                    nz->fft_spec.as<double2>());
+    MM_HIP(hipGetLastError());
+    // block table
+    std::vector<int64_t> blocks;
+    for (int i = 0; i < nz->n_int; ++i)
+        for (int64_t t = nz->h_istart[i]; t < nz->h_istart[i + 1]; t += nz->fft_valid) {
+            blocks.push_back(t);
+            blocks.push_back(i);
+        }
+    nz->n_fft_blocks = (int64_t)blocks.size() / 2;
+    nz->fft_blocks.alloc(sizeof(int64_t) * blocks.size());
+    MM_HIP(hipMemcpyAsync(nz->fft_blocks.ptr, blocks.data(), sizeof(int64_t) * blocks.size(),
+                          hipMemcpyHostToDevice, s));
+    MM_HIP(hipStreamSynchronize(s));
 }
 
 void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
-    (void)ctx; (void)nz; (void)nrhs; (void)y; (void)z;
-    throw Error(MM_E_INVALID, "FFT noise method not available");
+    Scope sc(ctx->prof, ctx->stream, "Ninv_fft");
+    dim3 grid((unsigned)nz->n_fft_blocks, nrhs);
+    if (nz->prec == MM_F32) {
+        const float2 *tw = nz->fft_tw.as<float2>();
+        k_noise_fft<float><<<grid, FFT_THREADS, 0, ctx->stream>>>(
+            nz->fft_blocks.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+            nz->fft_spec.as<float2>(), tw, tw + FFT_NC, nz->half_bw, nz->fft_valid, nrhs,
+            static_cast<const float *>(y), static_cast<float *>(z));
+    } else {
+        const double2 *tw = nz->fft_tw.as<double2>();
+        k_noise_fft<double><<<grid, FFT_THREADS, 0, ctx->stream>>>(
+            nz->fft_blocks.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+            nz->fft_spec.as<double2>(), tw, tw + FFT_NC, nz->half_bw, nz->fft_valid, nrhs,
+            static_cast<const double *>(y), static_cast<double *>(z));
+    }
+    MM_HIP(hipGetLastError());
 }
 
 }  // namespace mm

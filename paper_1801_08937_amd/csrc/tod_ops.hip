@@ -27,6 +27,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nb) {
 namespace {
 
 constexpr int BS = 256;
+constexpr int BAND_LDS_MAX = 2047;
 
 template <typename T, int R>
 __global__ void __launch_bounds__(BS) k_apply_P(const int32_t *__restrict__ jpix,
@@ -101,8 +102,11 @@ __global__ void __launch_bounds__(BS) k_band(const int64_t *__restrict__ tiles,
                                              const T *__restrict__ band, int lam, int TL,
                                              const T *__restrict__ y, T *__restrict__ z) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    // the band sits in LDS when it fits beside the input chunk, else it is
+    // read through the cache hierarchy
+    const bool band_in_lds = lam <= BAND_LDS_MAX;
+    const int band_slots = band_in_lds ? ((lam + 1 + 3) & ~3) : 0;
     T *sb = reinterpret_cast<T *>(smem_raw);
-    const int band_slots = (lam + 1 + 3) & ~3;
     T *sy = sb + band_slots;
     constexpr int CHR = 4096;          // LDS chunk, in elements
     constexpr int CH = CHR / R;        // samples per chunk
@@ -118,7 +122,9 @@ __global__ void __launch_bounds__(BS) k_band(const int64_t *__restrict__ tiles,
     if (t1 > tile_end) t1 = tile_end;
     if (t0 >= t1) return;
 
-    for (int i = threadIdx.x; i <= lam; i += BS) sb[i] = c[i];
+    if (band_in_lds)
+        for (int i = threadIdx.x; i <= lam; i += BS) sb[i] = c[i];
+    const T *cb = band_in_lds ? sb : c;
 
     constexpr int SPT = BS / R;  // sample slots per pass
     const int r = threadIdx.x % R;
@@ -149,7 +155,7 @@ __global__ void __launch_bounds__(BS) k_band(const int64_t *__restrict__ tiles,
                     T s = acc[q];
                     for (int64_t u = ulo; u < uhi; ++u) {
                         const int64_t d = t > u ? t - u : u - t;
-                        s += sb[d] * sy[(u - c0) * R + r];
+                        s += cb[d] * sy[(u - c0) * R + r];
                     }
                     acc[q] = s;
                 }
@@ -256,7 +262,7 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
         dim3 grid((unsigned)nz->n_tiles, R);
-        const int band_slots = (lam + 1 + 3) & ~3;
+        const int band_slots = lam <= BAND_LDS_MAX ? ((lam + 1 + 3) & ~3) : 0;
         if (nz->prec == MM_F32) {
             size_t sm = sizeof(float) * (band_slots + 4096);
             k_band<float, R><<<grid, BS, sm, ctx->stream>>>(

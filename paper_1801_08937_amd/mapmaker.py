@@ -87,6 +87,12 @@ def lib() -> C.CDLL:
             "mm_profile_enable": (C.c_int, [P, C.c_int]),
             "mm_profile_read": (C.c_int, [P, I32, P, P, P, C.POINTER(I32)]),
             "mm_hessenberg_eig": (C.c_int, [I32, P, P, P, P, P]),
+            "mm_pcg_create": (C.c_int, [P, P, P, P, I32, PP]),
+            "mm_pcg_start": (C.c_int, [P, P, I32, P, D, I32]),
+            "mm_pcg_iterate": (C.c_int, [P, P, I32]),
+            "mm_pcg_poll": (C.c_int, [P, P, P, P, P]),
+            "mm_pcg_finish": (C.c_int, [P, P, I32, P]),
+            "mm_pcg_destroy": (None, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -304,6 +310,12 @@ class Context:
                             history=h, status=st))
         return x, (out[0] if nrhs == 1 else out)
 
+    def pcg_session(self, p, nz, M, nrhs: int):
+        h = C.c_void_p()
+        self._check(lib().mm_pcg_create(self.h, p.h, nz.h, M.h if M is not None else None, nrhs,
+                                        C.byref(h)), "mm_pcg_create")
+        return PcgSession(self, h, p.n, nrhs)
+
     # ------------------------------------------------------------ profiling
     def profile(self, on: bool):
         self._check(lib().mm_profile_enable(self.h, 1 if on else 0), "mm_profile_enable")
@@ -420,3 +432,37 @@ class Precond(_Handle):
         self.ctx._check(lib().mm_defl_arnoldi_export(self.ctx.h, self.h, None, _ptr(W),
                                                      H.ctypes.data), "mm_defl_arnoldi_export")
         return W.t(), H.T.copy()
+
+
+class PcgSession(_Handle):
+    """Step-wise lockstep PCG over nrhs column slots (continuous batching)."""
+    _destroy = "mm_pcg_destroy"
+    STATES = {0: "free", 1: "running", 2: "converged", 3: "budget", 4: "breakdown"}
+
+    def __init__(self, ctx, h, n, nrhs):
+        super().__init__(ctx, h)
+        self.n, self.nrhs = n, nrhs
+
+    def start(self, slot: int, b, tol: float, max_iter: int):
+        import torch
+        _dev_check(b, torch.float64, self.n, "b")
+        self.ctx._check(lib().mm_pcg_start(self.ctx.h, self.h, slot, _ptr(b), tol, max_iter),
+                        "mm_pcg_start")
+
+    def iterate(self, n_iter: int):
+        self.ctx._check(lib().mm_pcg_iterate(self.ctx.h, self.h, n_iter), "mm_pcg_iterate")
+
+    def poll(self):
+        st = np.zeros(self.nrhs, dtype=np.int32)
+        it = np.zeros(self.nrhs, dtype=np.int32)
+        rr = np.zeros(self.nrhs)
+        self.ctx._check(lib().mm_pcg_poll(self.ctx.h, self.h, st.ctypes.data, it.ctypes.data,
+                                          rr.ctypes.data), "mm_pcg_poll")
+        return st, it, rr
+
+    def finish(self, slot: int, x=None):
+        import torch
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=self.ctx.torch_device)
+        self.ctx._check(lib().mm_pcg_finish(self.ctx.h, self.h, slot, _ptr(x)), "mm_pcg_finish")
+        return x

@@ -319,3 +319,90 @@ def test_config2_full_size_pointing_and_sampled_A(ctx):
     pix = [0, 1234, op.n_obs // 2, op.n_obs - 1]
     ref = O.apply_A_pixels(op, on, x, pix)
     assert maxrel(Ax[pix], ref) <= 1e-10
+
+
+def _fft_problem(lam, L, n_int, seed, n_filters=3):
+    rng = np.random.default_rng(seed)
+    lengths = (L + rng.integers(-L // 8, L // 8, n_int)).astype(np.int64)
+    istart = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    fid = rng.integers(0, n_filters, n_int).astype(np.int32)
+    band = np.stack([synth.band_from_psd(L, lam, fk) for fk in rng.uniform(0.05, 1, n_filters)])
+    return istart, fid, band
+
+
+@pytest.mark.parametrize("lam,L,n_int", [(300, 5000, 5), (1000, 20000, 3), (4096, 65536, 3),
+                                         (6000, 30000, 2)])
+def test_noise_fft_parity(ctx, lam, L, n_int):
+    """FFT form of N^-1 (overlap-save, partial last blocks, several filters)
+    against the oracle's direct band."""
+    import torch
+    istart, fid, band = _fft_problem(lam, L, n_int, lam)
+    nz = ctx.noise(istart, fid, band, lam, method=2)
+    assert nz.method == 2
+    on = O.noise_build(istart, fid, band, lam)
+    y = np.random.default_rng(1).standard_normal(int(istart[-1]))
+    z = host(ctx.noise_apply(nz, dev(y)))
+    ref = O.noise_apply_direct(on, y)
+    assert maxrel(z, ref) <= 1e-11, maxrel(z, ref)
+    # column independence with R = 4: each column equals the single apply bitwise
+    Y4 = np.random.default_rng(2).standard_normal((int(istart[-1]), 4))
+    Y4[:, 1] = y
+    Z4 = host(ctx.noise_apply(nz, dev(Y4.reshape(-1)), nrhs=4)).reshape(-1, 4)
+    np.testing.assert_array_equal(Z4[:, 1], z)
+    # FP32 form
+    nz32 = ctx.noise(istart, fid, band, lam, method=2, prec=1)
+    z32 = host(ctx.noise_apply(nz32, dev(y.astype(np.float32))))
+    assert rel(z32, ref) <= 1e-5
+
+
+def test_A_fft_parity_config2_shape(ctx):
+    p = synth.config2(n_side=64, grid=(4, 2), samp_per_det=1 << 16, L=1 << 14, half_bw=2048)
+    lp, ln, op, on = build_both(ctx, p, method=2)
+    assert ln.method == 2
+    x = np.random.default_rng(0).standard_normal(op.n)
+    assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x, "fft")) <= 1e-11
+    assert maxrel(host(ctx.rhs(lp, ln, dev(p.tod))), O.rhs(op, on, p.tod, "fft")) <= 1e-11
+
+
+def test_pcg_session_matches_solve_and_is_mix_independent(ctx):
+    """Step-wise sessions: a column's iterates do not depend on the other
+    slots (bitwise), and a slot restarted mid-flight converges like a fresh
+    solve."""
+    import torch
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    b0 = ctx.rhs(lp, ln, dev(p.tod))
+    p2 = synth.config4_realization(3)
+    b1 = ctx.rhs(lp, ln, dev(p2.tod))
+    # alone
+    S = ctx.pcg_session(lp, ln, M, 8)
+    S.start(5, b0, 1e-8, 2000)
+    for _ in range(400):
+        S.iterate(4)
+        st, it, rr = S.poll()
+        if st[5] != 1:
+            break
+    assert st[5] == 2
+    xa = S.finish(5)
+    ita = it[5]
+    # in a mix: another request already running in slot 0, ours joins later in slot 5
+    S2 = ctx.pcg_session(lp, ln, M, 8)
+    S2.start(0, b1, 1e-10, 2000)
+    S2.iterate(7)
+    S2.start(5, b0, 1e-8, 2000)
+    done5 = False
+    for _ in range(400):
+        S2.iterate(4)
+        st, it, rr = S2.poll()
+        if st[5] != 1 and not done5:
+            done5 = True
+            xb = S2.finish(5)
+            itb = it[5]
+        if done5 and st[0] != 1:
+            break
+    assert done5 and ita == itb
+    assert torch.equal(xa, xb)
+    # and the result solves the system
+    x, info = ctx.solve(lp, ln, M, b0, tol=1e-8)
+    assert rel(host(xa), host(x)) <= 1e-6
