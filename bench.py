@@ -96,7 +96,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="setup + timed steps only (for rocprofv3 runs)")
+    ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 5}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design (shard by "
               "detector intervals + one map all-reduce per A apply) is not built", file=sys.stderr)
@@ -138,13 +150,14 @@ def main():
         return r
 
     lp = timed("pointing_build_s", lambda: ctx.pointing(pix, psi, p.n_pix_total, p.min_hits))
+    lp.set_grid(p.n_side)
     ln = timed("noise_build_s", lambda: ctx.noise(p.interval_start, p.filter_id, p.band,
                                                   p.half_bw))
     Mbd = timed("mbd_build_s", lambda: ctx.mbd(lp, ln))
     b = timed("rhs_s", lambda: ctx.rhs(lp, ln, tod))
     del pix, psi
     M2 = timed("m2l_build_s", lambda: ctx.defl_build(lp, ln, Mbd, b, k=32, eps_arn=1e-8,
-                                                      m_max=256))
+                                                      m_max=args.m_max))
     arn = M2.arnoldi_info
     log(f"[bench] Arnoldi m={arn.m} k={arn.k} h_last={arn.h_last:.2e}")
 

@@ -105,6 +105,13 @@ const char *mm_version(void);
 mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
                             const int32_t *pix, const double *psi, int32_t min_hits,
                             mm_precision prec, mm_pointing **out);
+/* Optional locality hint: the global pixel ids are row-major on a grid of
+ * `width` columns (id = row * width + column).  P^T then visits the observed
+ * pixels in 32 x 32 tiles of that grid, so the pixels reduced together are
+ * hit by the same stretches of the scan and share cache lines.  Every pixel's
+ * sum keeps its order, so results are bitwise unchanged.  width = 0 restores
+ * ascending order.  Errors: MM_E_INVALID (negative width). */
+mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t width);
 /* n_obs (observed pixels) and n_valid (unflagged samples).  [host] outputs. */
 mm_status mm_pointing_counts(const mm_pointing *p, int32_t *n_obs, int64_t *n_valid);
 /* Hit counts per global pixel and the observed pixels' global ids.

@@ -302,6 +302,22 @@ extern "C" mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pi
     return MM_OK;
 }
 
+extern "C" mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t width) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(p, MM_E_INVALID, "set_grid: null pointing");
+    MM_CHECK(width >= 0, MM_E_INVALID, "set_grid: negative width");
+    if (width == 0) {
+        p->seg_order.release();
+        p->grid_width = 0;
+    } else {
+        pointing_set_grid_device(ctx, p, width, 32);
+        p->grid_width = width;
+    }
+    API_END
+    return MM_OK;
+}
+
 extern "C" mm_status mm_pointing_counts(const mm_pointing *p, int32_t *n_obs, int64_t *n_valid) {
     if (!p) return MM_E_INVALID;
     if (n_obs) *n_obs = p->n_obs;

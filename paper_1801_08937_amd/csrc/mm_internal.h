@@ -116,8 +116,12 @@ struct mm_pointing {
     int32_t n_obs = 0;
     int64_t n_valid = 0;
     mm_precision prec = MM_F64;
-    mm::DBuf hits, obs_pix, j, w, perm, ws, off, seg_order;
+    mm::DBuf hits, obs_pix, j, w, perm, ws, off;
     int32_t max_seg = 0;
+    // Order in which P^T visits the compact pixels (empty = ascending).  Each
+    // pixel's own sum is independent of it; it only shapes cache locality.
+    mm::DBuf seg_order;
+    int32_t grid_width = 0;
 };
 
 struct mm_noise {
@@ -162,6 +166,7 @@ namespace mm {
 // pointing.hip
 void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, const double *psi,
                            int32_t min_hits);
+void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_t tile);
 
 // tod_ops.hip
 void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y);

@@ -10,8 +10,9 @@
 //
 // One workgroup per block: the N real inputs are packed as NC complex values
 // z_m = y_{2m} + i y_{2m+1}, transformed by an NC-point complex FFT held in
-// LDS (Stockham, radices 16 x 8 x 8 x 8, data exchanged through LDS between
-// passes), multiplied by the spectrum in the packed domain
+// LDS (Stockham, radices 16 x 8 x 8 x 8; the first forward pass reads global
+// memory and the last inverse pass writes it, the others exchange through
+// padded LDS), multiplied by the spectrum in the packed domain
 //     Z'_k = A_k Z_k + B_k (W^k O_k + i W^-k E_k),
 //     E_k = (Z_k + conj Z_{NC-k}) / 2,  O_k = (Z_k - conj Z_{NC-k}) / 2i,
 //     A_k = (H_k + H_{k+NC}) / 2NC,     B_k = (H_k - H_{k+NC}) / 2NC,  W = e^{-2 pi i / N},
@@ -83,11 +84,49 @@ __device__ __forceinline__ void dft_small(T (&re)[R], T (&im)[R]) {
     }
 }
 
-// One Stockham pass of radix R at sub-transform size NS over the NC points in
-// LDS.  tw[m] = e^{-2 pi i m / NC}.
+// LDS index with one pad slot per 16 entries, so the stride-16 accesses of
+// the radix-16 pass fall in distinct banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+constexpr int FFT_LDS = FFT_NC + FFT_NC / 16;
+
+// Twiddles e^{DIR 2 pi i jm r SCALE / NC} for r = 1..R-1 from one table entry
+// (w1, r = 1) and products of at most three factors (w2 = w1^2, w4, w8).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void apply_twiddles(T (&re)[R], T (&im)[R], int jm, int scale,
+                                               const typename Vec2T<T>::type *__restrict__ tw) {
+    const auto t1 = tw[jm * scale];
+    T wr[R], wi[R];
+    wr[1] = t1.x;
+    wi[1] = DIR < 0 ? t1.y : -t1.y;
+#pragma unroll
+    for (int r = 2; r < R; ++r) {
+        // r = hi + lo with hi the largest power of two <= r (hi = r when r is a power of two)
+        int hi = 1;
+        while (hi * 2 <= r) hi *= 2;
+        const int lo = r - hi;
+        if (lo == 0) {
+            const int h = hi / 2;
+            wr[r] = wr[h] * wr[h] - wi[h] * wi[h];
+            wi[r] = 2 * wr[h] * wi[h];
+        } else {
+            wr[r] = wr[hi] * wr[lo] - wi[hi] * wi[lo];
+            wi[r] = wr[hi] * wi[lo] + wi[hi] * wr[lo];
+        }
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const T xr = re[r], xi = im[r];
+        re[r] = wr[r] * xr - wi[r] * xi;
+        im[r] = wr[r] * xi + wi[r] * xr;
+    }
+}
+
+// A Stockham pass of radix R at sub-transform size NS, LDS to LDS:
+// butterfly j reads x[j + r NC/R], twiddles by e^{DIR 2 pi i (j mod NS) r/(NS R)},
+// and writes x[(j/NS) NS R + j mod NS + r NS].
 template <typename T, int R, int NS, int DIR>
-__device__ __forceinline__ void stockham_pass(T *__restrict__ sre, T *__restrict__ sim,
-                                              const typename Vec2T<T>::type *__restrict__ tw) {
+__device__ __forceinline__ void pass_lds(T *__restrict__ sre, T *__restrict__ sim,
+                                         const typename Vec2T<T>::type *__restrict__ tw) {
     constexpr int NB = FFT_NC / R;
     constexpr int PER = NB / FFT_THREADS;
     T re[PER][R], im[PER][R];
@@ -97,8 +136,8 @@ __device__ __forceinline__ void stockham_pass(T *__restrict__ sre, T *__restrict
         const int j = tid + p * FFT_THREADS;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            re[p][r] = sre[j + r * NB];
-            im[p][r] = sim[j + r * NB];
+            re[p][r] = sre[pad(j + r * NB)];
+            im[p][r] = sim[pad(j + r * NB)];
         }
     }
     __syncthreads();
@@ -106,34 +145,16 @@ __device__ __forceinline__ void stockham_pass(T *__restrict__ sre, T *__restrict
     for (int p = 0; p < PER; ++p) {
         const int j = tid + p * FFT_THREADS;
         const int jm = j % NS;
-        if (NS > 1) {
-            constexpr int SCALE = FFT_NC / (NS * R);
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const auto w = tw[jm * r * SCALE];
-                const T wr = w.x, wi = DIR < 0 ? w.y : -w.y;
-                const T xr = re[p][r], xi = im[p][r];
-                re[p][r] = wr * xr - wi * xi;
-                im[p][r] = wr * xi + wi * xr;
-            }
-        }
+        if (NS > 1) apply_twiddles<T, R, DIR>(re[p], im[p], jm, FFT_NC / (NS * R), tw);
         dft_small<T, R, DIR>(re[p], im[p]);
         const int idx = (j / NS) * NS * R + jm;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            sre[idx + r * NS] = re[p][r];
-            sim[idx + r * NS] = im[p][r];
+            sre[pad(idx + r * NS)] = re[p][r];
+            sim[pad(idx + r * NS)] = im[p][r];
         }
     }
     __syncthreads();
-}
-
-template <typename T, int DIR>
-__device__ __forceinline__ void fft8192(T *sre, T *sim, const typename Vec2T<T>::type *tw) {
-    stockham_pass<T, 16, 1, DIR>(sre, sim, tw);
-    stockham_pass<T, 8, 16, DIR>(sre, sim, tw);
-    stockham_pass<T, 8, 128, DIR>(sre, sim, tw);
-    stockham_pass<T, 8, 1024, DIR>(sre, sim, tw);
 }
 
 template <typename T>
@@ -143,39 +164,54 @@ __global__ void __launch_bounds__(FFT_THREADS)
                 const typename Vec2T<T>::type *__restrict__ tw,
                 const typename Vec2T<T>::type *__restrict__ twN, int lam, int V, int R,
                 const T *__restrict__ y, T *__restrict__ z) {
-    __shared__ T sre[FFT_NC];
-    __shared__ T sim[FFT_NC];
+    __shared__ T sre[FFT_LDS];
+    __shared__ T sim[FFT_LDS];
     const int tid = threadIdx.x;
-    const int r = blockIdx.y;
+    const int rr = blockIdx.y;
     const int64_t t0 = blocks[2 * blockIdx.x];
     const int64_t iv = blocks[2 * blockIdx.x + 1];
     const int64_t a = istart[iv], e = istart[iv + 1];
     const int64_t base = t0 - lam;
-    for (int m = tid; m < FFT_NC; m += FFT_THREADS) {
-        const int64_t u0 = base + 2 * m, u1 = u0 + 1;
-        sre[m] = (u0 >= a && u0 < e) ? y[u0 * R + r] : (T)0;
-        sim[m] = (u1 >= a && u1 < e) ? y[u1 * R + r] : (T)0;
+
+    // forward pass 1 (radix 16, NS = 1) straight from global memory:
+    // butterfly j takes z_m, m = j + 512 r, z_m = y_{base+2m} + i y_{base+2m+1}
+    {
+        T re[16], im[16];
+        const int j = tid;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t u0 = base + 2 * (int64_t)(j + 512 * r), u1 = u0 + 1;
+            re[r] = (u0 >= a && u0 < e) ? y[u0 * R + rr] : (T)0;
+            im[r] = (u1 >= a && u1 < e) ? y[u1 * R + rr] : (T)0;
+        }
+        dft_small<T, 16, -1>(re, im);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            sre[pad(j * 16 + r)] = re[r];
+            sim[pad(j * 16 + r)] = im[r];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    fft8192<T, -1>(sre, sim, tw);
+    pass_lds<T, 8, 16, -1>(sre, sim, tw);
+    pass_lds<T, 8, 128, -1>(sre, sim, tw);
+    pass_lds<T, 8, 1024, -1>(sre, sim, tw);
+
     // spectrum in the packed domain, one (k, NC-k) pair per thread step
     const auto *abf = ab + (int64_t)fid[iv] * FFT_NC;
     for (int k = tid; k <= FFT_NC / 2; k += FFT_THREADS) {
         const int kp = (FFT_NC - k) & (FFT_NC - 1);
-        const T zr = sre[k], zi = sim[k], pr = sre[kp], pi = sim[kp];
-        // pair member k
+        const T zr = sre[pad(k)], zi = sim[pad(k)], pr = sre[pad(kp)], pi = sim[pad(kp)];
         {
             const T er = (zr + pr) * (T)0.5, ei = (zi - pi) * (T)0.5;   // E = (Z + conj Zp)/2
             const T orr = (zi + pi) * (T)0.5, oi = -(zr - pr) * (T)0.5; // O = (Z - conj Zp)/2i
             const auto w = twN[k];
             const T wr = w.x, wi = w.y;                                 // W^k
-            // W^k O + i W^-k E
-            const T a1r = wr * orr - wi * oi, a1i = wr * oi + wi * orr;
+            const T a1r = wr * orr - wi * oi, a1i = wr * oi + wi * orr; // W^k O
             const T b1r = wr * er + wi * ei, b1i = wr * ei - wi * er;   // W^-k E
-            const T sr = a1r - b1i, si = a1i + b1r;
+            const T sr = a1r - b1i, si = a1i + b1r;                     // W^k O + i W^-k E
             const auto c = abf[k];
-            sre[k] = c.x * zr + c.y * sr;
-            sim[k] = c.x * zi + c.y * si;
+            sre[pad(k)] = c.x * zr + c.y * sr;
+            sim[pad(k)] = c.x * zi + c.y * si;
         }
         if (kp != k) {
             const T er = (pr + zr) * (T)0.5, ei = (pi - zi) * (T)0.5;
@@ -186,18 +222,37 @@ __global__ void __launch_bounds__(FFT_THREADS)
             const T b1r = wr * er + wi * ei, b1i = wr * ei - wi * er;
             const T sr = a1r - b1i, si = a1i + b1r;
             const auto c = abf[kp];
-            sre[kp] = c.x * pr + c.y * sr;
-            sim[kp] = c.x * pi + c.y * si;
+            sre[pad(kp)] = c.x * pr + c.y * sr;
+            sim[pad(kp)] = c.x * pi + c.y * si;
         }
     }
     __syncthreads();
-    fft8192<T, 1>(sre, sim, tw);
+
+    // inverse
+    pass_lds<T, 16, 1, 1>(sre, sim, tw);
+    pass_lds<T, 8, 16, 1>(sre, sim, tw);
+    pass_lds<T, 8, 128, 1>(sre, sim, tw);
+    // last pass (radix 8, NS = 1024) straight to global memory: butterfly j
+    // produces z'_m, m = j + 1024 r, i.e. outputs 2m and 2m + 1 of the block
     int64_t nvalid = e - t0;
     if (nvalid > V) nvalid = V;
-    for (int q = tid; q < nvalid; q += FFT_THREADS) {
-        const int np = lam + q;
-        const T v = (np & 1) ? sim[np >> 1] : sre[np >> 1];
-        z[(t0 + q) * R + r] = v;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int j = tid + p * FFT_THREADS;
+        T re[8], im[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            re[r] = sre[pad(j + 1024 * r)];
+            im[r] = sim[pad(j + 1024 * r)];
+        }
+        apply_twiddles<T, 8, 1>(re, im, j, FFT_NC / (1024 * 8), tw);
+        dft_small<T, 8, 1>(re, im);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t q0 = 2 * (int64_t)(j + 1024 * r) - lam;  // output offset from t0
+            if (q0 >= 0 && q0 < nvalid) z[(t0 + q0) * R + rr] = re[r];
+            if (q0 + 1 >= 0 && q0 + 1 < nvalid) z[(t0 + q0 + 1) * R + rr] = im[r];
+        }
     }
 }
 
@@ -326,5 +381,6 @@ void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *
     }
     MM_HIP(hipGetLastError());
 }
+
 
 }  // namespace mm

@@ -94,6 +94,22 @@ __global__ void k_gather_w(const int32_t *__restrict__ perm, const T2 *__restric
         ws[i] = w[perm[i]];
 }
 
+// order[s] = compact pixel visited s-th when P^T walks the observed pixels in
+// square tiles of a row-major grid of the given width: key = (tile row, tile
+// column, row in tile, column in tile) of the global id.
+__global__ void k_tile_keys(const int32_t *__restrict__ obs_pix, int32_t n_obs, int32_t width,
+                            int32_t tile, uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int32_t c = blockIdx.x * BS + threadIdx.x;
+    if (c >= n_obs) return;
+    const int64_t g = obs_pix[c];
+    const int64_t y = g / width, x = g % width;
+    const int64_t tiles_x = (width + tile - 1) / tile;
+    const uint64_t k = ((uint64_t)((y / tile) * tiles_x + x / tile) << 24) |
+                       (uint64_t)((y % tile) * tile + (x % tile));
+    keys[c] = k;
+    vals[c] = c;
+}
+
 int grid_for(int64_t n, int max_blocks = 8192) {
     int64_t g = (n + BS - 1) / BS;
     if (g > max_blocks) g = max_blocks;
@@ -101,6 +117,28 @@ int grid_for(int64_t n, int max_blocks = 8192) {
 }
 
 }  // namespace
+
+void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_t tile) {
+    hipStream_t s = ctx->stream;
+    const int32_t n_obs = p->n_obs;
+    if (n_obs == 0) return;
+    DBuf keys, vals, ko, vo, tmp;
+    keys.alloc(sizeof(uint64_t) * n_obs);
+    vals.alloc(sizeof(int32_t) * n_obs);
+    ko.alloc(sizeof(uint64_t) * n_obs);
+    p->seg_order.alloc(sizeof(int32_t) * n_obs);
+    k_tile_keys<<<(n_obs + BS - 1) / BS, BS, 0, s>>>(p->obs_pix.as<int32_t>(), n_obs, width, tile,
+                                                     keys.as<uint64_t>(), vals.as<int32_t>());
+    size_t tb = 0;
+    MM_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
+                                     vals.as<int32_t>(), p->seg_order.as<int32_t>(),
+                                     (size_t)n_obs, 0u, 64u, s));
+    tmp.alloc(tb + 16);
+    MM_HIP(rocprim::radix_sort_pairs(tmp.ptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
+                                     vals.as<int32_t>(), p->seg_order.as<int32_t>(),
+                                     (size_t)n_obs, 0u, 64u, s));
+    MM_HIP(hipStreamSynchronize(s));
+}
 
 void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, const double *psi,
                            int32_t min_hits) {

@@ -30,6 +30,17 @@ constexpr int BS = 256;
 constexpr int BAND_LDS_MAX = 2047;
 
 template <typename T, int R>
+__device__ __forceinline__ T p_gather(int32_t j, typename Vec2<T>::type ww,
+                                      const double *__restrict__ x, int r) {
+    if (j < 0) return (T)0;
+    const double *xp = x + (int64_t)3 * j * R + r;
+    return (T)xp[0] + ww.x * (T)xp[R] + ww.y * (T)xp[2 * R];
+}
+
+// y = P x.  Each wave step covers G = 64/R consecutive samples x R columns;
+// four steps are issued together so each lane has four pixel-index loads and
+// twelve map gathers in flight.
+template <typename T, int R>
 __global__ void __launch_bounds__(BS) k_apply_P(const int32_t *__restrict__ jpix,
                                                 const typename Vec2<T>::type *__restrict__ w,
                                                 int64_t n, const double *__restrict__ x,
@@ -39,42 +50,69 @@ __global__ void __launch_bounds__(BS) k_apply_P(const int32_t *__restrict__ jpix
     const int sub = lane / R, r = lane % R;
     const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) >> 6;
     const int64_t nwave = ((int64_t)gridDim.x * BS) >> 6;
-    for (int64_t t = wave * G + sub; t < n; t += nwave * G) {
-        const int32_t j = jpix[t];
-        T v = (T)0;
-        if (j >= 0) {
-            const auto ww = w[t];
-            const double *xp = x + (int64_t)3 * j * R + r;
-            v = (T)xp[0] + ww.x * (T)xp[R] + ww.y * (T)xp[2 * R];
+    const int64_t step = nwave * G;
+    int64_t t = wave * G + sub;
+    for (; t + 3 * step < n; t += 4 * step) {
+        int32_t j[4];
+        typename Vec2<T>::type ww[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            j[q] = jpix[t + q * step];
+            ww[q] = w[t + q * step];
         }
-        y[t * R + r] = v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[(t + q * step) * R + r] = p_gather<T, R>(j[q], ww[q], x, r);
     }
+    for (; t < n; t += step) y[t * R + r] = p_gather<T, R>(jpix[t], w[t], x, r);
 }
 
-// One wave per compact pixel j: lanes stride through the segment
-// perm[off[j]..off[j+1]) in order, accumulating (1, cos, sin) * z; the G
-// lane groups are then combined by a fixed xor butterfly.
+// Pixels are visited in the order `order` (NULL = ascending), e.g. square
+// tiles of the map, and each XCD takes a contiguous range of that order: the
+// pixels one XCD reduces together are neighbours, hit by the same stretches of
+// the scan, so their gathers of z share cache lines in that XCD's L2.
 template <typename T, int R>
 __global__ void __launch_bounds__(BS) k_apply_PT(const int32_t *__restrict__ off,
                                                  const int32_t *__restrict__ perm,
                                                  const typename Vec2<T>::type *__restrict__ ws,
-                                                 int32_t n_obs, const T *__restrict__ z,
+                                                 int32_t n_obs, const int32_t *__restrict__ order,
+                                                 const T *__restrict__ z,
                                                  double *__restrict__ x) {
     constexpr int G = 64 / R;
     const int lane = threadIdx.x & 63;
     const int sub = lane / R, r = lane % R;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t j = blk * (BS / 64) + (threadIdx.x >> 6);
-    if (j >= n_obs) return;
+    const int64_t s = blk * (BS / 64) + (threadIdx.x >> 6);
+    if (s >= n_obs) return;
+    const int64_t j = order ? order[s] : s;
     const int32_t a = off[j], b = off[j + 1];
     T s0 = 0, s1 = 0, s2 = 0;
-    for (int32_t i = a + sub; i < b; i += G) {
-        const int32_t t = perm[i];
-        const T zz = z[(int64_t)t * R + r];
-        const auto ww = ws[i];
-        s0 += zz;
-        s1 += ww.x * zz;
-        s2 += ww.y * zz;
+    int32_t i = a + sub;
+    // four entries in flight per lane, accumulated in segment order
+    for (; i + 3 * G < b; i += 4 * G) {
+        int32_t tt[4];
+        T zz[4];
+        typename Vec2<T>::type ww[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tt[q] = perm[i + q * G];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            zz[q] = z[(int64_t)tt[q] * R + r];
+            ww[q] = ws[i + q * G];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            s0 += zz[q];
+            s1 += ww[q].x * zz[q];
+            s2 += ww[q].y * zz[q];
+        }
+    }
+    for (; i < b; i += G) {
+        const int32_t tq = perm[i];
+        const T zq = z[(int64_t)tq * R + r];
+        const auto wq = ws[i];
+        s0 += zq;
+        s1 += wq.x * zq;
+        s2 += wq.y * zq;
     }
 #pragma unroll
     for (int m = 32; m >= R; m >>= 1) {
@@ -236,16 +274,17 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
     if (p->n_obs == 0) return;
     int64_t nb = (p->n_obs + 3) / 4;
     if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
+    const int32_t *order = p->seg_order.ptr ? p->seg_order.as<int32_t>() : nullptr;
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
         if (p->prec == MM_F32)
             k_apply_PT<float, R><<<(unsigned)nb, BS, 0, ctx->stream>>>(
-                p->off.as<int32_t>(), p->perm.as<int32_t>(), p->ws.as<float2>(), p->n_obs,
+                p->off.as<int32_t>(), p->perm.as<int32_t>(), p->ws.as<float2>(), p->n_obs, order,
                 static_cast<const float *>(z), x);
         else
             k_apply_PT<double, R><<<(unsigned)nb, BS, 0, ctx->stream>>>(
                 p->off.as<int32_t>(), p->perm.as<int32_t>(), p->ws.as<double2>(), p->n_obs,
-                static_cast<const double *>(z), x);
+                order, static_cast<const double *>(z), x);
     });
     MM_HIP(hipGetLastError());
 }

@@ -64,6 +64,7 @@ def lib() -> C.CDLL:
             "mm_last_error": (C.c_char_p, [P]),
             "mm_pointing_build": (C.c_int, [P, I64, I32, P, P, I32, C.c_int, PP]),
             "mm_pointing_counts": (C.c_int, [P, C.POINTER(I32), C.POINTER(I64)]),
+            "mm_pointing_set_grid": (C.c_int, [P, P, I32]),
             "mm_pointing_hits": (C.c_int, [P, P, P, P]),
             "mm_pointing_export": (C.c_int, [P, P, P, P, P]),
             "mm_pointing_destroy": (None, [P]),
@@ -363,6 +364,11 @@ class Pointing(_Handle):
         lib().mm_pointing_counts(h, C.byref(n_obs), C.byref(n_valid))
         self.n_obs, self.n_valid = n_obs.value, n_valid.value
         self.n = 3 * self.n_obs
+
+    def set_grid(self, width: int):
+        """Locality hint: global ids are row-major with `width` columns."""
+        self.ctx._check(lib().mm_pointing_set_grid(self.ctx.h, self.h, width),
+                        "mm_pointing_set_grid")
 
     def hits(self):
         import torch

@@ -406,3 +406,33 @@ def test_pcg_session_matches_solve_and_is_mix_independent(ctx):
     # and the result solves the system
     x, info = ctx.solve(lp, ln, M, b0, tol=1e-8)
     assert rel(host(xa), host(x)) <= 1e-6
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_PT_tiled_order_bitwise_and_parity(ctx, case):
+    """The grid hint changes only the order pixels are visited in: P^T and A
+    are bitwise unchanged, and match the oracle."""
+    import torch
+    p = _problems()[case]
+    lp, ln, op, on = build_both(ctx, p, method=1)
+    rng = np.random.default_rng(10 + case)
+    y = dev(rng.standard_normal(op.n_samp))
+    a = ctx.apply_PT(lp, y)
+    Y8 = dev(rng.standard_normal(op.n_samp * 8))
+    a8 = ctx.apply_PT(lp, Y8, nrhs=8)
+    lp.set_grid(p.n_side)
+    b = ctx.apply_PT(lp, y)
+    b8 = ctx.apply_PT(lp, Y8, nrhs=8)
+    assert torch.equal(a, b) and torch.equal(a8, b8)
+    assert maxrel(host(b), O.apply_PT(op, host(y))) <= TOL_OP
+
+
+def test_A_fft_tiled_config2_shape(ctx):
+    """A = P^T N^-1 P with the FFT form of N^-1 and the tiled P^T order on a
+    2^21-sample cross-linked scan."""
+    p = synth.config2(n_side=64, grid=(4, 2), samp_per_det=1 << 18, L=1 << 15, half_bw=1024)
+    lp, ln, op, on = build_both(ctx, p, method=2)
+    lp.set_grid(p.n_side)
+    assert ln.method == 2
+    x = np.random.default_rng(4).standard_normal(op.n)
+    assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x, "fft")) <= 1e-11
