@@ -230,9 +230,13 @@ typedef struct {
 
 /* PCG flags */
 #define MM_SOLVE_CHECK_EVERY(c) ((c) & 0xff)  /* host convergence poll period (0 = 1) */
+#define MM_SOLVE_GRAPH (1u << 8) /* replay each poll period's iterations as one captured HIP graph */
+#define MM_SOLVE_BLOCK (1u << 9) /* block PCG over the nrhs columns (O'Leary), nrhs >= 2 */
 
 /* Preconditioned conjugate gradients (Eq. pcg), column-independent for
- * nrhs > 1:  r = b - A x; z = M r; p = z; rho = r.z; repeat q = A p;
+ * nrhs > 1 (with MM_SOLVE_BLOCK: block PCG, O'Leary 1980, whose search space
+ * is the block Krylov space of all columns; its Gram and block products run
+ * on FP64 MFMA and numerically dependent directions are dropped):  r = b - A x; z = M r; p = z; rho = r.z; repeat q = A p;
  * alpha = rho / p.q; x += alpha p; r -= alpha q; z = M r; rho' = r.z;
  * beta = rho'/rho; p = z + beta p -- until ||r|| / ||b|| <= tol (the
  * unpreconditioned residual, Sect. 6.1) or max_iter.  M may be NULL (no
@@ -265,6 +269,10 @@ mm_status mm_pcg_start(mm_ctx *ctx, mm_pcg *s, int32_t slot, const double *b, do
 /* Run n_iter lockstep iterations over the live slots (finished and free slots
  * are skipped). */
 mm_status mm_pcg_iterate(mm_ctx *ctx, mm_pcg *s, int32_t n_iter);
+/* Replay iterations in captured HIP graphs of `chunk` iterations (0 = off).
+ * The first iteration after creation runs eagerly; results are bitwise the
+ * same as eager iterations. */
+mm_status mm_pcg_use_graph(mm_ctx *ctx, mm_pcg *s, int32_t chunk);
 /* Per-slot state [host] arrays of nrhs (any may be NULL): state 0 = free,
  * 1 = running, 2 = converged, 3 = iteration budget spent, 4 = breakdown;
  * iterations taken; recursive relative residual. */

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 #include "mm_internal.h"
@@ -184,6 +185,21 @@ struct PcgWork {
         sd.rn2 = sb + 256; sd.bn2 = sb + 320; sd.tol2 = sb + 384;
         int *ib = reinterpret_cast<int *>(sb + 448);
         sd.done = ib; sd.brk = ib + 64; sd.iters = ib + 128;
+        sd.hist = nullptr;
+        sd.hist_len = 0;
+    }
+};
+
+// A captured chunk of PCG iterations, replayed with one hipGraphLaunch.  The
+// kernels of an iteration take only device-resident scalars, so the chunk is
+// the same graph every time; finished columns turn every kernel into a no-op.
+struct PcgGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    int chunk = 0;
+    ~PcgGraph() {
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (g) (void)hipGraphDestroy(g);
     }
 };
 
@@ -214,6 +230,33 @@ void pcg_iteration(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const 
     pcg_apply_M(ctx, M, w, w.r.as<double>(), w.z.as<double>());
     pcg_after_rz(ctx, R, w.sd, w.part.as<double>(), w.n_part, 0);
     pcg_update_p(ctx, w.n, R, w.sd, w.z.as<double>(), w.pv.as<double>());
+}
+
+void capture_chunk(mm_ctx *ctx, PcgGraph &G, int chunk, const std::function<void()> &body) {
+    if (!ctx->cap) MM_HIP(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    hipStream_t keep = ctx->stream;
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    ctx->stream = ctx->cap;
+    hipError_t e = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        try {
+            for (int i = 0; i < chunk; ++i) body();
+        } catch (...) {
+            hipGraph_t junk;
+            (void)hipStreamEndCapture(ctx->cap, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            ctx->stream = keep;
+            ctx->prof.on = prof;
+            throw;
+        }
+        e = hipStreamEndCapture(ctx->cap, &G.g);
+    }
+    ctx->stream = keep;
+    ctx->prof.on = prof;
+    MM_HIP(e);
+    MM_HIP(hipGraphInstantiate(&G.ex, G.g, nullptr, nullptr, 0));
+    G.chunk = chunk;
 }
 
 int choose_tile(int64_t n_samp, int n_cu) {
@@ -266,6 +309,7 @@ extern "C" void mm_ctx_destroy(mm_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
 
@@ -815,6 +859,10 @@ extern "C" void mm_precond_destroy(mm_precond *M) { delete M; }
 
 // ================================================================== solve
 
+static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                          const mm_precond *M, int R, const double *b, double *x, double tol,
+                          int max_iter, int check, double *history, mm_solve_info *info);
+
 extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                               const mm_precond *M, int32_t nrhs, const double *b, double *x,
                               double tol, int32_t max_iter, uint32_t flags, double *history,
@@ -827,6 +875,12 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     MM_CHECK(b && x && b != x, MM_E_INVALID, "solve: bad b/x");
     MM_CHECK(tol >= 0 && max_iter >= 0, MM_E_INVALID, "solve: bad tol/max_iter");
     MM_CHECK(!M || M->n_obs == p->n_obs, MM_E_INVALID, "solve: preconditioner of another pointing");
+    if (flags & MM_SOLVE_BLOCK) {
+        MM_CHECK(nrhs >= 2, MM_E_INVALID, "solve: block CG needs nrhs >= 2");
+        result = block_cg(ctx, p, nz, M, nrhs, b, x, tol, max_iter, std::max(1u, flags & 0xffu),
+                          history, info);
+        return result;
+    }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = ctx->stream;
     const int64_t n = 3 * (int64_t)p->n_obs;
@@ -835,6 +889,8 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     w.alloc(n, R);
     DBuf hist;
     hist.alloc(sizeof(double) * (size_t)(max_iter + 1) * R);
+    w.sd.hist = hist.as<double>();
+    w.sd.hist_len = max_iter + 1;
     pcg_init_scalars(ctx, R, w.sd, tol);
     dot_cols(ctx, n, R, b, b, w.sd.bn2);
     // r = b - A x0
@@ -848,8 +904,9 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     MM_HIP(hipMemcpyAsync(w.pv.ptr, w.z.ptr, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
     std::vector<double> h_rn2((size_t)(max_iter + 1) * R, -1.0);
     int *hpin = reinterpret_cast<int *>(pinned(ctx, sizeof(int) * 64));
-    MM_HIP(hipMemcpyAsync(hist.ptr, w.sd.rn2, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
     const int check = std::max(1u, flags & 0xffu);
+    const bool use_graph = (flags & MM_SOLVE_GRAPH) != 0;
+    PcgGraph G;
     int it = 0;
     auto poll = [&]() -> bool {
         MM_HIP(hipMemcpyAsync(hpin, w.sd.done, sizeof(int) * R, hipMemcpyDeviceToHost, s));
@@ -860,11 +917,17 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     };
     bool all_done = poll();
     while (!all_done && it < max_iter) {
+        if (use_graph && it >= 1 && it + check <= max_iter) {
+            // first iteration ran eagerly (workspace sized); later chunks replay a graph
+            if (!G.ex) capture_chunk(ctx, G, check, [&]() { pcg_iteration(ctx, p, nz, M, w, x); });
+            MM_HIP(hipGraphLaunch(G.ex, s));
+            it += check;
+            all_done = poll();
+            continue;
+        }
         pcg_iteration(ctx, p, nz, M, w, x);
         ++it;
-        MM_HIP(hipMemcpyAsync(hist.as<double>() + (size_t)it * R, w.sd.rn2, sizeof(double) * R,
-                              hipMemcpyDeviceToDevice, s));
-        if (it % check == 0 || it == max_iter) all_done = poll();
+        if (it % check == 0 || it == max_iter || (use_graph && it == 1)) all_done = poll();
     }
     // true residual
     apply_A_impl(ctx, p, nz, R, x, w.q.as<double>());
@@ -914,6 +977,113 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     return result;
 }
 
+// ============================================================= block CG
+
+// Block PCG (O'Leary 1980) with A-orthonormal search blocks:
+//   R = B - A X; Z = M R; P~ = Z; Q~ = A P~; U = chol_drop(P~^T Q~)^-T;
+//   P = P~ U; Q = Q~ U;  repeat: alpha = P^T R; X += P alpha; R -= Q alpha;
+//   Z = M R; beta = Q^T Z; P~ = Z - P beta; Q~ = A P~; U; P = P~ U; Q = Q~ U.
+// P^T A P = I on the kept directions, so alpha and beta need no solves; the
+// Gram and block products run on FP64 MFMA.  Convergence is checked every
+// `check` iterations on each column's ||r|| / ||b||.
+static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                          const mm_precond *M, int R, const double *b, double *x, double tol,
+                          int max_iter, int check, double *history, mm_solve_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = ctx->stream;
+    const int64_t n = 3 * (int64_t)p->n_obs;
+    const size_t vb = sizeof(double) * n * R;
+    DBuf Rr, Z, Pb, Q, Qt, sm, ib, rn, bn;
+    Rr.alloc(vb); Z.alloc(vb); Pb.alloc(vb); Q.alloc(vb); Qt.alloc(vb);
+    sm.alloc(sizeof(double) * 3 * 64 * 64);
+    ib.alloc(sizeof(int) * 64);
+    rn.alloc(sizeof(double) * 64);
+    bn.alloc(sizeof(double) * 64);
+    double *G = sm.as<double>(), *U = G + 4096, *AB = G + 8192;
+    const double tau = 1e-10;
+    auto precond = [&](const double *in, double *out) {
+        if (M) precond_apply_impl(ctx, M, R, in, out, nullptr, 0);
+        else MM_HIP(hipMemcpyAsync(out, in, vb, hipMemcpyDeviceToDevice, s));
+    };
+    // direction update from P~ (in Z): Q~ = A P~, U, P = P~ U, Q = Q~ U
+    auto orthonormalise = [&]() {
+        apply_A_impl(ctx, p, nz, R, Z.as<double>(), Qt.as<double>());
+        gram_mfma(ctx, n, R, R, Z.as<double>(), R, 1, Qt.as<double>(), R, 1, G);
+        chol_inv_drop(ctx, R, G, tau, U, ib.as<int>());
+        gemm_rows_small(ctx, n, R, Z.as<double>(), U, 1.0, 0.0, Pb.as<double>());
+        gemm_rows_small(ctx, n, R, Qt.as<double>(), U, 1.0, 0.0, Q.as<double>());
+    };
+    dot_cols(ctx, n, R, b, b, bn.as<double>());
+    apply_A_impl(ctx, p, nz, R, x, Q.as<double>());
+    axpby_cols(ctx, n, R, b, Q.as<double>(), Rr.as<double>());
+    dot_cols(ctx, n, R, Rr.as<double>(), Rr.as<double>(), rn.as<double>());
+    std::vector<double> h_bn(R), h_rn(R), hist_rn;
+    MM_HIP(hipMemcpyAsync(h_bn.data(), bn.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipMemcpyAsync(h_rn.data(), rn.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    auto all_conv = [&]() {
+        for (int c = 0; c < R; ++c)
+            if (!(h_rn[c] <= tol * tol * h_bn[c])) return false;
+        return true;
+    };
+    hist_rn.insert(hist_rn.end(), h_rn.begin(), h_rn.end());
+    int it = 0;
+    bool conv = all_conv();
+    if (!conv) {
+        precond(Rr.as<double>(), Z.as<double>());
+        orthonormalise();
+    }
+    while (!conv && it < max_iter) {
+        gram_mfma(ctx, n, R, R, Pb.as<double>(), R, 1, Rr.as<double>(), R, 1, AB);    // alpha
+        gemm_rows_small(ctx, n, R, Pb.as<double>(), AB, 1.0, 1.0, x);
+        gemm_rows_small(ctx, n, R, Q.as<double>(), AB, -1.0, 1.0, Rr.as<double>());
+        ++it;
+        const bool poll = (it % check == 0) || it == max_iter || history;
+        if (poll) {
+            dot_cols(ctx, n, R, Rr.as<double>(), Rr.as<double>(), rn.as<double>());
+            MM_HIP(hipMemcpyAsync(h_rn.data(), rn.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+            MM_HIP(hipStreamSynchronize(s));
+            if (history) hist_rn.insert(hist_rn.end(), h_rn.begin(), h_rn.end());
+            conv = all_conv();
+            if (conv || it == max_iter) break;
+        }
+        precond(Rr.as<double>(), Z.as<double>());
+        gram_mfma(ctx, n, R, R, Q.as<double>(), R, 1, Z.as<double>(), R, 1, AB);      // beta
+        gemm_rows_small(ctx, n, R, Pb.as<double>(), AB, -1.0, 1.0, Z.as<double>());   // P~
+        orthonormalise();
+    }
+    // true residuals
+    apply_A_impl(ctx, p, nz, R, x, Q.as<double>());
+    axpby_cols(ctx, n, R, b, Q.as<double>(), Rr.as<double>());
+    dot_cols(ctx, n, R, Rr.as<double>(), Rr.as<double>(), rn.as<double>());
+    std::vector<double> h_tr(R);
+    MM_HIP(hipMemcpyAsync(h_tr.data(), rn.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool all = true;
+    const int nh = (int)(hist_rn.size() / R);
+    for (int c = 0; c < R; ++c) {
+        const double bnc = h_bn[c] > 0 ? std::sqrt(h_bn[c]) : 1.0;
+        const bool cv = h_rn[c] <= tol * tol * h_bn[c];
+        all &= cv;
+        if (info) {
+            info[c].iters = it;
+            info[c].converged = cv;
+            info[c].breakdown = 0;
+            info[c].pad = 0;
+            info[c].rel_res_recursive = std::sqrt(std::max(h_rn[c], 0.0)) / bnc;
+            info[c].rel_res_true = std::sqrt(std::max(h_tr[c], 0.0)) / bnc;
+            info[c].solve_seconds = secs;
+        }
+        if (history)
+            for (int k2 = 0; k2 <= max_iter; ++k2)
+                history[(size_t)c * (max_iter + 1) + k2] =
+                    k2 < nh ? std::sqrt(std::max(hist_rn[(size_t)k2 * R + c], 0.0)) / bnc : -1.0;
+    }
+    return all ? MM_OK : MM_NOT_CONVERGED;
+}
+
 // ========================================================== PCG sessions
 
 struct mm_pcg {
@@ -922,6 +1092,9 @@ struct mm_pcg {
     const mm_precond *M = nullptr;
     PcgWork w;
     DBuf x, tb;
+    int graph_chunk = 0;
+    bool warm = false;
+    PcgGraph G;
     std::vector<int> state, host_iters, max_iter;
     std::vector<double> tol;
 };
@@ -1011,7 +1184,21 @@ extern "C" mm_status mm_pcg_iterate(mm_ctx *ctx, mm_pcg *S, int32_t n_iter) {
                 chunk = std::min(chunk, rem);
             }
         if (!any) break;
-        for (int i = 0; i < chunk; ++i) pcg_iteration(ctx, S->p, S->nz, S->M, S->w, S->x.as<double>());
+        int done_it = 0;
+        if (S->graph_chunk > 0 && S->warm) {
+            while (done_it + S->graph_chunk <= chunk) {
+                if (!S->G.ex)
+                    capture_chunk(ctx, S->G, S->graph_chunk, [&]() {
+                        pcg_iteration(ctx, S->p, S->nz, S->M, S->w, S->x.as<double>());
+                    });
+                MM_HIP(hipGraphLaunch(S->G.ex, ctx->stream));
+                done_it += S->graph_chunk;
+            }
+        }
+        for (; done_it < chunk; ++done_it) {
+            pcg_iteration(ctx, S->p, S->nz, S->M, S->w, S->x.as<double>());
+            S->warm = true;
+        }
         for (int c = 0; c < S->w.R; ++c)
             if (S->state[c] == 1) {
                 S->host_iters[c] += chunk;
@@ -1021,6 +1208,19 @@ extern "C" mm_status mm_pcg_iterate(mm_ctx *ctx, mm_pcg *S, int32_t n_iter) {
                 }
             }
         left -= chunk;
+    }
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pcg_use_graph(mm_ctx *ctx, mm_pcg *S, int32_t chunk) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(S && chunk >= 0 && chunk <= 1024, MM_E_INVALID, "pcg_use_graph: bad arguments");
+    if (chunk != S->graph_chunk) {
+        S->G.~PcgGraph();
+        new (&S->G) PcgGraph();
+        S->graph_chunk = chunk;
     }
     API_END
     return MM_OK;

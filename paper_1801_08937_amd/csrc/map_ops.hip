@@ -17,6 +17,7 @@ template <> struct Vec2w<double> { using type = double2; };
 namespace {
 
 constexpr int BS = 256;
+using d4m = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 
 // ------------------------------------------------------------------ M_BD
 
@@ -272,6 +273,7 @@ __global__ void k_pcg_rn(const double *__restrict__ partial, int n_part, int R, 
         s.iters[r] += 1;
     }
     s.rn2[r] = rn;
+    if (s.hist && s.iters[r] < s.hist_len) s.hist[(int64_t)s.iters[r] * R + r] = rn;
     if (rn <= s.tol2[r] * s.bn2[r]) s.done[r] = 1;
 }
 
@@ -363,8 +365,6 @@ __global__ void k_scale(int64_t n, const double *__restrict__ src, const double 
 // column-major, kout <= 64) on FP64 MFMA: each wave owns 16 output rows and
 // all kout columns (up to four 16 x 16 accumulators), stepping through kin four
 // columns of V at a time.
-using d4m = __attribute__((__vector_size__(4 * sizeof(double)))) double;
-
 __global__ void __launch_bounds__(BS) k_gemm_tall_small(int64_t n, int kin, int kout,
                                                         const double *__restrict__ V,
                                                         const double *__restrict__ Y,
@@ -605,6 +605,117 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
     if (partial) block_col_reduce<R>(acc, partial);
 }
 
+// ------------------------------------------------------------- block CG
+//
+// Out = beta Out + alpha In S for column-batched In, Out ([n][R], R <= 64)
+// and a small S ([R][R] row-major) on FP64 MFMA: a wave owns 16 rows and all
+// R columns.
+__global__ void __launch_bounds__(BS) k_gemm_rows_small(int64_t n, int R,
+                                                        const double *__restrict__ In,
+                                                        const double *__restrict__ S,
+                                                        double alpha, double beta,
+                                                        double *__restrict__ Out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+    if (row0 >= n) return;
+    const int i16 = lane % 16, k4 = lane / 16;
+    const int64_t arow = row0 + i16;
+    const int TB = (R + 15) / 16;
+    d4m acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = d4m{0, 0, 0, 0};
+    for (int m = 0; m < R; m += 4) {
+        const int mm = m + k4;
+        const double av = (arow < n && mm < R) ? In[arow * R + mm] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < TB) {
+                const int col = q * 16 + i16;
+                const double bv = (mm < R && col < R) ? S[mm * R + col] : 0.0;
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < TB) {
+            const int col = q * 16 + i16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + k4 + 4 * v;
+                if (row < n && col < R) {
+                    const int64_t e = row * R + col;
+                    Out[e] = (beta == 0.0 ? 0.0 : beta * Out[e]) + alpha * acc[q][v];
+                }
+            }
+        }
+    }
+}
+
+// G (R x R) -> U with U^T G U = I on the kept directions.  G is symmetrised
+// and scaled to unit diagonal (Gs = D^-1 G D^-1, D = diag(G)^1/2) so that the
+// drop test measures linear dependence, not magnitude; Gs = L L^T by Cholesky,
+// dropping a direction whose pivot^2 is <= tau (numerically dependent on the
+// earlier ones) or whose diagonal is not positive; U = D^-1 L^-T, with zero
+// rows and columns for dropped directions.  Row-major.  rank[0] = kept count.
+__global__ void k_chol_inv_drop(int R, const double *__restrict__ G, double tau,
+                                double *__restrict__ U, int *__restrict__ rank) {
+    __shared__ double A[64][65];
+    __shared__ double Li[64][65];
+    __shared__ double dsc[64];
+    __shared__ int keep[64];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < R; i += blockDim.x) {
+        const double g = G[i * R + i];
+        dsc[i] = g > 1e-300 ? sqrt(g) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < R * R; e += blockDim.x) {
+        const int i = e / R, j = e % R;
+        const double s = 0.5 * (G[i * R + j] + G[j * R + i]);
+        A[i][j] = (dsc[i] > 0 && dsc[j] > 0) ? s / (dsc[i] * dsc[j]) : (i == j ? 0.0 : 0.0);
+    }
+    __syncthreads();
+    for (int c = 0; c < R; ++c) {
+        if (tid == 0) {
+            const double d = A[c][c];
+            keep[c] = (dsc[c] > 0 && d > tau) ? 1 : 0;
+            A[c][c] = keep[c] ? sqrt(d) : 0.0;
+        }
+        __syncthreads();
+        const double lcc = A[c][c];
+        for (int i = c + 1 + tid; i < R; i += blockDim.x) A[i][c] = keep[c] ? A[i][c] / lcc : 0.0;
+        __syncthreads();
+        for (int e = tid; e < (R - c - 1) * (R - c - 1); e += blockDim.x) {
+            const int i = c + 1 + e / (R - c - 1), j = c + 1 + e % (R - c - 1);
+            if (j <= i) A[i][j] -= A[i][c] * A[j][c];
+        }
+        __syncthreads();
+    }
+    // Li = L^-1 on the kept directions (forward substitution per column)
+    for (int c = tid; c < R; c += blockDim.x) {
+        for (int i = 0; i < R; ++i) Li[i][c] = 0.0;
+        if (!keep[c]) continue;
+        Li[c][c] = 1.0 / A[c][c];
+        for (int i = c + 1; i < R; ++i) {
+            if (!keep[i]) continue;
+            double s = 0;
+            for (int k = c; k < i; ++k) s += A[i][k] * Li[k][c];
+            Li[i][c] = -s / A[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < R * R; e += blockDim.x) {
+        const int i = e / R, j = e % R;
+        U[e] = dsc[i] > 0 ? Li[j][i] / dsc[i] : 0.0;  // D^-1 (L^-1)^T
+    }
+    if (tid == 0) {
+        int r = 0;
+        for (int c = 0; c < R; ++c) r += keep[c];
+        rank[0] = r;
+    }
+}
+
 // ----------------------------------------------------- session slot helpers
 
 // dst[i R + slot] = src ? src[i] : 0
@@ -794,6 +905,19 @@ void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const d
         constexpr int R = decltype(RR)::value;
         k_copy_masked<R><<<grid_for(n * R), BS, 0, ctx->stream>>>(n, done, src, dst);
     });
+    MM_HIP(hipGetLastError());
+}
+
+void gemm_rows_small(mm_ctx *ctx, int64_t n, int R, const double *In, const double *S,
+                     double alpha, double beta, double *Out) {
+    Scope sc(ctx->prof, ctx->stream, "gemm_mfma");
+    k_gemm_rows_small<<<(unsigned)((n + 63) / 64), BS, 0, ctx->stream>>>(n, R, In, S, alpha, beta,
+                                                                      Out);
+    MM_HIP(hipGetLastError());
+}
+
+void chol_inv_drop(mm_ctx *ctx, int R, const double *G, double tau, double *U, int *rank) {
+    k_chol_inv_drop<<<1, 64, 0, ctx->stream>>>(R, G, tau, U, rank);
     MM_HIP(hipGetLastError());
 }
 

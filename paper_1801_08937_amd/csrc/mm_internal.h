@@ -105,6 +105,7 @@ struct mm_ctx {
     mm::DBuf red;                  // reduction partials
     mm::DBuf scal;                 // small device scalars
     mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
+    hipStream_t cap = nullptr;     // private stream for graph capture
     double *pinned = nullptr;      // host pinned scratch (scalar readback)
     size_t pinned_bytes = 0;
     int n_cu = 256;
@@ -206,6 +207,8 @@ void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, d
 struct PcgDev {
     double *rho, *pq, *alpha, *beta, *rn2, *bn2, *tol2;
     int *done, *brk, *iters;
+    double *hist;   // rn2 per iteration, [hist_len][R], or null
+    int hist_len;
 };
 void pcg_init_scalars(mm_ctx *ctx, int nrhs, PcgDev s, double tol);
 void axpby_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *b, const double *Ax, double *r);
@@ -219,6 +222,9 @@ void pcg_update_p(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *z, d
 void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b,
                       double *partial, int n_part);
 void col_set(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst);
+void gemm_rows_small(mm_ctx *ctx, int64_t n, int R, const double *In, const double *S,
+                     double alpha, double beta, double *Out);
+void chol_inv_drop(mm_ctx *ctx, int R, const double *G, double tau, double *U, int *rank);
 void col_get(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst);
 void slot_ctl(mm_ctx *ctx, PcgDev s, int slot, int mode, double tol);
 void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const double *src,

@@ -91,6 +91,7 @@ def lib() -> C.CDLL:
             "mm_pcg_create": (C.c_int, [P, P, P, P, I32, PP]),
             "mm_pcg_start": (C.c_int, [P, P, I32, P, D, I32]),
             "mm_pcg_iterate": (C.c_int, [P, P, I32]),
+            "mm_pcg_use_graph": (C.c_int, [P, P, I32]),
             "mm_pcg_poll": (C.c_int, [P, P, P, P, P]),
             "mm_pcg_finish": (C.c_int, [P, P, I32, P]),
             "mm_pcg_destroy": (None, [P]),
@@ -290,7 +291,8 @@ class Context:
 
     # ---------------------------------------------------------------- solve
     def solve(self, p, nz, M, b, x=None, tol: float = 1e-8, max_iter: int = 2000,
-              nrhs: int = 1, check_every: int = 1, history: bool = True):
+              nrhs: int = 1, check_every: int = 1, history: bool = True, graph: bool = False,
+              block: bool = False):
         import torch
         _dev_check(b, torch.float64, p.n * nrhs, "b")
         if x is None:
@@ -298,7 +300,7 @@ class Context:
         hist = np.zeros((nrhs, max_iter + 1)) if history else None
         infos = (SolveInfo * nrhs)()
         st = lib().mm_solve(self.h, p.h, nz.h, M.h if M is not None else None, nrhs, _ptr(b),
-                            _ptr(x), tol, max_iter, check_every & 0xFF,
+                            _ptr(x), tol, max_iter, (check_every & 0xFF) | (256 if graph else 0) | (512 if block else 0),
                             hist.ctypes.data if hist is not None else None, infos)
         self._check(st, "mm_solve")
         out = []
@@ -454,6 +456,9 @@ class PcgSession(_Handle):
         _dev_check(b, torch.float64, self.n, "b")
         self.ctx._check(lib().mm_pcg_start(self.ctx.h, self.h, slot, _ptr(b), tol, max_iter),
                         "mm_pcg_start")
+
+    def use_graph(self, chunk: int):
+        self.ctx._check(lib().mm_pcg_use_graph(self.ctx.h, self.h, chunk), "mm_pcg_use_graph")
 
     def iterate(self, n_iter: int):
         self.ctx._check(lib().mm_pcg_iterate(self.ctx.h, self.h, n_iter), "mm_pcg_iterate")

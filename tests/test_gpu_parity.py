@@ -436,3 +436,90 @@ def test_A_fft_tiled_config2_shape(ctx):
     assert ln.method == 2
     x = np.random.default_rng(4).standard_normal(op.n)
     assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x, "fft")) <= 1e-11
+
+
+def test_graph_replayed_solve_bitwise(ctx):
+    """PCG chunks replayed from a captured HIP graph give bitwise the eager
+    result (M_BD and M_2l, single and 8 columns); eager work and host polls
+    run between replays."""
+    import torch
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    M = ctx.mbd(lp, ln)
+    b = ctx.rhs(lp, ln, dev(p.tod))
+    M2 = ctx.defl_build(lp, ln, M, b, k=16, eps_arn=1e-8, m_max=64)
+    for Mx in (M, M2):
+        xe, ie = ctx.solve(lp, ln, Mx, b, tol=1e-8, check_every=8)
+        xg, ig = ctx.solve(lp, ln, Mx, b, tol=1e-8, check_every=8, graph=True)
+        assert ie["iters"] == ig["iters"] and torch.equal(xe, xg)
+        np.testing.assert_array_equal(ie["history"], ig["history"])
+    B8 = torch.cat([b.view(-1, 1)] * 8, dim=1).contiguous().view(-1) * dev(
+        np.tile(np.arange(1, 9, dtype=np.float64), op.n))
+    xe, _ = ctx.solve(lp, ln, M, B8, tol=1e-8, nrhs=8, check_every=4, history=False)
+    xg, _ = ctx.solve(lp, ln, M, B8, tol=1e-8, nrhs=8, check_every=4, history=False, graph=True)
+    assert torch.equal(xe, xg)
+    # sessions with graph chunks
+    S1 = ctx.pcg_session(lp, ln, M, 4)
+    S2 = ctx.pcg_session(lp, ln, M, 4)
+    S2.use_graph(5)
+    for S in (S1, S2):
+        S.start(2, b, 1e-8, 2000)
+        for _ in range(100):
+            S.iterate(10)
+            st, it, rr = S.poll()
+            if st[2] != 1:
+                break
+    assert torch.equal(S1.finish(2), S2.finish(2))
+
+
+def _c4_batch(n_real=64):
+    reals = [synth.config4_realization(r) for r in range(n_real)]
+    tods = np.stack([q.tod for q in reals])
+    return reals[0], tods
+
+
+def test_batched_block_cg_config4(ctx):
+    """Batching form: 64 Monte Carlo right-hand sides on config 1's pointing;
+    block PCG (MFMA Gram/block products) and column-independent PCG both reach
+    1e-8 on every column and agree with the oracle's tight solutions."""
+    import torch
+    p0, tods = _c4_batch()
+    R = tods.shape[0]
+    lp, ln, op, on = build_both(ctx, p0)
+    M = ctx.mbd(lp, ln)
+    B = ctx.rhs(lp, ln, dev(tods.reshape(-1)), nrhs=R)
+    xi, ii = ctx.solve(lp, ln, M, B, tol=1e-8, nrhs=R, check_every=4, history=False)
+    xb, ib = ctx.solve(lp, ln, M, B, tol=1e-8, nrhs=R, check_every=1, history=False, block=True)
+    it_ind = max(i["iters"] for i in ii)
+    it_blk = max(i["iters"] for i in ib)
+    print(f"batch 64: independent PCG {it_ind} iterations, block PCG {it_blk}")
+    assert all(i["converged"] and i["rel_res_true"] <= 1.5e-8 for i in ii)
+    assert all(i["converged"] and i["rel_res_true"] <= 1.5e-8 for i in ib)
+    assert it_blk <= it_ind
+    OM = O.mbd_build(op, on)
+    Xb = host(xb).reshape(op.n, R)
+    for c in (0, R - 1):
+        bo = O.rhs(op, on, tods[c])
+        xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-12, 5000)
+        assert rel(Xb[:, c], xo) <= 1e-6
+    # M_2l shared by all realisations (Z from realisation 0)
+    b0 = ctx.rhs(lp, ln, dev(tods[0]))
+    M2 = ctx.defl_build(lp, ln, M, b0, k=32, eps_arn=1e-8, m_max=256)
+    x2, i2 = ctx.solve(lp, ln, M2, B, tol=1e-8, nrhs=R, check_every=4, history=False)
+    assert all(i["converged"] for i in i2)
+    assert max(i["iters"] for i in i2) <= it_ind
+
+
+def test_batched_fp32_variant(ctx):
+    p0, tods = _c4_batch(8)
+    lp, ln, op, on = build_both(ctx, p0, prec=1)
+    M = ctx.mbd(lp, ln)
+    B = ctx.rhs(lp, ln, dev(tods.astype(np.float32).reshape(-1)), nrhs=8)
+    xb, ib = ctx.solve(lp, ln, M, B, tol=1e-6, nrhs=8, history=False, block=True)
+    assert all(i["converged"] for i in ib)
+    OM = O.mbd_build(op, on)
+    bo = O.rhs(op, on, tods[3])
+    xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-12, 5000)
+    err = rel(host(xb).reshape(op.n, 8)[:, 3], xo)
+    print(f"fp32 batched block CG: map error vs FP64 oracle {err:.2e}")
+    assert err <= 1e-3
