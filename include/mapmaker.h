@@ -281,6 +281,70 @@ mm_status mm_pcg_poll(mm_ctx *ctx, mm_pcg *s, int32_t *state, int32_t *iters, do
 mm_status mm_pcg_finish(mm_ctx *ctx, mm_pcg *s, int32_t slot, double *x);
 void mm_pcg_destroy(mm_pcg *s);
 
+/* ----------------------------------------------------------------- serving */
+
+/* A serving engine for map-making solves of several recurring scan
+ * strategies on one GPU, continuously batched.  Each strategy gets its own
+ * context (HIP stream), pointing, noise and M_BD at registration, and a
+ * two-level M_2l built from its first request's right-hand side and reused for
+ * every later request of that strategy (Sect. 6.3.2: M_2l pays off when the
+ * same system is solved many times).  mm_server_step admits queued requests
+ * into free column slots of the strategy's lockstep PCG session -- also while
+ * other slots are mid-solve -- runs `iters_per_step` iterations on every
+ * strategy with running slots (all streams enqueued before any is waited on,
+ * so strategies overlap on the device), and retires finished slots into the
+ * caller's output buffers.  A request's result does not depend on which other
+ * requests share its session.  Not thread safe. */
+typedef struct mm_server mm_server;
+
+typedef struct {
+    int32_t state;          /* 0 queued, 1 running, 2 converged, 3 budget spent, 4 failed */
+    int32_t iters;
+    int32_t slot;
+    int32_t m2l_built;      /* 1 if this request paid for the M_2l build (cache miss) */
+    double rel_res;         /* recursive ||r|| / ||b|| at exit */
+    double queue_seconds;   /* submit -> admitted */
+    double latency_seconds; /* submit -> done (or now) */
+} mm_request_info;
+
+/* hbm_budget_bytes: cap on the library memory of all registered strategies;
+ * slots: columns per strategy session (1..64, power of two); defl_k: M_2l
+ * deflation vectors (0 = M_BD only); iters_per_step: PCG iterations per step. */
+mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots, int32_t defl_k,
+                           int32_t iters_per_step, mm_server **out);
+/* Register a scan strategy; arguments as mm_pointing_build / mm_noise_build
+ * (pix, psi [device] are read during the call only; grid_width as
+ * mm_pointing_set_grid, 0 = none).  Errors: MM_E_BUSY if its estimated
+ * footprint exceeds the remaining budget; the build errors otherwise. */
+mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t n_samp, int32_t n_pix_total,
+                                 const int32_t *pix, const double *psi, int32_t min_hits,
+                                 int32_t grid_width, int32_t n_intervals,
+                                 const int64_t *interval_start, const int32_t *filter_id,
+                                 int32_t n_filters, int32_t half_bw, const double *band,
+                                 mm_precision prec);
+/* Queue a solve.  tod [device] (the strategy's TOD precision, n_samp values)
+ * must stay valid until the request is admitted; x_out [device] f64[n]
+ * receives the map when it is done.  request_id [host] out. */
+mm_status mm_server_submit(mm_server *srv, int32_t strategy, const void *tod, double tol,
+                           int32_t max_iter, double *x_out, int64_t *request_id);
+/* One scheduling step; n_running, n_queued [host] or NULL. */
+mm_status mm_server_step(mm_server *srv, int32_t *n_running, int32_t *n_queued);
+mm_status mm_server_poll(mm_server *srv, int64_t request_id, mm_request_info *info);
+const char *mm_server_last_error(const mm_server *srv);
+void mm_server_destroy(mm_server *srv);
+
+/* -------------------------------------------------------------- autotuning */
+
+/* Time candidate launch shapes for nrhs columns with HIP events and keep the
+ * fastest: the P kernel's grid size and, for the direct band, its tile
+ * length.  Each candidate computes bitwise the same values (every output sums
+ * its terms in a fixed order), so tuning changes speed only.  Choices are
+ * stored in the handles and used by later calls with that nrhs.
+ *   report [host] f64[3 * 16] or NULL: (stage 0 = P / 1 = band, candidate, ms)
+ *   n_report [host] or NULL: entries written */
+mm_status mm_autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int32_t nrhs, double *report,
+                      int32_t *n_report);
+
 /* ---------------------------------------------------------- profiling aid */
 
 /* When on, each kernel of mm_apply_A / mm_solve is bracketed by HIP events on

@@ -477,19 +477,7 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
                                   hipMemcpyHostToDevice, s));
         }
         // direct-band tile table: (first sample, interval) per tile
-        const int tl = choose_tile(nz->n_samp, ctx->n_cu);
-        std::vector<int64_t> tiles;
-        for (int i = 0; i < n_intervals; ++i)
-            for (int64_t t = interval_start[i]; t < interval_start[i + 1]; t += tl) {
-                tiles.push_back(t);
-                tiles.push_back(i);
-            }
-        nz->tile_len = tl;
-        nz->n_tiles = (int64_t)tiles.size() / 2;
-        nz->tiles.alloc(sizeof(int64_t) * tiles.size());
-        MM_HIP(hipMemcpyAsync(nz->tiles.ptr, tiles.data(), sizeof(int64_t) * tiles.size(),
-                              hipMemcpyHostToDevice, s));
-        MM_HIP(hipStreamSynchronize(s));
+        set_band_tiles(ctx, nz, choose_tile(nz->n_samp, ctx->n_cu));
         if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
     } catch (...) {
         delete nz;
@@ -1272,6 +1260,21 @@ extern "C" mm_status mm_pcg_finish(mm_ctx *ctx, mm_pcg *S, int32_t slot, double 
 }
 
 extern "C" void mm_pcg_destroy(mm_pcg *S) { delete S; }
+
+// ============================================================== autotune
+
+extern "C" mm_status mm_autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int32_t nrhs,
+                                 double *report, int32_t *n_report) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    check_nrhs(nrhs);
+    int nr = 0;
+    autotune(ctx, p, nz, nrhs, report, &nr);
+    if (n_report) *n_report = nr;
+    API_END
+    return MM_OK;
+}
 
 // ============================================================== profiling
 

@@ -123,6 +123,7 @@ struct mm_pointing {
     // pixel's own sum is independent of it; it only shapes cache locality.
     mm::DBuf seg_order;
     int32_t grid_width = 0;
+    int32_t p_blocks[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned P grid per log2(nrhs); 0 = default
 };
 
 struct mm_noise {
@@ -138,6 +139,7 @@ struct mm_noise {
     mm::DBuf tiles;  // int64 pairs (tile start sample, interval index)
     int64_t n_tiles = 0;
     int32_t tile_len = 0;
+    int32_t tuned_tile_len[7] = {0, 0, 0, 0, 0, 0, 0};  // per log2(nrhs); 0 = untuned
     // FFT: per-filter packed spectrum and block table
     int32_t fft_n = 0;       // real block length
     int32_t fft_valid = 0;   // valid outputs per block
@@ -237,6 +239,10 @@ template <typename T> struct Vec2T;
 template <> struct Vec2T<float> { using type = float2; };
 template <> struct Vec2T<double> { using type = double2; };
 
+void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl);
+void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *report, int *n_report);
+
+inline int log2i(int r) { int l = 0; while ((1 << l) < r) ++l; return l; }
 inline int pow2_ok(int r) { return r >= 1 && r <= 64 && (r & (r - 1)) == 0; }
 
 }  // namespace mm

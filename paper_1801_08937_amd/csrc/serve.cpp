@@ -1,0 +1,298 @@
+// Serving engine: map-making solves of several recurring scan strategies,
+// continuously batched on one GPU.
+//
+// Each strategy owns a context (its own HIP stream), its pointing, noise and
+// M_BD built at registration, and a PCG session of `slots` lockstep columns.
+// Its two-level preconditioner M_2l is built from the first request's
+// right-hand side and reused for every later request of that strategy -- the
+// paper's point that M_2l pays off when the same system is solved many times
+// (Sect. 6.3.2).  A step admits queued requests into free slots (computing
+// their b on the strategy's stream), runs a chunk of iterations on every
+// strategy with running slots -- enqueued on all streams before any is
+// waited on, so strategies overlap on the device -- and retires finished
+// slots, writing each solution to the caller's buffer.  Memory is admitted
+// against a byte budget when a strategy is registered.
+#include <chrono>
+#include <deque>
+#include <map>
+#include <memory>
+
+#include "mm_internal.h"
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    int64_t id = 0;
+    int32_t strategy = 0;
+    const void *tod = nullptr;
+    double *x_out = nullptr;
+    double tol = 1e-8;
+    int32_t max_iter = 1000;
+    int32_t state = 0;  // 0 queued, 1 running, 2 converged, 3 budget spent, 4 failed
+    int32_t slot = -1;
+    int32_t iters = 0;
+    double rel_res = 0;
+    double t_submit = 0, t_start = 0, t_done = 0;
+    int32_t m2l_built = 0;  // 1 if this request triggered the M_2l build
+};
+
+struct Strategy {
+    int32_t id = 0;
+    mm_ctx *ctx = nullptr;
+    mm_pointing *p = nullptr;
+    mm_noise *nz = nullptr;
+    mm_precond *mbd = nullptr;
+    mm_precond *m2l = nullptr;
+    mm_pcg *sess = nullptr;
+    std::vector<int64_t> slot_req;
+    mm::DBuf b;
+    size_t bytes = 0;
+    int64_t n = 0;
+    bool m2l_failed = false;
+    ~Strategy() {
+        mm_pcg_destroy(sess);
+        mm_precond_destroy(m2l);
+        mm_precond_destroy(mbd);
+        mm_noise_destroy(nz);
+        mm_pointing_destroy(p);
+        b.release();
+        mm_ctx_destroy(ctx);
+    }
+};
+
+}  // namespace
+
+struct mm_server {
+    int device = 0;
+    int64_t budget = 0;
+    int64_t used = 0;
+    int32_t slots = 8;
+    int32_t defl_k = 32;
+    int32_t chunk = 4;
+    int32_t m_max = 256;
+    double eps_arn = 1e-8;
+    int64_t next_id = 1;
+    std::map<int32_t, std::unique_ptr<Strategy>> strat;
+    std::deque<int64_t> queue;
+    std::map<int64_t, Request> req;
+    std::string last_error;
+};
+
+using namespace mm;
+
+#define SRV_TRY try {
+#define SRV_END                                               \
+    }                                                         \
+    catch (const mm::Error &e) {                              \
+        srv->last_error = e.what();                           \
+        return e.code;                                        \
+    }                                                         \
+    catch (const std::exception &e) {                         \
+        srv->last_error = e.what();                           \
+        return MM_E_DEVICE;                                   \
+    }
+
+static void check(mm_status st, mm_ctx *ctx, const char *what) {
+    if (st < 0) throw Error(st, std::string(what) + ": " + mm_last_error(ctx));
+}
+
+extern "C" mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots,
+                                      int32_t defl_k, int32_t iters_per_step,
+                                      mm_server **out) {
+    if (!out) return MM_E_INVALID;
+    *out = nullptr;
+    if (hbm_budget_bytes <= 0 || !pow2_ok(slots) || defl_k < 0 || defl_k > 63 ||
+        iters_per_step < 1)
+        return MM_E_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return MM_E_INVALID;
+    auto *s = new mm_server();
+    s->device = device;
+    s->budget = hbm_budget_bytes;
+    s->slots = slots;
+    s->defl_k = defl_k;
+    s->chunk = iters_per_step;
+    *out = s;
+    return MM_OK;
+}
+
+extern "C" const char *mm_server_last_error(const mm_server *srv) {
+    return srv ? srv->last_error.c_str() : "null server";
+}
+
+extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t n_samp,
+                                            int32_t n_pix_total, const int32_t *pix,
+                                            const double *psi, int32_t min_hits,
+                                            int32_t grid_width, int32_t n_intervals,
+                                            const int64_t *interval_start,
+                                            const int32_t *filter_id, int32_t n_filters,
+                                            int32_t half_bw, const double *band,
+                                            mm_precision prec) {
+    if (!srv) return MM_E_INVALID;
+    SRV_TRY
+    MM_CHECK(!srv->strat.count(id), MM_E_INVALID, "server: strategy id already registered");
+    MM_CHECK(n_samp > 0 && n_pix_total > 0 && n_intervals > 0, MM_E_INVALID,
+             "server: bad strategy sizes");
+    // footprint: pointing (index, weights, permutation, sorted weights), two TOD
+    // workspaces of `slots` columns, session vectors, M_2l (Z, AZ, W basis)
+    const int64_t te = prec == MM_F32 ? 4 : 8;
+    const int64_t est_n = 3 * (int64_t)std::min<int64_t>(n_pix_total, n_samp);
+    const int64_t bytes = n_samp * (4 + 2 * 2 * te + 4) + 2 * n_samp * te * srv->slots +
+                          est_n * 8 * (7 * srv->slots + 2 * srv->defl_k + srv->m_max + 1);
+    if (srv->used + bytes > srv->budget)
+        throw Error(MM_E_BUSY, "server: strategy footprint " + std::to_string(bytes) +
+                                   " B exceeds the remaining budget");
+    auto st = std::make_unique<Strategy>();
+    st->id = id;
+    check(mm_ctx_create(srv->device, nullptr, &st->ctx), nullptr, "server: context");
+    check(mm_pointing_build(st->ctx, n_samp, n_pix_total, pix, psi, min_hits, prec, &st->p),
+          st->ctx, "server: pointing");
+    if (grid_width > 0) check(mm_pointing_set_grid(st->ctx, st->p, grid_width), st->ctx, "grid");
+    check(mm_noise_build(st->ctx, n_intervals, interval_start, filter_id, n_filters, half_bw, band,
+                         MM_NOISE_AUTO, prec, &st->nz),
+          st->ctx, "server: noise");
+    check(mm_mbd_build(st->ctx, st->p, st->nz, &st->mbd), st->ctx, "server: M_BD");
+    st->n = 3 * (int64_t)st->p->n_obs;
+    st->b.alloc(sizeof(double) * st->n);
+    st->slot_req.assign(srv->slots, -1);
+    st->bytes = bytes;
+    srv->used += bytes;
+    srv->strat[id] = std::move(st);
+    SRV_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_server_submit(mm_server *srv, int32_t strategy, const void *tod,
+                                      double tol, int32_t max_iter, double *x_out,
+                                      int64_t *request_id) {
+    if (!srv) return MM_E_INVALID;
+    SRV_TRY
+    MM_CHECK(srv->strat.count(strategy), MM_E_INVALID, "server: unknown strategy");
+    MM_CHECK(tod && x_out && tol >= 0 && max_iter >= 1, MM_E_INVALID, "server: bad request");
+    Request r;
+    r.id = srv->next_id++;
+    r.strategy = strategy;
+    r.tod = tod;
+    r.x_out = x_out;
+    r.tol = tol;
+    r.max_iter = max_iter;
+    r.t_submit = now_s();
+    srv->req[r.id] = r;
+    srv->queue.push_back(r.id);
+    if (request_id) *request_id = r.id;
+    SRV_END
+    return MM_OK;
+}
+
+// Admit queued requests (FIFO per strategy) into free slots.
+static void admit(mm_server *srv) {
+    for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+        Request &r = srv->req[*it];
+        Strategy &st = *srv->strat[r.strategy];
+        int slot = -1;
+        for (int c = 0; c < srv->slots; ++c)
+            if (st.slot_req[c] < 0) {
+                slot = c;
+                break;
+            }
+        if (slot < 0) {
+            ++it;
+            continue;
+        }
+        mm_ctx *ctx = st.ctx;
+        mm_status s = mm_rhs(ctx, st.p, st.nz, 1, r.tod, st.b.as<double>());
+        if (s < 0) {
+            r.state = 4;
+            r.t_done = now_s();
+            it = srv->queue.erase(it);
+            continue;
+        }
+        if (!st.m2l && !st.m2l_failed && srv->defl_k > 0) {
+            // cache miss: build M_2l from this request's right-hand side
+            const int k = std::min<int64_t>(srv->defl_k, st.n - 1);
+            const int mmax = (int)std::min<int64_t>(srv->m_max, st.n);
+            s = mm_defl_build(ctx, st.p, st.nz, st.mbd, st.b.as<double>(), k, 0.0, srv->eps_arn,
+                              mmax, nullptr, nullptr, &st.m2l);
+            if (s < 0) st.m2l_failed = true;
+            r.m2l_built = 1;
+        }
+        if (!st.sess) {
+            const mm_precond *M = st.m2l ? st.m2l : st.mbd;
+            check(mm_pcg_create(ctx, st.p, st.nz, M, srv->slots, &st.sess), ctx, "server: session");
+        }
+        check(mm_pcg_start(ctx, st.sess, slot, st.b.as<double>(), r.tol, r.max_iter), ctx,
+              "server: start");
+        st.slot_req[slot] = r.id;
+        r.slot = slot;
+        r.state = 1;
+        r.t_start = now_s();
+        it = srv->queue.erase(it);
+    }
+}
+
+extern "C" mm_status mm_server_step(mm_server *srv, int32_t *n_running, int32_t *n_queued) {
+    if (!srv) return MM_E_INVALID;
+    SRV_TRY
+    admit(srv);
+    // enqueue a chunk of iterations on every strategy's stream, then poll
+    for (auto &kv : srv->strat) {
+        Strategy &st = *kv.second;
+        bool any = false;
+        for (auto q : st.slot_req) any |= q >= 0;
+        if (any) check(mm_pcg_iterate(st.ctx, st.sess, srv->chunk), st.ctx, "server: iterate");
+    }
+    int running = 0;
+    std::vector<int32_t> state(srv->slots), iters(srv->slots);
+    std::vector<double> rr(srv->slots);
+    for (auto &kv : srv->strat) {
+        Strategy &st = *kv.second;
+        bool any = false;
+        for (auto q : st.slot_req) any |= q >= 0;
+        if (!any) continue;
+        check(mm_pcg_poll(st.ctx, st.sess, state.data(), iters.data(), rr.data()), st.ctx,
+              "server: poll");
+        for (int c = 0; c < srv->slots; ++c) {
+            if (st.slot_req[c] < 0) continue;
+            Request &r = srv->req[st.slot_req[c]];
+            if (state[c] == 1) {
+                ++running;
+                continue;
+            }
+            r.iters = iters[c];
+            r.rel_res = rr[c];
+            r.state = state[c] == 2 ? 2 : (state[c] == 3 ? 3 : 4);
+            check(mm_pcg_finish(st.ctx, st.sess, c, r.x_out), st.ctx, "server: finish");
+            r.t_done = now_s();
+            st.slot_req[c] = -1;
+        }
+    }
+    if (n_running) *n_running = running;
+    if (n_queued) *n_queued = (int32_t)srv->queue.size();
+    SRV_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_server_poll(mm_server *srv, int64_t request_id, mm_request_info *info) {
+    if (!srv || !info) return MM_E_INVALID;
+    SRV_TRY
+    auto it = srv->req.find(request_id);
+    MM_CHECK(it != srv->req.end(), MM_E_INVALID, "server: unknown request");
+    const Request &r = it->second;
+    info->state = r.state;
+    info->iters = r.iters;
+    info->slot = r.slot;
+    info->m2l_built = r.m2l_built;
+    info->rel_res = r.rel_res;
+    info->queue_seconds = (r.state >= 1 ? r.t_start : now_s()) - r.t_submit;
+    info->latency_seconds = (r.state >= 2 ? r.t_done : now_s()) - r.t_submit;
+    SRV_END
+    return MM_OK;
+}
+
+extern "C" void mm_server_destroy(mm_server *srv) { delete srv; }

@@ -8,6 +8,8 @@
 // so one wave step touches G consecutive samples x R columns: contiguous TOD
 // rows.  Each column is computed with the same arithmetic and order whatever
 // the other columns hold.
+#include <functional>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -256,7 +258,8 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
     const int64_t n = p->n_samp;
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        const int grid = grid_for(n * R, 8 * ctx->n_cu * 4);
+        const int tuned = p->p_blocks[log2i(R)];
+        const int grid = tuned > 0 ? tuned : grid_for(n * R, 8 * ctx->n_cu * 4);
         if (p->prec == MM_F32)
             k_apply_P<float, R><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(),
                                                               p->w.as<float2>(), n, x,
@@ -298,6 +301,8 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
+    const int want = nz->tuned_tile_len[log2i(nrhs)];
+    if (want > 0 && want != nz->tile_len) set_band_tiles(ctx, const_cast<mm_noise *>(nz), want);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
         dim3 grid((unsigned)nz->n_tiles, R);
@@ -335,6 +340,96 @@ void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod, 
                                                             static_cast<double *>(y), flag);
     });
     MM_HIP(hipGetLastError());
+}
+
+}  // namespace mm
+
+namespace mm {
+
+// (Re)build the direct band's tile table for tile length tl.
+void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl) {
+    std::vector<int64_t> tiles;
+    for (int i = 0; i < nz->n_int; ++i)
+        for (int64_t t = nz->h_istart[i]; t < nz->h_istart[i + 1]; t += tl) {
+            tiles.push_back(t);
+            tiles.push_back(i);
+        }
+    nz->tile_len = tl;
+    nz->n_tiles = (int64_t)tiles.size() / 2;
+    nz->tiles.alloc(sizeof(int64_t) * tiles.size());
+    MM_HIP(hipMemcpyAsync(nz->tiles.ptr, tiles.data(), sizeof(int64_t) * tiles.size(),
+                          hipMemcpyHostToDevice, ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+// Measure candidate launch shapes with HIP events and keep the fastest:
+// the direct band's tile length and the P kernel's grid size, per nrhs.
+// Every candidate computes the same values (each output's terms are summed
+// in a fixed order independent of the launch shape), so tuning never changes
+// results.  report: (stage, candidate, ms) triples.
+void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *report,
+              int *n_report) {
+    const int li = log2i(nrhs);
+    const size_t te = p->prec == MM_F32 ? sizeof(float) : sizeof(double);
+    DBuf x, y, z;
+    x.alloc(sizeof(double) * 3 * (size_t)p->n_obs * nrhs);
+    y.alloc(te * (size_t)p->n_samp * nrhs);
+    z.alloc(te * (size_t)p->n_samp * nrhs);
+    MM_HIP(hipMemsetAsync(x.ptr, 0, x.bytes, ctx->stream));
+    MM_HIP(hipMemsetAsync(y.ptr, 0, y.bytes, ctx->stream));
+    hipEvent_t e0, e1;
+    MM_HIP(hipEventCreate(&e0));
+    MM_HIP(hipEventCreate(&e1));
+    int nr = 0;
+    auto time_it = [&](const std::function<void()> &f) {
+        f();
+        MM_HIP(hipEventRecord(e0, ctx->stream));
+        for (int i = 0; i < 5; ++i) f();
+        MM_HIP(hipEventRecord(e1, ctx->stream));
+        MM_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        MM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return ms / 5.0;
+    };
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    try {
+        // P grid size
+        double best = 1e30;
+        int best_g = 0;
+        for (int mult : {2, 4, 8, 16, 32}) {
+            const int g = ctx->n_cu * mult;
+            p->p_blocks[li] = g;
+            const double ms = time_it([&]() { apply_P_dev(ctx, p, nrhs, x.as<double>(), y.ptr); });
+            if (report) { report[3 * nr] = 0; report[3 * nr + 1] = g; report[3 * nr + 2] = ms; }
+            ++nr;
+            if (ms < best) { best = ms; best_g = g; }
+        }
+        p->p_blocks[li] = best_g;
+        // direct band tile length
+        if (nz->method == MM_NOISE_DIRECT) {
+            best = 1e30;
+            int best_tl = nz->tile_len;
+            for (int tl : {256, 512, 1024, 2048, 4096}) {
+                if (tl < nrhs) continue;
+                nz->tuned_tile_len[li] = tl;
+                const double ms = time_it([&]() { noise_apply_dev(ctx, nz, nrhs, y.ptr, z.ptr); });
+                if (report) { report[3 * nr] = 1; report[3 * nr + 1] = tl; report[3 * nr + 2] = ms; }
+                ++nr;
+                if (ms < best) { best = ms; best_tl = tl; }
+            }
+            nz->tuned_tile_len[li] = best_tl;
+        }
+    } catch (...) {
+        ctx->prof.on = prof;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    ctx->prof.on = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_report) *n_report = nr;
 }
 
 }  // namespace mm

@@ -40,6 +40,12 @@ class SolveInfo(C.Structure):
                 ("rel_res_true", C.c_double), ("solve_seconds", C.c_double)]
 
 
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("iters", C.c_int32), ("slot", C.c_int32),
+                ("m2l_built", C.c_int32), ("rel_res", C.c_double),
+                ("queue_seconds", C.c_double), ("latency_seconds", C.c_double)]
+
+
 class ArnoldiInfo(C.Structure):
     _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("h_last", C.c_double),
                 ("setup_seconds", C.c_double)]
@@ -86,6 +92,15 @@ def lib() -> C.CDLL:
             "mm_precond_destroy": (None, [P]),
             "mm_solve": (C.c_int, [P, P, P, P, I32, P, P, D, I32, U32, P, P]),
             "mm_profile_enable": (C.c_int, [P, C.c_int]),
+            "mm_autotune": (C.c_int, [P, P, P, I32, P, C.POINTER(I32)]),
+            "mm_server_create": (C.c_int, [C.c_int, I64, I32, I32, I32, PP]),
+            "mm_server_add_strategy": (C.c_int, [P, I32, I64, I32, P, P, I32, I32, I32, P, P, I32,
+                                                 I32, P, C.c_int]),
+            "mm_server_submit": (C.c_int, [P, I32, P, D, I32, P, C.POINTER(I64)]),
+            "mm_server_step": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
+            "mm_server_poll": (C.c_int, [P, I64, C.POINTER(RequestInfo)]),
+            "mm_server_last_error": (C.c_char_p, [P]),
+            "mm_server_destroy": (None, [P]),
             "mm_profile_read": (C.c_int, [P, I32, P, P, P, C.POINTER(I32)]),
             "mm_hessenberg_eig": (C.c_int, [I32, P, P, P, P, P]),
             "mm_pcg_create": (C.c_int, [P, P, P, P, I32, PP]),
@@ -313,6 +328,15 @@ class Context:
                             history=h, status=st))
         return x, (out[0] if nrhs == 1 else out)
 
+    def autotune(self, p, nz, nrhs: int = 1):
+        """Pick launch shapes by measurement; returns [(stage, candidate, ms)]."""
+        rep = np.zeros(3 * 16)
+        n = C.c_int32()
+        self._check(lib().mm_autotune(self.h, p.h, nz.h, nrhs, rep.ctypes.data, C.byref(n)),
+                    "mm_autotune")
+        return [({0: "P", 1: "band"}[int(rep[3 * i])], int(rep[3 * i + 1]), float(rep[3 * i + 2]))
+                for i in range(n.value)]
+
     def pcg_session(self, p, nz, M, nrhs: int):
         h = C.c_void_p()
         self._check(lib().mm_pcg_create(self.h, p.h, nz.h, M.h if M is not None else None, nrhs,
@@ -477,3 +501,65 @@ class PcgSession(_Handle):
             x = torch.empty(self.n, dtype=torch.float64, device=self.ctx.torch_device)
         self.ctx._check(lib().mm_pcg_finish(self.ctx.h, self.h, slot, _ptr(x)), "mm_pcg_finish")
         return x
+
+
+class Server:
+    """Continuous-batching serving engine (mm_server_*): recurring strategies,
+    cached M_BD/M_2l, per-strategy streams, column slots admitted mid-flight."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 200 << 30, slots: int = 8,
+                 defl_k: int = 32, iters_per_step: int = 4):
+        h = C.c_void_p()
+        st = lib().mm_server_create(device, hbm_budget_bytes, slots, defl_k, iters_per_step,
+                                    C.byref(h))
+        if st != 0:
+            raise MapmakerError(st, "mm_server_create failed")
+        self.h = h
+        self.device = device
+        self.n = {}
+
+    def _check(self, st, what):
+        if st < 0:
+            msg = lib().mm_server_last_error(self.h)
+            raise MapmakerError(st, f"{what}: {msg.decode() if msg else ''}")
+        return st
+
+    def add_strategy(self, sid: int, pix, psi, n_pix_total: int, interval_start, filter_id, band,
+                     half_bw: int, min_hits: int = 3, grid_width: int = 0, prec: int = F64):
+        import torch
+        _dev_check(pix, torch.int32, name="pix")
+        _dev_check(psi, torch.float64, pix.numel(), name="psi")
+        istart = np.ascontiguousarray(interval_start, dtype=np.int64)
+        fid = np.ascontiguousarray(filter_id, dtype=np.int32)
+        band = np.ascontiguousarray(band, dtype=np.float64).reshape(-1, half_bw + 1)
+        self._check(lib().mm_server_add_strategy(
+            self.h, sid, pix.numel(), n_pix_total, _ptr(pix), _ptr(psi), min_hits, grid_width,
+            fid.shape[0], istart.ctypes.data, fid.ctypes.data, band.shape[0], half_bw,
+            band.ctypes.data, prec), "mm_server_add_strategy")
+
+    def submit(self, sid: int, tod, x_out, tol: float = 1e-8, max_iter: int = 1000) -> int:
+        rid = C.c_int64()
+        self._check(lib().mm_server_submit(self.h, sid, _ptr(tod), tol, max_iter, _ptr(x_out),
+                                           C.byref(rid)), "mm_server_submit")
+        return rid.value
+
+    def step(self):
+        nr, nq = C.c_int32(), C.c_int32()
+        self._check(lib().mm_server_step(self.h, C.byref(nr), C.byref(nq)), "mm_server_step")
+        return nr.value, nq.value
+
+    def poll(self, rid: int) -> dict:
+        info = RequestInfo()
+        self._check(lib().mm_server_poll(self.h, rid, C.byref(info)), "mm_server_poll")
+        return {f: getattr(info, f) for f, _ in RequestInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

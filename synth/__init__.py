@@ -296,19 +296,22 @@ SERVE_STRATEGIES = (
 )
 
 
-def serve_strategy(s: int, realization: int = 0, noiseless: bool = False) -> Problem:
-    n_side, grid, spd, lam = SERVE_STRATEGIES[s]
+def serve_strategy(s: int, realization: int = 0, noiseless: bool = False,
+                   shapes=None, L: int = 1 << 16) -> Problem:
+    """Strategy s of the serving trace.  Pointing and noise model are fixed per
+    strategy; the sky and noise realisation change with `realization`.
+    `shapes` = (n_side, grid, samples/detector, lambda) overrides the table
+    (smaller instances for tests)."""
+    n_side, grid, spd, lam = shapes if shapes is not None else SERVE_STRATEGIES[s]
     n_det = grid[0] * grid[1]
     pix = rotated_raster(n_side, grid, spd)
     fk = rng_for(50 + s, 0, STREAM_FKNEE).uniform(0.05, 1.0, n_det)
-    # pointing and noise model are fixed per strategy (realization 0);
-    # the sky and noise realisation change per request
-    p = _finish(f"s{s}", 50 + s, 0, n_side, pix, 1 << 16, lam, fk, spd, True)
+    p = _finish(f"s{s}", 50 + s, 0, n_side, pix, L, lam, fk, spd, True)
     if realization != 0 or not noiseless:
         sky = white_sky(rng_for(50 + s, realization, STREAM_SIGNAL), p.n_pix_total)
         d = signal_tod(p.pix, p.psi, sky)
         if not noiseless:
-            noise = noise_1f(rng_for(50 + s, realization, STREAM_NOISE), 1 << 16,
+            noise = noise_1f(rng_for(50 + s, realization, STREAM_NOISE), L,
                              p.n_intervals, fk[p.filter_id]).reshape(-1)
             d = d + noise
         p.signal, p.tod = sky, d

@@ -523,3 +523,17 @@ def test_batched_fp32_variant(ctx):
     err = rel(host(xb).reshape(op.n, 8)[:, 3], xo)
     print(f"fp32 batched block CG: map error vs FP64 oracle {err:.2e}")
     assert err <= 1e-3
+
+
+def test_autotune_keeps_results_bitwise(ctx):
+    import torch
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p, method=1)
+    x = dev(np.random.default_rng(9).standard_normal(op.n * 8))
+    a1 = ctx.apply_A(lp, ln, x[: op.n])
+    a8 = ctx.apply_A(lp, ln, x, nrhs=8)
+    rep1 = ctx.autotune(lp, ln, 1)
+    rep8 = ctx.autotune(lp, ln, 8)
+    assert len(rep1) >= 5 and any(r[0] == "band" for r in rep1)
+    assert torch.equal(a1, ctx.apply_A(lp, ln, x[: op.n]))
+    assert torch.equal(a8, ctx.apply_A(lp, ln, x, nrhs=8))

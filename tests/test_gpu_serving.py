@@ -1,0 +1,102 @@
+"""Serving form: continuous batching of map-making solves over recurring scan
+strategies (mm_server_*), through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from gpu_util import dev, host, rel
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(32, (4, 2), 1 << 12, 128), (64, (4, 4), 1 << 13, 256)]
+
+
+def _strategy(s, r):
+    return synth.serve_strategy(s, r, shapes=SMALL[s], L=1 << 11)
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1801_08937_amd import mapmaker
+    return mapmaker
+
+
+def _server(mm, slots=4, k=8):
+    srv = mm.Server(0, hbm_budget_bytes=8 << 30, slots=slots, defl_k=k, iters_per_step=3)
+    for s in range(2):
+        p = _strategy(s, 0)
+        srv.add_strategy(s, dev(p.pix), dev(p.psi), p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+    return srv
+
+
+def _run(srv, reqs, join_after=1):
+    """reqs: list of (strategy, realization, tol); the first is submitted,
+    `join_after` steps run, then the rest join mid-flight."""
+    import torch
+    outs, ids = [], []
+    for i, (s, r, tol) in enumerate(reqs):
+        p = _strategy(s, r)
+        x = torch.zeros(3 * int(np.sum(np.bincount(p.pix[p.pix >= 0], minlength=p.n_pix_total)
+                                       >= p.min_hits)), dtype=torch.float64, device="cuda")
+        tod = dev(p.tod)
+        outs.append((x, tod, p))
+        ids.append(srv.submit(s, tod, x, tol=tol))
+        if i == 0:
+            for _ in range(join_after):
+                srv.step()
+    for _ in range(2000):
+        run, q = srv.step()
+        if run == 0 and q == 0:
+            break
+    return [srv.poll(i) for i in ids], outs
+
+
+def test_server_result_same_alone_and_in_mix(mm):
+    import torch
+    srv = _server(mm)
+    infos_a, outs_a = _run(srv, [(0, 1, 1e-8)])
+    srv.close()
+    srv = _server(mm)
+    infos_b, outs_b = _run(srv, [(0, 1, 1e-8), (0, 2, 1e-6), (1, 3, 1e-8), (0, 4, 1e-8),
+                                 (1, 5, 1e-6)], join_after=2)
+    srv.close()
+    assert infos_a[0]["state"] == 2 and all(i["state"] == 2 for i in infos_b)
+    # the first request's map: bitwise the same alone and with four others joining
+    assert infos_a[0]["iters"] == infos_b[0]["iters"]
+    assert torch.equal(outs_a[0][0], outs_b[0][0])
+    assert infos_b[0]["m2l_built"] == 1 and infos_b[1]["m2l_built"] == 0
+    # every result solves its own system (oracle solution within kappa * tol)
+    for (x, tod, p), info, tol in zip(outs_b, infos_b, (1e-8, 1e-6, 1e-8, 1e-8, 1e-6)):
+        op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+        on = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+        OM = O.mbd_build(op, on)
+        bo = O.rhs(op, on, p.tod)
+        xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-13,
+                      5000)
+        e = rel(host(x), xo)
+        assert e <= 1e4 * tol, (e, tol)
+
+
+def test_server_continuous_batching_many(mm):
+    srv = _server(mm, slots=4)
+    reqs = [(i % 2, 10 + i, 1e-8 if i % 3 else 1e-6) for i in range(14)]
+    infos, outs = _run(srv, reqs, join_after=1)
+    srv.close()
+    assert all(i["state"] == 2 for i in infos)
+    assert sum(i["m2l_built"] for i in infos) == 2   # one M_2l per strategy, then cached
+    # more requests than slots: some waited in the queue and were admitted later
+    assert max(i["queue_seconds"] for i in infos) > 0
+
+
+def test_server_budget_rejects(mm):
+    srv = mm.Server(0, hbm_budget_bytes=1 << 20, slots=4, defl_k=8)
+    p = _strategy(1, 0)
+    with pytest.raises(mm.MapmakerError) as e:
+        srv.add_strategy(1, dev(p.pix), dev(p.psi), p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw)
+    assert e.value.name == "MM_E_BUSY"
+    srv.close()
