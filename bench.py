@@ -104,10 +104,17 @@ def main():
         import torch
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 5}))
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        print(json.dumps({"copy_bytes": src.numel() * 8, "copies": 5, "ms": ms,
+                          "GBps_read_plus_write": 2 * src.numel() * 8 / ms / 1e6}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU design (shard by "

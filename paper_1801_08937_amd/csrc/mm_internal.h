@@ -105,6 +105,7 @@ struct mm_ctx {
     mm::DBuf red;                  // reduction partials
     mm::DBuf scal;                 // small device scalars
     mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
+    mm::DBuf xpack;                // map packed as (I, Q, U, 0) records for P
     hipStream_t cap = nullptr;     // private stream for graph capture
     double *pinned = nullptr;      // host pinned scratch (scalar readback)
     size_t pinned_bytes = 0;

@@ -20,69 +20,16 @@
 // even and odd outputs.
 #include <cmath>
 
-#include "mm_internal.h"
+#include "fft_common.h"
 
 namespace mm {
 namespace {
 
+using fft::dft_small;
+
 constexpr int FFT_NC = 8192;       // complex points per block
 constexpr int FFT_N = 2 * FFT_NC;  // real samples per block
 constexpr int FFT_THREADS = 512;
-constexpr int FFT_MAX_LAMBDA = 6144;
-
-// e^{2 pi i m / 16}
-__device__ constexpr double C16[16] = {
-    1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898,
-    0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
-    -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898,
-    0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
-__device__ constexpr double S16[16] = {
-    0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867,
-    1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898,
-    0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
-    -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
-
-constexpr int ilog2(int r) { return r <= 1 ? 0 : 1 + ilog2(r / 2); }
-constexpr int bitrev(int i, int bits) {
-    int o = 0;
-    for (int b = 0; b < bits; ++b) o |= ((i >> b) & 1) << (bits - 1 - b);
-    return o;
-}
-
-// In-register R-point DFT, DIR = -1 forward, +1 inverse (radix-2, decimation
-// in time).
-template <typename T, int R, int DIR>
-__device__ __forceinline__ void dft_small(T (&re)[R], T (&im)[R]) {
-    constexpr int B = ilog2(R);
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int j = bitrev(i, B);
-        if (i < j) {
-            T t = re[i]; re[i] = re[j]; re[j] = t;
-            t = im[i]; im[i] = im[j]; im[j] = t;
-        }
-    }
-#pragma unroll
-    for (int len = 2; len <= R; len *= 2) {
-        const int half = len / 2;
-        const int step = 16 / len;
-#pragma unroll
-        for (int i = 0; i < R; i += len) {
-#pragma unroll
-            for (int k = 0; k < half; ++k) {
-                const T wr = (T)C16[k * step];
-                const T wi = (T)(DIR * S16[k * step]);
-                const T xr = re[i + k + half], xi = im[i + k + half];
-                const T tr = wr * xr - wi * xi;
-                const T ti = wr * xi + wi * xr;
-                re[i + k + half] = re[i + k] - tr;
-                im[i + k + half] = im[i + k] - ti;
-                re[i + k] += tr;
-                im[i + k] += ti;
-            }
-        }
-    }
-}
 
 // LDS index with one pad slot per 16 entries, so the stride-16 accesses of
 // the radix-16 pass fall in distinct banks.
@@ -256,71 +203,87 @@ __global__ void __launch_bounds__(FFT_THREADS)
     }
 }
 
-// H_k = c_0 + 2 sum_d c_d cos(2 pi k d / N) for k in [0, NC], with the cosine
-// table cos(2 pi m / N), m < N, staged in LDS (exact argument reduction by
-// integer arithmetic on k d mod N).
+// H_k = c_0 + 2 sum_d c_d cos(2 pi k d / N) for k in [0, N/2].  The cosine of
+// 2 pi m / N comes from a quarter-period table in LDS (m reduced by integer
+// arithmetic, k d mod N, then folded by symmetry), so every angle is exact.
+constexpr int QMAX = 8192;  // N/4 for the largest block
 __global__ void __launch_bounds__(256)
-    k_fft_spectrum(const double *__restrict__ band, int lam, const double *__restrict__ ctab,
-                   double *__restrict__ H) {
-    __shared__ double sc[FFT_N];
-    for (int m = threadIdx.x; m < FFT_N; m += 256) sc[m] = ctab[m];
+    k_fft_spectrum(const double *__restrict__ band, int lam, int N,
+                   const double *__restrict__ qtab, double *__restrict__ H) {
+    __shared__ double sc[QMAX + 1];
+    const int Q = N / 4;
+    for (int m = threadIdx.x; m <= Q; m += 256) sc[m] = qtab[m];
     __syncthreads();
     const int f = blockIdx.y;
     const double *c = band + (int64_t)f * (lam + 1);
+    const int NC = N / 2;
     const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k > FFT_NC) return;
+    if (k > NC) return;
     double s = 0;
-    for (int d = 1; d <= lam; ++d) s += c[d] * sc[(int)(((int64_t)k * d) & (FFT_N - 1))];
-    H[(int64_t)f * (FFT_NC + 1) + k] = c[0] + 2.0 * s;
+    for (int d = 1; d <= lam; ++d) {
+        int m = (int)(((int64_t)k * d) & (N - 1));
+        if (m > NC) m = N - m;                       // cos(2 pi m/N) = cos(2 pi (N-m)/N)
+        const double v = m > Q ? -sc[NC - m] : sc[m];  // cos(pi - x) = -cos x
+        s += c[d] * v;
+    }
+    H[(int64_t)f * (NC + 1) + k] = c[0] + 2.0 * s;
 }
 
 template <typename T>
-__global__ void k_fft_ab(const double *__restrict__ H, int n_filters,
+__global__ void k_fft_ab(const double *__restrict__ H, int n_filters, int NC,
                          typename Vec2T<T>::type *__restrict__ ab) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)n_filters * FFT_NC) return;
-    const int64_t f = e / FFT_NC;
-    const int k = (int)(e % FFT_NC);
-    const double hk = H[f * (FFT_NC + 1) + k];
-    const double hc = H[f * (FFT_NC + 1) + (FFT_NC - k)];  // H_{k+NC} = H_{NC-k}
+    if (e >= (int64_t)n_filters * NC) return;
+    const int64_t f = e / NC;
+    const int k = (int)(e % NC);
+    const double hk = H[f * (NC + 1) + k];
+    const double hc = H[f * (NC + 1) + (NC - k)];  // H_{k+NC} = H_{NC-k}
     typename Vec2T<T>::type v;
-    v.x = (T)((hk + hc) / (2.0 * FFT_NC));
-    v.y = (T)((hk - hc) / (2.0 * FFT_NC));
+    v.x = (T)((hk + hc) / (2.0 * NC));
+    v.y = (T)((hk - hc) / (2.0 * NC));
     ab[e] = v;
 }
 
 }  // namespace
 
+bool noise_fft_big_supported(int half_bw);
+int noise_fft_big_nc();
+void noise_fft_big_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
+
 bool noise_fft_supported(int half_bw, int64_t min_len) {
     (void)min_len;
-    return half_bw >= 1 && half_bw <= FFT_MAX_LAMBDA;
+    return half_bw >= 1 && noise_fft_big_supported(half_bw);
 }
 
+// Block size: 16,384 real samples while that leaves at least 3/4 of each block
+// valid (lambda <= 2048), else 32,768.
 void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz) {
     hipStream_t s = ctx->stream;
     const int lam = nz->half_bw;
     MM_CHECK(noise_fft_supported(lam, 0), MM_E_INVALID, "FFT: bandwidth unsupported");
-    nz->fft_n = FFT_N;
-    nz->fft_valid = FFT_N - 2 * lam;
+    const int NC = lam <= 2048 ? FFT_NC : noise_fft_big_nc();
+    const int N = 2 * NC;
+    nz->fft_n = N;
+    nz->fft_valid = N - 2 * lam;
     const bool f32 = nz->prec == MM_F32;
     const size_t e2 = f32 ? sizeof(float2) : sizeof(double2);
     // twiddle tables (long double on the host, rounded once)
-    std::vector<double> ctab(FFT_N);
-    std::vector<double> tw(2 * FFT_NC), twN(2 * FFT_NC);
+    std::vector<double> qtab(N / 4 + 1);
+    std::vector<double> tw(2 * NC), twN(2 * NC);
     const long double pi2 = 6.283185307179586476925286766559L;
-    for (int m = 0; m < FFT_N; ++m) ctab[m] = (double)cosl(pi2 * m / FFT_N);
-    for (int m = 0; m < FFT_NC; ++m) {
-        tw[2 * m] = (double)cosl(pi2 * m / FFT_NC);
-        tw[2 * m + 1] = (double)-sinl(pi2 * m / FFT_NC);
-        twN[2 * m] = (double)cosl(pi2 * m / FFT_N);
-        twN[2 * m + 1] = (double)-sinl(pi2 * m / FFT_N);
+    for (int m = 0; m <= N / 4; ++m) qtab[m] = (double)cosl(pi2 * m / N);
+    for (int m = 0; m < NC; ++m) {
+        tw[2 * m] = (double)cosl(pi2 * m / NC);
+        tw[2 * m + 1] = (double)-sinl(pi2 * m / NC);
+        twN[2 * m] = (double)cosl(pi2 * m / N);
+        twN[2 * m + 1] = (double)-sinl(pi2 * m / N);
     }
-    nz->fft_tw.alloc(2 * e2 * FFT_NC);  // tw then twN
+    nz->fft_tw.alloc(2 * e2 * NC);  // tw then twN
     if (f32) {
-        std::vector<float> a(4 * FFT_NC);
-        for (int i = 0; i < 2 * FFT_NC; ++i) {
+        std::vector<float> a(4 * (size_t)NC);
+        for (int i = 0; i < 2 * NC; ++i) {
             a[i] = (float)tw[i];
-            a[2 * FFT_NC + i] = (float)twN[i];
+            a[2 * NC + i] = (float)twN[i];
         }
         MM_HIP(hipMemcpyAsync(nz->fft_tw.ptr, a.data(), sizeof(float) * a.size(),
                               hipMemcpyHostToDevice, s));
@@ -328,26 +291,27 @@ void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz) {
     } else {
         MM_HIP(hipMemcpyAsync(nz->fft_tw.ptr, tw.data(), sizeof(double) * tw.size(),
                               hipMemcpyHostToDevice, s));
-        MM_HIP(hipMemcpyAsync(nz->fft_tw.as<double>() + 2 * FFT_NC, twN.data(),
+        MM_HIP(hipMemcpyAsync(nz->fft_tw.as<double>() + 2 * NC, twN.data(),
                               sizeof(double) * twN.size(), hipMemcpyHostToDevice, s));
         MM_HIP(hipStreamSynchronize(s));
     }
     // spectra
-    DBuf dctab, H;
-    dctab.alloc(sizeof(double) * FFT_N);
-    H.alloc(sizeof(double) * (size_t)nz->n_filters * (FFT_NC + 1));
-    MM_HIP(hipMemcpyAsync(dctab.ptr, ctab.data(), sizeof(double) * FFT_N, hipMemcpyHostToDevice, s));
-    dim3 g((FFT_NC + 1 + 255) / 256, nz->n_filters);
-    k_fft_spectrum<<<g, 256, 0, s>>>(nz->band64.as<double>(), lam,
-                                                           dctab.as<double>(), H.as<double>());
-    nz->fft_spec.alloc(e2 * (size_t)nz->n_filters * FFT_NC);
-    const int64_t tot = (int64_t)nz->n_filters * FFT_NC;
+    DBuf dq, H;
+    dq.alloc(sizeof(double) * qtab.size());
+    H.alloc(sizeof(double) * (size_t)nz->n_filters * (NC + 1));
+    MM_HIP(hipMemcpyAsync(dq.ptr, qtab.data(), sizeof(double) * qtab.size(), hipMemcpyHostToDevice,
+                          s));
+    dim3 g((NC + 1 + 255) / 256, nz->n_filters);
+    k_fft_spectrum<<<g, 256, 0, s>>>(nz->band64.as<double>(), lam, N, dq.as<double>(),
+                                     H.as<double>());
+    nz->fft_spec.alloc(e2 * (size_t)nz->n_filters * NC);
+    const int64_t tot = (int64_t)nz->n_filters * NC;
     if (f32)
-        k_fft_ab<float><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(H.as<double>(), nz->n_filters,
-                                                                   nz->fft_spec.as<float2>());
+        k_fft_ab<float><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+            H.as<double>(), nz->n_filters, NC, nz->fft_spec.as<float2>());
     else
-        k_fft_ab<double><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(H.as<double>(), nz->n_filters,
-                                                                    nz->fft_spec.as<double2>());
+        k_fft_ab<double><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(
+            H.as<double>(), nz->n_filters, NC, nz->fft_spec.as<double2>());
     MM_HIP(hipGetLastError());
     // block table
     std::vector<int64_t> blocks;
@@ -364,6 +328,10 @@ void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz) {
 }
 
 void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
+    if (nz->fft_n != FFT_N) {
+        noise_fft_big_apply_dev(ctx, nz, nrhs, y, z);
+        return;
+    }
     Scope sc(ctx->prof, ctx->stream, "Ninv_fft");
     dim3 grid((unsigned)nz->n_fft_blocks, nrhs);
     if (nz->prec == MM_F32) {

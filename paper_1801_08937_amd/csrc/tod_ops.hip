@@ -68,6 +68,48 @@ __global__ void __launch_bounds__(BS) k_apply_P(const int32_t *__restrict__ jpix
     for (; t < n; t += step) y[t * R + r] = p_gather<T, R>(jpix[t], w[t], x, r);
 }
 
+// Single column: the map is first packed as 32-byte records (I, Q, U, 0) so
+// each sample's gather is two aligned 16-byte loads instead of three 8-byte
+// ones.
+__global__ void __launch_bounds__(BS) k_pack_map(const double *__restrict__ x, int32_t n_obs,
+                                                 double2 *__restrict__ x4) {
+    for (int64_t j = (int64_t)blockIdx.x * BS + threadIdx.x; j < n_obs;
+         j += (int64_t)gridDim.x * BS) {
+        x4[2 * j] = make_double2(x[3 * j], x[3 * j + 1]);
+        x4[2 * j + 1] = make_double2(x[3 * j + 2], 0.0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T p_gather4(int32_t j, typename Vec2<T>::type ww,
+                                       const double2 *__restrict__ x4) {
+    if (j < 0) return (T)0;
+    const double2 iq = x4[2 * (int64_t)j];
+    const double u = x4[2 * (int64_t)j + 1].x;
+    return (T)iq.x + ww.x * (T)iq.y + ww.y * (T)u;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpix,
+                                                 const typename Vec2<T>::type *__restrict__ w,
+                                                 int64_t n, const double2 *__restrict__ x4,
+                                                 T *__restrict__ y) {
+    const int64_t step = (int64_t)gridDim.x * BS;
+    int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    for (; t + 3 * step < n; t += 4 * step) {
+        int32_t j[4];
+        typename Vec2<T>::type ww[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            j[q] = jpix[t + q * step];
+            ww[q] = w[t + q * step];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[t + q * step] = p_gather4<T>(j[q], ww[q], x4);
+    }
+    for (; t < n; t += step) y[t] = p_gather4<T>(jpix[t], w[t], x4);
+}
+
 // Pixels are visited in the order `order` (NULL = ascending), e.g. square
 // tiles of the map, and each XCD takes a contiguous range of that order: the
 // pixels one XCD reduces together are neighbours, hit by the same stretches of
@@ -256,6 +298,24 @@ template <typename F> void dispatch_r(int nrhs, F &&f) {
 void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y) {
     Scope sc(ctx->prof, ctx->stream, "P");
     const int64_t n = p->n_samp;
+    if (nrhs == 1) {
+        ctx->xpack.alloc(sizeof(double2) * 2 * (size_t)(p->n_obs > 0 ? p->n_obs : 1));
+        k_pack_map<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(x, p->n_obs,
+                                                                    ctx->xpack.as<double2>());
+        const int tuned = p->p_blocks[0];
+        const int grid = tuned > 0 ? tuned : grid_for(n, 8 * ctx->n_cu * 4);
+        if (p->prec == MM_F32)
+            k_apply_P1<float><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), p->w.as<float2>(),
+                                                            n, ctx->xpack.as<double2>(),
+                                                            static_cast<float *>(y));
+        else
+            k_apply_P1<double><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(),
+                                                             p->w.as<double2>(), n,
+                                                             ctx->xpack.as<double2>(),
+                                                             static_cast<double *>(y));
+        MM_HIP(hipGetLastError());
+        return;
+    }
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
         const int tuned = p->p_blocks[log2i(R)];
