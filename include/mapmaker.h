@@ -106,14 +106,22 @@ mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
                             const int32_t *pix, const double *psi, int32_t min_hits,
                             mm_precision prec, mm_pointing **out);
 /* Optional locality hint: the global pixel ids are row-major on a grid of
- * `width` columns (id = row * width + column).  P^T then visits the observed
- * pixels in 32 x 32 tiles of that grid, so the pixels reduced together are
- * hit by the same stretches of the scan and share cache lines.  Every pixel's
- * sum keeps its order, so results are bitwise unchanged.  width = 0 restores
- * ascending order.  Errors: MM_E_INVALID (negative width). */
+ * `width` columns (id = row * width + column).  P^T then groups neighbouring
+ * pixels of that grid (32 x 32 tiles in the one-wave-per-pixel form, 8 x 8
+ * blocks in the sliced single-column form), so the pixels reduced together
+ * are hit by the same stretches of the scan and share cache lines.  Every
+ * pixel's sum keeps its order, so results are bitwise unchanged.  width = 0
+ * restores ascending order.  Errors: MM_E_INVALID (negative width). */
 mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t width);
 /* n_obs (observed pixels) and n_valid (unflagged samples).  [host] outputs. */
 mm_status mm_pointing_counts(const mm_pointing *p, int32_t *n_obs, int64_t *n_valid);
+/* Execution layout of the single-column P^T (Eq. mapmaking's P^T as a
+ * pixel-sorted reduction): *slices = pixel slices of 64 and *segments = time
+ * segments of the sliced form, both 0 when the problem is small enough for
+ * the one-wave-per-pixel form.  Each pixel sums its samples in time order
+ * within a segment, then the segments in order; the layout is a function of
+ * n_obs and n_valid only, never of the device.  [host] outputs. */
+mm_status mm_pointing_pt_layout(const mm_pointing *p, int32_t *slices, int32_t *segments);
 /* Hit counts per global pixel and the observed pixels' global ids.
  *   hits [device] int32[n_pix_total]; obs_pix [device] int32[n_obs] (either may be NULL) */
 mm_status mm_pointing_hits(mm_ctx *ctx, const mm_pointing *p, int32_t *hits, int32_t *obs_pix);
@@ -140,6 +148,10 @@ mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals, const int64_t *interv
                          mm_noise **out);
 /* The method actually used (MM_NOISE_DIRECT or MM_NOISE_FFT). */
 mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method);
+/* Overlap-save block geometry of the FFT method (Sect. 3, the Toeplitz apply
+ * as a circulant product): each block transforms *n_fft samples and keeps
+ * *n_valid = *n_fft - 2 lambda outputs.  Both 0 for the direct method. */
+mm_status mm_noise_fft_block(const mm_noise *nz, int32_t *n_fft, int32_t *n_valid);
 /* z = N^-1 y on the TOD layout.  y, z [device], TOD precision, distinct. */
 mm_status mm_noise_apply(mm_ctx *ctx, const mm_noise *nz, int32_t nrhs, const void *y, void *z);
 void mm_noise_destroy(mm_noise *nz);

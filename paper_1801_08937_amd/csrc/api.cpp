@@ -108,8 +108,8 @@ void check_pair(const mm_pointing *p, const mm_noise *nz) {
 
 void ensure_tod(mm_ctx *ctx, const mm_pointing *p, int nrhs) {
     const size_t b = tod_elem(p->prec) * (size_t)p->n_samp * nrhs;
-    ctx->tod_a.alloc(b);
-    ctx->tod_b.alloc(b);
+    ws_alloc(ctx, ctx->tod_a, b);
+    ws_alloc(ctx, ctx->tod_b, b);
 }
 
 void apply_A_impl(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, int nrhs,
@@ -197,10 +197,18 @@ struct PcgGraph {
     hipGraph_t g = nullptr;
     hipGraphExec_t ex = nullptr;
     int chunk = 0;
-    ~PcgGraph() {
+    uint64_t gen = 0;  // context workspace generation the graph was captured with
+    void reset() {
         if (ex) (void)hipGraphExecDestroy(ex);
         if (g) (void)hipGraphDestroy(g);
+        ex = nullptr;
+        g = nullptr;
     }
+    // A graph whose workspaces have since been reallocated must be captured again.
+    void drop_if_stale(const mm_ctx *ctx) {
+        if (ex && gen != ctx->ws_gen) reset();
+    }
+    ~PcgGraph() { reset(); }
 };
 
 // z = M r on all columns with the fused partial sums of r.z.
@@ -257,6 +265,7 @@ void capture_chunk(mm_ctx *ctx, PcgGraph &G, int chunk, const std::function<void
     MM_HIP(e);
     MM_HIP(hipGraphInstantiate(&G.ex, G.g, nullptr, nullptr, 0));
     G.chunk = chunk;
+    G.gen = ctx->ws_gen;
 }
 
 int choose_tile(int64_t n_samp, int n_cu) {
@@ -358,7 +367,16 @@ extern "C" mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t w
         pointing_set_grid_device(ctx, p, width, 32);
         p->grid_width = width;
     }
+    pointing_slices_device(ctx, p, width);
     API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pointing_pt_layout(const mm_pointing *p, int32_t *slices,
+                                           int32_t *segments) {
+    if (!p || !slices || !segments) return MM_E_INVALID;
+    *slices = p->sl_G;
+    *segments = p->sl_S;
     return MM_OK;
 }
 
@@ -491,6 +509,14 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
 extern "C" mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method) {
     if (!nz || !method) return MM_E_INVALID;
     *method = nz->method;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_noise_fft_block(const mm_noise *nz, int32_t *n_fft, int32_t *n_valid) {
+    if (!nz || !n_fft || !n_valid) return MM_E_INVALID;
+    const bool fft = nz->method == MM_NOISE_FFT;
+    *n_fft = fft ? (int32_t)nz->fft_n : 0;
+    *n_valid = fft ? (int32_t)nz->fft_valid : 0;
     return MM_OK;
 }
 
@@ -907,6 +933,7 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     while (!all_done && it < max_iter) {
         if (use_graph && it >= 1 && it + check <= max_iter) {
             // first iteration ran eagerly (workspace sized); later chunks replay a graph
+            G.drop_if_stale(ctx);
             if (!G.ex) capture_chunk(ctx, G, check, [&]() { pcg_iteration(ctx, p, nz, M, w, x); });
             MM_HIP(hipGraphLaunch(G.ex, s));
             it += check;
@@ -1175,6 +1202,7 @@ extern "C" mm_status mm_pcg_iterate(mm_ctx *ctx, mm_pcg *S, int32_t n_iter) {
         int done_it = 0;
         if (S->graph_chunk > 0 && S->warm) {
             while (done_it + S->graph_chunk <= chunk) {
+                S->G.drop_if_stale(ctx);
                 if (!S->G.ex)
                     capture_chunk(ctx, S->G, S->graph_chunk, [&]() {
                         pcg_iteration(ctx, S->p, S->nz, S->M, S->w, S->x.as<double>());

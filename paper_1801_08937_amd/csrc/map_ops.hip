@@ -843,7 +843,7 @@ void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const d
 void dot_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b, double *out) {
     Scope sc(ctx->prof, ctx->stream, "vec");
     const int parts = reduction_parts(n);
-    ctx->red.alloc(sizeof(double) * parts * 64);
+    ws_alloc(ctx, ctx->red, sizeof(double) * parts * 64);
     dot_partial_cols(ctx, n, nrhs, a, b, ctx->red.as<double>(), parts);
     k_dot_final<<<nrhs, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, nrhs, out);
     MM_HIP(hipGetLastError());
@@ -939,7 +939,7 @@ void slot_ctl(mm_ctx *ctx, PcgDev s, int slot, int mode, double tol) {
 void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, double *h) {
     Scope sc(ctx->prof, ctx->stream, "gemv");
     const int parts = reduction_parts(n);
-    ctx->red.alloc(sizeof(double) * parts * (ncol > 64 ? ncol : 64));
+    ws_alloc(ctx, ctx->red, sizeof(double) * parts * (ncol > 64 ? ncol : 64));
     k_gemv_t<<<dim3(parts, ncol), BS, 0, ctx->stream>>>(n, W, v, ctx->red.as<double>(),
                                                          rows_per(n, parts), ncol);
     k_dot_final<<<ncol, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, ncol, h);
@@ -977,7 +977,7 @@ void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t 
     if (parts < 1) parts = 1;
     int64_t rpb = (n + parts - 1) / parts;
     rpb = (rpb + GR_ROWS - 1) / GR_ROWS * GR_ROWS;
-    ctx->gram_part.alloc(sizeof(double) * 4096 * parts);
+    ws_alloc(ctx, ctx->gram_part, sizeof(double) * 4096 * parts);
     k_gram_mfma<<<parts, BS, 0, ctx->stream>>>(n, ka, kb, X, x_rs, x_cs, Y, y_rs, y_cs,
                                                 ctx->gram_part.as<double>(), rpb);
     k_gram_final<<<(ka * kb + BS - 1) / BS, BS, 0, ctx->stream>>>(ctx->gram_part.as<double>(),
@@ -993,7 +993,7 @@ void chol_small_dev(mm_ctx *ctx, int k, const double *E, double *Lc, int *flag) 
 void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c) {
     const int64_t n = 3 * (int64_t)M->n_obs;
     const int k = M->k;
-    ctx->coef_g.alloc(sizeof(double) * 64 * 64);
+    ws_alloc(ctx, ctx->coef_g, sizeof(double) * 64 * 64);
     double *g = ctx->coef_g.as<double>();
     if (nrhs == 1) {
         gemv_t(ctx, n, k, M->Z.as<double>(), v, g);
@@ -1010,7 +1010,7 @@ void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, 
     Scope sc(ctx->prof, ctx->stream, "precond");
     const int64_t n = 3 * (int64_t)M->n_obs;
     const int k = M->k;
-    ctx->scal.alloc(sizeof(double) * 64 * 64 + 4096);
+    ws_alloc(ctx, ctx->scal, sizeof(double) * 64 * 64 + 4096);
     double *c = ctx->scal.as<double>();
     m2l_coef_dev(ctx, M, nrhs, v, c);
     const int parts = partial ? n_part : reduction_parts(n);

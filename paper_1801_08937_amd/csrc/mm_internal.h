@@ -106,11 +106,24 @@ struct mm_ctx {
     mm::DBuf scal;                 // small device scalars
     mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
     mm::DBuf xpack;                // map packed as (I, Q, U, 0) records for P
+    mm::DBuf pt_part;              // per-segment partial maps of the sliced P^T
+    // Bumped whenever one of the workspaces above is reallocated: captured
+    // graphs hold their addresses and are re-captured when it changes.
+    uint64_t ws_gen = 0;
     hipStream_t cap = nullptr;     // private stream for graph capture
     double *pinned = nullptr;      // host pinned scratch (scalar readback)
     size_t pinned_bytes = 0;
     int n_cu = 256;
 };
+
+namespace mm {
+// Grow a context workspace, recording the reallocation.
+inline void ws_alloc(mm_ctx *ctx, DBuf &b, size_t bytes) {
+    if (b.ptr && bytes <= b.bytes) return;
+    b.alloc(bytes);
+    ++ctx->ws_gen;
+}
+}  // namespace mm
 
 struct mm_pointing {
     int64_t n_samp = 0;
@@ -125,6 +138,16 @@ struct mm_pointing {
     mm::DBuf seg_order;
     int32_t grid_width = 0;
     int32_t p_blocks[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned P grid per log2(nrhs); 0 = default
+    // Sliced single-column P^T: observed pixels in slices of 64 (one pixel per
+    // lane; neighbours on the map when a grid is set), the samples cut into
+    // sl_S equal time segments.  Wave (s, g) walks its lanes' entries of
+    // segment s in time order from sl_perm / sl_w, stored interleaved (entry k
+    // of lane l at sl_base[s G + g] + 64 k + l, padding t = -1, w = 0).
+    int32_t sl_G = 0, sl_S = 0;
+    mm::DBuf sl_pix;   // int32[G * 64] compact pixel per lane, -1 past n_obs
+    mm::DBuf sl_base;  // int64[G * S + 1] entry offsets, segment-major
+    mm::DBuf sl_perm;  // int32 sample index per entry
+    mm::DBuf sl_w;     // weights per entry (TOD precision)
 };
 
 struct mm_noise {
@@ -171,6 +194,9 @@ namespace mm {
 void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, const double *psi,
                            int32_t min_hits);
 void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_t tile);
+// (Re)build the sliced P^T layout; width > 0 groups 8 x 8 pixel blocks of a
+// row-major grid of that width into slices, width 0 takes ascending pixels.
+void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width);
 
 // tod_ops.hip
 void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y);

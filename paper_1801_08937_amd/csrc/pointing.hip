@@ -110,6 +110,84 @@ __global__ void k_tile_keys(const int32_t *__restrict__ obs_pix, int32_t n_obs, 
     vals[c] = c;
 }
 
+// Sliced P^T layout.  Lane (g, l) finds, by binary search in its pixel's
+// time-sorted list perm[off[c], off[c+1]), where each time segment
+// [n s / S, n (s+1) / S) starts; cnt / start are stored per (s G + g, l).
+__global__ void k_sl_bounds(const int32_t *__restrict__ sl_pix, int32_t G, int32_t S,
+                            int64_t n_samp, const int32_t *__restrict__ off,
+                            const int32_t *__restrict__ perm, int32_t *__restrict__ cnt,
+                            int32_t *__restrict__ start) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= (int64_t)G * 64) return;
+    const int64_t g = i >> 6, l = i & 63;
+    const int32_t c = sl_pix[i];
+    int32_t prev = c >= 0 ? off[c] : 0;
+    const int32_t end = c >= 0 ? off[c + 1] : 0;
+    for (int32_t sg = 0; sg < S; ++sg) {
+        int32_t hi = end;
+        if (sg + 1 < S) {
+            const int64_t T = n_samp * (sg + 1) / S;
+            int32_t lo = prev;
+            hi = end;
+            while (lo < hi) {  // first entry with perm >= T
+                const int32_t mid = lo + ((hi - lo) >> 1);
+                if (perm[mid] < T)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+        }
+        const int64_t o = ((int64_t)sg * G + g) * 64 + l;
+        cnt[o] = hi - prev;
+        start[o] = prev;
+        prev = hi;
+    }
+}
+
+// sizes[w] = 64 x (largest lane count of wave w); sizes[n_waves] = 0.
+__global__ void k_sl_width(const int32_t *__restrict__ cnt, int64_t n_waves,
+                           int64_t *__restrict__ sizes) {
+    const int64_t w = ((int64_t)blockIdx.x * BS + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w > n_waves) return;
+    if (w == n_waves) {
+        if (lane == 0) sizes[w] = 0;
+        return;
+    }
+    int32_t m = cnt[w * 64 + lane];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, __shfl_xor(m, d));
+    if (lane == 0) sizes[w] = 64 * (int64_t)m;
+}
+
+template <typename T2>
+__global__ void k_sl_fill(const int64_t *__restrict__ base, const int32_t *__restrict__ cnt,
+                          const int32_t *__restrict__ start, const int32_t *__restrict__ perm,
+                          const T2 *__restrict__ ws, int64_t n_waves,
+                          int32_t *__restrict__ sl_perm, T2 *__restrict__ sl_w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * BS) >> 6;
+    for (int64_t w = ((int64_t)blockIdx.x * BS + threadIdx.x) >> 6; w < n_waves; w += nw) {
+        const int64_t b0 = base[w];
+        const int64_t W = (base[w + 1] - b0) >> 6;
+        const int32_t c = cnt[w * 64 + lane];
+        const int32_t st = start[w * 64 + lane];
+        for (int64_t k = 0; k < W; ++k) {
+            const int64_t idx = b0 + 64 * k + lane;
+            if (k < c) {
+                sl_perm[idx] = perm[st + k];
+                sl_w[idx] = ws[st + k];
+            } else {
+                T2 zero;
+                zero.x = 0;
+                zero.y = 0;
+                sl_perm[idx] = -1;
+                sl_w[idx] = zero;
+            }
+        }
+    }
+}
+
 int grid_for(int64_t n, int max_blocks = 8192) {
     int64_t g = (n + BS - 1) / BS;
     if (g > max_blocks) g = max_blocks;
@@ -138,6 +216,102 @@ void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_
                                      vals.as<int32_t>(), p->seg_order.as<int32_t>(),
                                      (size_t)n_obs, 0u, 64u, s));
     MM_HIP(hipStreamSynchronize(s));
+}
+
+// Time segments for the sliced P^T: enough (segment, slice) waves to fill
+// the device (8,192 = 32 per CU on 256 CUs) with at least 32 entries per lane
+// and segment on average; a fixed target, so the summation order (and the
+// bits of the result) does not depend on the device.
+static int32_t slice_segments(int64_t n_valid, int32_t n_obs, int32_t G) {
+    int64_t S = 8192 / G;
+    if (S > 64) S = 64;
+    const int64_t cap = n_obs > 0 ? n_valid / n_obs / 32 : 0;
+    if (S > cap) S = cap;
+    return (int32_t)(S < 1 ? 1 : S);
+}
+
+void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
+    hipStream_t s = ctx->stream;
+    p->sl_G = p->sl_S = 0;
+    p->sl_pix.release();
+    p->sl_base.release();
+    p->sl_perm.release();
+    p->sl_w.release();
+    const int32_t n_obs = p->n_obs;
+    if (n_obs == 0 || p->n_valid == 0) return;
+    const int32_t G = (n_obs + 63) / 64;
+    const int32_t S = slice_segments(p->n_valid, n_obs, G);
+    // below ~2,048 waves the one-wave-per-pixel kernel is the faster one
+    if ((int64_t)G * S < 2048) return;
+
+    p->sl_pix.alloc(sizeof(int32_t) * (size_t)G * 64);
+    MM_HIP(hipMemsetAsync(p->sl_pix.ptr, 0xff, sizeof(int32_t) * (size_t)G * 64, s));
+    if (width > 0) {
+        DBuf keys, vals, ko;
+        keys.alloc(sizeof(uint64_t) * n_obs);
+        vals.alloc(sizeof(int32_t) * n_obs);
+        ko.alloc(sizeof(uint64_t) * n_obs);
+        k_tile_keys<<<(n_obs + BS - 1) / BS, BS, 0, s>>>(p->obs_pix.as<int32_t>(), n_obs, width, 8,
+                                                         keys.as<uint64_t>(), vals.as<int32_t>());
+        size_t tb = 0;
+        MM_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
+                                         vals.as<int32_t>(), p->sl_pix.as<int32_t>(),
+                                         (size_t)n_obs, 0u, 64u, s));
+        DBuf tmp;
+        tmp.alloc(tb + 16);
+        MM_HIP(rocprim::radix_sort_pairs(tmp.ptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
+                                         vals.as<int32_t>(), p->sl_pix.as<int32_t>(),
+                                         (size_t)n_obs, 0u, 64u, s));
+        MM_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<int32_t> id(n_obs);
+        for (int32_t c = 0; c < n_obs; ++c) id[c] = c;
+        MM_HIP(hipMemcpyAsync(p->sl_pix.ptr, id.data(), sizeof(int32_t) * n_obs,
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipStreamSynchronize(s));
+    }
+
+    const int64_t n_waves = (int64_t)G * S;
+    DBuf cnt, start, sizes, tmp;
+    cnt.alloc(sizeof(int32_t) * n_waves * 64);
+    start.alloc(sizeof(int32_t) * n_waves * 64);
+    sizes.alloc(sizeof(int64_t) * (n_waves + 1));
+    p->sl_base.alloc(sizeof(int64_t) * (n_waves + 1));
+    k_sl_bounds<<<(unsigned)((G * 64 + BS - 1) / BS), BS, 0, s>>>(
+        p->sl_pix.as<int32_t>(), G, S, p->n_samp, p->off.as<int32_t>(), p->perm.as<int32_t>(),
+        cnt.as<int32_t>(), start.as<int32_t>());
+    k_sl_width<<<(unsigned)((n_waves + 1) * 64 / BS + 1), BS, 0, s>>>(cnt.as<int32_t>(), n_waves,
+                                                                      sizes.as<int64_t>());
+    size_t tb = 0;
+    MM_HIP(rocprim::exclusive_scan(nullptr, tb, sizes.as<int64_t>(), p->sl_base.as<int64_t>(),
+                                   (int64_t)0, (size_t)(n_waves + 1), rocprim::plus<int64_t>(),
+                                   s));
+    tmp.alloc(tb + 16);
+    MM_HIP(rocprim::exclusive_scan(tmp.ptr, tb, sizes.as<int64_t>(), p->sl_base.as<int64_t>(),
+                                   (int64_t)0, (size_t)(n_waves + 1), rocprim::plus<int64_t>(),
+                                   s));
+    int64_t total = 0;
+    MM_HIP(hipMemcpyAsync(&total, p->sl_base.as<int64_t>() + n_waves, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    const bool f32 = p->prec == MM_F32;
+    p->sl_perm.alloc(sizeof(int32_t) * (size_t)total);
+    p->sl_w.alloc((f32 ? sizeof(float2) : sizeof(double2)) * (size_t)total);
+    const unsigned fb = (unsigned)std::min<int64_t>((n_waves * 64 + BS - 1) / BS, 16384);
+    if (f32)
+        k_sl_fill<float2><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
+                                            start.as<int32_t>(), p->perm.as<int32_t>(),
+                                            p->ws.as<float2>(), n_waves, p->sl_perm.as<int32_t>(),
+                                            p->sl_w.as<float2>());
+    else
+        k_sl_fill<double2><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
+                                             start.as<int32_t>(), p->perm.as<int32_t>(),
+                                             p->ws.as<double2>(), n_waves,
+                                             p->sl_perm.as<int32_t>(), p->sl_w.as<double2>());
+    MM_HIP(hipGetLastError());
+    MM_HIP(hipStreamSynchronize(s));
+    p->sl_G = G;
+    p->sl_S = S;
 }
 
 void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, const double *psi,
@@ -248,6 +422,7 @@ void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, cons
     int32_t mx = 0;
     for (int32_t c = 0; c < n_obs; ++c) mx = std::max(mx, hoff[c + 1] - hoff[c]);
     p->max_seg = mx;
+    pointing_slices_device(ctx, p, 0);
 }
 
 }  // namespace mm

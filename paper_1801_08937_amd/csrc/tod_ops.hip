@@ -172,6 +172,78 @@ __global__ void __launch_bounds__(BS) k_apply_PT(const int32_t *__restrict__ off
     }
 }
 
+// Sliced single-column P^T.  Wave w = s G + g (remapped so that each XCD takes
+// a contiguous range of w) owns 64 pixels (one per lane) and time segment s;
+// every lane walks its pixel's entries of that segment in time order and
+// accumulates in registers.  Lanes hold neighbouring pixels, and all waves
+// are resident together, so the whole grid advances through the TOD at a
+// similar pace and the lines of z it gathers are shared in L2 and the
+// Infinity Cache instead of re-read from HBM.  Partial maps per segment go to
+// part[s][3 c + a] (or straight to x when S = 1).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ base,
+                                                    const int32_t *__restrict__ sl_perm,
+                                                    const typename Vec2<T>::type *__restrict__ sl_w,
+                                                    const int32_t *__restrict__ sl_pix, int32_t G,
+                                                    int32_t S, int32_t n_obs,
+                                                    const T *__restrict__ z,
+                                                    double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t w = blk * (BS / 64) + (threadIdx.x >> 6);
+    if (w >= (int64_t)G * S) return;
+    const int32_t sg = (int32_t)(w / G), g = (int32_t)(w % G);
+    const int64_t b0 = base[w];
+    const int64_t W = (base[w + 1] - b0) >> 6;
+    const int32_t *pp = sl_perm + b0 + lane;
+    const auto *wp = sl_w + b0 + lane;
+    T s0 = 0, s1 = 0, s2 = 0;
+    int64_t k = 0;
+    for (; k + 3 < W; k += 4) {
+        int32_t tt[4];
+        typename Vec2<T>::type ww[4];
+        T zz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tt[q] = pp[64 * (k + q)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ww[q] = wp[64 * (k + q)];
+            zz[q] = tt[q] >= 0 ? z[tt[q]] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            s0 += zz[q];
+            s1 += ww[q].x * zz[q];
+            s2 += ww[q].y * zz[q];
+        }
+    }
+    for (; k < W; ++k) {
+        const int32_t tq = pp[64 * k];
+        const auto wq = wp[64 * k];
+        const T zq = tq >= 0 ? z[tq] : (T)0;
+        s0 += zq;
+        s1 += wq.x * zq;
+        s2 += wq.y * zq;
+    }
+    const int32_t c = sl_pix[(int64_t)g * 64 + lane];
+    if (c < 0) return;
+    double *o = out + ((int64_t)sg * n_obs + c) * 3;
+    o[0] = (double)s0;
+    o[1] = (double)s1;
+    o[2] = (double)s2;
+}
+
+// x[e] = part[0][e] + part[1][e] + ... in segment order.
+__global__ void __launch_bounds__(BS) k_pt_sum_parts(const double *__restrict__ part, int32_t S,
+                                                     int64_t n3, double *__restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n3;
+         e += (int64_t)gridDim.x * BS) {
+        double acc = part[e];
+        for (int32_t sg = 1; sg < S; ++sg) acc += part[sg * n3 + e];
+        x[e] = acc;
+    }
+}
+
 // Direct banded Toeplitz: block (tile, part) computes outputs
 // t in [t0 + part*TL/R, t0 + (part+1)*TL/R) of one interval for all R columns.
 // The input window [t - lambda, t + lambda] (clipped to the interval) is
@@ -299,7 +371,7 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
     Scope sc(ctx->prof, ctx->stream, "P");
     const int64_t n = p->n_samp;
     if (nrhs == 1) {
-        ctx->xpack.alloc(sizeof(double2) * 2 * (size_t)(p->n_obs > 0 ? p->n_obs : 1));
+        ws_alloc(ctx, ctx->xpack, sizeof(double2) * 2 * (size_t)(p->n_obs > 0 ? p->n_obs : 1));
         k_pack_map<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(x, p->n_obs,
                                                                     ctx->xpack.as<double2>());
         const int tuned = p->p_blocks[0];
@@ -335,6 +407,29 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
 void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x) {
     Scope sc(ctx->prof, ctx->stream, "PT");
     if (p->n_obs == 0) return;
+    if (nrhs == 1 && p->sl_G > 0) {
+        const int32_t G = p->sl_G, S = p->sl_S;
+        const int64_t n3 = 3 * (int64_t)p->n_obs;
+        double *out = x;
+        if (S > 1) {
+            ws_alloc(ctx, ctx->pt_part, sizeof(double) * (size_t)(n3 * S));
+            out = ctx->pt_part.as<double>();
+        }
+        int64_t nb = ((int64_t)G * S + 3) / 4;
+        if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
+        if (p->prec == MM_F32)
+            k_apply_PT_sl<float><<<(unsigned)nb, BS, 0, ctx->stream>>>(
+                p->sl_base.as<int64_t>(), p->sl_perm.as<int32_t>(), p->sl_w.as<float2>(),
+                p->sl_pix.as<int32_t>(), G, S, p->n_obs, static_cast<const float *>(z), out);
+        else
+            k_apply_PT_sl<double><<<(unsigned)nb, BS, 0, ctx->stream>>>(
+                p->sl_base.as<int64_t>(), p->sl_perm.as<int32_t>(), p->sl_w.as<double2>(),
+                p->sl_pix.as<int32_t>(), G, S, p->n_obs, static_cast<const double *>(z), out);
+        if (S > 1)
+            k_pt_sum_parts<<<grid_for(n3, 2048), BS, 0, ctx->stream>>>(out, S, n3, x);
+        MM_HIP(hipGetLastError());
+        return;
+    }
     int64_t nb = (p->n_obs + 3) / 4;
     if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
     const int32_t *order = p->seg_order.ptr ? p->seg_order.as<int32_t>() : nullptr;

@@ -70,12 +70,14 @@ def lib() -> C.CDLL:
             "mm_last_error": (C.c_char_p, [P]),
             "mm_pointing_build": (C.c_int, [P, I64, I32, P, P, I32, C.c_int, PP]),
             "mm_pointing_counts": (C.c_int, [P, C.POINTER(I32), C.POINTER(I64)]),
+            "mm_pointing_pt_layout": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
             "mm_pointing_set_grid": (C.c_int, [P, P, I32]),
             "mm_pointing_hits": (C.c_int, [P, P, P, P]),
             "mm_pointing_export": (C.c_int, [P, P, P, P, P]),
             "mm_pointing_destroy": (None, [P]),
             "mm_noise_build": (C.c_int, [P, I32, P, P, I32, I32, P, C.c_int, C.c_int, PP]),
             "mm_noise_method_used": (C.c_int, [P, C.POINTER(C.c_int)]),
+            "mm_noise_fft_block": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "mm_noise_apply": (C.c_int, [P, P, I32, P, P]),
             "mm_noise_destroy": (None, [P]),
             "mm_apply_P": (C.c_int, [P, P, I32, P, P]),
@@ -396,6 +398,13 @@ class Pointing(_Handle):
         self.ctx._check(lib().mm_pointing_set_grid(self.ctx.h, self.h, width),
                         "mm_pointing_set_grid")
 
+    def pt_layout(self):
+        """(slices, segments) of the sliced single-column P^T; (0, 0) when the
+        one-wave-per-pixel form is used."""
+        g, s = C.c_int32(0), C.c_int32(0)
+        lib().mm_pointing_pt_layout(self.h, C.byref(g), C.byref(s))
+        return g.value, s.value
+
     def hits(self):
         import torch
         dev = self.ctx.torch_device
@@ -425,6 +434,9 @@ class Noise(_Handle):
         m = C.c_int()
         lib().mm_noise_method_used(h, C.byref(m))
         self.method = m.value
+        nf, nv = C.c_int32(0), C.c_int32(0)
+        lib().mm_noise_fft_block(h, C.byref(nf), C.byref(nv))
+        self.fft_n, self.fft_valid = nf.value, nv.value
 
 
 class Precond(_Handle):

@@ -537,3 +537,64 @@ def test_autotune_keeps_results_bitwise(ctx):
     assert len(rep1) >= 5 and any(r[0] == "band" for r in rep1)
     assert torch.equal(a1, ctx.apply_A(lp, ln, x[: op.n]))
     assert torch.equal(a8, ctx.apply_A(lp, ln, x, nrhs=8))
+
+
+def test_PT_sliced_layout_parity_and_order(ctx):
+    """The sliced single-column P^T (one pixel per lane, time segments summed
+    in order) on a cross-linked scan: parity with the oracle,
+    bitwise independence of the grid grouping, agreement with the
+    one-wave-per-pixel form used for several columns, and the FP32 form
+    (2^23 samples, 16,384 pixels: 256 slices x 14 segments)."""
+    import torch
+    p = synth.config2(n_side=128, grid=(4, 4), samp_per_det=1 << 19, L=1 << 15, half_bw=1024)
+    lp, ln, op, on = build_both(ctx, p, method=2)
+    G, S = lp.pt_layout()
+    assert G == (op.n_obs + 63) // 64 and S > 1 and G * S >= 2048
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal(op.n_samp)
+    a = ctx.apply_PT(lp, dev(y))
+    ref = O.apply_PT(op, y)
+    assert maxrel(host(a), ref) <= TOL_OP
+    lp.set_grid(p.n_side)
+    assert lp.pt_layout() == (G, S)
+    assert torch.equal(a, ctx.apply_PT(lp, dev(y)))
+    Y2 = np.stack([y, rng.standard_normal(op.n_samp)], axis=1)
+    a2 = host(ctx.apply_PT(lp, dev(Y2.reshape(-1)), nrhs=2)).reshape(-1, 2)
+    assert maxrel(a2[:, 0], host(a)) <= TOL_OP
+    x = rng.standard_normal(op.n)
+    assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x, "fft")) <= 1e-11
+    lp32, _, _, _ = build_both(ctx, p, prec=1, method=2)
+    assert lp32.pt_layout() == (G, S)
+    a32 = host(ctx.apply_PT(lp32, dev(y.astype(np.float32))))
+    assert rel(a32, ref) <= 1e-5
+
+
+def test_graph_recaptured_after_workspace_growth(ctx):
+    """A session's captured PCG graph is captured again when the context's
+    workspaces are reallocated by a larger problem in between; the result is
+    bitwise the graph-free one."""
+    import torch
+    from paper_1801_08937_amd import mapmaker as mm
+    p = synth.config1()
+    c2 = mm.Context(0)
+    try:
+        lp, ln, op, on = build_both(c2, p)
+        M = c2.mbd(lp, ln)
+        b = c2.rhs(lp, ln, dev(p.tod))
+        ref = c2.pcg_session(lp, ln, M, 1)
+        ref.start(0, b, 0.0, 10 ** 6)
+        ref.iterate(30)
+        x_ref = ref.finish(0)
+        S = c2.pcg_session(lp, ln, M, 1)
+        S.use_graph(5)
+        S.start(0, b, 0.0, 10 ** 6)
+        S.iterate(1)   # eager (warms the workspaces)
+        S.iterate(10)  # captured, replayed twice
+        big = synth.config2(n_side=64, grid=(4, 2), samp_per_det=1 << 16, L=1 << 14, half_bw=256)
+        lb, lnb, _, _ = build_both(c2, big)
+        c2.apply_A(lb, lnb, dev(np.ones(lb.n)))
+        torch.cuda.synchronize()
+        S.iterate(19)  # stale graph dropped, captured again
+        assert torch.equal(S.finish(0), x_ref)
+    finally:
+        c2.close()
