@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5"], default=None,
+                    help="measure one form (latency, FP32, batched, serving) instead")
+    ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -138,6 +141,15 @@ def main():
 
     import synth
     from paper_1801_08937_amd import mapmaker as mm
+
+    if args.form:
+        torch.cuda.init()
+        ctx = mm.Context(0)
+        fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4,
+              "c5": lambda m, c: form_c5(m, c, n_requests=args.requests)}[args.form]
+        print(json.dumps(fn(mm, ctx)), flush=True)
+        ctx.close()
+        return
 
     t = time.perf_counter()
     if args.workload == "c2":
@@ -275,6 +287,271 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+
+
+# ------------------------------------------------------------------ forms
+# `--form c1|c3|c4|c5` prints one JSON line for that form of the solver
+# instead of the default line: small-problem latency (config 1), the FP32
+# precision form, the 64-column batched form and the serving form, each next
+# to the plain FP64 solver on the same inputs.
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _wall(fn, reps=1):
+    """(result of the last call, median wall seconds over reps calls)."""
+    ts, r = [], None
+    for _ in range(reps):
+        _sync()
+        t0 = time.perf_counter()
+        r = fn()
+        _sync()
+        ts.append(time.perf_counter() - t0)
+    return r, float(np.median(ts))
+
+
+def form_c1(mm, ctx):
+    """Config 1 (32x32 patch, 2 x 65,536 samples, lambda 32): everything sits
+    in cache, so this is a latency figure: A apply, one PCG iteration eager
+    and graph-replayed, and time to 1e-8 for M_BD and M_2l (k = 32)."""
+    import torch
+    import synth
+    p = synth.config1()
+    dev = torch.device("cuda", 0)
+    lp = ctx.pointing(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.psi).to(dev),
+                      p.n_pix_total, p.min_hits)
+    ln = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw)
+    Mbd = ctx.mbd(lp, ln)
+    b = ctx.rhs(lp, ln, torch.from_numpy(p.tod).to(dev))
+    x = torch.randn(lp.n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        ctx.apply_A(lp, ln, x, y)
+    _sync()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(ctx.stream)
+    for _ in range(200):
+        ctx.apply_A(lp, ln, x, y)
+    ev[1].record(ctx.stream)
+    ev[1].synchronize()
+    a_us = ev[0].elapsed_time(ev[1]) / 200 * 1e3
+    (M2, t_m2l) = _wall(lambda: ctx.defl_build(lp, ln, Mbd, b, k=32, eps_arn=1e-8, m_max=256))
+    out = {"a_apply_us": a_us}
+    for name, M in (("mbd", Mbd), ("m2l", M2)):
+        for graph in (False, True):
+            (r, t) = _wall(lambda: ctx.solve(lp, ln, M, b, tol=1e-8, max_iter=2000,
+                                             check_every=8, history=False, graph=graph), reps=5)
+            _, info = r
+            out[f"{name}_{'graph' if graph else 'eager'}"] = {
+                "iters": info["iters"], "converged": info["converged"],
+                "rel_res_true": info["rel_res_true"], "solve_ms": t * 1e3,
+                "us_per_iter": t * 1e6 / max(info["iters"], 1)}
+    out["m2l_setup_ms"] = t_m2l * 1e3
+    return {"form": "c1", "workload": "config1: 32x32 patch, 2 det x 65,536 samples, "
+            "lambda 32 direct band, FP64, tol 1e-8", **out}
+
+
+def form_c3(mm, ctx):
+    """Config 1 in the FP32 form (TOD, weights and N^-1 in FP32; dots, M_BD
+    inverses and the coarse solve in FP64): time to a 1e-6 and a 1e-8 FP64
+    true residual next to the FP64 solver, and the map error against the FP64
+    oracle's solution."""
+    import torch
+    import synth
+    import oracle as O
+    p = synth.config1()
+    dev = torch.device("cuda", 0)
+    pix, psi = torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.psi).to(dev)
+    tod = torch.from_numpy(p.tod).to(dev)
+    lp64 = ctx.pointing(pix, psi, p.n_pix_total, p.min_hits)
+    ln64 = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw)
+    lp32 = ctx.pointing(pix, psi, p.n_pix_total, p.min_hits, prec=1)
+    ln32 = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw, prec=1)
+    b64 = ctx.rhs(lp64, ln64, tod)
+    b32 = ctx.rhs(lp32, ln32, tod.float())
+    M64, M32 = ctx.mbd(lp64, ln64), ctx.mbd(lp32, ln32)
+    op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    on = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    Mo = O.mbd_build(op, on)
+    x_or, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(Mo, v),
+                    O.rhs(op, on, p.tod), tol=1e-12, max_iter=5000)
+    bn = float(torch.linalg.norm(b64))
+
+    def true_res(xs):
+        r = b64 - ctx.apply_A(lp64, ln64, xs)
+        return float(torch.linalg.norm(r)) / bn
+
+    out = {}
+    for tol in (1e-6, 1e-8):
+        for name, lp, ln, M, b in (("fp64", lp64, ln64, M64, b64), ("fp32", lp32, ln32, M32, b32)):
+            (r, t) = _wall(lambda: ctx.solve(lp, ln, M, b, tol=tol, max_iter=3000, check_every=8,
+                                             history=False), reps=5)
+            xs, info = r
+            xh = xs.cpu().numpy()
+            out[f"{name}_tol{tol:g}"] = {
+                "iters": info["iters"], "converged": info["converged"], "solve_ms": t * 1e3,
+                "rel_res_own": info["rel_res_true"], "rel_res_fp64": true_res(xs),
+                "map_rel_err_vs_oracle": float(np.linalg.norm(xh - x_or) / np.linalg.norm(x_or))}
+    return {"form": "c3", "workload": "config1 in FP32 (TOD, weights, N^-1 FP32; dots, M_BD, "
+            "coarse FP64), M_BD, tol 1e-6 and 1e-8", **out}
+
+
+def form_c4(mm, ctx):
+    """64 Monte Carlo realizations on config 1's pointing: one 64-column solve
+    (lockstep columns and block CG, eager and graph-replayed) against 64
+    sequential single-column solves; M_BD and M_2l (Z from realization 0);
+    FP64 and FP32."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    reals = [synth.config4_realization(r) for r in range(64)]
+    p = reals[0]
+    pix, psi = torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.psi).to(dev)
+    T = np.stack([q.tod for q in reals], axis=1)  # [n_samp][64]
+    out = {}
+    for prec in (0, 1):
+        tag = "fp64" if prec == 0 else "fp32"
+        lp = ctx.pointing(pix, psi, p.n_pix_total, p.min_hits, prec=prec)
+        ln = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw, prec=prec)
+        Td = torch.from_numpy(T).to(dev)
+        if prec == 1:
+            Td = Td.float()
+        B = ctx.rhs(lp, ln, Td.reshape(-1), nrhs=64)
+        Mbd = ctx.mbd(lp, ln)
+        b0 = B.view(-1, 64)[:, 0].contiguous()
+        M2 = ctx.defl_build(lp, ln, Mbd, b0, k=32, eps_arn=1e-8, m_max=256)
+        cols = [B.view(-1, 64)[:, c].contiguous() for c in range(64)]
+        for mname, M in (("mbd", Mbd), ("m2l", M2)):
+            res = {}
+            for mode, kw in (("lockstep", {}), ("lockstep_graph", {"graph": True}),
+                             ("block", {"block": True})):
+                (r, t) = _wall(lambda: ctx.solve(lp, ln, M, B, tol=1e-8, max_iter=3000, nrhs=64,
+                                                 check_every=8, history=False, **kw), reps=3)
+                _, infos = r
+                infos = infos if isinstance(infos, list) else [infos]
+                res[mode] = {"solve_ms": t * 1e3, "max_iters": max(i["iters"] for i in infos),
+                             "all_converged": all(i["converged"] for i in infos)}
+
+            def seq():
+                its = []
+                for c in range(64):
+                    _, inf = ctx.solve(lp, ln, M, cols[c], tol=1e-8, max_iter=3000,
+                                       check_every=8, history=False)
+                    its.append(inf["iters"])
+                return its
+            (its, t) = _wall(seq)
+            res["sequential_64"] = {"solve_ms": t * 1e3, "max_iters": max(its),
+                                    "mean_iters": float(np.mean(its))}
+            out[f"{tag}_{mname}"] = res
+    return {"form": "c4", "workload": "64 realizations (CMB-like sky + noise each) on config 1's "
+            "pointing and noise model, tol 1e-8", **out}
+
+
+def form_c5(mm, ctx, n_requests=200, slots=2):
+    """Serving: a Poisson trace (4 requests/s) over four recurring strategies
+    of uneven size (2^20 to 2^27 samples, lambda 1,024 to 8,192), tolerance
+    1e-6 or 1e-8.  Served by mm_server_* (cached pointing, M_BD and M_2l per
+    strategy, continuous batching over `slots` columns) and, as the baseline,
+    one request at a time with plain FP64 M_BD and no cache (pointing, noise
+    model and M_BD built per request)."""
+    import torch
+    import synth
+    import synth.gpu as sg
+    from paper_1801_08937_amd import serving
+    dev = torch.device("cuda", 0)
+    arrivals, strat, tol = synth.poisson_arrivals(n_requests, 4.0, seed=0)
+    S = []
+    for s in range(4):
+        t0 = time.perf_counter()
+        p = synth.serve_strategy(s, 0, noiseless=True)
+        n_det = synth.SERVE_STRATEGIES[s][1][0] * synth.SERVE_STRATEGIES[s][1][1]
+        fk = synth.rng_for(50 + s, 0, synth.STREAM_FKNEE).uniform(0.05, 1.0, n_det)
+        S.append({"p": p, "pix": torch.from_numpy(p.pix).to(dev),
+                  "psi": torch.from_numpy(p.psi).to(dev), "fk": fk[p.filter_id]})
+        p.pix = p.psi = p.tod = None
+        log(f"[bench] strategy {s}: {S[-1]['pix'].numel()} samples "
+            f"({time.perf_counter() - t0:.1f} s)")
+
+    def make_tod(i):
+        s = int(strat[i])
+        st = S[s]
+        sky = synth.white_sky(synth.rng_for(50 + s, 1000 + i, synth.STREAM_SIGNAL),
+                              st["p"].n_pix_total)
+        d = sg.signal(st["pix"], st["psi"], sky, dev)
+        d += sg.noise_1f(50 + s, 1000 + i, synth.STREAM_NOISE, 1 << 16, st["fk"], dev)
+        return d
+
+    n_obs = []
+    for s in range(4):
+        lp = ctx.pointing(S[s]["pix"], S[s]["psi"], S[s]["p"].n_pix_total, S[s]["p"].min_hits)
+        n_obs.append(lp.n)
+        lp.close() if hasattr(lp, "close") else None
+        del lp
+    # served
+    srv = mm.Server(0, hbm_budget_bytes=240 << 30, slots=slots, defl_k=32, iters_per_step=4)
+    t0 = time.perf_counter()
+    for s in range(4):
+        p = S[s]["p"]
+        srv.add_strategy(s, S[s]["pix"], S[s]["psi"], p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+    t_reg = time.perf_counter() - t0
+    xs_srv = {}
+
+    def req(i):
+        d = make_tod(i)
+        _sync()
+        x = torch.zeros(n_obs[int(strat[i])], dtype=torch.float64, device=dev)
+        xs_srv[i] = x
+        return int(strat[i]), d, x, float(tol[i])
+    log("[bench] serving trace ...")
+    infos, wall = serving.run_trace(srv, arrivals, req)
+    served = serving.latency_stats(infos, wall)
+    served["iters_mean"] = float(np.mean([d["iters"] for d in infos]))
+    served["register_s"] = t_reg
+    log(f"[bench] served: {served}")
+    srv.close()
+    # baseline: one at a time, FP64 M_BD, nothing cached
+    log("[bench] baseline trace ...")
+    lat, iters, diffs = [], [], []
+    t_start = time.perf_counter()
+    for i in range(n_requests):
+        now = time.perf_counter() - t_start
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        s = int(strat[i])
+        p = S[s]["p"]
+        tg = time.perf_counter()
+        d = make_tod(i)
+        _sync()
+        g = time.perf_counter() - tg
+        lp = ctx.pointing(S[s]["pix"], S[s]["psi"], p.n_pix_total, p.min_hits)
+        ln = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw)
+        M = ctx.mbd(lp, ln)
+        b = ctx.rhs(lp, ln, d)
+        x, info = ctx.solve(lp, ln, M, b, tol=float(tol[i]), max_iter=3000, check_every=4,
+                            history=False)
+        _sync()
+        done = time.perf_counter() - t_start
+        lat.append(done - arrivals[i] - g)
+        iters.append(info["iters"])
+        if i < 8:
+            xa = xs_srv[i]
+            diffs.append(float(torch.linalg.norm(xa - x) / torch.linalg.norm(x)))
+        del lp, ln, M, b, x, d
+    wall_b = time.perf_counter() - t_start
+    lat = np.array(lat)
+    base = {"n": n_requests, "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+            "solves_per_s": n_requests / wall_b, "wall_s": wall_b,
+            "iters_mean": float(np.mean(iters))}
+    log(f"[bench] baseline: {base}")
+    return {"form": "c5", "workload": "Poisson 4 req/s, 4 strategies: 64^2/16 det x 2^16 "
+            "(lambda 1024), 128^2/32 x 2^18 (2048), 256^2/64 x 2^20 (4096), 256^2/128 x 2^20 "
+            "(8192); tol 1e-6 or 1e-8; slots %d" % slots, "served": served,
+            "one_at_a_time_mbd_no_cache": base,
+            "served_vs_baseline_map_rel_diff_first8": diffs}
 
 
 if __name__ == "__main__":

@@ -132,6 +132,7 @@ struct mm_pointing {
     int64_t n_valid = 0;
     mm_precision prec = MM_F64;
     mm::DBuf hits, obs_pix, j, w, perm, ws, off;
+    mm::DBuf psi;  // f64[n_samp] angles (FP64 form only)
     int32_t max_seg = 0;
     // Order in which P^T visits the compact pixels (empty = ascending).  Each
     // pixel's own sum is independent of it; it only shapes cache locality.
@@ -147,7 +148,7 @@ struct mm_pointing {
     mm::DBuf sl_pix;   // int32[G * 64] compact pixel per lane, -1 past n_obs
     mm::DBuf sl_base;  // int64[G * S + 1] entry offsets, segment-major
     mm::DBuf sl_perm;  // int32 sample index per entry
-    mm::DBuf sl_w;     // weights per entry (TOD precision)
+    mm::DBuf sl_w;     // per entry: psi (FP64 form) or the weights (FP32 form)
 };
 
 struct mm_noise {

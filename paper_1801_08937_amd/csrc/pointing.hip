@@ -12,6 +12,7 @@
 #include <rocprim/device/device_scan.hpp>
 
 #include "mm_internal.h"
+#include "pol_weights.h"
 
 namespace mm {
 namespace {
@@ -79,7 +80,7 @@ __global__ void k_weights(const double *__restrict__ psi, int64_t n, T2 *__restr
     using T = decltype(T2::x);
     for (int64_t t = blockIdx.x * (int64_t)BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
         double s, c;
-        sincos(2.0 * psi[t], &s, &c);
+        pol_weights(psi[t], c, s);
         T2 v;
         v.x = (T)c;
         v.y = (T)s;
@@ -160,11 +161,27 @@ __global__ void k_sl_width(const int32_t *__restrict__ cnt, int64_t n_waves,
     if (lane == 0) sizes[w] = 64 * (int64_t)m;
 }
 
-template <typename T2>
+// Entries of wave w: lane l's k-th sample of its pixel in the segment (or
+// padding).  V is the per-entry weight record: the stored weights (FP32
+// form) or the angle psi gathered from time order (FP64 form, weights formed
+// on the fly).
+template <typename V>
+__device__ __forceinline__ V sl_value(const V *__restrict__ src, int64_t i, int32_t t) {
+    return src[i];
+}
+template <>
+__device__ __forceinline__ double sl_value<double>(const double *__restrict__ psi, int64_t,
+                                                   int32_t t) {
+    return psi[t];
+}
+__device__ __forceinline__ void sl_zero(float2 &v) { v = make_float2(0.f, 0.f); }
+__device__ __forceinline__ void sl_zero(double &v) { v = 0.0; }
+
+template <typename V>
 __global__ void k_sl_fill(const int64_t *__restrict__ base, const int32_t *__restrict__ cnt,
                           const int32_t *__restrict__ start, const int32_t *__restrict__ perm,
-                          const T2 *__restrict__ ws, int64_t n_waves,
-                          int32_t *__restrict__ sl_perm, T2 *__restrict__ sl_w) {
+                          const V *__restrict__ src, int64_t n_waves,
+                          int32_t *__restrict__ sl_perm, V *__restrict__ sl_w) {
     const int lane = threadIdx.x & 63;
     const int64_t nw = ((int64_t)gridDim.x * BS) >> 6;
     for (int64_t w = ((int64_t)blockIdx.x * BS + threadIdx.x) >> 6; w < n_waves; w += nw) {
@@ -175,12 +192,12 @@ __global__ void k_sl_fill(const int64_t *__restrict__ base, const int32_t *__res
         for (int64_t k = 0; k < W; ++k) {
             const int64_t idx = b0 + 64 * k + lane;
             if (k < c) {
-                sl_perm[idx] = perm[st + k];
-                sl_w[idx] = ws[st + k];
+                const int32_t t = perm[st + k];
+                sl_perm[idx] = t;
+                sl_w[idx] = sl_value<V>(src, st + k, t);
             } else {
-                T2 zero;
-                zero.x = 0;
-                zero.y = 0;
+                V zero;
+                sl_zero(zero);
                 sl_perm[idx] = -1;
                 sl_w[idx] = zero;
             }
@@ -296,7 +313,7 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     MM_HIP(hipStreamSynchronize(s));
     const bool f32 = p->prec == MM_F32;
     p->sl_perm.alloc(sizeof(int32_t) * (size_t)total);
-    p->sl_w.alloc((f32 ? sizeof(float2) : sizeof(double2)) * (size_t)total);
+    p->sl_w.alloc((f32 ? sizeof(float2) : sizeof(double)) * (size_t)total);
     const unsigned fb = (unsigned)std::min<int64_t>((n_waves * 64 + BS - 1) / BS, 16384);
     if (f32)
         k_sl_fill<float2><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
@@ -304,10 +321,10 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
                                             p->ws.as<float2>(), n_waves, p->sl_perm.as<int32_t>(),
                                             p->sl_w.as<float2>());
     else
-        k_sl_fill<double2><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
-                                             start.as<int32_t>(), p->perm.as<int32_t>(),
-                                             p->ws.as<double2>(), n_waves,
-                                             p->sl_perm.as<int32_t>(), p->sl_w.as<double2>());
+        k_sl_fill<double><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
+                                            start.as<int32_t>(), p->perm.as<int32_t>(),
+                                            p->psi.as<double>(), n_waves,
+                                            p->sl_perm.as<int32_t>(), p->sl_w.as<double>());
     MM_HIP(hipGetLastError());
     MM_HIP(hipStreamSynchronize(s));
     p->sl_G = G;
@@ -396,8 +413,14 @@ void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, cons
     vals.release();
     p->perm = std::move(vals_out);  // first n_valid entries are the permutation
 
-    // weights in time order and in pixel-sorted order
+    // weights in time order and in pixel-sorted order; the FP64 form also
+    // keeps the angles, from which its single-column P and P^T form the
+    // weights on the fly (8 bytes per sample read instead of 16)
     const bool f32 = p->prec == MM_F32;
+    if (!f32) {
+        p->psi.alloc(sizeof(double) * n);
+        MM_HIP(hipMemcpyAsync(p->psi.ptr, psi, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
     const size_t wsz = f32 ? sizeof(float2) : sizeof(double2);
     p->w.alloc(wsz * n);
     p->ws.alloc(wsz * (nv > 0 ? nv : 1));

@@ -11,6 +11,7 @@
 #include <functional>
 
 #include "mm_internal.h"
+#include "pol_weights.h"
 
 namespace mm {
 
@@ -110,6 +111,39 @@ __global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpi
     for (; t < n; t += step) y[t] = p_gather4<T>(jpix[t], w[t], x4);
 }
 
+// Single column, FP64: the weights are formed from the stored angles, so a
+// sample costs its pixel index and angle (12 bytes) instead of index and two
+// weights (20 bytes).
+__device__ __forceinline__ double p_gather_psi(int32_t j, double psi,
+                                               const double2 *__restrict__ x4) {
+    if (j < 0) return 0.0;
+    double c, s;
+    pol_weights(psi, c, s);
+    const double2 iq = x4[2 * (int64_t)j];
+    const double u = x4[2 * (int64_t)j + 1].x;
+    return iq.x + c * iq.y + s * u;
+}
+
+__global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__ jpix,
+                                                     const double *__restrict__ psi, int64_t n,
+                                                     const double2 *__restrict__ x4,
+                                                     double *__restrict__ y) {
+    const int64_t step = (int64_t)gridDim.x * BS;
+    int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    for (; t + 3 * step < n; t += 4 * step) {
+        int32_t j[4];
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            j[q] = jpix[t + q * step];
+            a[q] = psi[t + q * step];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[t + q * step] = p_gather_psi(j[q], a[q], x4);
+    }
+    for (; t < n; t += step) y[t] = p_gather_psi(jpix[t], psi[t], x4);
+}
+
 // Pixels are visited in the order `order` (NULL = ascending), e.g. square
 // tiles of the map, and each XCD takes a contiguous range of that order: the
 // pixels one XCD reduces together are neighbours, hit by the same stretches of
@@ -180,10 +214,25 @@ __global__ void __launch_bounds__(BS) k_apply_PT(const int32_t *__restrict__ off
 // similar pace and the lines of z it gathers are shared in L2 and the
 // Infinity Cache instead of re-read from HBM.  Partial maps per segment go to
 // part[s][3 c + a] (or straight to x when S = 1).
+// Weight record of an entry: FP64 stores the angle and forms the weights
+// here; FP32 stores the two weights.
+template <typename T> struct SlRec;
+template <> struct SlRec<double> {
+    using type = double;
+    __device__ static void weights(double psi, double &c, double &s) { pol_weights(psi, c, s); }
+};
+template <> struct SlRec<float> {
+    using type = float2;
+    __device__ static void weights(float2 w, float &c, float &s) {
+        c = w.x;
+        s = w.y;
+    }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ base,
                                                     const int32_t *__restrict__ sl_perm,
-                                                    const typename Vec2<T>::type *__restrict__ sl_w,
+                                                    const typename SlRec<T>::type *__restrict__ sl_w,
                                                     const int32_t *__restrict__ sl_pix, int32_t G,
                                                     int32_t S, int32_t n_obs,
                                                     const T *__restrict__ z,
@@ -201,7 +250,7 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
     int64_t k = 0;
     for (; k + 3 < W; k += 4) {
         int32_t tt[4];
-        typename Vec2<T>::type ww[4];
+        typename SlRec<T>::type ww[4];
         T zz[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) tt[q] = pp[64 * (k + q)];
@@ -212,18 +261,21 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            T c, sn;
+            SlRec<T>::weights(ww[q], c, sn);
             s0 += zz[q];
-            s1 += ww[q].x * zz[q];
-            s2 += ww[q].y * zz[q];
+            s1 += c * zz[q];
+            s2 += sn * zz[q];
         }
     }
     for (; k < W; ++k) {
         const int32_t tq = pp[64 * k];
-        const auto wq = wp[64 * k];
+        T c, sn;
+        SlRec<T>::weights(wp[64 * k], c, sn);
         const T zq = tq >= 0 ? z[tq] : (T)0;
         s0 += zq;
-        s1 += wq.x * zq;
-        s2 += wq.y * zq;
+        s1 += c * zq;
+        s2 += sn * zq;
     }
     const int32_t c = sl_pix[(int64_t)g * 64 + lane];
     if (c < 0) return;
@@ -381,10 +433,9 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
                                                             n, ctx->xpack.as<double2>(),
                                                             static_cast<float *>(y));
         else
-            k_apply_P1<double><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(),
-                                                             p->w.as<double2>(), n,
-                                                             ctx->xpack.as<double2>(),
-                                                             static_cast<double *>(y));
+            k_apply_P1_psi<<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), p->psi.as<double>(),
+                                                         n, ctx->xpack.as<double2>(),
+                                                         static_cast<double *>(y));
         MM_HIP(hipGetLastError());
         return;
     }
@@ -423,7 +474,7 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
                 p->sl_pix.as<int32_t>(), G, S, p->n_obs, static_cast<const float *>(z), out);
         else
             k_apply_PT_sl<double><<<(unsigned)nb, BS, 0, ctx->stream>>>(
-                p->sl_base.as<int64_t>(), p->sl_perm.as<int32_t>(), p->sl_w.as<double2>(),
+                p->sl_base.as<int64_t>(), p->sl_perm.as<int32_t>(), p->sl_w.as<double>(),
                 p->sl_pix.as<int32_t>(), G, S, p->n_obs, static_cast<const double *>(z), out);
         if (S > 1)
             k_pt_sum_parts<<<grid_for(n3, 2048), BS, 0, ctx->stream>>>(out, S, n3, x);

@@ -14,23 +14,29 @@ import numpy as np
 
 def run_trace(server, arrivals, requests, poll_sleep: float = 0.0):
     """Submit requests[i] = (strategy, tod, x_out, tol) at arrivals[i] seconds
-    after start, stepping the server in between.  Returns per-request info
-    dicts (with latency) and the wall time of the whole trace."""
+    after start, stepping the server in between.  `requests` may also be a
+    callable i -> request, called at the arrival (for data made on demand);
+    the time stream is released once the server has admitted the request.
+    Returns per-request info dicts (with latency) and the trace's wall time."""
     t0 = time.perf_counter()
     pending = list(range(len(arrivals)))
     ids = {}
+    live = {}
     done = {}
     while pending or len(done) < len(ids):
         now = time.perf_counter() - t0
         while pending and arrivals[pending[0]] <= now:
             i = pending.pop(0)
-            sid, tod, x_out, tol = requests[i]
+            sid, tod, x_out, tol = requests(i) if callable(requests) else requests[i]
             ids[i] = server.submit(sid, tod, x_out, tol=tol, max_iter=2000)
+            live[i] = tod
         running, queued = server.step()
         for i, rid in ids.items():
             if i in done:
                 continue
             info = server.poll(rid)
+            if info["state"] >= 1:
+                live.pop(i, None)
             if info["state"] >= 2:
                 done[i] = info
         if running == 0 and queued == 0 and pending and len(done) == len(ids):
