@@ -349,6 +349,27 @@ def form_c1(mm, ctx):
                 "rel_res_true": info["rel_res_true"], "solve_ms": t * 1e3,
                 "us_per_iter": t * 1e6 / max(info["iters"], 1)}
     out["m2l_setup_ms"] = t_m2l * 1e3
+    # steady-state cost of one iteration inside a session, eager and replayed
+    # from captured graphs of 10 iterations
+    for name, M in (("mbd", Mbd), ("m2l", M2)):
+        for graph in (False, True):
+            S = ctx.pcg_session(lp, ln, M, 1)
+            if graph:
+                S.use_graph(10)
+            S.start(0, b, 0.0, 10 ** 7)
+            S.iterate(1)
+            S.iterate(20)  # graph captured here
+            ts = []
+            for _ in range(5):
+                S.start(0, b, 0.0, 10 ** 7)
+                S.iterate(1)
+                (_, t) = _wall(lambda: S.iterate(30))
+                st, _, _ = S.poll()
+                assert st[0] == 1, "column left the running state during the timing"
+                ts.append(t)
+            out[f"{name}_session_us_per_iter_{'graph' if graph else 'eager'}"] = \
+                float(np.median(ts)) * 1e6 / 30
+            S.close()
     return {"form": "c1", "workload": "config1: 32x32 patch, 2 det x 65,536 samples, "
             "lambda 32 direct band, FP64, tol 1e-8", **out}
 

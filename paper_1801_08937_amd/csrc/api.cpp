@@ -172,7 +172,7 @@ struct PcgWork {
     void alloc(int64_t n_, int R_) {
         n = n_;
         R = R_;
-        n_part = reduction_parts(n);
+        n_part = reduction_parts(n, R_);
         const size_t vb = sizeof(double) * n * R;
         r.alloc(vb);
         z.alloc(vb);
@@ -495,7 +495,8 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
                                   hipMemcpyHostToDevice, s));
         }
         // direct-band tile table: (first sample, interval) per tile
-        set_band_tiles(ctx, nz, choose_tile(nz->n_samp, ctx->n_cu));
+        nz->default_tile_len = choose_tile(nz->n_samp, ctx->n_cu);
+        set_band_tiles(ctx, nz, nz->default_tile_len);
         if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
     } catch (...) {
         delete nz;

@@ -463,7 +463,8 @@ __global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
     }
     // D layout of v_mfma_f64_16x16x4f64 (checked on gfx950): item v of lane l
     // holds row l/16 + 4 v, column l % 16.
-    double *out = partial + (int64_t)blockIdx.x * 64 * 64;
+    // partials are stored element-major, partial[(row 64 + col) P + block]
+    const int64_t P = gridDim.x;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int t = wv + 4 * q;
@@ -473,20 +474,25 @@ __global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
             for (int v = 0; v < 4; ++v) {
                 const int row = ta * 16 + (lane / 16) + 4 * v;
                 const int col = tb * 16 + (lane % 16);
-                out[row * 64 + col] = acc[q][v];
+                partial[(int64_t)(row * 64 + col) * P + blockIdx.x] = acc[q][v];
             }
         }
     }
 }
 
+// One wave per element: lane-strided partial sums over the blocks, then a
+// xor butterfly (a fixed order).
 __global__ void k_gram_final(const double *__restrict__ partial, int n_part, int ka, int kb,
                              double *__restrict__ C) {
-    const int e = blockIdx.x * BS + threadIdx.x;
+    const int e = (blockIdx.x * BS + threadIdx.x) >> 6, lane = threadIdx.x & 63;
     if (e >= ka * kb) return;
     const int a = e / kb, b = e % kb;
+    const double *pp = partial + (int64_t)(a * 64 + b) * n_part;
     double s = 0;
-    for (int p = 0; p < n_part; ++p) s += partial[(int64_t)p * 4096 + a * 64 + b];
-    C[a * kb + b] = s;
+    for (int p = lane; p < n_part; p += 64) s += pp[p];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) C[a * kb + b] = s;
 }
 
 // -------------------------------------------------------- small Cholesky
@@ -538,22 +544,32 @@ __global__ void k_chol_small(int k, double *__restrict__ E, double *__restrict__
 
 // c = E^-1 g per column: forward then backward substitution with Lc.
 // g[a * R + r] (k x R), c likewise.  One thread per column.
-__global__ void k_coarse_solve(int k, int R, const double *__restrict__ Lc,
-                               const double *__restrict__ g, double *__restrict__ c) {
-    const int r = threadIdx.x;
-    if (r >= R) return;
-    double y[64];
-    for (int i = 0; i < k; ++i) {
-        double s = g[i * R + r];
-        for (int j = 0; j < i; ++j) s -= Lc[i * k + j] * y[j];
-        y[i] = s / Lc[i * k + i];
+// c = E^-1 g for each column r (block r): forward then backward substitution
+// with the Cholesky factor staged in LDS.  Lane i holds y_i; each step's
+// inner product is a wave sum in a fixed butterfly order.
+__global__ void __launch_bounds__(64) k_coarse_solve(int k, int R, const double *__restrict__ Lc,
+                                                     const double *__restrict__ g,
+                                                     double *__restrict__ c) {
+    __shared__ double L[64][65];
+    const int i = threadIdx.x, r = blockIdx.x;
+    for (int e = i; e < k * k; e += 64) L[e / k][e % k] = Lc[e];
+    __syncthreads();
+    double y = i < k ? g[i * R + r] : 0.0;
+    for (int j = 0; j < k; ++j) {  // L y' = g
+        double t = (i < j) ? L[j][i] * y : 0.0;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+        const double yj = (__shfl(y, j) - t) / L[j][j];
+        if (i == j) y = yj;
     }
-    for (int i = k - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int j = i + 1; j < k; ++j) s -= Lc[j * k + i] * y[j];
-        y[i] = s / Lc[i * k + i];
+    for (int j = k - 1; j >= 0; --j) {  // L^T c = y'
+        double t = (i > j && i < k) ? L[i][j] * y : 0.0;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+        const double cj = (__shfl(y, j) - t) / L[j][j];
+        if (i == j) y = cj;
     }
-    for (int i = 0; i < k; ++i) c[i * R + r] = y[i];
+    if (i < k) c[i * R + r] = y;
 }
 
 // out = M_BD (v - AZ c) + Z c per pixel and column (Eq. m2l), with optional
@@ -770,8 +786,8 @@ int grid_for(int64_t n, int max_blocks = 4096) {
 
 // ----------------------------------------------------------------- launchers
 
-int reduction_parts(int64_t n_rows) {
-    int64_t p = (n_rows + 1023) / 1024;
+int reduction_parts(int64_t n_rows, int nrhs) {
+    int64_t p = (n_rows * nrhs + 1023) / 1024;
     if (p > 512) p = 512;
     return (int)(p < 1 ? 1 : p);
 }
@@ -821,7 +837,7 @@ void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nrhs, cons
     Scope sc(ctx->prof, ctx->stream, "precond");
     if (n_obs == 0) return;
     // partition: n_part blocks over pixels (3 rows each)
-    const int parts = partial ? n_part : reduction_parts(3 * (int64_t)n_obs);
+    const int parts = partial ? n_part : reduction_parts(3 * (int64_t)n_obs, nrhs);
     const int64_t ppb = rows_per(n_obs, parts);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
@@ -842,7 +858,7 @@ void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const d
 
 void dot_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b, double *out) {
     Scope sc(ctx->prof, ctx->stream, "vec");
-    const int parts = reduction_parts(n);
+    const int parts = reduction_parts(n, nrhs);
     ws_alloc(ctx, ctx->red, sizeof(double) * parts * 64);
     dot_partial_cols(ctx, n, nrhs, a, b, ctx->red.as<double>(), parts);
     k_dot_final<<<nrhs, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, nrhs, out);
@@ -972,16 +988,18 @@ void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t 
                int64_t x_cs, const double *Y, int64_t y_rs, int64_t y_cs, double *C) {
     Scope sc(ctx->prof, ctx->stream, "gram_mfma");
     MM_CHECK(ka >= 1 && ka <= 64 && kb >= 1 && kb <= 64, MM_E_INVALID, "gram: sizes");
-    int parts = (int)((n + 2047) / 2048);
-    if (parts > 1024) parts = 1024;
-    if (parts < 1) parts = 1;
+    // about four 32-row chunks per block, at most 1,024 blocks
+    int64_t parts64 = (n + 4 * GR_ROWS - 1) / (4 * GR_ROWS);
+    if (parts64 > 1024) parts64 = 1024;
+    if (parts64 < 1) parts64 = 1;
+    const int parts = (int)parts64;
     int64_t rpb = (n + parts - 1) / parts;
     rpb = (rpb + GR_ROWS - 1) / GR_ROWS * GR_ROWS;
     ws_alloc(ctx, ctx->gram_part, sizeof(double) * 4096 * parts);
     k_gram_mfma<<<parts, BS, 0, ctx->stream>>>(n, ka, kb, X, x_rs, x_cs, Y, y_rs, y_cs,
                                                 ctx->gram_part.as<double>(), rpb);
-    k_gram_final<<<(ka * kb + BS - 1) / BS, BS, 0, ctx->stream>>>(ctx->gram_part.as<double>(),
-                                                                   parts, ka, kb, C);
+    k_gram_final<<<(ka * kb * 64 + BS - 1) / BS, BS, 0, ctx->stream>>>(
+        ctx->gram_part.as<double>(), parts, ka, kb, C);
     MM_HIP(hipGetLastError());
 }
 
@@ -1001,7 +1019,7 @@ void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, d
         // g[a][r] = sum_i Z[a n + i] v[i R + r]   (Z^T V on MFMA)
         gram_mfma(ctx, n, k, nrhs, M->Z.as<double>(), 1, n, v, nrhs, 1, g);
     }
-    k_coarse_solve<<<1, 64, 0, ctx->stream>>>(k, nrhs, M->Lc.as<double>(), g, c);
+    k_coarse_solve<<<nrhs, 64, 0, ctx->stream>>>(k, nrhs, M->Lc.as<double>(), g, c);
     MM_HIP(hipGetLastError());
 }
 
@@ -1013,7 +1031,7 @@ void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, 
     ws_alloc(ctx, ctx->scal, sizeof(double) * 64 * 64 + 4096);
     double *c = ctx->scal.as<double>();
     m2l_coef_dev(ctx, M, nrhs, v, c);
-    const int parts = partial ? n_part : reduction_parts(n);
+    const int parts = partial ? n_part : reduction_parts(n, nrhs);
     const int64_t ppb = rows_per(M->n_obs, parts);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;

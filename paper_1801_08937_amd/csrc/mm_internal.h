@@ -164,7 +164,13 @@ struct mm_noise {
     mm::DBuf tiles;  // int64 pairs (tile start sample, interval index)
     int64_t n_tiles = 0;
     int32_t tile_len = 0;
+    int32_t default_tile_len = 0;  // single-column default, from the device size
     int32_t tuned_tile_len[7] = {0, 0, 0, 0, 0, 0, 0};  // per log2(nrhs); 0 = untuned
+    // a second table for multi-column applies, whose tiles are longer (each
+    // block covers TL/R samples of all R columns)
+    mm::DBuf tiles_m;
+    int64_t n_tiles_m = 0;
+    int32_t tile_len_m = 0;
     // FFT: per-filter packed spectrum and block table
     int32_t fft_n = 0;       // real block length
     int32_t fft_valid = 0;   // valid outputs per block
@@ -217,7 +223,8 @@ void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nrhs, cons
 // Deterministic dot products of columns: out[r] = sum_i a[i R + r] b[i R + r]
 // over n rows (two stages, fixed order).
 void dot_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b, double *out);
-int reduction_parts(int64_t n_rows);
+// Blocks of a two-stage column reduction over n_rows x nrhs elements.
+int reduction_parts(int64_t n_rows, int nrhs = 1);
 
 // Small dense helpers
 void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t x_rs,
@@ -267,7 +274,7 @@ template <typename T> struct Vec2T;
 template <> struct Vec2T<float> { using type = float2; };
 template <> struct Vec2T<double> { using type = double2; };
 
-void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl);
+void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl, bool multi = false);
 void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *report, int *n_report);
 
 inline int log2i(int r) { int l = 0; while ((1 << l) < r) ++l; return l; }

@@ -507,24 +507,32 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
-    const int want = nz->tuned_tile_len[log2i(nrhs)];
-    if (want > 0 && want != nz->tile_len) set_band_tiles(ctx, const_cast<mm_noise *>(nz), want);
+    // Tile length: the tuned one, else the single-column default, grown with
+    // the column count so that a block's TL/R samples stay well above the
+    // band's reach (TL <= 16 x 256 keeps each thread's outputs in registers).
+    const bool multi = nrhs > 1;
+    int want = nz->tuned_tile_len[log2i(nrhs)];
+    if (want <= 0) want = multi ? std::min(4096, std::max(nz->default_tile_len, 256 * nrhs))
+                                : nz->default_tile_len;
+    if (want != (multi ? nz->tile_len_m : nz->tile_len))
+        set_band_tiles(ctx, const_cast<mm_noise *>(nz), want, multi);
+    const int64_t *tiles = multi ? nz->tiles_m.as<int64_t>() : nz->tiles.as<int64_t>();
+    const int64_t n_tiles = multi ? nz->n_tiles_m : nz->n_tiles;
+    const int tl = multi ? nz->tile_len_m : nz->tile_len;
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        dim3 grid((unsigned)nz->n_tiles, R);
+        dim3 grid((unsigned)n_tiles, R);
         const int band_slots = lam <= BAND_LDS_MAX ? ((lam + 1 + 3) & ~3) : 0;
         if (nz->prec == MM_F32) {
             size_t sm = sizeof(float) * (band_slots + 4096);
             k_band<float, R><<<grid, BS, sm, ctx->stream>>>(
-                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
-                nz->band.as<float>(), lam, nz->tile_len, static_cast<const float *>(y),
-                static_cast<float *>(z));
+                tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<float>(),
+                lam, tl, static_cast<const float *>(y), static_cast<float *>(z));
         } else {
             size_t sm = sizeof(double) * (band_slots + 4096);
             k_band<double, R><<<grid, BS, sm, ctx->stream>>>(
-                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
-                nz->band.as<double>(), lam, nz->tile_len, static_cast<const double *>(y),
-                static_cast<double *>(z));
+                tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<double>(),
+                lam, tl, static_cast<const double *>(y), static_cast<double *>(z));
         }
     });
     MM_HIP(hipGetLastError());
@@ -552,20 +560,22 @@ void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod, 
 
 namespace mm {
 
-// (Re)build the direct band's tile table for tile length tl.
-void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl) {
+// (Re)build the direct band's tile table for tile length tl (the
+// single-column table, or the multi-column one).
+void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl, bool multi) {
     std::vector<int64_t> tiles;
     for (int i = 0; i < nz->n_int; ++i)
         for (int64_t t = nz->h_istart[i]; t < nz->h_istart[i + 1]; t += tl) {
             tiles.push_back(t);
             tiles.push_back(i);
         }
-    nz->tile_len = tl;
-    nz->n_tiles = (int64_t)tiles.size() / 2;
-    nz->tiles.alloc(sizeof(int64_t) * tiles.size());
-    MM_HIP(hipMemcpyAsync(nz->tiles.ptr, tiles.data(), sizeof(int64_t) * tiles.size(),
+    DBuf &buf = multi ? nz->tiles_m : nz->tiles;
+    buf.alloc(sizeof(int64_t) * tiles.size());
+    MM_HIP(hipMemcpyAsync(buf.ptr, tiles.data(), sizeof(int64_t) * tiles.size(),
                           hipMemcpyHostToDevice, ctx->stream));
     MM_HIP(hipStreamSynchronize(ctx->stream));
+    (multi ? nz->tile_len_m : nz->tile_len) = tl;
+    (multi ? nz->n_tiles_m : nz->n_tiles) = (int64_t)tiles.size() / 2;
 }
 
 // Measure candidate launch shapes with HIP events and keep the fastest:
