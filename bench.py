@@ -115,6 +115,7 @@ def main():
     ap.add_argument("--form", choices=["c1", "c3", "c4", "c5"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
+    ap.add_argument("--slots", type=int, default=2, help="columns per serving session")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -146,7 +147,8 @@ def main():
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4,
-              "c5": lambda m, c: form_c5(m, c, n_requests=args.requests)}[args.form]
+              "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
+                                         slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
         ctx.close()
         return
@@ -415,8 +417,46 @@ def form_c3(mm, ctx):
                 "iters": info["iters"], "converged": info["converged"], "solve_ms": t * 1e3,
                 "rel_res_own": info["rel_res_true"], "rel_res_fp64": true_res(xs),
                 "map_rel_err_vs_oracle": float(np.linalg.norm(xh - x_or) / np.linalg.norm(x_or))}
+    # the same precision split at the config-2 scale, where the TOD passes are
+    # bandwidth-bound: A apply and PCG(M_BD) to 1e-6 / 1e-8 in both precisions
+    p2 = synth.config2()
+    pix2, psi2 = torch.from_numpy(p2.pix).to(dev), torch.from_numpy(p2.psi).to(dev)
+    tod2 = torch.from_numpy(p2.tod).to(dev)
+    big = {}
+    for name, prec in (("fp64", 0), ("fp32", 1)):
+        lp = ctx.pointing(pix2, psi2, p2.n_pix_total, p2.min_hits, prec=prec)
+        lp.set_grid(p2.n_side)
+        ln = ctx.noise(p2.interval_start, p2.filter_id, p2.band, p2.half_bw, prec=prec)
+        x = torch.randn(lp.n, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            ctx.apply_A(lp, ln, x, y)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(ctx.stream)
+        for _ in range(10):
+            ctx.apply_A(lp, ln, x, y)
+        ev[1].record(ctx.stream)
+        ev[1].synchronize()
+        b = ctx.rhs(lp, ln, tod2 if prec == 0 else tod2.float())
+        M = ctx.mbd(lp, ln)
+        res = {"a_apply_ms": ev[0].elapsed_time(ev[1]) / 10}
+        for tol in (1e-6, 1e-8):
+            (r, t) = _wall(lambda: ctx.solve(lp, ln, M, b, tol=tol, max_iter=500, check_every=4,
+                                             history=False))
+            xs, info = r
+            res[f"tol{tol:g}"] = {"iters": info["iters"], "converged": info["converged"],
+                                  "solve_s": t, "rel_res_own": info["rel_res_true"]}
+            res[f"x_tol{tol:g}"] = xs
+        big[name] = res
+        del lp, ln, M, b
+    for tol in (1e-6, 1e-8):
+        x64, x32 = big["fp64"].pop(f"x_tol{tol:g}"), big["fp32"].pop(f"x_tol{tol:g}")
+        big["fp32"][f"tol{tol:g}"]["map_rel_diff_vs_fp64"] = float(
+            torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    out["config2_scale"] = big
     return {"form": "c3", "workload": "config1 in FP32 (TOD, weights, N^-1 FP32; dots, M_BD, "
-            "coarse FP64), M_BD, tol 1e-6 and 1e-8", **out}
+            "coarse FP64), M_BD, tol 1e-6 and 1e-8; plus the config-2 scan at both "
+            "precisions", **out}
 
 
 def form_c4(mm, ctx):
@@ -470,7 +510,7 @@ def form_c4(mm, ctx):
             "pointing and noise model, tol 1e-8", **out}
 
 
-def form_c5(mm, ctx, n_requests=200, slots=2):
+def form_c5(mm, ctx, n_requests=200, slots=1):
     """Serving: a Poisson trace (4 requests/s) over four recurring strategies
     of uneven size (2^20 to 2^27 samples, lambda 1,024 to 8,192), tolerance
     1e-6 or 1e-8.  Served by mm_server_* (cached pointing, M_BD and M_2l per
@@ -527,10 +567,31 @@ def form_c5(mm, ctx, n_requests=200, slots=2):
         xs_srv[i] = x
         return int(strat[i]), d, x, float(tol[i])
     log("[bench] serving trace ...")
-    infos, wall = serving.run_trace(srv, arrivals, req)
+    ready = {"t": None}
+
+    def on_step(el):
+        if ready["t"] is None and all(srv.strategy_state(s_) in (2, 3) for s_ in range(4)):
+            ready["t"] = el
+    infos, wall = serving.run_trace(srv, arrivals, req, on_step=on_step)
     served = serving.latency_stats(infos, wall)
+    served["all_m2l_ready_at_s"] = ready["t"]
+    steady = [i for i in range(n_requests) if ready["t"] is not None and arrivals[i] >= ready["t"]]
     served["iters_mean"] = float(np.mean([d["iters"] for d in infos]))
     served["register_s"] = t_reg
+    lat_s = np.array([d["latency_seconds"] for d in infos])
+    served["per_strategy_p50_p99_s"] = {
+        int(s_): [float(np.percentile(lat_s[strat == s_], 50)),
+                  float(np.percentile(lat_s[strat == s_], 99))] for s_ in range(4)}
+    if steady:
+        served["steady_state"] = {"n": len(steady),
+                                  "p50_s": float(np.percentile(lat_s[steady], 50)),
+                                  "p99_s": float(np.percentile(lat_s[steady], 99)),
+                                  "mean_s": float(lat_s[steady].mean())}
+    slow = np.argsort(-lat_s)[:5]
+    served["slowest"] = [{"i": int(i), "strategy": int(strat[i]), "tol": float(tol[i]),
+                          "precond": int(infos[i]["precond"]), "iters": int(infos[i]["iters"]),
+                          "queue_s": float(infos[i]["queue_seconds"]),
+                          "latency_s": float(lat_s[i])} for i in slow]
     log(f"[bench] served: {served}")
     srv.close()
     # baseline: one at a time, FP64 M_BD, nothing cached
@@ -563,7 +624,15 @@ def form_c5(mm, ctx, n_requests=200, slots=2):
         del lp, ln, M, b, x, d
     wall_b = time.perf_counter() - t_start
     lat = np.array(lat)
-    base = {"n": n_requests, "p50_s": float(np.percentile(lat, 50)),
+    if steady:
+        steady_b = {"n": len(steady), "p50_s": float(np.percentile(lat[steady], 50)),
+                    "p99_s": float(np.percentile(lat[steady], 99)),
+                    "mean_s": float(lat[steady].mean())}
+    else:
+        steady_b = None
+    per_b = {int(s_): [float(np.percentile(lat[strat == s_], 50)),
+                       float(np.percentile(lat[strat == s_], 99))] for s_ in range(4)}
+    base = {"per_strategy_p50_p99_s": per_b, "steady_state": steady_b, "n": n_requests, "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
             "solves_per_s": n_requests / wall_b, "wall_s": wall_b,
             "iters_mean": float(np.mean(iters))}

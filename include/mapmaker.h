@@ -300,20 +300,25 @@ void mm_pcg_destroy(mm_pcg *s);
  * context (HIP stream), pointing, noise and M_BD at registration, and a
  * two-level M_2l built from its first request's right-hand side and reused for
  * every later request of that strategy (Sect. 6.3.2: M_2l pays off when the
- * same system is solved many times).  mm_server_step admits queued requests
- * into free column slots of the strategy's lockstep PCG session -- also while
- * other slots are mid-solve -- runs `iters_per_step` iterations on every
- * strategy with running slots (all streams enqueued before any is waited on,
- * so strategies overlap on the device), and retires finished slots into the
- * caller's output buffers.  A request's result does not depend on which other
- * requests share its session.  Not thread safe. */
+ * same system is solved many times).  The M_2l build runs on a host thread of
+ * its own (own context and stream) and blocks no request: until it is ready,
+ * requests of that strategy are solved with M_BD.  mm_server_step admits
+ * queued requests into free column slots of the strategy's lockstep PCG
+ * session for the current preconditioner -- also while other slots are
+ * mid-solve -- runs `iters_per_step` iterations on every session with running
+ * slots (all streams enqueued before any is waited on, so strategies overlap
+ * on the device), and retires finished slots into the caller's output
+ * buffers.  A request's result does not depend on which other requests share
+ * its session.  The server's calls are not thread safe (one caller thread). */
 typedef struct mm_server mm_server;
 
 typedef struct {
     int32_t state;          /* 0 queued, 1 running, 2 converged, 3 budget spent, 4 failed */
     int32_t iters;
     int32_t slot;
-    int32_t m2l_built;      /* 1 if this request paid for the M_2l build (cache miss) */
+    int32_t m2l_built;      /* 1 if this request started the M_2l build (cache miss) */
+    int32_t precond;        /* preconditioner it runs with: 0 M_BD, 1 M_2l; -1 queued */
+    int32_t reserved;
     double rel_res;         /* recursive ||r|| / ||b|| at exit */
     double queue_seconds;   /* submit -> admitted */
     double latency_seconds; /* submit -> done (or now) */
@@ -341,6 +346,9 @@ mm_status mm_server_submit(mm_server *srv, int32_t strategy, const void *tod, do
                            int32_t max_iter, double *x_out, int64_t *request_id);
 /* One scheduling step; n_running, n_queued [host] or NULL. */
 mm_status mm_server_step(mm_server *srv, int32_t *n_running, int32_t *n_queued);
+/* State of a strategy's M_2l cache: 0 not started, 1 building, 2 ready,
+ * 3 build failed (its requests keep M_BD).  [host] output. */
+mm_status mm_server_strategy_state(mm_server *srv, int32_t strategy, int32_t *m2l_state);
 mm_status mm_server_poll(mm_server *srv, int64_t request_id, mm_request_info *info);
 const char *mm_server_last_error(const mm_server *srv);
 void mm_server_destroy(mm_server *srv);

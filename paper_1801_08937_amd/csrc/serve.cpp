@@ -2,20 +2,26 @@
 // continuously batched on one GPU.
 //
 // Each strategy owns a context (its own HIP stream), its pointing, noise and
-// M_BD built at registration, and a PCG session of `slots` lockstep columns.
-// Its two-level preconditioner M_2l is built from the first request's
-// right-hand side and reused for every later request of that strategy -- the
-// paper's point that M_2l pays off when the same system is solved many times
-// (Sect. 6.3.2).  A step admits queued requests into free slots (computing
-// their b on the strategy's stream), runs a chunk of iterations on every
-// strategy with running slots -- enqueued on all streams before any is
-// waited on, so strategies overlap on the device -- and retires finished
-// slots, writing each solution to the caller's buffer.  Memory is admitted
-// against a byte budget when a strategy is registered.
+// M_BD built at registration, and up to two PCG sessions ("lanes") of `slots`
+// lockstep columns: one preconditioned by M_BD, one by M_2l.  M_2l is built
+// from the first request's right-hand side and reused for every later request
+// of that strategy -- the paper's point that M_2l pays off when the same
+// system is solved many times (Sect. 6.3.2).  The build (Arnoldi, Ritz
+// vectors, AZ, E) runs on a host thread of its own with a context and stream
+// of its own, so it never holds up other requests: the request that triggers
+// it and those admitted before it is ready are solved with M_BD, later ones
+// with M_2l.  A step admits queued requests into free slots (computing their b
+// on the strategy's stream), runs a chunk of iterations on every lane with
+// running slots -- enqueued on all streams before any is waited on, so
+// strategies overlap on the device -- and retires finished slots, writing
+// each solution to the caller's buffer.  Memory is admitted against a byte
+// budget when a strategy is registered.
+#include <atomic>
 #include <chrono>
 #include <deque>
 #include <map>
 #include <memory>
+#include <thread>
 
 #include "mm_internal.h"
 
@@ -39,7 +45,21 @@ struct Request {
     double rel_res = 0;
     double t_submit = 0, t_start = 0, t_done = 0;
     int32_t m2l_built = 0;  // 1 if this request triggered the M_2l build
+    int32_t lane = 0;       // 0 = M_BD session, 1 = M_2l session
 };
+
+// One PCG session of a strategy and the request held by each of its slots.
+struct Lane {
+    mm_pcg *sess = nullptr;
+    std::vector<int64_t> slot_req;
+    bool busy() const {
+        for (auto q : slot_req)
+            if (q >= 0) return true;
+        return false;
+    }
+};
+
+enum BuildState { BUILD_NONE = 0, BUILD_RUNNING = 1, BUILD_READY = 2, BUILD_FAILED = 3 };
 
 struct Strategy {
     int32_t id = 0;
@@ -47,20 +67,33 @@ struct Strategy {
     mm_pointing *p = nullptr;
     mm_noise *nz = nullptr;
     mm_precond *mbd = nullptr;
-    mm_precond *m2l = nullptr;
-    mm_pcg *sess = nullptr;
-    std::vector<int64_t> slot_req;
+    mm_precond *m2l = nullptr;  // adopted once the background build is ready
+    Lane lane[2];
     mm::DBuf b;
     size_t bytes = 0;
     int64_t n = 0;
-    bool m2l_failed = false;
+    // background M_2l build: its own context and stream, seeded with a copy
+    // of the first request's b; it only reads p, nz and mbd
+    std::thread builder;
+    std::atomic<int> build{BUILD_NONE};
+    mm_ctx *bctx = nullptr;
+    mm_precond *m2l_new = nullptr;
+    mm::DBuf b_seed;
+    void join_builder() {
+        if (builder.joinable()) builder.join();
+        mm_ctx_destroy(bctx);
+        bctx = nullptr;
+    }
     ~Strategy() {
-        mm_pcg_destroy(sess);
+        join_builder();
+        mm_precond_destroy(m2l_new);
+        for (auto &l : lane) mm_pcg_destroy(l.sess);
         mm_precond_destroy(m2l);
         mm_precond_destroy(mbd);
         mm_noise_destroy(nz);
         mm_pointing_destroy(p);
         b.release();
+        b_seed.release();
         mm_ctx_destroy(ctx);
     }
 };
@@ -142,12 +175,13 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
     // footprint: pointing (index, weights, permutation, sorted weights; the
     // FP64 form also keeps the angles), the sliced P^T layout (index and
     // angle or weights per entry, ~10 % padding), two TOD workspaces of
-    // `slots` columns, session vectors, M_2l (Z, AZ, W basis)
+    // `slots` columns plus the single-column ones of the M_2l build, two
+    // sessions' vectors, M_2l (Z, AZ, W basis)
     const int64_t te = prec == MM_F32 ? 4 : 8;
     const int64_t est_n = 3 * (int64_t)std::min<int64_t>(n_pix_total, n_samp);
     const int64_t per_samp = 4 + 2 * 2 * te + 4 + (prec == MM_F32 ? 0 : 8) + 14;
-    const int64_t bytes = n_samp * per_samp + 2 * n_samp * te * srv->slots +
-                          est_n * 8 * (7 * srv->slots + 2 * srv->defl_k + srv->m_max + 1);
+    const int64_t bytes = n_samp * per_samp + 2 * n_samp * te * (srv->slots + 1) +
+                          est_n * 8 * (14 * srv->slots + 2 * srv->defl_k + srv->m_max + 2);
     if (srv->used + bytes > srv->budget)
         throw Error(MM_E_BUSY, "server: strategy footprint " + std::to_string(bytes) +
                                    " B exceeds the remaining budget");
@@ -163,7 +197,7 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
     check(mm_mbd_build(st->ctx, st->p, st->nz, &st->mbd), st->ctx, "server: M_BD");
     st->n = 3 * (int64_t)st->p->n_obs;
     st->b.alloc(sizeof(double) * st->n);
-    st->slot_req.assign(srv->slots, -1);
+    for (auto &l : st->lane) l.slot_req.assign(srv->slots, -1);
     st->bytes = bytes;
     srv->used += bytes;
     srv->strat[id] = std::move(st);
@@ -193,14 +227,50 @@ extern "C" mm_status mm_server_submit(mm_server *srv, int32_t strategy, const vo
     return MM_OK;
 }
 
+// Adopt a finished background build (the M_2l lane takes requests admitted
+// from now on).
+static void poll_build(Strategy &st) {
+    const int b = st.build.load();
+    if (b == BUILD_READY && !st.m2l) {
+        st.join_builder();
+        st.m2l = st.m2l_new;
+        st.m2l_new = nullptr;
+    } else if (b == BUILD_FAILED && st.builder.joinable()) {
+        st.join_builder();
+    }
+}
+
+static void start_build(mm_server *srv, Strategy &st) {
+    st.b_seed.alloc(sizeof(double) * st.n);
+    MM_HIP(hipMemcpyAsync(st.b_seed.ptr, st.b.ptr, sizeof(double) * st.n,
+                          hipMemcpyDeviceToDevice, st.ctx->stream));
+    MM_HIP(hipStreamSynchronize(st.ctx->stream));
+    const int k = (int)std::min<int64_t>(srv->defl_k, st.n - 1);
+    const int mmax = (int)std::min<int64_t>(srv->m_max, st.n);
+    const double eps = srv->eps_arn;
+    const int dev = srv->device;
+    st.build = BUILD_RUNNING;
+    Strategy *sp = &st;
+    st.builder = std::thread([sp, k, mmax, eps, dev]() {
+        mm_status s = MM_E_DEVICE;
+        if (hipSetDevice(dev) == hipSuccess && mm_ctx_create(dev, nullptr, &sp->bctx) == MM_OK)
+            s = mm_defl_build(sp->bctx, sp->p, sp->nz, sp->mbd, sp->b_seed.as<double>(), k, 0.0,
+                              eps, mmax, nullptr, nullptr, &sp->m2l_new);
+        sp->build = s >= 0 ? BUILD_READY : BUILD_FAILED;
+    });
+}
+
 // Admit queued requests (FIFO per strategy) into free slots.
 static void admit(mm_server *srv) {
     for (auto it = srv->queue.begin(); it != srv->queue.end();) {
         Request &r = srv->req[*it];
         Strategy &st = *srv->strat[r.strategy];
+        poll_build(st);
+        const int li = st.m2l ? 1 : 0;
+        Lane &ln = st.lane[li];
         int slot = -1;
         for (int c = 0; c < srv->slots; ++c)
-            if (st.slot_req[c] < 0) {
+            if (ln.slot_req[c] < 0) {
                 slot = c;
                 break;
             }
@@ -216,23 +286,20 @@ static void admit(mm_server *srv) {
             it = srv->queue.erase(it);
             continue;
         }
-        if (!st.m2l && !st.m2l_failed && srv->defl_k > 0) {
-            // cache miss: build M_2l from this request's right-hand side
-            const int k = std::min<int64_t>(srv->defl_k, st.n - 1);
-            const int mmax = (int)std::min<int64_t>(srv->m_max, st.n);
-            s = mm_defl_build(ctx, st.p, st.nz, st.mbd, st.b.as<double>(), k, 0.0, srv->eps_arn,
-                              mmax, nullptr, nullptr, &st.m2l);
-            if (s < 0) st.m2l_failed = true;
+        if (!st.m2l && st.build == BUILD_NONE && srv->defl_k > 0) {
+            // cache miss: build M_2l from this request's right-hand side, in the background
+            start_build(srv, st);
             r.m2l_built = 1;
         }
-        if (!st.sess) {
-            const mm_precond *M = st.m2l ? st.m2l : st.mbd;
-            check(mm_pcg_create(ctx, st.p, st.nz, M, srv->slots, &st.sess), ctx, "server: session");
+        if (!ln.sess) {
+            const mm_precond *M = li ? st.m2l : st.mbd;
+            check(mm_pcg_create(ctx, st.p, st.nz, M, srv->slots, &ln.sess), ctx, "server: session");
         }
-        check(mm_pcg_start(ctx, st.sess, slot, st.b.as<double>(), r.tol, r.max_iter), ctx,
+        check(mm_pcg_start(ctx, ln.sess, slot, st.b.as<double>(), r.tol, r.max_iter), ctx,
               "server: start");
-        st.slot_req[slot] = r.id;
+        ln.slot_req[slot] = r.id;
         r.slot = slot;
+        r.lane = li;
         r.state = 1;
         r.t_start = now_s();
         it = srv->queue.erase(it);
@@ -243,40 +310,52 @@ extern "C" mm_status mm_server_step(mm_server *srv, int32_t *n_running, int32_t 
     if (!srv) return MM_E_INVALID;
     SRV_TRY
     admit(srv);
-    // enqueue a chunk of iterations on every strategy's stream, then poll
+    // enqueue a chunk of iterations on every busy lane, then poll
     for (auto &kv : srv->strat) {
         Strategy &st = *kv.second;
-        bool any = false;
-        for (auto q : st.slot_req) any |= q >= 0;
-        if (any) check(mm_pcg_iterate(st.ctx, st.sess, srv->chunk), st.ctx, "server: iterate");
+        for (auto &ln : st.lane)
+            if (ln.busy()) check(mm_pcg_iterate(st.ctx, ln.sess, srv->chunk), st.ctx, "server: iterate");
     }
     int running = 0;
     std::vector<int32_t> state(srv->slots), iters(srv->slots);
     std::vector<double> rr(srv->slots);
     for (auto &kv : srv->strat) {
         Strategy &st = *kv.second;
-        bool any = false;
-        for (auto q : st.slot_req) any |= q >= 0;
-        if (!any) continue;
-        check(mm_pcg_poll(st.ctx, st.sess, state.data(), iters.data(), rr.data()), st.ctx,
-              "server: poll");
-        for (int c = 0; c < srv->slots; ++c) {
-            if (st.slot_req[c] < 0) continue;
-            Request &r = srv->req[st.slot_req[c]];
-            if (state[c] == 1) {
-                ++running;
-                continue;
+        for (auto &ln : st.lane) {
+            if (!ln.busy()) continue;
+            check(mm_pcg_poll(st.ctx, ln.sess, state.data(), iters.data(), rr.data()), st.ctx,
+                  "server: poll");
+            for (int c = 0; c < srv->slots; ++c) {
+                if (ln.slot_req[c] < 0) continue;
+                Request &r = srv->req[ln.slot_req[c]];
+                if (state[c] == 1) {
+                    ++running;
+                    continue;
+                }
+                r.iters = iters[c];
+                r.rel_res = rr[c];
+                r.state = state[c] == 2 ? 2 : (state[c] == 3 ? 3 : 4);
+                check(mm_pcg_finish(st.ctx, ln.sess, c, r.x_out), st.ctx, "server: finish");
+                r.t_done = now_s();
+                ln.slot_req[c] = -1;
             }
-            r.iters = iters[c];
-            r.rel_res = rr[c];
-            r.state = state[c] == 2 ? 2 : (state[c] == 3 ? 3 : 4);
-            check(mm_pcg_finish(st.ctx, st.sess, c, r.x_out), st.ctx, "server: finish");
-            r.t_done = now_s();
-            st.slot_req[c] = -1;
         }
+        poll_build(st);
     }
     if (n_running) *n_running = running;
     if (n_queued) *n_queued = (int32_t)srv->queue.size();
+    SRV_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_server_strategy_state(mm_server *srv, int32_t strategy,
+                                              int32_t *m2l_state) {
+    if (!srv || !m2l_state) return MM_E_INVALID;
+    SRV_TRY
+    auto it = srv->strat.find(strategy);
+    MM_CHECK(it != srv->strat.end(), MM_E_INVALID, "server: unknown strategy");
+    poll_build(*it->second);
+    *m2l_state = it->second->m2l ? BUILD_READY : it->second->build.load();
     SRV_END
     return MM_OK;
 }
@@ -291,6 +370,8 @@ extern "C" mm_status mm_server_poll(mm_server *srv, int64_t request_id, mm_reque
     info->iters = r.iters;
     info->slot = r.slot;
     info->m2l_built = r.m2l_built;
+    info->precond = r.state >= 1 ? (r.lane ? 1 : 0) : -1;
+    info->reserved = 0;
     info->rel_res = r.rel_res;
     info->queue_seconds = (r.state >= 1 ? r.t_start : now_s()) - r.t_submit;
     info->latency_seconds = (r.state >= 2 ? r.t_done : now_s()) - r.t_submit;

@@ -42,7 +42,8 @@ class SolveInfo(C.Structure):
 
 class RequestInfo(C.Structure):
     _fields_ = [("state", C.c_int32), ("iters", C.c_int32), ("slot", C.c_int32),
-                ("m2l_built", C.c_int32), ("rel_res", C.c_double),
+                ("m2l_built", C.c_int32), ("precond", C.c_int32), ("reserved", C.c_int32),
+                ("rel_res", C.c_double),
                 ("queue_seconds", C.c_double), ("latency_seconds", C.c_double)]
 
 
@@ -101,6 +102,7 @@ def lib() -> C.CDLL:
             "mm_server_submit": (C.c_int, [P, I32, P, D, I32, P, C.POINTER(I64)]),
             "mm_server_step": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
             "mm_server_poll": (C.c_int, [P, I64, C.POINTER(RequestInfo)]),
+            "mm_server_strategy_state": (C.c_int, [P, I32, C.POINTER(I32)]),
             "mm_server_last_error": (C.c_char_p, [P]),
             "mm_server_destroy": (None, [P]),
             "mm_profile_read": (C.c_int, [P, I32, P, P, P, C.POINTER(I32)]),
@@ -559,6 +561,13 @@ class Server:
         nr, nq = C.c_int32(), C.c_int32()
         self._check(lib().mm_server_step(self.h, C.byref(nr), C.byref(nq)), "mm_server_step")
         return nr.value, nq.value
+
+    def strategy_state(self, sid: int) -> int:
+        """M_2l cache of a strategy: 0 not started, 1 building, 2 ready, 3 failed."""
+        st = C.c_int32()
+        self._check(lib().mm_server_strategy_state(self.h, sid, C.byref(st)),
+                    "mm_server_strategy_state")
+        return st.value
 
     def poll(self, rid: int) -> dict:
         info = RequestInfo()

@@ -12,11 +12,12 @@ import time
 import numpy as np
 
 
-def run_trace(server, arrivals, requests, poll_sleep: float = 0.0):
+def run_trace(server, arrivals, requests, poll_sleep: float = 0.0, on_step=None):
     """Submit requests[i] = (strategy, tod, x_out, tol) at arrivals[i] seconds
     after start, stepping the server in between.  `requests` may also be a
     callable i -> request, called at the arrival (for data made on demand);
     the time stream is released once the server has admitted the request.
+    on_step(elapsed_seconds) is called after every server step.
     Returns per-request info dicts (with latency) and the trace's wall time."""
     t0 = time.perf_counter()
     pending = list(range(len(arrivals)))
@@ -31,6 +32,8 @@ def run_trace(server, arrivals, requests, poll_sleep: float = 0.0):
             ids[i] = server.submit(sid, tod, x_out, tol=tol, max_iter=2000)
             live[i] = tod
         running, queued = server.step()
+        if on_step is not None:
+            on_step(time.perf_counter() - t0)
         for i, rid in ids.items():
             if i in done:
                 continue
@@ -56,4 +59,5 @@ def latency_stats(infos, wall):
             "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
             "solves_per_s": float(lat.size / wall), "wall_s": float(wall),
             "converged": int(sum(d["state"] == 2 for d in infos)),
-            "m2l_builds": int(sum(d["m2l_built"] for d in infos))}
+            "m2l_builds": int(sum(d["m2l_built"] for d in infos)),
+            "served_with_m2l": int(sum(d.get("precond", 0) == 1 for d in infos))}

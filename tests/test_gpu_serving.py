@@ -69,6 +69,8 @@ def test_server_result_same_alone_and_in_mix(mm):
     assert infos_a[0]["iters"] == infos_b[0]["iters"]
     assert torch.equal(outs_a[0][0], outs_b[0][0])
     assert infos_b[0]["m2l_built"] == 1 and infos_b[1]["m2l_built"] == 0
+    # the request that starts the (background) M_2l build is solved with M_BD
+    assert infos_a[0]["precond"] == 0 and infos_b[0]["precond"] == 0
     # every result solves its own system (oracle solution within kappa * tol)
     for (x, tod, p), info, tol in zip(outs_b, infos_b, (1e-8, 1e-6, 1e-8, 1e-8, 1e-6)):
         op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
@@ -79,6 +81,37 @@ def test_server_result_same_alone_and_in_mix(mm):
                       5000)
         e = rel(host(x), xo)
         assert e <= 1e4 * tol, (e, tol)
+
+
+def _warm(srv, strategies=(0, 1)):
+    """One request per strategy, then step until every M_2l cache is ready."""
+    import time
+    infos, _ = _run(srv, [(s, 90 + s, 1e-6) for s in strategies])
+    t0 = time.time()
+    while any(srv.strategy_state(s) == 1 for s in strategies):
+        srv.step()
+        time.sleep(0.01)
+        assert time.time() - t0 < 60, "M_2l build did not finish"
+    assert all(srv.strategy_state(s) == 2 for s in strategies)
+    return infos
+
+
+def test_server_m2l_lane_same_alone_and_in_mix(mm):
+    """Once a strategy's M_2l is cached, its requests run in the M_2l session;
+    a request's map is bitwise the same alone and with others joining."""
+    import torch
+    srv = _server(mm)
+    _warm(srv)
+    infos_a, outs_a = _run(srv, [(0, 7, 1e-8)])
+    srv.close()
+    srv = _server(mm)
+    _warm(srv)
+    infos_b, outs_b = _run(srv, [(0, 7, 1e-8), (0, 8, 1e-6), (1, 9, 1e-8), (0, 11, 1e-8)],
+                           join_after=2)
+    srv.close()
+    assert all(i["state"] == 2 and i["precond"] == 1 for i in infos_a + infos_b)
+    assert infos_a[0]["iters"] == infos_b[0]["iters"]
+    assert torch.equal(outs_a[0][0], outs_b[0][0])
 
 
 def test_server_continuous_batching_many(mm):
