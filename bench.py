@@ -115,7 +115,7 @@ def main():
     ap.add_argument("--form", choices=["c1", "c3", "c4", "c5"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
-    ap.add_argument("--slots", type=int, default=2, help="columns per serving session")
+    ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
