@@ -7,7 +7,7 @@
 // 1024 threads each hold 16 complex values in registers through the whole
 // transform: radices 16 x 16 x 16 x 4.  Between passes the values are
 // exchanged through LDS one component at a time (real parts, then imaginary
-// parts), so the exchange buffer is 16,384 FP64 values (plus padding) and the
+// parts), so the exchange buffer is 16,384 FP64 values (xor-swizzled) and the
 // thread's other component stays in registers.  The first forward pass reads
 // global memory, the radix-4 passes run in registers, the spectrum step reads
 // each value's partner Z_{NC-k} through the same LDS buffer, and the last
@@ -25,10 +25,13 @@ using fft::dft16;
 constexpr int BNC = 16384;
 constexpr int BN = 2 * BNC;
 constexpr int BTH = 1024;
-constexpr int BLDS = BNC + BNC / 16;
+constexpr int BLDS = BNC;
 constexpr int BIG_MAX_LAMBDA = 12288;
 
-__device__ __forceinline__ int padb(int i) { return i + (i >> 4); }
+// LDS index of element i: its low four bits xor-ed with the next four, a
+// bijection on [0, BNC) that spreads the stride-16 accesses of the radix-16
+// passes over distinct banks without padding.
+__device__ __forceinline__ int padb(int i) { return i ^ ((i >> 4) & 15); }
 
 // v[r] *= w1^r, r = 1..R-1, by repeated multiplication.
 template <typename T, int R>
