@@ -31,11 +31,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per sample per kernel launch, FP64 (weights 16 B, index 4 B,
-# TOD 8 B).  P: pixel index + weights + y written; P^T: permutation + sorted
-# weights + z gathered; direct band: y + z.  The FFT's figure depends on the
-# overlap-save geometry and is computed by fft_bytes_per_sample.
-ALG_BYTES = {"P": 28.0, "PT": 28.0, "Ninv_band": 16.0}
+# Algorithmic bytes per sample per kernel launch, FP64 (index 4 B, angle 8 B,
+# TOD 8 B; the weights are formed from the angle in the kernels).  P: map-slot
+# index + angle read, y written; P^T: sample index + angle of the sliced
+# layout + z gathered (its ~8 % padding entries not counted); direct band:
+# y + z.  The FFT's figure depends on the overlap-save geometry and is computed
+# by fft_bytes_per_sample.
+ALG_BYTES = {"P": 20.0, "PT": 20.0, "Ninv_band": 16.0}
 
 
 def fft_bytes_per_sample(interval_start, lam: int, n_valid: int, elem: int = 8) -> float:

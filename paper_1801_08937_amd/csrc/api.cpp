@@ -368,6 +368,7 @@ extern "C" mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t w
         p->grid_width = width;
     }
     pointing_slices_device(ctx, p, width);
+    pointing_p_slots_device(ctx, p, width);
     API_END
     return MM_OK;
 }

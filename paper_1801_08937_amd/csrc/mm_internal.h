@@ -105,7 +105,7 @@ struct mm_ctx {
     mm::DBuf red;                  // reduction partials
     mm::DBuf scal;                 // small device scalars
     mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
-    mm::DBuf xpack;                // map packed as (I, Q, U, 0) records for P
+    mm::DBuf xpack;                // map repacked for P: (I, Q, U, 0) records, or I and (Q, U) split
     mm::DBuf pt_part;              // per-segment partial maps of the sliced P^T
     // Bumped whenever one of the workspaces above is reallocated: captured
     // graphs hold their addresses and are re-captured when it changes.
@@ -133,6 +133,11 @@ struct mm_pointing {
     mm_precision prec = MM_F64;
     mm::DBuf hits, obs_pix, j, w, perm, ws, off;
     mm::DBuf psi;  // f64[n_samp] angles (FP64 form only)
+    // Map slots of the single-column FP64 P: with a grid, observed pixels are
+    // numbered in Morton order of (x, y) (p_slot[c]) and p_j[t] is the slot of
+    // sample t's pixel (-1 flagged), so neighbouring pixels share cache lines
+    // whatever the scan direction; without a grid the slot is the compact id.
+    mm::DBuf p_slot, p_j;
     int32_t max_seg = 0;
     // Order in which P^T visits the compact pixels (empty = ascending).  Each
     // pixel's own sum is independent of it; it only shapes cache locality.
@@ -204,6 +209,8 @@ void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_
 // (Re)build the sliced P^T layout; width > 0 groups 8 x 8 pixel blocks of a
 // row-major grid of that width into slices, width 0 takes ascending pixels.
 void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width);
+// (Re)build the Morton map slots of the FP64 P (width > 0), or drop them.
+void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width);
 
 // tod_ops.hip
 void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y);

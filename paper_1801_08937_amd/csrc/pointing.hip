@@ -111,6 +111,38 @@ __global__ void k_tile_keys(const int32_t *__restrict__ obs_pix, int32_t n_obs, 
     vals[c] = c;
 }
 
+// Morton key of an observed pixel's grid position (16 bits per coordinate,
+// interleaved) with its compact id as the value.
+__device__ __forceinline__ uint32_t spread16(uint32_t v) {
+    v &= 0xffff;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+__global__ void k_morton_keys(const int32_t *__restrict__ obs_pix, int32_t n_obs, int32_t width,
+                              uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int32_t c = blockIdx.x * BS + threadIdx.x;
+    if (c >= n_obs) return;
+    const int64_t g = obs_pix[c];
+    const uint32_t x = (uint32_t)(g % width), y = (uint32_t)(g / width);
+    keys[c] = ((uint64_t)(spread16(y) << 1 | spread16(x)) << 32) | (uint32_t)c;
+    vals[c] = c;
+}
+// slot[order[r]] = r
+__global__ void k_rank(const int32_t *__restrict__ order, int32_t n, int32_t *__restrict__ slot) {
+    const int32_t r = blockIdx.x * BS + threadIdx.x;
+    if (r < n) slot[order[r]] = r;
+}
+__global__ void k_slot_of_sample(const int32_t *__restrict__ j, const int32_t *__restrict__ slot,
+                                 int64_t n, int32_t *__restrict__ pj) {
+    for (int64_t t = blockIdx.x * (int64_t)BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+        const int32_t c = j[t];
+        pj[t] = c >= 0 ? slot[c] : -1;
+    }
+}
+
 // Sliced P^T layout.  Lane (g, l) finds, by binary search in its pixel's
 // time-sorted list perm[off[c], off[c+1]), where each time segment
 // [n s / S, n (s+1) / S) starts; cnt / start are stored per (s G + g, l).
@@ -212,6 +244,39 @@ int grid_for(int64_t n, int max_blocks = 8192) {
 }
 
 }  // namespace
+
+// Map slots of the FP64 P in Morton order of the grid (width > 0), or none.
+void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
+    hipStream_t s = ctx->stream;
+    p->p_slot.release();
+    p->p_j.release();
+    const int32_t n_obs = p->n_obs;
+    if (width <= 0 || n_obs == 0 || p->prec != MM_F64) return;
+    DBuf keys, vals, ko, order, tmp;
+    keys.alloc(sizeof(uint64_t) * n_obs);
+    vals.alloc(sizeof(int32_t) * n_obs);
+    ko.alloc(sizeof(uint64_t) * n_obs);
+    order.alloc(sizeof(int32_t) * n_obs);
+    k_morton_keys<<<(n_obs + BS - 1) / BS, BS, 0, s>>>(p->obs_pix.as<int32_t>(), n_obs, width,
+                                                       keys.as<uint64_t>(), vals.as<int32_t>());
+    size_t tb = 0;
+    MM_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
+                                     vals.as<int32_t>(), order.as<int32_t>(), (size_t)n_obs, 0u,
+                                     64u, s));
+    tmp.alloc(tb + 16);
+    MM_HIP(rocprim::radix_sort_pairs(tmp.ptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
+                                     vals.as<int32_t>(), order.as<int32_t>(), (size_t)n_obs, 0u,
+                                     64u, s));
+    p->p_slot.alloc(sizeof(int32_t) * n_obs);
+    k_rank<<<(n_obs + BS - 1) / BS, BS, 0, s>>>(order.as<int32_t>(), n_obs,
+                                                p->p_slot.as<int32_t>());
+    p->p_j.alloc(sizeof(int32_t) * p->n_samp);
+    k_slot_of_sample<<<grid_for(p->n_samp), BS, 0, s>>>(p->j.as<int32_t>(),
+                                                        p->p_slot.as<int32_t>(), p->n_samp,
+                                                        p->p_j.as<int32_t>());
+    MM_HIP(hipGetLastError());
+    MM_HIP(hipStreamSynchronize(s));
+}
 
 void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_t tile) {
     hipStream_t s = ctx->stream;

@@ -112,21 +112,38 @@ __global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpi
 }
 
 // Single column, FP64: the weights are formed from the stored angles, so a
-// sample costs its pixel index and angle (12 bytes) instead of index and two
-// weights (20 bytes).
+// sample costs its map slot and angle (12 bytes) instead of index and two
+// weights (20 bytes).  The map is split into I (8 bytes) and (Q, U) (16
+// bytes) per slot; with a grid the slots follow Morton order, so the pixels
+// of 64 consecutive samples fall in few cache lines whatever the scan
+// direction.  Same arithmetic and order as k_apply_P (bitwise the same y).
+__global__ void __launch_bounds__(BS) k_pack_map_split(const double *__restrict__ x,
+                                                       int32_t n_obs,
+                                                       const int32_t *__restrict__ slot,
+                                                       double *__restrict__ xi,
+                                                       double2 *__restrict__ xqu) {
+    for (int64_t c = (int64_t)blockIdx.x * BS + threadIdx.x; c < n_obs;
+         c += (int64_t)gridDim.x * BS) {
+        const int64_t s = slot ? slot[c] : c;
+        xi[s] = x[3 * c];
+        xqu[s] = make_double2(x[3 * c + 1], x[3 * c + 2]);
+    }
+}
+
 __device__ __forceinline__ double p_gather_psi(int32_t j, double psi,
-                                               const double2 *__restrict__ x4) {
+                                               const double *__restrict__ xi,
+                                               const double2 *__restrict__ xqu) {
     if (j < 0) return 0.0;
     double c, s;
     pol_weights(psi, c, s);
-    const double2 iq = x4[2 * (int64_t)j];
-    const double u = x4[2 * (int64_t)j + 1].x;
-    return iq.x + c * iq.y + s * u;
+    const double2 qu = xqu[j];
+    return xi[j] + c * qu.x + s * qu.y;
 }
 
 __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__ jpix,
                                                      const double *__restrict__ psi, int64_t n,
-                                                     const double2 *__restrict__ x4,
+                                                     const double *__restrict__ xi,
+                                                     const double2 *__restrict__ xqu,
                                                      double *__restrict__ y) {
     const int64_t step = (int64_t)gridDim.x * BS;
     int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -139,9 +156,9 @@ __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__
             a[q] = psi[t + q * step];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y[t + q * step] = p_gather_psi(j[q], a[q], x4);
+        for (int q = 0; q < 4; ++q) y[t + q * step] = p_gather_psi(j[q], a[q], xi, xqu);
     }
-    for (; t < n; t += step) y[t] = p_gather_psi(jpix[t], psi[t], x4);
+    for (; t < n; t += step) y[t] = p_gather_psi(jpix[t], psi[t], xi, xqu);
 }
 
 // Pixels are visited in the order `order` (NULL = ascending), e.g. square
@@ -423,19 +440,28 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
     Scope sc(ctx->prof, ctx->stream, "P");
     const int64_t n = p->n_samp;
     if (nrhs == 1) {
-        ws_alloc(ctx, ctx->xpack, sizeof(double2) * 2 * (size_t)(p->n_obs > 0 ? p->n_obs : 1));
-        k_pack_map<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(x, p->n_obs,
-                                                                    ctx->xpack.as<double2>());
+        const size_t no = (size_t)(p->n_obs > 0 ? p->n_obs : 1);
+        ws_alloc(ctx, ctx->xpack, sizeof(double2) * 2 * no);
         const int tuned = p->p_blocks[0];
-        const int grid = tuned > 0 ? tuned : grid_for(n, 8 * ctx->n_cu * 4);
-        if (p->prec == MM_F32)
+        if (p->prec == MM_F32) {
+            k_pack_map<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(
+                x, p->n_obs, ctx->xpack.as<double2>());
+            const int grid = tuned > 0 ? tuned : grid_for(n, 8 * ctx->n_cu * 4);
             k_apply_P1<float><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), p->w.as<float2>(),
                                                             n, ctx->xpack.as<double2>(),
                                                             static_cast<float *>(y));
-        else
-            k_apply_P1_psi<<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), p->psi.as<double>(),
-                                                         n, ctx->xpack.as<double2>(),
-                                                         static_cast<double *>(y));
+        } else {
+            // xpack holds I (n_obs doubles) then (Q, U) (n_obs double2)
+            double *xi = ctx->xpack.as<double>();
+            double2 *xqu = reinterpret_cast<double2 *>(xi + 2 * ((no + 1) / 2));
+            const bool slots = p->p_j.ptr != nullptr;
+            k_pack_map_split<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(
+                x, p->n_obs, slots ? p->p_slot.as<int32_t>() : nullptr, xi, xqu);
+            const int grid = tuned > 0 ? tuned : grid_for(n, 32 * ctx->n_cu * 4);
+            k_apply_P1_psi<<<grid, BS, 0, ctx->stream>>>(
+                slots ? p->p_j.as<int32_t>() : p->j.as<int32_t>(), p->psi.as<double>(), n, xi, xqu,
+                static_cast<double *>(y));
+        }
         MM_HIP(hipGetLastError());
         return;
     }

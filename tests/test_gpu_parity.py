@@ -542,7 +542,8 @@ def test_autotune_keeps_results_bitwise(ctx):
 def test_PT_sliced_layout_parity_and_order(ctx):
     """The sliced single-column P^T (one pixel per lane, time segments summed
     in order) on a cross-linked scan: parity with the oracle,
-    bitwise independence of the grid grouping, agreement with the
+    bitwise independence of the grid grouping (also for P's Morton-ordered
+    map slots), agreement with the
     one-wave-per-pixel form used for several columns, and the FP32 form
     (2^23 samples, 16,384 pixels: 256 slices x 14 segments)."""
     import torch
@@ -555,9 +556,14 @@ def test_PT_sliced_layout_parity_and_order(ctx):
     a = ctx.apply_PT(lp, dev(y))
     ref = O.apply_PT(op, y)
     assert maxrel(host(a), ref) <= TOL_OP
+    xm = rng.standard_normal(op.n)
+    yp = ctx.apply_P(lp, dev(xm))
+    assert maxrel(host(yp), O.apply_P(op, xm)) <= TOL_OP
     lp.set_grid(p.n_side)
     assert lp.pt_layout() == (G, S)
     assert torch.equal(a, ctx.apply_PT(lp, dev(y)))
+    # P through the Morton-ordered map slots: bitwise the same
+    assert torch.equal(yp, ctx.apply_P(lp, dev(xm)))
     Y2 = np.stack([y, rng.standard_normal(op.n_samp)], axis=1)
     a2 = host(ctx.apply_PT(lp, dev(Y2.reshape(-1)), nrhs=2)).reshape(-1, 2)
     assert maxrel(a2[:, 0], host(a)) <= TOL_OP
