@@ -301,11 +301,15 @@ void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_
 }
 
 // Time segments for the sliced P^T: enough (segment, slice) waves to fill
-// the device (8,192 = 32 per CU on 256 CUs) with at least 32 entries per lane
-// and segment on average; a fixed target, so the summation order (and the
-// bits of the result) does not depend on the device.
-static int32_t slice_segments(int64_t n_valid, int32_t n_obs, int32_t G) {
+// the device (8,192 = 32 per CU on 256 CUs), and at least one segment per 2^22
+// samples of time, so that the stretch of the TOD the resident waves gather from at
+// any moment stays small enough for the L2 (at 1.34e8 samples: 32 segments,
+// measured best among 8..128); at most 64, and at least 32 entries per lane
+// and segment on average.  A function of the problem size only, so the
+// summation order (and the bits of the result) does not depend on the device.
+static int32_t slice_segments(int64_t n_samp, int64_t n_valid, int32_t n_obs, int32_t G) {
     int64_t S = 8192 / G;
+    if (S < (n_samp >> 22)) S = n_samp >> 22;
     if (S > 64) S = 64;
     const int64_t cap = n_obs > 0 ? n_valid / n_obs / 32 : 0;
     if (S > cap) S = cap;
@@ -322,7 +326,7 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     const int32_t n_obs = p->n_obs;
     if (n_obs == 0 || p->n_valid == 0) return;
     const int32_t G = (n_obs + 63) / 64;
-    const int32_t S = slice_segments(p->n_valid, n_obs, G);
+    const int32_t S = slice_segments(p->n_samp, p->n_valid, n_obs, G);
     // below ~2,048 waves the one-wave-per-pixel kernel is the faster one
     if ((int64_t)G * S < 2048) return;
 
