@@ -12,6 +12,7 @@
 
 #include "mm_internal.h"
 #include "pol_weights.h"
+#include "xcd.h"
 
 namespace mm {
 
@@ -19,13 +20,6 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 
-// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
-// works on a contiguous range of logical blocks (neighbouring pixels share
-// their TOD cache lines in that XCD's L2).
-__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nb) {
-    if ((nb & 7) != 0) return bid;
-    return (bid & 7) * (nb >> 3) + (bid >> 3);
-}
 
 namespace {
 
