@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -148,7 +148,7 @@ def main():
     if args.form:
         torch.cuda.init()
         ctx = mm.Context(0)
-        fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4,
+        fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -510,6 +510,52 @@ def form_c4(mm, ctx):
             out[f"{tag}_{mname}"] = res
     return {"form": "c4", "workload": "64 realizations (CMB-like sky + noise each) on config 1's "
             "pointing and noise model, tol 1e-8", **out}
+
+
+def form_f1(mm, ctx):
+    """The paper's own weight on the config-2 scan: white noise and the
+    polynomial template filter F = W - W B (B^T W B)^-1 B^T W with quadratic
+    Legendre polynomials per subscan (one 256-sample sweep), A = P^T F P.
+    The filter leaves near-null sky modes (Sect. 4): M_BD against M_2l."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    p = synth.config2()
+    pix, psi = torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.psi).to(dev)
+    lp = ctx.pointing(pix, psi, p.n_pix_total, p.min_hits)
+    lp.set_grid(p.n_side)
+    sub = np.arange(0, p.n_samp + 1, 256, dtype=np.int64)
+    w = np.ones(p.n_intervals)
+    (lf, t_build) = _wall(lambda: ctx.polyfilter(lp, p.interval_start, w, sub, 2))
+    d = synth.signal_tod(p.pix, p.psi, p.signal) + \
+        synth.rng_for(2, 0, synth.STREAM_NOISE).standard_normal(p.n_samp)
+    y = torch.randn(p.n_samp, dtype=torch.float64, device=dev)
+    x = torch.randn(lp.n, dtype=torch.float64, device=dev)
+    out = {"filter_build_s": t_build}
+    for name, fn in (("F_apply_ms", lambda: ctx.noise_apply(lf, y)),
+                     ("A_apply_ms", lambda: ctx.apply_A(lp, lf, x))):
+        for _ in range(3):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(ctx.stream)
+        for _ in range(20):
+            fn()
+        ev[1].record(ctx.stream)
+        ev[1].synchronize()
+        out[name] = ev[0].elapsed_time(ev[1]) / 20
+    out["F_GBps_16B_per_sample"] = 16.0 * p.n_samp / (out["F_apply_ms"] * 1e-3) / 1e9
+    b = ctx.rhs(lp, lf, torch.from_numpy(d).to(dev))
+    Mbd = ctx.mbd(lp, lf)
+    (M2, t_m2l) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=32, eps_arn=1e-8, m_max=256))
+    out["m2l_setup_s"] = t_m2l
+    for name, M in (("mbd", Mbd), ("m2l", M2)):
+        ((xs, info), t) = _wall(lambda: ctx.solve(lp, lf, M, b, tol=1e-8, max_iter=3000,
+                                                  check_every=4, history=False))
+        out[name] = {"iters": info["iters"], "converged": info["converged"],
+                     "rel_res_true": info["rel_res_true"], "solve_s": t}
+    return {"form": "f1", "workload": "config-2 scan (1.34e8 samples), white noise, quadratic "
+            "Legendre polynomials removed per 256-sample subscan (F_T of Sect. 2), "
+            "M_BD vs M_2l (k = 32), tol 1e-8", **out}
 
 
 def form_c5(mm, ctx, n_requests=200, slots=1):

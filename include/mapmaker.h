@@ -70,8 +70,14 @@ typedef enum {
 typedef enum { MM_F64 = 0, MM_F32 = 1 } mm_precision;
 
 /* How N^-1 is applied: AUTO picks FFT for half bandwidths >= 256 when the
- * interval lengths allow it, else the direct band. */
-typedef enum { MM_NOISE_AUTO = 0, MM_NOISE_DIRECT = 1, MM_NOISE_FFT = 2 } mm_noise_method;
+ * interval lengths allow it, else the direct band.  MM_NOISE_POLY marks a
+ * weight built by mm_polyfilter_build (a template filter, not a band). */
+typedef enum {
+    MM_NOISE_AUTO = 0,
+    MM_NOISE_DIRECT = 1,
+    MM_NOISE_FFT = 2,
+    MM_NOISE_POLY = 3
+} mm_noise_method;
 
 typedef struct mm_ctx mm_ctx;
 typedef struct mm_pointing mm_pointing;
@@ -146,13 +152,38 @@ mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals, const int64_t *interv
                          const int32_t *filter_id, int32_t n_filters, int32_t half_bw,
                          const double *band, mm_noise_method method, mm_precision prec,
                          mm_noise **out);
-/* The method actually used (MM_NOISE_DIRECT or MM_NOISE_FFT). */
+/* Polynomial template filter as the time-domain weight, in place of N^-1
+ * (Sect. 2, Eqs. filt and filtnoise; Sect. 4: long modes are removed by
+ * low-order polynomials per subscan, the remaining noise taken as white):
+ *     F = W - W B (B^T W B)^-1 B^T W,
+ * B block diagonal over subscans, each block the Legendre polynomials of
+ * degree 0..order of the subscan time mapped onto [-1, 1] (F depends only on
+ * their span); W = diag(w), w_t = weight of the sample's interval times the
+ * flag mask of pointing p (flagged samples neither weigh in a fit nor receive
+ * output).  A subscan with at most order + 1 weighted samples is fitted
+ * exactly: its output is 0.  M_BD built on this handle uses diag(W)
+ * (Eq. mbd), and A = P^T F P, b = P^T F d follow (Eqs. unb, linearsystem).
+ *   p               the pointing (its n_samp, precision and flags)
+ *   interval_start  [host] int64[n_intervals+1], tiles [0, n_samp)
+ *   weight          [host] f64[n_intervals] >= 0 (inverse white-noise variance)
+ *   subscan_start   [host] int64[n_subscans+1], tiles [0, n_samp); every
+ *                   subscan lies inside one interval
+ *   order           0..7
+ * The handle keeps copies (it does not refer to p afterwards).
+ * Errors: MM_E_INVALID (tiling, a subscan across intervals, order, weight < 0),
+ * MM_E_NONFINITE (weight). */
+mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int32_t n_intervals,
+                              const int64_t *interval_start, const double *weight,
+                              int64_t n_subscans, const int64_t *subscan_start, int32_t order,
+                              mm_noise **out);
+/* The method actually used (MM_NOISE_DIRECT, MM_NOISE_FFT or MM_NOISE_POLY). */
 mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method);
 /* Overlap-save block geometry of the FFT method (Sect. 3, the Toeplitz apply
  * as a circulant product): each block transforms *n_fft samples and keeps
  * *n_valid = *n_fft - 2 lambda outputs.  Both 0 for the direct method. */
 mm_status mm_noise_fft_block(const mm_noise *nz, int32_t *n_fft, int32_t *n_valid);
-/* z = N^-1 y on the TOD layout.  y, z [device], TOD precision, distinct. */
+/* z = N^-1 y (or z = F y for a template filter) on the TOD layout.  y, z
+ * [device], TOD precision, distinct. */
 mm_status mm_noise_apply(mm_ctx *ctx, const mm_noise *nz, int32_t nrhs, const void *y, void *z);
 void mm_noise_destroy(mm_noise *nz);
 

@@ -35,7 +35,8 @@ __all__ = [
     "noise_build", "noise_apply_direct", "noise_apply_fft", "noise_apply",
     "apply_A", "apply_A_pixels", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
     "m2l_apply", "arnoldi", "ritz_select", "defl_build", "pcg", "SolveInfo",
-    "dense_P", "dense_Ninv",
+    "dense_P", "dense_Ninv", "PolyFilter", "polyfilter_build", "polyfilter_apply",
+    "dense_polyfilter",
 ]
 
 
@@ -212,7 +213,89 @@ def noise_apply_fft(nz: Noise, y) -> np.ndarray:
 
 
 def noise_apply(nz: Noise, y, method: str = "direct") -> np.ndarray:
+    if isinstance(nz, PolyFilter):
+        return polyfilter_apply(nz, y)
     return noise_apply_fft(nz, y) if method == "fft" else noise_apply_direct(nz, y)
+
+
+# ---------------------------------------------------------------------------
+# polynomial template filter as the weight (Sect. 2, Eqs. filt and filtnoise)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PolyFilter:
+    """F = W - W B (B^T W B)^-1 B^T W with B the piecewise Legendre
+    polynomials of degree 0..order on each subscan (Sect. 4: long modes
+    filtered by low-order polynomials per subscan) and W = diag(w), w_t the
+    white-noise weight of the sample's interval times the flag mask.  It
+    duck-types as a Noise (interval_start, filter_id, band with half_bw = 0,
+    band[i, 0] = omega_i), so diag(W) enters M_BD like c_0 does (Eq. mbd)."""
+    interval_start: np.ndarray   # int64[n_int+1]
+    filter_id: np.ndarray        # int32[n_int] = arange
+    band: np.ndarray             # f64[n_int, 1] interval weights omega_i
+    half_bw: int                 # 0
+    subscan_start: np.ndarray    # int64[n_sub+1]
+    order: int
+    w: np.ndarray                # f64[n_samp] omega of the interval x mask
+
+
+def polyfilter_build(pt: Pointing, interval_start, weight, subscan_start, order: int) -> PolyFilter:
+    istart = np.asarray(interval_start, dtype=np.int64)
+    wgt = np.asarray(weight, dtype=np.float64)
+    sub = np.asarray(subscan_start, dtype=np.int64)
+    if istart[0] != 0 or istart[-1] != pt.n_samp or np.any(np.diff(istart) <= 0):
+        raise OracleError("INVALID", "intervals must tile [0, n_samp)")
+    if sub[0] != 0 or sub[-1] != pt.n_samp or np.any(np.diff(sub) <= 0):
+        raise OracleError("INVALID", "subscans must tile [0, n_samp)")
+    if wgt.shape[0] != istart.shape[0] - 1 or np.any(wgt < 0) or not (0 <= order <= 7):
+        raise OracleError("INVALID", "one weight >= 0 per interval, order in [0, 7]")
+    # every subscan lies inside one interval
+    iv_a = np.searchsorted(istart, sub[:-1], side="right") - 1
+    iv_b = np.searchsorted(istart, sub[1:] - 1, side="right") - 1
+    if np.any(iv_a != iv_b):
+        raise OracleError("INVALID", "a subscan crosses an interval boundary")
+    w = np.empty(pt.n_samp)
+    for i in range(wgt.shape[0]):
+        w[istart[i]:istart[i + 1]] = wgt[i]
+    w = np.where(pt.j >= 0, w, 0.0)
+    return PolyFilter(istart, np.arange(wgt.shape[0], dtype=np.int32), wgt[:, None].copy(), 0,
+                      sub, int(order), w)
+
+
+def _subscan_u(L: int) -> np.ndarray:
+    """Subscan time mapped onto [-1, 1] (the Legendre interval)."""
+    if L == 1:
+        return np.zeros(1)
+    return -1.0 + 2.0 * np.arange(L, dtype=np.float64) / (L - 1)
+
+
+def polyfilter_apply(pf: PolyFilter, y) -> np.ndarray:
+    """z = W y - W B (B^T W B)^-1 B^T W y, subscan by subscan.  A subscan
+    with at most order + 1 weighted samples is fitted exactly by the
+    polynomials, so its output is 0 (the pseudo-inverse value)."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.zeros_like(y)
+    p = pf.order
+    for s in range(pf.subscan_start.shape[0] - 1):
+        a, b = int(pf.subscan_start[s]), int(pf.subscan_start[s + 1])
+        w = pf.w[a:b]
+        if np.count_nonzero(w > 0) <= p + 1:
+            continue
+        B = np.polynomial.legendre.legvander(_subscan_u(b - a), p)
+        G = B.T @ (w[:, None] * B)
+        c = np.linalg.solve(G, B.T @ (w * y[a:b]))
+        z[a:b] = w * (y[a:b] - B @ c)
+    return z
+
+
+def dense_polyfilter(pf: PolyFilter) -> np.ndarray:
+    n = pf.w.shape[0]
+    F = np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        F[:, i] = polyfilter_apply(pf, e)
+    return F
 
 
 def dense_Ninv(nz: Noise) -> np.ndarray:
@@ -402,24 +485,36 @@ def arnoldi(apply_B, r0, m_max: int, eps_arn: float, reorth: bool = True) -> Arn
     return ArnoldiResult(W[:, :m + 1], H[:m + 1, :m], m, h_last)
 
 
+NULL_RITZ_REL = 1e-10
+
+
 def ritz_select(H_m: np.ndarray, k: int, eps_lambda: float = 0.0):
     """Eigenpairs of the m x m Hessenberg matrix (numpy's LAPACK eig), ordered
-    by real part ascending.  Keep the k smallest (k+1 if that would split a
-    conjugate pair) or, with eps_lambda > 0, all with Re(theta) < eps_lambda.
+    by real part ascending.  Past the null directions (below), keep the k
+    smallest (k+1 if that would split a conjugate pair) or, with
+    eps_lambda > 0, all with Re(theta) < eps_lambda.
     Returns (theta_sorted, Y) with Y real: a complex pair contributes the real
     and imaginary parts of one of its vectors."""
     theta, Yc = np.linalg.eig(H_m)
     order = np.lexsort((theta.imag, theta.real))
     theta, Yc = theta[order], Yc[:, order]
     m = theta.shape[0]
+    # Ritz values at the rounding level (|theta| <= 1e-10 max |theta|) are exact
+    # null directions of M_BD A (sky modes a filter leaves unconstrained):
+    # E = Z^T A Z could not be inverted with them and a consistent right-hand
+    # side has no component along them, so they are left out of Z.
+    first = 0
+    tmax = float(np.max(np.abs(theta))) if m else 0.0
+    while first < m and abs(theta[first]) <= NULL_RITZ_REL * tmax:
+        first += 1
     if eps_lambda > 0:
         keep = int(np.sum(theta.real < eps_lambda))
     else:
-        keep = min(k, m)
+        keep = min(first + k, m)
     if 0 < keep < m and theta[keep - 1].imag != 0 and np.conj(theta[keep - 1]) == theta[keep]:
         keep += 1
     cols = []
-    i = 0
+    i = first
     while i < keep:
         if theta[i].imag != 0 and i + 1 < m and np.conj(theta[i]) == theta[i + 1]:
             cols.append(Yc[:, i].real)

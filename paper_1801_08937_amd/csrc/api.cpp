@@ -508,6 +508,80 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
     return MM_OK;
 }
 
+extern "C" mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int32_t n_intervals,
+                                         const int64_t *interval_start, const double *weight,
+                                         int64_t n_subscans, const int64_t *subscan_start,
+                                         int32_t order, mm_noise **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    MM_CHECK(p, MM_E_INVALID, "polyfilter: null pointing");
+    MM_CHECK(n_intervals > 0 && interval_start && weight && n_subscans > 0 && subscan_start,
+             MM_E_INVALID, "polyfilter: empty or null arguments");
+    MM_CHECK(order >= 0 && order <= polyfilter_max_order(), MM_E_INVALID,
+             "polyfilter: order must be in [0, 7]");
+    const int64_t n = p->n_samp;
+    MM_CHECK(interval_start[0] == 0 && interval_start[n_intervals] == n, MM_E_INVALID,
+             "polyfilter: intervals must tile [0, n_samp)");
+    for (int i = 0; i < n_intervals; ++i) {
+        MM_CHECK(interval_start[i + 1] > interval_start[i], MM_E_INVALID,
+                 "polyfilter: intervals must be strictly increasing");
+        MM_CHECK(std::isfinite(weight[i]), MM_E_NONFINITE, "polyfilter: non-finite weight");
+        MM_CHECK(weight[i] >= 0, MM_E_INVALID, "polyfilter: negative weight");
+    }
+    MM_CHECK(subscan_start[0] == 0 && subscan_start[n_subscans] == n, MM_E_INVALID,
+             "polyfilter: subscans must tile [0, n_samp)");
+    std::vector<double> om((size_t)n_subscans);
+    int iv = 0;
+    for (int64_t s2 = 0; s2 < n_subscans; ++s2) {
+        const int64_t a = subscan_start[s2], b = subscan_start[s2 + 1];
+        MM_CHECK(b > a, MM_E_INVALID, "polyfilter: subscans must be strictly increasing");
+        while (interval_start[iv + 1] <= a) ++iv;
+        MM_CHECK(b <= interval_start[iv + 1], MM_E_INVALID,
+                 "polyfilter: a subscan crosses an interval boundary");
+        om[(size_t)s2] = weight[iv];
+    }
+    auto *nz = new mm_noise();
+    try {
+        nz->n_samp = n;
+        nz->n_int = n_intervals;
+        nz->n_filters = n_intervals;
+        nz->half_bw = 0;
+        nz->prec = p->prec;
+        nz->method = MM_NOISE_POLY;
+        nz->h_istart.assign(interval_start, interval_start + n_intervals + 1);
+        nz->h_fid.resize(n_intervals);
+        std::iota(nz->h_fid.begin(), nz->h_fid.end(), 0);
+        nz->h_band.assign(weight, weight + n_intervals);
+        hipStream_t s = ctx->stream;
+        nz->istart.alloc(sizeof(int64_t) * (n_intervals + 1));
+        nz->fid.alloc(sizeof(int32_t) * n_intervals);
+        nz->band64.alloc(sizeof(double) * n_intervals);
+        MM_HIP(hipMemcpyAsync(nz->istart.ptr, interval_start, sizeof(int64_t) * (n_intervals + 1),
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipMemcpyAsync(nz->fid.ptr, nz->h_fid.data(), sizeof(int32_t) * n_intervals,
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipMemcpyAsync(nz->band64.ptr, weight, sizeof(double) * n_intervals,
+                              hipMemcpyHostToDevice, s));
+        nz->pf_order = order;
+        nz->pf_n_sub = n_subscans;
+        nz->pf_sub.alloc(sizeof(int64_t) * (n_subscans + 1));
+        nz->pf_omega.alloc(sizeof(double) * n_subscans);
+        MM_HIP(hipMemcpyAsync(nz->pf_sub.ptr, subscan_start, sizeof(int64_t) * (n_subscans + 1),
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipMemcpyAsync(nz->pf_omega.ptr, om.data(), sizeof(double) * n_subscans,
+                              hipMemcpyHostToDevice, s));
+        MM_HIP(hipStreamSynchronize(s));
+        polyfilter_prepare(ctx, p, nz);
+    } catch (...) {
+        delete nz;
+        throw;
+    }
+    *out = nz;
+    API_END
+    return MM_OK;
+}
+
 extern "C" mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method) {
     if (!nz || !method) return MM_E_INVALID;
     *method = nz->method;
@@ -741,18 +815,26 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
         for (int j = 0; j < m; ++j)
             for (int i = 0; i < m; ++i) Hm[(size_t)j * m + i] = H[(size_t)j * (m_max + 1) + i];
         hessenberg_eig(m, Hm.data(), wr.data(), wi.data(), vr.data(), vi.data());
+        // Ritz values at the rounding level (|theta| <= 1e-10 max |theta|) are
+        // exact null directions of M_BD A (sky modes a filter leaves
+        // unconstrained): E could not be inverted with them, and a consistent
+        // right-hand side has no component along them.  They stay out of Z.
+        double tmax = 0;
+        for (int i = 0; i < m; ++i) tmax = std::max(tmax, std::hypot(wr[i], wi[i]));
+        int first = 0;
+        while (first < m && std::hypot(wr[first], wi[first]) <= 1e-10 * tmax) ++first;
         int keep;
         if (eps_lambda > 0) {
             keep = 0;
             while (keep < m && wr[keep] < eps_lambda) ++keep;
         } else {
-            keep = std::min(k, m);
+            keep = std::min(first + k, m);
         }
         auto pair_at = [&](int i) { return i + 1 < m && wi[i] != 0 && wi[i] == -wi[i + 1] && wr[i] == wr[i + 1]; };
         if (keep > 0 && keep < m && wi[keep - 1] != 0 && pair_at(keep - 1)) ++keep;
         std::vector<double> Y;
         int kk = 0;
-        for (int i = 0; i < keep && kk < 64;) {
+        for (int i = first; i < keep && kk < 64;) {
             if (pair_at(i)) {
                 if (kk + 2 > 64) break;
                 Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);

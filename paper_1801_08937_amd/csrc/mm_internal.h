@@ -183,6 +183,12 @@ struct mm_noise {
     mm::DBuf fft_tw;         // twiddles exp(-2 pi i m / (fft_n/2)), m < fft_n/2
     mm::DBuf fft_blocks;     // int64 pairs (first output sample, interval index)
     int64_t n_fft_blocks = 0;
+    // polynomial template filter (method MM_NOISE_POLY): subscan table, the
+    // weight of each subscan's interval, G_s^-1 per subscan ((p+1)^2 FP64,
+    // zeros for a subscan fitted exactly) and the flag mask as bits
+    int32_t pf_order = 0;
+    int64_t pf_n_sub = 0;
+    mm::DBuf pf_sub, pf_omega, pf_ginv, pf_mask;
 };
 
 struct mm_precond {
@@ -219,6 +225,10 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
 void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_rm, void *y,
                   int *nonfinite_flag);
 void noise_prepare(mm_ctx *ctx, mm_noise *nz);  // tiles, FFT spectra
+// polyfilter.hip
+int polyfilter_max_order();
+void polyfilter_prepare(mm_ctx *ctx, const mm_pointing *p, mm_noise *nz);
+void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
 bool noise_fft_supported(int half_bw, int64_t min_len);
 
 // map_ops.hip

@@ -525,6 +525,10 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
         noise_fft_apply_dev(ctx, nz, nrhs, y, z);
         return;
     }
+    if (nz->method == MM_NOISE_POLY) {
+        polyfilter_apply_dev(ctx, nz, nrhs, y, z);
+        return;
+    }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
     // Tile length: the tuned one, else the single-column default, grown with

@@ -24,7 +24,7 @@ STATUS = {0: "MM_OK", 1: "MM_NOT_CONVERGED", -1: "MM_E_INVALID", -2: "MM_E_OOM",
           -3: "MM_E_DEVICE", -4: "MM_E_SINGULAR_BLOCK", -5: "MM_E_COARSE_NOT_SPD",
           -6: "MM_E_BREAKDOWN", -7: "MM_E_NONFINITE", -8: "MM_E_BUSY"}
 F64, F32 = 0, 1
-NOISE_AUTO, NOISE_DIRECT, NOISE_FFT = 0, 1, 2
+NOISE_AUTO, NOISE_DIRECT, NOISE_FFT, NOISE_POLY = 0, 1, 2, 3
 
 
 class MapmakerError(RuntimeError):
@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
             "mm_pointing_destroy": (None, [P]),
             "mm_noise_build": (C.c_int, [P, I32, P, P, I32, I32, P, C.c_int, C.c_int, PP]),
             "mm_noise_method_used": (C.c_int, [P, C.POINTER(C.c_int)]),
+            "mm_polyfilter_build": (C.c_int, [P, P, I32, P, P, I64, P, I32, PP]),
             "mm_noise_fft_block": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "mm_noise_apply": (C.c_int, [P, P, I32, P, P]),
             "mm_noise_destroy": (None, [P]),
@@ -222,6 +223,18 @@ class Context:
                                          band.ctypes.data, method, prec, C.byref(h)),
                     "mm_noise_build")
         return Noise(self, h, int(istart[-1]), half_bw, prec)
+
+    def polyfilter(self, p, interval_start, weight, subscan_start, order: int):
+        """Polynomial template filter F = W - W B (B^T W B)^-1 B^T W (piecewise
+        Legendre polynomials of degree <= order per subscan) as the weight."""
+        istart = np.ascontiguousarray(interval_start, dtype=np.int64)
+        w = np.ascontiguousarray(weight, dtype=np.float64)
+        sub = np.ascontiguousarray(subscan_start, dtype=np.int64)
+        h = C.c_void_p()
+        self._check(lib().mm_polyfilter_build(self.h, p.h, istart.shape[0] - 1, istart.ctypes.data,
+                                              w.ctypes.data, sub.shape[0] - 1, sub.ctypes.data,
+                                              order, C.byref(h)), "mm_polyfilter_build")
+        return Noise(self, h, p.n_samp, 0, p.prec)
 
     # ------------------------------------------------------------ operators
     def _tod_dtype(self, prec):

@@ -467,3 +467,117 @@ def test_m2l_fewer_iterations_than_mbd():
     assert i1.converged and i2.converged
     assert i2.iters <= i1.iters
     assert i2.rel_res_true <= 1e-8 * 1.5
+
+
+# ------------------------------------------ polynomial template filter (Sect. 2)
+
+def _pf_problem(seed=0, order=2, flag_frac=0.05):
+    """A tiny problem with ragged subscans inside intervals and per-interval
+    white-noise weights."""
+    p = synth.random_problem(seed, n_side=8, n_samp=1600, n_int=4, half_bw=5, n_filters=2,
+                             flag_frac=flag_frac)
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    rng = np.random.default_rng(seed + 100)
+    starts = [0]
+    for i in range(p.n_intervals):  # cut every interval into subscans of 5..120 samples
+        a, b = int(p.interval_start[i]), int(p.interval_start[i + 1])
+        t = a
+        while t < b:
+            t = min(b, t + int(rng.integers(5, 121)))
+            starts.append(t)
+    weight = rng.uniform(0.5, 2.0, p.n_intervals)
+    pf = O.polyfilter_build(pt, p.interval_start, weight, np.array(starts), order)
+    return p, pt, pf
+
+
+def _F_monomial(pf):
+    """F from Eq. filtnoise with an explicit monomial basis and dense algebra:
+    a different basis and a different code path from the oracle's; only the
+    span of the templates matters."""
+    n = pf.w.shape[0]
+    F = np.zeros((n, n))
+    p = pf.order
+    for s in range(pf.subscan_start.shape[0] - 1):
+        a, b = int(pf.subscan_start[s]), int(pf.subscan_start[s + 1])
+        w = pf.w[a:b]
+        if np.count_nonzero(w > 0) <= p + 1:
+            continue
+        tt = np.arange(b - a, dtype=np.float64) / max(b - a - 1, 1)
+        T = np.vander(tt, p + 1, increasing=True)
+        W = np.diag(w)
+        F[a:b, a:b] = W - W @ T @ np.linalg.inv(T.T @ W @ T) @ T.T @ W
+    return F
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_polyfilter_matches_monomial_definition(order):
+    _, _, pf = _pf_problem(1, order)
+    F = O.dense_polyfilter(pf)
+    Fm = _F_monomial(pf)
+    assert np.max(np.abs(F - Fm)) <= 1e-9 * np.max(np.abs(Fm))
+
+
+def test_polyfilter_removes_templates_and_is_a_weighted_projector():
+    _, _, pf = _pf_problem(2, 2)
+    rng = np.random.default_rng(3)
+    # F T = 0: any piecewise polynomial of degree <= 2 is removed
+    y = np.zeros(pf.w.shape[0])
+    for s in range(pf.subscan_start.shape[0] - 1):
+        a, b = int(pf.subscan_start[s]), int(pf.subscan_start[s + 1])
+        t = np.arange(b - a, dtype=np.float64)
+        y[a:b] = rng.standard_normal() + rng.standard_normal() * t + rng.standard_normal() * t * t
+    assert np.max(np.abs(O.polyfilter_apply(pf, y))) <= 1e-9 * np.max(np.abs(pf.w * y))
+    # symmetric, positive semi-definite, F W^+ F = F
+    F = O.dense_polyfilter(pf)
+    assert np.max(np.abs(F - F.T)) <= 1e-12 * np.max(np.abs(F))
+    assert np.min(np.linalg.eigvalsh(F)) >= -1e-10
+    Wp = np.where(pf.w > 0, 1.0 / np.where(pf.w > 0, pf.w, 1.0), 0.0)
+    assert np.max(np.abs(F @ (Wp[:, None] * F) - F)) <= 1e-9 * np.max(np.abs(F))
+
+
+def test_polyfilter_order0_is_weighted_mean_removal():
+    _, _, pf = _pf_problem(4, 0)
+    y = np.random.default_rng(5).standard_normal(pf.w.shape[0])
+    z = O.polyfilter_apply(pf, y)
+    for s in range(pf.subscan_start.shape[0] - 1):
+        a, b = int(pf.subscan_start[s]), int(pf.subscan_start[s + 1])
+        w = pf.w[a:b]
+        if np.count_nonzero(w > 0) <= 1:
+            assert np.all(z[a:b] == 0)
+            continue
+        ref = w * (y[a:b] - np.sum(w * y[a:b]) / np.sum(w))
+        assert np.max(np.abs(z[a:b] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_polyfilter_flags_and_short_subscans():
+    p, pt, pf = _pf_problem(6, 3, flag_frac=0.2)
+    y = np.random.default_rng(7).standard_normal(pt.n_samp)
+    z = O.polyfilter_apply(pf, y)
+    assert np.all(z[pt.j < 0] == 0)  # flagged samples carry no weight
+    # a subscan with at most order + 1 weighted samples is fitted exactly
+    sub = np.array([0, 3, 10, pt.n_samp], dtype=np.int64)
+    ist = np.array([0, pt.n_samp], dtype=np.int64)
+    pf2 = O.polyfilter_build(pt, ist, [1.0], sub, 3)
+    z2 = O.polyfilter_apply(pf2, y)
+    assert np.all(z2[0:3] == 0)
+    # a subscan may not cross an interval boundary
+    bad = np.array([0, int(p.interval_start[1]) + 1, pt.n_samp], dtype=np.int64)
+    with pytest.raises(O.OracleError):
+        O.polyfilter_build(pt, p.interval_start, np.ones(p.n_intervals), bad, 1)
+
+
+def test_polyfilter_degenerate_mode_of_A():
+    """Sect. 4: a sky mode whose time stream lies in the template span is
+    lost, P s = T y => P^T F P s = 0.  A constant intensity map is constant
+    on every subscan."""
+    _, pt, pf = _pf_problem(8, 1)
+    s = np.zeros(3 * pt.obs_pix.shape[0])
+    s[0::3] = 7.0
+    As = O.apply_A(pt, pf, s)
+    x = np.random.default_rng(9).standard_normal(s.shape[0])
+    assert np.max(np.abs(As)) <= 1e-10 * np.max(np.abs(O.apply_A(pt, pf, x)))
+    # and A = P^T F P is symmetric positive semi-definite
+    P = O.dense_P(pt)
+    A = P.T @ O.dense_polyfilter(pf) @ P
+    assert np.max(np.abs(A - A.T)) <= 1e-10 * np.max(np.abs(A))
+    assert np.min(np.linalg.eigvalsh(A)) >= -1e-8 * np.max(np.abs(A))
