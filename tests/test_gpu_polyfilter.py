@@ -146,3 +146,37 @@ def test_polyfilter_errors(ctx):
         ctx.polyfilter(lp, p.interval_start, np.ones(p.n_intervals), ok, 8)
     with pytest.raises(mm.MapmakerError):
         ctx.polyfilter(lp, p.interval_start, -np.ones(p.n_intervals), ok, 1)
+
+
+def test_transferred_deflation_space(ctx):
+    """The "simplified" two-level preconditioner of the divide-and-conquer run
+    (Sect. 6.3): Z built by Arnoldi on one subset of detectors, moved to
+    another subset's pixels, with AZ and E rebuilt there.  It is a valid M_2l
+    (Eq. ident holds on the new subset) and it still beats M_BD."""
+    import torch
+    from bench import transfer_Z
+    p = synth.config2(n_side=32, grid=(4, 2), samp_per_det=1 << 12, L=1 << 11, half_bw=10)
+    half = p.n_samp // 2
+    ih = p.n_intervals // 2
+    subs = []
+    for k in range(2):
+        sl = slice(k * half, (k + 1) * half)
+        lp = ctx.pointing(dev(p.pix[sl]), dev(p.psi[sl]), p.n_pix_total, p.min_hits)
+        ist = p.interval_start[k * ih:(k + 1) * ih + 1] - k * half
+        lf = ctx.polyfilter(lp, ist, np.ones(ih), np.arange(0, half + 1, 32), 2)
+        d = synth.signal_tod(p.pix[sl], p.psi[sl], p.signal) + \
+            np.random.default_rng(k).standard_normal(half)
+        b = ctx.rhs(lp, lf, dev(d))
+        subs.append((lp, lf, ctx.mbd(lp, lf), b, lp.hits()[1]))
+    lp0, lf0, M0, b0, obs0 = subs[0]
+    Z0 = ctx.defl_build(lp0, lf0, M0, b0, k=16, eps_arn=1e-8, m_max=120).export()[0].contiguous()
+    lp1, lf1, M1, b1, obs1 = subs[1]
+    Z1 = transfer_Z(Z0, obs0, obs1)
+    Ms = ctx.defl_from_Z(lp1, lf1, M1, Z1)
+    # Eq. ident on the new subset: M_2l A Z = Z
+    AZ = torch.stack([ctx.apply_A(lp1, lf1, Z1[:, c].contiguous()) for c in range(Z1.shape[1])], 1)
+    MAZ = torch.stack([ctx.precond_apply(Ms, AZ[:, c].contiguous()) for c in range(Z1.shape[1])], 1)
+    assert rel(host(MAZ), host(Z1)) <= 1e-8
+    _, i_bd = ctx.solve(lp1, lf1, M1, b1, tol=1e-8, max_iter=3000)
+    _, i_tr = ctx.solve(lp1, lf1, Ms, b1, tol=1e-8, max_iter=3000)
+    assert i_bd["converged"] and i_tr["converged"] and i_tr["iters"] < i_bd["iters"]
