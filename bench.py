@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "d1"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "d1", "z1"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -149,6 +149,7 @@ def main():
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
+              "z1": form_z1,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -637,6 +638,47 @@ def form_d1(mm, ctx, n_sub=8, full_m2l=2):
                         "transferred_m2l_iters_mean": float(np.mean(it_tr)),
                         "transferred_m2l_iters_max": int(max(it_tr))},
             "subsets": rows}
+
+
+def form_z1(mm, ctx):
+    """Deflation-space study on one filtered subset of form d1 (1.68e7 samples,
+    quadratic polynomials per subscan): iterations and times to 1e-8 against
+    dim Z (k) and the Arnoldi length m_max (our Arnoldi stops on
+    h_{j+1,j} <= eps_Arn or at m_max; on these scans h stays near 0.2, so
+    m_max plays the part of the paper's eps_Arn)."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    p = synth.config2()
+    per = p.n_samp // 8
+    ipd = p.n_intervals // 8
+    pix = torch.from_numpy(p.pix[:per]).to(dev)
+    psi = torch.from_numpy(p.psi[:per]).to(dev)
+    lp = ctx.pointing(pix, psi, p.n_pix_total, p.min_hits)
+    lp.set_grid(p.n_side)
+    lf = ctx.polyfilter(lp, p.interval_start[:ipd + 1], np.ones(ipd),
+                        np.arange(0, per + 1, 256), 2)
+    d = synth.signal_tod(p.pix[:per], p.psi[:per], p.signal) + \
+        synth.rng_for(2, 10, synth.STREAM_NOISE).standard_normal(per)
+    b = ctx.rhs(lp, lf, torch.from_numpy(d).to(dev))
+    Mbd = ctx.mbd(lp, lf)
+    ((_, i0), t0) = _wall(lambda: ctx.solve(lp, lf, Mbd, b, tol=1e-8, max_iter=3000,
+                                           check_every=4, history=False))
+    grid = []
+    for m_max in (64, 128, 256):
+        for k in (4, 8, 16, 32, 48):
+            if k >= m_max:
+                continue
+            (M2, ts) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=k, eps_arn=1e-8,
+                                                    m_max=m_max))
+            ((_, info), t) = _wall(lambda: ctx.solve(lp, lf, M2, b, tol=1e-8, max_iter=3000,
+                                                     check_every=4, history=False))
+            grid.append({"m_max": m_max, "k": k, "iters": info["iters"],
+                         "converged": info["converged"], "solve_s": t, "setup_s": ts})
+            log(f"[bench] z1 {grid[-1]}")
+    return {"form": "z1", "workload": "one detector subset of the config-2 scan (16 detectors, "
+            "1.68e7 samples), quadratic polynomial filter per 256-sample subscan, tol 1e-8",
+            "mbd": {"iters": i0["iters"], "solve_s": t0}, "grid": grid}
 
 
 def form_c5(mm, ctx, n_requests=200, slots=1):
