@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "d1", "z1"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -149,7 +149,7 @@ def main():
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
-              "z1": form_z1,
+              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True),
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -511,11 +511,14 @@ def form_c4(mm, ctx):
             "pointing and noise model, tol 1e-8", **out}
 
 
-def form_f1(mm, ctx):
+def form_f1(mm, ctx, ground=False):
     """The paper's own weight on the config-2 scan: white noise and the
     polynomial template filter F = W - W B (B^T W B)^-1 B^T W with quadratic
-    Legendre polynomials per subscan (one 256-sample sweep), A = P^T F P.
-    The filter leaves near-null sky modes (Sect. 4): M_BD against M_2l."""
+    Legendre polynomials per subscan (one 256-sample sweep), A = P^T F P;
+    with ground=True also the azimuth-binned ground templates of each
+    constant-elevation pass (1-pixel bins shared by the detectors), combined
+    as F_B W^+ F_G W^+ F_B.  The filter leaves near-null sky modes (Sect. 4):
+    M_BD against M_2l."""
     import torch
     import synth
     dev = torch.device("cuda", 0)
@@ -525,7 +528,11 @@ def form_f1(mm, ctx):
     lp.set_grid(p.n_side)
     sub = np.arange(0, p.n_samp + 1, 256, dtype=np.int64)
     w = np.ones(p.n_intervals)
-    (lf, t_build) = _wall(lambda: ctx.polyfilter(lp, p.interval_start, w, sub, 2))
+    gargs = ()
+    if ground:
+        gb, nb = synth.raster_ground_bins(p.n_side, (16, 8), p.n_samp // 128)
+        gargs = (torch.from_numpy(gb).to(dev), nb)
+    (lf, t_build) = _wall(lambda: ctx.polyfilter(lp, p.interval_start, w, sub, 2, *gargs))
     d = synth.signal_tod(p.pix, p.psi, p.signal) + \
         synth.rng_for(2, 0, synth.STREAM_NOISE).standard_normal(p.n_samp)
     y = torch.randn(p.n_samp, dtype=torch.float64, device=dev)
@@ -552,9 +559,13 @@ def form_f1(mm, ctx):
                                                   check_every=4, history=False))
         out[name] = {"iters": info["iters"], "converged": info["converged"],
                      "rel_res_true": info["rel_res_true"], "solve_s": t}
-    return {"form": "f1", "workload": "config-2 scan (1.34e8 samples), white noise, quadratic "
-            "Legendre polynomials removed per 256-sample subscan (F_T of Sect. 2), "
-            "M_BD vs M_2l (k = 32), tol 1e-8", **out}
+    if ground:
+        out["n_ground_bins"] = gargs[1]
+    return {"form": "g1" if ground else "f1",
+            "workload": "config-2 scan (1.34e8 samples), white noise, quadratic Legendre "
+            "polynomials removed per 256-sample subscan" +
+            (" and azimuth-binned ground templates per constant-elevation pass" if ground else "")
+            + " (F_T of Sects. 2 and 4), M_BD vs M_2l (k = 32), tol 1e-8", **out}
 
 
 def transfer_Z(Z, obs_from, obs_to):

@@ -152,29 +152,39 @@ mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals, const int64_t *interv
                          const int32_t *filter_id, int32_t n_filters, int32_t half_bw,
                          const double *band, mm_noise_method method, mm_precision prec,
                          mm_noise **out);
-/* Polynomial template filter as the time-domain weight, in place of N^-1
- * (Sect. 2, Eqs. filt and filtnoise; Sect. 4: long modes are removed by
- * low-order polynomials per subscan, the remaining noise taken as white):
- *     F = W - W B (B^T W B)^-1 B^T W,
+/* Template filter as the time-domain weight, in place of N^-1 (Sect. 2, Eqs.
+ * filt and filtnoise; Sect. 4: long modes are removed by low-order
+ * polynomials per subscan, the remaining noise taken as white, and ground
+ * pickup by azimuth-binned templates).  Polynomial part:
+ *     F_B = W - W B (B^T W B)^-1 B^T W,
  * B block diagonal over subscans, each block the Legendre polynomials of
  * degree 0..order of the subscan time mapped onto [-1, 1] (F depends only on
  * their span); W = diag(w), w_t = weight of the sample's interval times the
  * flag mask of pointing p (flagged samples neither weigh in a fit nor receive
  * output).  A subscan with at most order + 1 weighted samples is fitted
- * exactly: its output is 0.  M_BD built on this handle uses diag(W)
- * (Eq. mbd), and A = P^T F P, b = P^T F d follow (Eqs. unb, linearsystem).
+ * exactly: its output is 0.  Ground part (optional): G[t, b] = 1 when sample
+ * t falls in azimuth bin b; F_G is the same formula with G, i.e. each bin's
+ * w-weighted mean is removed (a bin without weight removes nothing).  With
+ * both, the filter is the symmetric combination of Sect. 4,
+ *     F = F_B W^+ F_G W^+ F_B    (W^+ zero on flagged samples).
+ * M_BD built on this handle uses diag(W) (Eq. mbd), and A = P^T F P,
+ * b = P^T F d follow (Eqs. unb, linearsystem).
  *   p               the pointing (its n_samp, precision and flags)
  *   interval_start  [host] int64[n_intervals+1], tiles [0, n_samp)
  *   weight          [host] f64[n_intervals] >= 0 (inverse white-noise variance)
  *   subscan_start   [host] int64[n_subscans+1], tiles [0, n_samp); every
  *                   subscan lies inside one interval
  *   order           0..7
- * The handle keeps copies (it does not refer to p afterwards).
- * Errors: MM_E_INVALID (tiling, a subscan across intervals, order, weight < 0),
- * MM_E_NONFINITE (weight). */
+ *   ground_bin      [device] int32[n_samp] azimuth bin of each sample in
+ *                   [0, n_ground_bins), -1 = in no bin; NULL = no ground part
+ *   n_ground_bins   number of bins (0 when ground_bin is NULL)
+ * The handle keeps copies (it does not refer to p or ground_bin afterwards).
+ * Errors: MM_E_INVALID (tiling, a subscan across intervals, order, weight < 0,
+ * a bin outside [-1, n_ground_bins)), MM_E_NONFINITE (weight). */
 mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int32_t n_intervals,
                               const int64_t *interval_start, const double *weight,
                               int64_t n_subscans, const int64_t *subscan_start, int32_t order,
+                              const int32_t *ground_bin, int32_t n_ground_bins,
                               mm_noise **out);
 /* The method actually used (MM_NOISE_DIRECT, MM_NOISE_FFT or MM_NOISE_POLY). */
 mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method);

@@ -224,12 +224,21 @@ def noise_apply(nz: Noise, y, method: str = "direct") -> np.ndarray:
 
 @dataclasses.dataclass
 class PolyFilter:
-    """F = W - W B (B^T W B)^-1 B^T W with B the piecewise Legendre
-    polynomials of degree 0..order on each subscan (Sect. 4: long modes
-    filtered by low-order polynomials per subscan) and W = diag(w), w_t the
-    white-noise weight of the sample's interval times the flag mask.  It
-    duck-types as a Noise (interval_start, filter_id, band with half_bw = 0,
-    band[i, 0] = omega_i), so diag(W) enters M_BD like c_0 does (Eq. mbd)."""
+    """Template filter used as the weight (Sect. 2, Eqs. filt and filtnoise).
+
+    Polynomial part: F_B = W - W B (B^T W B)^-1 B^T W with B the piecewise
+    Legendre polynomials of degree 0..order on each subscan (Sect. 4: long
+    modes filtered by low-order polynomials per subscan) and W = diag(w), w_t
+    the white-noise weight of the sample's interval times the flag mask.
+
+    Ground part (optional; Sect. 4, ground pickup): G has one column per
+    azimuth bin, G[t, b] = 1 when sample t falls in bin b, and F_G is the same
+    formula with G in place of B.  With both, the filter is the symmetric
+    combination F_B W^-1 F_G W^-1 F_B of Sect. 4, with W^-1 read as the
+    pseudo-inverse (zero on flagged samples).
+
+    It duck-types as a Noise (interval_start, filter_id, band with half_bw =
+    0, band[i, 0] = omega_i), so diag(W) enters M_BD like c_0 does (Eq. mbd)."""
     interval_start: np.ndarray   # int64[n_int+1]
     filter_id: np.ndarray        # int32[n_int] = arange
     band: np.ndarray             # f64[n_int, 1] interval weights omega_i
@@ -237,9 +246,12 @@ class PolyFilter:
     subscan_start: np.ndarray    # int64[n_sub+1]
     order: int
     w: np.ndarray                # f64[n_samp] omega of the interval x mask
+    ground_bin: np.ndarray | None = None   # int32[n_samp] azimuth bin, -1 = none
+    n_ground_bins: int = 0
 
 
-def polyfilter_build(pt: Pointing, interval_start, weight, subscan_start, order: int) -> PolyFilter:
+def polyfilter_build(pt: Pointing, interval_start, weight, subscan_start, order: int,
+                     ground_bin=None, n_ground_bins: int = 0) -> PolyFilter:
     istart = np.asarray(interval_start, dtype=np.int64)
     wgt = np.asarray(weight, dtype=np.float64)
     sub = np.asarray(subscan_start, dtype=np.int64)
@@ -254,12 +266,18 @@ def polyfilter_build(pt: Pointing, interval_start, weight, subscan_start, order:
     iv_b = np.searchsorted(istart, sub[1:] - 1, side="right") - 1
     if np.any(iv_a != iv_b):
         raise OracleError("INVALID", "a subscan crosses an interval boundary")
+    gb = None
+    if ground_bin is not None:
+        gb = np.asarray(ground_bin, dtype=np.int32)
+        if gb.shape != (pt.n_samp,) or n_ground_bins < 1 or np.any(gb < -1) \
+                or np.any(gb >= n_ground_bins):
+            raise OracleError("INVALID", "ground bins must lie in [-1, n_ground_bins)")
     w = np.empty(pt.n_samp)
     for i in range(wgt.shape[0]):
         w[istart[i]:istart[i + 1]] = wgt[i]
     w = np.where(pt.j >= 0, w, 0.0)
     return PolyFilter(istart, np.arange(wgt.shape[0], dtype=np.int32), wgt[:, None].copy(), 0,
-                      sub, int(order), w)
+                      sub, int(order), w, gb, int(n_ground_bins) if gb is not None else 0)
 
 
 def _subscan_u(L: int) -> np.ndarray:
@@ -269,12 +287,11 @@ def _subscan_u(L: int) -> np.ndarray:
     return -1.0 + 2.0 * np.arange(L, dtype=np.float64) / (L - 1)
 
 
-def polyfilter_apply(pf: PolyFilter, y) -> np.ndarray:
-    """z = W y - W B (B^T W B)^-1 B^T W y, subscan by subscan.  A subscan
-    with at most order + 1 weighted samples is fitted exactly by the
-    polynomials, so its output is 0 (the pseudo-inverse value)."""
-    y = np.asarray(y, dtype=np.float64)
-    z = np.zeros_like(y)
+def _poly_residual(pf: PolyFilter, y) -> np.ndarray:
+    """r = y - B (B^T W B)^-1 B^T W y, subscan by subscan.  A subscan with at
+    most order + 1 weighted samples is fitted exactly by the polynomials, so
+    its residual is 0 on every weighted sample; it is returned as 0 there."""
+    r = np.zeros_like(y)
     p = pf.order
     for s in range(pf.subscan_start.shape[0] - 1):
         a, b = int(pf.subscan_start[s]), int(pf.subscan_start[s + 1])
@@ -284,8 +301,42 @@ def polyfilter_apply(pf: PolyFilter, y) -> np.ndarray:
         B = np.polynomial.legendre.legvander(_subscan_u(b - a), p)
         G = B.T @ (w[:, None] * B)
         c = np.linalg.solve(G, B.T @ (w * y[a:b]))
-        z[a:b] = w * (y[a:b] - B @ c)
-    return z
+        r[a:b] = y[a:b] - B @ c
+    return r
+
+
+def _ground_residual(pf: PolyFilter, y) -> np.ndarray:
+    """r = y - G (G^T W G)^-1 G^T W y.  G^T W G is diagonal (a sample lies in
+    at most one bin): each bin's template amplitude is the w-weighted mean of
+    its samples, 0 for a bin without weight (pseudo-inverse)."""
+    num = np.zeros(pf.n_ground_bins)
+    den = np.zeros(pf.n_ground_bins)
+    for t in range(y.shape[0]):
+        b = pf.ground_bin[t]
+        if b >= 0:
+            num[b] += pf.w[t] * y[t]
+            den[b] += pf.w[t]
+    amp = np.divide(num, den, out=np.zeros_like(num), where=den > 0)
+    r = y.copy()
+    for t in range(y.shape[0]):
+        b = pf.ground_bin[t]
+        if b >= 0:
+            r[t] -= amp[b]
+    return r
+
+
+def polyfilter_apply(pf: PolyFilter, y) -> np.ndarray:
+    """z = F y.  Polynomial only: z = W (y - B (B^T W B)^-1 B^T W y).  With
+    ground templates: z = F_B W^+ F_G W^+ F_B y, where W^+ F_B y = M r_B(y)
+    (M the mask of weighted samples, r_B the residual above), and likewise for
+    F_G."""
+    y = np.asarray(y, dtype=np.float64)
+    mask = pf.w > 0
+    if pf.ground_bin is None:
+        return pf.w * _poly_residual(pf, y)
+    y1 = np.where(mask, _poly_residual(pf, y), 0.0)
+    y2 = np.where(mask, _ground_residual(pf, y1), 0.0)
+    return pf.w * _poly_residual(pf, y2)
 
 
 def dense_polyfilter(pf: PolyFilter) -> np.ndarray:

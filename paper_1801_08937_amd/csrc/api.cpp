@@ -511,7 +511,8 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
 extern "C" mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int32_t n_intervals,
                                          const int64_t *interval_start, const double *weight,
                                          int64_t n_subscans, const int64_t *subscan_start,
-                                         int32_t order, mm_noise **out) {
+                                         int32_t order, const int32_t *ground_bin,
+                                         int32_t n_ground_bins, mm_noise **out) {
     if (!ctx || !out) return MM_E_INVALID;
     *out = nullptr;
     API_BEGIN(ctx)
@@ -520,6 +521,8 @@ extern "C" mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int3
              MM_E_INVALID, "polyfilter: empty or null arguments");
     MM_CHECK(order >= 0 && order <= polyfilter_max_order(), MM_E_INVALID,
              "polyfilter: order must be in [0, 7]");
+    MM_CHECK(ground_bin ? n_ground_bins >= 1 : n_ground_bins == 0, MM_E_INVALID,
+             "polyfilter: ground bins need n_ground_bins >= 1 (0 without them)");
     const int64_t n = p->n_samp;
     MM_CHECK(interval_start[0] == 0 && interval_start[n_intervals] == n, MM_E_INVALID,
              "polyfilter: intervals must tile [0, n_samp)");
@@ -572,7 +575,7 @@ extern "C" mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int3
         MM_HIP(hipMemcpyAsync(nz->pf_omega.ptr, om.data(), sizeof(double) * n_subscans,
                               hipMemcpyHostToDevice, s));
         MM_HIP(hipStreamSynchronize(s));
-        polyfilter_prepare(ctx, p, nz);
+        polyfilter_prepare(ctx, p, nz, ground_bin, n_ground_bins);
     } catch (...) {
         delete nz;
         throw;

@@ -107,6 +107,8 @@ struct mm_ctx {
     mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
     mm::DBuf xpack;                // map repacked for P: (I, Q, U, 0) records, or I and (Q, U) split
     mm::DBuf pt_part;              // per-segment partial maps of the sliced P^T
+    mm::DBuf tod_c;                // TOD temporary of the template filter
+    mm::DBuf pf_g;                 // ground-template chunk sums and amplitudes
     // Bumped whenever one of the workspaces above is reallocated: captured
     // graphs hold their addresses and are re-captured when it changes.
     uint64_t ws_gen = 0;
@@ -189,6 +191,13 @@ struct mm_noise {
     int32_t pf_order = 0;
     int64_t pf_n_sub = 0;
     mm::DBuf pf_sub, pf_omega, pf_ginv, pf_mask;
+    // ground templates (pf_nb bins, 0 = none): each sample's bin, 1 / sum of
+    // w per bin, and the bin-sorted samples and weights interleaved per wave
+    // (wave w = a chunk of a group of 64 bins: entries [gbase[w], gbase[w+1]),
+    // lane = bin; gfirst[g] = first wave of group g)
+    int32_t pf_nb = 0;
+    int32_t pf_n_gwave = 0;
+    mm::DBuf pf_gbin, pf_gwinv, pf_gbase, pf_gfirst, pf_gsp, pf_gsw;
 };
 
 struct mm_precond {
@@ -227,7 +236,8 @@ void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_r
 void noise_prepare(mm_ctx *ctx, mm_noise *nz);  // tiles, FFT spectra
 // polyfilter.hip
 int polyfilter_max_order();
-void polyfilter_prepare(mm_ctx *ctx, const mm_pointing *p, mm_noise *nz);
+void polyfilter_prepare(mm_ctx *ctx, const mm_pointing *p, mm_noise *nz,
+                        const int32_t *ground_bin, int32_t n_ground_bins);
 void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
 bool noise_fft_supported(int half_bw, int64_t min_len);
 

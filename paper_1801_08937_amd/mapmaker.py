@@ -78,7 +78,7 @@ def lib() -> C.CDLL:
             "mm_pointing_destroy": (None, [P]),
             "mm_noise_build": (C.c_int, [P, I32, P, P, I32, I32, P, C.c_int, C.c_int, PP]),
             "mm_noise_method_used": (C.c_int, [P, C.POINTER(C.c_int)]),
-            "mm_polyfilter_build": (C.c_int, [P, P, I32, P, P, I64, P, I32, PP]),
+            "mm_polyfilter_build": (C.c_int, [P, P, I32, P, P, I64, P, I32, P, I32, PP]),
             "mm_noise_fft_block": (C.c_int, [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "mm_noise_apply": (C.c_int, [P, P, I32, P, P]),
             "mm_noise_destroy": (None, [P]),
@@ -224,16 +224,25 @@ class Context:
                     "mm_noise_build")
         return Noise(self, h, int(istart[-1]), half_bw, prec)
 
-    def polyfilter(self, p, interval_start, weight, subscan_start, order: int):
-        """Polynomial template filter F = W - W B (B^T W B)^-1 B^T W (piecewise
-        Legendre polynomials of degree <= order per subscan) as the weight."""
+    def polyfilter(self, p, interval_start, weight, subscan_start, order: int,
+                   ground_bin=None, n_ground_bins: int = 0):
+        """Template filter as the weight: F = W - W B (B^T W B)^-1 B^T W
+        (piecewise Legendre polynomials of degree <= order per subscan), or
+        with ground templates (ground_bin: int32 device tensor, one azimuth
+        bin per sample, -1 = none) F = F_B W^+ F_G W^+ F_B."""
+        import torch
         istart = np.ascontiguousarray(interval_start, dtype=np.int64)
         w = np.ascontiguousarray(weight, dtype=np.float64)
         sub = np.ascontiguousarray(subscan_start, dtype=np.int64)
+        gb = None
+        if ground_bin is not None:
+            _dev_check(ground_bin, torch.int32, p.n_samp, "ground_bin")
+            gb = _ptr(ground_bin)
         h = C.c_void_p()
         self._check(lib().mm_polyfilter_build(self.h, p.h, istart.shape[0] - 1, istart.ctypes.data,
                                               w.ctypes.data, sub.shape[0] - 1, sub.ctypes.data,
-                                              order, C.byref(h)), "mm_polyfilter_build")
+                                              order, gb, int(n_ground_bins), C.byref(h)),
+                    "mm_polyfilter_build")
         return Noise(self, h, p.n_samp, 0, p.prec)
 
     # ------------------------------------------------------------ operators

@@ -219,6 +219,39 @@ def rotated_raster(n_side: int, grid: tuple[int, int], n_samp_per_det: int) -> n
     return out
 
 
+def raster_ground_bins(n_side: int, grid: tuple[int, int], n_samp_per_det: int,
+                       bin_px: float = 1.0) -> tuple[np.ndarray, int]:
+    """Azimuth bins of the ground templates for rotated_raster's scans (ground
+    pickup, Sect. 4).  Each pass is one constant-elevation scan whose sweeps
+    run along the pass's rotated x axis, which plays the azimuth; a detector's
+    azimuth is the sweep coordinate plus its focal-plane offset along the
+    sweep.  The bins, bin_px pixels wide, are shared by all detectors of a
+    pass.  Returns (bin int32[n_det * n_samp_per_det], n_bins)."""
+    gx, gy = grid
+    n_det = gx * gy
+    per_pass = n_side * n_side
+    assert n_samp_per_det % per_pass == 0
+    n_pass = n_samp_per_det // per_pass
+    s = np.arange(per_pass, dtype=np.int64)
+    q = s // n_side
+    u = s % n_side
+    half = n_side / 2.0
+    a = np.where(q % 2 == 0, u, n_side - 1 - u).astype(np.float64) + 0.5 - half
+    margin = float(gx + gy)
+    n_loc = int(math.ceil((n_side + 2 * margin) / bin_px))
+    out = np.empty(n_det * n_samp_per_det, dtype=np.int32)
+    for k in range(n_det):
+        ox = 2 * (k % gx) - (gx - 1)
+        oy = 2 * (k // gx) - (gy - 1)
+        for m in range(n_pass):
+            th = math.radians(60.0 * (m % 3))
+            az = a + ox * math.cos(th) + oy * math.sin(th) + half + margin
+            loc = np.clip(np.floor(az / bin_px).astype(np.int64), 0, n_loc - 1)
+            base = k * n_samp_per_det + m * per_pass
+            out[base:base + per_pass] = m * n_loc + loc
+    return out, n_pass * n_loc
+
+
 def uniform_intervals(n_samp: int, L: int) -> np.ndarray:
     assert n_samp % L == 0
     return np.arange(0, n_samp + 1, L, dtype=np.int64)

@@ -180,3 +180,99 @@ def test_transferred_deflation_space(ctx):
     _, i_bd = ctx.solve(lp1, lf1, M1, b1, tol=1e-8, max_iter=3000)
     _, i_tr = ctx.solve(lp1, lf1, Ms, b1, tol=1e-8, max_iter=3000)
     assert i_bd["converged"] and i_tr["converged"] and i_tr["iters"] < i_bd["iters"]
+
+
+# ------------------------------------------------ ground templates (Sect. 4)
+
+def _ground_bins(p, seed, n_bins):
+    """Random azimuth bins, about a tenth of the samples in none, and (with
+    two bins or more) one bin that only flagged samples fall in."""
+    rng = np.random.default_rng(seed + 50)
+    gb = rng.integers(0, max(n_bins - 1, 1), p.n_samp).astype(np.int32)
+    gb[rng.random(p.n_samp) < 0.1] = -1
+    if n_bins > 1:
+        gb[np.flatnonzero(p.pix < 0)[:3]] = n_bins - 1
+    return gb
+
+
+def _both_ground(ctx, p, order, seed, n_bins, prec=0):
+    lp = ctx.pointing(dev(p.pix), dev(p.psi), p.n_pix_total, p.min_hits, prec)
+    op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    sub = _subscans(p, seed)
+    w = np.random.default_rng(seed + 1).uniform(0.5, 2.0, p.n_intervals)
+    gb = _ground_bins(p, seed, n_bins)
+    lf = ctx.polyfilter(lp, p.interval_start, w, sub, order, dev(gb), n_bins)
+    of = O.polyfilter_build(op, p.interval_start, w, sub, order, gb, n_bins)
+    return lp, lf, op, of
+
+
+@pytest.mark.parametrize("order,n_bins", [(0, 5), (2, 5), (2, 61), (3, 1)])
+def test_ground_filter_apply_parity(ctx, order, n_bins):
+    """F = F_B W^+ F_G W^+ F_B against the oracle; with 5 bins every bin
+    spans two or more chunks of the fixed-order bin sums."""
+    p = synth.random_problem(21, n_side=12, n_samp=30011, n_int=5, half_bw=5, n_filters=2,
+                             flag_frac=0.1)
+    lp, lf, op, of = _both_ground(ctx, p, order, 20 + order, n_bins)
+    y = np.random.default_rng(22).standard_normal(p.n_samp)
+    z = host(ctx.noise_apply(lf, dev(y)))
+    ref = O.polyfilter_apply(of, y)
+    assert maxrel(z, ref) <= TOL_OP, maxrel(z, ref)
+    Y = np.random.default_rng(23).standard_normal((p.n_samp, 4))
+    Y[:, 1] = y
+    Z = host(ctx.noise_apply(lf, dev(Y.reshape(-1)), nrhs=4)).reshape(-1, 4)
+    np.testing.assert_array_equal(Z[:, 1], z)
+
+
+def test_ground_filter_operators_mbd_and_fp32(ctx):
+    p = synth.random_problem(24, n_side=10, n_samp=20011, n_int=4, half_bw=5, n_filters=2,
+                             flag_frac=0.05)
+    lp, lf, op, of = _both_ground(ctx, p, 1, 24, 17)
+    x = np.random.default_rng(25).standard_normal(op.n)
+    assert maxrel(host(ctx.apply_A(lp, lf, dev(x))), O.apply_A(op, of, x)) <= TOL_OP
+    assert maxrel(host(ctx.rhs(lp, lf, dev(p.tod))), O.rhs(op, of, p.tod)) <= TOL_OP
+    v = np.random.default_rng(26).standard_normal(op.n)
+    M = ctx.mbd(lp, lf)
+    assert maxrel(host(ctx.precond_apply(M, dev(v))), O.mbd_apply(O.mbd_build(op, of), v)) <= TOL_OP
+    lp32, lf32, _, of32 = _both_ground(ctx, p, 1, 24, 17, prec=1)
+    y = np.random.default_rng(27).standard_normal(p.n_samp)
+    z = host(ctx.noise_apply(lf32, dev(y.astype(np.float32))))
+    assert rel(z, O.polyfilter_apply(of32, y)) <= 1e-5
+
+
+def test_ground_filter_raster_m2l_beats_mbd(ctx):
+    """Cross-linked scan, quadratic polynomials per sweep and azimuth-binned
+    ground templates shared by the detectors of each constant-elevation
+    pass: both preconditioners reach the true residual, M_2l in far fewer
+    iterations."""
+    p = synth.config2(n_side=32, grid=(4, 2), samp_per_det=1 << 12, L=1 << 11, half_bw=10)
+    gb, nb = synth.raster_ground_bins(32, (4, 2), 1 << 12)
+    lp = ctx.pointing(dev(p.pix), dev(p.psi), p.n_pix_total, p.min_hits)
+    lp.set_grid(p.n_side)
+    op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    sub = np.arange(0, p.n_samp + 1, 32, dtype=np.int64)
+    w = np.ones(p.n_intervals)
+    lf = ctx.polyfilter(lp, p.interval_start, w, sub, 2, dev(gb), nb)
+    of = O.polyfilter_build(op, p.interval_start, w, sub, 2, gb, nb)
+    d = synth.signal_tod(p.pix, p.psi, p.signal) + np.random.default_rng(1).standard_normal(p.n_samp)
+    b = ctx.rhs(lp, lf, dev(d))
+    assert maxrel(host(b), O.rhs(op, of, d)) <= TOL_OP
+    Mbd = ctx.mbd(lp, lf)
+    _, i1 = ctx.solve(lp, lf, Mbd, b, tol=1e-10, max_iter=3000)
+    M2 = ctx.defl_build(lp, lf, Mbd, b, k=16, eps_arn=1e-8, m_max=120)
+    _, i2 = ctx.solve(lp, lf, M2, b, tol=1e-10, max_iter=3000)
+    assert i1["converged"] and i2["converged"], (i1, i2)
+    assert i1["rel_res_true"] <= 1e-9 and i2["rel_res_true"] <= 1e-9
+    assert i2["iters"] * 2 < i1["iters"], (i1["iters"], i2["iters"])
+
+
+def test_ground_filter_errors(ctx):
+    from paper_1801_08937_amd import mapmaker as mm
+    p = synth.random_problem(28, n_side=8, n_samp=5000, n_int=3, half_bw=5, n_filters=1)
+    lp = ctx.pointing(dev(p.pix), dev(p.psi), p.n_pix_total, p.min_hits)
+    gb = _ground_bins(p, 28, 9)
+    args = (lp, p.interval_start, np.ones(p.n_intervals), p.interval_start, 1)
+    for bad, nb in ((np.where(gb == 3, 9, gb), 9), (np.where(gb == 3, -2, gb), 9), (gb, 0)):
+        with pytest.raises(mm.MapmakerError):
+            ctx.polyfilter(*args, dev(bad.astype(np.int32)), nb)
+    with pytest.raises(ValueError):
+        ctx.polyfilter(*args, dev(gb[:-1]), 9)

@@ -581,3 +581,136 @@ def test_polyfilter_degenerate_mode_of_A():
     A = P.T @ O.dense_polyfilter(pf) @ P
     assert np.max(np.abs(A - A.T)) <= 1e-10 * np.max(np.abs(A))
     assert np.min(np.linalg.eigvalsh(A)) >= -1e-8 * np.max(np.abs(A))
+
+
+# ------------------------------- ground templates in the filter (Sect. 4)
+
+def _pf_ground_problem(seed=0, order=2, flag_frac=0.1, n_bins=23):
+    """_pf_problem plus azimuth bins: random bins, some samples in none, one
+    bin that only flagged samples fall in, and two subscans short enough to
+    be fitted exactly."""
+    p, pt, pf = _pf_problem(seed, order, flag_frac)
+    rng = np.random.default_rng(seed + 200)
+    gb = rng.integers(0, n_bins - 1, pt.n_samp).astype(np.int32)
+    gb[rng.random(pt.n_samp) < 0.1] = -1
+    flagged = np.flatnonzero(pt.j < 0)
+    gb[flagged[:3]] = n_bins - 1          # a bin without weight
+    sub = pf.subscan_start.copy()
+    a = int(sub[1])                       # split the first subscan: lengths 2, 3, rest
+    sub = np.concatenate([[0, 2, 5], sub[1:]]) if a > 6 else sub
+    pf = O.polyfilter_build(pt, p.interval_start, pf.band[:, 0], sub, order, gb, n_bins)
+    return p, pt, pf
+
+
+def _F_template_definition(pf):
+    """F_B W^+ F_G W^+ F_B written out with explicit template matrices and
+    pseudo-inverses: T = monomials per subscan (a different basis from the
+    oracle's Legendre polynomials; only the span matters), G[t, b] = 1 for
+    sample t in bin b, F_X = W - W X (X^T W X)^+ X^T W, W^+ = diag(1/w, 0
+    where w = 0)."""
+    n = pf.w.shape[0]
+    W = np.diag(pf.w)
+    Wp = np.diag(np.where(pf.w > 0, 1.0 / np.where(pf.w > 0, pf.w, 1.0), 0.0))
+    p = pf.order
+    n_sub = pf.subscan_start.shape[0] - 1
+    B = np.zeros((n, n_sub * (p + 1)))
+    for s in range(n_sub):
+        a, b = int(pf.subscan_start[s]), int(pf.subscan_start[s + 1])
+        tt = np.arange(b - a, dtype=np.float64) / max(b - a - 1, 1)
+        B[a:b, s * (p + 1):(s + 1) * (p + 1)] = np.vander(tt, p + 1, increasing=True)
+    G = np.zeros((n, pf.n_ground_bins))
+    on = pf.ground_bin >= 0
+    G[np.flatnonzero(on), pf.ground_bin[on]] = 1.0
+
+    def filt(X, blocks):
+        M = X.T @ W @ X
+        Mp = np.zeros_like(M)
+        for lo, hi in blocks:  # X^T W X is block diagonal: pseudo-invert per block
+            Mp[lo:hi, lo:hi] = np.linalg.pinv(M[lo:hi, lo:hi], hermitian=True)
+        return W - W @ X @ Mp @ X.T @ W
+
+    FB = filt(B, [(s * (p + 1), (s + 1) * (p + 1)) for s in range(n_sub)])
+    FG = filt(G, [(b, b + 1) for b in range(pf.n_ground_bins)])
+    return FB @ Wp @ FG @ Wp @ FB, FB, B, G
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_template_filter_matches_definition(order):
+    _, _, pf = _pf_ground_problem(11, order)
+    F = O.dense_polyfilter(pf)
+    Fd, _, _, _ = _F_template_definition(pf)
+    assert np.max(np.abs(F - Fd)) <= 1e-9 * np.max(np.abs(Fd))
+
+
+def test_template_filter_symmetric_psd_and_removes_polynomials():
+    _, pt, pf = _pf_ground_problem(12, 2)
+    F = O.dense_polyfilter(pf)
+    _, _, B, G = _F_template_definition(pf)
+    assert np.max(np.abs(F - F.T)) <= 1e-12 * np.max(np.abs(F))
+    assert np.min(np.linalg.eigvalsh(F)) >= -1e-10 * np.max(np.abs(F))
+    assert np.max(np.abs(F @ B)) <= 1e-9 * np.max(np.abs(F)) * np.max(np.abs(B))
+    # the ground part changes the filter: G's columns are not in B's span
+    Fb = O.dense_polyfilter(O.polyfilter_build(pt, pf.interval_start, pf.band[:, 0],
+                                               pf.subscan_start, 2))
+    assert np.max(np.abs(F - Fb)) > 1e-3 * np.max(np.abs(Fb))
+
+
+def test_template_filter_ground_inside_polynomial_span_is_F_B():
+    """If every bin is a whole subscan, G's columns are order-0 polynomials,
+    (I - Pi_G)(I - Pi_B) = I - Pi_B and the combination reduces to F_B."""
+    _, pt, pf = _pf_ground_problem(13, 1)
+    sub = pf.subscan_start
+    gb = (np.searchsorted(sub, np.arange(pt.n_samp), side="right") - 1).astype(np.int32)
+    pfg = O.polyfilter_build(pt, pf.interval_start, pf.band[:, 0], sub, 1, gb, sub.shape[0] - 1)
+    pfb = O.polyfilter_build(pt, pf.interval_start, pf.band[:, 0], sub, 1)
+    y = np.random.default_rng(14).standard_normal(pt.n_samp)
+    zg, zb = O.polyfilter_apply(pfg, y), O.polyfilter_apply(pfb, y)
+    assert np.max(np.abs(zg - zb)) <= 1e-12 * np.max(np.abs(zb))
+
+
+def test_template_filter_ground_only_is_binned_mean_removal():
+    """One subscan per interval, order 0, and bins that split each interval
+    into halves: F_B removes the interval's weighted mean; the ground step
+    then removes each half's weighted mean, which the last F_B leaves alone
+    (the residual already has zero weighted mean over the interval).  So F y
+    = w (y - mean over the sample's half), a closed form."""
+    p, pt, _ = _pf_problem(15, 0, flag_frac=0.1)
+    ist = p.interval_start
+    w_int = np.linspace(0.7, 1.6, p.n_intervals)
+    gb = np.empty(pt.n_samp, dtype=np.int32)
+    for i in range(p.n_intervals):
+        a, b = int(ist[i]), int(ist[i + 1])
+        m = (a + b) // 2
+        gb[a:m], gb[m:b] = 2 * i, 2 * i + 1
+    pf = O.polyfilter_build(pt, ist, w_int, ist, 0, gb, 2 * p.n_intervals)
+    y = np.random.default_rng(16).standard_normal(pt.n_samp)
+    z = O.polyfilter_apply(pf, y)
+    ref = np.zeros_like(y)
+    for b in range(2 * p.n_intervals):
+        sel = gb == b
+        w = pf.w[sel]
+        ref[sel] = w * (y[sel] - np.sum(w * y[sel]) / np.sum(w))
+    assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_template_filter_validation():
+    _, pt, pf = _pf_ground_problem(17, 1)
+    gb = pf.ground_bin.copy()
+    for bad in (gb[:-1], np.where(gb == 0, -2, gb), np.where(gb == 0, 23, gb)):
+        with pytest.raises(O.OracleError):
+            O.polyfilter_build(pt, pf.interval_start, pf.band[:, 0], pf.subscan_start, 1,
+                               bad, 23)
+
+
+def test_raster_ground_bins_follow_azimuth():
+    """Bins are shared across detectors of a pass and advance one per sample
+    along each sweep (1-pixel bins, 1 px/sample scan)."""
+    gb, nb = synth.raster_ground_bins(16, (4, 2), 2 * 256)
+    assert gb.min() >= 0 and gb.max() < nb and nb == 2 * (16 + 12)
+    spd = 512
+    for k in range(8):
+        sw = gb[k * spd:k * spd + 16]                # first sweep runs forward
+        assert np.all(np.diff(sw) == 1)
+        sw2 = gb[k * spd + 16:k * spd + 32]          # the next runs back
+        assert np.all(np.diff(sw2) == -1)
+    assert np.all(gb[256:512] >= 28) and np.all(gb[:256] < 28)   # second pass, own bins
