@@ -65,22 +65,43 @@ class Pointing:
     off: np.ndarray       # int32[n_obs+1] segment offsets into perm
     cos2: np.ndarray      # f64[n_samp]
     sin2: np.ndarray      # f64[n_samp]
+    stokes: str = "IQU"   # map components: "IQU", "I" or "QU"
 
     @property
     def n_obs(self) -> int:
         return int(self.obs_pix.shape[0])
 
     @property
+    def nc(self) -> int:
+        return len(self.stokes)
+
+    @property
     def n(self) -> int:
-        return 3 * self.n_obs
+        return self.nc * self.n_obs
+
+    def weights(self) -> np.ndarray:
+        """f64[n_samp, nc]: the non-zeros of each row of P.  IQU: (1, cos 2phi,
+        sin 2phi) (Eq. datamodel); I: (1) for the pair-sum stream (Eq. d+);
+        QU: (cos 2phi, sin 2phi) for the pair-difference stream (Eq. d-)."""
+        cols = {"I": np.ones(self.n_samp), "Q": self.cos2, "U": self.sin2}
+        return np.stack([cols[a] for a in self.stokes], axis=1)
 
 
-def pointing_build(pix, psi, n_pix_total: int, min_hits: int = 3) -> Pointing:
+def pointing_build(pix, psi, n_pix_total: int, min_hits: int = 3,
+                   stokes: str = "IQU") -> Pointing:
     """P has three non-zeros per row, (1, cos 2phi_t, sin 2phi_t) at the
-    sample's pixel (Eq. datamodel).  Pixels seen fewer than min_hits times are
-    dropped and their samples flagged (the paper discards samples of pixels
-    observed without enough redundancy, Sect. 4)."""
+    sample's pixel (Eq. datamodel); with stokes = "I" or "QU" only the
+    intensity or the polarisation columns (the sum and difference streams of
+    a detector pair, Eqs. d+ and d-; psi may be None for "I").  Pixels seen
+    fewer than min_hits times are dropped and their samples flagged (the paper
+    discards samples of pixels observed without enough redundancy, Sect. 4)."""
+    if stokes not in ("IQU", "I", "QU"):
+        raise OracleError("INVALID", "stokes must be IQU, I or QU")
     pix = np.asarray(pix, dtype=np.int32)
+    if psi is None:
+        if stokes != "I":
+            raise OracleError("INVALID", "psi is needed for polarisation")
+        psi = np.zeros(pix.shape[0])
     psi = np.asarray(psi, dtype=np.float64)
     if pix.shape != psi.shape:
         raise OracleError("INVALID", "pix and psi differ in length")
@@ -99,42 +120,45 @@ def pointing_build(pix, psi, n_pix_total: int, min_hits: int = 3) -> Pointing:
     off[1:] = np.cumsum(hits[obs_pix])
     return Pointing(n_samp=pix.shape[0], n_pix_total=n_pix_total, hits=hits,
                     obs_pix=obs_pix, cidx=cidx, j=j, perm=perm, off=off,
-                    cos2=np.cos(2.0 * psi), sin2=np.sin(2.0 * psi))
+                    cos2=np.cos(2.0 * psi), sin2=np.sin(2.0 * psi), stokes=stokes)
 
 
 def apply_P(pt: Pointing, x) -> np.ndarray:
     """y_t = I_j + Q_j cos 2phi_t + U_j sin 2phi_t at j = j_t; 0 if flagged
-    (Eq. datamodel).  x is the map, [n_obs][3] interleaved."""
-    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    (Eq. datamodel); the I or QU terms alone for those pointings.  x is the
+    map, [n_obs][nc] interleaved."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, pt.nc)
     y = np.zeros(pt.n_samp)
     m = pt.j >= 0
     jj = pt.j[m]
-    y[m] = x[jj, 0] + pt.cos2[m] * x[jj, 1] + pt.sin2[m] * x[jj, 2]
+    w = pt.weights()[m]
+    for a in range(pt.nc):
+        y[m] += w[:, a] * x[jj, a]
     return y
 
 
 def apply_PT(pt: Pointing, z) -> np.ndarray:
     """(P^T z)_{j,a} = sum over samples t with j_t = j of w_t[a] z_t, with
-    w_t = (1, cos 2phi_t, sin 2phi_t); samples summed in time order."""
+    w_t the row's non-zeros (pt.weights); samples summed in time order."""
     z = np.asarray(z, dtype=np.float64)
     m = pt.j >= 0
     jj = pt.j[m]
-    out = np.empty((pt.n_obs, 3))
-    out[:, 0] = np.bincount(jj, weights=z[m], minlength=pt.n_obs)
-    out[:, 1] = np.bincount(jj, weights=pt.cos2[m] * z[m], minlength=pt.n_obs)
-    out[:, 2] = np.bincount(jj, weights=pt.sin2[m] * z[m], minlength=pt.n_obs)
+    w = pt.weights()[m]
+    out = np.empty((pt.n_obs, pt.nc))
+    for a in range(pt.nc):
+        out[:, a] = np.bincount(jj, weights=w[:, a] * z[m], minlength=pt.n_obs)
     return out.reshape(-1)
 
 
 def dense_P(pt: Pointing) -> np.ndarray:
-    """The N_t x 3 n_obs pointing matrix written out (tiny inputs only)."""
+    """The N_t x nc n_obs pointing matrix written out (tiny inputs only)."""
     P = np.zeros((pt.n_samp, pt.n))
+    cols = {"I": lambda t: 1.0, "Q": lambda t: pt.cos2[t], "U": lambda t: pt.sin2[t]}
     for t in range(pt.n_samp):
         j = pt.j[t]
         if j >= 0:
-            P[t, 3 * j] = 1.0
-            P[t, 3 * j + 1] = pt.cos2[t]
-            P[t, 3 * j + 2] = pt.sin2[t]
+            for a, name in enumerate(pt.stokes):
+                P[t, pt.nc * j + a] = cols[name](t)
     return P
 
 
@@ -376,7 +400,9 @@ def apply_A_pixels(pt: Pointing, nz: Noise, x, pixels) -> np.ndarray:
     z_t = sum_{u in I(t), |t-u| <= lambda} c_{|t-u|} (P x)_u, then
     sum_t w_t z_t.  Cost is per requested pixel, so it serves as a check at
     sizes where the whole product is too large for the oracle.
-    Returns f64[len(pixels), 3]."""
+    Returns f64[len(pixels), 3] (IQU pointings only)."""
+    if pt.stokes != "IQU":
+        raise OracleError("INVALID", "apply_A_pixels takes IQU pointings")
     x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
     lam = nz.half_bw
     out = np.zeros((len(pixels), 3))
@@ -410,8 +436,8 @@ def rhs(pt: Pointing, nz: Noise, d, method: str = "direct") -> np.ndarray:
 
 @dataclasses.dataclass
 class Mbd:
-    blocks: np.ndarray      # f64[n_obs, 3, 3]  B_j
-    inv: np.ndarray         # f64[n_obs, 3, 3]  B_j^-1
+    blocks: np.ndarray      # f64[n_obs, nc, nc]  B_j
+    inv: np.ndarray         # f64[n_obs, nc, nc]  B_j^-1
     rcond_min: float
 
 
@@ -425,30 +451,32 @@ def _diag_weight(pt: Pointing, nz: Noise) -> np.ndarray:
 
 
 def mbd_build(pt: Pointing, nz: Noise, rcond_tol: float = 1e-12) -> Mbd:
-    """B_j = sum_{t: j_t = j} c_0 w_t w_t^T with w_t = (1, cos 2phi, sin 2phi);
+    """B_j = sum_{t: j_t = j} c_0 w_t w_t^T with w_t the row's non-zeros
+    ((1, cos 2phi, sin 2phi) for IQU: 3x3 blocks; 1x1 for I, 2x2 for QU);
     M_BD is the block-diagonal matrix of the B_j^-1."""
     c0 = _diag_weight(pt, nz)
     m = pt.j >= 0
     jj = pt.j[m]
-    w = np.stack([np.ones(pt.n_samp), pt.cos2, pt.sin2], axis=1)[m]
+    w = pt.weights()[m]
     cw = c0[m]
-    B = np.zeros((pt.n_obs, 3, 3))
-    for a in range(3):
-        for b in range(3):
+    nc = pt.nc
+    B = np.zeros((pt.n_obs, nc, nc))
+    for a in range(nc):
+        for b in range(nc):
             B[:, a, b] = np.bincount(jj, weights=cw * w[:, a] * w[:, b], minlength=pt.n_obs)
     try:
         np.linalg.cholesky(B)
     except np.linalg.LinAlgError as e:
-        raise OracleError("SINGULAR_BLOCK", "a 3x3 block is not positive definite") from e
+        raise OracleError("SINGULAR_BLOCK", "a pixel block is not positive definite") from e
     inv = np.linalg.inv(B)
     rc = 1.0 / (np.abs(B).sum(axis=1).max(axis=1) * np.abs(inv).sum(axis=1).max(axis=1))
     if pt.n_obs and rc.min() < rcond_tol:
-        raise OracleError("SINGULAR_BLOCK", f"3x3 block rcond {rc.min():.3e}")
+        raise OracleError("SINGULAR_BLOCK", f"pixel block rcond {rc.min():.3e}")
     return Mbd(B, inv, float(rc.min()) if pt.n_obs else 1.0)
 
 
 def mbd_apply(M: Mbd, v) -> np.ndarray:
-    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    v = np.asarray(v, dtype=np.float64).reshape(-1, M.inv.shape[1])
     return np.einsum("jab,jb->ja", M.inv, v).reshape(-1)
 
 

@@ -714,3 +714,125 @@ def test_raster_ground_bins_follow_azimuth():
         sw2 = gb[k * spd + 16:k * spd + 32]          # the next runs back
         assert np.all(np.diff(sw2) == -1)
     assert np.all(gb[256:512] >= 28) and np.all(gb[:256] < 28)   # second pass, own bins
+
+
+# --------------------- intensity-only and polarisation-only maps (Eqs. d+, d-)
+
+@pytest.mark.parametrize("stokes,cols", [("I", [0]), ("QU", [1, 2])])
+def test_stokes_subsets_are_columns_of_the_IQU_pointing(stokes, cols):
+    """P for the pair-sum (I) and pair-difference (QU) streams keeps the
+    intensity or the polarisation columns of the IQU pointing matrix."""
+    p = synth.random_problem(31, n_side=5, n_samp=900, flag_frac=0.1)
+    full = O.pointing_build(p.pix, p.psi, p.n_pix_total, 1)
+    sub = O.pointing_build(p.pix, None if stokes == "I" else p.psi, p.n_pix_total, 1, stokes)
+    Pf = O.dense_P(full)
+    keep = np.concatenate([np.arange(full.n_obs) * 3 + c for c in cols])
+    keep = np.sort(keep)
+    Ps = O.dense_P(sub)
+    np.testing.assert_array_equal(Ps, Pf[:, keep])
+    x = np.random.default_rng(32).standard_normal(sub.n)
+    y = np.random.default_rng(33).standard_normal(p.n_samp)
+    assert np.max(np.abs(O.apply_P(sub, x) - Ps @ x)) <= 1e-13 * np.max(np.abs(Ps @ x))
+    assert np.max(np.abs(O.apply_PT(sub, y) - Ps.T @ y)) <= 1e-12 * np.max(np.abs(Ps.T @ y))
+
+
+def test_intensity_only_white_noise_solution_is_the_binned_mean():
+    """I-only pointing, white noise (lambda = 0): M_BD = A^-1, so PCG stops
+    after one step at the weighted binned mean of each pixel's samples."""
+    p = synth.random_problem(34, n_side=6, n_samp=2000, half_bw=0, n_filters=2)
+    pt = O.pointing_build(p.pix, None, p.n_pix_total, 3, "I")
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, 0)
+    M = O.mbd_build(pt, nz)
+    b = O.rhs(pt, nz, p.tod)
+    x, info = O.pcg(lambda v: O.apply_A(pt, nz, v), lambda v: O.mbd_apply(M, v), b, 1e-12, 10)
+    c0 = np.empty(p.n_samp)
+    for i in range(p.n_intervals):
+        c0[p.interval_start[i]:p.interval_start[i + 1]] = p.band[p.filter_id[i], 0]
+    ref = np.zeros(pt.n_obs)
+    for j in range(pt.n_obs):
+        t = pt.perm[pt.off[j]:pt.off[j + 1]]
+        ref[j] = np.sum(c0[t] * p.tod[t]) / np.sum(c0[t])
+    assert info.iters <= 1
+    assert np.max(np.abs(x - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _pair_problem(seed, half_bw=4):
+    """Detector pairs: B sees the same pixel as A at every sample with its
+    polariser turned by 90 degrees (psi + pi/2), so d_B = I - Q c - U s +
+    n_B.  Returns (p, pair pix/psi concatenated A then B, d_A, d_B)."""
+    p = synth.random_problem(seed, n_side=5, n_samp=1500, n_int=3, half_bw=half_bw,
+                             n_filters=2, flag_frac=0.05)
+    n = p.n_samp
+    psi_b = p.psi + 0.5 * np.pi
+    sky = p.signal
+    d_a = synth.signal_tod(p.pix, p.psi, sky) + np.random.default_rng(seed + 1).standard_normal(n)
+    d_b = synth.signal_tod(p.pix, psi_b, sky) + np.random.default_rng(seed + 2).standard_normal(n)
+    return p, np.concatenate([p.pix, p.pix]), np.concatenate([p.psi, psi_b]), d_a, d_b
+
+
+@pytest.mark.parametrize("weight", ["band", "filter"])
+def test_pair_sum_difference_separates_intensity_and_polarisation(weight):
+    """Sect. 4: for a detector pair with orthogonal polarisers and the same
+    noise weight, the IQU system of both detectors' data splits into an
+    intensity system on d+ = (d_A + d_B)/2 with the I pointing and a
+    polarisation system on d- = (d_A - d_B)/2 with the QU pointing: the cross
+    terms of P_A^T W P_A + P_B^T W P_B cancel.  So the IQU solution equals
+    the I and QU solutions side by side."""
+    p, pix2, psi2, d_a, d_b = _pair_problem(35)
+    n = p.n_samp
+    full = O.pointing_build(pix2, psi2, p.n_pix_total, 2)
+    ptI = O.pointing_build(p.pix, None, p.n_pix_total, 1, "I")
+    ptQ = O.pointing_build(p.pix, p.psi, p.n_pix_total, 1, "QU")
+    assert np.array_equal(full.obs_pix, ptI.obs_pix) and np.array_equal(full.obs_pix, ptQ.obs_pix)
+    ist2 = np.concatenate([p.interval_start, p.interval_start[1:] + n])
+    fid2 = np.concatenate([p.filter_id, p.filter_id])
+    if weight == "band":
+        nz2 = O.noise_build(ist2, fid2, p.band, p.half_bw)
+        nzI = nzQ = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    else:
+        sub = np.unique(np.concatenate([np.arange(0, n, 37), p.interval_start]))
+        w = np.array([1.3, 0.8, 1.1])
+        nz2 = O.polyfilter_build(full, ist2, np.concatenate([w, w]),
+                                 np.concatenate([sub, sub[1:] + n]), 1)
+        nzI = O.polyfilter_build(ptI, p.interval_start, w, sub, 1)
+        nzQ = O.polyfilter_build(ptQ, p.interval_start, w, sub, 1)
+    W2 = O.dense_polyfilter(nz2) if weight == "filter" else O.dense_Ninv(nz2)
+    WI = O.dense_polyfilter(nzI) if weight == "filter" else O.dense_Ninv(nzI)
+    WQ = O.dense_polyfilter(nzQ) if weight == "filter" else O.dense_Ninv(nzQ)
+    P2, PI, PQ = O.dense_P(full), O.dense_P(ptI), O.dense_P(ptQ)
+    d2 = np.concatenate([d_a, d_b])
+    dp, dm = 0.5 * (d_a + d_b), 0.5 * (d_a - d_b)
+    A2 = P2.T @ W2 @ P2
+    # the filter leaves the intensity monopole unconstrained: solve in the
+    # least-squares sense and compare modulo that direction
+    x2 = np.linalg.lstsq(A2, P2.T @ W2 @ d2, rcond=1e-12)[0].reshape(-1, 3)
+    xI = np.linalg.lstsq(PI.T @ WI @ PI, PI.T @ WI @ dp, rcond=1e-12)[0]
+    xQ = np.linalg.solve(PQ.T @ WQ @ PQ, PQ.T @ WQ @ dm).reshape(-1, 2)
+    if weight == "filter":
+        x2[:, 0] -= x2[:, 0].mean()
+        xI = xI - xI.mean()
+    # the operator blocks themselves
+    perm = np.concatenate([np.arange(full.n_obs) * 3, (np.arange(full.n_obs)[:, None] * 3
+                                                        + np.array([1, 2])).reshape(-1)])
+    Ap = A2[np.ix_(perm, perm)]
+    nI = full.n_obs
+    assert np.max(np.abs(Ap[:nI, nI:])) <= 1e-12 * np.max(np.abs(A2))
+    assert np.max(np.abs(Ap[:nI, :nI] - 2 * PI.T @ WI @ PI)) <= 1e-12 * np.max(np.abs(A2))
+    assert np.max(np.abs(Ap[nI:, nI:] - 2 * PQ.T @ WQ @ PQ)) <= 1e-12 * np.max(np.abs(A2))
+    assert np.max(np.abs(x2[:, 0] - xI)) <= 1e-9 * np.max(np.abs(xI))
+    assert np.max(np.abs(x2[:, 1:] - xQ)) <= 1e-9 * np.max(np.abs(xQ))
+
+
+def test_qu_mbd_blocks_and_stokes_validation():
+    p = synth.random_problem(36, n_side=5, n_samp=1200, half_bw=3)
+    ptQ = O.pointing_build(p.pix, p.psi, p.n_pix_total, 3, "QU")
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    M = O.mbd_build(ptQ, nz)
+    assert M.inv.shape == (ptQ.n_obs, 2, 2)
+    full = O.pointing_build(p.pix, p.psi, p.n_pix_total, 3)
+    Mf = O.mbd_build(full, nz)
+    np.testing.assert_allclose(M.blocks, Mf.blocks[:, 1:, 1:], rtol=1e-13, atol=1e-13)
+    with pytest.raises(O.OracleError):
+        O.pointing_build(p.pix, None, p.n_pix_total, 3, "QU")
+    with pytest.raises(O.OracleError):
+        O.pointing_build(p.pix, p.psi, p.n_pix_total, 3, "Q")
