@@ -79,6 +79,15 @@ typedef enum {
     MM_NOISE_POLY = 3
 } mm_noise_method;
 
+/* Map components.  IQU: a sample measures I + Q cos 2psi + U sin 2psi (Eq.
+ * datamodel), 3 unknowns per pixel.  The sum and difference streams of a
+ * detector pair with orthogonal polarisers separate the two (Sect. 4, Eqs.
+ * d+ and d-): I (the sum stream, 1 unknown per pixel, weight 1) and QU (the
+ * difference stream, 2 per pixel, weights cos 2psi, sin 2psi).  The map
+ * layout keeps the components of a pixel together: x[(nc j + a) * nrhs + r]
+ * with nc = 3, 1 or 2, and n = nc * n_obs. */
+typedef enum { MM_STOKES_IQU = 0, MM_STOKES_I = 1, MM_STOKES_QU = 2 } mm_stokes;
+
 typedef struct mm_ctx mm_ctx;
 typedef struct mm_pointing mm_pointing;
 typedef struct mm_noise mm_noise;
@@ -111,6 +120,23 @@ const char *mm_version(void);
 mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
                             const int32_t *pix, const double *psi, int32_t min_hits,
                             mm_precision prec, mm_pointing **out);
+/* The same for the map components `stokes` (mm_pointing_build is
+ * MM_STOKES_IQU).  With MM_STOKES_I, psi may be NULL (it is not used).
+ * M_BD on such a pointing has 1x1 (I) or 2x2 (QU) blocks; every operator and
+ * solver takes maps of n = nc * n_obs entries.  Errors: as mm_pointing_build,
+ * and MM_E_INVALID for an unknown `stokes` or a NULL psi with QU or IQU. */
+mm_status mm_pointing_build_stokes(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
+                                   const int32_t *pix, const double *psi, int32_t min_hits,
+                                   mm_precision prec, mm_stokes stokes, mm_pointing **out);
+/* The pointing's map components and their count nc (3, 1 or 2).  [host] outputs. */
+mm_status mm_pointing_stokes(const mm_pointing *p, mm_stokes *stokes, int32_t *nc);
+/* Sum and difference streams of a detector pair (Eqs. d+ and d-):
+ * plus_t = (a_t + b_t) / 2, minus_t = (a_t - b_t) / 2.  a, b are the two
+ * detectors' time-aligned streams, [device] f64 or f32 (prec) [n]; plus and
+ * minus [device] of the same type (either may be NULL; they may alias a or b
+ * element for element).  Errors: MM_E_INVALID (n < 0, null inputs). */
+mm_status mm_pair_sum_diff(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a,
+                           const void *b, void *plus, void *minus);
 /* Optional locality hint: the global pixel ids are row-major on a grid of
  * `width` columns (id = row * width + column).  P^T then groups neighbouring
  * pixels of that grid (32 x 32 tiles in the one-wave-per-pixel form, 8 x 8

@@ -136,7 +136,7 @@ double *pinned(mm_ctx *ctx, size_t bytes) {
 void precond_apply_impl(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
                         double *partial, int n_part) {
     if (M->kind == 0)
-        mbd_apply_dev(ctx, M->inv.as<double>(), M->n_obs, nrhs, v, out, partial ? v : nullptr,
+        mbd_apply_dev(ctx, M->inv.as<double>(), M->n_obs, M->nc, nrhs, v, out, partial ? v : nullptr,
                       partial, n_part);
     else
         m2l_apply_dev(ctx, M, nrhs, v, out, partial, n_part);
@@ -144,7 +144,7 @@ void precond_apply_impl(mm_ctx *ctx, const mm_precond *M, int nrhs, const double
 
 // M_2l from Z (device, column-major n x k): AZ, E = Z^T AZ, Cholesky on device.
 void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M) {
-    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int64_t n = p->n();
     const int k = M->k;
     M->AZ.alloc(sizeof(double) * n * k);
     for (int c = 0; c < k; ++c)
@@ -328,29 +328,60 @@ extern "C" const char *mm_last_error(const mm_ctx *ctx) {
 
 // =============================================================== pointing
 
-extern "C" mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
-                                       const int32_t *pix, const double *psi, int32_t min_hits,
-                                       mm_precision prec, mm_pointing **out) {
+extern "C" mm_status mm_pointing_build_stokes(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
+                                              const int32_t *pix, const double *psi,
+                                              int32_t min_hits, mm_precision prec,
+                                              mm_stokes stokes, mm_pointing **out) {
     if (!ctx || !out) return MM_E_INVALID;
     *out = nullptr;
     API_BEGIN(ctx)
     MM_CHECK(n_samp > 0 && n_samp < ((int64_t)1 << 31), MM_E_INVALID,
              "n_samp must be in (0, 2^31)");
     MM_CHECK(n_pix_total > 0, MM_E_INVALID, "n_pix_total must be positive");
-    MM_CHECK(pix && psi, MM_E_INVALID, "null pix/psi");
+    MM_CHECK(stokes == MM_STOKES_IQU || stokes == MM_STOKES_I || stokes == MM_STOKES_QU,
+             MM_E_INVALID, "stokes must be IQU, I or QU");
+    MM_CHECK(pix && (psi || stokes == MM_STOKES_I), MM_E_INVALID, "null pix/psi");
     MM_CHECK(min_hits >= 1, MM_E_INVALID, "min_hits must be >= 1");
     MM_CHECK(prec == MM_F64 || prec == MM_F32, MM_E_INVALID, "bad precision");
     auto *p = new mm_pointing();
     p->n_samp = n_samp;
     p->n_pix_total = n_pix_total;
     p->prec = prec;
+    p->stokes = stokes;
+    p->nc = stokes == MM_STOKES_IQU ? 3 : stokes == MM_STOKES_QU ? 2 : 1;
     try {
-        pointing_build_device(ctx, p, pix, psi, min_hits);
+        pointing_build_device(ctx, p, pix, stokes == MM_STOKES_I ? nullptr : psi, min_hits);
     } catch (...) {
         delete p;
         throw;
     }
     *out = p;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pointing_build(mm_ctx *ctx, int64_t n_samp, int32_t n_pix_total,
+                                       const int32_t *pix, const double *psi, int32_t min_hits,
+                                       mm_precision prec, mm_pointing **out) {
+    return mm_pointing_build_stokes(ctx, n_samp, n_pix_total, pix, psi, min_hits, prec,
+                                    MM_STOKES_IQU, out);
+}
+
+extern "C" mm_status mm_pointing_stokes(const mm_pointing *p, mm_stokes *stokes, int32_t *nc) {
+    if (!p) return MM_E_INVALID;
+    if (stokes) *stokes = p->stokes;
+    if (nc) *nc = p->nc;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_pair_sum_diff(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a,
+                                      const void *b, void *plus, void *minus) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(n >= 0, MM_E_INVALID, "pair_sum_diff: negative length");
+    MM_CHECK(prec == MM_F64 || prec == MM_F32, MM_E_INVALID, "bad precision");
+    MM_CHECK(n == 0 || (a && b), MM_E_INVALID, "pair_sum_diff: null input");
+    if (n > 0 && (plus || minus)) pair_sum_diff_dev(ctx, n, prec, a, b, plus, minus);
     API_END
     return MM_OK;
 }
@@ -681,6 +712,7 @@ extern "C" mm_status mm_mbd_build(mm_ctx *ctx, const mm_pointing *p, const mm_no
     auto *M = new mm_precond();
     M->kind = 0;
     M->n_obs = p->n_obs;
+    M->nc = p->nc;
     int bad = 0;
     try {
         mbd_build_dev(ctx, p, nz, M, &bad);
@@ -711,19 +743,20 @@ extern "C" mm_status mm_defl_from_Z(mm_ctx *ctx, const mm_pointing *p, const mm_
     *out = nullptr;
     API_BEGIN(ctx)
     check_pair(p, nz);
-    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs, MM_E_INVALID,
+    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs && mbd->nc == p->nc, MM_E_INVALID,
              "defl: needs an M_BD handle of the same pointing");
-    MM_CHECK(k >= 1 && k <= 64 && k <= 3 * p->n_obs, MM_E_INVALID, "defl: k must be in [1, 64]");
+    MM_CHECK(k >= 1 && k <= 64 && k <= p->n(), MM_E_INVALID, "defl: k must be in [1, 64]");
     MM_CHECK(Z, MM_E_INVALID, "defl: null Z");
-    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int64_t n = p->n();
     auto *M = new mm_precond();
     try {
         M->kind = 1;
         M->n_obs = p->n_obs;
+    M->nc = p->nc;
         M->k = k;
         M->rcond_min = mbd->rcond_min;
-        M->inv.alloc(sizeof(double) * 6 * p->n_obs);
-        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * 6 * p->n_obs,
+        M->inv.alloc(sizeof(double) * packed_sym(p->nc) * p->n_obs);
+        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * packed_sym(p->nc) * p->n_obs,
                               hipMemcpyDeviceToDevice, ctx->stream));
         M->Z.alloc(sizeof(double) * n * k);
         MM_HIP(hipMemcpyAsync(M->Z.ptr, Z, sizeof(double) * n * k, hipMemcpyDeviceToDevice,
@@ -747,10 +780,10 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
     API_BEGIN(ctx)
     auto t_start = std::chrono::steady_clock::now();
     check_pair(p, nz);
-    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs, MM_E_INVALID,
+    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs && mbd->nc == p->nc, MM_E_INVALID,
              "defl: needs an M_BD handle of the same pointing");
     MM_CHECK(b_seed, MM_E_INVALID, "defl: null b_seed");
-    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int64_t n = p->n();
     MM_CHECK(m_max >= 1 && m_max <= 500 && m_max <= n, MM_E_INVALID, "defl: m_max in [1, min(500, n)]");
     MM_CHECK(eps_lambda > 0 || (k >= 1 && k <= 63 && k <= m_max), MM_E_INVALID,
              "defl: k in [1, 63] and <= m_max");
@@ -759,9 +792,10 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
     try {
         M->kind = 1;
         M->n_obs = p->n_obs;
+    M->nc = p->nc;
         M->rcond_min = mbd->rcond_min;
-        M->inv.alloc(sizeof(double) * 6 * p->n_obs);
-        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * 6 * p->n_obs,
+        M->inv.alloc(sizeof(double) * packed_sym(p->nc) * p->n_obs);
+        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * packed_sym(p->nc) * p->n_obs,
                               hipMemcpyDeviceToDevice, s));
         M->W.alloc(sizeof(double) * n * (m_max + 1));
         double *W = M->W.as<double>();
@@ -771,7 +805,7 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
         hd.alloc(sizeof(double) * 1024);
         double *hp = pinned(ctx, sizeof(double) * 1024);
         // w_1 = r_0 / ||r_0||, r_0 = M_BD b
-        mbd_apply_dev(ctx, M->inv.as<double>(), p->n_obs, 1, b_seed, v.as<double>(), nullptr,
+        mbd_apply_dev(ctx, M->inv.as<double>(), p->n_obs, p->nc, 1, b_seed, v.as<double>(), nullptr,
                       nullptr, 0);
         dot_cols(ctx, n, 1, v.as<double>(), v.as<double>(), hd.as<double>());
         MM_HIP(hipMemcpyAsync(hp, hd.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -787,7 +821,7 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
         for (int j = 0; j < m_max; ++j) {
             const double *wj = W + (int64_t)j * n;
             apply_A_impl(ctx, p, nz, 1, wj, tmp.as<double>());
-            mbd_apply_dev(ctx, M->inv.as<double>(), p->n_obs, 1, tmp.as<double>(),
+            mbd_apply_dev(ctx, M->inv.as<double>(), p->n_obs, p->nc, 1, tmp.as<double>(),
                           v.as<double>(), nullptr, nullptr, 0);
             // classical Gram-Schmidt, applied twice
             gemv_t(ctx, n, j + 1, W, v.as<double>(), hd.as<double>());
@@ -919,7 +953,7 @@ extern "C" mm_status mm_defl_export(mm_ctx *ctx, const mm_precond *M, int32_t *k
     if (!ctx) return MM_E_INVALID;
     API_BEGIN(ctx)
     MM_CHECK(M && M->kind == 1, MM_E_INVALID, "defl_export: not an M_2l handle");
-    const int64_t n = 3 * (int64_t)M->n_obs;
+    const int64_t n = M->n();
     if (k) *k = M->k;
     if (Z) MM_HIP(hipMemcpyAsync(Z, M->Z.ptr, sizeof(double) * n * M->k, hipMemcpyDeviceToDevice, ctx->stream));
     if (AZ) MM_HIP(hipMemcpyAsync(AZ, M->AZ.ptr, sizeof(double) * n * M->k, hipMemcpyDeviceToDevice, ctx->stream));
@@ -934,7 +968,7 @@ extern "C" mm_status mm_defl_arnoldi_export(mm_ctx *ctx, const mm_precond *M, in
     if (!ctx) return MM_E_INVALID;
     API_BEGIN(ctx)
     MM_CHECK(M && M->kind == 1, MM_E_INVALID, "arnoldi_export: not an M_2l handle");
-    const int64_t n = 3 * (int64_t)M->n_obs;
+    const int64_t n = M->n();
     if (m) *m = M->arn_m;
     if (W && M->arn_m > 0)
         MM_HIP(hipMemcpyAsync(W, M->W.ptr, sizeof(double) * n * (M->arn_m + 1),
@@ -975,7 +1009,7 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     check_nrhs(nrhs);
     MM_CHECK(b && x && b != x, MM_E_INVALID, "solve: bad b/x");
     MM_CHECK(tol >= 0 && max_iter >= 0, MM_E_INVALID, "solve: bad tol/max_iter");
-    MM_CHECK(!M || M->n_obs == p->n_obs, MM_E_INVALID, "solve: preconditioner of another pointing");
+    MM_CHECK(!M || (M->n_obs == p->n_obs && M->nc == p->nc), MM_E_INVALID, "solve: preconditioner of another pointing");
     if (flags & MM_SOLVE_BLOCK) {
         MM_CHECK(nrhs >= 2, MM_E_INVALID, "solve: block CG needs nrhs >= 2");
         result = block_cg(ctx, p, nz, M, nrhs, b, x, tol, max_iter, std::max(1u, flags & 0xffu),
@@ -984,7 +1018,7 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = ctx->stream;
-    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int64_t n = p->n();
     const int R = nrhs;
     PcgWork w;
     w.alloc(n, R);
@@ -1093,7 +1127,7 @@ static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                           int max_iter, int check, double *history, mm_solve_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = ctx->stream;
-    const int64_t n = 3 * (int64_t)p->n_obs;
+    const int64_t n = p->n();
     const size_t vb = sizeof(double) * n * R;
     DBuf Rr, Z, Pb, Q, Qt, sm, ib, rn, bn;
     Rr.alloc(vb); Z.alloc(vb); Pb.alloc(vb); Q.alloc(vb); Qt.alloc(vb);
@@ -1208,13 +1242,13 @@ extern "C" mm_status mm_pcg_create(mm_ctx *ctx, const mm_pointing *p, const mm_n
     API_BEGIN(ctx)
     check_pair(p, nz);
     check_nrhs(nrhs);
-    MM_CHECK(!M || M->n_obs == p->n_obs, MM_E_INVALID, "pcg: preconditioner of another pointing");
+    MM_CHECK(!M || (M->n_obs == p->n_obs && M->nc == p->nc), MM_E_INVALID, "pcg: preconditioner of another pointing");
     auto *S = new mm_pcg();
     try {
         S->p = p;
         S->nz = nz;
         S->M = M;
-        const int64_t n = 3 * (int64_t)p->n_obs;
+        const int64_t n = p->n();
         S->w.alloc(n, nrhs);
         S->x.alloc(sizeof(double) * n * nrhs);
         S->tb.alloc(sizeof(double) * n);

@@ -99,6 +99,73 @@ __global__ void __launch_bounds__(BS) k_mbd_build(const int32_t *__restrict__ of
     o[0] = i00; o[1] = i01; o[2] = i02; o[3] = i11; o[4] = i12; o[5] = i22;
 }
 
+// I (NC = 1: B_j = sum c0) and QU (NC = 2: B_j = sum c0 (c, s)(c, s)^T)
+// blocks; one wave per compact pixel, lane 0 inverts.  inv holds the packed
+// symmetric inverse, (00) or (00, 01, 11).
+template <typename T, int NC>
+__global__ void __launch_bounds__(BS) k_mbd_build_nc(const int32_t *__restrict__ off,
+                                                     const int32_t *__restrict__ perm,
+                                                     const typename Vec2w<T>::type *__restrict__ ws,
+                                                     const int64_t *__restrict__ istart, int n_int,
+                                                     const int32_t *__restrict__ fid,
+                                                     const double *__restrict__ band64, int lam,
+                                                     int32_t n_obs, double *__restrict__ inv,
+                                                     double *__restrict__ rcond,
+                                                     int *__restrict__ n_bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (j >= n_obs) return;
+    const int32_t a = off[j], b = off[j + 1];
+    double s[3] = {0, 0, 0};
+    for (int32_t i = a + lane; i < b; i += 64) {
+        const int64_t t = perm[i];
+        const double c0 = band64[(int64_t)fid[find_interval(istart, n_int, t)] * (lam + 1)];
+        if constexpr (NC == 1) {
+            s[0] += c0;
+        } else {
+            const auto ww = ws[i];
+            const double c = (double)ww.x, sn = (double)ww.y;
+            s[0] += c0 * c * c;
+            s[1] += c0 * c * sn;
+            s[2] += c0 * sn * sn;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s[q] += __shfl_xor(s[q], m);
+    if (lane != 0) return;
+    bool ok;
+    double rc;
+    if constexpr (NC == 1) {
+        ok = s[0] > 0;
+        inv[j] = ok ? 1.0 / s[0] : 0.0;
+        rc = ok ? 1.0 : 0.0;
+    } else {
+        // Cholesky of [[b00, b01], [b01, b11]], then the inverse
+        const double b00 = s[0], b01 = s[1], b11 = s[2];
+        ok = b00 > 0;
+        const double l00 = ok ? sqrt(b00) : 1, l10 = b01 / l00;
+        const double d1 = b11 - l10 * l10;
+        ok = ok && d1 > 0;
+        const double l11 = d1 > 0 ? sqrt(d1) : 1;
+        const double m00 = 1 / l00, m11 = 1 / l11, m10 = -l10 * m00 * m11;
+        const double i00 = m00 * m00 + m10 * m10, i01 = m11 * m10, i11 = m11 * m11;
+        const double nb = fmax(fabs(b00) + fabs(b01), fabs(b01) + fabs(b11));
+        const double ni = fmax(fabs(i00) + fabs(i01), fabs(i01) + fabs(i11));
+        rc = ok ? 1.0 / (nb * ni) : 0.0;
+        double *o = inv + 3 * j;
+        o[0] = i00;
+        o[1] = i01;
+        o[2] = i11;
+    }
+    if (!(rc >= 1e-12)) {
+        atomicAdd(n_bad, 1);
+        ok = false;
+    }
+    rcond[j] = ok ? rc : 0.0;
+}
+
 __global__ void k_min_reduce(const double *__restrict__ v, int64_t n, double *__restrict__ out) {
     __shared__ double sm[BS];
     double m = 1e300;
@@ -132,7 +199,19 @@ __device__ __forceinline__ void block_col_reduce(double v, double *__restrict__ 
 
 // out = B_j^-1 v per pixel and column; optionally partial sums of
 // dot_with . out per column (fused r.z of PCG).
-template <int R>
+// Packed symmetric NC x NC block times a vector of NC entries (NC = 1, 2).
+template <int NC>
+__device__ __forceinline__ void sym_mul(const double *__restrict__ m, const double *u,
+                                        double *o) {
+    if constexpr (NC == 1) {
+        o[0] = m[0] * u[0];
+    } else {
+        o[0] = m[0] * u[0] + m[1] * u[1];
+        o[1] = m[1] * u[0] + m[2] * u[1];
+    }
+}
+
+template <int R, int NC>
 __global__ void __launch_bounds__(BS) k_mbd_apply(const double *__restrict__ inv, int32_t n_obs,
                                                   const double *__restrict__ v,
                                                   double *__restrict__ out,
@@ -145,6 +224,22 @@ __global__ void __launch_bounds__(BS) k_mbd_apply(const double *__restrict__ inv
     int64_t p1 = p0 + pix_per_block;
     if (p1 > n_obs) p1 = n_obs;
     double acc = 0;
+    if constexpr (NC != 3) {
+        for (int64_t j = p0 + rg; j < p1; j += NG) {
+            const int64_t base = NC * j * R + r;
+            double u[NC], o[NC];
+#pragma unroll
+            for (int a = 0; a < NC; ++a) u[a] = v[base + a * R];
+            sym_mul<NC>(inv + (NC * (NC + 1) / 2) * j, u, o);
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                out[base + a * R] = o[a];
+                if (dot_with) acc += dot_with[base + a * R] * o[a];
+            }
+        }
+        if (partial) block_col_reduce<R>(acc, partial);
+        return;
+    }
     for (int64_t j = p0 + rg; j < p1; j += NG) {
         const double *m = inv + 6 * j;
         const int64_t base = 3 * j * R + r;
@@ -574,7 +669,7 @@ __global__ void __launch_bounds__(64) k_coarse_solve(int k, int R, const double 
 
 // out = M_BD (v - AZ c) + Z c per pixel and column (Eq. m2l), with optional
 // partial sums of dot_with . out.  Z, AZ are column-major n x k, c is k x R.
-template <int R>
+template <int R, int NC>
 __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv, int32_t n_obs,
                                                   int k, int64_t n, const double *__restrict__ Z,
                                                   const double *__restrict__ AZ,
@@ -593,6 +688,33 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
     int64_t p1 = p0 + pix_per_block;
     if (p1 > n_obs) p1 = n_obs;
     double acc = 0;
+    if constexpr (NC != 3) {
+        for (int64_t j = p0 + rg; j < p1; j += NG) {
+            double u[NC], zc[NC], o[NC];
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                const int64_t row = NC * j + a;
+                double s_az = 0, s_z = 0;
+                for (int q = 0; q < k; ++q) {
+                    const double cq = sc[q * R + r];
+                    s_az += AZ[(int64_t)q * n + row] * cq;
+                    s_z += Z[(int64_t)q * n + row] * cq;
+                }
+                u[a] = v[row * R + r] - s_az;
+                zc[a] = s_z;
+            }
+            sym_mul<NC>(inv + (NC * (NC + 1) / 2) * j, u, o);
+#pragma unroll
+            for (int a = 0; a < NC; ++a) {
+                const int64_t e = (NC * j + a) * R + r;
+                const double oe = o[a] + zc[a];
+                out[e] = oe;
+                if (dot_with) acc += dot_with[e] * oe;
+            }
+        }
+        if (partial) block_col_reduce<R>(acc, partial);
+        return;
+    }
     for (int64_t j = p0 + rg; j < p1; j += NG) {
         double u[3], zc[3];
 #pragma unroll
@@ -798,7 +920,7 @@ void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_pre
                    int *n_bad_out) {
     hipStream_t s = ctx->stream;
     const int32_t n_obs = p->n_obs;
-    M->inv.alloc(sizeof(double) * 6 * (n_obs > 0 ? n_obs : 1));
+    M->inv.alloc(sizeof(double) * packed_sym(p->nc) * (n_obs > 0 ? n_obs : 1));
     DBuf rc, bad, mn;
     rc.alloc(sizeof(double) * (n_obs > 0 ? n_obs : 1));
     bad.alloc(sizeof(int));
@@ -806,7 +928,23 @@ void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_pre
     MM_HIP(hipMemsetAsync(bad.ptr, 0, sizeof(int), s));
     if (n_obs > 0) {
         const unsigned nb = (unsigned)((n_obs + 3) / 4);
-        if (p->prec == MM_F32)
+        auto nc_build = [&](auto TT, auto NN) {
+            using T = decltype(TT);
+            constexpr int NC = decltype(NN)::value;
+            k_mbd_build_nc<T, NC><<<nb, BS, 0, s>>>(
+                p->off.as<int32_t>(), p->perm.as<int32_t>(),
+                NC == 2 ? static_cast<const typename Vec2w<T>::type *>(p->ws.ptr) : nullptr,
+                nz->istart.as<int64_t>(), nz->n_int, nz->fid.as<int32_t>(),
+                nz->band64.as<double>(), nz->half_bw, n_obs, M->inv.as<double>(), rc.as<double>(),
+                bad.as<int>());
+        };
+        if (p->nc == 1)
+            nc_build(0.0, std::integral_constant<int, 1>());
+        else if (p->nc == 2 && p->prec == MM_F32)
+            nc_build(0.f, std::integral_constant<int, 2>());
+        else if (p->nc == 2)
+            nc_build(0.0, std::integral_constant<int, 2>());
+        else if (p->prec == MM_F32)
             k_mbd_build<float><<<nb, BS, 0, s>>>(p->off.as<int32_t>(), p->perm.as<int32_t>(),
                                                  p->ws.as<float2>(), nz->istart.as<int64_t>(),
                                                  nz->n_int, nz->fid.as<int32_t>(),
@@ -832,16 +970,25 @@ void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_pre
     *n_bad_out = hb;
 }
 
-void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nrhs, const double *v,
-                   double *out, const double *dot_with, double *partial, int n_part) {
+void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nc, int nrhs,
+                   const double *v, double *out, const double *dot_with, double *partial,
+                   int n_part) {
     Scope sc(ctx->prof, ctx->stream, "precond");
     if (n_obs == 0) return;
-    // partition: n_part blocks over pixels (3 rows each)
-    const int parts = partial ? n_part : reduction_parts(3 * (int64_t)n_obs, nrhs);
+    // partition: n_part blocks over pixels (nc rows each)
+    const int parts = partial ? n_part : reduction_parts((int64_t)nc * n_obs, nrhs);
     const int64_t ppb = rows_per(n_obs, parts);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        k_mbd_apply<R><<<parts, BS, 0, ctx->stream>>>(inv, n_obs, v, out, dot_with, partial, ppb);
+        if (nc == 1)
+            k_mbd_apply<R, 1><<<parts, BS, 0, ctx->stream>>>(inv, n_obs, v, out, dot_with,
+                                                              partial, ppb);
+        else if (nc == 2)
+            k_mbd_apply<R, 2><<<parts, BS, 0, ctx->stream>>>(inv, n_obs, v, out, dot_with,
+                                                              partial, ppb);
+        else
+            k_mbd_apply<R, 3><<<parts, BS, 0, ctx->stream>>>(inv, n_obs, v, out, dot_with,
+                                                              partial, ppb);
     });
     MM_HIP(hipGetLastError());
 }
@@ -1009,7 +1156,7 @@ void chol_small_dev(mm_ctx *ctx, int k, const double *E, double *Lc, int *flag) 
 }
 
 void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c) {
-    const int64_t n = 3 * (int64_t)M->n_obs;
+    const int64_t n = M->n();
     const int k = M->k;
     ws_alloc(ctx, ctx->coef_g, sizeof(double) * 64 * 64);
     double *g = ctx->coef_g.as<double>();
@@ -1026,7 +1173,7 @@ void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, d
 void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
                    double *partial, int n_part) {
     Scope sc(ctx->prof, ctx->stream, "precond");
-    const int64_t n = 3 * (int64_t)M->n_obs;
+    const int64_t n = M->n();
     const int k = M->k;
     ws_alloc(ctx, ctx->scal, sizeof(double) * 64 * 64 + 4096);
     double *c = ctx->scal.as<double>();
@@ -1035,9 +1182,15 @@ void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, 
     const int64_t ppb = rows_per(M->n_obs, parts);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        k_m2l_final<R><<<parts, BS, 0, ctx->stream>>>(M->inv.as<double>(), M->n_obs, k, n,
-                                                      M->Z.as<double>(), M->AZ.as<double>(), c,
-                                                      v, out, partial ? v : nullptr, partial, ppb);
+        auto go = [&](auto NN) {
+            constexpr int NC = decltype(NN)::value;
+            k_m2l_final<R, NC><<<parts, BS, 0, ctx->stream>>>(
+                M->inv.as<double>(), M->n_obs, k, n, M->Z.as<double>(), M->AZ.as<double>(), c, v,
+                out, partial ? v : nullptr, partial, ppb);
+        };
+        if (M->nc == 1) go(std::integral_constant<int, 1>());
+        else if (M->nc == 2) go(std::integral_constant<int, 2>());
+        else go(std::integral_constant<int, 3>());
     });
     MM_HIP(hipGetLastError());
 }

@@ -133,6 +133,11 @@ struct mm_pointing {
     int32_t n_obs = 0;
     int64_t n_valid = 0;
     mm_precision prec = MM_F64;
+    // map components: IQU (3 per pixel), I (1: weights 1, no angles kept) or
+    // QU (2: weights cos 2psi, sin 2psi)
+    mm_stokes stokes = MM_STOKES_IQU;
+    int32_t nc = 3;
+    int64_t n() const { return (int64_t)nc * n_obs; }
     mm::DBuf hits, obs_pix, j, w, perm, ws, off;
     mm::DBuf psi;  // f64[n_samp] angles (FP64 form only)
     // Map slots of the single-column FP64 P: with a grid, observed pixels are
@@ -203,7 +208,11 @@ struct mm_noise {
 struct mm_precond {
     int kind = 0;  // 0 = M_BD, 1 = M_2l
     int32_t n_obs = 0;
-    mm::DBuf inv;  // f64[n_obs][6] packed symmetric B_j^-1
+    int32_t nc = 3;  // map components per pixel (the pointing's)
+    int64_t n() const { return (int64_t)nc * n_obs; }
+    // f64[n_obs][nc (nc + 1) / 2] packed symmetric B_j^-1: (00, 01, 02, 11,
+    // 12, 22) for IQU, (00, 01, 11) for QU, (00) for I
+    mm::DBuf inv;
     double rcond_min = 0;
     // M_2l
     int32_t k = 0;
@@ -233,6 +242,8 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
 void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
 void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_rm, void *y,
                   int *nonfinite_flag);
+void pair_sum_diff_dev(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a, const void *b,
+                       void *plus, void *minus);
 void noise_prepare(mm_ctx *ctx, mm_noise *nz);  // tiles, FFT spectra
 // polyfilter.hip
 int polyfilter_max_order();
@@ -244,8 +255,10 @@ bool noise_fft_supported(int half_bw, int64_t min_len);
 // map_ops.hip
 void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M,
                    int *n_bad);
-void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nrhs, const double *v,
-                   double *out, const double *dot_with, double *dot_partial, int n_part);
+void mbd_apply_dev(mm_ctx *ctx, const double *inv, int32_t n_obs, int nc, int nrhs,
+                   const double *v, double *out, const double *dot_with, double *dot_partial,
+                   int n_part);
+inline int packed_sym(int nc) { return nc * (nc + 1) / 2; }
 
 // Deterministic dot products of columns: out[r] = sum_i a[i R + r] b[i R + r]
 // over n rows (two stages, fixed order).

@@ -25,7 +25,7 @@ __global__ void k_validate(const int32_t *__restrict__ pix, const double *__rest
     for (int64_t t = blockIdx.x * (int64_t)BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
         int32_t p = pix[t];
         bad_pix |= (p < -1 || p >= npt);
-        bad_psi |= !isfinite(psi[t]);
+        if (psi) bad_psi |= !isfinite(psi[t]);
     }
     if (bad_pix) atomicOr(&flags[0], 1);
     if (bad_psi) atomicOr(&flags[1], 1);
@@ -251,7 +251,7 @@ void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     p->p_slot.release();
     p->p_j.release();
     const int32_t n_obs = p->n_obs;
-    if (width <= 0 || n_obs == 0 || p->prec != MM_F64) return;
+    if (width <= 0 || n_obs == 0 || p->prec != MM_F64 || p->nc != 3) return;
     DBuf keys, vals, ko, order, tmp;
     keys.alloc(sizeof(uint64_t) * n_obs);
     vals.alloc(sizeof(int32_t) * n_obs);
@@ -324,7 +324,8 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     p->sl_perm.release();
     p->sl_w.release();
     const int32_t n_obs = p->n_obs;
-    if (n_obs == 0 || p->n_valid == 0) return;
+    // IQU only: the I and QU pointings reduce with the one-wave-per-pixel form
+    if (n_obs == 0 || p->n_valid == 0 || p->nc != 3) return;
     const int32_t G = (n_obs + 63) / 64;
     const int32_t S = slice_segments(p->n_samp, p->n_valid, n_obs, G);
     // below ~2,048 waves the one-wave-per-pixel kernel is the faster one
@@ -484,8 +485,19 @@ void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, cons
 
     // weights in time order and in pixel-sorted order; the FP64 form also
     // keeps the angles, from which its single-column P and P^T form the
-    // weights on the fly (8 bytes per sample read instead of 16)
+    // weights on the fly (8 bytes per sample read instead of 16).  An
+    // intensity-only pointing has unit weights and keeps neither.
     const bool f32 = p->prec == MM_F32;
+    if (p->nc == 1) {
+        std::vector<int32_t> hoff1(n_obs + 1);
+        MM_HIP(hipMemcpyAsync(hoff1.data(), p->off.ptr, sizeof(int32_t) * (n_obs + 1),
+                              hipMemcpyDeviceToHost, s));
+        MM_HIP(hipStreamSynchronize(s));
+        int32_t mx1 = 0;
+        for (int32_t c = 0; c < n_obs; ++c) mx1 = std::max(mx1, hoff1[c + 1] - hoff1[c]);
+        p->max_seg = mx1;
+        return;
+    }
     if (!f32) {
         p->psi.alloc(sizeof(double) * n);
         MM_HIP(hipMemcpyAsync(p->psi.ptr, psi, sizeof(double) * n, hipMemcpyDeviceToDevice, s));

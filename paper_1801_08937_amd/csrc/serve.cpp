@@ -195,7 +195,7 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
                          MM_NOISE_AUTO, prec, &st->nz),
           st->ctx, "server: noise");
     check(mm_mbd_build(st->ctx, st->p, st->nz, &st->mbd), st->ctx, "server: M_BD");
-    st->n = 3 * (int64_t)st->p->n_obs;
+    st->n = st->p->n();
     st->b.alloc(sizeof(double) * st->n);
     for (auto &l : st->lane) l.slot_req.assign(srv->slots, -1);
     st->bytes = bytes;

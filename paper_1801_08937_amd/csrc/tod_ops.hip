@@ -388,6 +388,89 @@ __global__ void __launch_bounds__(BS) k_band(const int64_t *__restrict__ tiles,
     }
 }
 
+// Pointings of the pair-sum (I, NC = 1: weight 1) and pair-difference (QU,
+// NC = 2: weights cos 2psi, sin 2psi) streams (Eqs. d+ and d-).  Same
+// structure as k_apply_P / k_apply_PT; map x[(NC j + a) R + r].
+template <typename T, int R, int NC>
+__device__ __forceinline__ T p_gather_nc(int32_t j, typename Vec2<T>::type ww,
+                                         const double *__restrict__ x, int r) {
+    if (j < 0) return (T)0;
+    const double *xp = x + (int64_t)NC * j * R + r;
+    if constexpr (NC == 1) return (T)xp[0];
+    else return ww.x * (T)xp[0] + ww.y * (T)xp[R];
+}
+
+template <typename T, int R, int NC>
+__global__ void __launch_bounds__(BS) k_apply_P_nc(const int32_t *__restrict__ jpix,
+                                                   const typename Vec2<T>::type *__restrict__ w,
+                                                   int64_t n, const double *__restrict__ x,
+                                                   T *__restrict__ y) {
+    constexpr int G = 64 / R;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / R, r = lane % R;
+    const int64_t wave = ((int64_t)blockIdx.x * BS + threadIdx.x) >> 6;
+    const int64_t nwave = ((int64_t)gridDim.x * BS) >> 6;
+    const int64_t step = nwave * G;
+    for (int64_t t = wave * G + sub; t < n; t += step) {
+        typename Vec2<T>::type ww{};
+        if constexpr (NC == 2) ww = w[t];
+        y[t * R + r] = p_gather_nc<T, R, NC>(jpix[t], ww, x, r);
+    }
+}
+
+template <typename T, int R, int NC>
+__global__ void __launch_bounds__(BS) k_apply_PT_nc(const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ perm,
+                                                    const typename Vec2<T>::type *__restrict__ ws,
+                                                    int32_t n_obs,
+                                                    const int32_t *__restrict__ order,
+                                                    const T *__restrict__ z,
+                                                    double *__restrict__ x) {
+    constexpr int G = 64 / R;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / R, r = lane % R;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t s = blk * (BS / 64) + (threadIdx.x >> 6);
+    if (s >= n_obs) return;
+    const int64_t j = order ? order[s] : s;
+    const int32_t a = off[j], b = off[j + 1];
+    T s0 = 0, s1 = 0;
+    for (int32_t i = a + sub; i < b; i += G) {
+        const T zq = z[(int64_t)perm[i] * R + r];
+        if constexpr (NC == 1) {
+            s0 += zq;
+        } else {
+            const auto wq = ws[i];
+            s0 += wq.x * zq;
+            s1 += wq.y * zq;
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= R; m >>= 1) {
+        s0 += __shfl_xor(s0, m);
+        if constexpr (NC == 2) s1 += __shfl_xor(s1, m);
+    }
+    if (sub == 0) {
+        double *xp = x + (int64_t)NC * j * R + r;
+        xp[0] = (double)s0;
+        if constexpr (NC == 2) xp[R] = (double)s1;
+    }
+}
+
+// plus = (a + b) / 2, minus = (a - b) / 2 (either output may be null; an
+// output may be one of the inputs, as each element is read before it is
+// written).
+template <typename T>
+__global__ void __launch_bounds__(BS) k_sum_diff(int64_t n, const T *a, const T *b, T *plus,
+                                                 T *minus) {
+    for (int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * BS) {
+        const T u = a[t], v = b[t];
+        if (plus) plus[t] = (u + v) * (T)0.5;
+        if (minus) minus[t] = (u - v) * (T)0.5;
+    }
+}
+
 // y[t R + r] = mask_t * tod[r * n + t]; flags non-finite data on kept samples.
 template <typename T, int R>
 __global__ void __launch_bounds__(BS) k_mask(const int32_t *__restrict__ jpix, int64_t n,
@@ -433,6 +516,29 @@ template <typename F> void dispatch_r(int nrhs, F &&f) {
 void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y) {
     Scope sc(ctx->prof, ctx->stream, "P");
     const int64_t n = p->n_samp;
+    if (p->nc != 3) {
+        dispatch_r(nrhs, [&](auto RR) {
+            constexpr int R = decltype(RR)::value;
+            const int grid = grid_for(n * R, 8 * ctx->n_cu * 4);
+            auto go = [&](auto TT, auto NN) {
+                using T = decltype(TT);
+                constexpr int NC = decltype(NN)::value;
+                k_apply_P_nc<T, R, NC><<<grid, BS, 0, ctx->stream>>>(
+                    p->j.as<int32_t>(),
+                    NC == 2 ? static_cast<const typename Vec2<T>::type *>(p->w.ptr) : nullptr, n,
+                    x, static_cast<T *>(y));
+            };
+            if (p->prec == MM_F32) {
+                if (p->nc == 1) go(0.f, std::integral_constant<int, 1>());
+                else go(0.f, std::integral_constant<int, 2>());
+            } else {
+                if (p->nc == 1) go(0.0, std::integral_constant<int, 1>());
+                else go(0.0, std::integral_constant<int, 2>());
+            }
+        });
+        MM_HIP(hipGetLastError());
+        return;
+    }
     if (nrhs == 1) {
         const size_t no = (size_t)(p->n_obs > 0 ? p->n_obs : 1);
         ws_alloc(ctx, ctx->xpack, sizeof(double2) * 2 * no);
@@ -478,6 +584,31 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
 void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x) {
     Scope sc(ctx->prof, ctx->stream, "PT");
     if (p->n_obs == 0) return;
+    if (p->nc != 3) {
+        int64_t nb = (p->n_obs + 3) / 4;
+        if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
+        const int32_t *order = p->seg_order.ptr ? p->seg_order.as<int32_t>() : nullptr;
+        dispatch_r(nrhs, [&](auto RR) {
+            constexpr int R = decltype(RR)::value;
+            auto go = [&](auto TT, auto NN) {
+                using T = decltype(TT);
+                constexpr int NC = decltype(NN)::value;
+                k_apply_PT_nc<T, R, NC><<<(unsigned)nb, BS, 0, ctx->stream>>>(
+                    p->off.as<int32_t>(), p->perm.as<int32_t>(),
+                    NC == 2 ? static_cast<const typename Vec2<T>::type *>(p->ws.ptr) : nullptr,
+                    p->n_obs, order, static_cast<const T *>(z), x);
+            };
+            if (p->prec == MM_F32) {
+                if (p->nc == 1) go(0.f, std::integral_constant<int, 1>());
+                else go(0.f, std::integral_constant<int, 2>());
+            } else {
+                if (p->nc == 1) go(0.0, std::integral_constant<int, 1>());
+                else go(0.0, std::integral_constant<int, 2>());
+            }
+        });
+        MM_HIP(hipGetLastError());
+        return;
+    }
     if (nrhs == 1 && p->sl_G > 0) {
         const int32_t G = p->sl_G, S = p->sl_S;
         const int64_t n3 = 3 * (int64_t)p->n_obs;
@@ -559,6 +690,20 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
                 lam, tl, static_cast<const double *>(y), static_cast<double *>(z));
         }
     });
+    MM_HIP(hipGetLastError());
+}
+
+void pair_sum_diff_dev(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a, const void *b,
+                       void *plus, void *minus) {
+    const int grid = grid_for(n);
+    if (prec == MM_F32)
+        k_sum_diff<float><<<grid, BS, 0, ctx->stream>>>(
+            n, static_cast<const float *>(a), static_cast<const float *>(b),
+            static_cast<float *>(plus), static_cast<float *>(minus));
+    else
+        k_sum_diff<double><<<grid, BS, 0, ctx->stream>>>(
+            n, static_cast<const double *>(a), static_cast<const double *>(b),
+            static_cast<double *>(plus), static_cast<double *>(minus));
     MM_HIP(hipGetLastError());
 }
 

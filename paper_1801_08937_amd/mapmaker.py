@@ -25,6 +25,7 @@ STATUS = {0: "MM_OK", 1: "MM_NOT_CONVERGED", -1: "MM_E_INVALID", -2: "MM_E_OOM",
           -6: "MM_E_BREAKDOWN", -7: "MM_E_NONFINITE", -8: "MM_E_BUSY"}
 F64, F32 = 0, 1
 NOISE_AUTO, NOISE_DIRECT, NOISE_FFT, NOISE_POLY = 0, 1, 2, 3
+STOKES = {"IQU": 0, "I": 1, "QU": 2}
 
 
 class MapmakerError(RuntimeError):
@@ -70,6 +71,9 @@ def lib() -> C.CDLL:
             "mm_ctx_destroy": (None, [P]),
             "mm_last_error": (C.c_char_p, [P]),
             "mm_pointing_build": (C.c_int, [P, I64, I32, P, P, I32, C.c_int, PP]),
+            "mm_pointing_build_stokes": (C.c_int, [P, I64, I32, P, P, I32, C.c_int, C.c_int, PP]),
+            "mm_pointing_stokes": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int32)]),
+            "mm_pair_sum_diff": (C.c_int, [P, I64, C.c_int, P, P, P, P]),
             "mm_pointing_counts": (C.c_int, [P, C.POINTER(I32), C.POINTER(I64)]),
             "mm_pointing_pt_layout": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
             "mm_pointing_set_grid": (C.c_int, [P, P, I32]),
@@ -202,15 +206,39 @@ class Context:
         self.stream.synchronize()
 
     # ------------------------------------------------------------- builders
-    def pointing(self, pix, psi, n_pix_total: int, min_hits: int = 3, prec: int = F64):
+    def pointing(self, pix, psi, n_pix_total: int, min_hits: int = 3, prec: int = F64,
+                 stokes: str = "IQU"):
+        """P from per-sample pixels and angles; stokes "IQU", "I" (pair-sum
+        stream, psi may be None) or "QU" (pair-difference stream)."""
         import torch
         _dev_check(pix, torch.int32, name="pix")
-        _dev_check(psi, torch.float64, pix.numel(), name="psi")
+        if stokes not in STOKES:
+            raise ValueError("stokes must be IQU, I or QU")
+        if psi is not None:
+            _dev_check(psi, torch.float64, pix.numel(), name="psi")
         h = C.c_void_p()
-        self._check(lib().mm_pointing_build(self.h, pix.numel(), n_pix_total, _ptr(pix),
-                                            _ptr(psi), min_hits, prec, C.byref(h)),
-                    "mm_pointing_build")
+        self._check(lib().mm_pointing_build_stokes(self.h, pix.numel(), n_pix_total, _ptr(pix),
+                                                   None if psi is None else _ptr(psi), min_hits,
+                                                   prec, STOKES[stokes], C.byref(h)),
+                    "mm_pointing_build_stokes")
         return Pointing(self, h, pix.numel(), n_pix_total, prec)
+
+    def pair_sum_diff(self, a, b, plus=None, minus=None):
+        """Sum and difference streams of a detector pair (Eqs. d+, d-):
+        ((a + b) / 2, (a - b) / 2), on the device."""
+        import torch
+        if a.dtype not in (torch.float64, torch.float32):
+            raise ValueError("a must be float64 or float32")
+        _dev_check(a, a.dtype, name="a")
+        _dev_check(b, a.dtype, a.numel(), name="b")
+        plus = torch.empty_like(a) if plus is None else plus
+        minus = torch.empty_like(a) if minus is None else minus
+        _dev_check(plus, a.dtype, a.numel(), name="plus")
+        _dev_check(minus, a.dtype, a.numel(), name="minus")
+        prec = F32 if a.dtype == torch.float32 else F64
+        self._check(lib().mm_pair_sum_diff(self.h, a.numel(), prec, _ptr(a), _ptr(b), _ptr(plus),
+                                           _ptr(minus)), "mm_pair_sum_diff")
+        return plus, minus
 
     def noise(self, interval_start, filter_id, band, half_bw: int, method: int = NOISE_AUTO,
               prec: int = F64):
@@ -415,7 +443,11 @@ class Pointing(_Handle):
         n_obs, n_valid = C.c_int32(), C.c_int64()
         lib().mm_pointing_counts(h, C.byref(n_obs), C.byref(n_valid))
         self.n_obs, self.n_valid = n_obs.value, n_valid.value
-        self.n = 3 * self.n_obs
+        st, nc = C.c_int(), C.c_int32()
+        lib().mm_pointing_stokes(h, C.byref(st), C.byref(nc))
+        self.stokes = {v: k for k, v in STOKES.items()}[st.value]
+        self.nc = nc.value
+        self.n = self.nc * self.n_obs
 
     def set_grid(self, width: int):
         """Locality hint: global ids are row-major with `width` columns."""
