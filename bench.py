@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -149,7 +149,7 @@ def main():
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
-              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True),
+              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -566,6 +566,90 @@ def form_f1(mm, ctx, ground=False):
             "polynomials removed per 256-sample subscan" +
             (" and azimuth-binned ground templates per constant-elevation pass" if ground else "")
             + " (F_T of Sects. 2 and 4), M_BD vs M_2l (k = 32), tol 1e-8", **out}
+
+
+def form_p1(mm, ctx, orders=(("I", 2), ("QU", 1))):
+    """Detector pairs and the sum/difference decomposition (Sect. 4, Eqs. d+
+    and d-): 64 pairs on the config-2 scan (a 16 x 4 focal-plane grid, 2^20
+    samples per detector, so 1.34e8 samples over both detectors of every
+    pair), B's polariser turned by 90 degrees.  White noise, and per 256-sample
+    subscan Legendre polynomials up to order 2 removed from d+ and up to order
+    1 from d-, as the paper filters its streams.  The intensity map comes
+    from the I system on d+, the polarisation map from the QU system on d-;
+    each is solved to 1e-8 with M_BD and with M_2l (k = 32).  Two angle
+    models: psi iid per sample (the scan's own), and a fixed angle per pair
+    (pi k / 64) plus a half-wave plate stepped by 22.5 degrees between passes,
+    so that the angle is constant along every subscan."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    p = synth.config2(grid=(16, 4), noiseless=True)
+    n = p.n_samp
+    spd = n // 64
+    k_of_t = np.arange(n) // spd
+    m_of_t = (np.arange(n) % spd) // (p.n_side * p.n_side)
+    psi_step = np.pi * k_of_t / 64.0 + (m_of_t % 8) * (np.pi / 8.0)
+    pix = torch.from_numpy(p.pix).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2024)
+    out = {"n_samp_per_stream": n}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sub = np.arange(0, n + 1, 256, dtype=np.int64)
+    w = np.ones(p.n_intervals)
+    for model, psi_a in (("psi_iid", p.psi), ("psi_stepped", psi_step)):
+        psi = torch.from_numpy(psi_a).to(dev)
+        d_a = torch.from_numpy(synth.signal_tod(p.pix, psi_a, p.signal)).to(dev) + \
+            torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+        d_b = torch.from_numpy(synth.signal_tod(p.pix, psi_a + 0.5 * np.pi, p.signal)).to(dev) + \
+            torch.randn(n, dtype=torch.float64, device=dev, generator=gen)
+        res = {}
+        if model == "psi_iid":
+            for _ in range(3):
+                ctx.pair_sum_diff(d_a, d_b)
+            ev[0].record(ctx.stream)
+            for _ in range(20):
+                ctx.pair_sum_diff(d_a, d_b)
+            ev[1].record(ctx.stream)
+            ev[1].synchronize()
+            out["sum_diff_ms"] = ev[0].elapsed_time(ev[1]) / 20
+        dp, dm = ctx.pair_sum_diff(d_a, d_b)
+        del d_a, d_b
+        for stokes, order in orders:
+            if stokes == "I" and model != "psi_iid":
+                continue  # the intensity system does not see the angles
+            d = dp if stokes == "I" else dm
+            (lp, t_pt) = _wall(lambda: ctx.pointing(pix, None if stokes == "I" else psi,
+                                                    p.n_pix_total, p.min_hits, stokes=stokes))
+            lp.set_grid(p.n_side)
+            lf = ctx.polyfilter(lp, p.interval_start, w, sub, order)
+            x = torch.randn(lp.n, dtype=torch.float64, device=dev, generator=gen)
+            for _ in range(3):
+                ctx.apply_A(lp, lf, x)
+            ev[0].record(ctx.stream)
+            for _ in range(20):
+                ctx.apply_A(lp, lf, x)
+            ev[1].record(ctx.stream)
+            ev[1].synchronize()
+            r = {"order": order, "n": lp.n, "pointing_build_s": t_pt,
+                 "A_apply_ms": ev[0].elapsed_time(ev[1]) / 20}
+            b = ctx.rhs(lp, lf, d)
+            Mbd = ctx.mbd(lp, lf)
+            (M2, t_m2l) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=32, eps_arn=1e-8,
+                                                       m_max=256))
+            r["m2l_setup_s"] = t_m2l
+            for name, M in (("mbd", Mbd), ("m2l", M2)):
+                ((xs, info), t) = _wall(lambda: ctx.solve(lp, lf, M, b, tol=1e-8, max_iter=3000,
+                                                          check_every=4, history=False))
+                r[name] = {"iters": info["iters"], "converged": info["converged"],
+                           "rel_res_true": info["rel_res_true"], "solve_s": t}
+            res[stokes] = r
+            del lp, lf, b, Mbd, M2
+        out[model] = res
+    return {"form": "p1", "workload": "64 detector pairs on the config-2 scan (2 x 6.7e7 "
+            "samples), white noise, sum/difference streams: I from d+ (Legendre order <= 2 "
+            "removed per 256-sample subscan), QU from d- (order <= 1), M_BD vs M_2l (k = 32), "
+            "tol 1e-8; angles iid per sample, or fixed per pair with a stepped half-wave plate",
+            **out}
 
 
 def transfer_Z(Z, obs_from, obs_to):
