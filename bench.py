@@ -57,26 +57,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+# Files whose text determines each measured kernel group's device code: the
+# source that defines it, the device-code headers it includes and the build
+# flags.  Host-side declarations (the internal structures, the C API header)
+# are left out: they do not change a kernel's code.
+KERNEL_SOURCES = {
+    "P": ["tod_ops.hip", "pol_weights.h", "xcd.h"],
+    "PT": ["tod_ops.hip", "pol_weights.h", "xcd.h"],
+    "Ninv_fft": ["noise_fft_big.hip", "fft_common.h"],
+    "Ninv_band": ["tod_ops.hip"],
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1801_08937_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1801_08937_amd", "csrc", f), "rb") as fh:
+    pkg = os.path.join(ROOT, "paper_1801_08937_amd")
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(pkg, "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(pkg, "build.py"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources."""
+    taken on the kernel's current sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_hash") != kernel_source_hash():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    if k is None or k.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(p, n_det_sample: int):
