@@ -633,14 +633,20 @@ class SolveInfo:
     history: np.ndarray
     breakdown: bool = False
     converged: bool = False
+    rel_res_precond: float = float("nan")   # ||M (b - A x)|| / ||M b|| at exit
 
 
-def pcg(apply_A_fn, apply_M_fn, b, tol: float, max_iter: int, x0=None):
+def pcg(apply_A_fn, apply_M_fn, b, tol: float, max_iter: int, x0=None, flexible: bool = False):
     """Textbook preconditioned conjugate gradients:
         r = b - A x; z = M r; p = z; rho = r.z
         repeat: q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q;
                 z = M r; rho' = r.z; beta = rho'/rho; p = z + beta p
-    until ||r|| / ||b|| <= tol or max_iter iterations."""
+    until ||r|| / ||b|| <= tol or max_iter iterations.  flexible: the
+    Polak-Ribiere choice beta = r'.(z' - z)/rho, which tolerates a
+    preconditioner that is not symmetric (M_2l is not, Sect. 3.2); for a
+    symmetric M the two coincide in exact arithmetic (r'.z = 0).
+    At exit the residual is also reported in the preconditioned norm of
+    Eq. residuals read literally, ||M (b - A x)|| / ||M b||."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - apply_A_fn(x)
@@ -662,13 +668,16 @@ def pcg(apply_A_fn, apply_M_fn, b, tol: float, max_iter: int, x0=None):
         alpha = rho / pq
         x = x + alpha * p
         r = r - alpha * q
+        rz_old = float(r @ z) if flexible else 0.0
         z = apply_M_fn(r)
         rho_new = float(r @ z)
-        beta = rho_new / rho
+        beta = (rho_new - rz_old) / rho if flexible else rho_new / rho
         p = z + beta * p
         rho = rho_new
         k += 1
         hist.append(float(np.linalg.norm(r)) / bnorm)
-    true_res = float(np.linalg.norm(b - apply_A_fn(x))) / bnorm
+    r_true = b - apply_A_fn(x)
+    true_res = float(np.linalg.norm(r_true)) / bnorm
+    prec_res = float(np.linalg.norm(apply_M_fn(r_true))) / float(np.linalg.norm(apply_M_fn(b)))
     return x, SolveInfo(k, hist[-1], true_res, np.array(hist), breakdown,
-                        converged=hist[-1] <= tol)
+                        converged=hist[-1] <= tol, rel_res_precond=prec_res)

@@ -441,6 +441,34 @@ def test_pcg_errnorm_bound_each_iteration():
         assert err <= kap * np.linalg.norm(Md @ r) / np.linalg.norm(Md @ b) * (1 + 1e-8)
 
 
+def test_pcg_flexible_beta():
+    """Polak-Ribiere beta = r'.(z' - z)/rho.  With a symmetric M the residuals
+    are M-orthogonal (r'.M r = 0), so the iterates equal the Fletcher-Reeves
+    ones; with the non-symmetric M_2l it still reaches the direct solution.
+    The literal preconditioned residual ||M r||/||M b|| is reported beside
+    the plain one and matches its definition."""
+    p, pt, nz = _setup(14, n_side=3, n_samp=600, n_int=3, half_bw=12)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    A = P.T @ _dense_N_scipy(p) @ P
+    b = O.rhs(pt, nz, p.tod)
+    xd = scipy.linalg.cho_solve(scipy.linalg.cho_factor(A), b)
+    M = O.mbd_build(pt, nz)
+    Md = scipy.linalg.block_diag(*M.inv)
+    for it in (1, 3, 6):
+        x1, i1 = O.pcg(lambda v: A @ v, lambda v: Md @ v, b, 0.0, it)
+        x2, i2 = O.pcg(lambda v: A @ v, lambda v: Md @ v, b, 0.0, it, flexible=True)
+        assert np.linalg.norm(x1 - x2) <= 1e-10 * np.linalg.norm(x1)
+        r = b - A @ x1
+        assert abs(i1.rel_res_precond - np.linalg.norm(Md @ r) / np.linalg.norm(Md @ b)) \
+            <= 1e-12 * i1.rel_res_precond
+    M2, _, _ = O.defl_build(pt, nz, M, b, 4, 1e-300, 40)
+    Mm = np.stack([O.m2l_apply(M2, e) for e in np.eye(pt.n)], axis=1)
+    assert np.max(np.abs(Mm - Mm.T)) > 1e-6 * np.max(np.abs(Mm)), "M_2l is not symmetric"
+    x3, i3 = O.pcg(lambda v: A @ v, lambda v: O.m2l_apply(M2, v), b, 1e-12, 500, flexible=True)
+    assert i3.converged
+    assert np.linalg.norm(x3 - xd) <= np.linalg.cond(A) * 1e-12 * np.linalg.norm(xd) * 10
+
+
 def test_noiseless_recovery_config1():
     """Signal-only TOD: the solution is the input map (error-norm analogue)."""
     p = synth.config1(noiseless=True)
