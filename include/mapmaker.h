@@ -305,12 +305,17 @@ typedef struct {
     double rel_res_recursive;  /* ||r_k|| / ||b|| from the recursion */
     double rel_res_true;       /* ||b - A x_k|| / ||b|| recomputed at exit */
     double solve_seconds;      /* wall time of the solve (all columns) */
+    double rel_res_precond;    /* ||M (b - A x_k)|| / ||M b|| at exit: Eq. residuals
+                                  read literally (= rel_res_true when M is NULL) */
 } mm_solve_info;
 
 /* PCG flags */
 #define MM_SOLVE_CHECK_EVERY(c) ((c) & 0xff)  /* host convergence poll period (0 = 1) */
 #define MM_SOLVE_GRAPH (1u << 8) /* replay each poll period's iterations as one captured HIP graph */
 #define MM_SOLVE_BLOCK (1u << 9) /* block PCG over the nrhs columns (O'Leary), nrhs >= 2 */
+#define MM_SOLVE_FLEXIBLE (1u << 10) /* beta = r'.(z' - z) / rho (Polak-Ribiere), for a
+                                        preconditioner that is not symmetric, such as
+                                        M_2l; not with MM_SOLVE_BLOCK */
 
 /* Preconditioned conjugate gradients (Eq. pcg), column-independent for
  * nrhs > 1 (with MM_SOLVE_BLOCK: block PCG, O'Leary 1980, whose search space

@@ -142,6 +142,32 @@ void precond_apply_impl(mm_ctx *ctx, const mm_precond *M, int nrhs, const double
         m2l_apply_dev(ctx, M, nrhs, v, out, partial, n_part);
 }
 
+// ||M r|| / ||M b|| per column (the residual of Eq. residuals read
+// literally), into host out[R]; with M NULL, ||r|| / ||b||.  tmp: n R doubles.
+void precond_rel_res(mm_ctx *ctx, const mm_precond *M, int64_t n, int R, const double *r,
+                     const double *b, double *tmp, std::vector<double> &out) {
+    DBuf d;
+    d.alloc(sizeof(double) * 2 * R);
+    const double *vr = r, *vb = b;
+    if (M) {
+        precond_apply_impl(ctx, M, R, r, tmp, nullptr, 0);
+        vr = tmp;
+    }
+    dot_cols(ctx, n, R, vr, vr, d.as<double>());
+    if (M) {
+        precond_apply_impl(ctx, M, R, b, tmp, nullptr, 0);
+        vb = tmp;
+    }
+    dot_cols(ctx, n, R, vb, vb, d.as<double>() + R);
+    std::vector<double> h(2 * R);
+    MM_HIP(hipMemcpyAsync(h.data(), d.ptr, sizeof(double) * 2 * R, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    out.resize(R);
+    for (int c = 0; c < R; ++c)
+        out[c] = h[R + c] > 0 ? std::sqrt(std::max(h[c], 0.0) / h[R + c]) : 0.0;
+}
+
 // M_2l from Z (device, column-major n x k): AZ, E = Z^T AZ, Cholesky on device.
 void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M) {
     const int64_t n = p->n();
@@ -169,6 +195,7 @@ struct PcgWork {
     int n_part = 1;
     DBuf r, z, pv, q, part, sc;
     PcgDev sd{};
+    bool flexible = false;  // Polak-Ribiere beta (sd.rzo holds r'.z_old)
     void alloc(int64_t n_, int R_) {
         n = n_;
         R = R_;
@@ -179,11 +206,12 @@ struct PcgWork {
         pv.alloc(vb);
         q.alloc(vb);
         part.alloc(sizeof(double) * n_part * R);
-        sc.alloc(sizeof(double) * 7 * 64 + sizeof(int) * 3 * 64);
+        sc.alloc(sizeof(double) * 8 * 64 + sizeof(int) * 3 * 64);
         double *sb = sc.as<double>();
         sd.rho = sb; sd.pq = sb + 64; sd.alpha = sb + 128; sd.beta = sb + 192;
         sd.rn2 = sb + 256; sd.bn2 = sb + 320; sd.tol2 = sb + 384;
-        int *ib = reinterpret_cast<int *>(sb + 448);
+        sd.rzo = flexible ? sb + 448 : nullptr;
+        int *ib = reinterpret_cast<int *>(sb + 512);
         sd.done = ib; sd.brk = ib + 64; sd.iters = ib + 128;
         sd.hist = nullptr;
         sd.hist_len = 0;
@@ -235,6 +263,11 @@ void pcg_iteration(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const 
     pcg_update_xr(ctx, w.n, R, w.sd, w.pv.as<double>(), w.q.as<double>(), x, w.r.as<double>(),
                   w.part.as<double>(), w.n_part);
     pcg_after_rn(ctx, R, w.sd, w.part.as<double>(), w.n_part, 1);
+    if (w.flexible) {  // r'.z_old before z is overwritten
+        dot_partial_cols(ctx, w.n, R, w.r.as<double>(), w.z.as<double>(), w.part.as<double>(),
+                         w.n_part);
+        pcg_store_rzo(ctx, R, w.sd, w.part.as<double>(), w.n_part);
+    }
     pcg_apply_M(ctx, M, w, w.r.as<double>(), w.z.as<double>());
     pcg_after_rz(ctx, R, w.sd, w.part.as<double>(), w.n_part, 0);
     pcg_update_p(ctx, w.n, R, w.sd, w.z.as<double>(), w.pv.as<double>());
@@ -1010,6 +1043,8 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     MM_CHECK(b && x && b != x, MM_E_INVALID, "solve: bad b/x");
     MM_CHECK(tol >= 0 && max_iter >= 0, MM_E_INVALID, "solve: bad tol/max_iter");
     MM_CHECK(!M || (M->n_obs == p->n_obs && M->nc == p->nc), MM_E_INVALID, "solve: preconditioner of another pointing");
+    MM_CHECK(!((flags & MM_SOLVE_BLOCK) && (flags & MM_SOLVE_FLEXIBLE)), MM_E_INVALID,
+             "solve: the flexible beta is for independent columns, not block CG");
     if (flags & MM_SOLVE_BLOCK) {
         MM_CHECK(nrhs >= 2, MM_E_INVALID, "solve: block CG needs nrhs >= 2");
         result = block_cg(ctx, p, nz, M, nrhs, b, x, tol, max_iter, std::max(1u, flags & 0xffu),
@@ -1021,6 +1056,7 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     const int64_t n = p->n();
     const int R = nrhs;
     PcgWork w;
+    w.flexible = (flags & MM_SOLVE_FLEXIBLE) != 0;
     w.alloc(n, R);
     DBuf hist;
     hist.alloc(sizeof(double) * (size_t)(max_iter + 1) * R);
@@ -1081,6 +1117,8 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     MM_HIP(hipMemcpyAsync(h_rn2.data(), hist.ptr, sizeof(double) * (size_t)(it + 1) * R,
                           hipMemcpyDeviceToHost, s));
     MM_HIP(hipStreamSynchronize(s));
+    std::vector<double> h_pr;
+    if (info) precond_rel_res(ctx, M, n, R, w.r.as<double>(), b, w.z.as<double>(), h_pr);
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool any_brk = false, all_conv = true;
@@ -1097,6 +1135,7 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
             info[c].rel_res_recursive = std::sqrt(std::max(h_rn[c], 0.0)) / bn;
             info[c].rel_res_true = std::sqrt(std::max(h_tr[c], 0.0)) / bn;
             info[c].solve_seconds = secs;
+            info[c].rel_res_precond = h_pr[c];
         }
         if (history) {
             for (int k2 = 0; k2 <= max_iter; ++k2) {
@@ -1195,6 +1234,8 @@ static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
     std::vector<double> h_tr(R);
     MM_HIP(hipMemcpyAsync(h_tr.data(), rn.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
     MM_HIP(hipStreamSynchronize(s));
+    std::vector<double> h_pr;
+    if (info) precond_rel_res(ctx, M, n, R, Rr.as<double>(), b, Z.as<double>(), h_pr);
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool all = true;
@@ -1211,6 +1252,7 @@ static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
             info[c].rel_res_recursive = std::sqrt(std::max(h_rn[c], 0.0)) / bnc;
             info[c].rel_res_true = std::sqrt(std::max(h_tr[c], 0.0)) / bnc;
             info[c].solve_seconds = secs;
+            info[c].rel_res_precond = h_pr[c];
         }
         if (history)
             for (int k2 = 0; k2 <= max_iter; ++k2)

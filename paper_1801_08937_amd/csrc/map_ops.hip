@@ -384,8 +384,14 @@ __global__ void k_pcg_rz(const double *__restrict__ partial, int n_part, int R, 
         return;
     }
     if (s.done[r]) return;
-    s.beta[r] = rz / s.rho[r];
+    s.beta[r] = s.rzo ? (rz - s.rzo[r]) / s.rho[r] : rz / s.rho[r];
     s.rho[r] = rz;
+}
+
+__global__ void k_pcg_rzo(const double *__restrict__ partial, int n_part, int R, PcgDev s) {
+    const int r = blockIdx.x;
+    const double v = wave_sum_parts(partial, n_part, R, r);
+    if ((threadIdx.x & 63) == 0) s.rzo[r] = v;
 }
 
 template <int R>
@@ -1050,6 +1056,11 @@ void pcg_after_rn(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_
 
 void pcg_after_rz(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part, int init) {
     k_pcg_rz<<<nrhs, 64, 0, ctx->stream>>>(partial, n_part, nrhs, s, init);
+    MM_HIP(hipGetLastError());
+}
+
+void pcg_store_rzo(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part) {
+    k_pcg_rzo<<<nrhs, 64, 0, ctx->stream>>>(partial, n_part, nrhs, s);
     MM_HIP(hipGetLastError());
 }
 

@@ -286,6 +286,7 @@ struct PcgDev {
     int *done, *brk, *iters;
     double *hist;   // rn2 per iteration, [hist_len][R], or null
     int hist_len;
+    double *rzo;    // flexible beta: r'.z_old per column, or null (beta = rho'/rho)
 };
 void pcg_init_scalars(mm_ctx *ctx, int nrhs, PcgDev s, double tol);
 void axpby_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *b, const double *Ax, double *r);
@@ -295,6 +296,8 @@ void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *p, 
 void pcg_after_rn(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part,
                   int count_iter);
 void pcg_after_rz(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part, int init);
+// s.rzo[r] = sum of the column's partial dot products (flexible beta)
+void pcg_store_rzo(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part);
 void pcg_update_p(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *z, double *p);
 void dot_partial_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *a, const double *b,
                       double *partial, int n_part);

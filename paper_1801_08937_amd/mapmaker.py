@@ -38,7 +38,8 @@ class MapmakerError(RuntimeError):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("breakdown", C.c_int32),
                 ("pad", C.c_int32), ("rel_res_recursive", C.c_double),
-                ("rel_res_true", C.c_double), ("solve_seconds", C.c_double)]
+                ("rel_res_true", C.c_double), ("solve_seconds", C.c_double),
+                ("rel_res_precond", C.c_double)]
 
 
 class RequestInfo(C.Structure):
@@ -361,7 +362,11 @@ class Context:
     # ---------------------------------------------------------------- solve
     def solve(self, p, nz, M, b, x=None, tol: float = 1e-8, max_iter: int = 2000,
               nrhs: int = 1, check_every: int = 1, history: bool = True, graph: bool = False,
-              block: bool = False):
+              block: bool = False, flexible: bool = False):
+        """PCG (Eq. pcg).  block: O'Leary's block PCG over the columns;
+        flexible: Polak-Ribiere beta (for the non-symmetric M_2l).  The info
+        dict carries the plain residual ||b - Ax||/||b|| and the literal
+        preconditioned one ||M (b - Ax)||/||M b||."""
         import torch
         _dev_check(b, torch.float64, p.n * nrhs, "b")
         if x is None:
@@ -369,7 +374,9 @@ class Context:
         hist = np.zeros((nrhs, max_iter + 1)) if history else None
         infos = (SolveInfo * nrhs)()
         st = lib().mm_solve(self.h, p.h, nz.h, M.h if M is not None else None, nrhs, _ptr(b),
-                            _ptr(x), tol, max_iter, (check_every & 0xFF) | (256 if graph else 0) | (512 if block else 0),
+                            _ptr(x), tol, max_iter,
+                            (check_every & 0xFF) | (256 if graph else 0) | (512 if block else 0)
+                            | (1024 if flexible else 0),
                             hist.ctypes.data if hist is not None else None, infos)
         self._check(st, "mm_solve")
         out = []
@@ -379,7 +386,7 @@ class Context:
             out.append(dict(iters=i.iters, converged=bool(i.converged),
                             breakdown=bool(i.breakdown), rel_res_recursive=i.rel_res_recursive,
                             rel_res_true=i.rel_res_true, solve_seconds=i.solve_seconds,
-                            history=h, status=st))
+                            rel_res_precond=i.rel_res_precond, history=h, status=st))
         return x, (out[0] if nrhs == 1 else out)
 
     def autotune(self, p, nz, nrhs: int = 1):
