@@ -36,7 +36,7 @@ __all__ = [
     "apply_A", "apply_A_pixels", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
     "m2l_apply", "arnoldi", "ritz_select", "defl_build", "pcg", "SolveInfo",
     "dense_P", "dense_Ninv", "PolyFilter", "polyfilter_build", "polyfilter_apply",
-    "dense_polyfilter",
+    "dense_polyfilter", "pcg_lanczos", "defl_build_pcg", "LanczosResult",
 ]
 
 
@@ -618,6 +618,67 @@ def defl_build(pt: Pointing, nz: Noise, mbd: Mbd, b_seed, k: int, eps_arn: float
     theta, Y = ritz_select(res.H[:res.m, :res.m], k, eps_lambda)
     V = res.W[:, :res.m] @ Y
     Z = np.linalg.qr(V)[0] if V.shape[1] else V
+    return m2l_from_Z(pt, nz, mbd, Z, method), res, theta
+
+
+@dataclasses.dataclass
+class LanczosResult:
+    V: np.ndarray        # f64[n, m] Lanczos vectors z_j / sqrt(rho_j)
+    T: np.ndarray        # f64[m, m] symmetric tridiagonal
+    m: int
+    alpha: np.ndarray    # CG step lengths alpha_0..alpha_{m-1}
+    beta: np.ndarray     # CG coefficients beta_0..beta_{m-1}
+
+
+def pcg_lanczos(apply_A_fn, apply_M_fn, b, m: int) -> LanczosResult:
+    """m PCG iterations from x_0 = 0 (Eq. pcg), keeping what the Lanczos
+    process on M A hides in them: with z_j = M r_j and rho_j = r_j.z_j, the
+    vectors v_j = z_j / sqrt(rho_j) are orthonormal in the M^-1 inner product
+    (r_i.M r_j = 0 for i != j), and M A V_m = V_m T_m + (last column term),
+    T_m tridiagonal with
+        T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_{j,j+1} = -sqrt(beta_j)/alpha_j.
+    The Ritz pairs of T_m are those of a prior M_BD solve (the reading of
+    "Ritz vectors from a prior solve" that keeps the CG inner product).
+    Stops early if rho reaches 0."""
+    r = np.asarray(b, dtype=np.float64).copy()
+    z = apply_M_fn(r)
+    rho = float(r @ z)
+    p = z.copy()
+    V = [z / np.sqrt(rho)]
+    alpha, beta = [], []
+    for j in range(m):
+        q = apply_A_fn(p)
+        a = rho / float(p @ q)
+        r = r - a * q
+        z = apply_M_fn(r)
+        rho_new = float(r @ z)
+        bt = rho_new / rho
+        alpha.append(a)
+        beta.append(bt)
+        if j + 1 == m or not rho_new > 0:
+            break
+        V.append(z / np.sqrt(rho_new))
+        p = z + bt * p
+        rho = rho_new
+    mm = len(V)
+    T = np.zeros((mm, mm))
+    for j in range(mm):
+        T[j, j] = 1.0 / alpha[j] + (beta[j - 1] / alpha[j - 1] if j > 0 else 0.0)
+        if j + 1 < mm:
+            T[j, j + 1] = T[j + 1, j] = -np.sqrt(beta[j]) / alpha[j]
+    return LanczosResult(np.stack(V, axis=1), T, mm, np.array(alpha), np.array(beta))
+
+
+def defl_build_pcg(pt: Pointing, nz: Noise, mbd: Mbd, b, k: int, m: int,
+                   eps_lambda: float = 0.0, method: str = "direct"):
+    """Deflation space from the Ritz vectors of an M_BD PCG run of m
+    iterations on A x = b (config 2's "Ritz vectors from a prior M_BD
+    solve"): Ritz selection on T_m as for Arnoldi's H_m, V = V_m Y, Z = Q of
+    a QR of V.  Returns (M2l, LanczosResult, theta)."""
+    res = pcg_lanczos(lambda v: apply_A(pt, nz, v, method), lambda v: mbd_apply(mbd, v), b, m)
+    theta, Y = ritz_select(res.T, k, eps_lambda)
+    Vz = res.V @ Y
+    Z = np.linalg.qr(Vz)[0] if Vz.shape[1] else Vz
     return m2l_from_Z(pt, nz, mbd, Z, method), res, theta
 
 

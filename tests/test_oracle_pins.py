@@ -864,3 +864,50 @@ def test_qu_mbd_blocks_and_stokes_validation():
         O.pointing_build(p.pix, None, p.n_pix_total, 3, "QU")
     with pytest.raises(O.OracleError):
         O.pointing_build(p.pix, p.psi, p.n_pix_total, 3, "Q")
+
+
+# ------------------------- Ritz vectors from a prior M_BD solve (PCG-Lanczos)
+
+def test_pcg_lanczos_relation_and_ritz_bounds():
+    """The PCG coefficients define the Lanczos tridiagonal of M A: the
+    vectors z_j / sqrt(rho_j) are M^-1-orthonormal, M A V_m = V_m T_m up to
+    the last column, and the Ritz values lie inside the spectrum of M A and
+    approach its ends as m grows."""
+    p, pt, nz = _setup(15, n_side=3, n_samp=600, n_int=3, half_bw=12)
+    P = _dense_P_test(p.pix, p.psi, pt.cidx)
+    A = P.T @ _dense_N_scipy(p) @ P
+    M = O.mbd_build(pt, nz)
+    Md = scipy.linalg.block_diag(*M.inv)
+    b = O.rhs(pt, nz, p.tod)
+    lam = np.sort(np.linalg.eigvals(Md @ A).real)
+    for m in (4, 8, 12):
+        res = O.pcg_lanczos(lambda v: A @ v, lambda v: Md @ v, b, m)
+        V, T = res.V, res.T
+        if m == 4:  # before CG converges; later the vectors lose orthogonality
+            G = V.T @ np.linalg.solve(Md, V)  # as finite-precision Lanczos does
+            assert np.max(np.abs(G - np.eye(res.m))) <= 1e-10
+        R = Md @ A @ V - V @ T
+        assert np.max(np.abs(R[:, :-1])) <= 1e-9 * np.max(np.abs(Md @ A @ V))
+        th = np.linalg.eigvalsh(T)
+        assert th[0] >= lam[0] * (1 - 1e-9) and th[-1] <= lam[-1] * (1 + 1e-9)
+    res = O.pcg_lanczos(lambda v: A @ v, lambda v: Md @ v, b, 20)
+    th = np.linalg.eigvalsh(res.T)
+    assert abs(th[0] - lam[0]) <= 1e-6 * lam[0] and abs(th[-1] - lam[-1]) <= 1e-6 * lam[-1]
+
+
+def test_defl_build_from_prior_mbd_solve():
+    """Z from the Ritz vectors of an M_BD solve: a valid M_2l (Eq. ident) that
+    cuts the iteration count like the Arnoldi-built one."""
+    p = synth.config1()
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    M = O.mbd_build(pt, nz)
+    b = O.rhs(pt, nz, p.tod)
+    M2, res, theta = O.defl_build_pcg(pt, nz, M, b, 16, 60)
+    assert M2.Z.shape[1] == 16 and res.m == 60
+    MAZ = np.stack([O.m2l_apply(M2, O.apply_A(pt, nz, M2.Z[:, c])) for c in range(16)], 1)
+    assert np.max(np.abs(MAZ - M2.Z)) <= 1e-8
+    A = lambda v: O.apply_A(pt, nz, v)
+    _, i1 = O.pcg(A, lambda v: O.mbd_apply(M, v), b, 1e-8, 1000)
+    _, i2 = O.pcg(A, lambda v: O.m2l_apply(M2, v), b, 1e-8, 1000)
+    assert i1.converged and i2.converged and i2.iters < i1.iters
