@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1", "h1"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -164,7 +164,7 @@ def main():
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
-              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1,
+              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1, "h1": form_h1,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -665,6 +665,41 @@ def form_p1(mm, ctx, orders=(("I", 2), ("QU", 1))):
             "removed per 256-sample subscan), QU from d- (order <= 1), M_BD vs M_2l (k = 32), "
             "tol 1e-8; angles iid per sample, or fixed per pair with a stepped half-wave plate",
             **out}
+
+
+def form_h1(mm, ctx, tols=(1e-8, 1e-10, 1e-12), k=32):
+    """Config 2's "Ritz vectors from a prior M_BD solve" taken literally: the
+    Lanczos tridiagonal of an M_BD PCG solve of the system itself to
+    tolerance tol (mm_defl_build_pcg) against the default Arnoldi build
+    (mm_defl_build, m = 256, CGS2), each followed by an M_2l solve to 1e-8."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    p = synth.config2()
+    lp = ctx.pointing(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.psi).to(dev),
+                      p.n_pix_total, p.min_hits)
+    lp.set_grid(p.n_side)
+    ln = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw)
+    b = ctx.rhs(lp, ln, torch.from_numpy(p.tod).to(dev))
+    Mbd = ctx.mbd(lp, ln)
+    out = {}
+    ((_, i0), t0) = _wall(lambda: ctx.solve(lp, ln, Mbd, b, tol=1e-8, max_iter=3000,
+                                            check_every=4, history=False))
+    out["mbd"] = {"iters": i0["iters"], "solve_s": t0}
+    builds = [("arnoldi_m256", lambda: ctx.defl_build(lp, ln, Mbd, b, k=k, eps_arn=1e-8,
+                                                      m_max=256))]
+    builds += [(f"pcg_tol{t:.0e}", (lambda t=t: ctx.defl_build_pcg(lp, ln, Mbd, b, k=k,
+                                                                    m_max=500, tol=t)))
+               for t in tols]
+    for name, fn in builds:
+        (M2, t_set) = _wall(fn)
+        ((_, info), t) = _wall(lambda: ctx.solve(lp, ln, M2, b, tol=1e-8, max_iter=3000,
+                                                 check_every=4, history=False))
+        out[name] = {"setup_s": t_set, "steps": M2.arnoldi_info.m, "k": M2.arnoldi_info.k,
+                     "iters": info["iters"], "solve_s": t, "rel_res_true": info["rel_res_true"]}
+        del M2
+    return {"form": "h1", "workload": "config 2, M_2l (k = 32) from Arnoldi vs from the "
+            "Lanczos tridiagonal of a prior M_BD PCG solve to tol, then M_2l to 1e-8", **out}
 
 
 def transfer_Z(Z, obs_from, obs_to):

@@ -275,6 +275,27 @@ mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                         const mm_precond *mbd, const double *b_seed, int32_t k,
                         double eps_lambda, double eps_arn, int32_t m_max,
                         double *h_history, mm_arnoldi_info *info, mm_precond **out);
+/* M_2l from the Ritz vectors of a prior M_BD solve: PCG with M_BD on
+ * A x = b from x_0 = 0 (Eq. pcg) until ||r||/||b|| <= tol or m_max
+ * iterations, whose coefficients give the
+ * Lanczos tridiagonal of B = M_BD A, T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+ * T_{j,j+1} = -sqrt(beta_j)/alpha_j, with Lanczos vectors z_j / sqrt(r_j.z_j)
+ * (orthonormal in the M_BD^-1 inner product).  The Ritz selection, V = V_m Y
+ * and the orthonormal Z follow mm_defl_build, except that numerically
+ * dependent Ritz vectors are dropped (finite-precision Lanczos repeats
+ * converged Ritz values), so info->k may be below k; AZ and E as there.  Same
+ * Krylov space as mm_defl_build's Arnoldi from M_BD b, with the CG inner
+ * product and no Gram-Schmidt.
+ *   b [device] f64[n]; theta [host] f64[m_max] Ritz values ascending (or NULL)
+ *   x_out [device] f64[n] or NULL: the prior solve's solution (its iterate
+ *         after the last step), so the first solve and the deflation space
+ *         come from one run
+ *   info [host]: m = Lanczos steps, k, h_last = |T_{m,m+1}|, setup time
+ * Errors: as mm_defl_build; MM_E_BREAKDOWN if p^T A p <= 0. */
+mm_status mm_defl_build_pcg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                            const mm_precond *mbd, const double *b, int32_t k,
+                            double eps_lambda, double tol, int32_t m_max, double *theta,
+                            double *x_out, mm_arnoldi_info *info, mm_precond **out);
 /* M_2l from a caller-supplied deflation matrix (Eq. m2l).
  *   Z [device] f64[k][n] column-major (column c at Z + c*n), 1 <= k <= 64.
  * Errors: MM_E_COARSE_NOT_SPD if Z^T A Z is not (numerically) SPD: a Cholesky

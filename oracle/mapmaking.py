@@ -36,7 +36,7 @@ __all__ = [
     "apply_A", "apply_A_pixels", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
     "m2l_apply", "arnoldi", "ritz_select", "defl_build", "pcg", "SolveInfo",
     "dense_P", "dense_Ninv", "PolyFilter", "polyfilter_build", "polyfilter_apply",
-    "dense_polyfilter", "pcg_lanczos", "defl_build_pcg", "LanczosResult",
+    "dense_polyfilter", "pcg_lanczos", "defl_build_pcg", "LanczosResult", "orth_drop",
 ]
 
 
@@ -630,7 +630,7 @@ class LanczosResult:
     beta: np.ndarray     # CG coefficients beta_0..beta_{m-1}
 
 
-def pcg_lanczos(apply_A_fn, apply_M_fn, b, m: int) -> LanczosResult:
+def pcg_lanczos(apply_A_fn, apply_M_fn, b, m: int, tol: float = 0.0) -> LanczosResult:
     """m PCG iterations from x_0 = 0 (Eq. pcg), keeping what the Lanczos
     process on M A hides in them: with z_j = M r_j and rho_j = r_j.z_j, the
     vectors v_j = z_j / sqrt(rho_j) are orthonormal in the M^-1 inner product
@@ -639,8 +639,10 @@ def pcg_lanczos(apply_A_fn, apply_M_fn, b, m: int) -> LanczosResult:
         T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_{j,j+1} = -sqrt(beta_j)/alpha_j.
     The Ritz pairs of T_m are those of a prior M_BD solve (the reading of
     "Ritz vectors from a prior solve" that keeps the CG inner product).
-    Stops early if rho reaches 0."""
+    Stops after m iterations, when the solve reaches ||r||/||b|| <= tol, or if
+    rho reaches 0."""
     r = np.asarray(b, dtype=np.float64).copy()
+    bnorm = float(np.linalg.norm(r))
     z = apply_M_fn(r)
     rho = float(r @ z)
     p = z.copy()
@@ -655,7 +657,7 @@ def pcg_lanczos(apply_A_fn, apply_M_fn, b, m: int) -> LanczosResult:
         bt = rho_new / rho
         alpha.append(a)
         beta.append(bt)
-        if j + 1 == m or not rho_new > 0:
+        if j + 1 == m or not rho_new > 0 or float(np.linalg.norm(r)) <= tol * bnorm:
             break
         V.append(z / np.sqrt(rho_new))
         p = z + bt * p
@@ -669,16 +671,32 @@ def pcg_lanczos(apply_A_fn, apply_M_fn, b, m: int) -> LanczosResult:
     return LanczosResult(np.stack(V, axis=1), T, mm, np.array(alpha), np.array(beta))
 
 
-def defl_build_pcg(pt: Pointing, nz: Noise, mbd: Mbd, b, k: int, m: int,
+DEPENDENT_REL = 1e-12
+
+
+def orth_drop(V: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of span(V) that leaves out numerically dependent
+    directions: eigenvectors of V^T V whose eigenvalue is below 1e-12 of the
+    largest are dropped (finite-precision Lanczos repeats converged Ritz
+    values, whose vectors then coincide), then Q of a QR."""
+    if V.shape[1] == 0:
+        return V
+    lam, U = np.linalg.eigh(V.T @ V)
+    keep = lam > DEPENDENT_REL * lam[-1]
+    return np.linalg.qr(V @ (U[:, keep] / np.sqrt(lam[keep])))[0]
+
+
+def defl_build_pcg(pt: Pointing, nz: Noise, mbd: Mbd, b, k: int, m: int, tol: float = 0.0,
                    eps_lambda: float = 0.0, method: str = "direct"):
-    """Deflation space from the Ritz vectors of an M_BD PCG run of m
-    iterations on A x = b (config 2's "Ritz vectors from a prior M_BD
-    solve"): Ritz selection on T_m as for Arnoldi's H_m, V = V_m Y, Z = Q of
-    a QR of V.  Returns (M2l, LanczosResult, theta)."""
-    res = pcg_lanczos(lambda v: apply_A(pt, nz, v, method), lambda v: mbd_apply(mbd, v), b, m)
+    """Deflation space from the Ritz vectors of an M_BD PCG run on A x = b of
+    at most m iterations, stopped at ||r||/||b|| <= tol (config 2's "Ritz
+    vectors from a prior M_BD solve"): Ritz selection on T_m as for
+    Arnoldi's H_m, V = V_m Y, Z = an orthonormal basis of span(V) without
+    dependent directions.  Returns (M2l, LanczosResult, theta)."""
+    res = pcg_lanczos(lambda v: apply_A(pt, nz, v, method), lambda v: mbd_apply(mbd, v), b, m,
+                      tol)
     theta, Y = ritz_select(res.T, k, eps_lambda)
-    Vz = res.V @ Y
-    Z = np.linalg.qr(Vz)[0] if Vz.shape[1] else Vz
+    Z = orth_drop(res.V @ Y)
     return m2l_from_Z(pt, nz, mbd, Z, method), res, theta
 
 

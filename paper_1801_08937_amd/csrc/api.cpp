@@ -804,6 +804,180 @@ extern "C" mm_status mm_defl_from_Z(mm_ctx *ctx, const mm_pointing *p, const mm_
     return MM_OK;
 }
 
+// Eigen-decomposition of a small symmetric matrix (cyclic Jacobi rotations):
+// A (n x n, row-major) is destroyed; w = eigenvalues, U column j = vector j.
+static void sym_eig_jacobi(int n, std::vector<double> &A, std::vector<double> &w,
+                           std::vector<double> &U) {
+    U.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double a = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int pq = 0; pq < n * n; ++pq) {
+            const int pi = pq / n, qi = pq % n;
+            if (qi <= pi) continue;
+            const double apq = A[(size_t)pi * n + qi];
+            if (apq == 0.0) continue;
+            const double app = A[(size_t)pi * n + pi], aqq = A[(size_t)qi * n + qi];
+            const double th = 0.5 * (aqq - app) / apq;
+            const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+            const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+            for (int r = 0; r < n; ++r) {  // A <- A J (columns pi, qi)
+                const double x = A[(size_t)r * n + pi], y = A[(size_t)r * n + qi];
+                A[(size_t)r * n + pi] = c * x - sn * y;
+                A[(size_t)r * n + qi] = sn * x + c * y;
+            }
+            for (int r = 0; r < n; ++r) {  // A <- J^T A (rows pi, qi)
+                const double x = A[(size_t)pi * n + r], y = A[(size_t)qi * n + r];
+                A[(size_t)pi * n + r] = c * x - sn * y;
+                A[(size_t)qi * n + r] = sn * x + c * y;
+            }
+            for (int r = 0; r < n; ++r) {  // U <- U J
+                const double x = U[(size_t)r * n + pi], y = U[(size_t)r * n + qi];
+                U[(size_t)r * n + pi] = c * x - sn * y;
+                U[(size_t)r * n + qi] = sn * x + c * y;
+            }
+        }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+// Ritz pairs of the m x m projected matrix Hm (column-major; Arnoldi's
+// Hessenberg H_m or the Lanczos tridiagonal T_m), selection of the k smallest
+// past the null directions (or all with Re theta < eps_lambda), V = W Y and
+// Cholesky-QR twice: M->Z (n x kk, orthonormal) and M->k.  Then AZ, E.
+// With drop_dependent, directions of V that are numerically dependent (an
+// eigenvalue of V^T V below 1e-12 of the largest; finite-precision Lanczos
+// repeats converged Ritz values) are left out before the Cholesky-QR, and kk
+// shrinks accordingly; otherwise a dependent V is an error.
+static void z_from_ritz(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M,
+                        const double *W, int m, std::vector<double> &Hm, int k,
+                        double eps_lambda, double *theta_out, bool drop_dependent = false) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = p->n();
+    std::vector<double> wr(m), wi(m), vr((size_t)m * m), vi((size_t)m * m);
+    hessenberg_eig(m, Hm.data(), wr.data(), wi.data(), vr.data(), vi.data());
+    if (theta_out)
+        for (int i = 0; i < m; ++i) theta_out[i] = wr[i];
+    // Ritz values at the rounding level (|theta| <= 1e-10 max |theta|) are
+    // exact null directions of M_BD A (sky modes a filter leaves
+    // unconstrained): E could not be inverted with them, and a consistent
+    // right-hand side has no component along them.  They stay out of Z.
+    double tmax = 0;
+    for (int i = 0; i < m; ++i) tmax = std::max(tmax, std::hypot(wr[i], wi[i]));
+    int first = 0;
+    while (first < m && std::hypot(wr[first], wi[first]) <= 1e-10 * tmax) ++first;
+    int keep;
+    if (eps_lambda > 0) {
+        keep = 0;
+        while (keep < m && wr[keep] < eps_lambda) ++keep;
+    } else {
+        keep = std::min(first + k, m);
+    }
+    auto pair_at = [&](int i) { return i + 1 < m && wi[i] != 0 && wi[i] == -wi[i + 1] && wr[i] == wr[i + 1]; };
+    if (keep > 0 && keep < m && wi[keep - 1] != 0 && pair_at(keep - 1)) ++keep;
+    std::vector<double> Y;
+    int kk = 0;
+    for (int i = first; i < keep && kk < 64;) {
+        if (pair_at(i)) {
+            if (kk + 2 > 64) break;
+            Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);
+            Y.insert(Y.end(), vi.begin() + (size_t)i * m, vi.begin() + (size_t)(i + 1) * m);
+            kk += 2;
+            i += 2;
+        } else {
+            Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);
+            kk += 1;
+            i += 1;
+        }
+    }
+    MM_CHECK(kk >= 1, MM_E_INVALID, "defl: no Ritz vector selected");
+    // V = W_m Y, then Cholesky-QR applied twice for an orthonormal Z
+    DBuf Yd, V, G;
+    Yd.alloc(sizeof(double) * Y.size());
+    MM_HIP(hipMemcpyAsync(Yd.ptr, Y.data(), sizeof(double) * Y.size(), hipMemcpyHostToDevice, s));
+    V.alloc(sizeof(double) * n * kk);
+    M->Z.alloc(sizeof(double) * n * kk);
+    matmul_small_right(ctx, n, m, kk, W, Yd.as<double>(), V.as<double>());
+    G.alloc(sizeof(double) * kk * kk);
+    if (drop_dependent) {
+        // V <- V U_keep Lambda_keep^-1/2 (orthonormal up to rounding), into Z then back
+        gram_mfma(ctx, n, kk, kk, V.as<double>(), 1, n, V.as<double>(), 1, n, G.as<double>());
+        std::vector<double> g0((size_t)kk * kk), lam, U;
+        MM_HIP(hipMemcpyAsync(g0.data(), G.ptr, sizeof(double) * kk * kk, hipMemcpyDeviceToHost, s));
+        MM_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < kk; ++i)
+            for (int j = 0; j < i; ++j)
+                g0[(size_t)i * kk + j] = g0[(size_t)j * kk + i] =
+                    0.5 * (g0[(size_t)i * kk + j] + g0[(size_t)j * kk + i]);
+        sym_eig_jacobi(kk, g0, lam, U);
+        double lmax = 0;
+        for (double l : lam) lmax = std::max(lmax, l);
+        std::vector<double> S;  // column-major kk x kk2
+        int kk2 = 0;
+        for (int j = 0; j < kk; ++j) {
+            if (!(lam[j] > 1e-12 * lmax)) continue;
+            const double sc = 1.0 / std::sqrt(lam[j]);
+            for (int i = 0; i < kk; ++i) S.push_back(U[(size_t)i * kk + j] * sc);
+            ++kk2;
+        }
+        MM_CHECK(kk2 >= 1, MM_E_COARSE_NOT_SPD, "defl: no independent Ritz vector");
+        DBuf Sd;
+        Sd.alloc(sizeof(double) * S.size());
+        MM_HIP(hipMemcpyAsync(Sd.ptr, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, s));
+        matmul_small_right(ctx, n, kk, kk2, V.as<double>(), Sd.as<double>(), M->Z.as<double>());
+        MM_HIP(hipMemcpyAsync(V.ptr, M->Z.ptr, sizeof(double) * n * kk2, hipMemcpyDeviceToDevice, s));
+        MM_HIP(hipStreamSynchronize(s));
+        kk = kk2;
+    }
+    std::vector<double> g((size_t)kk * kk), rinv((size_t)kk * kk);
+    for (int pass = 0; pass < 2; ++pass) {
+        double *src = pass == 0 ? V.as<double>() : M->Z.as<double>();
+        double *dst = pass == 0 ? M->Z.as<double>() : V.as<double>();
+        gram_mfma(ctx, n, kk, kk, src, 1, n, src, 1, n, G.as<double>());
+        MM_HIP(hipMemcpyAsync(g.data(), G.ptr, sizeof(double) * kk * kk, hipMemcpyDeviceToHost, s));
+        MM_HIP(hipStreamSynchronize(s));
+        // upper Cholesky factor R (G = R^T R), then R^-1 (column-major for the kernel)
+        std::vector<double> R((size_t)kk * kk, 0.0);
+        for (int c = 0; c < kk; ++c) {
+            for (int r2 = 0; r2 <= c; ++r2) {
+                double sum = 0.5 * (g[(size_t)r2 * kk + c] + g[(size_t)c * kk + r2]);
+                for (int q = 0; q < r2; ++q) sum -= R[(size_t)q * kk + r2] * R[(size_t)q * kk + c];
+                if (r2 == c) {
+                    MM_CHECK(sum > 0, MM_E_COARSE_NOT_SPD, "defl: Ritz vectors linearly dependent");
+                    R[(size_t)c * kk + c] = std::sqrt(sum);
+                } else {
+                    R[(size_t)r2 * kk + c] = sum / R[(size_t)r2 * kk + r2];
+                }
+            }
+        }
+        std::fill(rinv.begin(), rinv.end(), 0.0);
+        for (int c = 0; c < kk; ++c) {  // solve R x = e_c
+            std::vector<double> x(kk, 0.0);
+            for (int r2 = c; r2 >= 0; --r2) {
+                double sum = (r2 == c) ? 1.0 : 0.0;
+                for (int q = r2 + 1; q <= c; ++q) sum -= R[(size_t)r2 * kk + q] * x[q];
+                x[r2] = sum / R[(size_t)r2 * kk + r2];
+            }
+            for (int r2 = 0; r2 < kk; ++r2) rinv[(size_t)c * kk + r2] = x[r2];
+        }
+        MM_HIP(hipMemcpyAsync(G.ptr, rinv.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
+        matmul_small_right(ctx, n, kk, kk, src, G.as<double>(), dst);
+        MM_HIP(hipStreamSynchronize(s));
+    }
+    // after two passes the orthonormal basis is in V
+    std::swap(M->Z, V);
+    M->k = kk;
+    finish_m2l(ctx, p, nz, M);
+}
+
 extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                                    const mm_precond *mbd, const double *b_seed, int32_t k,
                                    double eps_lambda, double eps_arn, int32_t m_max,
@@ -880,95 +1054,123 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
         for (int j = 0; j < m; ++j)
             for (int i = 0; i <= m; ++i)
                 M->H[(size_t)j * (m + 1) + i] = H[(size_t)j * (m_max + 1) + i];
-        // Ritz pairs of H_m
-        std::vector<double> Hm((size_t)m * m), wr(m), wi(m), vr((size_t)m * m), vi((size_t)m * m);
+        std::vector<double> Hm((size_t)m * m);
         for (int j = 0; j < m; ++j)
             for (int i = 0; i < m; ++i) Hm[(size_t)j * m + i] = H[(size_t)j * (m_max + 1) + i];
-        hessenberg_eig(m, Hm.data(), wr.data(), wi.data(), vr.data(), vi.data());
-        // Ritz values at the rounding level (|theta| <= 1e-10 max |theta|) are
-        // exact null directions of M_BD A (sky modes a filter leaves
-        // unconstrained): E could not be inverted with them, and a consistent
-        // right-hand side has no component along them.  They stay out of Z.
-        double tmax = 0;
-        for (int i = 0; i < m; ++i) tmax = std::max(tmax, std::hypot(wr[i], wi[i]));
-        int first = 0;
-        while (first < m && std::hypot(wr[first], wi[first]) <= 1e-10 * tmax) ++first;
-        int keep;
-        if (eps_lambda > 0) {
-            keep = 0;
-            while (keep < m && wr[keep] < eps_lambda) ++keep;
-        } else {
-            keep = std::min(first + k, m);
-        }
-        auto pair_at = [&](int i) { return i + 1 < m && wi[i] != 0 && wi[i] == -wi[i + 1] && wr[i] == wr[i + 1]; };
-        if (keep > 0 && keep < m && wi[keep - 1] != 0 && pair_at(keep - 1)) ++keep;
-        std::vector<double> Y;
-        int kk = 0;
-        for (int i = first; i < keep && kk < 64;) {
-            if (pair_at(i)) {
-                if (kk + 2 > 64) break;
-                Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);
-                Y.insert(Y.end(), vi.begin() + (size_t)i * m, vi.begin() + (size_t)(i + 1) * m);
-                kk += 2;
-                i += 2;
-            } else {
-                Y.insert(Y.end(), vr.begin() + (size_t)i * m, vr.begin() + (size_t)(i + 1) * m);
-                kk += 1;
-                i += 1;
-            }
-        }
-        MM_CHECK(kk >= 1, MM_E_INVALID, "defl: no Ritz vector selected");
-        // V = W_m Y, then Cholesky-QR applied twice for an orthonormal Z
-        DBuf Yd, V, G;
-        Yd.alloc(sizeof(double) * Y.size());
-        MM_HIP(hipMemcpyAsync(Yd.ptr, Y.data(), sizeof(double) * Y.size(), hipMemcpyHostToDevice, s));
-        V.alloc(sizeof(double) * n * kk);
-        M->Z.alloc(sizeof(double) * n * kk);
-        matmul_small_right(ctx, n, m, kk, W, Yd.as<double>(), V.as<double>());
-        G.alloc(sizeof(double) * kk * kk);
-        std::vector<double> g((size_t)kk * kk), rinv((size_t)kk * kk);
-        for (int pass = 0; pass < 2; ++pass) {
-            double *src = pass == 0 ? V.as<double>() : M->Z.as<double>();
-            double *dst = pass == 0 ? M->Z.as<double>() : V.as<double>();
-            gram_mfma(ctx, n, kk, kk, src, 1, n, src, 1, n, G.as<double>());
-            MM_HIP(hipMemcpyAsync(g.data(), G.ptr, sizeof(double) * kk * kk, hipMemcpyDeviceToHost, s));
-            MM_HIP(hipStreamSynchronize(s));
-            // upper Cholesky factor R (G = R^T R), then R^-1 (column-major for the kernel)
-            std::vector<double> R((size_t)kk * kk, 0.0);
-            for (int c = 0; c < kk; ++c) {
-                for (int r2 = 0; r2 <= c; ++r2) {
-                    double sum = 0.5 * (g[(size_t)r2 * kk + c] + g[(size_t)c * kk + r2]);
-                    for (int q = 0; q < r2; ++q) sum -= R[(size_t)q * kk + r2] * R[(size_t)q * kk + c];
-                    if (r2 == c) {
-                        MM_CHECK(sum > 0, MM_E_COARSE_NOT_SPD, "defl: Ritz vectors linearly dependent");
-                        R[(size_t)c * kk + c] = std::sqrt(sum);
-                    } else {
-                        R[(size_t)r2 * kk + c] = sum / R[(size_t)r2 * kk + r2];
-                    }
-                }
-            }
-            std::fill(rinv.begin(), rinv.end(), 0.0);
-            for (int c = 0; c < kk; ++c) {  // solve R x = e_c
-                std::vector<double> x(kk, 0.0);
-                for (int r2 = c; r2 >= 0; --r2) {
-                    double sum = (r2 == c) ? 1.0 : 0.0;
-                    for (int q = r2 + 1; q <= c; ++q) sum -= R[(size_t)r2 * kk + q] * x[q];
-                    x[r2] = sum / R[(size_t)r2 * kk + r2];
-                }
-                for (int r2 = 0; r2 < kk; ++r2) rinv[(size_t)c * kk + r2] = x[r2];
-            }
-            MM_HIP(hipMemcpyAsync(G.ptr, rinv.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
-            matmul_small_right(ctx, n, kk, kk, src, G.as<double>(), dst);
-            MM_HIP(hipStreamSynchronize(s));
-        }
-        // after two passes the orthonormal basis is in V
-        std::swap(M->Z, V);
-        M->k = kk;
-        finish_m2l(ctx, p, nz, M);
+        z_from_ritz(ctx, p, nz, M, W, m, Hm, k, eps_lambda, nullptr);
+        const int kk = M->k;
         if (info) {
             info->m = m;
             info->k = kk;
             info->h_last = h_last;
+            info->setup_seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        }
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    *out = M;
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_defl_build_pcg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                       const mm_precond *mbd, const double *b, int32_t k,
+                                       double eps_lambda, double tol, int32_t m_max,
+                                       double *theta, double *x_out, mm_arnoldi_info *info,
+                                       mm_precond **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    auto t_start = std::chrono::steady_clock::now();
+    check_pair(p, nz);
+    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs && mbd->nc == p->nc, MM_E_INVALID,
+             "defl: needs an M_BD handle of the same pointing");
+    MM_CHECK(b, MM_E_INVALID, "defl: null b");
+    const int64_t n = p->n();
+    MM_CHECK(m_max >= 1 && m_max <= 500 && m_max <= n, MM_E_INVALID,
+             "defl: m_max in [1, min(500, n)]");
+    MM_CHECK(eps_lambda > 0 || (k >= 1 && k <= 63 && k <= m_max), MM_E_INVALID,
+             "defl: k in [1, 63] and <= m_max");
+    hipStream_t s = ctx->stream;
+    auto *M = new mm_precond();
+    try {
+        M->kind = 1;
+        M->n_obs = p->n_obs;
+        M->nc = p->nc;
+        M->rcond_min = mbd->rcond_min;
+        M->inv.alloc(sizeof(double) * packed_sym(p->nc) * p->n_obs);
+        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * packed_sym(p->nc) * p->n_obs,
+                              hipMemcpyDeviceToDevice, s));
+        M->W.alloc(sizeof(double) * n * (m_max + 1));
+        double *W = M->W.as<double>();
+        // PCG with M_BD from x_0 = 0 (tol 0: it runs m_max iterations unless
+        // the residual vanishes), keeping v_j = z_j / sqrt(rho_j) and the
+        // coefficients alpha_j, beta_j
+        PcgWork w;
+        w.alloc(n, 1);
+        DBuf xd, sq;
+        xd.alloc(sizeof(double) * n);
+        sq.alloc(sizeof(double));
+        MM_HIP(hipMemsetAsync(xd.ptr, 0, sizeof(double) * n, s));
+        pcg_init_scalars(ctx, 1, w.sd, 0.0);
+        dot_cols(ctx, n, 1, b, b, w.sd.bn2);
+        MM_HIP(hipMemcpyAsync(w.r.ptr, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        pcg_apply_M(ctx, mbd, w, w.r.as<double>(), w.z.as<double>());
+        pcg_after_rz(ctx, 1, w.sd, w.part.as<double>(), w.n_part, 1);
+        MM_HIP(hipMemcpyAsync(w.pv.ptr, w.z.ptr, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        double *hp = pinned(ctx, sizeof(double) * 8);
+        auto read_scalars = [&]() {  // rho, alpha, beta, breakdown flag, ||r||^2, ||b||^2
+            MM_HIP(hipMemcpyAsync(hp, w.sd.rho, sizeof(double), hipMemcpyDeviceToHost, s));
+            MM_HIP(hipMemcpyAsync(hp + 1, w.sd.alpha, sizeof(double), hipMemcpyDeviceToHost, s));
+            MM_HIP(hipMemcpyAsync(hp + 2, w.sd.beta, sizeof(double), hipMemcpyDeviceToHost, s));
+            MM_HIP(hipMemcpyAsync(reinterpret_cast<int *>(hp + 3), w.sd.brk, sizeof(int),
+                                  hipMemcpyDeviceToHost, s));
+            MM_HIP(hipMemcpyAsync(hp + 5, w.sd.rn2, sizeof(double), hipMemcpyDeviceToHost, s));
+            MM_HIP(hipMemcpyAsync(hp + 6, w.sd.bn2, sizeof(double), hipMemcpyDeviceToHost, s));
+            MM_HIP(hipStreamSynchronize(s));
+        };
+        auto save_v = [&](int j, double rho) {
+            hp[4] = std::sqrt(rho);
+            MM_HIP(hipMemcpyAsync(sq.ptr, hp + 4, sizeof(double), hipMemcpyHostToDevice, s));
+            scale_copy(ctx, n, w.z.as<double>(), sq.as<double>(), W + (int64_t)j * n, 1);
+            MM_HIP(hipStreamSynchronize(s));
+        };
+        read_scalars();
+        MM_CHECK(hp[0] > 0 && std::isfinite(hp[0]), MM_E_INVALID, "defl: zero start vector");
+        save_v(0, hp[0]);
+        std::vector<double> alpha, beta;
+        int m = 1;
+        for (int j = 0; j < m_max; ++j) {
+            pcg_iteration(ctx, p, nz, mbd, w, xd.as<double>());
+            read_scalars();
+            MM_CHECK(!*reinterpret_cast<int *>(hp + 3), MM_E_BREAKDOWN, "defl: PCG breakdown");
+            alpha.push_back(hp[1]);
+            beta.push_back(hp[2]);
+            if (j + 1 == m_max || !(hp[0] > 0) || hp[5] <= tol * tol * hp[6]) break;
+            save_v(j + 1, hp[0]);
+            m = j + 2;
+        }
+        // T_m: T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = -sqrt(beta_j)/alpha_j
+        std::vector<double> T((size_t)m * m, 0.0);
+        for (int j = 0; j < m; ++j) {
+            T[(size_t)j * m + j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+            if (j + 1 < m)
+                T[(size_t)j * m + j + 1] = T[(size_t)(j + 1) * m + j] =
+                    -std::sqrt(beta[j]) / alpha[j];
+        }
+        if (x_out)
+            MM_HIP(hipMemcpyAsync(x_out, xd.ptr, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        M->arn_m = m;
+        M->H.assign((size_t)(m + 1) * m, 0.0);
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) M->H[(size_t)j * (m + 1) + i] = T[(size_t)j * m + i];
+        z_from_ritz(ctx, p, nz, M, W, m, T, k, eps_lambda, theta, true);
+        if (info) {
+            info->m = m;
+            info->k = M->k;
+            info->h_last = std::sqrt(beta[m - 1]) / alpha[m - 1];
             info->setup_seconds =
                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         }

@@ -94,6 +94,7 @@ def lib() -> C.CDLL:
             "mm_mbd_build": (C.c_int, [P, P, P, PP]),
             "mm_mbd_rcond": (C.c_int, [P, C.POINTER(D)]),
             "mm_defl_build": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, PP]),
+            "mm_defl_build_pcg": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, P, PP]),
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
             "mm_defl_export": (C.c_int, [P, P, C.POINTER(I32), P, P, P]),
             "mm_defl_arnoldi_export": (C.c_int, [P, P, C.POINTER(I32), P, P]),
@@ -348,6 +349,28 @@ class Context:
         M = Precond(self, h, p.n, 1)
         M.arnoldi_info = info
         M.h_history = hist[: info.m].copy()
+        return M
+
+    def defl_build_pcg(self, p, nz, mbd, b, k: int = 32, m_max: int = 256, tol: float = 0.0,
+                       eps_lambda: float = 0.0, x_out=None):
+        """M_2l from the Ritz vectors of a prior M_BD PCG run on A x = b (at
+        most m_max iterations, stopped at ||r||/||b|| <= tol; Lanczos
+        tridiagonal from the CG coefficients).  The returned handle carries
+        .theta (Ritz values) and .arnoldi_info."""
+        import torch
+        _dev_check(b, torch.float64, p.n, "b")
+        theta = np.zeros(m_max)
+        info = ArnoldiInfo()
+        h = C.c_void_p()
+        if x_out is not None:
+            _dev_check(x_out, torch.float64, p.n, "x_out")
+        self._check(lib().mm_defl_build_pcg(self.h, p.h, nz.h, mbd.h, _ptr(b), k, eps_lambda,
+                                            tol, m_max, theta.ctypes.data,
+                                            None if x_out is None else _ptr(x_out), C.byref(info),
+                                            C.byref(h)), "mm_defl_build_pcg")
+        M = Precond(self, h, p.n, 1)
+        M.arnoldi_info = info
+        M.theta = theta[: info.m].copy()
         return M
 
     def precond_apply(self, M, v, out=None, nrhs: int = 1):

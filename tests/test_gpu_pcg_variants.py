@@ -88,3 +88,54 @@ def test_literal_preconditioned_residual(ctx, c1):
         r = B[:, c] - O.apply_A(op, on, Xh[:, c])
         ref = np.linalg.norm(O.mbd_apply(OM, r)) / np.linalg.norm(O.mbd_apply(OM, B[:, c]))
         assert abs(infos[c]["rel_res_precond"] - ref) <= 1e-9 * ref
+
+
+def test_defl_from_prior_mbd_solve_parity(ctx, c1):
+    """Ritz pairs harvested from an M_BD PCG run: the Lanczos tridiagonal's
+    eigenvalues match the oracle's, the M_2l built from them satisfies
+    Eq. ident and cuts the iterations."""
+    p, lp, ln, op, on, b = c1
+    M = ctx.mbd(lp, ln)
+    OM = O.mbd_build(op, on)
+    bd = dev(b)
+    # 15 iterations: short of convergence (M_BD needs 18 to 1e-8), so the
+    # Lanczos vectors keep their orthogonality and no Ritz value repeats
+    M2 = ctx.defl_build_pcg(lp, ln, M, bd, k=8, m_max=15)
+    res = O.pcg_lanczos(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), b, 15)
+    th_o = np.linalg.eigvalsh(res.T)
+    assert M2.arnoldi_info.m == res.m == 15 and M2.arnoldi_info.k == 8
+    np.testing.assert_allclose(M2.theta, th_o, rtol=1e-8)
+    OM2, _, _ = O.defl_build_pcg(op, on, OM, b, 8, 15)
+    import scipy.linalg
+    ang = scipy.linalg.subspace_angles(host(M2.export()[0]), OM2.Z)
+    assert np.max(np.sin(ang)) <= 1e-6
+    Z = M2.export()[0]
+    AZ = torch_stack_apply(ctx, lp, ln, Z)
+    MAZ = torch_stack_precond(ctx, M2, AZ)
+    assert rel(host(MAZ), host(Z)) <= 1e-9
+    _, i1 = ctx.solve(lp, ln, M, bd, tol=1e-8, max_iter=500)
+    _, i2 = ctx.solve(lp, ln, M2, bd, tol=1e-8, max_iter=500)
+    assert i1["converged"] and i2["converged"] and i2["iters"] < i1["iters"]
+    # stopped at the prior solve's tolerance: as many steps as that solve,
+    # and running far past convergence still yields a valid M_2l (repeated
+    # Ritz values are dropped, not an error)
+    import torch
+    x3 = torch.empty_like(bd)
+    M3 = ctx.defl_build_pcg(lp, ln, M, bd, k=16, m_max=500, tol=1e-6, x_out=x3)
+    x6, i6 = ctx.solve(lp, ln, M, bd, tol=1e-6, max_iter=500)
+    assert M3.arnoldi_info.m == i6["iters"]
+    np.testing.assert_array_equal(host(x3), host(x6))  # the same solve, the same bits
+    M4 = ctx.defl_build_pcg(lp, ln, M, bd, k=32, m_max=120)
+    assert 1 <= M4.arnoldi_info.k <= 32
+    _, i4 = ctx.solve(lp, ln, M4, bd, tol=1e-8, max_iter=500)
+    assert i4["converged"]
+
+
+def torch_stack_apply(ctx, lp, ln, Z):
+    import torch
+    return torch.stack([ctx.apply_A(lp, ln, Z[:, c].contiguous()) for c in range(Z.shape[1])], 1)
+
+
+def torch_stack_precond(ctx, M, V):
+    import torch
+    return torch.stack([ctx.precond_apply(M, V[:, c].contiguous()) for c in range(V.shape[1])], 1)

@@ -911,3 +911,26 @@ def test_defl_build_from_prior_mbd_solve():
     _, i1 = O.pcg(A, lambda v: O.mbd_apply(M, v), b, 1e-8, 1000)
     _, i2 = O.pcg(A, lambda v: O.m2l_apply(M2, v), b, 1e-8, 1000)
     assert i1.converged and i2.converged and i2.iters < i1.iters
+
+
+def test_orth_drop_removes_dependent_directions():
+    rng = np.random.default_rng(40)
+    A = rng.standard_normal((50, 4))
+    V = np.concatenate([A, A[:, :2] * 3.0 + 1e-15 * rng.standard_normal((50, 2))], axis=1)
+    Q = O.orth_drop(V)
+    assert Q.shape[1] == 4
+    assert np.max(np.abs(Q.T @ Q - np.eye(4))) <= 1e-13
+    # same span as the independent part
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Q, A))) <= 1e-12
+
+
+def test_pcg_lanczos_stops_at_tolerance():
+    p = synth.config1()
+    pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    M = O.mbd_build(pt, nz)
+    b = O.rhs(pt, nz, p.tod)
+    A = lambda v: O.apply_A(pt, nz, v)
+    _, i1 = O.pcg(A, lambda v: O.mbd_apply(M, v), b, 1e-6, 1000)
+    res = O.pcg_lanczos(A, lambda v: O.mbd_apply(M, v), b, 1000, tol=1e-6)
+    assert res.m == i1.iters   # the prior solve's own iteration count
