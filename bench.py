@@ -886,50 +886,57 @@ def form_c5(mm, ctx, n_requests=200, slots=1):
         n_obs.append(lp.n)
         lp.close() if hasattr(lp, "close") else None
         del lp
-    # served
-    srv = mm.Server(0, hbm_budget_bytes=240 << 30, slots=slots, defl_k=32, iters_per_step=4)
-    t0 = time.perf_counter()
-    for s in range(4):
-        p = S[s]["p"]
-        srv.add_strategy(s, S[s]["pix"], S[s]["psi"], p.n_pix_total, p.interval_start,
-                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
-    t_reg = time.perf_counter() - t0
-    xs_srv = {}
+    def serve(prebuild):
+        srv = mm.Server(0, hbm_budget_bytes=240 << 30, slots=slots, defl_k=32, iters_per_step=4,
+                        prebuild=prebuild)
+        t0 = time.perf_counter()
+        for s in range(4):
+            p = S[s]["p"]
+            srv.add_strategy(s, S[s]["pix"], S[s]["psi"], p.n_pix_total, p.interval_start,
+                             p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+        t_reg = time.perf_counter() - t0
+        xs = {}
 
-    def req(i):
-        d = make_tod(i)
-        _sync()
-        x = torch.zeros(n_obs[int(strat[i])], dtype=torch.float64, device=dev)
-        xs_srv[i] = x
-        return int(strat[i]), d, x, float(tol[i])
-    log("[bench] serving trace ...")
-    ready = {"t": None}
+        def req(i):
+            d = make_tod(i)
+            _sync()
+            x = torch.zeros(n_obs[int(strat[i])], dtype=torch.float64, device=dev)
+            xs[i] = x
+            return int(strat[i]), d, x, float(tol[i])
+        log(f"[bench] serving trace (M_2l {'at registration' if prebuild else 'in background'}) ...")
+        ready = {"t": None}
 
-    def on_step(el):
-        if ready["t"] is None and all(srv.strategy_state(s_) in (2, 3) for s_ in range(4)):
-            ready["t"] = el
-    infos, wall = serving.run_trace(srv, arrivals, req, on_step=on_step)
-    served = serving.latency_stats(infos, wall)
-    served["all_m2l_ready_at_s"] = ready["t"]
-    steady = [i for i in range(n_requests) if ready["t"] is not None and arrivals[i] >= ready["t"]]
-    served["iters_mean"] = float(np.mean([d["iters"] for d in infos]))
-    served["register_s"] = t_reg
-    lat_s = np.array([d["latency_seconds"] for d in infos])
-    served["per_strategy_p50_p99_s"] = {
-        int(s_): [float(np.percentile(lat_s[strat == s_], 50)),
-                  float(np.percentile(lat_s[strat == s_], 99))] for s_ in range(4)}
-    if steady:
-        served["steady_state"] = {"n": len(steady),
-                                  "p50_s": float(np.percentile(lat_s[steady], 50)),
-                                  "p99_s": float(np.percentile(lat_s[steady], 99)),
-                                  "mean_s": float(lat_s[steady].mean())}
-    slow = np.argsort(-lat_s)[:5]
-    served["slowest"] = [{"i": int(i), "strategy": int(strat[i]), "tol": float(tol[i]),
-                          "precond": int(infos[i]["precond"]), "iters": int(infos[i]["iters"]),
-                          "queue_s": float(infos[i]["queue_seconds"]),
-                          "latency_s": float(lat_s[i])} for i in slow]
-    log(f"[bench] served: {served}")
-    srv.close()
+        def on_step(el):
+            if ready["t"] is None and all(srv.strategy_state(s_) in (2, 3) for s_ in range(4)):
+                ready["t"] = el
+        infos, wall = serving.run_trace(srv, arrivals, req, on_step=on_step)
+        served = serving.latency_stats(infos, wall)
+        served["all_m2l_ready_at_s"] = ready["t"]
+        steady = [i for i in range(n_requests)
+                  if ready["t"] is not None and arrivals[i] >= ready["t"]]
+        served["iters_mean"] = float(np.mean([d["iters"] for d in infos]))
+        served["register_s"] = t_reg
+        lat_s = np.array([d["latency_seconds"] for d in infos])
+        served["per_strategy_p50_p99_s"] = {
+            int(s_): [float(np.percentile(lat_s[strat == s_], 50)),
+                      float(np.percentile(lat_s[strat == s_], 99))] for s_ in range(4)}
+        if steady:
+            served["steady_state"] = {"n": len(steady),
+                                      "p50_s": float(np.percentile(lat_s[steady], 50)),
+                                      "p99_s": float(np.percentile(lat_s[steady], 99)),
+                                      "mean_s": float(lat_s[steady].mean())}
+        slow = np.argsort(-lat_s)[:5]
+        served["slowest"] = [{"i": int(i), "strategy": int(strat[i]), "tol": float(tol[i]),
+                              "precond": int(infos[i]["precond"]),
+                              "iters": int(infos[i]["iters"]),
+                              "queue_s": float(infos[i]["queue_seconds"]),
+                              "latency_s": float(lat_s[i])} for i in slow]
+        log(f"[bench] served: {served}")
+        srv.close()
+        return served, xs, steady
+
+    served, xs_srv, steady = serve(False)
+    served_pre, _, _ = serve(True)
     # baseline: one at a time, FP64 M_BD, nothing cached
     log("[bench] baseline trace ...")
     lat, iters, diffs = [], [], []
@@ -976,6 +983,7 @@ def form_c5(mm, ctx, n_requests=200, slots=1):
     return {"form": "c5", "workload": "Poisson 4 req/s, 4 strategies: 64^2/16 det x 2^16 "
             "(lambda 1024), 128^2/32 x 2^18 (2048), 256^2/64 x 2^20 (4096), 256^2/128 x 2^20 "
             "(8192); tol 1e-6 or 1e-8; slots %d" % slots, "served": served,
+            "served_m2l_at_registration": served_pre,
             "one_at_a_time_mbd_no_cache": base,
             "served_vs_baseline_map_rel_diff_first8": diffs}
 

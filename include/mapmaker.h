@@ -422,6 +422,13 @@ typedef struct {
  * deflation vectors (0 = M_BD only); iters_per_step: PCG iterations per step. */
 mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots, int32_t defl_k,
                            int32_t iters_per_step, mm_server **out);
+/* on != 0: strategies registered from now on get their M_2l at registration,
+ * built synchronously on the strategy's stream from the Ritz vectors of an
+ * M_BD solve (mm_defl_build_pcg, to 1e-12) of A x = A u with u a fixed
+ * pseudo-random map, so every request of the strategy runs with M_2l;
+ * registration takes that much longer.  Off (the default): M_2l is built in
+ * the background from the first request's right-hand side. */
+mm_status mm_server_set_prebuild(mm_server *srv, int32_t on);
 /* Register a scan strategy; arguments as mm_pointing_build / mm_noise_build
  * (pix, psi [device] are read during the call only; grid_width as
  * mm_pointing_set_grid, 0 = none).  Errors: MM_E_BUSY if its estimated

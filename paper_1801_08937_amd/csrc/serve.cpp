@@ -109,6 +109,10 @@ struct mm_server {
     int32_t chunk = 4;
     int32_t m_max = 256;
     double eps_arn = 1e-8;
+    // build M_2l at registration (synchronously, on the strategy's stream)
+    // from the Ritz vectors of an M_BD solve of A x = A u, u a fixed
+    // pseudo-random map, instead of in the background from the first request
+    bool prebuild = false;
     int64_t next_id = 1;
     std::map<int32_t, std::unique_ptr<Strategy>> strat;
     std::deque<int64_t> queue;
@@ -155,6 +159,12 @@ extern "C" mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int3
     return MM_OK;
 }
 
+extern "C" mm_status mm_server_set_prebuild(mm_server *srv, int32_t on) {
+    if (!srv) return MM_E_INVALID;
+    srv->prebuild = on != 0;
+    return MM_OK;
+}
+
 extern "C" const char *mm_server_last_error(const mm_server *srv) {
     return srv ? srv->last_error.c_str() : "null server";
 }
@@ -197,6 +207,32 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
     check(mm_mbd_build(st->ctx, st->p, st->nz, &st->mbd), st->ctx, "server: M_BD");
     st->n = st->p->n();
     st->b.alloc(sizeof(double) * st->n);
+    if (srv->prebuild && srv->defl_k > 0) {
+        // b = A u for a fixed u with entries uniform in [-1, 1): a consistent
+        // right-hand side whose Krylov space holds every eigenvector of M_BD A
+        std::vector<double> hu((size_t)st->n);
+        uint64_t z = 0x9E3779B97F4A7C15ull ^ (uint64_t)id;
+        for (auto &v : hu) {  // splitmix64
+            z += 0x9E3779B97F4A7C15ull;
+            uint64_t q = z;
+            q = (q ^ (q >> 30)) * 0xBF58476D1CE4E5B9ull;
+            q = (q ^ (q >> 27)) * 0x94D049BB133111EBull;
+            q ^= q >> 31;
+            v = 2.0 * (double)(q >> 11) * 0x1.0p-53 - 1.0;
+        }
+        mm::DBuf u;
+        u.alloc(sizeof(double) * st->n);
+        MM_HIP(hipMemcpyAsync(u.ptr, hu.data(), sizeof(double) * st->n, hipMemcpyHostToDevice,
+                              st->ctx->stream));
+        check(mm_apply_A(st->ctx, st->p, st->nz, 1, u.as<double>(), st->b.as<double>()),
+              st->ctx, "server: prebuild A u");
+        const int k = (int)std::min<int64_t>(srv->defl_k, st->n - 1);
+        const int mmax = (int)std::min<int64_t>(srv->m_max, st->n);
+        check(mm_defl_build_pcg(st->ctx, st->p, st->nz, st->mbd, st->b.as<double>(), k, 0.0,
+                                1e-12, mmax, nullptr, nullptr, nullptr, &st->m2l),
+              st->ctx, "server: prebuild M_2l");
+        st->build = BUILD_READY;
+    }
     for (auto &l : st->lane) l.slot_req.assign(srv->slots, -1);
     st->bytes = bytes;
     srv->used += bytes;

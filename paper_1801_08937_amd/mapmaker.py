@@ -104,6 +104,7 @@ def lib() -> C.CDLL:
             "mm_profile_enable": (C.c_int, [P, C.c_int]),
             "mm_autotune": (C.c_int, [P, P, P, I32, P, C.POINTER(I32)]),
             "mm_server_create": (C.c_int, [C.c_int, I64, I32, I32, I32, PP]),
+            "mm_server_set_prebuild": (C.c_int, [P, I32]),
             "mm_server_add_strategy": (C.c_int, [P, I32, I64, I32, P, P, I32, I32, I32, P, P, I32,
                                                  I32, P, C.c_int]),
             "mm_server_submit": (C.c_int, [P, I32, P, D, I32, P, C.POINTER(I64)]),
@@ -606,13 +607,15 @@ class Server:
     cached M_BD/M_2l, per-strategy streams, column slots admitted mid-flight."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 200 << 30, slots: int = 8,
-                 defl_k: int = 32, iters_per_step: int = 4):
+                 defl_k: int = 32, iters_per_step: int = 4, prebuild: bool = False):
         h = C.c_void_p()
         st = lib().mm_server_create(device, hbm_budget_bytes, slots, defl_k, iters_per_step,
                                     C.byref(h))
         if st != 0:
             raise MapmakerError(st, "mm_server_create failed")
         self.h = h
+        if prebuild:
+            lib().mm_server_set_prebuild(h, 1)
         self.device = device
         self.n = {}
 

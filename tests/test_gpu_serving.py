@@ -133,3 +133,31 @@ def test_server_budget_rejects(mm):
                          p.filter_id, p.band, p.half_bw)
     assert e.value.name == "MM_E_BUSY"
     srv.close()
+
+
+def test_server_prebuilt_m2l(mm):
+    """With M_2l built at registration, every request (the first included)
+    runs with M_2l, a request's map is bitwise the same alone and in a mix,
+    and it solves its own system."""
+    import torch
+    srv = mm.Server(0, hbm_budget_bytes=8 << 30, slots=4, defl_k=8, iters_per_step=3,
+                    prebuild=True)
+    for s in range(2):
+        p = _strategy(s, 0)
+        srv.add_strategy(s, dev(p.pix), dev(p.psi), p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+    assert all(srv.strategy_state(s) == 2 for s in range(2))
+    infos_a, outs_a = _run(srv, [(0, 21, 1e-8)])
+    infos_b, outs_b = _run(srv, [(0, 21, 1e-8), (1, 22, 1e-8), (0, 23, 1e-6)], join_after=2)
+    srv.close()
+    assert all(i["state"] == 2 and i["precond"] == 1 and i["m2l_built"] == 0
+               for i in infos_a + infos_b)
+    assert torch.equal(outs_a[0][0], outs_b[0][0])
+    for (x, tod, p), tol in zip(outs_b, (1e-8, 1e-8, 1e-6)):
+        op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+        on = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+        OM = O.mbd_build(op, on)
+        bo = O.rhs(op, on, p.tod)
+        xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-13,
+                      5000)
+        assert rel(host(x), xo) <= 1e4 * tol
