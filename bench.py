@@ -30,6 +30,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FP64_PEAK_TF = 78.6
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per sample per kernel launch, FP64 (index 4 B, angle 8 B,
 # TOD 8 B; the weights are formed from the angle in the kernels).  P: map-slot
@@ -129,7 +130,7 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1", "h1"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1", "h1", "n1"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -164,7 +165,7 @@ def main():
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
-              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1, "h1": form_h1,
+              "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1, "h1": form_h1, "n1": form_n1,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -720,6 +721,65 @@ def form_h1(mm, ctx, tols=(1e-8, 1e-10, 1e-12), k=32):
         del M2
     return {"form": "h1", "workload": "config 2, M_2l (k = 32) from Arnoldi vs from the "
             "Lanczos tridiagonal of a prior M_BD PCG solve to tol, then M_2l to 1e-8", **out}
+
+
+def form_n1(mm, ctx, lams=(16, 32, 64, 128, 256, 512, 1024, 2048, 4096),
+            sizes=(1 << 20, 1 << 23, 1 << 27), L=1 << 16):
+    """N^-1 method by measured time: the direct band and the overlap-save FFT
+    on a config-2-sized stream (1.34e8 samples in 2^16-sample intervals, one
+    1/f filter) for a range of half bandwidths, each against its own bound:
+    the band against FP64 vector peak (2 (2 lambda + 1) flops per sample),
+    the FFT against HBM (its algorithmic bytes per sample)."""
+    import torch
+    import synth
+    dev = torch.device("cuda", 0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    rows = []
+    for n_samp in sizes:
+        rows += _n1_size(mm, ctx, lams, n_samp, L, dev, ev)
+    return {"form": "n1", "workload": "2^20, 2^23 and 2^27 samples in 2^16-sample intervals, one "
+            "1/f filter; direct band vs overlap-save FFT per half bandwidth", "rows": rows}
+
+
+def _n1_size(mm, ctx, lams, n_samp, L, dev, ev):
+    import torch
+    import synth
+    istart = np.arange(0, n_samp + 1, L, dtype=np.int64)
+    fid = np.zeros(istart.shape[0] - 1, dtype=np.int32)
+    y = torch.randn(n_samp, dtype=torch.float64, device=dev)
+    z = torch.empty_like(y)
+    rows = []
+    for lam in lams:
+        band = synth.band_from_psd(L, lam, 0.5)[None, :]
+        row = {"n_samp": n_samp, "half_bw": lam}
+        for name, method in (("direct", 1), ("fft", 2)):
+            try:
+                ln = ctx.noise(istart, fid, band, lam, method)
+            except mm.MapmakerError:
+                continue
+            reps = 3 if (method == 1 and lam >= 1024) else 20
+            ctx.noise_apply(ln, y, z)
+            ev[0].record(ctx.stream)
+            for _ in range(reps):
+                ctx.noise_apply(ln, y, z)
+            ev[1].record(ctx.stream)
+            ev[1].synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / reps
+            if method == 1:
+                tf = n_samp * 2.0 * (2 * lam + 1) / (ms * 1e-3) / 1e12
+                row[name] = {"ms": ms, "TFLOPs": tf, "frac_fp64_peak": tf / FP64_PEAK_TF}
+            else:
+                bps = fft_bytes_per_sample(istart, lam, ln.fft_valid)
+                gbs = n_samp * bps / (ms * 1e-3) / 1e9
+                row[name] = {"ms": ms, "GBps": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS,
+                             "fft_n": ln.fft_n}
+            ln.close()
+        picked = ctx.noise(istart, fid, band, lam, 0)
+        row["auto_picks"] = {1: "direct", 2: "fft"}[picked.method]
+        picked.close()
+        rows.append(row)
+        log(f"[bench] n1 {row}")
+    return rows
 
 
 def transfer_Z(Z, obs_from, obs_to):

@@ -535,7 +535,11 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
             MM_CHECK(fft_ok, MM_E_INVALID, "FFT noise method unsupported for this bandwidth");
             nz->method = MM_NOISE_FFT;
         } else if (method == MM_NOISE_AUTO) {
-            nz->method = (fft_ok && half_bw >= 256) ? MM_NOISE_FFT : MM_NOISE_DIRECT;
+            // measured crossover (direct band vs overlap-save FFT, 2^20..2^27
+            // samples): the band wins up to lambda = 32, the FFT from 64 on
+            // streams of 2^22 samples and more, from 128 on shorter ones
+            const int cross = nz->n_samp >= ((int64_t)1 << 22) ? 64 : 128;
+            nz->method = (fft_ok && half_bw >= cross) ? MM_NOISE_FFT : MM_NOISE_DIRECT;
         } else {
             nz->method = MM_NOISE_DIRECT;
         }
@@ -560,7 +564,11 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
                                   hipMemcpyHostToDevice, s));
         }
         // direct-band tile table: (first sample, interval) per tile
-        nz->default_tile_len = choose_tile(nz->n_samp, ctx->n_cu);
+        // the single-column direct band uses the register-tiled kernel's fixed
+        // tile when its window fits in LDS (set here, so that applies never
+        // rebuild the table)
+        const int tl1 = band1_tile_len(half_bw, prec);
+        nz->default_tile_len = tl1 > 0 ? tl1 : choose_tile(nz->n_samp, ctx->n_cu);
         set_band_tiles(ctx, nz, nz->default_tile_len);
         if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
     } catch (...) {

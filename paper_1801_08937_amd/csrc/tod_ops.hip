@@ -471,6 +471,66 @@ __global__ void __launch_bounds__(BS) k_sum_diff(int64_t n, const T *a, const T 
     }
 }
 
+// Single-column direct band, register-tiled.  A block owns BT_TL = 2,048
+// consecutive outputs of one interval; their input window [t0 - lambda,
+// t0 + BT_TL + lambda) (zero outside the interval) and the taps laid out as a
+// full symmetric filter f[d + lambda] = c_|d| sit in LDS.  Thread i keeps
+// outputs i*BT_OPT .. i*BT_OPT + 7 in registers and walks the taps in blocks
+// of BT_OPT: per block it loads 15 inputs and 8 taps and does 64 FMAs from
+// registers.  Every output sums its taps in ascending offset, as k_band
+// does; the zero-padded terms add exactly +0, so the two give the same bits.
+constexpr int BT_OPT = 8;
+constexpr int BT_TL = BS * BT_OPT;
+
+template <typename T>
+__global__ void __launch_bounds__(BS) k_band1(const int64_t *__restrict__ tiles,
+                                              const int64_t *__restrict__ istart,
+                                              const int32_t *__restrict__ fid,
+                                              const T *__restrict__ band, int lam,
+                                              const T *__restrict__ y, T *__restrict__ z) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nf = 2 * lam + 1;
+    const int nf_pad = (nf + BT_OPT - 1) / BT_OPT * BT_OPT;
+    T *sf = reinterpret_cast<T *>(smem_raw);  // nf_pad taps
+    T *sy = sf + nf_pad;                       // BT_TL + nf_pad - 1 inputs
+    const int64_t t0 = tiles[2 * blockIdx.x];
+    const int64_t iv = tiles[2 * blockIdx.x + 1];
+    const int64_t a = istart[iv], b = istart[iv + 1];
+    const T *c = band + (int64_t)fid[iv] * (lam + 1);
+    for (int k = threadIdx.x; k < nf_pad; k += BS) {
+        const int d = k - lam;
+        sf[k] = k < nf ? c[d < 0 ? -d : d] : (T)0;
+    }
+    const int nw = BT_TL + nf_pad - 1;
+    const int64_t w0 = t0 - lam;
+    for (int k = threadIdx.x; k < nw; k += BS) {
+        const int64_t t = w0 + k;
+        sy[k] = (t >= a && t < b) ? y[t] : (T)0;
+    }
+    __syncthreads();
+    const int m0 = threadIdx.x * BT_OPT;
+    T acc[BT_OPT];
+#pragma unroll
+    for (int m = 0; m < BT_OPT; ++m) acc[m] = 0;
+    for (int db = 0; db < nf; db += BT_OPT) {
+        T w[2 * BT_OPT - 1], cf[BT_OPT];
+#pragma unroll
+        for (int q = 0; q < 2 * BT_OPT - 1; ++q) w[q] = sy[m0 + db + q];
+#pragma unroll
+        for (int q = 0; q < BT_OPT; ++q) cf[q] = sf[db + q];
+#pragma unroll
+        for (int q = 0; q < BT_OPT; ++q)
+#pragma unroll
+            for (int m = 0; m < BT_OPT; ++m) acc[m] += cf[q] * w[m + q];
+    }
+    const int64_t t1 = t0 + BT_TL < b ? t0 + BT_TL : b;
+#pragma unroll
+    for (int m = 0; m < BT_OPT; ++m) {
+        const int64_t t = t0 + m0 + m;
+        if (t < t1) z[t] = acc[m];
+    }
+}
+
 // y[t R + r] = mask_t * tod[r * n + t]; flags non-finite data on kept samples.
 template <typename T, int R>
 __global__ void __launch_bounds__(BS) k_mask(const int32_t *__restrict__ jpix, int64_t n,
@@ -651,6 +711,14 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
 
 void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
 
+// Tile length of the register-tiled single-column band (k_band1) when its
+// LDS window (2 lambda + 1 taps, BT_TL + 2 lambda inputs) fits in 64 KB, else 0.
+int band1_tile_len(int lam, mm_precision prec) {
+    const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
+    const size_t te = prec == MM_F32 ? sizeof(float) : sizeof(double);
+    return lam >= 0 && te * (size_t)(2 * nf_pad + BT_TL - 1) <= 65536 ? BT_TL : 0;
+}
+
 void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
     if (nz->method == MM_NOISE_FFT) {
         noise_fft_apply_dev(ctx, nz, nrhs, y, z);
@@ -662,6 +730,23 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
+    if (nrhs == 1 && band1_tile_len(lam, nz->prec) > 0 && nz->tuned_tile_len[0] <= 0 &&
+        nz->tile_len == BT_TL) {
+        const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
+        const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
+        const size_t sm = te * (size_t)(nf_pad + BT_TL + nf_pad - 1);
+        if (nz->prec == MM_F32)
+            k_band1<float><<<(unsigned)nz->n_tiles, BS, sm, ctx->stream>>>(
+                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+                nz->band.as<float>(), lam, static_cast<const float *>(y), static_cast<float *>(z));
+        else
+            k_band1<double><<<(unsigned)nz->n_tiles, BS, sm, ctx->stream>>>(
+                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+                nz->band.as<double>(), lam, static_cast<const double *>(y),
+                static_cast<double *>(z));
+        MM_HIP(hipGetLastError());
+        return;
+    }
     // Tile length: the tuned one, else the single-column default, grown with
     // the column count so that a block's TL/R samples stay well above the
     // band's reach (TL <= 16 x 256 keeps each thread's outputs in registers).
@@ -791,8 +876,10 @@ void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *repor
             if (ms < best) { best = ms; best_g = g; }
         }
         p->p_blocks[li] = best_g;
-        // direct band tile length
-        if (nz->method == MM_NOISE_DIRECT) {
+        // direct band tile length (the single-column register-tiled band has
+        // a fixed tile)
+        if (nz->method == MM_NOISE_DIRECT &&
+            !(nrhs == 1 && band1_tile_len(nz->half_bw, nz->prec) > 0)) {
             best = 1e30;
             int best_tl = nz->tile_len;
             for (int tl : {256, 512, 1024, 2048, 4096}) {
