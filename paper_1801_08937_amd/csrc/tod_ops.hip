@@ -531,6 +531,63 @@ __global__ void __launch_bounds__(BS) k_band1(const int64_t *__restrict__ tiles,
     }
 }
 
+// Several columns, register-tiled: thread (g, r) = (threadIdx / R, threadIdx
+// mod R) keeps outputs g*BT_OPT .. g*BT_OPT + 7 of column r; a block covers
+// (BS / R) * BT_OPT consecutive outputs of one interval.  The window rows hold
+// the R columns side by side, so a wave's LDS reads are consecutive.  Same
+// tap order per output as k_band1 and k_band, so a column's bits do not
+// depend on R.
+template <typename T, int R>
+__global__ void __launch_bounds__(BS) k_bandR(const int64_t *__restrict__ tiles,
+                                              const int64_t *__restrict__ istart,
+                                              const int32_t *__restrict__ fid,
+                                              const T *__restrict__ band, int lam,
+                                              const T *__restrict__ y, T *__restrict__ z) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TL = (BS / R) * BT_OPT;
+    const int nf = 2 * lam + 1;
+    const int nf_pad = (nf + BT_OPT - 1) / BT_OPT * BT_OPT;
+    T *sf = reinterpret_cast<T *>(smem_raw);
+    T *sy = sf + nf_pad;  // (TL + nf_pad - 1) rows of R
+    const int64_t t0 = tiles[2 * blockIdx.x];
+    const int64_t iv = tiles[2 * blockIdx.x + 1];
+    const int64_t a = istart[iv], b = istart[iv + 1];
+    const T *c = band + (int64_t)fid[iv] * (lam + 1);
+    for (int k = threadIdx.x; k < nf_pad; k += BS) {
+        const int d = k - lam;
+        sf[k] = k < nf ? c[d < 0 ? -d : d] : (T)0;
+    }
+    const int rows = TL + nf_pad - 1;
+    const int64_t w0 = t0 - lam;
+    for (int e = threadIdx.x; e < rows * R; e += BS) {
+        const int64_t t = w0 + e / R;
+        sy[e] = (t >= a && t < b) ? y[t * R + e % R] : (T)0;
+    }
+    __syncthreads();
+    const int r = threadIdx.x % R;
+    const int m0 = (threadIdx.x / R) * BT_OPT;
+    T acc[BT_OPT];
+#pragma unroll
+    for (int m = 0; m < BT_OPT; ++m) acc[m] = 0;
+    for (int db = 0; db < nf; db += BT_OPT) {
+        T w[2 * BT_OPT - 1], cf[BT_OPT];
+#pragma unroll
+        for (int q = 0; q < 2 * BT_OPT - 1; ++q) w[q] = sy[(m0 + db + q) * R + r];
+#pragma unroll
+        for (int q = 0; q < BT_OPT; ++q) cf[q] = sf[db + q];
+#pragma unroll
+        for (int q = 0; q < BT_OPT; ++q)
+#pragma unroll
+            for (int m = 0; m < BT_OPT; ++m) acc[m] += cf[q] * w[m + q];
+    }
+    const int64_t t1 = t0 + TL < b ? t0 + TL : b;
+#pragma unroll
+    for (int m = 0; m < BT_OPT; ++m) {
+        const int64_t t = t0 + m0 + m;
+        if (t < t1) z[t * R + r] = acc[m];
+    }
+}
+
 // y[t R + r] = mask_t * tod[r * n + t]; flags non-finite data on kept samples.
 template <typename T, int R>
 __global__ void __launch_bounds__(BS) k_mask(const int32_t *__restrict__ jpix, int64_t n,
@@ -719,6 +776,15 @@ int band1_tile_len(int lam, mm_precision prec) {
     return lam >= 0 && te * (size_t)(2 * nf_pad + BT_TL - 1) <= 65536 ? BT_TL : 0;
 }
 
+// The same for k_bandR with R columns: tile (BS / R) * BT_OPT outputs; its
+// window holds R values per row.
+static int bandR_tile_len(int lam, int R, mm_precision prec) {
+    const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
+    const int tl = (BS / R) * BT_OPT;
+    const size_t te = prec == MM_F32 ? sizeof(float) : sizeof(double);
+    return lam >= 0 && te * (size_t)(nf_pad + (size_t)(tl + nf_pad - 1) * R) <= 65536 ? tl : 0;
+}
+
 void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
     if (nz->method == MM_NOISE_FFT) {
         noise_fft_apply_dev(ctx, nz, nrhs, y, z);
@@ -751,6 +817,31 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     // the column count so that a block's TL/R samples stay well above the
     // band's reach (TL <= 16 x 256 keeps each thread's outputs in registers).
     const bool multi = nrhs > 1;
+    const int tlR = multi && nz->tuned_tile_len[log2i(nrhs)] <= 0
+                        ? bandR_tile_len(lam, nrhs, nz->prec) : 0;
+    if (tlR > 0) {
+        if (nz->tile_len_m != tlR) set_band_tiles(ctx, const_cast<mm_noise *>(nz), tlR, true);
+        const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
+        const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
+        const size_t sm = te * (size_t)(nf_pad + (size_t)(tlR + nf_pad - 1) * nrhs);
+        dispatch_r(nrhs, [&](auto RR) {
+            constexpr int R = decltype(RR)::value;
+            if constexpr (R > 1) {
+                if (nz->prec == MM_F32)
+                    k_bandR<float, R><<<(unsigned)nz->n_tiles_m, BS, sm, ctx->stream>>>(
+                        nz->tiles_m.as<int64_t>(), nz->istart.as<int64_t>(),
+                        nz->fid.as<int32_t>(), nz->band.as<float>(), lam,
+                        static_cast<const float *>(y), static_cast<float *>(z));
+                else
+                    k_bandR<double, R><<<(unsigned)nz->n_tiles_m, BS, sm, ctx->stream>>>(
+                        nz->tiles_m.as<int64_t>(), nz->istart.as<int64_t>(),
+                        nz->fid.as<int32_t>(), nz->band.as<double>(), lam,
+                        static_cast<const double *>(y), static_cast<double *>(z));
+            }
+        });
+        MM_HIP(hipGetLastError());
+        return;
+    }
     int want = nz->tuned_tile_len[log2i(nrhs)];
     if (want <= 0) want = multi ? std::min(4096, std::max(nz->default_tile_len, 256 * nrhs))
                                 : nz->default_tile_len;
@@ -876,10 +967,11 @@ void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *repor
             if (ms < best) { best = ms; best_g = g; }
         }
         p->p_blocks[li] = best_g;
-        // direct band tile length (the single-column register-tiled band has
-        // a fixed tile)
-        if (nz->method == MM_NOISE_DIRECT &&
-            !(nrhs == 1 && band1_tile_len(nz->half_bw, nz->prec) > 0)) {
+        // direct band tile length, for the shapes the register-tiled kernels
+        // (fixed tiles) do not cover
+        const bool tiled = nrhs == 1 ? band1_tile_len(nz->half_bw, nz->prec) > 0
+                                     : bandR_tile_len(nz->half_bw, nrhs, nz->prec) > 0;
+        if (nz->method == MM_NOISE_DIRECT && !tiled) {
             best = 1e30;
             int best_tl = nz->tile_len;
             for (int tl : {256, 512, 1024, 2048, 4096}) {
