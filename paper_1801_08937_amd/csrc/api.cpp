@@ -301,12 +301,6 @@ void capture_chunk(mm_ctx *ctx, PcgGraph &G, int chunk, const std::function<void
     G.gen = ctx->ws_gen;
 }
 
-int choose_tile(int64_t n_samp, int n_cu) {
-    int64_t per = n_samp / (4 * (int64_t)n_cu);
-    int tl = 256;
-    while (tl < 4096 && tl < per) tl <<= 1;
-    return tl;
-}
 
 }  // namespace
 
@@ -563,12 +557,9 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
             MM_HIP(hipMemcpyAsync(nz->band.ptr, band, sizeof(double) * nb,
                                   hipMemcpyHostToDevice, s));
         }
-        // direct-band tile table: (first sample, interval) per tile
-        // the single-column direct band uses the register-tiled kernel's fixed
-        // tile when its window fits in LDS (set here, so that applies never
-        // rebuild the table)
-        const int tl1 = band1_tile_len(half_bw, prec);
-        nz->default_tile_len = tl1 > 0 ? tl1 : choose_tile(nz->n_samp, ctx->n_cu);
+        // single-column direct-band tile table (first sample, interval) per
+        // tile, built here so that applies never rebuild it
+        nz->default_tile_len = band_tile_len(1);
         set_band_tiles(ctx, nz, nz->default_tile_len);
         if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
     } catch (...) {

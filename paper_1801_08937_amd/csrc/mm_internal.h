@@ -176,8 +176,7 @@ struct mm_noise {
     mm::DBuf tiles;  // int64 pairs (tile start sample, interval index)
     int64_t n_tiles = 0;
     int32_t tile_len = 0;
-    int32_t default_tile_len = 0;  // single-column default, from the device size
-    int32_t tuned_tile_len[7] = {0, 0, 0, 0, 0, 0, 0};  // per log2(nrhs); 0 = untuned
+    int32_t default_tile_len = 0;  // single-column tile of the direct band
     // a second table for multi-column applies, whose tiles are longer (each
     // block covers TL/R samples of all R columns)
     mm::DBuf tiles_m;
@@ -240,7 +239,7 @@ void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width);
 void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y);
 void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x);
 void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
-int band1_tile_len(int lam, mm_precision prec);
+int band_tile_len(int nrhs);
 void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_rm, void *y,
                   int *nonfinite_flag);
 void pair_sum_diff_dev(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a, const void *b,

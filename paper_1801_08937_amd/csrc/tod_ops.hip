@@ -24,7 +24,6 @@ template <> struct Vec2<double> { using type = double2; };
 namespace {
 
 constexpr int BS = 256;
-constexpr int BAND_LDS_MAX = 2047;
 
 template <typename T, int R>
 __device__ __forceinline__ T p_gather(int32_t j, typename Vec2<T>::type ww,
@@ -307,87 +306,6 @@ __global__ void __launch_bounds__(BS) k_pt_sum_parts(const double *__restrict__ 
     }
 }
 
-// Direct banded Toeplitz: block (tile, part) computes outputs
-// t in [t0 + part*TL/R, t0 + (part+1)*TL/R) of one interval for all R columns.
-// The input window [t - lambda, t + lambda] (clipped to the interval) is
-// streamed through LDS in chunks; every output accumulates its taps in
-// ascending u, so its value does not depend on the tiling or on R.
-template <typename T, int R>
-__global__ void __launch_bounds__(BS) k_band(const int64_t *__restrict__ tiles,
-                                             const int64_t *__restrict__ istart,
-                                             const int32_t *__restrict__ fid,
-                                             const T *__restrict__ band, int lam, int TL,
-                                             const T *__restrict__ y, T *__restrict__ z) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    // the band sits in LDS when it fits beside the input chunk, else it is
-    // read through the cache hierarchy
-    const bool band_in_lds = lam <= BAND_LDS_MAX;
-    const int band_slots = band_in_lds ? ((lam + 1 + 3) & ~3) : 0;
-    T *sb = reinterpret_cast<T *>(smem_raw);
-    T *sy = sb + band_slots;
-    constexpr int CHR = 4096;          // LDS chunk, in elements
-    constexpr int CH = CHR / R;        // samples per chunk
-
-    const int64_t t_tile = tiles[2 * blockIdx.x];
-    const int64_t iv = tiles[2 * blockIdx.x + 1];
-    const int64_t a = istart[iv], b = istart[iv + 1];
-    const T *c = band + (int64_t)fid[iv] * (lam + 1);
-    const int sub_len = TL / R;
-    const int64_t t0 = t_tile + (int64_t)blockIdx.y * sub_len;
-    int64_t t1 = t0 + sub_len;
-    const int64_t tile_end = t_tile + TL < b ? t_tile + TL : b;
-    if (t1 > tile_end) t1 = tile_end;
-    if (t0 >= t1) return;
-
-    if (band_in_lds)
-        for (int i = threadIdx.x; i <= lam; i += BS) sb[i] = c[i];
-    const T *cb = band_in_lds ? sb : c;
-
-    constexpr int SPT = BS / R;  // sample slots per pass
-    const int r = threadIdx.x % R;
-    const int ts = threadIdx.x / R;
-    const int opt = (sub_len + SPT - 1) / SPT;  // consecutive outputs per thread
-    constexpr int MAXO = 16;
-    T acc[MAXO];
-#pragma unroll
-    for (int q = 0; q < MAXO; ++q) acc[q] = 0;
-    const int64_t my0 = t0 + (int64_t)ts * opt;
-
-    const int64_t lo = t0 - lam > a ? t0 - lam : a;
-    const int64_t hi = t1 + lam < b ? t1 + lam : b;
-    for (int64_t c0 = lo; c0 < hi; c0 += CH) {
-        const int64_t c1 = c0 + CH < hi ? c0 + CH : hi;
-        __syncthreads();
-        const int64_t cnt = (c1 - c0) * R;
-        const T *src = y + c0 * R;
-        for (int64_t e = threadIdx.x; e < cnt; e += BS) sy[e] = src[e];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < MAXO; ++q) {
-            if (q < opt) {
-                const int64_t t = my0 + q;
-                if (t < t1) {
-                    int64_t ulo = t - lam > c0 ? t - lam : c0;
-                    int64_t uhi = t + lam + 1 < c1 ? t + lam + 1 : c1;
-                    T s = acc[q];
-                    for (int64_t u = ulo; u < uhi; ++u) {
-                        const int64_t d = t > u ? t - u : u - t;
-                        s += cb[d] * sy[(u - c0) * R + r];
-                    }
-                    acc[q] = s;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < MAXO; ++q) {
-        if (q < opt) {
-            const int64_t t = my0 + q;
-            if (t < t1) z[t * R + r] = acc[q];
-        }
-    }
-}
-
 // Pointings of the pair-sum (I, NC = 1: weight 1) and pair-difference (QU,
 // NC = 2: weights cos 2psi, sin 2psi) streams (Eqs. d+ and d-).  Same
 // structure as k_apply_P / k_apply_PT; map x[(NC j + a) R + r].
@@ -471,114 +389,70 @@ __global__ void __launch_bounds__(BS) k_sum_diff(int64_t n, const T *a, const T 
     }
 }
 
-// Single-column direct band, register-tiled.  A block owns BT_TL = 2,048
-// consecutive outputs of one interval; their input window [t0 - lambda,
-// t0 + BT_TL + lambda) (zero outside the interval) and the taps laid out as a
-// full symmetric filter f[d + lambda] = c_|d| sit in LDS.  Thread i keeps
-// outputs i*BT_OPT .. i*BT_OPT + 7 in registers and walks the taps in blocks
-// of BT_OPT: per block it loads 15 inputs and 8 taps and does 64 FMAs from
-// registers.  Every output sums its taps in ascending offset, as k_band
-// does; the zero-padded terms add exactly +0, so the two give the same bits.
+// Direct band, register-tiled.  A block owns TL = (BS / R) * BT_OPT
+// consecutive outputs of one interval for all R columns; thread (g, r) =
+// (threadIdx / R, threadIdx mod R) keeps outputs g*BT_OPT .. g*BT_OPT + 7 of
+// column r in registers.  The filter is taken as the full symmetric one,
+// f[d] = c_|d - lambda|, d = 0 .. 2 lambda, and walked in chunks of at most
+// CL taps; for each chunk the taps and the input window [t0 - lambda + d0,
+// t0 + TL - lambda + d0 + CL - 1) (zero outside the interval, R values per
+// row, so a wave's reads are consecutive) are staged in LDS.  Per block of
+// BT_OPT taps a thread loads 15 inputs and 8 taps and does 64 FMAs from
+// registers.  Every output sums its taps in ascending offset, chunk after
+// chunk, so its value does not depend on R, TL or CL; zero-padded terms add
+// exactly +0.
 constexpr int BT_OPT = 8;
-constexpr int BT_TL = BS * BT_OPT;
+constexpr int BT_LDS = 65536;  // bytes of LDS per block
 
-template <typename T>
-__global__ void __launch_bounds__(BS) k_band1(const int64_t *__restrict__ tiles,
-                                              const int64_t *__restrict__ istart,
-                                              const int32_t *__restrict__ fid,
-                                              const T *__restrict__ band, int lam,
-                                              const T *__restrict__ y, T *__restrict__ z) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nf = 2 * lam + 1;
-    const int nf_pad = (nf + BT_OPT - 1) / BT_OPT * BT_OPT;
-    T *sf = reinterpret_cast<T *>(smem_raw);  // nf_pad taps
-    T *sy = sf + nf_pad;                       // BT_TL + nf_pad - 1 inputs
-    const int64_t t0 = tiles[2 * blockIdx.x];
-    const int64_t iv = tiles[2 * blockIdx.x + 1];
-    const int64_t a = istart[iv], b = istart[iv + 1];
-    const T *c = band + (int64_t)fid[iv] * (lam + 1);
-    for (int k = threadIdx.x; k < nf_pad; k += BS) {
-        const int d = k - lam;
-        sf[k] = k < nf ? c[d < 0 ? -d : d] : (T)0;
-    }
-    const int nw = BT_TL + nf_pad - 1;
-    const int64_t w0 = t0 - lam;
-    for (int k = threadIdx.x; k < nw; k += BS) {
-        const int64_t t = w0 + k;
-        sy[k] = (t >= a && t < b) ? y[t] : (T)0;
-    }
-    __syncthreads();
-    const int m0 = threadIdx.x * BT_OPT;
-    T acc[BT_OPT];
-#pragma unroll
-    for (int m = 0; m < BT_OPT; ++m) acc[m] = 0;
-    for (int db = 0; db < nf; db += BT_OPT) {
-        T w[2 * BT_OPT - 1], cf[BT_OPT];
-#pragma unroll
-        for (int q = 0; q < 2 * BT_OPT - 1; ++q) w[q] = sy[m0 + db + q];
-#pragma unroll
-        for (int q = 0; q < BT_OPT; ++q) cf[q] = sf[db + q];
-#pragma unroll
-        for (int q = 0; q < BT_OPT; ++q)
-#pragma unroll
-            for (int m = 0; m < BT_OPT; ++m) acc[m] += cf[q] * w[m + q];
-    }
-    const int64_t t1 = t0 + BT_TL < b ? t0 + BT_TL : b;
-#pragma unroll
-    for (int m = 0; m < BT_OPT; ++m) {
-        const int64_t t = t0 + m0 + m;
-        if (t < t1) z[t] = acc[m];
-    }
-}
-
-// Several columns, register-tiled: thread (g, r) = (threadIdx / R, threadIdx
-// mod R) keeps outputs g*BT_OPT .. g*BT_OPT + 7 of column r; a block covers
-// (BS / R) * BT_OPT consecutive outputs of one interval.  The window rows hold
-// the R columns side by side, so a wave's LDS reads are consecutive.  Same
-// tap order per output as k_band1 and k_band, so a column's bits do not
-// depend on R.
 template <typename T, int R>
-__global__ void __launch_bounds__(BS) k_bandR(const int64_t *__restrict__ tiles,
-                                              const int64_t *__restrict__ istart,
-                                              const int32_t *__restrict__ fid,
-                                              const T *__restrict__ band, int lam,
-                                              const T *__restrict__ y, T *__restrict__ z) {
+__global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ tiles,
+                                                   const int64_t *__restrict__ istart,
+                                                   const int32_t *__restrict__ fid,
+                                                   const T *__restrict__ band, int lam, int CL,
+                                                   const T *__restrict__ y, T *__restrict__ z) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TL = (BS / R) * BT_OPT;
     const int nf = 2 * lam + 1;
     const int nf_pad = (nf + BT_OPT - 1) / BT_OPT * BT_OPT;
-    T *sf = reinterpret_cast<T *>(smem_raw);
-    T *sy = sf + nf_pad;  // (TL + nf_pad - 1) rows of R
+    // CL is a multiple of BT_OPT; rounding it here lets the compiler see
+    // that the window is 16-byte aligned and read it with 128-bit LDS loads
+    const int CLa = CL / BT_OPT * BT_OPT;
+    T *sf = reinterpret_cast<T *>(smem_raw);  // CL taps
+    T *sy = sf + CLa;                          // (TL + CL - 1) rows of R
     const int64_t t0 = tiles[2 * blockIdx.x];
     const int64_t iv = tiles[2 * blockIdx.x + 1];
     const int64_t a = istart[iv], b = istart[iv + 1];
     const T *c = band + (int64_t)fid[iv] * (lam + 1);
-    for (int k = threadIdx.x; k < nf_pad; k += BS) {
-        const int d = k - lam;
-        sf[k] = k < nf ? c[d < 0 ? -d : d] : (T)0;
-    }
-    const int rows = TL + nf_pad - 1;
-    const int64_t w0 = t0 - lam;
-    for (int e = threadIdx.x; e < rows * R; e += BS) {
-        const int64_t t = w0 + e / R;
-        sy[e] = (t >= a && t < b) ? y[t * R + e % R] : (T)0;
-    }
-    __syncthreads();
     const int r = threadIdx.x % R;
     const int m0 = (threadIdx.x / R) * BT_OPT;
     T acc[BT_OPT];
 #pragma unroll
     for (int m = 0; m < BT_OPT; ++m) acc[m] = 0;
-    for (int db = 0; db < nf; db += BT_OPT) {
-        T w[2 * BT_OPT - 1], cf[BT_OPT];
+    for (int d0 = 0; d0 < nf_pad; d0 += CLa) {
+        const int cl = nf_pad - d0 < CLa ? nf_pad - d0 : CLa;
+        __syncthreads();  // the previous chunk's reads are done
+        for (int k = threadIdx.x; k < cl; k += BS) {
+            const int d = d0 + k - lam;
+            sf[k] = d0 + k < nf ? c[d < 0 ? -d : d] : (T)0;
+        }
+        const int rows = TL + cl - 1;
+        const int64_t w0 = t0 - lam + d0;
+        for (int e = threadIdx.x; e < rows * R; e += BS) {
+            const int64_t t = w0 + e / R;
+            sy[e] = (t >= a && t < b) ? y[t * R + e % R] : (T)0;
+        }
+        __syncthreads();
+        for (int db = 0; db < cl; db += BT_OPT) {
+            T w[2 * BT_OPT - 1], cf[BT_OPT];
 #pragma unroll
-        for (int q = 0; q < 2 * BT_OPT - 1; ++q) w[q] = sy[(m0 + db + q) * R + r];
+            for (int q = 0; q < 2 * BT_OPT - 1; ++q) w[q] = sy[(m0 + db + q) * R + r];
 #pragma unroll
-        for (int q = 0; q < BT_OPT; ++q) cf[q] = sf[db + q];
+            for (int q = 0; q < BT_OPT; ++q) cf[q] = sf[db + q];
 #pragma unroll
-        for (int q = 0; q < BT_OPT; ++q)
+            for (int q = 0; q < BT_OPT; ++q)
 #pragma unroll
-            for (int m = 0; m < BT_OPT; ++m) acc[m] += cf[q] * w[m + q];
+                for (int m = 0; m < BT_OPT; ++m) acc[m] += cf[q] * w[m + q];
+        }
     }
     const int64_t t1 = t0 + TL < b ? t0 + TL : b;
 #pragma unroll
@@ -768,21 +642,18 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
 
 void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
 
-// Tile length of the register-tiled single-column band (k_band1) when its
-// LDS window (2 lambda + 1 taps, BT_TL + 2 lambda inputs) fits in 64 KB, else 0.
-int band1_tile_len(int lam, mm_precision prec) {
-    const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
-    const size_t te = prec == MM_F32 ? sizeof(float) : sizeof(double);
-    return lam >= 0 && te * (size_t)(2 * nf_pad + BT_TL - 1) <= 65536 ? BT_TL : 0;
-}
+// Tile length of the direct band for R columns.
+int band_tile_len(int nrhs) { return (BS / nrhs) * BT_OPT; }
 
-// The same for k_bandR with R columns: tile (BS / R) * BT_OPT outputs; its
-// window holds R values per row.
-static int bandR_tile_len(int lam, int R, mm_precision prec) {
-    const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
-    const int tl = (BS / R) * BT_OPT;
+// Taps per LDS chunk of the direct band: taps + window rows of R values fit
+// in BT_LDS bytes; a multiple of BT_OPT, at most the padded filter length.
+static int band_chunk(int lam, int R, mm_precision prec) {
     const size_t te = prec == MM_F32 ? sizeof(float) : sizeof(double);
-    return lam >= 0 && te * (size_t)(nf_pad + (size_t)(tl + nf_pad - 1) * R) <= 65536 ? tl : 0;
+    const int tl = band_tile_len(R);
+    const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
+    int cl = (int)(((int64_t)(BT_LDS / te) - (int64_t)(tl - 1) * R) / (R + 1));
+    cl = cl / BT_OPT * BT_OPT;
+    return cl < nf_pad ? cl : nf_pad;
 }
 
 void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
@@ -796,75 +667,27 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
-    if (nrhs == 1 && band1_tile_len(lam, nz->prec) > 0 && nz->tuned_tile_len[0] <= 0 &&
-        nz->tile_len == BT_TL) {
-        const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
-        const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
-        const size_t sm = te * (size_t)(nf_pad + BT_TL + nf_pad - 1);
-        if (nz->prec == MM_F32)
-            k_band1<float><<<(unsigned)nz->n_tiles, BS, sm, ctx->stream>>>(
-                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
-                nz->band.as<float>(), lam, static_cast<const float *>(y), static_cast<float *>(z));
-        else
-            k_band1<double><<<(unsigned)nz->n_tiles, BS, sm, ctx->stream>>>(
-                nz->tiles.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
-                nz->band.as<double>(), lam, static_cast<const double *>(y),
-                static_cast<double *>(z));
-        MM_HIP(hipGetLastError());
-        return;
-    }
-    // Tile length: the tuned one, else the single-column default, grown with
-    // the column count so that a block's TL/R samples stay well above the
-    // band's reach (TL <= 16 x 256 keeps each thread's outputs in registers).
     const bool multi = nrhs > 1;
-    const int tlR = multi && nz->tuned_tile_len[log2i(nrhs)] <= 0
-                        ? bandR_tile_len(lam, nrhs, nz->prec) : 0;
-    if (tlR > 0) {
-        if (nz->tile_len_m != tlR) set_band_tiles(ctx, const_cast<mm_noise *>(nz), tlR, true);
-        const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
-        const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
-        const size_t sm = te * (size_t)(nf_pad + (size_t)(tlR + nf_pad - 1) * nrhs);
-        dispatch_r(nrhs, [&](auto RR) {
-            constexpr int R = decltype(RR)::value;
-            if constexpr (R > 1) {
-                if (nz->prec == MM_F32)
-                    k_bandR<float, R><<<(unsigned)nz->n_tiles_m, BS, sm, ctx->stream>>>(
-                        nz->tiles_m.as<int64_t>(), nz->istart.as<int64_t>(),
-                        nz->fid.as<int32_t>(), nz->band.as<float>(), lam,
-                        static_cast<const float *>(y), static_cast<float *>(z));
-                else
-                    k_bandR<double, R><<<(unsigned)nz->n_tiles_m, BS, sm, ctx->stream>>>(
-                        nz->tiles_m.as<int64_t>(), nz->istart.as<int64_t>(),
-                        nz->fid.as<int32_t>(), nz->band.as<double>(), lam,
-                        static_cast<const double *>(y), static_cast<double *>(z));
-            }
-        });
-        MM_HIP(hipGetLastError());
-        return;
-    }
-    int want = nz->tuned_tile_len[log2i(nrhs)];
-    if (want <= 0) want = multi ? std::min(4096, std::max(nz->default_tile_len, 256 * nrhs))
-                                : nz->default_tile_len;
-    if (want != (multi ? nz->tile_len_m : nz->tile_len))
-        set_band_tiles(ctx, const_cast<mm_noise *>(nz), want, multi);
+    const int tl = band_tile_len(nrhs);
+    // the tables are built at noise build for one column and on first use for
+    // several (the single-column one is shared with background callers)
+    if (tl != (multi ? nz->tile_len_m : nz->tile_len))
+        set_band_tiles(ctx, const_cast<mm_noise *>(nz), tl, multi);
     const int64_t *tiles = multi ? nz->tiles_m.as<int64_t>() : nz->tiles.as<int64_t>();
-    const int64_t n_tiles = multi ? nz->n_tiles_m : nz->n_tiles;
-    const int tl = multi ? nz->tile_len_m : nz->tile_len;
+    const unsigned n_tiles = (unsigned)(multi ? nz->n_tiles_m : nz->n_tiles);
+    const int cl = band_chunk(lam, nrhs, nz->prec);
+    const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
+    const size_t sm = te * ((size_t)cl + (size_t)(tl + cl - 1) * nrhs);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        dim3 grid((unsigned)n_tiles, R);
-        const int band_slots = lam <= BAND_LDS_MAX ? ((lam + 1 + 3) & ~3) : 0;
-        if (nz->prec == MM_F32) {
-            size_t sm = sizeof(float) * (band_slots + 4096);
-            k_band<float, R><<<grid, BS, sm, ctx->stream>>>(
-                tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<float>(),
-                lam, tl, static_cast<const float *>(y), static_cast<float *>(z));
-        } else {
-            size_t sm = sizeof(double) * (band_slots + 4096);
-            k_band<double, R><<<grid, BS, sm, ctx->stream>>>(
+        if (nz->prec == MM_F32)
+            k_band_tiled<float, R><<<n_tiles, BS, sm, ctx->stream>>>(
+                tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<float>(), lam,
+                cl, static_cast<const float *>(y), static_cast<float *>(z));
+        else
+            k_band_tiled<double, R><<<n_tiles, BS, sm, ctx->stream>>>(
                 tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<double>(),
-                lam, tl, static_cast<const double *>(y), static_cast<double *>(z));
-        }
+                lam, cl, static_cast<const double *>(y), static_cast<double *>(z));
     });
     MM_HIP(hipGetLastError());
 }
@@ -923,8 +746,9 @@ void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl, bool multi) {
     (multi ? nz->n_tiles_m : nz->n_tiles) = (int64_t)tiles.size() / 2;
 }
 
-// Measure candidate launch shapes with HIP events and keep the fastest:
-// the direct band's tile length and the P kernel's grid size, per nrhs.
+// Measure candidate launch shapes with HIP events and keep the fastest: the
+// P kernel's grid size, per nrhs (the direct band's tiles are fixed by its
+// register tiling).
 // Every candidate computes the same values (each output's terms are summed
 // in a fixed order independent of the launch shape), so tuning never changes
 // results.  report: (stage, candidate, ms) triples.
@@ -967,23 +791,6 @@ void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *repor
             if (ms < best) { best = ms; best_g = g; }
         }
         p->p_blocks[li] = best_g;
-        // direct band tile length, for the shapes the register-tiled kernels
-        // (fixed tiles) do not cover
-        const bool tiled = nrhs == 1 ? band1_tile_len(nz->half_bw, nz->prec) > 0
-                                     : bandR_tile_len(nz->half_bw, nrhs, nz->prec) > 0;
-        if (nz->method == MM_NOISE_DIRECT && !tiled) {
-            best = 1e30;
-            int best_tl = nz->tile_len;
-            for (int tl : {256, 512, 1024, 2048, 4096}) {
-                if (tl < nrhs) continue;
-                nz->tuned_tile_len[li] = tl;
-                const double ms = time_it([&]() { noise_apply_dev(ctx, nz, nrhs, y.ptr, z.ptr); });
-                if (report) { report[3 * nr] = 1; report[3 * nr + 1] = tl; report[3 * nr + 2] = ms; }
-                ++nr;
-                if (ms < best) { best = ms; best_tl = tl; }
-            }
-            nz->tuned_tile_len[li] = best_tl;
-        }
     } catch (...) {
         ctx->prof.on = prof;
         (void)hipEventDestroy(e0);
