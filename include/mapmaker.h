@@ -457,11 +457,12 @@ void mm_server_destroy(mm_server *srv);
 /* -------------------------------------------------------------- autotuning */
 
 /* Time candidate launch shapes for nrhs columns with HIP events and keep the
- * fastest: the P kernel's grid size and, for the direct band, its tile
- * length.  Each candidate computes bitwise the same values (every output sums
- * its terms in a fixed order), so tuning changes speed only.  Choices are
- * stored in the handles and used by later calls with that nrhs.
- *   report [host] f64[3 * 16] or NULL: (stage 0 = P / 1 = band, candidate, ms)
+ * fastest: the P kernel's grid size (the direct band's tiles follow from its
+ * register tiling and are not tuned).  Each candidate computes bitwise the
+ * same values (every output sums its terms in a fixed order), so tuning
+ * changes speed only.  Choices are stored in the handles and used by later
+ * calls with that nrhs.
+ *   report [host] f64[3 * 16] or NULL: (stage 0 = P, candidate, ms)
  *   n_report [host] or NULL: entries written */
 mm_status mm_autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int32_t nrhs, double *report,
                       int32_t *n_report);

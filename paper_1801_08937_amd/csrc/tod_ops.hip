@@ -756,10 +756,10 @@ void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *repor
               int *n_report) {
     const int li = log2i(nrhs);
     const size_t te = p->prec == MM_F32 ? sizeof(float) : sizeof(double);
-    DBuf x, y, z;
-    x.alloc(sizeof(double) * 3 * (size_t)p->n_obs * nrhs);
+    (void)nz;
+    DBuf x, y;
+    x.alloc(sizeof(double) * (size_t)p->n() * nrhs);
     y.alloc(te * (size_t)p->n_samp * nrhs);
-    z.alloc(te * (size_t)p->n_samp * nrhs);
     MM_HIP(hipMemsetAsync(x.ptr, 0, x.bytes, ctx->stream));
     MM_HIP(hipMemsetAsync(y.ptr, 0, y.bytes, ctx->stream));
     hipEvent_t e0, e1;
