@@ -276,3 +276,31 @@ def test_ground_filter_errors(ctx):
             ctx.polyfilter(*args, dev(bad.astype(np.int32)), nb)
     with pytest.raises(ValueError):
         ctx.polyfilter(*args, dev(gb[:-1]), 9)
+
+
+@pytest.mark.parametrize("stokes", ["I", "QU"])
+def test_filter_on_stokes_subset_pointing(ctx, stokes):
+    """The template filter (with ground bins) as the weight of the I-only
+    and QU-only systems of a detector pair's sum and difference streams:
+    A, b and M_BD (1x1 / 2x2 blocks) against the oracle, and one M_BD solve
+    to the true residual."""
+    p = synth.random_problem(29, n_side=10, n_samp=20011, n_int=4, half_bw=5, n_filters=2,
+                             flag_frac=0.05)
+    psi = None if stokes == "I" else p.psi
+    lp = ctx.pointing(dev(p.pix), None if psi is None else dev(psi), p.n_pix_total,
+                      p.min_hits, stokes=stokes)
+    op = O.pointing_build(p.pix, psi, p.n_pix_total, p.min_hits, stokes)
+    sub = _subscans(p, 30)
+    w = np.random.default_rng(31).uniform(0.5, 2.0, p.n_intervals)
+    gb = _ground_bins(p, 32, 13)
+    lf = ctx.polyfilter(lp, p.interval_start, w, sub, 2, dev(gb), 13)
+    of = O.polyfilter_build(op, p.interval_start, w, sub, 2, gb, 13)
+    assert lp.nc == len(stokes) and lp.n == op.n
+    x = np.random.default_rng(33).standard_normal(op.n)
+    assert maxrel(host(ctx.apply_A(lp, lf, dev(x))), O.apply_A(op, of, x)) <= TOL_OP
+    b = ctx.rhs(lp, lf, dev(p.tod))
+    assert maxrel(host(b), O.rhs(op, of, p.tod)) <= TOL_OP
+    M = ctx.mbd(lp, lf)
+    assert maxrel(host(ctx.precond_apply(M, dev(x))), O.mbd_apply(O.mbd_build(op, of), x)) <= TOL_OP
+    xs, info = ctx.solve(lp, lf, M, b, tol=1e-10, max_iter=3000)
+    assert info["converged"] and info["rel_res_true"] <= 1e-9, info
