@@ -330,15 +330,17 @@ def _fft_problem(lam, L, n_int, seed, n_filters=3):
     return istart, fid, band
 
 
-@pytest.mark.parametrize("lam,L,n_int", [(300, 5000, 5), (1000, 20000, 3), (4096, 65536, 3),
-                                         (6000, 30000, 2)])
-def test_noise_fft_parity(ctx, lam, L, n_int):
+@pytest.mark.parametrize("lam,L,n_int,block", [(300, 5000, 5, 16384), (1000, 20000, 3, 16384),
+                                               (2048, 65536, 2, 16384), (4096, 65536, 3, 32768),
+                                               (6000, 30000, 2, 32768)])
+def test_noise_fft_parity(ctx, lam, L, n_int, block):
     """FFT form of N^-1 (overlap-save, partial last blocks, several filters)
-    against the oracle's direct band."""
+    against the oracle's direct band.  A few blocks fill less than one wave
+    of CUs, so the 16,384-sample blocks are taken up to lambda = 2,048."""
     import torch
     istart, fid, band = _fft_problem(lam, L, n_int, lam)
     nz = ctx.noise(istart, fid, band, lam, method=2)
-    assert nz.method == 2
+    assert nz.method == 2 and nz.fft_n == block
     on = O.noise_build(istart, fid, band, lam)
     y = np.random.default_rng(1).standard_normal(int(istart[-1]))
     z = host(ctx.noise_apply(nz, dev(y)))
@@ -353,6 +355,30 @@ def test_noise_fft_parity(ctx, lam, L, n_int):
     nz32 = ctx.noise(istart, fid, band, lam, method=2, prec=1)
     z32 = host(ctx.noise_apply(nz32, dev(y.astype(np.float32))))
     assert rel(z32, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n_int,block", [(100, 16384), (320, 32768)])
+def test_noise_fft_block_choice_full_size(ctx, n_int, block):
+    """lambda = 2,048 over 2^16-sample intervals: 100 intervals take the
+    16,384-sample blocks (600 blocks, 3 waves of CUs, against 300 larger
+    blocks in 2 waves), 320 intervals the 32,768-sample ones (7/8 valid
+    against 3/4).  N^-1 is block diagonal over intervals, so whole intervals
+    are checked against the oracle applied to that interval alone."""
+    import torch
+    lam, L = 2048, 1 << 16
+    rng = np.random.default_rng(n_int)
+    istart = np.arange(n_int + 1, dtype=np.int64) * L
+    fid = rng.integers(0, 3, n_int).astype(np.int32)
+    band = np.stack([synth.band_from_psd(L, lam, fk) for fk in rng.uniform(0.05, 1, 3)])
+    nz = ctx.noise(istart, fid, band, lam, method=2)
+    assert nz.method == 2 and nz.fft_n == block
+    y = rng.standard_normal(n_int * L)
+    z = host(ctx.noise_apply(nz, dev(y)))
+    for i in (0, n_int // 2, n_int - 1):
+        a, e = int(istart[i]), int(istart[i + 1])
+        on = O.noise_build(np.array([0, L], dtype=np.int64), fid[i:i + 1], band, lam)
+        ref = O.noise_apply_direct(on, y[a:e])
+        assert maxrel(z[a:e], ref) <= 1e-11, (i, maxrel(z[a:e], ref))
 
 
 def test_A_fft_parity_config2_shape(ctx):
