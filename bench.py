@@ -217,15 +217,20 @@ def main():
     solves = {}
     if not args.no_solves and not args.profile_only:
         for name, M in (("m2l", M2), ("mbd", Mbd)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            x, info = ctx.solve(lp, ln, M, b, tol=1e-8, max_iter=3000, check_every=4,
-                                history=False)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
+            # each solve twice: the first in the process also pays one-time
+            # costs (code object loads, workspace); the second is reported
+            els = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = ctx.solve(lp, ln, M, b, tol=1e-8, max_iter=3000, check_every=4,
+                                    history=False)
+                torch.cuda.synchronize()
+                els.append(time.perf_counter() - t0)
+            el = els[1]
             solves[name] = {"iters": info["iters"], "converged": info["converged"],
                             "rel_res_true": info["rel_res_true"], "solve_s": el,
-                            "s_per_iter": el / max(info["iters"], 1)}
+                            "first_solve_s": els[0], "s_per_iter": el / max(info["iters"], 1)}
             log(f"[bench] solve {name}: {solves[name]}")
         solves["m2l"]["setup_s"] = setup["m2l_build_s"]
         solves["m2l"]["total_s"] = setup["m2l_build_s"] + solves["m2l"]["solve_s"]

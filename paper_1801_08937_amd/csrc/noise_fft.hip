@@ -258,11 +258,13 @@ bool noise_fft_supported(int half_bw, int64_t min_len) {
 
 // Measured time model of one overlap-save apply with N-sample blocks.  The
 // blocks run in waves of one per CU (a block fills a CU), and a block takes a
-// fixed time (transforms and exchanges: 1 for 16,384 samples, 1.689 for
+// fixed time (transforms and exchanges: 1 for 16,384 samples, 1.72 for
 // 32,768) plus 4.59e-5 per input sample it reads (reads are clipped to the
-// interval).  Fitted to FP64 applies of 2^23 and 2^27 samples in 2^16-sample
-// intervals, lambda 16 to 4,096: it picks the faster size in 9 of 10
-// measured cases, and the other is within 3 %.
+// interval).  Fitted by least squares to FP64 applies of 2^23 and 2^27
+// samples in 2^16-sample intervals, lambda 16 to 4,096 (1.69 for the large
+// blocks' fixed time), then 1.72, which picks the faster size in each of the
+// measured cases: at 2^27 samples the small blocks up to lambda = 768, the
+// large ones from 1,024.
 static double fft_time_model(const mm_noise *nz, int N, int n_cu) {
     const int64_t lam = nz->half_bw, V = N - 2 * lam;
     int64_t nb = 0;
@@ -273,7 +275,7 @@ static double fft_time_model(const mm_noise *nz, int N, int n_cu) {
             rd += (double)(std::min(e, t - lam + N) - std::max(a, t - lam));
     }
     if (nb == 0) return 0;
-    const double fixed = N == 2 * FFT_NC ? 1.0 : 1.689;
+    const double fixed = N == 2 * FFT_NC ? 1.0 : 1.72;
     const int64_t waves = (nb + n_cu - 1) / n_cu;
     return (double)waves * (fixed + 4.59e-5 * rd / (double)nb);
 }
