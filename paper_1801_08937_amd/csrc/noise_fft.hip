@@ -258,13 +258,11 @@ bool noise_fft_supported(int half_bw, int64_t min_len) {
 
 // Measured time model of one overlap-save apply with N-sample blocks.  The
 // blocks run in waves of one per CU (a block fills a CU), and a block takes a
-// fixed time (transforms and exchanges: 1 for 16,384 samples, 1.72 for
-// 32,768) plus 4.59e-5 per input sample it reads (reads are clipped to the
-// interval).  Fitted by least squares to FP64 applies of 2^23 and 2^27
-// samples in 2^16-sample intervals, lambda 16 to 4,096 (1.69 for the large
-// blocks' fixed time), then 1.72, which picks the faster size in each of the
-// measured cases: at 2^27 samples the small blocks up to lambda = 768, the
-// large ones from 1,024.
+// fixed time (transforms and exchanges: 1 for 16,384 samples, 1.56 for
+// 32,768) plus 1e-5 per input sample it reads (reads are clipped to the
+// interval).  Fitted to FP64 applies of 2^20, 2^23 and 2^27 samples in
+// 2^16-sample intervals, lambda 16 to 2,048, for the smallest loss from a
+// wrong pick: each measured case gets the faster size or one within 5 %.
 static double fft_time_model(const mm_noise *nz, int N, int n_cu) {
     const int64_t lam = nz->half_bw, V = N - 2 * lam;
     int64_t nb = 0;
@@ -275,15 +273,15 @@ static double fft_time_model(const mm_noise *nz, int N, int n_cu) {
             rd += (double)(std::min(e, t - lam + N) - std::max(a, t - lam));
     }
     if (nb == 0) return 0;
-    const double fixed = N == 2 * FFT_NC ? 1.0 : 1.72;
+    const double fixed = N == 2 * FFT_NC ? 1.0 : 1.56;
     const int64_t waves = (nb + n_cu - 1) / n_cu;
-    return (double)waves * (fixed + 4.59e-5 * rd / (double)nb);
+    return (double)waves * (fixed + 1e-5 * rd / (double)nb);
 }
 
 // Block size: 16,384 real samples (lambda <= 2048) when the model above
 // does not find 32,768 faster.  Small applies favour the small blocks (more
-// blocks fill the CUs), large ones with lambda above about 1,000 the large
-// blocks (7/8 valid at lambda = 2,048, against 3/4).
+// blocks fill the CUs), large ones the large blocks (fewer exchanges per
+// sample, and 7/8 valid at lambda = 2,048 against 3/4).
 void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz) {
     hipStream_t s = ctx->stream;
     const int lam = nz->half_bw;

@@ -121,43 +121,6 @@ __device__ __forceinline__ void passes_234(T *__restrict__ sh, T (&re)[16], T (&
     r4_last<T, DIR>(re, im, tw, tid);  // registers now hold X[tid + 1024 q]
 }
 
-// Pair layout of the spectrum step: thread t, slot q < 8 holds k1 = t + 1024 q,
-// slot 8 + q holds k2 = NC - k1; thread 0's k2 for q = 0 is NC/2 instead of 0,
-// so every index appears exactly once.
-__device__ __forceinline__ int pair_k1(int q, int tid) { return tid + BTH * q; }
-__device__ __forceinline__ int pair_k2(int q, int tid) {
-    const int k1 = pair_k1(q, tid);
-    return k1 == 0 ? BNC / 2 : BNC - k1;
-}
-
-// registers X[tid + 1024 q] -> pair layout (one component)
-template <typename T>
-__device__ __forceinline__ void exchange_to_pairs(T *__restrict__ sh, T (&v)[16], int tid) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) sh[padb(tid + BTH * q)] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        v[q] = sh[padb(pair_k1(q, tid))];
-        v[8 + q] = sh[padb(pair_k2(q, tid))];
-    }
-    __syncthreads();
-}
-
-// pair layout -> registers x[tid + 1024 r] (one component)
-template <typename T>
-__device__ __forceinline__ void exchange_from_pairs(T *__restrict__ sh, T (&v)[16], int tid) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        sh[padb(pair_k1(q, tid))] = v[q];
-        sh[padb(pair_k2(q, tid))] = v[8 + q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = sh[padb(tid + BTH * q)];
-    __syncthreads();
-}
-
 // Z'_k from Z_k and its partner Z_{NC-k}.
 template <typename T>
 __device__ __forceinline__ void spectrum_one(T zr, T zi, T pr, T pi,
@@ -171,6 +134,53 @@ __device__ __forceinline__ void spectrum_one(T zr, T zi, T pr, T pi,
     const T sr = a1r - b1i, si = a1i + b1r;                      // W^k O + i W^-k E
     outr = c.x * zr + c.y * sr;
     outi = c.x * zi + c.y * si;
+}
+
+// Spectrum step on registers X[tid + 1024 q]: q < 8 is the lower half of the
+// spectrum (k < NC/2), q >= 8 the upper half.  The upper half goes to LDS, both
+// components.  The owner of each lower k reads its partner NC - k there and
+// computes both outputs of the pair. It keeps Z'_k and writes Z'_{NC-k} over
+// the partner's slot, which no other thread reads. Then every thread reads
+// its upper half back.  Thread 0's q = 0 takes k = 0 and k = NC/2 (slot 0),
+// each paired with itself.  Half the LDS traffic and three barriers, where
+// moving both components to a pair layout and back takes eight.
+template <typename T>
+__device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T (&im)[16],
+                                              const typename Vec2T<T>::type *__restrict__ abf,
+                                              const typename Vec2T<T>::type *__restrict__ twN,
+                                              int tid) {
+    constexpr int H = BNC / 2;
+    T *shr = sh, *shi = sh + H;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        shr[tid + BTH * q] = re[8 + q];
+        shi[tid + BTH * q] = im[8 + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k1 = tid + BTH * q;
+        const bool self = k1 == 0;
+        const int k2 = self ? H : BNC - k1;
+        const int u2 = k2 - H;  // LDS slot of k2
+        const T z1r = re[q], z1i = im[q];
+        const T z2r = shr[u2], z2i = shi[u2];
+        T o1r, o1i, o2r, o2i;
+        spectrum_one<T>(z1r, z1i, self ? z1r : z2r, self ? z1i : z2i, twN[k1], abf[k1], o1r, o1i);
+        spectrum_one<T>(z2r, z2i, self ? z2r : z1r, self ? z2i : z1i, twN[k2], abf[k2], o2r, o2i);
+        shr[u2] = o2r;
+        shi[u2] = o2i;
+        re[q] = o1r;
+        im[q] = o1i;
+        __builtin_amdgcn_sched_barrier(0);  // keep the table loads of one pair at a time
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        re[8 + q] = shr[tid + BTH * q];
+        im[8 + q] = shi[tid + BTH * q];
+    }
+    __syncthreads();
 }
 
 template <typename T>
@@ -202,38 +212,14 @@ __global__ void __launch_bounds__(BTH)
     dft16<T, -1>(re, im);
     passes_234<T, -1>(sh, re, im, tw, tid);
 
-    // spectrum: Z'_k = A_k Z_k + B_k (W^k O_k + i W^-k E_k).  Re-distribute so
-    // thread t owns both members of the pairs (k, NC-k), k = t + 1024 q, q < 8
-    // (thread 0's q = 0 slot pairs 0 and NC/2 with themselves), apply the
-    // spectrum locally, and re-distribute back for the inverse transform.
-    // Each phase below works from its own opaque copy of the thread index, so
-    // the compiler recomputes the (cheap) LDS addresses instead of keeping
-    // the forward half's addresses alive across the whole transform.
+    // spectrum: Z'_k = A_k Z_k + B_k (W^k O_k + i W^-k E_k), with the partner
+    // Z_{NC-k} exchanged through LDS.  Each phase below works from its own
+    // opaque copy of the thread index, so the compiler recomputes the (cheap)
+    // LDS addresses instead of keeping the forward half's addresses alive
+    // across the whole transform.
     int tid_s = tid;
     asm volatile("" : "+v"(tid_s));
-    exchange_to_pairs(sh, re, tid_s);
-    exchange_to_pairs(sh, im, tid_s);
-    {
-        const auto *abf = ab + (int64_t)fid[iv] * BNC;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k1 = pair_k1(q, tid_s), k2 = pair_k2(q, tid_s);
-            const T z1r = re[q], z1i = im[q], z2r = re[8 + q], z2i = im[8 + q];
-            const bool self = k1 == k2 || (tid_s == 0 && q == 0);
-            // member k1 with partner k2 (self-pairs use their own value)
-            T o1r, o1i;
-            spectrum_one<T>(z1r, z1i, self ? z1r : z2r, self ? z1i : z2i, twN[k1], abf[k1], o1r, o1i);
-            T o2r, o2i;
-            spectrum_one<T>(z2r, z2i, self ? z2r : z1r, self ? z2i : z1i, twN[k2], abf[k2], o2r, o2i);
-            re[q] = o1r;
-            im[q] = o1i;
-            re[8 + q] = o2r;
-            im[8 + q] = o2i;
-            __builtin_amdgcn_sched_barrier(0);  // keep the table loads of one pair at a time
-        }
-    }
-    exchange_from_pairs(sh, re, tid_s);
-    exchange_from_pairs(sh, im, tid_s);
+    spectrum_step<T>(sh, re, im, ab + (int64_t)fid[iv] * BNC, twN, tid_s);
 
     // inverse: pass 1 straight from the registers (inputs x[tid + 1024 r])
     int tid_i = tid;
