@@ -431,6 +431,12 @@ extern "C" mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t w
     return MM_OK;
 }
 
+extern "C" mm_status mm_pointing_p_layout(const mm_pointing *p, int32_t *copies) {
+    if (!p || !copies) return MM_E_INVALID;
+    *copies = p->p_j.ptr ? p->p_copies : 0;
+    return MM_OK;
+}
+
 extern "C" mm_status mm_pointing_pt_layout(const mm_pointing *p, int32_t *slices,
                                            int32_t *segments) {
     if (!p || !slices || !segments) return MM_E_INVALID;

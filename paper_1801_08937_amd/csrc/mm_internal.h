@@ -140,11 +140,14 @@ struct mm_pointing {
     int64_t n() const { return (int64_t)nc * n_obs; }
     mm::DBuf hits, obs_pix, j, w, perm, ws, off;
     mm::DBuf psi;  // f64[n_samp] angles (FP64 form only)
-    // Map slots of the single-column FP64 P: with a grid, observed pixels are
-    // numbered in Morton order of (x, y) (p_slot[c]) and p_j[t] is the slot of
-    // sample t's pixel (-1 flagged), so neighbouring pixels share cache lines
-    // whatever the scan direction; without a grid the slot is the compact id.
+    // Map copies of the single-column FP64 P (with a grid): p_copies copies,
+    // one per scan direction found, each ordered by first touch along its
+    // samples.  p_slot[g n_obs + c] is pixel c's slot in copy g (counted over
+    // all copies) and p_j[t] the slot of sample t's pixel in its chunk's copy
+    // (-1 flagged), so the pixels a wave gathers along the scan share cache
+    // lines.  Without a grid the slot is the compact id and there is one copy.
     mm::DBuf p_slot, p_j;
+    int32_t p_copies = 0;
     int32_t max_seg = 0;
     // Order in which P^T visits the compact pixels (empty = ascending).  Each
     // pixel's own sum is independent of it; it only shapes cache locality.

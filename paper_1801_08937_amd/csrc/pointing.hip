@@ -6,7 +6,10 @@
 // bit-exact and independent of scheduling: the histogram uses integer atomics
 // (order does not change a sum of integers); the permutation comes from a
 // stable LSD radix sort of (pixel, time).
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -111,35 +114,87 @@ __global__ void k_tile_keys(const int32_t *__restrict__ obs_pix, int32_t n_obs, 
     vals[c] = c;
 }
 
-// Morton key of an observed pixel's grid position (16 bits per coordinate,
-// interleaved) with its compact id as the value.
-__device__ __forceinline__ uint32_t spread16(uint32_t v) {
-    v &= 0xffff;
-    v = (v | (v << 8)) & 0x00ff00ffu;
-    v = (v | (v << 4)) & 0x0f0f0f0fu;
-    v = (v | (v << 2)) & 0x33333333u;
-    v = (v | (v << 1)) & 0x55555555u;
-    return v;
-}
-__global__ void k_morton_keys(const int32_t *__restrict__ obs_pix, int32_t n_obs, int32_t width,
-                              uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
-    const int32_t c = blockIdx.x * BS + threadIdx.x;
-    if (c >= n_obs) return;
-    const int64_t g = obs_pix[c];
-    const uint32_t x = (uint32_t)(g % width), y = (uint32_t)(g / width);
-    keys[c] = ((uint64_t)(spread16(y) << 1 | spread16(x)) << 32) | (uint32_t)c;
-    vals[c] = c;
-}
 // slot[order[r]] = r
 __global__ void k_rank(const int32_t *__restrict__ order, int32_t n, int32_t *__restrict__ slot) {
     const int32_t r = blockIdx.x * BS + threadIdx.x;
     if (r < n) slot[order[r]] = r;
 }
-__global__ void k_slot_of_sample(const int32_t *__restrict__ j, const int32_t *__restrict__ slot,
-                                 int64_t n, int32_t *__restrict__ pj) {
+// Scan direction of each chunk of DIR_CHUNK consecutive samples: the
+// displacement over DIR_STEP samples, where both ends are observed, at most
+// DIR_MAXD pixels and not zero, votes for one of DIR_BINS angle bins over
+// [0, 180) degrees; the chunk takes the bin with most votes (the lowest on a
+// tie), or -1 without any vote.  Integer counts only, so the result does not
+// depend on scheduling.
+constexpr int DIR_CHUNK = 4096;
+constexpr int DIR_STEP = 8;
+constexpr int DIR_MAXD = 12;
+constexpr int DIR_BINS = 12;
+__global__ void __launch_bounds__(BS) k_chunk_dir(const int32_t *__restrict__ j,
+                                                  const int32_t *__restrict__ obs_pix, int64_t n,
+                                                  int32_t width, int32_t *__restrict__ bin) {
+    __shared__ int cnt[DIR_BINS];
+    if (threadIdx.x < DIR_BINS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * DIR_CHUNK;
+    const int64_t c1 = min(c0 + DIR_CHUNK, n) - DIR_STEP;
+    for (int64_t t = c0 + threadIdx.x; t < c1; t += BS) {
+        const int32_t a = j[t], b = j[t + DIR_STEP];
+        if (a < 0 || b < 0) continue;
+        const int32_t ga = obs_pix[a], gb = obs_pix[b];
+        const int dx = gb % width - ga % width, dy = gb / width - ga / width;
+        if ((dx == 0 && dy == 0) || abs(dx) > DIR_MAXD || abs(dy) > DIR_MAXD) continue;
+        float ang = atan2f((float)dy, (float)dx) * (180.0f / 3.14159265f);
+        if (ang < 0) ang += 180.0f;
+        int k = (int)(ang * (DIR_BINS / 180.0f));
+        k = k < 0 ? 0 : (k >= DIR_BINS ? DIR_BINS - 1 : k);
+        atomicAdd(&cnt[k], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int best = -1, bc = 0;
+        for (int k = 0; k < DIR_BINS; ++k)
+            if (cnt[k] > bc) {
+                bc = cnt[k];
+                best = k;
+            }
+        bin[blockIdx.x] = best;
+    }
+}
+
+// First sample of each copy's samples that hits each pixel:
+// first[g n_obs + c] = min t over samples t of copy g with pixel c.
+__global__ void k_first_touch(const int32_t *__restrict__ j, const int32_t *__restrict__ grp,
+                              int64_t n, int32_t n_obs,
+                              unsigned long long *__restrict__ first) {
     for (int64_t t = blockIdx.x * (int64_t)BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
         const int32_t c = j[t];
-        pj[t] = c >= 0 ? slot[c] : -1;
+        if (c < 0) continue;
+        const int64_t g = grp[t / DIR_CHUNK];
+        atomicMin(&first[g * n_obs + c], (unsigned long long)t);
+    }
+}
+
+// Sort keys: copy in the top byte, then the first touch (unhit pixels last,
+// in compact id order through the stable sort); value = g n_obs + c.
+__global__ void k_touch_keys(const unsigned long long *__restrict__ first, int64_t total,
+                             int32_t n_obs, uint64_t *__restrict__ keys,
+                             int32_t *__restrict__ vals) {
+    for (int64_t e = blockIdx.x * (int64_t)BS + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * BS) {
+        const uint64_t g = (uint64_t)(e / n_obs);
+        const uint64_t f = first[e];
+        keys[e] = (g << 56) | (f < (1ull << 56) ? f : (1ull << 56) - 1);
+        vals[e] = (int32_t)e;
+    }
+}
+
+// p_j[t] = slot of sample t's pixel in its chunk's copy (-1 flagged).
+__global__ void k_slot_of_sample_g(const int32_t *__restrict__ j, const int32_t *__restrict__ grp,
+                                   const int32_t *__restrict__ slot, int64_t n, int32_t n_obs,
+                                   int32_t *__restrict__ pj) {
+    for (int64_t t = blockIdx.x * (int64_t)BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+        const int32_t c = j[t];
+        pj[t] = c >= 0 ? slot[(int64_t)grp[t / DIR_CHUNK] * n_obs + c] : -1;
     }
 }
 
@@ -245,37 +300,112 @@ int grid_for(int64_t n, int max_blocks = 8192) {
 
 }  // namespace
 
-// Map slots of the FP64 P in Morton order of the grid (width > 0), or none.
+// Map copies of the single-column FP64 P (width > 0), or none.  The lanes of
+// a wave gather the map at consecutive samples, i.e. along the scan, so the
+// gather touches few cache lines when pixels met one after the other along
+// the scan sit next to each other in memory.  One order cannot do that for
+// several scan directions, so the map is kept in up to MAX_COPIES copies,
+// one per scan direction found (chunks of samples voting by their
+// displacement), each ordered by the first sample of its chunks that hits
+// each pixel.  The values gathered, hence P's output, do not depend on it.
+constexpr int MAX_COPIES = 4;
+
 void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     hipStream_t s = ctx->stream;
     p->p_slot.release();
     p->p_j.release();
+    p->p_copies = 0;
     const int32_t n_obs = p->n_obs;
     if (width <= 0 || n_obs == 0 || p->prec != MM_F64 || p->nc != 3) return;
-    DBuf keys, vals, ko, order, tmp;
-    keys.alloc(sizeof(uint64_t) * n_obs);
-    vals.alloc(sizeof(int32_t) * n_obs);
-    ko.alloc(sizeof(uint64_t) * n_obs);
-    order.alloc(sizeof(int32_t) * n_obs);
-    k_morton_keys<<<(n_obs + BS - 1) / BS, BS, 0, s>>>(p->obs_pix.as<int32_t>(), n_obs, width,
-                                                       keys.as<uint64_t>(), vals.as<int32_t>());
+    const int64_t n = p->n_samp;
+    const int64_t n_chunks = (n + DIR_CHUNK - 1) / DIR_CHUNK;
+    DBuf dbin;
+    dbin.alloc(sizeof(int32_t) * n_chunks);
+    k_chunk_dir<<<(unsigned)n_chunks, BS, 0, s>>>(p->j.as<int32_t>(), p->obs_pix.as<int32_t>(), n,
+                                                  width, dbin.as<int32_t>());
+    MM_HIP(hipGetLastError());
+    std::vector<int32_t> bin(n_chunks);
+    MM_HIP(hipMemcpyAsync(bin.data(), dbin.ptr, sizeof(int32_t) * n_chunks,
+                          hipMemcpyDeviceToHost, s));
+    MM_HIP(hipStreamSynchronize(s));
+    // directions holding at least 1/16 of the directed chunks, most first; a
+    // bin next to a kept one is not kept (a direction on a bin boundary
+    // splits its chunks between two bins)
+    int64_t cnt[DIR_BINS] = {};
+    int64_t directed = 0;
+    for (int32_t b : bin)
+        if (b >= 0) {
+            ++cnt[b];
+            ++directed;
+        }
+    std::vector<int> kept;
+    {
+        std::vector<int> byc(DIR_BINS);
+        for (int k = 0; k < DIR_BINS; ++k) byc[k] = k;
+        std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+        for (int k : byc) {
+            if (cnt[k] == 0 || cnt[k] * 16 < directed || (int)kept.size() == MAX_COPIES) continue;
+            bool near = false;
+            for (int q : kept) {
+                const int d = std::abs(k - q);
+                near |= std::min(d, DIR_BINS - d) <= 1;
+            }
+            if (!near) kept.push_back(k);
+        }
+    }
+    int G = kept.empty() ? 1 : (int)kept.size();
+    if ((int64_t)G * n_obs >= (int64_t)1 << 31) G = 1;
+    // each chunk to the copy of the nearest kept direction (angles mod 180),
+    // undirected chunks to the most common one
+    std::vector<int32_t> grp(n_chunks, 0);
+    if (G > 1)
+        for (int64_t c = 0; c < n_chunks; ++c) {
+            if (bin[c] < 0) continue;
+            int bg = 0, bd = DIR_BINS;
+            for (int g = 0; g < G; ++g) {
+                int d = std::abs(bin[c] - kept[g]);
+                d = std::min(d, DIR_BINS - d);
+                if (d < bd) {
+                    bd = d;
+                    bg = g;
+                }
+            }
+            grp[c] = bg;
+        }
+    DBuf dgrp, first, keys, vals, ko, order, tmp;
+    dgrp.alloc(sizeof(int32_t) * n_chunks);
+    MM_HIP(hipMemcpyAsync(dgrp.ptr, grp.data(), sizeof(int32_t) * n_chunks,
+                          hipMemcpyHostToDevice, s));
+    const int64_t total = (int64_t)G * n_obs;
+    first.alloc(sizeof(unsigned long long) * total);
+    MM_HIP(hipMemsetAsync(first.ptr, 0xff, sizeof(unsigned long long) * total, s));
+    k_first_touch<<<grid_for(n), BS, 0, s>>>(p->j.as<int32_t>(), dgrp.as<int32_t>(), n, n_obs,
+                                             first.as<unsigned long long>());
+    keys.alloc(sizeof(uint64_t) * total);
+    vals.alloc(sizeof(int32_t) * total);
+    ko.alloc(sizeof(uint64_t) * total);
+    order.alloc(sizeof(int32_t) * total);
+    k_touch_keys<<<grid_for(total), BS, 0, s>>>(first.as<unsigned long long>(), total, n_obs,
+                                                keys.as<uint64_t>(), vals.as<int32_t>());
     size_t tb = 0;
     MM_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
-                                     vals.as<int32_t>(), order.as<int32_t>(), (size_t)n_obs, 0u,
+                                     vals.as<int32_t>(), order.as<int32_t>(), (size_t)total, 0u,
                                      64u, s));
     tmp.alloc(tb + 16);
     MM_HIP(rocprim::radix_sort_pairs(tmp.ptr, tb, keys.as<uint64_t>(), ko.as<uint64_t>(),
-                                     vals.as<int32_t>(), order.as<int32_t>(), (size_t)n_obs, 0u,
+                                     vals.as<int32_t>(), order.as<int32_t>(), (size_t)total, 0u,
                                      64u, s));
-    p->p_slot.alloc(sizeof(int32_t) * n_obs);
-    k_rank<<<(n_obs + BS - 1) / BS, BS, 0, s>>>(order.as<int32_t>(), n_obs,
-                                                p->p_slot.as<int32_t>());
-    p->p_j.alloc(sizeof(int32_t) * p->n_samp);
-    k_slot_of_sample<<<grid_for(p->n_samp), BS, 0, s>>>(p->j.as<int32_t>(),
-                                                        p->p_slot.as<int32_t>(), p->n_samp,
-                                                        p->p_j.as<int32_t>());
+    // copy g's slots are [g n_obs, (g + 1) n_obs): the key's top byte is g
+    p->p_slot.alloc(sizeof(int32_t) * total);
+    k_rank<<<(unsigned)((total + BS - 1) / BS), BS, 0, s>>>(order.as<int32_t>(), (int32_t)total,
+                                                           p->p_slot.as<int32_t>());
+    p->p_j.alloc(sizeof(int32_t) * n);
+    k_slot_of_sample_g<<<grid_for(n), BS, 0, s>>>(p->j.as<int32_t>(), dgrp.as<int32_t>(),
+                                                  p->p_slot.as<int32_t>(), n, n_obs,
+                                                  p->p_j.as<int32_t>());
     MM_HIP(hipGetLastError());
     MM_HIP(hipStreamSynchronize(s));
+    p->p_copies = G;
 }
 
 void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_t tile) {

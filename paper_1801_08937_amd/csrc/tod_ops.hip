@@ -110,16 +110,22 @@ __global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpi
 // bytes) per slot; with a grid the slots follow Morton order, so the pixels
 // of 64 consecutive samples fall in few cache lines whatever the scan
 // direction.  Same arithmetic and order as k_apply_P (bitwise the same y).
+// Split map for P: I in xi, (Q, U) in xqu, at each of the n_copies slots of
+// every pixel (slot = NULL: one copy at the compact id).
 __global__ void __launch_bounds__(BS) k_pack_map_split(const double *__restrict__ x,
-                                                       int32_t n_obs,
+                                                       int32_t n_obs, int n_copies,
                                                        const int32_t *__restrict__ slot,
                                                        double *__restrict__ xi,
                                                        double2 *__restrict__ xqu) {
     for (int64_t c = (int64_t)blockIdx.x * BS + threadIdx.x; c < n_obs;
          c += (int64_t)gridDim.x * BS) {
-        const int64_t s = slot ? slot[c] : c;
-        xi[s] = x[3 * c];
-        xqu[s] = make_double2(x[3 * c + 1], x[3 * c + 2]);
+        const double vi = x[3 * c];
+        const double2 vqu = make_double2(x[3 * c + 1], x[3 * c + 2]);
+        for (int g = 0; g < n_copies; ++g) {
+            const int64_t s = slot ? slot[(int64_t)g * n_obs + c] : c;
+            xi[s] = vi;
+            xqu[s] = vqu;
+        }
     }
 }
 
@@ -531,7 +537,9 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
         return;
     }
     if (nrhs == 1) {
-        const size_t no = (size_t)(p->n_obs > 0 ? p->n_obs : 1);
+        const bool slots = p->p_j.ptr != nullptr;
+        const int copies = slots ? p->p_copies : 1;
+        const size_t no = (size_t)(p->n_obs > 0 ? p->n_obs : 1) * copies;
         ws_alloc(ctx, ctx->xpack, sizeof(double2) * 2 * no);
         const int tuned = p->p_blocks[0];
         if (p->prec == MM_F32) {
@@ -542,12 +550,11 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
                                                             n, ctx->xpack.as<double2>(),
                                                             static_cast<float *>(y));
         } else {
-            // xpack holds I (n_obs doubles) then (Q, U) (n_obs double2)
+            // xpack holds I (no doubles) then (Q, U) (no double2), no = n_obs x copies
             double *xi = ctx->xpack.as<double>();
             double2 *xqu = reinterpret_cast<double2 *>(xi + 2 * ((no + 1) / 2));
-            const bool slots = p->p_j.ptr != nullptr;
             k_pack_map_split<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(
-                x, p->n_obs, slots ? p->p_slot.as<int32_t>() : nullptr, xi, xqu);
+                x, p->n_obs, copies, slots ? p->p_slot.as<int32_t>() : nullptr, xi, xqu);
             const int grid = tuned > 0 ? tuned : grid_for(n, 32 * ctx->n_cu * 4);
             k_apply_P1_psi<<<grid, BS, 0, ctx->stream>>>(
                 slots ? p->p_j.as<int32_t>() : p->j.as<int32_t>(), p->psi.as<double>(), n, xi, xqu,

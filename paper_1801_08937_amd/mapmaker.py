@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
             "mm_pair_sum_diff": (C.c_int, [P, I64, C.c_int, P, P, P, P]),
             "mm_pointing_counts": (C.c_int, [P, C.POINTER(I32), C.POINTER(I64)]),
             "mm_pointing_pt_layout": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32)]),
+            "mm_pointing_p_layout": (C.c_int, [P, C.POINTER(I32)]),
             "mm_pointing_set_grid": (C.c_int, [P, P, I32]),
             "mm_pointing_hits": (C.c_int, [P, P, P, P]),
             "mm_pointing_export": (C.c_int, [P, P, P, P, P]),
@@ -484,6 +485,12 @@ class Pointing(_Handle):
         """Locality hint: global ids are row-major with `width` columns."""
         self.ctx._check(lib().mm_pointing_set_grid(self.ctx.h, self.h, width),
                         "mm_pointing_set_grid")
+
+    def p_copies(self) -> int:
+        """Map copies the single-column FP64 P gathers from (0 = no grid)."""
+        g = C.c_int32(0)
+        lib().mm_pointing_p_layout(self.h, C.byref(g))
+        return g.value
 
     def pt_layout(self):
         """(slices, segments) of the sliced single-column P^T; (0, 0) when the

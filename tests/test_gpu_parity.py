@@ -453,6 +453,39 @@ def test_PT_tiled_order_bitwise_and_parity(ctx, case):
     assert maxrel(host(b), O.apply_PT(op, host(y))) <= TOL_OP
 
 
+@pytest.mark.parametrize("case", range(3))
+def test_P_map_copies_bitwise_and_parity(ctx, case):
+    """With the grid hint the FP64 P gathers from one map copy per scan
+    direction (cross-linked rasters at 0, 60 and 120 degrees: three), each in
+    first-touch order along its samples.  P and A are bitwise those without
+    the hint, and match the oracle."""
+    import torch
+    if case < 2:
+        p = _problems()[case]
+    else:
+        p = synth.config2(n_side=64, grid=(4, 2), samp_per_det=1 << 14, L=1 << 12, half_bw=50)
+    lp, ln, op, on = build_both(ctx, p, method=1)
+    x = dev(np.random.default_rng(20 + case).standard_normal(op.n))
+    assert lp.p_copies() == 0
+    y0 = ctx.apply_P(lp, x)
+    a0 = ctx.apply_A(lp, ln, x)
+    lp.set_grid(p.n_side)
+    copies = lp.p_copies()
+    assert 1 <= copies <= 4
+    if case == 2:
+        assert copies == 3
+    y1 = ctx.apply_P(lp, x)
+    a1 = ctx.apply_A(lp, ln, x)
+    assert torch.equal(y0, y1) and torch.equal(a0, a1)
+    assert maxrel(host(y1), O.apply_P(op, host(x))) <= TOL_OP
+    # twice in a row (the packed copies are rewritten each call), then no hint
+    x2 = dev(np.random.default_rng(30 + case).standard_normal(op.n))
+    y2 = ctx.apply_P(lp, x2)
+    lp.set_grid(0)
+    assert lp.p_copies() == 0
+    assert torch.equal(y2, ctx.apply_P(lp, x2))
+
+
 def test_A_fft_tiled_config2_shape(ctx):
     """A = P^T N^-1 P with the FFT form of N^-1 and the tiled P^T order on a
     2^21-sample cross-linked scan."""
