@@ -143,16 +143,16 @@ mm_status mm_pair_sum_diff(mm_ctx *ctx, int64_t n, mm_precision prec, const void
  * pixels of that grid (32 x 32 tiles in the one-wave-per-pixel form, 8 x 8
  * blocks in the sliced single-column form), so the pixels reduced together
  * are hit by the same stretches of the scan and share cache lines.  The
- * single-column FP64 IQU P gathers from up to 4 copies of the map, one per
- * scan direction found in the samples (chunks of 4,096 samples vote by
- * their displacement over 8 samples), each ordered by the first sample of
- * its chunks that hits each pixel, so the lanes of a wave, which take
- * consecutive samples along the scan, read few cache lines.  Every pixel's
+ * single-column IQU P (FP64 and FP32) gathers from up to 4 copies of the
+ * map, one per scan direction found in the samples (chunks of 4,096 samples
+ * vote by their displacement over 8 samples), each ordered by the first
+ * sample of its chunks that hits each pixel, so the lanes of a wave, which
+ * take consecutive samples along the scan, read few cache lines.  Every pixel's
  * sum keeps its order and P gathers the same values, so results are bitwise
  * unchanged.  width = 0 restores ascending order and one map copy.
  * Errors: MM_E_INVALID (negative width). */
 mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t width);
-/* Map copies the single-column FP64 P gathers from: 0 without a grid (one
+/* Map copies the single-column IQU P gathers from: 0 without a grid (one
  * copy in compact id order), else 1 to 4.  [host] output. */
 mm_status mm_pointing_p_layout(const mm_pointing *p, int32_t *copies);
 /* n_obs (observed pixels) and n_valid (unflagged samples).  [host] outputs. */

@@ -140,7 +140,7 @@ struct mm_pointing {
     int64_t n() const { return (int64_t)nc * n_obs; }
     mm::DBuf hits, obs_pix, j, w, perm, ws, off;
     mm::DBuf psi;  // f64[n_samp] angles (FP64 form only)
-    // Map copies of the single-column FP64 P (with a grid): p_copies copies,
+    // Map copies of the single-column IQU P (with a grid): p_copies copies,
     // one per scan direction found, each ordered by first touch along its
     // samples.  p_slot[g n_obs + c] is pixel c's slot in copy g (counted over
     // all copies) and p_j[t] the slot of sample t's pixel in its chunk's copy

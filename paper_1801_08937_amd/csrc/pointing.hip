@@ -300,7 +300,7 @@ int grid_for(int64_t n, int max_blocks = 8192) {
 
 }  // namespace
 
-// Map copies of the single-column FP64 P (width > 0), or none.  The lanes of
+// Map copies of the single-column IQU P (width > 0), or none.  The lanes of
 // a wave gather the map at consecutive samples, i.e. along the scan, so the
 // gather touches few cache lines when pixels met one after the other along
 // the scan sit next to each other in memory.  One order cannot do that for
@@ -316,7 +316,7 @@ void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     p->p_j.release();
     p->p_copies = 0;
     const int32_t n_obs = p->n_obs;
-    if (width <= 0 || n_obs == 0 || p->prec != MM_F64 || p->nc != 3) return;
+    if (width <= 0 || n_obs == 0 || p->nc != 3) return;
     const int64_t n = p->n_samp;
     const int64_t n_chunks = (n + DIR_CHUNK - 1) / DIR_CHUNK;
     DBuf dbin;

@@ -65,12 +65,20 @@ __global__ void __launch_bounds__(BS) k_apply_P(const int32_t *__restrict__ jpix
 // Single column: the map is first packed as 32-byte records (I, Q, U, 0) so
 // each sample's gather is two aligned 16-byte loads instead of three 8-byte
 // ones.
+// 32-byte records (I, Q, U, 0) at each of the n_copies slots of every pixel
+// (slot = NULL: one copy at the compact id).
 __global__ void __launch_bounds__(BS) k_pack_map(const double *__restrict__ x, int32_t n_obs,
+                                                 int n_copies, const int32_t *__restrict__ slot,
                                                  double2 *__restrict__ x4) {
     for (int64_t j = (int64_t)blockIdx.x * BS + threadIdx.x; j < n_obs;
          j += (int64_t)gridDim.x * BS) {
-        x4[2 * j] = make_double2(x[3 * j], x[3 * j + 1]);
-        x4[2 * j + 1] = make_double2(x[3 * j + 2], 0.0);
+        const double2 iq = make_double2(x[3 * j], x[3 * j + 1]);
+        const double2 u0 = make_double2(x[3 * j + 2], 0.0);
+        for (int g = 0; g < n_copies; ++g) {
+            const int64_t s = slot ? slot[(int64_t)g * n_obs + j] : j;
+            x4[2 * s] = iq;
+            x4[2 * s + 1] = u0;
+        }
     }
 }
 
@@ -544,11 +552,12 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
         const int tuned = p->p_blocks[0];
         if (p->prec == MM_F32) {
             k_pack_map<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(
-                x, p->n_obs, ctx->xpack.as<double2>());
+                x, p->n_obs, copies, slots ? p->p_slot.as<int32_t>() : nullptr,
+                ctx->xpack.as<double2>());
             const int grid = tuned > 0 ? tuned : grid_for(n, 8 * ctx->n_cu * 4);
-            k_apply_P1<float><<<grid, BS, 0, ctx->stream>>>(p->j.as<int32_t>(), p->w.as<float2>(),
-                                                            n, ctx->xpack.as<double2>(),
-                                                            static_cast<float *>(y));
+            k_apply_P1<float><<<grid, BS, 0, ctx->stream>>>(
+                slots ? p->p_j.as<int32_t>() : p->j.as<int32_t>(), p->w.as<float2>(), n,
+                ctx->xpack.as<double2>(), static_cast<float *>(y));
         } else {
             // xpack holds I (no doubles) then (Q, U) (no double2), no = n_obs x copies
             double *xi = ctx->xpack.as<double>();

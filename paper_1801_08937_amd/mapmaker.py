@@ -487,7 +487,7 @@ class Pointing(_Handle):
                         "mm_pointing_set_grid")
 
     def p_copies(self) -> int:
-        """Map copies the single-column FP64 P gathers from (0 = no grid)."""
+        """Map copies the single-column IQU P gathers from (0 = no grid)."""
         g = C.c_int32(0)
         lib().mm_pointing_p_layout(self.h, C.byref(g))
         return g.value

@@ -484,6 +484,13 @@ def test_P_map_copies_bitwise_and_parity(ctx, case):
     lp.set_grid(0)
     assert lp.p_copies() == 0
     assert torch.equal(y2, ctx.apply_P(lp, x2))
+    # FP32 form: the same copies, FP32 output bitwise unchanged
+    lp32 = ctx.pointing(dev(p.pix), dev(p.psi), p.n_pix_total, p.min_hits, 1)
+    z0 = ctx.apply_P(lp32, x)
+    lp32.set_grid(p.n_side)
+    assert lp32.p_copies() == copies
+    assert torch.equal(z0, ctx.apply_P(lp32, x))
+    assert rel(host(z0), O.apply_P(op, host(x))) <= 1e-6
 
 
 def test_A_fft_tiled_config2_shape(ctx):
