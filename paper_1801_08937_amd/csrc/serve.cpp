@@ -183,13 +183,15 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
     MM_CHECK(n_samp > 0 && n_pix_total > 0 && n_intervals > 0, MM_E_INVALID,
              "server: bad strategy sizes");
     // footprint: pointing (index, weights, permutation, sorted weights; the
-    // FP64 form also keeps the angles), the sliced P^T layout (index and
-    // angle or weights per entry, ~10 % padding), two TOD workspaces of
+    // FP64 form also keeps the angles; with a grid, P's map-copy slot per
+    // sample), the sliced P^T layout (index and angle or weights per entry,
+    // ~10 % padding), two TOD workspaces of
     // `slots` columns plus the single-column ones of the M_2l build, two
     // sessions' vectors, M_2l (Z, AZ, W basis)
     const int64_t te = prec == MM_F32 ? 4 : 8;
     const int64_t est_n = 3 * (int64_t)std::min<int64_t>(n_pix_total, n_samp);
-    const int64_t per_samp = 4 + 2 * 2 * te + 4 + (prec == MM_F32 ? 0 : 8) + 14;
+    const int64_t per_samp =
+        4 + 2 * 2 * te + 4 + (prec == MM_F32 ? 0 : 8) + 14 + (grid_width > 0 ? 4 : 0);
     const int64_t bytes = n_samp * per_samp + 2 * n_samp * te * (srv->slots + 1) +
                           est_n * 8 * (14 * srv->slots + 2 * srv->defl_k + srv->m_max + 2);
     if (srv->used + bytes > srv->budget)
