@@ -139,17 +139,24 @@ mm_status mm_pointing_stokes(const mm_pointing *p, mm_stokes *stokes, int32_t *n
 mm_status mm_pair_sum_diff(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a,
                            const void *b, void *plus, void *minus);
 /* Optional locality hint: the global pixel ids are row-major on a grid of
- * `width` columns (id = row * width + column).  P^T then groups neighbouring
- * pixels of that grid (32 x 32 tiles in the one-wave-per-pixel form, 8 x 8
- * blocks in the sliced single-column form), so the pixels reduced together
- * are hit by the same stretches of the scan and share cache lines.  The
+ * `width` columns (id = row * width + column).  The one-wave-per-pixel P^T
+ * then visits the pixels in 32 x 32 tiles of that grid, so the pixels reduced
+ * together are hit by the same stretches of the scan and share cache lines.
+ * The
  * single-column IQU P (FP64 and FP32) gathers from up to 4 copies of the
  * map, one per scan direction found in the samples (chunks of 4,096 samples
  * vote by their displacement over 8 samples), each ordered by the first
  * sample of its chunks that hits each pixel, so the lanes of a wave, which
- * take consecutive samples along the scan, read few cache lines.  Every pixel's
- * sum keeps its order and P gathers the same values, so results are bitwise
- * unchanged.  width = 0 restores ascending order and one map copy.
+ * take consecutive samples along the scan, read few cache lines.  The
+ * sliced single-column P^T is then cut by the same directions: each
+ * direction's slices take 64 pixels in that copy's order, a lane sums its
+ * pixel's samples of that direction in time order per segment, and the
+ * (segment, direction) partial maps are added in a fixed order.  P gathers
+ * the same values, so P is bitwise unchanged; with one direction (or
+ * without the sliced form) P^T and A are bitwise unchanged too; with
+ * several, P^T sums each pixel's samples in another fixed order: bitwise
+ * repeatable, equal to the unhinted result to rounding.  width = 0
+ * restores ascending order and one map copy.
  * Errors: MM_E_INVALID (negative width). */
 mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t width);
 /* Map copies the single-column IQU P gathers from: 0 without a grid (one
@@ -158,11 +165,13 @@ mm_status mm_pointing_p_layout(const mm_pointing *p, int32_t *copies);
 /* n_obs (observed pixels) and n_valid (unflagged samples).  [host] outputs. */
 mm_status mm_pointing_counts(const mm_pointing *p, int32_t *n_obs, int64_t *n_valid);
 /* Execution layout of the single-column P^T (Eq. mapmaking's P^T as a
- * pixel-sorted reduction): *slices = pixel slices of 64 and *segments = time
+ * pixel-sorted reduction): *slices = pixel slices of 64 (over all scan
+ * directions when the grid hint cuts them by direction) and *segments = time
  * segments of the sliced form, both 0 when the problem is small enough for
  * the one-wave-per-pixel form.  Each pixel sums its samples in time order
- * within a segment, then the segments in order; the layout is a function of
- * n_obs and n_valid only, never of the device.  [host] outputs. */
+ * within a segment (and scan direction), then those partial sums in order;
+ * the layout is a function of the pointing (n_obs, n_valid, the directions
+ * found), never of the device.  [host] outputs. */
 mm_status mm_pointing_pt_layout(const mm_pointing *p, int32_t *slices, int32_t *segments);
 /* Hit counts per global pixel and the observed pixels' global ids.
  *   hits [device] int32[n_pix_total]; obs_pix [device] int32[n_obs] (either may be NULL) */

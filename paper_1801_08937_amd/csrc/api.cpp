@@ -425,8 +425,9 @@ extern "C" mm_status mm_pointing_set_grid(mm_ctx *ctx, mm_pointing *p, int32_t w
         pointing_set_grid_device(ctx, p, width, 32);
         p->grid_width = width;
     }
-    pointing_slices_device(ctx, p, width);
+    // P's map copies first: the sliced P^T is cut by the same scan directions
     pointing_p_slots_device(ctx, p, width);
+    pointing_slices_device(ctx, p, width);
     API_END
     return MM_OK;
 }

@@ -148,6 +148,7 @@ struct mm_pointing {
     // lines.  Without a grid the slot is the compact id and there is one copy.
     mm::DBuf p_slot, p_j;
     int32_t p_copies = 0;
+    mm::DBuf p_chunk_grp;  // int32 copy (scan direction) of each 4,096-sample chunk
     int32_t max_seg = 0;
     // Order in which P^T visits the compact pixels (empty = ascending).  Each
     // pixel's own sum is independent of it; it only shapes cache locality.
@@ -159,7 +160,12 @@ struct mm_pointing {
     // sl_S equal time segments.  Wave (s, g) walks its lanes' entries of
     // segment s in time order from sl_perm / sl_w, stored interleaved (entry k
     // of lane l at sl_base[s G + g] + 64 k + l, padding t = -1, w = 0).
-    int32_t sl_G = 0, sl_S = 0;
+    // With map copies (grid hint) the slices are cut per scan direction d:
+    // lane pixels are virtual ids v = d n_obs + c in copy d's first-touch
+    // order, each walking only its pixel's samples of direction d, so sl_G
+    // counts sl_D direction blocks of slices and wave (s, g) writes partial
+    // map s sl_D + g / (sl_G / sl_D).
+    int32_t sl_G = 0, sl_S = 0, sl_D = 1;
     mm::DBuf sl_pix;   // int32[G * 64] compact pixel per lane, -1 past n_obs
     mm::DBuf sl_base;  // int64[G * S + 1] entry offsets, segment-major
     mm::DBuf sl_perm;  // int32 sample index per entry

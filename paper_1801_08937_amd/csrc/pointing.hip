@@ -201,6 +201,48 @@ __global__ void k_slot_of_sample_g(const int32_t *__restrict__ j, const int32_t 
 // Sliced P^T layout.  Lane (g, l) finds, by binary search in its pixel's
 // time-sorted list perm[off[c], off[c+1]), where each time segment
 // [n s / S, n (s+1) / S) starts; cnt / start are stored per (s G + g, l).
+// Sliced P^T per scan direction.  Sort keys of the pixel-sorted samples by
+// their chunk's direction (a stable sort keeps pixel, then time, order inside
+// each direction), the sample counts of every virtual pixel d n_obs + c, and
+// the lane pixels: copy d's first-touch order of the pixels, a block of G
+// slices per direction.
+__global__ void k_perm_dir_keys(const int32_t *__restrict__ perm, int64_t n_valid,
+                                const int32_t *__restrict__ grp, uint32_t *__restrict__ keys,
+                                int32_t *__restrict__ vals) {
+    for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n_valid;
+         i += (int64_t)gridDim.x * BS) {
+        keys[i] = (uint32_t)grp[perm[i] / DIR_CHUNK];
+        vals[i] = (int32_t)i;
+    }
+}
+__global__ void k_dir_counts(const int32_t *__restrict__ j, const int32_t *__restrict__ grp,
+                             int64_t n, int32_t n_obs, int32_t *__restrict__ cnt) {
+    for (int64_t t = blockIdx.x * (int64_t)BS + threadIdx.x; t < n; t += (int64_t)gridDim.x * BS) {
+        const int32_t c = j[t];
+        if (c >= 0) atomicAdd(&cnt[(int64_t)grp[t / DIR_CHUNK] * n_obs + c], 1);
+    }
+}
+template <typename V>
+__global__ void k_perm_gather(const int32_t *__restrict__ idx, const int32_t *__restrict__ perm,
+                              const V *__restrict__ w, int64_t n_valid,
+                              int32_t *__restrict__ perm2, V *__restrict__ w2) {
+    for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n_valid;
+         i += (int64_t)gridDim.x * BS) {
+        const int32_t k = idx[i];
+        perm2[i] = perm[k];
+        if (w) w2[i] = w[k];
+    }
+}
+__global__ void k_sl_pix_dir(const int32_t *__restrict__ slot, int64_t total, int32_t n_obs,
+                             int32_t G, int32_t *__restrict__ sl_pix) {
+    for (int64_t v = blockIdx.x * (int64_t)BS + threadIdx.x; v < total;
+         v += (int64_t)gridDim.x * BS) {
+        const int64_t d = v / n_obs;
+        const int64_t r = slot[v] - d * n_obs;  // rank in copy d
+        sl_pix[d * G * 64 + r] = (int32_t)v;
+    }
+}
+
 __global__ void k_sl_bounds(const int32_t *__restrict__ sl_pix, int32_t G, int32_t S,
                             int64_t n_samp, const int32_t *__restrict__ off,
                             const int32_t *__restrict__ perm, int32_t *__restrict__ cnt,
@@ -314,6 +356,7 @@ void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     hipStream_t s = ctx->stream;
     p->p_slot.release();
     p->p_j.release();
+    p->p_chunk_grp.release();
     p->p_copies = 0;
     const int32_t n_obs = p->n_obs;
     if (width <= 0 || n_obs == 0 || p->nc != 3) return;
@@ -372,7 +415,8 @@ void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
             }
             grp[c] = bg;
         }
-    DBuf dgrp, first, keys, vals, ko, order, tmp;
+    DBuf first, keys, vals, ko, order, tmp;
+    DBuf &dgrp = p->p_chunk_grp;
     dgrp.alloc(sizeof(int32_t) * n_chunks);
     MM_HIP(hipMemcpyAsync(dgrp.ptr, grp.data(), sizeof(int32_t) * n_chunks,
                           hipMemcpyHostToDevice, s));
@@ -434,14 +478,15 @@ void pointing_set_grid_device(mm_ctx *ctx, mm_pointing *p, int32_t width, int32_
 // the device (8,192 = 32 per CU on 256 CUs), and at least one segment per 2^22
 // samples of time, so that the stretch of the TOD the resident waves gather from at
 // any moment stays small enough for the L2 (at 1.34e8 samples: 32 segments,
-// measured best among 8..128); at most 64, and at least 32 entries per lane
-// and segment on average.  A function of the problem size only, so the
+// measured best among 8..128); at most 64, and at least 32 entries per lane,
+// segment and scan direction on average.  A function of the problem size only, so the
 // summation order (and the bits of the result) does not depend on the device.
-static int32_t slice_segments(int64_t n_samp, int64_t n_valid, int32_t n_obs, int32_t G) {
+static int32_t slice_segments(int64_t n_samp, int64_t n_valid, int32_t n_obs, int32_t G,
+                              int32_t D) {
     int64_t S = 8192 / G;
     if (S < (n_samp >> 22)) S = n_samp >> 22;
     if (S > 64) S = 64;
-    const int64_t cap = n_obs > 0 ? n_valid / n_obs / 32 : 0;
+    const int64_t cap = n_obs > 0 ? n_valid / n_obs / 32 / D : 0;
     if (S > cap) S = cap;
     return (int32_t)(S < 1 ? 1 : S);
 }
@@ -449,6 +494,7 @@ static int32_t slice_segments(int64_t n_samp, int64_t n_valid, int32_t n_obs, in
 void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     hipStream_t s = ctx->stream;
     p->sl_G = p->sl_S = 0;
+    p->sl_D = 1;
     p->sl_pix.release();
     p->sl_base.release();
     p->sl_perm.release();
@@ -456,14 +502,78 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     const int32_t n_obs = p->n_obs;
     // IQU only: the I and QU pointings reduce with the one-wave-per-pixel form
     if (n_obs == 0 || p->n_valid == 0 || p->nc != 3) return;
-    const int32_t G = (n_obs + 63) / 64;
-    const int32_t S = slice_segments(p->n_samp, p->n_valid, n_obs, G);
+    const int32_t G0 = (n_obs + 63) / 64;
     // below ~2,048 waves the one-wave-per-pixel kernel is the faster one
-    if ((int64_t)G * S < 2048) return;
+    if ((int64_t)G0 * slice_segments(p->n_samp, p->n_valid, n_obs, G0, 1) < 2048) return;
+    // per scan direction when the map copies of P are there
+    const bool dirs = width > 0 && p->p_copies > 0 && p->p_chunk_grp.ptr;
+    const int32_t D = dirs ? p->p_copies : 1;
+    const int32_t S = slice_segments(p->n_samp, p->n_valid, n_obs, G0, D);
+    const int32_t G = G0 * D;
+    const int64_t nv = p->n_valid;
+    const bool f32 = p->prec == MM_F32;
+    // the pixel-sorted samples and their CSR offsets, over virtual pixels
+    // d n_obs + c when cut by direction
+    const int32_t *perm_u = p->perm.as<int32_t>();
+    const int32_t *off_u = p->off.as<int32_t>();
+    const void *ws_u = f32 ? p->ws.ptr : nullptr;
+    DBuf perm2, off2, ws2;
+    if (dirs && D > 1) {
+        DBuf keys, vals, ko, idx, cnt2, tmp;
+        keys.alloc(sizeof(uint32_t) * nv);
+        vals.alloc(sizeof(int32_t) * nv);
+        ko.alloc(sizeof(uint32_t) * nv);
+        idx.alloc(sizeof(int32_t) * nv);
+        k_perm_dir_keys<<<grid_for(nv), BS, 0, s>>>(perm_u, nv, p->p_chunk_grp.as<int32_t>(),
+                                                   keys.as<uint32_t>(), vals.as<int32_t>());
+        size_t tb = 0;
+        MM_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys.as<uint32_t>(), ko.as<uint32_t>(),
+                                         vals.as<int32_t>(), idx.as<int32_t>(), (size_t)nv, 0u,
+                                         8u, s));
+        tmp.alloc(tb + 16);
+        MM_HIP(rocprim::radix_sort_pairs(tmp.ptr, tb, keys.as<uint32_t>(), ko.as<uint32_t>(),
+                                         vals.as<int32_t>(), idx.as<int32_t>(), (size_t)nv, 0u,
+                                         8u, s));
+        perm2.alloc(sizeof(int32_t) * nv);
+        if (f32) {
+            ws2.alloc(sizeof(float2) * nv);
+            k_perm_gather<float2><<<grid_for(nv), BS, 0, s>>>(
+                idx.as<int32_t>(), perm_u, p->ws.as<float2>(), nv, perm2.as<int32_t>(),
+                ws2.as<float2>());
+        } else {
+            k_perm_gather<float2><<<grid_for(nv), BS, 0, s>>>(
+                idx.as<int32_t>(), perm_u, nullptr, nv, perm2.as<int32_t>(), nullptr);
+        }
+        const int64_t nvp = (int64_t)D * n_obs;
+        cnt2.alloc(sizeof(int32_t) * (nvp + 1));
+        MM_HIP(hipMemsetAsync(cnt2.ptr, 0, sizeof(int32_t) * (nvp + 1), s));
+        k_dir_counts<<<grid_for(p->n_samp), BS, 0, s>>>(p->j.as<int32_t>(),
+                                                        p->p_chunk_grp.as<int32_t>(), p->n_samp,
+                                                        n_obs, cnt2.as<int32_t>());
+        off2.alloc(sizeof(int32_t) * (nvp + 1));
+        size_t tb2 = 0;
+        MM_HIP(rocprim::exclusive_scan(nullptr, tb2, cnt2.as<int32_t>(), off2.as<int32_t>(),
+                                       (int32_t)0, (size_t)(nvp + 1), rocprim::plus<int32_t>(),
+                                       s));
+        DBuf tmp2;
+        tmp2.alloc(tb2 + 16);
+        MM_HIP(rocprim::exclusive_scan(tmp2.ptr, tb2, cnt2.as<int32_t>(), off2.as<int32_t>(),
+                                       (int32_t)0, (size_t)(nvp + 1), rocprim::plus<int32_t>(),
+                                       s));
+        MM_HIP(hipStreamSynchronize(s));
+        perm_u = perm2.as<int32_t>();
+        off_u = off2.as<int32_t>();
+        if (f32) ws_u = ws2.ptr;
+    }
 
     p->sl_pix.alloc(sizeof(int32_t) * (size_t)G * 64);
     MM_HIP(hipMemsetAsync(p->sl_pix.ptr, 0xff, sizeof(int32_t) * (size_t)G * 64, s));
-    if (width > 0) {
+    if (dirs) {
+        const int64_t nvp = (int64_t)D * n_obs;
+        k_sl_pix_dir<<<grid_for(nvp), BS, 0, s>>>(p->p_slot.as<int32_t>(), nvp, n_obs, G0,
+                                                  p->sl_pix.as<int32_t>());
+        MM_HIP(hipStreamSynchronize(s));
+    } else if (width > 0) {
         DBuf keys, vals, ko;
         keys.alloc(sizeof(uint64_t) * n_obs);
         vals.alloc(sizeof(int32_t) * n_obs);
@@ -495,8 +605,8 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     sizes.alloc(sizeof(int64_t) * (n_waves + 1));
     p->sl_base.alloc(sizeof(int64_t) * (n_waves + 1));
     k_sl_bounds<<<(unsigned)((G * 64 + BS - 1) / BS), BS, 0, s>>>(
-        p->sl_pix.as<int32_t>(), G, S, p->n_samp, p->off.as<int32_t>(), p->perm.as<int32_t>(),
-        cnt.as<int32_t>(), start.as<int32_t>());
+        p->sl_pix.as<int32_t>(), G, S, p->n_samp, off_u, perm_u, cnt.as<int32_t>(),
+        start.as<int32_t>());
     k_sl_width<<<(unsigned)((n_waves + 1) * 64 / BS + 1), BS, 0, s>>>(cnt.as<int32_t>(), n_waves,
                                                                       sizes.as<int64_t>());
     size_t tb = 0;
@@ -511,24 +621,24 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width) {
     MM_HIP(hipMemcpyAsync(&total, p->sl_base.as<int64_t>() + n_waves, sizeof(int64_t),
                           hipMemcpyDeviceToHost, s));
     MM_HIP(hipStreamSynchronize(s));
-    const bool f32 = p->prec == MM_F32;
     p->sl_perm.alloc(sizeof(int32_t) * (size_t)total);
     p->sl_w.alloc((f32 ? sizeof(float2) : sizeof(double)) * (size_t)total);
     const unsigned fb = (unsigned)std::min<int64_t>((n_waves * 64 + BS - 1) / BS, 16384);
     if (f32)
         k_sl_fill<float2><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
-                                            start.as<int32_t>(), p->perm.as<int32_t>(),
-                                            p->ws.as<float2>(), n_waves, p->sl_perm.as<int32_t>(),
-                                            p->sl_w.as<float2>());
+                                            start.as<int32_t>(), perm_u,
+                                            static_cast<const float2 *>(ws_u), n_waves,
+                                            p->sl_perm.as<int32_t>(), p->sl_w.as<float2>());
     else
         k_sl_fill<double><<<fb, BS, 0, s>>>(p->sl_base.as<int64_t>(), cnt.as<int32_t>(),
-                                            start.as<int32_t>(), p->perm.as<int32_t>(),
-                                            p->psi.as<double>(), n_waves,
-                                            p->sl_perm.as<int32_t>(), p->sl_w.as<double>());
+                                            start.as<int32_t>(), perm_u, p->psi.as<double>(),
+                                            n_waves, p->sl_perm.as<int32_t>(),
+                                            p->sl_w.as<double>());
     MM_HIP(hipGetLastError());
     MM_HIP(hipStreamSynchronize(s));
     p->sl_G = G;
     p->sl_S = S;
+    p->sl_D = D;
 }
 
 void pointing_build_device(mm_ctx *ctx, mm_pointing *p, const int32_t *pix, const double *psi,

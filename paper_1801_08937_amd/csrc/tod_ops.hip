@@ -617,25 +617,30 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
         return;
     }
     if (nrhs == 1 && p->sl_G > 0) {
-        const int32_t G = p->sl_G, S = p->sl_S;
+        // lane pixels are virtual ids d n_obs + c (sl_D scan directions), so
+        // wave (s, g) writes partial map s D + d; the partials are then
+        // added in that fixed order
+        const int32_t G = p->sl_G, S = p->sl_S, D = p->sl_D;
         const int64_t n3 = 3 * (int64_t)p->n_obs;
+        const int32_t parts = S * D;
         double *out = x;
-        if (S > 1) {
-            ws_alloc(ctx, ctx->pt_part, sizeof(double) * (size_t)(n3 * S));
+        if (parts > 1) {
+            ws_alloc(ctx, ctx->pt_part, sizeof(double) * (size_t)(n3 * parts));
             out = ctx->pt_part.as<double>();
         }
+        const int32_t nv = D * p->n_obs;
         int64_t nb = ((int64_t)G * S + 3) / 4;
         if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
         if (p->prec == MM_F32)
             k_apply_PT_sl<float><<<(unsigned)nb, BS, 0, ctx->stream>>>(
                 p->sl_base.as<int64_t>(), p->sl_perm.as<int32_t>(), p->sl_w.as<float2>(),
-                p->sl_pix.as<int32_t>(), G, S, p->n_obs, static_cast<const float *>(z), out);
+                p->sl_pix.as<int32_t>(), G, S, nv, static_cast<const float *>(z), out);
         else
             k_apply_PT_sl<double><<<(unsigned)nb, BS, 0, ctx->stream>>>(
                 p->sl_base.as<int64_t>(), p->sl_perm.as<int32_t>(), p->sl_w.as<double>(),
-                p->sl_pix.as<int32_t>(), G, S, p->n_obs, static_cast<const double *>(z), out);
-        if (S > 1)
-            k_pt_sum_parts<<<grid_for(n3, 2048), BS, 0, ctx->stream>>>(out, S, n3, x);
+                p->sl_pix.as<int32_t>(), G, S, nv, static_cast<const double *>(z), out);
+        if (parts > 1)
+            k_pt_sum_parts<<<grid_for(n3, 2048), BS, 0, ctx->stream>>>(out, parts, n3, x);
         MM_HIP(hipGetLastError());
         return;
     }

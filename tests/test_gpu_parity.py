@@ -609,11 +609,13 @@ def test_autotune_keeps_results_bitwise(ctx):
 
 def test_PT_sliced_layout_parity_and_order(ctx):
     """The sliced single-column P^T (one pixel per lane, time segments summed
-    in order) on a cross-linked scan: parity with the oracle,
-    bitwise independence of the grid grouping (also for P's Morton-ordered
-    map slots), agreement with the
-    one-wave-per-pixel form used for several columns, and the FP32 form
-    (2^23 samples, 16,384 pixels: 256 slices x 14 segments)."""
+    in order) on a cross-linked scan: parity with the oracle; with the grid
+    hint, slices cut per scan direction (three here: a pixel's samples of each
+    direction summed by their own lane, the partial maps added in a fixed
+    order), still within the bar and bitwise repeatable, and P bitwise
+    unchanged (its map copies); agreement with the one-wave-per-pixel form
+    used for several columns, and the FP32 form (2^23 samples, 16,384
+    pixels: 256 slices x 14 segments)."""
     import torch
     p = synth.config2(n_side=128, grid=(4, 4), samp_per_det=1 << 19, L=1 << 15, half_bw=1024)
     lp, ln, op, on = build_both(ctx, p, method=2)
@@ -628,13 +630,17 @@ def test_PT_sliced_layout_parity_and_order(ctx):
     yp = ctx.apply_P(lp, dev(xm))
     assert maxrel(host(yp), O.apply_P(op, xm)) <= TOL_OP
     lp.set_grid(p.n_side)
-    assert lp.pt_layout() == (G, S)
-    assert torch.equal(a, ctx.apply_PT(lp, dev(y)))
-    # P through the Morton-ordered map slots: bitwise the same
+    D = lp.p_copies()
+    Gd, Sd = lp.pt_layout()
+    assert D == 3 and Gd == G * D and 1 <= Sd <= S
+    ad = ctx.apply_PT(lp, dev(y))
+    assert maxrel(host(ad), ref) <= TOL_OP
+    assert torch.equal(ad, ctx.apply_PT(lp, dev(y)))
+    # P through the per-direction map copies: bitwise the same
     assert torch.equal(yp, ctx.apply_P(lp, dev(xm)))
     Y2 = np.stack([y, rng.standard_normal(op.n_samp)], axis=1)
     a2 = host(ctx.apply_PT(lp, dev(Y2.reshape(-1)), nrhs=2)).reshape(-1, 2)
-    assert maxrel(a2[:, 0], host(a)) <= TOL_OP
+    assert maxrel(a2[:, 0], host(ad)) <= TOL_OP
     x = rng.standard_normal(op.n)
     assert maxrel(host(ctx.apply_A(lp, ln, dev(x))), O.apply_A(op, on, x, "fft")) <= 1e-11
     lp32, _, _, _ = build_both(ctx, p, prec=1, method=2)
