@@ -64,7 +64,7 @@ def log(*a):
 # are left out: they do not change a kernel's code.
 KERNEL_SOURCES = {
     "P": ["tod_ops.hip", "pointing.hip", "pol_weights.h", "xcd.h"],
-    "PT": ["tod_ops.hip", "pol_weights.h", "xcd.h"],
+    "PT": ["tod_ops.hip", "pointing.hip", "pol_weights.h", "xcd.h"],
     "Ninv_fft": ["noise_fft_big.hip", "fft_common.h"],
     "Ninv_band": ["tod_ops.hip"],
 }
