@@ -417,26 +417,47 @@ __global__ void __launch_bounds__(BS) k_copy_masked(int64_t n, const int *__rest
 
 // -------------------------------------------------------- skinny products
 
-// partial[chunk * ncol + col] = sum_{i in chunk} W[col * n + i] v[i]
-__global__ void __launch_bounds__(BS) k_gemv_t(int64_t n, const double *__restrict__ W,
-                                               const double *__restrict__ v,
-                                               double *__restrict__ partial, int64_t rows,
-                                               int ncol) {
-    const int col = blockIdx.y;
+// partial[chunk * ncol + col] = sum_{i in chunk} W[col * n + i] v[i] for
+// GT columns at once (col = blockIdx.y GT + c): v is read once
+// per group of columns, and each thread keeps GT independent loads in
+// flight.  Each column sums a thread's rows in order, then the lanes of a
+// wave by a fixed butterfly, then the waves in order.
+constexpr int GT = 16;
+__global__ void __launch_bounds__(BS) k_gemv_t_grp(int64_t n, const double *__restrict__ W,
+                                                   const double *__restrict__ v,
+                                                   double *__restrict__ partial, int64_t rows,
+                                                   int ncol) {
+    const int c0 = blockIdx.y * GT;
+    const int nc = ncol - c0 < GT ? ncol - c0 : GT;
     const int64_t i0 = (int64_t)blockIdx.x * rows;
     int64_t i1 = i0 + rows;
     if (i1 > n) i1 = n;
-    const double *w = W + (int64_t)col * n;
-    double acc = 0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += BS) acc += w[i] * v[i];
-    __shared__ double sm[BS];
-    sm[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = BS / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-        __syncthreads();
+    double acc[GT];
+#pragma unroll
+    for (int c = 0; c < GT; ++c) acc[c] = 0;
+    const double *w = W + (int64_t)c0 * n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BS) {
+        const double vi = v[i];
+#pragma unroll
+        for (int c = 0; c < GT; ++c)
+            if (c < nc) acc[c] += w[(int64_t)c * n + i] * vi;
     }
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncol + col] = sm[0];
+    __shared__ double sm[BS / 64][GT];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < GT; ++c) {
+        double a = acc[c];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d);
+        if (lane == 0) sm[wv][c] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+        double t = 0;
+#pragma unroll
+        for (int q = 0; q < BS / 64; ++q) t += sm[q][threadIdx.x];
+        partial[(int64_t)blockIdx.x * ncol + c0 + threadIdx.x] = t;
+    }
 }
 
 // v[i] -= sum_c W[c n + i] h[c]
@@ -722,19 +743,22 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
         return;
     }
     for (int64_t j = p0 + rg; j < p1; j += NG) {
-        double u[3], zc[3];
+        // the three rows of pixel j together for each q, so a wave reads
+        // whole lines of Z and AZ at once (each sum still runs over q in order)
+        double u[3], zc[3], s_az[3] = {0, 0, 0};
+        zc[0] = zc[1] = zc[2] = 0;
+        for (int q = 0; q < k; ++q) {
+            const double cq = sc[q * R + r];
+            const double *azq = AZ + (int64_t)q * n + 3 * j;
+            const double *zq = Z + (int64_t)q * n + 3 * j;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int64_t row = 3 * j + a;
-            double s_az = 0, s_z = 0;
-            for (int q = 0; q < k; ++q) {
-                const double cq = sc[q * R + r];
-                s_az += AZ[(int64_t)q * n + row] * cq;
-                s_z += Z[(int64_t)q * n + row] * cq;
+            for (int a = 0; a < 3; ++a) {
+                s_az[a] += azq[a] * cq;
+                zc[a] += zq[a] * cq;
             }
-            u[a] = v[row * R + r] - s_az;
-            zc[a] = s_z;
         }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = v[(3 * j + a) * R + r] - s_az[a];
         const double *m = inv + 6 * j;
         const double o0 = m[0] * u[0] + m[1] * u[1] + m[2] * u[2] + zc[0];
         const double o1 = m[1] * u[0] + m[3] * u[1] + m[4] * u[2] + zc[1];
@@ -1114,8 +1138,8 @@ void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, 
     Scope sc(ctx->prof, ctx->stream, "gemv");
     const int parts = reduction_parts(n);
     ws_alloc(ctx, ctx->red, sizeof(double) * parts * (ncol > 64 ? ncol : 64));
-    k_gemv_t<<<dim3(parts, ncol), BS, 0, ctx->stream>>>(n, W, v, ctx->red.as<double>(),
-                                                         rows_per(n, parts), ncol);
+    k_gemv_t_grp<<<dim3(parts, (ncol + GT - 1) / GT), BS, 0, ctx->stream>>>(
+        n, W, v, ctx->red.as<double>(), rows_per(n, parts), ncol);
     k_dot_final<<<ncol, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, ncol, h);
     MM_HIP(hipGetLastError());
 }
