@@ -235,7 +235,12 @@ mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int32_t n_inter
 mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method);
 /* Overlap-save block geometry of the FFT method (Sect. 3, the Toeplitz apply
  * as a circulant product): each block transforms *n_fft samples and keeps
- * *n_valid = *n_fft - 2 lambda outputs.  Both 0 for the direct method. */
+ * *n_valid = *n_fft - 2 lambda outputs.  Both 0 for the direct method.
+ * *n_fft is 16,384 or 32,768, picked at build by a measured time model
+ * (blocks run in waves of one per compute unit; a block costs a fixed time,
+ * 1.56 times more for the large size, plus a term per input sample read),
+ * so it depends on the interval lengths, lambda (16,384 only up to 2,048)
+ * and the device's compute-unit count. */
 mm_status mm_noise_fft_block(const mm_noise *nz, int32_t *n_fft, int32_t *n_valid);
 /* z = N^-1 y (or z = F y for a template filter) on the TOD layout.  y, z
  * [device], TOD precision, distinct. */
