@@ -647,6 +647,28 @@ def test_PT_sliced_layout_parity_and_order(ctx):
     assert lp32.pt_layout() == (G, S)
     a32 = host(ctx.apply_PT(lp32, dev(y.astype(np.float32))))
     assert rel(a32, ref) <= 1e-5
+    # FP32 with the hint: the same direction slices, repeatable, within the bar
+    lp32.set_grid(p.n_side)
+    assert lp32.p_copies() == D and lp32.pt_layout() == (Gd, Sd)
+    b32 = ctx.apply_PT(lp32, dev(y.astype(np.float32)))
+    assert rel(host(b32), ref) <= 1e-5
+    assert torch.equal(b32, ctx.apply_PT(lp32, dev(y.astype(np.float32))))
+
+
+def test_P_map_copies_one_direction(ctx):
+    """A straight back-and-forth raster (config 1) has one scan direction:
+    one map copy, and P, P^T, A bitwise those without the hint."""
+    import torch
+    p = synth.config1()
+    lp, ln, op, on = build_both(ctx, p)
+    x = dev(np.random.default_rng(40).standard_normal(op.n))
+    y = dev(np.random.default_rng(41).standard_normal(op.n_samp))
+    r0 = (ctx.apply_P(lp, x), ctx.apply_PT(lp, y), ctx.apply_A(lp, ln, x))
+    lp.set_grid(p.n_side)
+    assert lp.p_copies() == 1
+    r1 = (ctx.apply_P(lp, x), ctx.apply_PT(lp, y), ctx.apply_A(lp, ln, x))
+    for a, b in zip(r0, r1):
+        assert torch.equal(a, b)
 
 
 def test_graph_recaptured_after_workspace_growth(ctx):
