@@ -417,8 +417,31 @@ __global__ void __launch_bounds__(BS) k_copy_masked(int64_t n, const int *__rest
 
 // -------------------------------------------------------- skinny products
 
-// partial[chunk * ncol + col] = sum_{i in chunk} W[col * n + i] v[i] for
-// GT columns at once (col = blockIdx.y GT + c): v is read once
+// partial[chunk * ncol + col] = sum_{i in chunk} W[col * n + i] v[i], one
+// column per block (many columns: the Arnoldi basis).
+__global__ void __launch_bounds__(BS) k_gemv_t(int64_t n, const double *__restrict__ W,
+                                               const double *__restrict__ v,
+                                               double *__restrict__ partial, int64_t rows,
+                                               int ncol) {
+    const int col = blockIdx.y;
+    const int64_t i0 = (int64_t)blockIdx.x * rows;
+    int64_t i1 = i0 + rows;
+    if (i1 > n) i1 = n;
+    const double *w = W + (int64_t)col * n;
+    double acc = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BS) acc += w[i] * v[i];
+    __shared__ double sm[BS];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ncol + col] = sm[0];
+}
+
+// The same for GT columns at once (col = blockIdx.y GT + c), for few
+// columns (Z^T v of M_2l): v is read once
 // per group of columns, and each thread keeps GT independent loads in
 // flight.  Each column sums a thread's rows in order, then the lanes of a
 // wave by a fixed butterfly, then the waves in order.
@@ -1138,8 +1161,14 @@ void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, 
     Scope sc(ctx->prof, ctx->stream, "gemv");
     const int parts = reduction_parts(n);
     ws_alloc(ctx, ctx->red, sizeof(double) * parts * (ncol > 64 ? ncol : 64));
-    k_gemv_t_grp<<<dim3(parts, (ncol + GT - 1) / GT), BS, 0, ctx->stream>>>(
-        n, W, v, ctx->red.as<double>(), rows_per(n, parts), ncol);
+    // grouped columns measured faster for k = 32 (M_2l), one column per
+    // block for the long Arnoldi bases
+    if (ncol <= 32)
+        k_gemv_t_grp<<<dim3(parts, (ncol + GT - 1) / GT), BS, 0, ctx->stream>>>(
+            n, W, v, ctx->red.as<double>(), rows_per(n, parts), ncol);
+    else
+        k_gemv_t<<<dim3(parts, ncol), BS, 0, ctx->stream>>>(n, W, v, ctx->red.as<double>(),
+                                                             rows_per(n, parts), ncol);
     k_dot_final<<<ncol, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, ncol, h);
     MM_HIP(hipGetLastError());
 }
