@@ -98,16 +98,16 @@ __global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpi
                                                  T *__restrict__ y) {
     const int64_t step = (int64_t)gridDim.x * BS;
     int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
-    for (; t + 3 * step < n; t += 4 * step) {
-        int32_t j[4];
-        typename Vec2<T>::type ww[4];
+    for (; t + 7 * step < n; t += 8 * step) {
+        int32_t j[8];
+        typename Vec2<T>::type ww[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             j[q] = jpix[t + q * step];
             ww[q] = w[t + q * step];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y[t + q * step] = p_gather4<T>(j[q], ww[q], x4);
+        for (int q = 0; q < 8; ++q) y[t + q * step] = p_gather4<T>(j[q], ww[q], x4);
     }
     for (; t < n; t += step) y[t] = p_gather4<T>(jpix[t], w[t], x4);
 }
@@ -154,16 +154,18 @@ __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__
                                                      double *__restrict__ y) {
     const int64_t step = (int64_t)gridDim.x * BS;
     int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
-    for (; t + 3 * step < n; t += 4 * step) {
-        int32_t j[4];
-        double a[4];
+    // eight samples in flight per thread (measured: 0.70 ms against 0.73 with
+    // four at 1.34e8 samples; sixteen gave no more)
+    for (; t + 7 * step < n; t += 8 * step) {
+        int32_t j[8];
+        double a[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             j[q] = jpix[t + q * step];
             a[q] = psi[t + q * step];
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y[t + q * step] = p_gather_psi(j[q], a[q], xi, xqu);
+        for (int q = 0; q < 8; ++q) y[t + q * step] = p_gather_psi(j[q], a[q], xi, xqu);
     }
     for (; t < n; t += step) y[t] = p_gather_psi(jpix[t], psi[t], xi, xqu);
 }
@@ -272,19 +274,20 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
     const auto *wp = sl_w + b0 + lane;
     T s0 = 0, s1 = 0, s2 = 0;
     int64_t k = 0;
-    for (; k + 3 < W; k += 4) {
-        int32_t tt[4];
-        typename SlRec<T>::type ww[4];
-        T zz[4];
+    // eight entries in flight per lane, accumulated in entry order
+    for (; k + 7 < W; k += 8) {
+        int32_t tt[8];
+        typename SlRec<T>::type ww[8];
+        T zz[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tt[q] = pp[64 * (k + q)];
+        for (int q = 0; q < 8; ++q) tt[q] = pp[64 * (k + q)];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             ww[q] = wp[64 * (k + q)];
             zz[q] = tt[q] >= 0 ? z[tt[q]] : (T)0;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             T c, sn;
             SlRec<T>::weights(ww[q], c, sn);
             s0 += zz[q];
