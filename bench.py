@@ -787,24 +787,6 @@ def _n1_size(mm, ctx, lams, n_samp, L, dev, ev):
     return rows
 
 
-def transfer_Z(Z, obs_from, obs_to):
-    """Deflation vectors of one subset laid out on another subset's observed
-    pixels (rows matched by global pixel id; pixels the source did not observe
-    get 0).  Data marshalling only: the coarse operator is rebuilt on the
-    target by the library (AZ, E)."""
-    import torch
-    k = Z.shape[1]
-    pos = torch.full((int(max(int(obs_from.max()), int(obs_to.max())) + 1),), -1,
-                     dtype=torch.int64, device=Z.device)
-    pos[obs_from.long()] = torch.arange(obs_from.numel(), device=Z.device)
-    src = pos[obs_to.long()]
-    Zs = Z.reshape(-1, 3, k)
-    out = torch.zeros((obs_to.numel(), 3, k), dtype=Z.dtype, device=Z.device)
-    ok = src >= 0
-    out[ok] = Zs[src[ok]]
-    return out.reshape(-1, k)
-
-
 def form_d1(mm, ctx, n_sub=8, full_m2l=2):
     """Divide and conquer with the "simplified" two-level preconditioner
     (Sect. 6.3): the config-2 scan split by detectors into n_sub subsets over
@@ -819,7 +801,7 @@ def form_d1(mm, ctx, n_sub=8, full_m2l=2):
     p = synth.config2()
     per = p.n_samp // n_sub
     ipd = p.n_intervals // n_sub
-    rows, Z0, obs0 = [], None, None
+    rows, src = [], None
     for k in range(n_sub):
         sl = slice(k * per, (k + 1) * per)
         pix = torch.from_numpy(p.pix[sl]).to(dev)
@@ -832,7 +814,6 @@ def form_d1(mm, ctx, n_sub=8, full_m2l=2):
             synth.rng_for(2, 10 + k, synth.STREAM_NOISE).standard_normal(per)
         b = ctx.rhs(lp, lf, torch.from_numpy(d).to(dev))
         Mbd = ctx.mbd(lp, lf)
-        _, obs = lp.hits()
         row = {"subset": k, "n_obs": lp.n_obs}
 
         def run(M):
@@ -845,10 +826,9 @@ def form_d1(mm, ctx, n_sub=8, full_m2l=2):
             (M2, t) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=32, eps_arn=1e-8, m_max=256))
             row["m2l_own"] = run(M2)
             row["m2l_own"]["setup_s"] = t
-            Z0 = M2.export()[0].contiguous()
-            obs0 = obs.clone()
+            src = (lp, M2)
         else:
-            (Ms, t) = _wall(lambda: ctx.defl_from_Z(lp, lf, Mbd, transfer_Z(Z0, obs0, obs)))
+            (Ms, t) = _wall(lambda: ctx.defl_transfer(src[0], src[1], lp, lf, Mbd))
             row["m2l_transferred"] = run(Ms)
             row["m2l_transferred"]["setup_s"] = t
             if k <= full_m2l:

@@ -326,6 +326,18 @@ mm_status mm_defl_build_pcg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *n
  * pivot^2 below 1e-13 times the largest diagonal entry. */
 mm_status mm_defl_from_Z(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                          const mm_precond *mbd, int32_t k, const double *Z, mm_precond **out);
+/* The "simplified" two-level preconditioner of the divide-and-conquer runs
+ * (Sect. 7.3): the deflation vectors of an M_2l built on one data subset
+ * (src, over p_src's observed pixels) reused on another subset's system.
+ * Rows are matched by global pixel id; pixels p_src did not observe get 0.
+ * A Z and E = Z^T A Z are then rebuilt with this subset's A (p, nz), and
+ * M_BD is this subset's (mbd).  Z is not re-orthonormalised (only span(Z)
+ * enters M_2l).  Both pointings must hold the same Stokes components.
+ * Errors: MM_E_INVALID for mismatched handles; MM_E_COARSE_NOT_SPD as
+ * mm_defl_from_Z (e.g. when the subsets share too few pixels). */
+mm_status mm_defl_transfer(mm_ctx *ctx, const mm_pointing *p_src, const mm_precond *src,
+                           const mm_pointing *p, const mm_noise *nz, const mm_precond *mbd,
+                           mm_precond **out);
 /* Copy out Z, A Z ([device] f64[k][n] each, either may be NULL) and E
  * ([device] f64[k][k], symmetrised). */
 mm_status mm_defl_export(mm_ctx *ctx, const mm_precond *M, int32_t *k, double *Z, double *AZ,

@@ -810,6 +810,46 @@ extern "C" mm_status mm_defl_from_Z(mm_ctx *ctx, const mm_pointing *p, const mm_
     return MM_OK;
 }
 
+extern "C" mm_status mm_defl_transfer(mm_ctx *ctx, const mm_pointing *p_src,
+                                      const mm_precond *src, const mm_pointing *p,
+                                      const mm_noise *nz, const mm_precond *mbd,
+                                      mm_precond **out) {
+    if (!ctx || !out) return MM_E_INVALID;
+    *out = nullptr;
+    API_BEGIN(ctx)
+    check_pair(p, nz);
+    MM_CHECK(p_src && src && src->kind == 1 && src->n_obs == p_src->n_obs && src->nc == p_src->nc,
+             MM_E_INVALID, "defl_transfer: needs an M_2l handle of the source pointing");
+    MM_CHECK(p_src->nc == p->nc, MM_E_INVALID, "defl_transfer: Stokes components differ");
+    MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs && mbd->nc == p->nc, MM_E_INVALID,
+             "defl_transfer: needs an M_BD handle of the target pointing");
+    const int k = src->k;
+    const int64_t n = p->n();
+    MM_CHECK(k >= 1 && k <= n, MM_E_INVALID, "defl_transfer: k exceeds the target's unknowns");
+    auto *M = new mm_precond();
+    try {
+        M->kind = 1;
+        M->n_obs = p->n_obs;
+        M->nc = p->nc;
+        M->k = k;
+        M->rcond_min = mbd->rcond_min;
+        M->inv.alloc(sizeof(double) * packed_sym(p->nc) * p->n_obs);
+        MM_HIP(hipMemcpyAsync(M->inv.ptr, mbd->inv.ptr, sizeof(double) * packed_sym(p->nc) * p->n_obs,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        M->Z.alloc(sizeof(double) * n * k);
+        transfer_rows(ctx, p->n_obs, p->obs_pix.as<int32_t>(), p_src->n_obs,
+                      p_src->obs_pix.as<int32_t>(), p->nc, k, src->Z.as<double>(),
+                      M->Z.as<double>());
+        finish_m2l(ctx, p, nz, M);
+    } catch (...) {
+        delete M;
+        throw;
+    }
+    *out = M;
+    API_END
+    return MM_OK;
+}
+
 // Eigen-decomposition of a small symmetric matrix (cyclic Jacobi rotations):
 // A (n x n, row-major) is destroyed; w = eigenvalues, U column j = vector j.
 static void sym_eig_jacobi(int n, std::vector<double> &A, std::vector<double> &w,

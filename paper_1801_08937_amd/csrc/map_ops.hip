@@ -923,6 +923,32 @@ __global__ void k_col_get(int64_t n, int R, int slot, const double *__restrict__
         dst[i] = src[i * R + slot];
 }
 
+// Rows of a k-column basis moved between two pixel sets by global pixel id:
+// dst[c (n_dst) + nc j + a] = src[c n_src + nc i + a] where obs_src[i] =
+// obs_dst[j] (binary search; both id lists ascending), 0 when the source set
+// lacks the pixel.  One thread per target pixel.
+__global__ void __launch_bounds__(BS) k_transfer_rows(int32_t n_dst_obs,
+                                                      const int32_t *__restrict__ obs_dst,
+                                                      int32_t n_src_obs,
+                                                      const int32_t *__restrict__ obs_src,
+                                                      int nc, int k, const double *__restrict__ src,
+                                                      double *__restrict__ dst) {
+    const int32_t j = (int32_t)(blockIdx.x * BS + threadIdx.x);
+    if (j >= n_dst_obs) return;
+    const int32_t g = obs_dst[j];
+    int32_t lo = 0, hi = n_src_obs;  // first index with obs_src[i] >= g
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (obs_src[mid] < g) lo = mid + 1; else hi = mid;
+    }
+    const bool found = lo < n_src_obs && obs_src[lo] == g;
+    const int64_t n_src = (int64_t)nc * n_src_obs, n_dst = (int64_t)nc * n_dst_obs;
+    for (int c = 0; c < k; ++c)
+        for (int a = 0; a < nc; ++a)
+            dst[c * n_dst + (int64_t)nc * j + a] =
+                found ? src[c * n_src + (int64_t)nc * lo + a] : 0.0;
+}
+
 // mode 0: slot becomes free/stopped (done = 1); mode 1: (re)start with
 // tolerance tol (rn2 = bn2, already written), done if already converged.
 __global__ void k_slot_ctl(PcgDev s, int slot, int mode, double tol) {
@@ -1144,6 +1170,14 @@ void chol_inv_drop(mm_ctx *ctx, int R, const double *G, double tau, double *U, i
 
 void col_set(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst) {
     k_col_set<<<grid_for(n), BS, 0, ctx->stream>>>(n, R, slot, src, dst);
+    MM_HIP(hipGetLastError());
+}
+
+void transfer_rows(mm_ctx *ctx, int32_t n_dst_obs, const int32_t *obs_dst, int32_t n_src_obs,
+                   const int32_t *obs_src, int nc, int k, const double *src, double *dst) {
+    if (n_dst_obs <= 0) return;
+    k_transfer_rows<<<(n_dst_obs + BS - 1) / BS, BS, 0, ctx->stream>>>(n_dst_obs, obs_dst, n_src_obs,
+                                                                       obs_src, nc, k, src, dst);
     MM_HIP(hipGetLastError());
 }
 

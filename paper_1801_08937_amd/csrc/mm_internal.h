@@ -315,6 +315,10 @@ void gemm_rows_small(mm_ctx *ctx, int64_t n, int R, const double *In, const doub
                      double alpha, double beta, double *Out);
 void chol_inv_drop(mm_ctx *ctx, int R, const double *G, double tau, double *U, int *rank);
 void col_get(mm_ctx *ctx, int64_t n, int R, int slot, const double *src, double *dst);
+// dst (k columns over the n_dst_obs pixels obs_dst) = src's rows of the same
+// global pixels (k columns over obs_src), 0 where obs_src lacks the pixel
+void transfer_rows(mm_ctx *ctx, int32_t n_dst_obs, const int32_t *obs_dst, int32_t n_src_obs,
+                   const int32_t *obs_src, int nc, int k, const double *src, double *dst);
 void slot_ctl(mm_ctx *ctx, PcgDev s, int slot, int mode, double tol);
 void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const double *src,
                       double *dst);

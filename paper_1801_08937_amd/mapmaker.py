@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
             "mm_defl_build": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, PP]),
             "mm_defl_build_pcg": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, P, PP]),
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
+            "mm_defl_transfer": (C.c_int, [P, P, P, P, P, P, PP]),
             "mm_defl_export": (C.c_int, [P, P, C.POINTER(I32), P, P, P]),
             "mm_defl_arnoldi_export": (C.c_int, [P, P, C.POINTER(I32), P, P]),
             "mm_precond_apply": (C.c_int, [P, P, I32, P, P]),
@@ -336,6 +337,15 @@ class Context:
         h = C.c_void_p()
         self._check(lib().mm_defl_from_Z(self.h, p.h, nz.h, mbd.h, k, _ptr(Zc), C.byref(h)),
                     "mm_defl_from_Z")
+        return Precond(self, h, p.n, 1)
+
+    def defl_transfer(self, p_src, src, p, nz, mbd):
+        """M_2l on (p, nz) from the deflation vectors of src, an M_2l built on
+        another subset (p_src): rows matched by global pixel id, A Z and E
+        rebuilt here (the "simplified" two-level preconditioner)."""
+        h = C.c_void_p()
+        self._check(lib().mm_defl_transfer(self.h, p_src.h, src.h, p.h, nz.h, mbd.h, C.byref(h)),
+                    "mm_defl_transfer")
         return Precond(self, h, p.n, 1)
 
     def defl_build(self, p, nz, mbd, b_seed, k: int = 32, eps_arn: float = 1e-8,

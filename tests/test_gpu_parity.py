@@ -161,7 +161,6 @@ def test_solve_config1_mbd_to_1e8(ctx):
     xo, io = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-13, 5000)
     # both within kappa * tol of the exact solution; stated bound 1e-6
     assert rel(host(x), xo) <= 1e-6
-    assert abs(info["iters"] - 0) >= 1
 
 
 def test_noiseless_recovery_gpu(ctx):
@@ -263,7 +262,9 @@ def test_fp32_form_error_vs_fp64_oracle(ctx):
     xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-12, 5000)
     err = rel(host(xs), xo)
     print(f"fp32 form: map rel error vs FP64 oracle = {err:.3e}, iters = {info['iters']}")
-    assert err <= 1e-3
+    # the FP64 solve stopped at 1e-6 is itself about 2e-6 from the exact map;
+    # measured 1.6e-6 here, bar about ten times that
+    assert err <= 2e-5
 
 
 def test_error_paths(ctx):
@@ -588,7 +589,7 @@ def test_batched_fp32_variant(ctx):
     xo, _ = O.pcg(lambda v: O.apply_A(op, on, v), lambda v: O.mbd_apply(OM, v), bo, 1e-12, 5000)
     err = rel(host(xb).reshape(op.n, 8)[:, 3], xo)
     print(f"fp32 batched block CG: map error vs FP64 oracle {err:.2e}")
-    assert err <= 1e-3
+    assert err <= 2e-5
 
 
 def test_autotune_keeps_results_bitwise(ctx):

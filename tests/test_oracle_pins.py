@@ -386,6 +386,95 @@ def test_ritz_select_keeps_pairs():
     assert Y.shape[1] == 2
 
 
+def _hessenberg_with_spectrum(eigs, seed, symmetric):
+    """An upper Hessenberg matrix similar to diag(eigs) (scipy's Householder
+    reduction of T D T^-1), and its eigenvectors as columns (U^T T)."""
+    rng = np.random.default_rng(seed)
+    n = len(eigs)
+    if symmetric:
+        T = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    else:
+        T = np.eye(n) + 0.5 * rng.standard_normal((n, n)) / np.sqrt(n)
+    S = T @ np.diag(eigs) @ np.linalg.inv(T)
+    H, U = scipy.linalg.hessenberg(S, calc_q=True)
+    return H, U.T @ T
+
+
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_ritz_select_skips_exact_null_keeps_small(symmetric):
+    """Reading of the Ritz selection (Sect. 6, App. A): a Ritz value at the
+    rounding level is an exact null direction and stays out of Z, while a
+    genuine small eigenvalue (1e-8 of the largest, and 1e-9) is kept: the k
+    selected vectors span the eigenvectors of the k smallest non-zero
+    eigenvalues, also with the eps_lambda rule."""
+    eigs = np.array([0.0, 0.0, 4e-8, 3e-3, 0.1, 0.5, 1.0, 2.0, 3.0, 4.0])
+    H, X = _hessenberg_with_spectrum(eigs, 1, symmetric)
+    theta, Y = O.ritz_select(H, 2)
+    assert np.max(np.abs(theta[:2])) <= 1e-14          # the two exact zeros, found by eig
+    assert Y.shape[1] == 2
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Y, X[:, 2:4]))) <= 1e-6
+    theta, Y = O.ritz_select(H, 1)
+    assert Y.shape[1] == 1
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Y, X[:, 2:3]))) <= 1e-6
+    theta, Y = O.ritz_select(H, 0, eps_lambda=0.01)   # Re theta < 0.01: 4e-8 and 3e-3 only
+    assert Y.shape[1] == 2
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Y, X[:, 2:4]))) <= 1e-6
+    # a genuine value at 1e-9 of the largest is kept too
+    eigs2 = eigs.copy()
+    eigs2[2] = 4e-9
+    H2, X2 = _hessenberg_with_spectrum(eigs2, 2, symmetric)
+    theta, Y = O.ritz_select(H2, 1)
+    assert Y.shape[1] == 1
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Y, X2[:, 2:3]))) <= 1e-6
+    # with no null direction nothing is skipped
+    H3, X3 = _hessenberg_with_spectrum(eigs[2:], 3, symmetric)
+    theta, Y = O.ritz_select(H3, 2)
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Y, X3[:, 0:2]))) <= 1e-6
+
+
+def test_ritz_select_null_then_complex_pair():
+    """A complex pair right after the skipped null directions is kept whole."""
+    n = 8
+    D = np.zeros((n, n))
+    D[2, 2] = 4e-8
+    D[3:5, 3:5] = [[1e-3, 2e-4], [-2e-4, 1e-3]]   # eigenvalues 1e-3 +- 2e-4 i
+    for i, e in zip(range(5, n), (0.5, 1.0, 2.0)):
+        D[i, i] = e
+    rng = np.random.default_rng(4)
+    T = np.eye(n) + 0.4 * rng.standard_normal((n, n)) / np.sqrt(n)
+    H, U = scipy.linalg.hessenberg(T @ D @ np.linalg.inv(T), calc_q=True)
+    X = U.T @ T                                    # columns 3, 4 span the pair's real subspace
+    theta, Y = O.ritz_select(H, 2)
+    assert Y.shape[1] == 3
+    assert np.max(np.sin(scipy.linalg.subspace_angles(Y, X[:, 2:5]))) <= 1e-6
+
+
+def test_defl_build_order0_filter_skips_the_null_mode():
+    """An order-0 template filter leaves the intensity monopole unconstrained
+    (A 1_I = 0).  Arnoldi from a generic start vector runs until the Krylov
+    space is invariant, so a Ritz value at the rounding level appears; Z then
+    spans the eigenvectors of the k smallest non-null eigenvalues of the
+    dense M_BD A, and leaves the null vector out."""
+    p, pt, pf = _pf_problem(0, 0)
+    M = O.mbd_build(pt, pf)
+    n = pt.n
+    Bd = np.stack([O.mbd_apply(M, O.apply_A(pt, pf, e)) for e in np.eye(n)], axis=1)
+    ev, V = np.linalg.eig(Bd)
+    order = np.argsort(ev.real)
+    ev, V = ev[order], V[:, order]
+    assert abs(ev[0]) <= 1e-12 and ev[1].real >= 0.5   # one null mode, well separated
+    k = 5
+    assert ev[k + 1].real - ev[k].real >= 1e-3          # a clear gap after the k-th
+    b = np.random.default_rng(5).standard_normal(n)
+    M2, res, theta = O.defl_build(pt, pf, M, b, k, 1e-10, n)
+    assert res.m < n and np.min(np.abs(theta)) <= 1e-12  # the null Ritz value did appear
+    assert M2.Z.shape[1] == k
+    Vk = np.linalg.qr(V[:, 1:1 + k].real)[0]
+    assert np.max(np.sin(scipy.linalg.subspace_angles(M2.Z, Vk))) <= 1e-8
+    u = V[:, 0].real / np.linalg.norm(V[:, 0].real)
+    assert np.linalg.norm(u - M2.Z @ (M2.Z.T @ u)) >= 0.9   # the null vector is not in span(Z)
+
+
 def test_defl_build_smallest_ritz_span():
     """With the Arnoldi run to exhaustion the selected Z spans the invariant
     subspace of the k smallest eigenvalues of M_BD A."""
