@@ -68,29 +68,6 @@ void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz);
 
 using namespace mm;
 
-#define API_BEGIN(ctxp)                                   \
-    mm_ctx *api_ctx_ = (ctxp);                            \
-    try {                                                 \
-        if (api_ctx_) {                                   \
-            api_ctx_->last_error.clear();                 \
-            MM_HIP(hipSetDevice(api_ctx_->device));       \
-        }
-
-#define API_END                                                            \
-    }                                                                      \
-    catch (const mm::Error &e) {                                           \
-        if (api_ctx_) api_ctx_->last_error = e.what();                     \
-        return e.code;                                                     \
-    }                                                                      \
-    catch (const std::bad_alloc &) {                                       \
-        if (api_ctx_) api_ctx_->last_error = "host allocation failed";     \
-        return MM_E_OOM;                                                   \
-    }                                                                      \
-    catch (const std::exception &e) {                                      \
-        if (api_ctx_) api_ctx_->last_error = e.what();                     \
-        return MM_E_DEVICE;                                                \
-    }
-
 namespace {
 
 size_t tod_elem(mm_precision p) { return p == MM_F32 ? sizeof(float) : sizeof(double); }
@@ -564,10 +541,9 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
             MM_HIP(hipMemcpyAsync(nz->band.ptr, band, sizeof(double) * nb,
                                   hipMemcpyHostToDevice, s));
         }
-        // single-column direct-band tile table (first sample, interval) per
-        // tile, built here so that applies never rebuild it
-        nz->default_tile_len = band_tile_len(1);
-        set_band_tiles(ctx, nz, nz->default_tile_len);
+        // direct-band tile counts for every column count, built here so that
+        // applies never modify the handle
+        build_band_tiles(ctx, nz);
         if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
     } catch (...) {
         delete nz;

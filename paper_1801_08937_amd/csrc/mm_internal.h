@@ -107,8 +107,7 @@ struct mm_ctx {
     mm::DBuf gram_part, coef_g;    // MFMA Gram partials, coarse right-hand sides
     mm::DBuf xpack;                // map repacked for P: (I, Q, U, 0) records, or I and (Q, U) split
     mm::DBuf pt_part;              // per-segment partial maps of the sliced P^T
-    mm::DBuf tod_c;                // TOD temporary of the template filter
-    mm::DBuf pf_g;                 // ground-template chunk sums and amplitudes
+    mm::DBuf tod_c;                // template filter: filtered TOD, ground sums and amplitudes
     // Bumped whenever one of the workspaces above is reallocated: captured
     // graphs hold their addresses and are re-captured when it changes.
     uint64_t ws_gen = 0;
@@ -181,16 +180,11 @@ struct mm_noise {
     std::vector<int32_t> h_fid;
     std::vector<double> h_band;
     mm::DBuf istart, fid, band, band64;
-    // direct band: tile table
-    mm::DBuf tiles;  // int64 pairs (tile start sample, interval index)
-    int64_t n_tiles = 0;
-    int32_t tile_len = 0;
-    int32_t default_tile_len = 0;  // single-column tile of the direct band
-    // a second table for multi-column applies, whose tiles are longer (each
-    // block covers TL/R samples of all R columns)
-    mm::DBuf tiles_m;
-    int64_t n_tiles_m = 0;
-    int32_t tile_len_m = 0;
+    // direct band: per column count R = 2^li (li = 0..6), the number of
+    // tiles in the intervals before each interval, int64[7][n_int + 1]
+    // (device copy and host copy); built with the handle, read-only after
+    mm::DBuf tile_pref;
+    std::vector<int64_t> h_tile_pref;
     // FFT: per-filter packed spectrum and block table
     int32_t fft_n = 0;       // real block length
     int32_t fft_valid = 0;   // valid outputs per block
@@ -245,9 +239,18 @@ void pointing_slices_device(mm_ctx *ctx, mm_pointing *p, int32_t width);
 void pointing_p_slots_device(mm_ctx *ctx, mm_pointing *p, int32_t width);
 
 // tod_ops.hip
-void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y);
-void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x);
-void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
+// The P, P^T and N^-1 launchers take an optional device scratch region of at
+// least *_scratch_bytes(...) bytes (256-byte aligned); with nullptr they use
+// (and grow) the context's workspaces instead.
+size_t apply_P_scratch_bytes(const mm_pointing *p, int nrhs);
+size_t apply_PT_scratch_bytes(const mm_pointing *p, int nrhs);
+size_t noise_scratch_bytes(const mm_noise *nz, int nrhs);
+void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y,
+                 char *scratch = nullptr);
+void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x,
+                  char *scratch = nullptr);
+void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z,
+                     char *scratch = nullptr);
 int band_tile_len(int nrhs);
 void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_rm, void *y,
                   int *nonfinite_flag);
@@ -258,7 +261,9 @@ void noise_prepare(mm_ctx *ctx, mm_noise *nz);  // tiles, FFT spectra
 int polyfilter_max_order();
 void polyfilter_prepare(mm_ctx *ctx, const mm_pointing *p, mm_noise *nz,
                         const int32_t *ground_bin, int32_t n_ground_bins);
-void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
+size_t polyfilter_scratch_bytes(const mm_noise *nz, int nrhs);
+void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z,
+                          char *scratch = nullptr);
 bool noise_fft_supported(int half_bw, int64_t min_len);
 
 // map_ops.hip
@@ -330,10 +335,36 @@ template <typename T> struct Vec2T;
 template <> struct Vec2T<float> { using type = float2; };
 template <> struct Vec2T<double> { using type = double2; };
 
-void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl, bool multi = false);
+void build_band_tiles(mm_ctx *ctx, mm_noise *nz);
 void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *report, int *n_report);
 
 inline int log2i(int r) { int l = 0; while ((1 << l) < r) ++l; return l; }
 inline int pow2_ok(int r) { return r >= 1 && r <= 64 && (r & (r - 1)) == 0; }
 
 }  // namespace mm
+
+// Error handling at the C-ABI boundary: an mm::Error (or a host allocation
+// failure) inside API_BEGIN(ctx) ... API_END becomes the call's status and the
+// context's last-error message.
+#define API_BEGIN(ctxp)                                   \
+    mm_ctx *api_ctx_ = (ctxp);                            \
+    try {                                                 \
+        if (api_ctx_) {                                   \
+            api_ctx_->last_error.clear();                 \
+            MM_HIP(hipSetDevice(api_ctx_->device));       \
+        }
+
+#define API_END                                                            \
+    }                                                                      \
+    catch (const mm::Error &e) {                                           \
+        if (api_ctx_) api_ctx_->last_error = e.what();                     \
+        return e.code;                                                     \
+    }                                                                      \
+    catch (const std::bad_alloc &) {                                       \
+        if (api_ctx_) api_ctx_->last_error = "host allocation failed";     \
+        return MM_E_OOM;                                                   \
+    }                                                                      \
+    catch (const std::exception &e) {                                      \
+        if (api_ctx_) api_ctx_->last_error = e.what();                     \
+        return MM_E_DEVICE;                                                \
+    }

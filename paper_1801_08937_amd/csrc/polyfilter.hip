@@ -520,7 +520,16 @@ void polyfilter_prepare(mm_ctx *ctx, const mm_pointing *p, mm_noise *nz,
     if (ground_bin) ground_prepare(ctx, nz, ground_bin, n_ground_bins);
 }
 
-void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
+size_t polyfilter_scratch_bytes(const mm_noise *nz, int nrhs) {
+    if (nz->pf_nb == 0) return 0;
+    const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
+    const size_t n_part = (size_t)(nz->pf_n_gwave > 0 ? nz->pf_n_gwave : 1) * nrhs * 64;
+    const size_t n_ghat = (size_t)nz->pf_nb * nrhs;
+    return (te * (size_t)nz->n_samp * nrhs + 255) / 256 * 256 + te * (n_part + n_ghat);
+}
+
+void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z,
+                          char *scratch) {
     Scope sc(ctx->prof, ctx->stream, "Ninv_poly");
     const int NP = nz->pf_order + 1;
     hipStream_t s = ctx->stream;
@@ -556,13 +565,17 @@ void polyfilter_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void 
         MM_HIP(hipGetLastError());
         return;
     }
-    ws_alloc(ctx, ctx->tod_c, te * (size_t)nz->n_samp * nrhs);
+    // scratch: the filtered TOD y1, then the ground chunk sums and amplitudes
     const size_t n_part = (size_t)(nz->pf_n_gwave > 0 ? nz->pf_n_gwave : 1) * nrhs * 64;
     const size_t n_ghat = (size_t)nz->pf_nb * nrhs;
-    ws_alloc(ctx, ctx->pf_g, te * (n_part + n_ghat));
-    char *part = static_cast<char *>(ctx->pf_g.ptr);
+    const size_t y1_bytes = (te * (size_t)nz->n_samp * nrhs + 255) / 256 * 256;
+    if (!scratch) {
+        ws_alloc(ctx, ctx->tod_c, polyfilter_scratch_bytes(nz, nrhs));
+        scratch = static_cast<char *>(ctx->tod_c.ptr);
+    }
+    void *y1 = scratch;
+    char *part = scratch + y1_bytes;
     char *ghat = part + te * n_part;
-    void *y1 = ctx->tod_c.ptr;
     if (f32) {
         run(0.f, y, nullptr, false, y1);
         ground(0.f, y1, part, ghat);

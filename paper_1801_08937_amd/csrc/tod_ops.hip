@@ -422,7 +422,7 @@ constexpr int BT_OPT = 8;
 constexpr int BT_LDS = 65536;  // bytes of LDS per block
 
 template <typename T, int R>
-__global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ tiles,
+__global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ pref, int n_int,
                                                    const int64_t *__restrict__ istart,
                                                    const int32_t *__restrict__ fid,
                                                    const T *__restrict__ band, int lam, int CL,
@@ -436,9 +436,16 @@ __global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ t
     const int CLa = CL / BT_OPT * BT_OPT;
     T *sf = reinterpret_cast<T *>(smem_raw);  // CL taps
     T *sy = sf + CLa;                          // (TL + CL - 1) rows of R
-    const int64_t t0 = tiles[2 * blockIdx.x];
-    const int64_t iv = tiles[2 * blockIdx.x + 1];
+    // tile -> interval: pref[i] counts the tiles of intervals before i
+    const int64_t bt = blockIdx.x;
+    int lo = 0, hi = n_int;  // pref[lo] <= bt < pref[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= bt) lo = mid; else hi = mid;
+    }
+    const int64_t iv = lo;
     const int64_t a = istart[iv], b = istart[iv + 1];
+    const int64_t t0 = a + (bt - pref[iv]) * TL;
     const T *c = band + (int64_t)fid[iv] * (lam + 1);
     const int r = threadIdx.x % R;
     const int m0 = (threadIdx.x / R) * BT_OPT;
@@ -521,7 +528,8 @@ template <typename F> void dispatch_r(int nrhs, F &&f) {
 
 }  // namespace
 
-void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y) {
+void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, void *y,
+                 char *scratch) {
     Scope sc(ctx->prof, ctx->stream, "P");
     const int64_t n = p->n_samp;
     if (p->nc != 3) {
@@ -551,19 +559,22 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
         const bool slots = p->p_j.ptr != nullptr;
         const int copies = slots ? p->p_copies : 1;
         const size_t no = (size_t)(p->n_obs > 0 ? p->n_obs : 1) * copies;
-        ws_alloc(ctx, ctx->xpack, sizeof(double2) * 2 * no);
+        if (!scratch) {
+            ws_alloc(ctx, ctx->xpack, apply_P_scratch_bytes(p, nrhs));
+            scratch = static_cast<char *>(ctx->xpack.ptr);
+        }
+        double2 *xpack = reinterpret_cast<double2 *>(scratch);
         const int tuned = p->p_blocks[0];
         if (p->prec == MM_F32) {
             k_pack_map<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(
-                x, p->n_obs, copies, slots ? p->p_slot.as<int32_t>() : nullptr,
-                ctx->xpack.as<double2>());
+                x, p->n_obs, copies, slots ? p->p_slot.as<int32_t>() : nullptr, xpack);
             const int grid = tuned > 0 ? tuned : grid_for(n, 8 * ctx->n_cu * 4);
             k_apply_P1<float><<<grid, BS, 0, ctx->stream>>>(
-                slots ? p->p_j.as<int32_t>() : p->j.as<int32_t>(), p->w.as<float2>(), n,
-                ctx->xpack.as<double2>(), static_cast<float *>(y));
+                slots ? p->p_j.as<int32_t>() : p->j.as<int32_t>(), p->w.as<float2>(), n, xpack,
+                static_cast<float *>(y));
         } else {
             // xpack holds I (no doubles) then (Q, U) (no double2), no = n_obs x copies
-            double *xi = ctx->xpack.as<double>();
+            double *xi = reinterpret_cast<double *>(scratch);
             double2 *xqu = reinterpret_cast<double2 *>(xi + 2 * ((no + 1) / 2));
             k_pack_map_split<<<grid_for(p->n_obs, 1024), BS, 0, ctx->stream>>>(
                 x, p->n_obs, copies, slots ? p->p_slot.as<int32_t>() : nullptr, xi, xqu);
@@ -591,7 +602,20 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
     MM_HIP(hipGetLastError());
 }
 
-void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x) {
+size_t apply_P_scratch_bytes(const mm_pointing *p, int nrhs) {
+    if (p->nc != 3 || nrhs != 1) return 0;
+    const int copies = p->p_j.ptr != nullptr ? p->p_copies : 1;
+    return sizeof(double2) * 2 * (size_t)(p->n_obs > 0 ? p->n_obs : 1) * copies;
+}
+
+size_t apply_PT_scratch_bytes(const mm_pointing *p, int nrhs) {
+    if (p->nc != 3 || nrhs != 1 || p->sl_G <= 0 || p->n_obs == 0) return 0;
+    const int64_t parts = (int64_t)p->sl_S * p->sl_D;
+    return parts > 1 ? sizeof(double) * (size_t)(3 * (int64_t)p->n_obs * parts) : 0;
+}
+
+void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, double *x,
+                  char *scratch) {
     Scope sc(ctx->prof, ctx->stream, "PT");
     if (p->n_obs == 0) return;
     if (p->nc != 3) {
@@ -628,8 +652,11 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
         const int32_t parts = S * D;
         double *out = x;
         if (parts > 1) {
-            ws_alloc(ctx, ctx->pt_part, sizeof(double) * (size_t)(n3 * parts));
-            out = ctx->pt_part.as<double>();
+            if (!scratch) {
+                ws_alloc(ctx, ctx->pt_part, apply_PT_scratch_bytes(p, nrhs));
+                scratch = static_cast<char *>(ctx->pt_part.ptr);
+            }
+            out = reinterpret_cast<double *>(scratch);
         }
         const int32_t nv = D * p->n_obs;
         int64_t nb = ((int64_t)G * S + 3) / 4;
@@ -680,25 +707,28 @@ static int band_chunk(int lam, int R, mm_precision prec) {
     return cl < nf_pad ? cl : nf_pad;
 }
 
-void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
+size_t noise_scratch_bytes(const mm_noise *nz, int nrhs) {
+    return nz->method == MM_NOISE_POLY ? polyfilter_scratch_bytes(nz, nrhs) : 0;
+}
+
+void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z,
+                     char *scratch) {
     if (nz->method == MM_NOISE_FFT) {
         noise_fft_apply_dev(ctx, nz, nrhs, y, z);
         return;
     }
     if (nz->method == MM_NOISE_POLY) {
-        polyfilter_apply_dev(ctx, nz, nrhs, y, z);
+        polyfilter_apply_dev(ctx, nz, nrhs, y, z, scratch);
         return;
     }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
-    const bool multi = nrhs > 1;
     const int tl = band_tile_len(nrhs);
-    // the tables are built at noise build for one column and on first use for
-    // several (the single-column one is shared with background callers)
-    if (tl != (multi ? nz->tile_len_m : nz->tile_len))
-        set_band_tiles(ctx, const_cast<mm_noise *>(nz), tl, multi);
-    const int64_t *tiles = multi ? nz->tiles_m.as<int64_t>() : nz->tiles.as<int64_t>();
-    const unsigned n_tiles = (unsigned)(multi ? nz->n_tiles_m : nz->n_tiles);
+    // tile counts for every column count are built with the noise handle, so
+    // an apply never modifies it (handles may be shared across contexts)
+    const int li = log2i(nrhs);
+    const int64_t *pref = nz->tile_pref.as<int64_t>() + (int64_t)li * (nz->n_int + 1);
+    const unsigned n_tiles = (unsigned)nz->h_tile_pref[(size_t)li * (nz->n_int + 1) + nz->n_int];
     const int cl = band_chunk(lam, nrhs, nz->prec);
     const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
     const size_t sm = te * ((size_t)cl + (size_t)(tl + cl - 1) * nrhs);
@@ -706,11 +736,11 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
         constexpr int R = decltype(RR)::value;
         if (nz->prec == MM_F32)
             k_band_tiled<float, R><<<n_tiles, BS, sm, ctx->stream>>>(
-                tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<float>(), lam,
+                pref, nz->n_int, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<float>(), lam,
                 cl, static_cast<const float *>(y), static_cast<float *>(z));
         else
             k_band_tiled<double, R><<<n_tiles, BS, sm, ctx->stream>>>(
-                tiles, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<double>(),
+                pref, nz->n_int, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(), nz->band.as<double>(),
                 lam, cl, static_cast<const double *>(y), static_cast<double *>(z));
     });
     MM_HIP(hipGetLastError());
@@ -752,22 +782,22 @@ void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod, 
 
 namespace mm {
 
-// (Re)build the direct band's tile table for tile length tl (the
-// single-column table, or the multi-column one).
-void set_band_tiles(mm_ctx *ctx, mm_noise *nz, int tl, bool multi) {
-    std::vector<int64_t> tiles;
-    for (int i = 0; i < nz->n_int; ++i)
-        for (int64_t t = nz->h_istart[i]; t < nz->h_istart[i + 1]; t += tl) {
-            tiles.push_back(t);
-            tiles.push_back(i);
-        }
-    DBuf &buf = multi ? nz->tiles_m : nz->tiles;
-    buf.alloc(sizeof(int64_t) * tiles.size());
-    MM_HIP(hipMemcpyAsync(buf.ptr, tiles.data(), sizeof(int64_t) * tiles.size(),
-                          hipMemcpyHostToDevice, ctx->stream));
+// Tile counts of the direct band for every column count R = 2^li (tile
+// length band_tile_len(R)): pref[li][i] = tiles in the intervals before i.
+void build_band_tiles(mm_ctx *ctx, mm_noise *nz) {
+    const size_t np = (size_t)nz->n_int + 1;
+    nz->h_tile_pref.assign(7 * np, 0);
+    for (int li = 0; li < 7; ++li) {
+        const int64_t tl = band_tile_len(1 << li);
+        int64_t *pr = nz->h_tile_pref.data() + li * np;
+        for (int i = 0; i < nz->n_int; ++i)
+            pr[i + 1] = pr[i] + (nz->h_istart[i + 1] - nz->h_istart[i] + tl - 1) / tl;
+    }
+    nz->tile_pref.alloc(sizeof(int64_t) * nz->h_tile_pref.size());
+    MM_HIP(hipMemcpyAsync(nz->tile_pref.ptr, nz->h_tile_pref.data(),
+                          sizeof(int64_t) * nz->h_tile_pref.size(), hipMemcpyHostToDevice,
+                          ctx->stream));
     MM_HIP(hipStreamSynchronize(ctx->stream));
-    (multi ? nz->tile_len_m : nz->tile_len) = tl;
-    (multi ? nz->n_tiles_m : nz->n_tiles) = (int64_t)tiles.size() / 2;
 }
 
 // Measure candidate launch shapes with HIP events and keep the fastest: the
