@@ -45,6 +45,7 @@
 #ifndef MAPMAKER_H
 #define MAPMAKER_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -260,6 +261,22 @@ mm_status mm_apply_PT(mm_ctx *ctx, const mm_pointing *p, int32_t nrhs, const voi
  * and n_samp. */
 mm_status mm_apply_A(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, int32_t nrhs,
                      const double *x, double *y);
+/* y = A x as mm_apply_A, allocating nothing: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The temporaries (two TOD vectors of
+ * nrhs columns and the largest stage scratch) live in one static device
+ * array per GPU of mm_apply_A_noalloc_max_bytes() bytes (128 MiB; about 4e6
+ * FP64 or 8e6 FP32 samples at nrhs = 1), held until the process ends.
+ * Same kernels and bitwise the same result as mm_apply_A.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * contexts or threads) race, and must be serialised by the caller.
+ *   scratch_used [host] or NULL: bytes of scratch this call needs.
+ * Errors: MM_E_INVALID (as mm_apply_A, or a problem needing more scratch than
+ * the maximum; use mm_apply_A there).  Per-stage profiling is not recorded. */
+mm_status mm_apply_A_noalloc(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                             int32_t nrhs, const double *x, double *y, size_t *scratch_used);
+/* Size in bytes of the static scratch array of mm_apply_A_noalloc. */
+size_t mm_apply_A_noalloc_max_bytes(void);
 /* b = P^T N^-1 (mask . d): flagged samples are zeroed before weighting.
  * tod [device] TOD precision, layout [nrhs][n_samp] (each realisation
  * contiguous); b [device] f64 map layout.  Errors: MM_E_NONFINITE. */

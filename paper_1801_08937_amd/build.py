@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libmapmaker.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["pointing.hip", "tod_ops.hip", "noise_fft.hip", "noise_fft_big.hip", "polyfilter.hip",
-           "map_ops.hip", "api.cpp", "eig.cpp", "serve.cpp"]
+           "map_ops.hip", "api.cpp", "eig.cpp", "serve.cpp", "noalloc.hip"]
 ARCH = os.environ.get("MM_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code (-packed-fp32-ops).

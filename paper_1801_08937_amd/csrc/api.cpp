@@ -305,6 +305,7 @@ extern "C" mm_status mm_ctx_create(int device, void *hip_stream, mm_ctx **out) {
         hipDeviceProp_t prop;
         MM_HIP(hipGetDeviceProperties(&prop, device));
         ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        noalloc_init(device);
         *out = ctx;
         return MM_OK;
     } catch (const mm::Error &e) {

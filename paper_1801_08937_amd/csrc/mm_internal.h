@@ -368,3 +368,10 @@ inline int pow2_ok(int r) { return r >= 1 && r <= 64 && (r & (r - 1)) == 0; }
         if (api_ctx_) api_ctx_->last_error = e.what();                     \
         return MM_E_DEVICE;                                                \
     }
+
+namespace mm {
+// Looks up, once per device and with that device current, the device address
+// of the static scratch array of mm_apply_A_noalloc (called at context
+// creation).
+void noalloc_init(int device);
+}  // namespace mm

@@ -98,6 +98,8 @@ def lib() -> C.CDLL:
             "mm_defl_build_pcg": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, P, PP]),
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
             "mm_defl_transfer": (C.c_int, [P, P, P, P, P, P, PP]),
+            "mm_apply_A_noalloc": (C.c_int, [P, P, P, I32, P, P, C.POINTER(C.c_size_t)]),
+            "mm_apply_A_noalloc_max_bytes": (C.c_size_t, []),
             "mm_defl_export": (C.c_int, [P, P, C.POINTER(I32), P, P, P]),
             "mm_defl_arnoldi_export": (C.c_int, [P, P, C.POINTER(I32), P, P]),
             "mm_precond_apply": (C.c_int, [P, P, I32, P, P]),
@@ -314,6 +316,17 @@ class Context:
             y = torch.empty_like(x)
         self._check(lib().mm_apply_A(self.h, p.h, nz.h, nrhs, _ptr(x), _ptr(y)), "mm_apply_A")
         return y
+
+    def apply_A_noalloc(self, p, nz, x, y, nrhs: int = 1) -> int:
+        """y = A x with no device allocation (the library's static scratch);
+        y must be given.  Returns the scratch bytes the call needed."""
+        import torch
+        _dev_check(x, torch.float64, p.n * nrhs, "x")
+        _dev_check(y, torch.float64, p.n * nrhs, "y")
+        used = C.c_size_t(0)
+        self._check(lib().mm_apply_A_noalloc(self.h, p.h, nz.h, nrhs, _ptr(x), _ptr(y),
+                                             C.byref(used)), "mm_apply_A_noalloc")
+        return used.value
 
     def rhs(self, p, nz, tod, b=None, nrhs: int = 1):
         import torch
