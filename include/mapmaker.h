@@ -451,7 +451,10 @@ void mm_pcg_destroy(mm_pcg *s);
  * requests of that strategy are solved with M_BD.  mm_server_step admits
  * queued requests into free column slots of the strategy's lockstep PCG
  * session for the current preconditioner -- also while other slots are
- * mid-solve -- runs `iters_per_step` iterations on every session with running
+ * mid-solve; a lane's session is created (and charged against the budget)
+ * when it admits its first request, and idle sessions are evicted when a
+ * waiting request needs their memory -- runs `iters_per_step` iterations on
+ * every session with running
  * slots (all streams enqueued before any is waited on, so strategies overlap
  * on the device), and retires finished slots into the caller's output
  * buffers.  A request's result does not depend on which other requests share
@@ -464,13 +467,16 @@ typedef struct {
     int32_t slot;
     int32_t m2l_built;      /* 1 if this request started the M_2l build (cache miss) */
     int32_t precond;        /* preconditioner it runs with: 0 M_BD, 1 M_2l; -1 queued */
-    int32_t reserved;
+    int32_t waited;         /* what it waited for before admission (bits): 1 a free slot
+                               of its lane's session, 2 memory for that session */
     double rel_res;         /* recursive ||r|| / ||b|| at exit */
     double queue_seconds;   /* submit -> admitted */
     double latency_seconds; /* submit -> done (or now) */
 } mm_request_info;
 
-/* hbm_budget_bytes: cap on the library memory of all registered strategies;
+/* hbm_budget_bytes: cap on the library memory of the server: every
+ * registered strategy's resident part plus every live lane session (see
+ * mm_server_memory);
  * slots: columns per strategy session (1..64, power of two); defl_k: M_2l
  * deflation vectors (0 = M_BD only); iters_per_step: PCG iterations per step. */
 mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots, int32_t defl_k,
@@ -485,7 +491,8 @@ mm_status mm_server_set_prebuild(mm_server *srv, int32_t on);
 /* Register a scan strategy; arguments as mm_pointing_build / mm_noise_build
  * (pix, psi [device] are read during the call only; grid_width as
  * mm_pointing_set_grid, 0 = none).  Errors: MM_E_BUSY if its estimated
- * footprint exceeds the remaining budget; the build errors otherwise. */
+ * resident footprint plus one lane session exceeds the budget left by the
+ * other strategies' resident parts; the build errors otherwise. */
 mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t n_samp, int32_t n_pix_total,
                                  const int32_t *pix, const double *psi, int32_t min_hits,
                                  int32_t grid_width, int32_t n_intervals,
@@ -503,6 +510,15 @@ mm_status mm_server_step(mm_server *srv, int32_t *n_running, int32_t *n_queued);
  * 3 build failed (its requests keep M_BD).  [host] output. */
 mm_status mm_server_strategy_state(mm_server *srv, int32_t strategy, int32_t *m2l_state);
 mm_status mm_server_poll(mm_server *srv, int64_t request_id, mm_request_info *info);
+/* Memory accounting [host] outputs, any may be NULL: the budget, the bytes in
+ * use (resident parts of all strategies plus live sessions), and for
+ * `strategy` its resident bytes (pointing, noise, M_BD, M_2l build reserve,
+ * charged at registration) and the bytes of one lane session (`slots`
+ * columns of PCG vectors and TOD workspaces, charged when the lane admits its
+ * first request and released when the idle session is evicted to make room
+ * for another). */
+mm_status mm_server_memory(mm_server *srv, int32_t strategy, int64_t *budget, int64_t *used,
+                           int64_t *resident, int64_t *session);
 const char *mm_server_last_error(const mm_server *srv);
 void mm_server_destroy(mm_server *srv);
 

@@ -14,8 +14,17 @@
 // on the strategy's stream), runs a chunk of iterations on every lane with
 // running slots -- enqueued on all streams before any is waited on, so
 // strategies overlap on the device -- and retires finished slots, writing
-// each solution to the caller's buffer.  Memory is admitted against a byte
-// budget when a strategy is registered.
+// each solution to the caller's buffer.
+//
+// Memory is admitted against a byte budget in two parts.  A strategy's
+// resident data (pointing, noise, M_BD, the M_2l build's reserve) is charged
+// when it is registered.  A lane's session -- its `slots` columns of PCG
+// vectors and the strategy context's TOD workspaces for that many columns --
+// is charged when the lane first admits a request, and stays (cached) while
+// memory allows; a request whose lane has no session and whose session does
+// not fit waits for memory, and idle sessions of other lanes are evicted (their
+// memory freed) to make room.  A request joining a session with a free slot
+// needs no new memory; one whose session is full waits for a slot.
 #include <atomic>
 #include <chrono>
 #include <deque>
@@ -46,11 +55,13 @@ struct Request {
     double t_submit = 0, t_start = 0, t_done = 0;
     int32_t m2l_built = 0;  // 1 if this request triggered the M_2l build
     int32_t lane = 0;       // 0 = M_BD session, 1 = M_2l session
+    int32_t waited = 0;     // what it waited for before admission: 1 slot, 2 memory
 };
 
 // One PCG session of a strategy and the request held by each of its slots.
 struct Lane {
     mm_pcg *sess = nullptr;
+    int64_t charged = 0;  // bytes of the budget this session holds
     std::vector<int64_t> slot_req;
     bool busy() const {
         for (auto q : slot_req)
@@ -70,7 +81,8 @@ struct Strategy {
     mm_precond *m2l = nullptr;  // adopted once the background build is ready
     Lane lane[2];
     mm::DBuf b;
-    size_t bytes = 0;
+    int64_t bytes = 0;         // resident part, charged at registration
+    int64_t session_bytes = 0; // one lane session of `slots` columns
     int64_t n = 0;
     // background M_2l build: its own context and stream, seeded with a copy
     // of the first request's b; it only reads p, nz and mbd
@@ -138,6 +150,28 @@ static void check(mm_status st, mm_ctx *ctx, const char *what) {
     if (st < 0) throw Error(st, std::string(what) + ": " + mm_last_error(ctx));
 }
 
+// Resident footprint of a strategy: per sample, the pointing (compact pixel,
+// weights, permutation, sorted weights, the angle in the FP64 form, the
+// sliced P^T entries with ~10 % padding, P's map-copy slot with a grid);
+// per unknown, M_BD, b and the M_2l reserve (Z, AZ, the Arnoldi basis); and
+// the single-column TOD workspaces of the M_2l builder's context.
+static int64_t resident_bytes(const mm_server *srv, int64_t n_samp, int64_t est_n, int64_t te,
+                              bool grid) {
+    const int64_t per_samp = 4 + 2 * 2 * te + 4 + (te == 4 ? 0 : 8) + 14 + (grid ? 4 : 0);
+    return n_samp * per_samp + 2 * n_samp * te +
+           est_n * 8 * (4 + 2 * srv->defl_k + srv->m_max + 2);
+}
+
+// One lane session of `slots` columns: the session's column vectors (x, r,
+// z, p, q) and its single-column buffer, the strategy context's TOD
+// workspaces for `slots` columns, and the sliced P^T's partial maps of the
+// right-hand side.
+static int64_t session_bytes(const mm_server *srv, int64_t n_samp, int64_t n, int64_t n_obs,
+                             int64_t te) {
+    return 8 * n * (5 * (int64_t)srv->slots + 1) + 2 * n_samp * te * srv->slots +
+           8 * 3 * n_obs * 64;
+}
+
 extern "C" mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots,
                                       int32_t defl_k, int32_t iters_per_step,
                                       mm_server **out) {
@@ -190,13 +224,14 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
     // sessions' vectors, M_2l (Z, AZ, W basis)
     const int64_t te = prec == MM_F32 ? 4 : 8;
     const int64_t est_n = 3 * (int64_t)std::min<int64_t>(n_pix_total, n_samp);
-    const int64_t per_samp =
-        4 + 2 * 2 * te + 4 + (prec == MM_F32 ? 0 : 8) + 14 + (grid_width > 0 ? 4 : 0);
-    const int64_t bytes = n_samp * per_samp + 2 * n_samp * te * (srv->slots + 1) +
-                          est_n * 8 * (14 * srv->slots + 2 * srv->defl_k + srv->m_max + 2);
-    if (srv->used + bytes > srv->budget)
-        throw Error(MM_E_BUSY, "server: strategy footprint " + std::to_string(bytes) +
-                                   " B exceeds the remaining budget");
+    const int64_t bytes = resident_bytes(srv, n_samp, est_n, te, grid_width > 0);
+    // its resident part, and room for one lane session once the other
+    // strategies' sessions are evicted
+    const int64_t sess = session_bytes(srv, n_samp, est_n, est_n / 3, te);
+    if (srv->used + bytes + sess > srv->budget)
+        throw Error(MM_E_BUSY, "server: strategy footprint " + std::to_string(bytes) + " B + " +
+                                   std::to_string(sess) +
+                                   " B for a session exceeds the remaining budget");
     auto st = std::make_unique<Strategy>();
     st->id = id;
     check(mm_ctx_create(srv->device, nullptr, &st->ctx), nullptr, "server: context");
@@ -237,6 +272,7 @@ extern "C" mm_status mm_server_add_strategy(mm_server *srv, int32_t id, int64_t 
     }
     for (auto &l : st->lane) l.slot_req.assign(srv->slots, -1);
     st->bytes = bytes;
+    st->session_bytes = session_bytes(srv, n_samp, st->n, st->p->n_obs, te);
     srv->used += bytes;
     srv->strat[id] = std::move(st);
     SRV_END
@@ -298,7 +334,37 @@ static void start_build(mm_server *srv, Strategy &st) {
     });
 }
 
-// Admit queued requests (FIFO per strategy) into free slots.
+// Free a lane's session and its charge.  With both lanes of the strategy
+// idle, the context's TOD workspaces go too.
+static void evict(mm_server *srv, Strategy &st, Lane &ln) {
+    mm_pcg_destroy(ln.sess);
+    ln.sess = nullptr;
+    srv->used -= ln.charged;
+    ln.charged = 0;
+    if (!st.lane[0].sess && !st.lane[1].sess) {
+        MM_HIP(hipStreamSynchronize(st.ctx->stream));
+        for (mm::DBuf *d : {&st.ctx->tod_a, &st.ctx->tod_b, &st.ctx->tod_c, &st.ctx->pt_part,
+                            &st.ctx->xpack})
+            d->release();
+        ++st.ctx->ws_gen;
+    }
+}
+
+// Make room for `need` bytes by evicting idle sessions other than `keep`;
+// true if the budget then has room.
+static bool make_room(mm_server *srv, int64_t need, const Lane *keep) {
+    if (srv->used + need <= srv->budget) return true;
+    for (auto &kv : srv->strat)
+        for (auto &ln : kv.second->lane) {
+            if (&ln == keep || !ln.sess || ln.busy()) continue;
+            evict(srv, *kv.second, ln);
+            if (srv->used + need <= srv->budget) return true;
+        }
+    return srv->used + need <= srv->budget;
+}
+
+// Admit queued requests (FIFO per strategy, no head-of-line blocking across
+// strategies) into free slots, creating a lane's session when memory allows.
 static void admit(mm_server *srv) {
     for (auto it = srv->queue.begin(); it != srv->queue.end();) {
         Request &r = srv->req[*it];
@@ -306,6 +372,11 @@ static void admit(mm_server *srv) {
         poll_build(st);
         const int li = st.m2l ? 1 : 0;
         Lane &ln = st.lane[li];
+        if (!ln.sess && !make_room(srv, st.session_bytes, &ln)) {
+            r.waited |= 2;  // waits for memory
+            ++it;
+            continue;
+        }
         int slot = -1;
         for (int c = 0; c < srv->slots; ++c)
             if (ln.slot_req[c] < 0) {
@@ -313,10 +384,17 @@ static void admit(mm_server *srv) {
                 break;
             }
         if (slot < 0) {
+            r.waited |= 1;  // waits for a slot
             ++it;
             continue;
         }
         mm_ctx *ctx = st.ctx;
+        if (!ln.sess) {
+            const mm_precond *M = li ? st.m2l : st.mbd;
+            check(mm_pcg_create(ctx, st.p, st.nz, M, srv->slots, &ln.sess), ctx, "server: session");
+            ln.charged = st.session_bytes;
+            srv->used += ln.charged;
+        }
         mm_status s = mm_rhs(ctx, st.p, st.nz, 1, r.tod, st.b.as<double>());
         if (s < 0) {
             r.state = 4;
@@ -328,10 +406,6 @@ static void admit(mm_server *srv) {
             // cache miss: build M_2l from this request's right-hand side, in the background
             start_build(srv, st);
             r.m2l_built = 1;
-        }
-        if (!ln.sess) {
-            const mm_precond *M = li ? st.m2l : st.mbd;
-            check(mm_pcg_create(ctx, st.p, st.nz, M, srv->slots, &ln.sess), ctx, "server: session");
         }
         check(mm_pcg_start(ctx, ln.sess, slot, st.b.as<double>(), r.tol, r.max_iter), ctx,
               "server: start");
@@ -409,10 +483,26 @@ extern "C" mm_status mm_server_poll(mm_server *srv, int64_t request_id, mm_reque
     info->slot = r.slot;
     info->m2l_built = r.m2l_built;
     info->precond = r.state >= 1 ? (r.lane ? 1 : 0) : -1;
-    info->reserved = 0;
+    info->waited = r.waited;
     info->rel_res = r.rel_res;
     info->queue_seconds = (r.state >= 1 ? r.t_start : now_s()) - r.t_submit;
     info->latency_seconds = (r.state >= 2 ? r.t_done : now_s()) - r.t_submit;
+    SRV_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_server_memory(mm_server *srv, int32_t strategy, int64_t *budget,
+                                      int64_t *used, int64_t *resident, int64_t *session) {
+    if (!srv) return MM_E_INVALID;
+    SRV_TRY
+    if (budget) *budget = srv->budget;
+    if (used) *used = srv->used;
+    if (resident || session) {
+        auto it = srv->strat.find(strategy);
+        MM_CHECK(it != srv->strat.end(), MM_E_INVALID, "server: unknown strategy");
+        if (resident) *resident = it->second->bytes;
+        if (session) *session = it->second->session_bytes;
+    }
     SRV_END
     return MM_OK;
 }

@@ -44,7 +44,7 @@ class SolveInfo(C.Structure):
 
 class RequestInfo(C.Structure):
     _fields_ = [("state", C.c_int32), ("iters", C.c_int32), ("slot", C.c_int32),
-                ("m2l_built", C.c_int32), ("precond", C.c_int32), ("reserved", C.c_int32),
+                ("m2l_built", C.c_int32), ("precond", C.c_int32), ("waited", C.c_int32),
                 ("rel_res", C.c_double),
                 ("queue_seconds", C.c_double), ("latency_seconds", C.c_double)]
 
@@ -116,6 +116,7 @@ def lib() -> C.CDLL:
             "mm_server_poll": (C.c_int, [P, I64, C.POINTER(RequestInfo)]),
             "mm_server_strategy_state": (C.c_int, [P, I32, C.POINTER(I32)]),
             "mm_server_last_error": (C.c_char_p, [P]),
+            "mm_server_memory": (C.c_int, [P, I32] + [C.POINTER(I64)] * 4),
             "mm_server_destroy": (None, [P]),
             "mm_profile_read": (C.c_int, [P, I32, P, P, P, C.POINTER(I32)]),
             "mm_hessenberg_eig": (C.c_int, [I32, P, P, P, P, P]),
@@ -690,6 +691,19 @@ class Server:
         info = RequestInfo()
         self._check(lib().mm_server_poll(self.h, rid, C.byref(info)), "mm_server_poll")
         return {f: getattr(info, f) for f, _ in RequestInfo._fields_}
+
+    def memory(self, sid: int = -1) -> dict:
+        """Budget, bytes in use, and (for a registered strategy sid) its
+        resident bytes and the bytes of one lane session."""
+        v = [C.c_int64() for _ in range(4)]
+        self._check(lib().mm_server_memory(self.h, sid, C.byref(v[0]), C.byref(v[1]),
+                                           C.byref(v[2]) if sid >= 0 else None,
+                                           C.byref(v[3]) if sid >= 0 else None),
+                    "mm_server_memory")
+        out = {"budget": v[0].value, "used": v[1].value}
+        if sid >= 0:
+            out.update(resident=v[2].value, session=v[3].value)
+        return out
 
     def close(self):
         if getattr(self, "h", None):

@@ -160,8 +160,9 @@ def test_server_continuous_batching_many(mm):
     srv.close()
     assert all(i["state"] == 2 for i in infos)
     assert sum(i["m2l_built"] for i in infos) == 2   # one M_2l per strategy, then cached
-    # more requests than slots: some waited in the queue and were admitted later
+    # more requests than slots: some waited in the queue for a slot and were admitted later
     assert max(i["queue_seconds"] for i in infos) > 0
+    assert any(i["waited"] & 1 for i in infos) and not any(i["waited"] & 2 for i in infos)
     errs = _check_vs_oracle(outs, infos, [t for _, _, t in reqs])
     print("14 requests vs oracle (map error, true residual):", errs)
 
@@ -198,3 +199,40 @@ def test_server_prebuilt_m2l(mm):
         assert torch.equal(oa[0], ob[0])
     errs = _check_vs_oracle(outs_b, infos_b, [t for _, _, t in reqs])
     print("prebuilt M_2l vs oracle (map error, true residual):", errs)
+
+
+def test_server_admits_by_memory(mm):
+    """Admission by HBM footprint: with a budget that holds both strategies'
+    resident data but only one lane session, a request of the second
+    strategy waits for memory -- with its lane's slots all free -- while the
+    first strategy's session runs, and is admitted once that request retires
+    and its idle session is evicted.  Both maps are bitwise the solo ones
+    and solve their systems (oracle bar)."""
+    import torch
+    big = mm.Server(0, hbm_budget_bytes=8 << 30, slots=4, defl_k=0, iters_per_step=3)
+    for s in range(2):
+        p = _strategy(s, 0)
+        big.add_strategy(s, dev(p.pix), dev(p.psi), p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+    mem = [big.memory(s) for s in range(2)]
+    reqs = [(0, 31, 1e-8), (1, 32, 1e-8)]
+    infos_a, outs_a = _run_each_alone(big, reqs)
+    big.close()
+    budget = mem[0]["resident"] + mem[1]["resident"] + max(m["session"] for m in mem) + 1
+    assert budget < mem[0]["resident"] + mem[1]["resident"] + mem[0]["session"] + mem[1]["session"]
+    srv = mm.Server(0, hbm_budget_bytes=budget, slots=4, defl_k=0, iters_per_step=3)
+    for s in range(2):
+        p = _strategy(s, 0)
+        srv.add_strategy(s, dev(p.pix), dev(p.psi), p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+    assert srv.memory()["used"] == mem[0]["resident"] + mem[1]["resident"]
+    infos_b, outs_b = _run(srv, reqs, join_after=0)
+    assert srv.memory()["used"] <= budget
+    srv.close()
+    print("memory:", mem, "budget", budget, "requests:", infos_b)
+    assert infos_b[0]["waited"] == 0
+    assert infos_b[1]["waited"] & 2 and not infos_b[1]["waited"] & 1   # memory, not a slot
+    assert infos_b[1]["queue_seconds"] > 0
+    for oa, ob in zip(outs_a, outs_b):
+        assert torch.equal(oa[0], ob[0])
+    _check_vs_oracle(outs_b, infos_b, [t for _, _, t in reqs])
