@@ -789,7 +789,7 @@ def _n1_size(mm, ctx, lams, n_samp, L, dev, ev):
 
 def form_d1(mm, ctx, n_sub=8, full_m2l=2):
     """Divide and conquer with the "simplified" two-level preconditioner
-    (Sect. 6.3): the config-2 scan split by detectors into n_sub subsets over
+    (Sect. 7.3): the config-2 scan split by detectors into n_sub subsets over
     the same patch, each filtered as in form f1 (white noise, quadratic
     polynomials per 256-sample subscan).  Z is built once, by Arnoldi on
     subset 0, and reused on the others with AZ and E rebuilt per subset; each

@@ -16,7 +16,7 @@
  *     M_2l = M_BD (1 - A Z E^-1 Z^T) + Z E^-1 Z^T,   E = Z^T A Z   (Eq. m2l)
  *
  * whose deflation space Z is built from Ritz vectors of an Arnoldi run on
- * M_BD A (Sect. 5, Appendix A).
+ * M_BD A (Sect. 6, Appendix A).
  *
  * Conventions
  *  - Every call returns mm_status.  MM_OK = 0.  MM_NOT_CONVERGED = 1 is a
@@ -112,7 +112,7 @@ const char *mm_version(void);
 /* Build P from per-sample pixels and angles (Eq. datamodel).  Samples with
  * pix = -1 are flagged.  Pixels with fewer than min_hits unflagged samples
  * are dropped and their samples flagged too (the paper keeps only pixels
- * observed with enough redundancy, Sect. 4).  Observed pixels get compact
+ * observed with enough redundancy, Sect. 5).  Observed pixels get compact
  * ids 0..n_obs-1 in ascending global id.
  *   n_samp       number of samples, 0 < n_samp < 2^31
  *   n_pix_total  number of global pixels; pix must lie in [-1, n_pix_total)
@@ -234,15 +234,23 @@ mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int32_t n_inter
                               mm_noise **out);
 /* The method actually used (MM_NOISE_DIRECT, MM_NOISE_FFT or MM_NOISE_POLY). */
 mm_status mm_noise_method_used(const mm_noise *nz, mm_noise_method *method);
-/* Overlap-save block geometry of the FFT method (Sect. 3, the Toeplitz apply
- * as a circulant product): each block transforms *n_fft samples and keeps
+/* Overlap-save block geometry of the FFT method (a way of applying the
+ * banded W = N^-1 of Sect. 2: each interval's Toeplitz block as circulant
+ * products of blocks): each block transforms *n_fft samples and keeps
  * *n_valid = *n_fft - 2 lambda outputs.  Both 0 for the direct method.
- * *n_fft is 16,384 or 32,768, picked at build by a measured time model
- * (blocks run in waves of one per compute unit; a block costs a fixed time,
- * 1.56 times more for the large size, plus a term per input sample read),
- * so it depends on the interval lengths, lambda (16,384 only up to 2,048)
- * and the device's compute-unit count. */
+ * *n_fft is 16,384 (lambda <= 6,144; two blocks share a compute unit) or
+ * 32,768 (one block per compute unit), picked at build by a measured time
+ * model (blocks run in waves over the compute units; a wave of the large
+ * blocks takes 1.1 times as long), so it depends on the interval lengths,
+ * lambda and the device's compute-unit count; mm_noise_set_fft_block and
+ * mm_autotune can change it. */
 mm_status mm_noise_fft_block(const mm_noise *nz, int32_t *n_fft, int32_t *n_valid);
+/* Rebuild the FFT method's tables for blocks of n_fft real samples: 16,384
+ * (lambda <= 6,144) or 32,768, or 0 for the time model's pick.  Results are
+ * the same to rounding (<= 1e-11 relative in FP64), not bitwise.  The handle
+ * is modified: no other call may use it meanwhile.  Errors: MM_E_INVALID for
+ * a non-FFT handle or an unsupported size. */
+mm_status mm_noise_set_fft_block(mm_ctx *ctx, mm_noise *nz, int32_t n_fft);
 /* z = N^-1 y (or z = F y for a template filter) on the TOD layout.  y, z
  * [device], TOD precision, distinct. */
 mm_status mm_noise_apply(mm_ctx *ctx, const mm_noise *nz, int32_t nrhs, const void *y, void *z);
@@ -301,7 +309,7 @@ typedef struct {
     double setup_seconds; /* wall time of the whole build */
 } mm_arnoldi_info;
 
-/* M_2l from Ritz vectors (Sect. 5, Appendix A): Arnoldi on B = M_BD A from
+/* M_2l from Ritz vectors (Sect. 6, Appendix A): Arnoldi on B = M_BD A from
  * r_0 = M_BD b_seed, classical Gram-Schmidt applied twice, until
  * h_{j+1,j} <= eps_arn or m_max steps; eigenpairs of H_m ordered by real
  * part; keep the k smallest (k+1 rather than split a complex pair) or, if
@@ -397,7 +405,7 @@ typedef struct {
  * on FP64 MFMA and numerically dependent directions are dropped):  r = b - A x; z = M r; p = z; rho = r.z; repeat q = A p;
  * alpha = rho / p.q; x += alpha p; r -= alpha q; z = M r; rho' = r.z;
  * beta = rho'/rho; p = z + beta p -- until ||r|| / ||b|| <= tol (the
- * unpreconditioned residual, Sect. 6.1) or max_iter.  M may be NULL (no
+ * unpreconditioned residual, Sect. 7.1) or max_iter.  M may be NULL (no
  * preconditioner), an M_BD or an M_2l handle.
  *   b [device] f64 map layout; x [device] in: x_0, out: solution
  *   history [host] f64[nrhs][max_iter+1] or NULL: ||r_k||/||b|| per column
@@ -445,7 +453,7 @@ void mm_pcg_destroy(mm_pcg *s);
  * strategies on one GPU, continuously batched.  Each strategy gets its own
  * context (HIP stream), pointing, noise and M_BD at registration, and a
  * two-level M_2l built from its first request's right-hand side and reused for
- * every later request of that strategy (Sect. 6.3.2: M_2l pays off when the
+ * every later request of that strategy (Sect. 7.3: M_2l pays off when the
  * same system is solved many times).  The M_2l build runs on a host thread of
  * its own (own context and stream) and blocks no request: until it is ready,
  * requests of that strategy are solved with M_BD.  mm_server_step admits

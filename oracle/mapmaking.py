@@ -6,8 +6,8 @@ estimate solves A x = b with A = P^T W P, b = P^T W d (Eqs. estimator,
 linearsystem); here W = N^-1 is a banded Toeplitz matrix per stationary
 interval.  Preconditioners: M_BD (Eq. mbd) and M_2l (Eq. m2l) with E = Z^T A Z.
 The deflation space comes from Ritz vectors of an Arnoldi run on B = M_BD A
-(Sect. 5 and Appendix A, Alg. arnoldi, Eqs. factoriz and ritz).  The solver is
-PCG (Eq. pcg) with the relative residual of the metric in Sect. 6.1.
+(Sect. 6 and Appendix A, Alg. arnoldi, Eqs. factoriz and ritz).  The solver is
+PCG (Eq. pcg) with the relative residual of the metric in Sect. 7.1.
 
 Readings where the paper is silent or garbled (each is listed in the design doc):
   * residual: the stop test and the reported residual use the
@@ -50,7 +50,7 @@ class OracleError(RuntimeError):
 
 
 # ---------------------------------------------------------------------------
-# O1  pointing  (Eqs. probl, datamodel; observed-pixel selection, Sect. 4)
+# O1  pointing  (Eqs. probl, datamodel; observed-pixel selection, Sect. 5)
 # ---------------------------------------------------------------------------
 
 @dataclasses.dataclass
@@ -609,7 +609,7 @@ def ritz_select(H_m: np.ndarray, k: int, eps_lambda: float = 0.0):
 def defl_build(pt: Pointing, nz: Noise, mbd: Mbd, b_seed, k: int, eps_arn: float,
                m_max: int, eps_lambda: float = 0.0, method: str = "direct",
                reorth: bool = True):
-    """Deflation space from Ritz vectors of B = M_BD A (Sect. 5): Arnoldi from
+    """Deflation space from Ritz vectors of B = M_BD A (Sect. 6): Arnoldi from
     r_0 = M_BD b_seed, Ritz selection, V = W_m Y, Z = Q of a Householder QR
     of V (numpy's QR).  Returns (M2l, ArnoldiResult, theta)."""
     r0 = mbd_apply(mbd, b_seed)
@@ -701,7 +701,7 @@ def defl_build_pcg(pt: Pointing, nz: Noise, mbd: Mbd, b, k: int, m: int, tol: fl
 
 
 # ---------------------------------------------------------------------------
-# O10  PCG (Eq. pcg; stop on ||b - A x|| / ||b|| <= tol, Sect. 6.1)
+# O10  PCG (Eq. pcg; stop on ||b - A x|| / ||b|| <= tol, Sect. 7.1)
 # ---------------------------------------------------------------------------
 
 @dataclasses.dataclass

@@ -62,7 +62,6 @@ Scope::~Scope() {
     }
 }
 
-void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz);
 
 }  // namespace mm
 
@@ -545,7 +544,7 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
         // direct-band tile counts for every column count, built here so that
         // applies never modify the handle
         build_band_tiles(ctx, nz);
-        if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz);
+        if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz, 0);
     } catch (...) {
         delete nz;
         throw;
@@ -643,6 +642,18 @@ extern "C" mm_status mm_noise_fft_block(const mm_noise *nz, int32_t *n_fft, int3
     const bool fft = nz->method == MM_NOISE_FFT;
     *n_fft = fft ? (int32_t)nz->fft_n : 0;
     *n_valid = fft ? (int32_t)nz->fft_valid : 0;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_noise_set_fft_block(mm_ctx *ctx, mm_noise *nz, int32_t n_fft) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(nz && nz->method == MM_NOISE_FFT, MM_E_INVALID,
+             "noise_set_fft_block: needs a noise handle applied by FFT");
+    MM_CHECK(n_fft >= 0, MM_E_INVALID, "noise_set_fft_block: negative block length");
+    MM_HIP(hipStreamSynchronize(ctx->stream));
+    noise_fft_prepare(ctx, nz, n_fft);
+    API_END
     return MM_OK;
 }
 

@@ -256,7 +256,9 @@ void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_r
                   int *nonfinite_flag);
 void pair_sum_diff_dev(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a, const void *b,
                        void *plus, void *minus);
-void noise_prepare(mm_ctx *ctx, mm_noise *nz);  // tiles, FFT spectra
+// FFT tables (spectra, twiddles, block table) for overlap-save blocks of
+// n_fft real samples (16,384 or 32,768; 0 = pick by the measured time model)
+void noise_fft_prepare(mm_ctx *ctx, mm_noise *nz, int n_fft);
 // polyfilter.hip
 int polyfilter_max_order();
 void polyfilter_prepare(mm_ctx *ctx, const mm_pointing *p, mm_noise *nz,

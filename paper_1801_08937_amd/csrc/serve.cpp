@@ -6,7 +6,7 @@
 // lockstep columns: one preconditioned by M_BD, one by M_2l.  M_2l is built
 // from the first request's right-hand side and reused for every later request
 // of that strategy -- the paper's point that M_2l pays off when the same
-// system is solved many times (Sect. 6.3.2).  The build (Arnoldi, Ritz
+// system is solved many times (Sect. 7.3).  The build (Arnoldi, Ritz
 // vectors, AZ, E) runs on a host thread of its own with a context and stream
 // of its own, so it never holds up other requests: the request that triggers
 // it and those admitted before it is ready are solved with M_BD, later ones

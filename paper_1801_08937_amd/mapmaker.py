@@ -98,6 +98,7 @@ def lib() -> C.CDLL:
             "mm_defl_build_pcg": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, P, PP]),
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
             "mm_defl_transfer": (C.c_int, [P, P, P, P, P, P, PP]),
+            "mm_noise_set_fft_block": (C.c_int, [P, P, I32]),
             "mm_apply_A_noalloc": (C.c_int, [P, P, P, I32, P, P, C.POINTER(C.c_size_t)]),
             "mm_apply_A_noalloc_max_bytes": (C.c_size_t, []),
             "mm_defl_export": (C.c_int, [P, P, C.POINTER(I32), P, P, P]),
@@ -552,9 +553,18 @@ class Noise(_Handle):
         m = C.c_int()
         lib().mm_noise_method_used(h, C.byref(m))
         self.method = m.value
+        self._read_block()
+
+    def _read_block(self):
         nf, nv = C.c_int32(0), C.c_int32(0)
-        lib().mm_noise_fft_block(h, C.byref(nf), C.byref(nv))
+        lib().mm_noise_fft_block(self.h, C.byref(nf), C.byref(nv))
         self.fft_n, self.fft_valid = nf.value, nv.value
+
+    def set_fft_block(self, n_fft: int):
+        """Overlap-save block length of the FFT method (16384, 32768, 0 = model)."""
+        self.ctx._check(lib().mm_noise_set_fft_block(self.ctx.h, self.h, n_fft),
+                        "mm_noise_set_fft_block")
+        self._read_block()
 
 
 class Precond(_Handle):

@@ -331,42 +331,51 @@ def _fft_problem(lam, L, n_int, seed, n_filters=3):
     return istart, fid, band
 
 
-@pytest.mark.parametrize("lam,L,n_int,block", [(300, 5000, 5, 16384), (1000, 20000, 3, 16384),
-                                               (2048, 65536, 2, 16384), (4096, 65536, 3, 32768),
-                                               (6000, 30000, 2, 32768)])
-def test_noise_fft_parity(ctx, lam, L, n_int, block):
+@pytest.mark.parametrize("lam,L,n_int", [(300, 5000, 5), (1000, 20000, 3), (2048, 65536, 2),
+                                         (4096, 65536, 3), (6000, 30000, 2), (9000, 40000, 2)])
+def test_noise_fft_parity(ctx, lam, L, n_int):
     """FFT form of N^-1 (overlap-save, partial last blocks, several filters)
-    against the oracle's direct band.  A few blocks fill less than one wave
-    of CUs, so the 16,384-sample blocks are taken up to lambda = 2,048."""
+    against the oracle's direct band, with each block length the lambda
+    allows (16,384-sample blocks up to lambda = 6,144, 32,768 up to 12,288)."""
     import torch
     istart, fid, band = _fft_problem(lam, L, n_int, lam)
-    nz = ctx.noise(istart, fid, band, lam, method=2)
-    assert nz.method == 2 and nz.fft_n == block
     on = O.noise_build(istart, fid, band, lam)
     y = np.random.default_rng(1).standard_normal(int(istart[-1]))
-    z = host(ctx.noise_apply(nz, dev(y)))
     ref = O.noise_apply_direct(on, y)
-    assert maxrel(z, ref) <= 1e-11, maxrel(z, ref)
-    # column independence with R = 4: each column equals the single apply bitwise
-    Y4 = np.random.default_rng(2).standard_normal((int(istart[-1]), 4))
-    Y4[:, 1] = y
-    Z4 = host(ctx.noise_apply(nz, dev(Y4.reshape(-1)), nrhs=4)).reshape(-1, 4)
-    np.testing.assert_array_equal(Z4[:, 1], z)
-    # FP32 form
+    nz = ctx.noise(istart, fid, band, lam, method=2)
     nz32 = ctx.noise(istart, fid, band, lam, method=2, prec=1)
-    z32 = host(ctx.noise_apply(nz32, dev(y.astype(np.float32))))
-    assert rel(z32, ref) <= 1e-5
+    assert nz.method == 2
+    for block in (16384, 32768):
+        if block == 16384 and lam > 6144:
+            from paper_1801_08937_amd import mapmaker as mm
+            with pytest.raises(mm.MapmakerError):
+                nz.set_fft_block(block)
+            continue
+        nz.set_fft_block(block)
+        nz32.set_fft_block(block)
+        assert nz.fft_n == block and nz.fft_valid == block - 2 * lam
+        z = host(ctx.noise_apply(nz, dev(y)))
+        assert maxrel(z, ref) <= 1e-11, (block, maxrel(z, ref))
+        # column independence with R = 4: each column equals the single apply bitwise
+        Y4 = np.random.default_rng(2).standard_normal((int(istart[-1]), 4))
+        Y4[:, 1] = y
+        Z4 = host(ctx.noise_apply(nz, dev(Y4.reshape(-1)), nrhs=4)).reshape(-1, 4)
+        np.testing.assert_array_equal(Z4[:, 1], z)
+        # FP32 form
+        z32 = host(ctx.noise_apply(nz32, dev(y.astype(np.float32))))
+        assert rel(z32, ref) <= 1e-5, (block, rel(z32, ref))
 
 
-@pytest.mark.parametrize("n_int,block", [(100, 16384), (320, 32768)])
+@pytest.mark.parametrize("n_int,block", [(40, 16384), (320, 32768)])
 def test_noise_fft_block_choice_full_size(ctx, n_int, block):
-    """lambda = 2,048 over 2^16-sample intervals: 100 intervals take the
-    16,384-sample blocks (600 blocks, 3 waves of CUs, against 300 larger
-    blocks in 2 waves), 320 intervals the 32,768-sample ones (7/8 valid
-    against 3/4).  N^-1 is block diagonal over intervals, so whole intervals
-    are checked against the oracle applied to that interval alone."""
+    """lambda = 4,096 over 2^16-sample intervals: 40 intervals take the
+    16,384-sample blocks (320 blocks, one wave of two per CU, against 120
+    larger blocks, also one wave), 320 intervals the 32,768-sample ones (2,560
+    smaller blocks in 5 waves against 960 larger ones in 4).  N^-1 is block
+    diagonal over intervals, so whole intervals are checked against the
+    oracle applied to that interval alone."""
     import torch
-    lam, L = 2048, 1 << 16
+    lam, L = 4096, 1 << 16
     rng = np.random.default_rng(n_int)
     istart = np.arange(n_int + 1, dtype=np.int64) * L
     fid = rng.integers(0, 3, n_int).astype(np.int32)
