@@ -95,26 +95,115 @@ def measured_traffic(kernel: str):
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(p, n_det_sample: int):
-    """The FP64 oracle's A apply (FFT path) on the first n_det_sample
-    detectors' samples of the same inputs, single process on the host."""
+# Oracle objects shared with forked workers of the all-cores CPU baseline.
+_CPU = {}
+
+
+def _cpu_partial(rng):
+    """The oracle's A apply on the intervals [i0, i1) of the sample: N^-1 is
+    block diagonal over intervals, so A x is the sum of these partial maps."""
+    import dataclasses
     import oracle as O
+    i0, i1 = rng
+    pt, nz, x = _CPU["pt"], _CPU["nz"], _CPU["x"]
+    s0, s1 = int(nz.interval_start[i0]), int(nz.interval_start[i1])
+    sub = dataclasses.replace(pt, n_samp=s1 - s0, j=pt.j[s0:s1], cos2=pt.cos2[s0:s1],
+                              sin2=pt.sin2[s0:s1])
+    snz = O.Noise(nz.interval_start[i0:i1 + 1] - s0, nz.filter_id[i0:i1], nz.band, nz.half_bw)
+    return O.apply_A(sub, snz, x, "fft")
+
+
+def cpu_baseline(p, n_det_sample: int):
+    """The FP64 oracle on the host cores, on the first n_det_sample detectors'
+    samples of the same inputs (a bounded sample): its A apply (FFT path) on
+    one core, and on all the host's cores (at most 16, the GPU's CPU share)
+    with a fixed partition of the intervals over forked worker processes and
+    the partial maps added in partition order; plus the per-iteration map-
+    domain costs (M_BD apply, the PCG vector updates) for the solve-time
+    extrapolation.  Runs before the GPU is initialised (workers fork)."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    t_all = time.perf_counter()
     spd = p.n_samp // 128 if p.n_samp >= 128 else p.n_samp
     ns = n_det_sample * spd
     n_int = int(np.searchsorted(p.interval_start, ns))
     pt = O.pointing_build(p.pix[:ns], p.psi[:ns], p.n_pix_total, 1)
     nz = O.noise_build(p.interval_start[: n_int + 1], p.filter_id[:n_int], p.band, p.half_bw)
     x = np.random.default_rng(0).standard_normal(pt.n)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.apply_A(pt, nz, x, "fft")
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 5:
-            break
-    return {"value": ns * reps / el, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"A apply (numpy FFT path) on the first {n_det_sample} of 128 detectors "
-                      f"({ns} samples) of the same inputs, {reps} applies in {el:.1f} s"}
+    out = {"nproc": os.cpu_count()}
+    with threadpool_limits(1):
+        ref = None
+        ts = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            ref = O.apply_A(pt, nz, x, "fft")
+            ts.append(time.perf_counter() - t0)
+        t1 = min(ts)
+        M = O.mbd_build(pt, nz)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            O.mbd_apply(M, x)
+        t_mbd = (time.perf_counter() - t0) / 5
+        t0 = time.perf_counter()
+        for _ in range(5):  # the vector work of one PCG iteration: 3 dots, 3 axpys
+            v = x + 0.5 * ref
+            _ = float(v @ v) + float(x @ ref) + float(ref @ ref)
+            v = ref + 0.25 * v
+            v = v - 0.125 * x
+        t_vec = (time.perf_counter() - t0) / 5
+    W = max(1, min(16, os.cpu_count() or 1))
+    bounds = np.linspace(0, n_int, W + 1).round().astype(int)
+    parts = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    _CPU.update(pt=pt, nz=nz, x=x)
+    tw = []
+    with threadpool_limits(1), mp.get_context("fork").Pool(len(parts)) as pool:
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ys = pool.map(_cpu_partial, parts, chunksize=1)
+            acc = np.zeros_like(ref)
+            for yv in ys:
+                acc += yv
+            tw.append(time.perf_counter() - t0)
+    _CPU.clear()
+    err = float(np.max(np.abs(acc - ref)) / np.max(np.abs(ref)))
+    tW = min(tw)
+    out.update({
+        "value": ns / tW, "unit": "samples/s", "cores": len(parts), "kind": "oracle",
+        "sample": f"A apply (numpy FFT path) on the first {n_det_sample} of 128 detectors "
+                  f"({ns} samples, {n_int} intervals) of the same inputs; all cores: "
+                  f"{len(parts)} forked workers over a fixed partition of the intervals, "
+                  f"best of 3 applies; one core: best of 2",
+        "single_core": {"value": ns / t1, "unit": "samples/s", "cores": 1, "apply_s": t1},
+        "all_cores_apply_s": tW, "all_cores_vs_single_maxrel": err,
+        "sample_samples": ns, "mbd_apply_s": t_mbd, "vec_ops_s": t_vec,
+        "sample_unknowns": pt.n, "wall_s": time.perf_counter() - t_all})
+    return out
+
+
+def cpu_solve_estimates(cpu, n_samp, n_unknowns, solves, m_max, k):
+    """Oracle time to a 1e-8 residual at the full workload, extrapolated: one
+    PCG iteration = A apply (the sample's measured time scaled by samples) +
+    M_BD apply and vector updates (scaled by unknowns) (+ the M_2l coarse
+    terms, 3 n k multiply-adds, counted as three more vector passes per column
+    group of 8), times the iteration counts the GPU solves took; M_2l's setup
+    = m_max Arnoldi steps at the same per-step cost plus k A applies."""
+    if not cpu or not solves:
+        return None
+    sc_n = n_unknowns / max(cpu["sample_unknowns"], 1)
+    res = {"method": "extrapolated from the measured sample costs and the GPU iteration counts"}
+    for label, a_rate in (("single_core", cpu["single_core"]["value"]), ("all_cores", cpu["value"])):
+        t_a = n_samp / a_rate
+        t_map = (cpu["mbd_apply_s"] + cpu["vec_ops_s"]) * sc_n
+        t_m2l_extra = cpu["vec_ops_s"] * sc_n * 3 * k / 8
+        e = {"A_apply_s": t_a}
+        if "mbd" in solves:
+            e["mbd_s"] = solves["mbd"]["iters"] * (t_a + t_map)
+        if "m2l" in solves:
+            e["m2l_solve_s"] = solves["m2l"]["iters"] * (t_a + t_map + t_m2l_extra)
+            e["m2l_setup_s"] = m_max * (t_a + t_map) + k * t_a
+        res[label] = e
+    return res
 
 
 def main():
@@ -130,7 +219,8 @@ def main():
     ap.add_argument("--m-max", type=int, default=256, help="Arnoldi steps for M_2l")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1", "h1", "n1"], default=None,
+    ap.add_argument("--form", choices=["c1", "c3", "c4", "c5", "f1", "g1", "d1", "z1", "p1", "h1", "n1",
+                                       "mf"], default=None,
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
@@ -166,6 +256,7 @@ def main():
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
               "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1, "h1": form_h1, "n1": form_n1,
+              "mf": form_mf,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
@@ -184,6 +275,11 @@ def main():
         wl = ("config1: 32x32 patch, 2 det x 65,536 samples, lambda 32 direct band, FP64, "
               "M_BD and M_2l k=32, tol 1e-8")
     log(f"[bench] generated {p.name}: {p.n_samp} samples in {time.perf_counter() - t:.1f} s")
+    cpu = None
+    if not args.no_cpu and not args.profile_only and args.workload == "c2":
+        # before the GPU is initialised: the all-cores leg forks worker processes
+        cpu = cpu_baseline(p, 32)
+        log(f"[bench] cpu baseline: {cpu}")
     torch.cuda.init()
     dev = torch.device("cuda", 0)
     pix = torch.from_numpy(p.pix).to(dev)
@@ -278,6 +374,10 @@ def main():
                "design_GBps": p.n_samp * (alg_bytes["P"] + alg_bytes["PT"] + ninv)
                / (a_ms * 1e-3) / 1e9,
                "lower_bound_GBps": p.n_samp * 20.0 / (a_ms * 1e-3) / 1e9}
+    # the A apply against HBM peak, on the design's bytes per sample and on the
+    # 20 B/sample lower bound (P's non-zeros read once)
+    a_apply["design_frac_hbm_peak"] = a_apply["design_GBps"] / HBM_PEAK_GBS
+    a_apply["lower_bound_frac_hbm_peak"] = a_apply["lower_bound_GBps"] / HBM_PEAK_GBS
     log(f"[bench] A apply: {a_apply}")
 
     # timed steps: PCG iterations with M_2l
@@ -310,10 +410,8 @@ def main():
                 "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
                 "alg_bytes_per_launch": alg}
 
-    cpu = None
-    if not args.no_cpu and not args.profile_only and args.workload == "c2":
-        cpu = cpu_baseline(p, 32)
-        log(f"[bench] cpu baseline: {cpu}")
+    if cpu is not None:
+        cpu["solve_estimates"] = cpu_solve_estimates(cpu, p.n_samp, lp.n, solves, args.m_max, 32)
 
     line = {
         "metric": "A-apply samples/s (HBM GB/s) + time-to-1e-8 residual, M_2l vs M_BD, 1 GPU",
@@ -526,16 +624,36 @@ def form_c4(mm, ctx):
         b0 = B.view(-1, 64)[:, 0].contiguous()
         M2 = ctx.defl_build(lp, ln, Mbd, b0, k=32, eps_arn=1e-8, m_max=256)
         cols = [B.view(-1, 64)[:, c].contiguous() for c in range(64)]
+        # per-stage autotuner for 64 and 1 columns: the 64-column A apply
+        # before and after (results bitwise the same)
+        X = torch.randn(lp.n * 64, dtype=torch.float64, device=dev)
+        (_, a_before) = _wall(lambda: ctx.apply_A(lp, ln, X, nrhs=64), reps=10)
+        tune = {"nrhs64": ctx.autotune(lp, ln, 64), "nrhs1": ctx.autotune(lp, ln, 1)}
+        (_, a_after) = _wall(lambda: ctx.apply_A(lp, ln, X, nrhs=64), reps=10)
+        out[f"{tag}_autotune"] = {"a64_ms_before": a_before * 1e3, "a64_ms_after": a_after * 1e3,
+                                  "report": tune}
         for mname, M in (("mbd", Mbd), ("m2l", M2)):
             res = {}
+            # graph chunk length (iterations per captured graph), measured
+            chunks = {}
+            for ch in (2, 4, 8, 16):
+                (_, t) = _wall(lambda: ctx.solve(lp, ln, M, B, tol=1e-8, max_iter=3000, nrhs=64,
+                                                 check_every=ch, history=False, graph=True),
+                               reps=3)
+                chunks[ch] = t * 1e3
+            best_ch = min(chunks, key=chunks.get)
+            res["graph_chunk_ms"] = chunks
             for mode, kw in (("lockstep", {}), ("lockstep_graph", {"graph": True}),
-                             ("block", {"block": True})):
+                             ("block", {"block": True}),
+                             ("block_graph", {"block": True, "graph": True})):
+                ch = best_ch if mode.endswith("graph") else 8
                 (r, t) = _wall(lambda: ctx.solve(lp, ln, M, B, tol=1e-8, max_iter=3000, nrhs=64,
-                                                 check_every=8, history=False, **kw), reps=3)
+                                                 check_every=ch, history=False, **kw), reps=3)
                 _, infos = r
                 infos = infos if isinstance(infos, list) else [infos]
                 res[mode] = {"solve_ms": t * 1e3, "max_iters": max(i["iters"] for i in infos),
-                             "all_converged": all(i["converged"] for i in infos)}
+                             "all_converged": all(i["converged"] for i in infos),
+                             "check_every": ch}
 
             def seq():
                 its = []
@@ -550,6 +668,70 @@ def form_c4(mm, ctx):
             out[f"{tag}_{mname}"] = res
     return {"form": "c4", "workload": "64 realizations (CMB-like sky + noise each) on config 1's "
             "pointing and noise model, tol 1e-8", **out}
+
+
+def form_mf(mm, ctx, reps=20):
+    """The FP64 MFMA products at the path's shapes, each timed with HIP events
+    on the context's stream: E = Z^T (A Z) and the Cholesky-QR Gram of the
+    coarse build (config 2, k = 32), Z = W_m Y of the Ritz step (m = 256), and
+    block PCG's 64 x 64 Gram and update products (config 4's n = 3,072, and
+    at config 2's n).  Reported against the 78.6 TFLOP/s FP64 MFMA peak and,
+    with the algorithmic bytes (inputs read once, outputs written once),
+    against 8 TB/s HBM; the lower of the two bounds the product."""
+    import torch
+    dev = torch.device("cuda", 0)
+    g = torch.Generator(device=dev).manual_seed(0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    n2, n4 = 196608, 3072
+
+    def colmajor(n, k):
+        return torch.randn(k, n, dtype=torch.float64, device=dev, generator=g).t()
+
+    def rowmajor(n, k):
+        return torch.randn(n, k, dtype=torch.float64, device=dev, generator=g)
+
+    cases = []
+    Z, AZ = colmajor(n2, 32), colmajor(n2, 32)
+    cases.append(("E = Z^T (AZ), config 2, k = 32", lambda: ctx.dense_gram(Z, AZ),
+                  2.0 * n2 * 32 * 32, 8.0 * n2 * 64))
+    W, Y = colmajor(n2, 256), torch.randn(256, 32, dtype=torch.float64, device=dev, generator=g)
+    Wc, Yc = W.t().contiguous(), Y.t().contiguous()
+    Zo = torch.empty(32, n2, dtype=torch.float64, device=dev)
+    from paper_1801_08937_amd.mapmaker import lib, _ptr
+    cases.append(("Z = W_m Y, config 2, m = 256, k = 32",
+                  lambda: lib().mm_dense_tall(ctx.h, n2, 256, 32, _ptr(Wc), _ptr(Yc), _ptr(Zo)),
+                  2.0 * n2 * 256 * 32, 8.0 * n2 * (256 + 32)))
+    for n, tag in ((n4, "config 4"), (n2, "config-2 size")):
+        P_, Q_ = rowmajor(n, 64), rowmajor(n, 64)
+        S_ = torch.randn(64, 64, dtype=torch.float64, device=dev, generator=g)
+        O_ = rowmajor(n, 64)
+        cases.append((f"block CG Gram P^T Q, {tag}, n = {n}, R = 64",
+                      lambda P_=P_, Q_=Q_: ctx.dense_gram(P_, Q_), 2.0 * n * 64 * 64,
+                      8.0 * n * 128))
+        cases.append((f"block CG update X += P S, {tag}, n = {n}, R = 64",
+                      lambda P_=P_, S_=S_, O_=O_: ctx.dense_rows(P_, S_, out=O_, beta=1.0),
+                      2.0 * n * 64 * 64, 8.0 * n * 64 * 3))
+    rows = []
+    for name, fn, flops, nbytes in cases:
+        for _ in range(3):
+            fn()
+        ev[0].record(ctx.stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(ctx.stream)
+        ev[1].synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        tf = flops / (ms * 1e-3) / 1e12
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        bound_tf = min(FP64_PEAK_TF, nbytes and flops / nbytes * HBM_PEAK_GBS / 1e3)
+        rows.append({"product": name, "us": ms * 1e3, "TFLOPs": tf,
+                     "mfma_util": tf / FP64_PEAK_TF, "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                     "flop_per_byte": flops / nbytes, "roofline_TFLOPs": bound_tf,
+                     "frac_of_roofline": tf / bound_tf})
+        log(f"[bench] mf {rows[-1]}")
+    return {"form": "mf", "workload": "FP64 MFMA products of the coarse build and block PCG at "
+            "config-2 and config-4 shapes", "peak_fp64_mfma_TFLOPs": FP64_PEAK_TF,
+            "rows": rows}
 
 
 def form_f1(mm, ctx, ground=False):

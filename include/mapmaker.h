@@ -447,6 +447,28 @@ mm_status mm_pcg_poll(mm_ctx *ctx, mm_pcg *s, int32_t *state, int32_t *iters, do
 mm_status mm_pcg_finish(mm_ctx *ctx, mm_pcg *s, int32_t slot, double *x);
 void mm_pcg_destroy(mm_pcg *s);
 
+/* ---------------------------------------------------- small dense products */
+
+/* The FP64 MFMA products of the two-level preconditioner and of block CG
+ * (Eq. m2l: E = Z^T (A Z); the Ritz step Z = W_m Y of Sect. 6; the Gram and
+ * update products of block PCG), exposed for callers that build their own
+ * deflation spaces and for measurement.  All arrays [device] f64, distinct.
+ * The sums run in a fixed order (bitwise repeatable).
+ * C = X^T Y with X(i, a) = X[i x_rs + a x_cs], Y(i, b) likewise, i < n;
+ * C [ka][kb] row-major; 1 <= ka, kb <= 64. */
+mm_status mm_dense_gram(mm_ctx *ctx, int64_t n, int32_t ka, int32_t kb, const double *X,
+                        int64_t x_rs, int64_t x_cs, const double *Y, int64_t y_rs, int64_t y_cs,
+                        double *C);
+/* Z = V Y: V n x kin and Z n x kout column-major (column c at + c n), Y
+ * kin x kout column-major; kin >= 1, 1 <= kout <= 64. */
+mm_status mm_dense_tall(mm_ctx *ctx, int64_t n, int32_t kin, int32_t kout, const double *V,
+                        const double *Y, double *Z);
+/* Out = beta Out + alpha In S for column-batched In, Out ([n][R], column
+ * fastest) and S [R][R] row-major; R a power of two <= 64 (beta = 0 does not
+ * read Out). */
+mm_status mm_dense_rows(mm_ctx *ctx, int64_t n, int32_t R, const double *In, const double *S,
+                        double alpha, double beta, double *Out);
+
 /* ----------------------------------------------------------------- serving */
 
 /* A serving engine for map-making solves of several recurring scan
@@ -532,16 +554,23 @@ void mm_server_destroy(mm_server *srv);
 
 /* -------------------------------------------------------------- autotuning */
 
-/* Time candidate launch shapes for nrhs columns with HIP events and keep the
- * fastest: the P kernel's grid size (the direct band's tiles follow from its
- * register tiling and are not tuned).  Each candidate computes bitwise the
- * same values (every output sums its terms in a fixed order), so tuning
- * changes speed only.  Choices are stored in the handles and used by later
- * calls with that nrhs.
- *   report [host] f64[3 * 16] or NULL: (stage 0 = P, candidate, ms)
+/* Per-stage autotuner: for nrhs columns, time candidates with HIP events and
+ * keep the fastest, stored in the handles for later calls with that nrhs
+ * (the handles are modified: no other call may use them meanwhile).
+ *   stage 0, P: the grid size;
+ *   stage 1, direct band N^-1: taps per LDS chunk (less LDS per block, more
+ *            blocks per compute unit);
+ *   stage 2, P^T with several columns: tiled or ascending pixel order;
+ *   stage 3, FFT N^-1, only with MM_TUNE_FFT_BLOCK in flags: the overlap-save
+ *            block length (16,384 or 32,768; see mm_noise_set_fft_block).
+ * Stages 0-2 change speed only: every output sums its terms in an order no
+ * candidate changes, so results stay bitwise the same.  Stage 3 changes
+ * results at the rounding level (<= 1e-11 relative in FP64).
+ *   report [host] f64[3 * max_report] or NULL: (stage, candidate, ms) triples
  *   n_report [host] or NULL: entries written */
-mm_status mm_autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int32_t nrhs, double *report,
-                      int32_t *n_report);
+enum { MM_TUNE_FFT_BLOCK = 1 };
+mm_status mm_autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int32_t nrhs, int32_t flags,
+                      double *report, int32_t max_report, int32_t *n_report);
 
 /* ---------------------------------------------------------- profiling aid */
 

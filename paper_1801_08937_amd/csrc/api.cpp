@@ -1265,7 +1265,8 @@ extern "C" void mm_precond_destroy(mm_precond *M) { delete M; }
 
 static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                           const mm_precond *M, int R, const double *b, double *x, double tol,
-                          int max_iter, int check, double *history, mm_solve_info *info);
+                          int max_iter, int check, bool use_graph, double *history,
+                          mm_solve_info *info);
 
 extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                               const mm_precond *M, int32_t nrhs, const double *b, double *x,
@@ -1284,7 +1285,7 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     if (flags & MM_SOLVE_BLOCK) {
         MM_CHECK(nrhs >= 2, MM_E_INVALID, "solve: block CG needs nrhs >= 2");
         result = block_cg(ctx, p, nz, M, nrhs, b, x, tol, max_iter, std::max(1u, flags & 0xffu),
-                          history, info);
+                          (flags & MM_SOLVE_GRAPH) != 0, history, info);
         return result;
     }
     const auto t0 = std::chrono::steady_clock::now();
@@ -1396,10 +1397,14 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
 //   Z = M R; beta = Q^T Z; P~ = Z - P beta; Q~ = A P~; U; P = P~ U; Q = Q~ U.
 // P^T A P = I on the kept directions, so alpha and beta need no solves; the
 // Gram and block products run on FP64 MFMA.  Convergence is checked every
-// `check` iterations on each column's ||r|| / ||b||.
+// `check` iterations on each column's ||r|| / ||b||.  With use_graph (and no
+// history), the iterations after the first are replayed in chunks of `check`
+// from a captured HIP graph; the convergence test follows each chunk, so a
+// solve may run up to check - 1 iterations past the one that converged.
 static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                           const mm_precond *M, int R, const double *b, double *x, double tol,
-                          int max_iter, int check, double *history, mm_solve_info *info) {
+                          int max_iter, int check, bool use_graph, double *history,
+                          mm_solve_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = ctx->stream;
     const int64_t n = p->n();
@@ -1444,7 +1449,29 @@ static mm_status block_cg(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
         precond(Rr.as<double>(), Z.as<double>());
         orthonormalise();
     }
+    // one whole iteration: X, R update, then the next A-orthonormal block
+    auto iteration = [&]() {
+        gram_mfma(ctx, n, R, R, Pb.as<double>(), R, 1, Rr.as<double>(), R, 1, AB);    // alpha
+        gemm_rows_small(ctx, n, R, Pb.as<double>(), AB, 1.0, 1.0, x);
+        gemm_rows_small(ctx, n, R, Q.as<double>(), AB, -1.0, 1.0, Rr.as<double>());
+        precond(Rr.as<double>(), Z.as<double>());
+        gram_mfma(ctx, n, R, R, Q.as<double>(), R, 1, Z.as<double>(), R, 1, AB);      // beta
+        gemm_rows_small(ctx, n, R, Pb.as<double>(), AB, -1.0, 1.0, Z.as<double>());   // P~
+        orthonormalise();
+    };
+    PcgGraph Gr;
     while (!conv && it < max_iter) {
+        if (use_graph && !history && it >= 1 && it + check <= max_iter) {
+            Gr.drop_if_stale(ctx);
+            if (!Gr.ex) capture_chunk(ctx, Gr, check, iteration);
+            MM_HIP(hipGraphLaunch(Gr.ex, s));
+            it += check;
+            dot_cols(ctx, n, R, Rr.as<double>(), Rr.as<double>(), rn.as<double>());
+            MM_HIP(hipMemcpyAsync(h_rn.data(), rn.ptr, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+            MM_HIP(hipStreamSynchronize(s));
+            conv = all_conv();
+            continue;
+        }
         gram_mfma(ctx, n, R, R, Pb.as<double>(), R, 1, Rr.as<double>(), R, 1, AB);    // alpha
         gemm_rows_small(ctx, n, R, Pb.as<double>(), AB, 1.0, 1.0, x);
         gemm_rows_small(ctx, n, R, Q.as<double>(), AB, -1.0, 1.0, Rr.as<double>());
@@ -1691,14 +1718,54 @@ extern "C" void mm_pcg_destroy(mm_pcg *S) { delete S; }
 // ============================================================== autotune
 
 extern "C" mm_status mm_autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int32_t nrhs,
-                                 double *report, int32_t *n_report) {
+                                 int32_t flags, double *report, int32_t max_report,
+                                 int32_t *n_report) {
     if (!ctx) return MM_E_INVALID;
     API_BEGIN(ctx)
     check_pair(p, nz);
     check_nrhs(nrhs);
+    MM_CHECK(max_report >= 0 && (report || max_report == 0), MM_E_INVALID,
+             "autotune: report needs max_report entries");
     int nr = 0;
-    autotune(ctx, p, nz, nrhs, report, &nr);
+    autotune(ctx, p, nz, nrhs, flags, report, &nr, max_report);
     if (n_report) *n_report = nr;
+    API_END
+    return MM_OK;
+}
+
+// ======================================================= dense products
+
+extern "C" mm_status mm_dense_gram(mm_ctx *ctx, int64_t n, int32_t ka, int32_t kb,
+                                   const double *X, int64_t x_rs, int64_t x_cs, const double *Y,
+                                   int64_t y_rs, int64_t y_cs, double *C) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(n >= 1 && ka >= 1 && ka <= 64 && kb >= 1 && kb <= 64 && X && Y && C, MM_E_INVALID,
+             "dense_gram: sizes in [1, 64] and non-null arrays");
+    gram_mfma(ctx, n, ka, kb, X, x_rs, x_cs, Y, y_rs, y_cs, C);
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_dense_tall(mm_ctx *ctx, int64_t n, int32_t kin, int32_t kout,
+                                   const double *V, const double *Y, double *Z) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    MM_CHECK(n >= 1 && kin >= 1 && kout >= 1 && kout <= 64 && V && Y && Z && Z != V, MM_E_INVALID,
+             "dense_tall: kin >= 1, kout in [1, 64], distinct non-null arrays");
+    matmul_small_right(ctx, n, kin, kout, V, Y, Z);
+    API_END
+    return MM_OK;
+}
+
+extern "C" mm_status mm_dense_rows(mm_ctx *ctx, int64_t n, int32_t R, const double *In,
+                                   const double *S, double alpha, double beta, double *Out) {
+    if (!ctx) return MM_E_INVALID;
+    API_BEGIN(ctx)
+    check_nrhs(R);
+    MM_CHECK(n >= 1 && In && S && Out && In != Out, MM_E_INVALID,
+             "dense_rows: distinct non-null arrays");
+    gemm_rows_small(ctx, n, R, In, S, alpha, beta, Out);
     API_END
     return MM_OK;
 }

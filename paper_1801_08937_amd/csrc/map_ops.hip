@@ -798,31 +798,41 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
 
 // ------------------------------------------------------------- block CG
 //
-// Out = beta Out + alpha In S for column-batched In, Out ([n][R], R <= 64)
-// and a small S ([R][R] row-major) on FP64 MFMA: a wave owns 16 rows and all
-// R columns.
-__global__ void __launch_bounds__(BS) k_gemm_rows_small(int64_t n, int R,
+// Out = beta Out + alpha In S for column-batched In, Out ([n][R], R a power
+// of two <= 64) and a small S ([R][R] row-major) on FP64 MFMA.  A block takes
+// 64 rows: S and the block's rows of In are staged in LDS with coalesced
+// loads, then each wave multiplies its 16 rows by S from LDS.
+__global__ void __launch_bounds__(BS) k_gemm_rows_small(int64_t n, int lgR,
                                                         const double *__restrict__ In,
                                                         const double *__restrict__ S,
                                                         double alpha, double beta,
                                                         double *__restrict__ Out) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+    __shared__ double sS[64][65];
+    __shared__ double sA[64][65];
+    const int R = 1 << lgR;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t brow = (int64_t)blockIdx.x * 64;
+    for (int e = tid; e < R * R; e += BS) sS[e >> lgR][e & (R - 1)] = S[e];
+    for (int e = tid; e < 64 * R; e += BS) {
+        const int r = e >> lgR, c = e & (R - 1);
+        sA[r][c] = brow + r < n ? In[(brow + r) * R + c] : 0.0;
+    }
+    __syncthreads();
+    const int64_t row0 = brow + wv * 16;
     if (row0 >= n) return;
     const int i16 = lane % 16, k4 = lane / 16;
-    const int64_t arow = row0 + i16;
     const int TB = (R + 15) / 16;
     d4m acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = d4m{0, 0, 0, 0};
     for (int m = 0; m < R; m += 4) {
         const int mm = m + k4;
-        const double av = (arow < n && mm < R) ? In[arow * R + mm] : 0.0;
+        const double av = mm < R ? sA[wv * 16 + i16][mm] : 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q < TB) {
                 const int col = q * 16 + i16;
-                const double bv = (mm < R && col < R) ? S[mm * R + col] : 0.0;
+                const double bv = (mm < R && col < R) ? sS[mm][col] : 0.0;
                 acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
             }
         }
@@ -849,57 +859,79 @@ __global__ void __launch_bounds__(BS) k_gemm_rows_small(int64_t n, int R,
 // dropping a direction whose pivot^2 is <= tau (numerically dependent on the
 // earlier ones) or whose diagonal is not positive; U = D^-1 L^-T, with zero
 // rows and columns for dropped directions.  Row-major.  rank[0] = kept count.
-__global__ void k_chol_inv_drop(int R, const double *__restrict__ G, double tau,
-                                double *__restrict__ U, int *__restrict__ rank) {
+constexpr int CHOL_BS = 1024;  // threads of k_chol_inv_drop: a 32 x 32 grid
+
+__global__ void __launch_bounds__(CHOL_BS) k_chol_inv_drop(int R, const double *__restrict__ G,
+                                                           double tau, double *__restrict__ U,
+                                                           int *__restrict__ rank) {
     __shared__ double A[64][65];
-    __shared__ double Li[64][65];
+    __shared__ double X[64][65];
     __shared__ double dsc[64];
     __shared__ int keep[64];
     const int tid = threadIdx.x;
-    for (int i = tid; i < R; i += blockDim.x) {
+    const int ti = tid >> 5, tj = tid & 31;  // 32 x 32 thread grid
+    for (int i = tid; i < R; i += CHOL_BS) {
         const double g = G[i * R + i];
         dsc[i] = g > 1e-300 ? sqrt(g) : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < R * R; e += blockDim.x) {
-        const int i = e / R, j = e % R;
-        const double s = 0.5 * (G[i * R + j] + G[j * R + i]);
-        A[i][j] = (dsc[i] > 0 && dsc[j] > 0) ? s / (dsc[i] * dsc[j]) : (i == j ? 0.0 : 0.0);
-    }
+    for (int i = ti; i < R; i += 32)
+        for (int j = tj; j < R; j += 32) {
+            const double s = 0.5 * (G[i * R + j] + G[j * R + i]);
+            A[i][j] = (dsc[i] > 0 && dsc[j] > 0) ? s / (dsc[i] * dsc[j]) : 0.0;
+            X[i][j] = i == j ? 1.0 : 0.0;
+        }
     __syncthreads();
-    for (int c = 0; c < R; ++c) {
-        if (tid == 0) {
+    // Right-looking Cholesky, one barrier per column: in the interval of
+    // column c every thread reads the pivot A[c][c], the update of the
+    // trailing entries (j > c) uses the unscaled column c divided by the
+    // pivot, and column c - 1 is scaled (disjoint entries).
+    for (int c = 0; c <= R; ++c) {
+        if (c > 0) {
+            const int q = c - 1;
+            const double d = A[q][q];
+            const bool kq = dsc[q] > 0 && d > tau;
+            const double l = kq ? sqrt(d) : 0.0;
+            for (int i = q + 1 + tid; i < R; i += CHOL_BS) A[i][q] = kq ? A[i][q] / l : 0.0;
+            if (tid == 0) {
+                keep[q] = kq ? 1 : 0;
+                A[q][q] = l;
+            }
+        }
+        if (c < R) {
             const double d = A[c][c];
-            keep[c] = (dsc[c] > 0 && d > tau) ? 1 : 0;
-            A[c][c] = keep[c] ? sqrt(d) : 0.0;
-        }
-        __syncthreads();
-        const double lcc = A[c][c];
-        for (int i = c + 1 + tid; i < R; i += blockDim.x) A[i][c] = keep[c] ? A[i][c] / lcc : 0.0;
-        __syncthreads();
-        for (int e = tid; e < (R - c - 1) * (R - c - 1); e += blockDim.x) {
-            const int i = c + 1 + e / (R - c - 1), j = c + 1 + e % (R - c - 1);
-            if (j <= i) A[i][j] -= A[i][c] * A[j][c];
+            if (dsc[c] > 0 && d > tau) {
+                const double inv = 1.0 / d;
+                for (int i = c + 1 + ti; i < R; i += 32)
+                    for (int j = c + 1 + tj; j <= i; j += 32) A[i][j] -= A[i][c] * A[j][c] * inv;
+            }
         }
         __syncthreads();
     }
-    // Li = L^-1 on the kept directions (forward substitution per column)
-    for (int c = tid; c < R; c += blockDim.x) {
-        for (int i = 0; i < R; ++i) Li[i][c] = 0.0;
-        if (!keep[c]) continue;
-        Li[c][c] = 1.0 / A[c][c];
-        for (int i = c + 1; i < R; ++i) {
-            if (!keep[i]) continue;
-            double s = 0;
-            for (int k = c; k < i; ++k) s += A[i][k] * Li[k][c];
-            Li[i][c] = -s / A[i][i];
+    // X = L^-1 on the kept directions, by row elimination on [L | I]: at step
+    // k the rows below k take row k times L[i][k] / L[k][k] (row k is final:
+    // only earlier steps change it), and row k - 1 is divided by its pivot
+    // (no later step reads it).  A dropped direction has L[k][k] = 0 and a
+    // zero column, so its row of X is zeroed and feeds no other row.
+    for (int k = 0; k <= R; ++k) {
+        if (k > 0) {
+            const int q = k - 1;
+            const double l = A[q][q];
+            for (int j = tid; j < R; j += CHOL_BS) X[q][j] = keep[q] ? X[q][j] / l : 0.0;
         }
+        if (k < R && keep[k]) {
+            const double inv = 1.0 / A[k][k];
+            for (int i = k + 1 + ti; i < R; i += 32) {
+                const double f = A[i][k] * inv;
+                if (f != 0.0)
+                    for (int j = tj; j <= k; j += 32) X[i][j] -= f * X[k][j];
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < R * R; e += blockDim.x) {
-        const int i = e / R, j = e % R;
-        U[e] = dsc[i] > 0 ? Li[j][i] / dsc[i] : 0.0;  // D^-1 (L^-1)^T
-    }
+    for (int i = ti; i < R; i += 32)
+        for (int j = tj; j < R; j += 32)
+            U[i * R + j] = dsc[i] > 0 ? X[j][i] / dsc[i] : 0.0;  // D^-1 (L^-1)^T
     if (tid == 0) {
         int r = 0;
         for (int c = 0; c < R; ++c) r += keep[c];
@@ -1158,13 +1190,14 @@ void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const d
 void gemm_rows_small(mm_ctx *ctx, int64_t n, int R, const double *In, const double *S,
                      double alpha, double beta, double *Out) {
     Scope sc(ctx->prof, ctx->stream, "gemm_mfma");
-    k_gemm_rows_small<<<(unsigned)((n + 63) / 64), BS, 0, ctx->stream>>>(n, R, In, S, alpha, beta,
-                                                                      Out);
+    MM_CHECK(pow2_ok(R), MM_E_INVALID, "gemm_rows_small: R must be a power of two <= 64");
+    k_gemm_rows_small<<<(unsigned)((n + 63) / 64), BS, 0, ctx->stream>>>(n, log2i(R), In, S, alpha,
+                                                                      beta, Out);
     MM_HIP(hipGetLastError());
 }
 
 void chol_inv_drop(mm_ctx *ctx, int R, const double *G, double tau, double *U, int *rank) {
-    k_chol_inv_drop<<<1, 64, 0, ctx->stream>>>(R, G, tau, U, rank);
+    k_chol_inv_drop<<<1, CHOL_BS, 0, ctx->stream>>>(R, G, tau, U, rank);
     MM_HIP(hipGetLastError());
 }
 
@@ -1233,8 +1266,9 @@ void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t 
                int64_t x_cs, const double *Y, int64_t y_rs, int64_t y_cs, double *C) {
     Scope sc(ctx->prof, ctx->stream, "gram_mfma");
     MM_CHECK(ka >= 1 && ka <= 64 && kb >= 1 && kb <= 64, MM_E_INVALID, "gram: sizes");
-    // about four 32-row chunks per block, at most 1,024 blocks
-    int64_t parts64 = (n + 4 * GR_ROWS - 1) / (4 * GR_ROWS);
+    // one 32-row chunk per block up to 1,024 blocks (small n: more blocks in
+    // flight), then more chunks per block
+    int64_t parts64 = (n + GR_ROWS - 1) / GR_ROWS;
     if (parts64 > 1024) parts64 = 1024;
     if (parts64 < 1) parts64 = 1;
     const int parts = (int)parts64;

@@ -154,6 +154,9 @@ struct mm_pointing {
     mm::DBuf seg_order;
     int32_t grid_width = 0;
     int32_t p_blocks[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned P grid per log2(nrhs); 0 = default
+    // tuned: visit pixels in seg_order (1) or ascending (0) in the
+    // one-wave-per-pixel P^T, per log2(nrhs); -1 = default (seg_order if set)
+    int32_t pt_order[7] = {-1, -1, -1, -1, -1, -1, -1};
     // Sliced single-column P^T: observed pixels in slices of 64 (one pixel per
     // lane; neighbours on the map when a grid is set), the samples cut into
     // sl_S equal time segments.  Wave (s, g) walks its lanes' entries of
@@ -185,6 +188,7 @@ struct mm_noise {
     // (device copy and host copy); built with the handle, read-only after
     mm::DBuf tile_pref;
     std::vector<int64_t> h_tile_pref;
+    int32_t band_cl[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned taps per LDS chunk per log2(nrhs); 0 = default
     // FFT: per-filter packed spectrum and block table
     int32_t fft_n = 0;       // real block length
     int32_t fft_valid = 0;   // valid outputs per block
@@ -338,7 +342,8 @@ template <> struct Vec2T<float> { using type = float2; };
 template <> struct Vec2T<double> { using type = double2; };
 
 void build_band_tiles(mm_ctx *ctx, mm_noise *nz);
-void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *report, int *n_report);
+void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, int flags, double *report,
+              int *n_report, int max_report);
 
 inline int log2i(int r) { int l = 0; while ((1 << l) < r) ++l; return l; }
 inline int pow2_ok(int r) { return r >= 1 && r <= 64 && (r & (r - 1)) == 0; }

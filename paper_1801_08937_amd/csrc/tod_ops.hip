@@ -676,7 +676,8 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
     }
     int64_t nb = (p->n_obs + 3) / 4;
     if (nb >= 64) nb = (nb + 7) & ~(int64_t)7;
-    const int32_t *order = p->seg_order.ptr ? p->seg_order.as<int32_t>() : nullptr;
+    const int po = p->pt_order[log2i(nrhs)];
+    const int32_t *order = (p->seg_order.ptr && po != 0) ? p->seg_order.as<int32_t>() : nullptr;
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
         if (p->prec == MM_F32)
@@ -729,7 +730,7 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     const int li = log2i(nrhs);
     const int64_t *pref = nz->tile_pref.as<int64_t>() + (int64_t)li * (nz->n_int + 1);
     const unsigned n_tiles = (unsigned)nz->h_tile_pref[(size_t)li * (nz->n_int + 1) + nz->n_int];
-    const int cl = band_chunk(lam, nrhs, nz->prec);
+    const int cl = nz->band_cl[li] > 0 ? nz->band_cl[li] : band_chunk(lam, nrhs, nz->prec);
     const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
     const size_t sm = te * ((size_t)cl + (size_t)(tl + cl - 1) * nrhs);
     dispatch_r(nrhs, [&](auto RR) {
@@ -800,20 +801,24 @@ void build_band_tiles(mm_ctx *ctx, mm_noise *nz) {
     MM_HIP(hipStreamSynchronize(ctx->stream));
 }
 
-// Measure candidate launch shapes with HIP events and keep the fastest: the
-// P kernel's grid size, per nrhs (the direct band's tiles are fixed by its
-// register tiling).
-// Every candidate computes the same values (each output's terms are summed
-// in a fixed order independent of the launch shape), so tuning never changes
-// results.  report: (stage, candidate, ms) triples.
-void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *report,
-              int *n_report) {
+// Measure candidates for each stage with HIP events and keep the fastest:
+//   stage 0, P: the grid size (grid-stride kernels);
+//   stage 1, direct band: the taps per LDS chunk (smaller chunks need less
+//     LDS per block, so more blocks share a CU);
+//   stage 2, P^T with several columns: visiting the pixels in the tiled
+//     order or ascending;
+//   stage 3 (flag MM_TUNE_FFT_BLOCK only), FFT: the overlap-save block length.
+// Stages 0-2 change speed only: every output sums its terms in a fixed order
+// that no candidate changes, so results are bitwise the same.  Stage 3 moves
+// results at the rounding level.  report: (stage, candidate, ms) triples.
+void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, int flags, double *report,
+              int *n_report, int max_report) {
     const int li = log2i(nrhs);
     const size_t te = p->prec == MM_F32 ? sizeof(float) : sizeof(double);
-    (void)nz;
-    DBuf x, y;
+    DBuf x, y, z;
     x.alloc(sizeof(double) * (size_t)p->n() * nrhs);
     y.alloc(te * (size_t)p->n_samp * nrhs);
+    z.alloc(te * (size_t)p->n_samp * nrhs);
     MM_HIP(hipMemsetAsync(x.ptr, 0, x.bytes, ctx->stream));
     MM_HIP(hipMemsetAsync(y.ptr, 0, y.bytes, ctx->stream));
     hipEvent_t e0, e1;
@@ -830,31 +835,87 @@ void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, double *repor
         MM_HIP(hipEventElapsedTime(&ms, e0, e1));
         return ms / 5.0;
     };
+    auto note = [&](int stage, double cand, double ms) {
+        if (report && nr < max_report) {
+            report[3 * nr] = stage;
+            report[3 * nr + 1] = cand;
+            report[3 * nr + 2] = ms;
+        }
+        ++nr;
+    };
     const bool prof = ctx->prof.on;
     ctx->prof.on = false;
     try {
-        // P grid size
-        double best = 1e30;
-        int best_g = 0;
-        for (int mult : {2, 4, 8, 16, 32}) {
-            const int g = ctx->n_cu * mult;
-            p->p_blocks[li] = g;
-            const double ms = time_it([&]() { apply_P_dev(ctx, p, nrhs, x.as<double>(), y.ptr); });
-            if (report) { report[3 * nr] = 0; report[3 * nr + 1] = g; report[3 * nr + 2] = ms; }
-            ++nr;
-            if (ms < best) { best = ms; best_g = g; }
+        // stage 0: P grid size
+        {
+            double best = 1e30;
+            int best_g = 0;
+            for (int mult : {2, 4, 8, 16, 32}) {
+                const int g = ctx->n_cu * mult;
+                p->p_blocks[li] = g;
+                const double ms =
+                    time_it([&]() { apply_P_dev(ctx, p, nrhs, x.as<double>(), y.ptr); });
+                note(0, g, ms);
+                if (ms < best) { best = ms; best_g = g; }
+            }
+            p->p_blocks[li] = best_g;
         }
-        p->p_blocks[li] = best_g;
+        // stage 1: taps per LDS chunk of the direct band
+        if (nz->method == MM_NOISE_DIRECT) {
+            const int def = band_chunk(nz->half_bw, nrhs, nz->prec);
+            double best = 1e30;
+            int best_c = 0;
+            for (int div : {1, 2, 4, 8}) {
+                const int c = def / div / BT_OPT * BT_OPT;
+                if (c < BT_OPT || (div > 1 && c == def)) continue;
+                nz->band_cl[li] = c;
+                const double ms = time_it([&]() { noise_apply_dev(ctx, nz, nrhs, y.ptr, z.ptr); });
+                note(1, c, ms);
+                if (ms < best) { best = ms; best_c = c; }
+            }
+            nz->band_cl[li] = best_c == def ? 0 : best_c;
+        }
+        // stage 2: visiting order of the one-wave-per-pixel P^T
+        if (nrhs > 1 && p->seg_order.ptr) {
+            double best = 1e30;
+            int best_o = -1;
+            for (int o : {1, 0}) {
+                p->pt_order[li] = o;
+                const double ms = time_it([&]() { apply_PT_dev(ctx, p, nrhs, z.ptr, x.as<double>()); });
+                note(2, o, ms);
+                if (ms < best) { best = ms; best_o = o; }
+            }
+            p->pt_order[li] = best_o;
+        }
+        // stage 3: FFT block length (results move at the rounding level)
+        if ((flags & MM_TUNE_FFT_BLOCK) && nz->method == MM_NOISE_FFT) {
+            const int keep = nz->fft_n;
+            double best = 1e30;
+            int best_n = keep;
+            for (int n_fft : {16384, 32768}) {
+                if (n_fft == 16384 && nz->half_bw > 6144) continue;
+                MM_HIP(hipStreamSynchronize(ctx->stream));
+                noise_fft_prepare(ctx, nz, n_fft);
+                const double ms = time_it([&]() { noise_apply_dev(ctx, nz, nrhs, y.ptr, z.ptr); });
+                note(3, n_fft, ms);
+                if (ms < best) { best = ms; best_n = n_fft; }
+            }
+            if (best_n != nz->fft_n) {
+                MM_HIP(hipStreamSynchronize(ctx->stream));
+                noise_fft_prepare(ctx, nz, best_n);
+            }
+        }
     } catch (...) {
         ctx->prof.on = prof;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         throw;
     }
+    MM_HIP(hipStreamSynchronize(ctx->stream));
     ctx->prof.on = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (n_report) *n_report = nr;
+    if (n_report) *n_report = nr < max_report ? nr : max_report;
 }
 
 }  // namespace mm

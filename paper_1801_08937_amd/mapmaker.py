@@ -99,6 +99,9 @@ def lib() -> C.CDLL:
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
             "mm_defl_transfer": (C.c_int, [P, P, P, P, P, P, PP]),
             "mm_noise_set_fft_block": (C.c_int, [P, P, I32]),
+            "mm_dense_gram": (C.c_int, [P, I64, I32, I32, P, I64, I64, P, I64, I64, P]),
+            "mm_dense_tall": (C.c_int, [P, I64, I32, I32, P, P, P]),
+            "mm_dense_rows": (C.c_int, [P, I64, I32, P, P, D, D, P]),
             "mm_apply_A_noalloc": (C.c_int, [P, P, P, I32, P, P, C.POINTER(C.c_size_t)]),
             "mm_apply_A_noalloc_max_bytes": (C.c_size_t, []),
             "mm_defl_export": (C.c_int, [P, P, C.POINTER(I32), P, P, P]),
@@ -107,7 +110,7 @@ def lib() -> C.CDLL:
             "mm_precond_destroy": (None, [P]),
             "mm_solve": (C.c_int, [P, P, P, P, I32, P, P, D, I32, U32, P, P]),
             "mm_profile_enable": (C.c_int, [P, C.c_int]),
-            "mm_autotune": (C.c_int, [P, P, P, I32, P, C.POINTER(I32)]),
+            "mm_autotune": (C.c_int, [P, P, P, I32, I32, P, I32, C.POINTER(I32)]),
             "mm_server_create": (C.c_int, [C.c_int, I64, I32, I32, I32, PP]),
             "mm_server_set_prebuild": (C.c_int, [P, I32]),
             "mm_server_add_strategy": (C.c_int, [P, I32, I64, I32, P, P, I32, I32, I32, P, P, I32,
@@ -439,14 +442,54 @@ class Context:
                             rel_res_precond=i.rel_res_precond, history=h, status=st))
         return x, (out[0] if nrhs == 1 else out)
 
-    def autotune(self, p, nz, nrhs: int = 1):
-        """Pick launch shapes by measurement; returns [(stage, candidate, ms)]."""
-        rep = np.zeros(3 * 16)
+    def autotune(self, p, nz, nrhs: int = 1, fft_block: bool = False):
+        """Per-stage autotuner; returns [(stage, candidate, ms)].  fft_block:
+        also tune the FFT block length (changes results at rounding level)."""
+        rep = np.zeros(3 * 32)
         n = C.c_int32()
-        self._check(lib().mm_autotune(self.h, p.h, nz.h, nrhs, rep.ctypes.data, C.byref(n)),
-                    "mm_autotune")
-        return [({0: "P", 1: "band"}[int(rep[3 * i])], int(rep[3 * i + 1]), float(rep[3 * i + 2]))
+        self._check(lib().mm_autotune(self.h, p.h, nz.h, nrhs, 1 if fft_block else 0,
+                                      rep.ctypes.data, 32, C.byref(n)), "mm_autotune")
+        if fft_block:
+            nz._read_block()
+        names = {0: "P", 1: "band_chunk", 2: "PT_order", 3: "fft_block"}
+        return [(names[int(rep[3 * i])], int(rep[3 * i + 1]), float(rep[3 * i + 2]))
                 for i in range(n.value)]
+
+    # ---------------------------------------------- small dense products
+    def dense_gram(self, X, Y):
+        """C = X^T Y for X (n, ka), Y (n, kb) torch float64 tensors (any
+        strides), ka, kb <= 64."""
+        import torch
+        n, ka = X.shape
+        kb = Y.shape[1]
+        C_ = torch.empty(ka, kb, dtype=torch.float64, device=X.device)
+        self._check(lib().mm_dense_gram(self.h, n, ka, kb, _ptr(X), X.stride(0), X.stride(1),
+                                        _ptr(Y), Y.stride(0), Y.stride(1), _ptr(C_)),
+                    "mm_dense_gram")
+        return C_
+
+    def dense_tall(self, V, Y):
+        """Z = V Y for V (n, kin) and Y (kin, kout), column-major storage
+        (V.t() and Y.t() contiguous); returns Z (n, kout) as a transposed view."""
+        import torch
+        n, kin = V.shape
+        kout = Y.shape[1]
+        Vc, Yc = V.t().contiguous(), Y.t().contiguous()
+        Z = torch.empty(kout, n, dtype=torch.float64, device=V.device)
+        self._check(lib().mm_dense_tall(self.h, n, kin, kout, _ptr(Vc), _ptr(Yc), _ptr(Z)),
+                    "mm_dense_tall")
+        return Z.t()
+
+    def dense_rows(self, In, S, out=None, alpha: float = 1.0, beta: float = 0.0):
+        """Out = beta Out + alpha In S for In (n, R) row-major, S (R, R)."""
+        import torch
+        n, R = In.shape
+        Inc, Sc = In.contiguous(), S.contiguous()
+        if out is None:
+            out = torch.empty_like(Inc)
+        self._check(lib().mm_dense_rows(self.h, n, R, _ptr(Inc), _ptr(Sc), alpha, beta, _ptr(out)),
+                    "mm_dense_rows")
+        return out
 
     def pcg_session(self, p, nz, M, nrhs: int):
         h = C.c_void_p()

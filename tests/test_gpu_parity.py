@@ -572,6 +572,14 @@ def test_batched_block_cg_config4(ctx):
     assert all(i["converged"] and i["rel_res_true"] <= 1.5e-8 for i in ii)
     assert all(i["converged"] and i["rel_res_true"] <= 1.5e-8 for i in ib)
     assert it_blk <= it_ind
+    # block CG replayed from captured graphs (one iteration per chunk): the same
+    # iterations and bitwise the same map; with 8-iteration chunks, converged
+    xg, ig = ctx.solve(lp, ln, M, B, tol=1e-8, nrhs=R, check_every=1, history=False, block=True,
+                       graph=True)
+    assert max(i["iters"] for i in ig) == it_blk and torch.equal(xg, xb)
+    xg8, ig8 = ctx.solve(lp, ln, M, B, tol=1e-8, nrhs=R, check_every=8, history=False, block=True,
+                         graph=True)
+    assert all(i["converged"] and i["rel_res_true"] <= 1.5e-8 for i in ig8)
     OM = O.mbd_build(op, on)
     Xb = host(xb).reshape(op.n, R)
     for c in (0, R - 1):
@@ -601,20 +609,35 @@ def test_batched_fp32_variant(ctx):
     assert err <= 2e-5
 
 
-def test_autotune_keeps_results_bitwise(ctx):
+@pytest.mark.parametrize("nrhs", [1, 8, 64])
+def test_autotune_keeps_results_bitwise(ctx, nrhs):
+    """Stages 0-2 of the autotuner (P grid, the band's taps per LDS chunk,
+    P^T's pixel order) leave A bitwise unchanged, also on a band long enough
+    for several chunk lengths (lambda = 600); with the FFT block stage the
+    apply moves only at the rounding level."""
     import torch
     p = synth.config1()
-    lp, ln, op, on = build_both(ctx, p, method=1)
-    x = dev(np.random.default_rng(9).standard_normal(op.n * 8))
-    a1 = ctx.apply_A(lp, ln, x[: op.n])
-    a8 = ctx.apply_A(lp, ln, x, nrhs=8)
-    rep1 = ctx.autotune(lp, ln, 1)
-    rep8 = ctx.autotune(lp, ln, 8)
-    # at lambda = 32 the register-tiled band kernels (fixed tiles) serve one
-    # and eight columns: only P's grid is tuned
-    assert len(rep1) >= 5 and not any(r[0] == "band" for r in rep1 + rep8)
-    assert torch.equal(a1, ctx.apply_A(lp, ln, x[: op.n]))
-    assert torch.equal(a8, ctx.apply_A(lp, ln, x, nrhs=8))
+    for lam, method in ((32, 1), (600, 1)):
+        q = synth.config1() if lam == 32 else synth.config2(
+            n_side=32, grid=(2, 2), samp_per_det=1 << 15, L=1 << 13, half_bw=lam)
+        lp, ln, op, on = build_both(ctx, q, method=method)
+        lp.set_grid(q.n_side)
+        x = dev(np.random.default_rng(9).standard_normal(op.n * nrhs))
+        a0 = ctx.apply_A(lp, ln, x, nrhs=nrhs)
+        rep = ctx.autotune(lp, ln, nrhs)
+        stages = {r[0] for r in rep}
+        print(f"lambda {lam}, nrhs {nrhs}: {rep}")
+        assert "P" in stages and "band_chunk" in stages
+        assert ("PT_order" in stages) == (nrhs > 1)
+        assert torch.equal(a0, ctx.apply_A(lp, ln, x, nrhs=nrhs))
+    # FFT block stage: chosen block recorded, result within the FFT bar
+    q = synth.config2(n_side=32, grid=(2, 2), samp_per_det=1 << 15, L=1 << 13, half_bw=1000)
+    lp, ln, op, on = build_both(ctx, q, method=2)
+    x1 = np.random.default_rng(10).standard_normal(op.n)
+    rep = ctx.autotune(lp, ln, 1, fft_block=True)
+    assert {r[1] for r in rep if r[0] == "fft_block"} == {16384, 32768}
+    assert ln.fft_n in (16384, 32768)
+    assert maxrel(host(ctx.apply_A(lp, ln, dev(x1))), O.apply_A(op, on, x1)) <= 1e-11
 
 
 def test_PT_sliced_layout_parity_and_order(ctx):
