@@ -518,11 +518,21 @@ def form_c1(mm, ctx):
             "lambda 32 direct band, FP64, tol 1e-8", **out}
 
 
+def _config1_oracle_map():
+    """The FP64 oracle's config-1 map (PCG to 1e-13), stored by the committed
+    script tests/golden/make_config1_solution.py (the bench reads the file;
+    it does not run the oracle)."""
+    with open(os.path.join(ROOT, "tests", "golden", "config1_solution.json")) as f:
+        return np.array(json.load(f)["x"])
+
+
 def form_c3(mm, ctx):
     """Config 1 in the FP32 form (TOD, weights and N^-1 in FP32; dots, M_BD
     inverses and the coarse solve in FP64): time to a 1e-6 and a 1e-8 FP64
-    true residual next to the FP64 solver, and the map error against the FP64
-    solution at 1e-12."""
+    true residual next to the FP64 solver, plain and with FP64-residual
+    iterative refinement (FP32 PCG corrections, one FP64 A apply per outer
+    step), each map's error against the FP64 oracle's solution; and the same
+    at the config-2 scale."""
     import torch
     import synth
     p = synth.config1()
@@ -536,33 +546,42 @@ def form_c3(mm, ctx):
     b64 = ctx.rhs(lp64, ln64, tod)
     b32 = ctx.rhs(lp32, ln32, tod.float())
     M64, M32 = ctx.mbd(lp64, ln64), ctx.mbd(lp32, ln32)
-    # reference map: the FP64 solve to 1e-12 (the FP64 path itself is checked
-    # against the oracle by the GPU tests)
-    x_ref, _ = ctx.solve(lp64, ln64, M64, b64, tol=1e-12, max_iter=5000, history=False)
-    x_or = x_ref.cpu().numpy()
+    x_or = _config1_oracle_map()
     bn = float(torch.linalg.norm(b64))
 
     def true_res(xs):
         r = b64 - ctx.apply_A(lp64, ln64, xs)
         return float(torch.linalg.norm(r)) / bn
 
-    out = {}
+    def err(xs):
+        xh = xs.cpu().numpy()
+        return float(np.linalg.norm(xh - x_or) / np.linalg.norm(x_or))
+
+    out = {"map_reference": "FP64 oracle, PCG to 1e-13 (tests/golden/config1_solution.json)"}
     for tol in (1e-6, 1e-8):
         for name, lp, ln, M, b in (("fp64", lp64, ln64, M64, b64), ("fp32", lp32, ln32, M32, b32)):
             (r, t) = _wall(lambda: ctx.solve(lp, ln, M, b, tol=tol, max_iter=3000, check_every=8,
                                              history=False), reps=5)
             xs, info = r
-            xh = xs.cpu().numpy()
             out[f"{name}_tol{tol:g}"] = {
                 "iters": info["iters"], "converged": info["converged"], "solve_ms": t * 1e3,
                 "rel_res_own": info["rel_res_true"], "rel_res_fp64": true_res(xs),
-                "map_rel_err_vs_fp64_1e-12": float(np.linalg.norm(xh - x_or) / np.linalg.norm(x_or))}
+                "map_rel_err_vs_oracle": err(xs)}
+        for itol in (1e-4, 1e-5):
+            (r, t) = _wall(lambda: ctx.solve_refined(lp32, ln32, lp64, ln64, M64, b64, tol=tol,
+                                                     inner_tol=itol), reps=5)
+            xs, info = r
+            out[f"fp32_refined_inner{itol:g}_tol{tol:g}"] = {
+                "outer": info["outer"], "inner_iters": info["inner_iters"],
+                "converged": info["converged"], "solve_ms": t * 1e3,
+                "rel_res_fp64": true_res(xs), "map_rel_err_vs_oracle": err(xs)}
     # the same precision split at the config-2 scale, where the TOD passes are
-    # bandwidth-bound: A apply and PCG(M_BD) to 1e-6 / 1e-8 in both precisions
+    # bandwidth-bound: A apply and PCG(M_BD) to 1e-6 / 1e-8 in both precisions,
+    # and the FP32 form refined to 1e-8 against the FP64 residual
     p2 = synth.config2()
     pix2, psi2 = torch.from_numpy(p2.pix).to(dev), torch.from_numpy(p2.psi).to(dev)
     tod2 = torch.from_numpy(p2.tod).to(dev)
-    big = {}
+    big, H = {}, {}
     for name, prec in (("fp64", 0), ("fp32", 1)):
         lp = ctx.pointing(pix2, psi2, p2.n_pix_total, p2.min_hits, prec=prec)
         lp.set_grid(p2.n_side)
@@ -588,15 +607,26 @@ def form_c3(mm, ctx):
                                   "solve_s": t, "rel_res_own": info["rel_res_true"]}
             res[f"x_tol{tol:g}"] = xs
         big[name] = res
-        del lp, ln, M, b
+        H[name] = (lp, ln, M, b)
+    lp64b, ln64b, M64b, b64b = H["fp64"]
+    lp32b, ln32b, _, _ = H["fp32"]
+    (r, t) = _wall(lambda: ctx.solve_refined(lp32b, ln32b, lp64b, ln64b, M64b, b64b, tol=1e-8,
+                                             inner_tol=1e-5, max_inner=500))
+    xs, info = r
+    big["fp32_refined_tol1e-08"] = {
+        "outer": info["outer"], "inner_iters": info["inner_iters"], "converged": info["converged"],
+        "solve_s": t, "rel_res_fp64": info["rel_res_true"],
+        "map_rel_diff_vs_fp64_tol1e-8": float(torch.linalg.norm(xs - big["fp64"]["x_tol1e-08"])
+                                              / torch.linalg.norm(big["fp64"]["x_tol1e-08"]))}
+    del H
     for tol in (1e-6, 1e-8):
         x64, x32 = big["fp64"].pop(f"x_tol{tol:g}"), big["fp32"].pop(f"x_tol{tol:g}")
         big["fp32"][f"tol{tol:g}"]["map_rel_diff_vs_fp64"] = float(
             torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
     out["config2_scale"] = big
     return {"form": "c3", "workload": "config1 in FP32 (TOD, weights, N^-1 FP32; dots, M_BD, "
-            "coarse FP64), M_BD, tol 1e-6 and 1e-8; plus the config-2 scan at both "
-            "precisions", **out}
+            "coarse FP64), M_BD, tol 1e-6 and 1e-8, plain and with FP64-residual refinement; "
+            "plus the config-2 scan at both precisions", **out}
 
 
 def form_c4(mm, ctx):

@@ -416,6 +416,34 @@ mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const 
                    int32_t nrhs, const double *b, double *x, double tol, int32_t max_iter,
                    uint32_t flags, double *history, mm_solve_info *info);
 
+/* Mixed-precision iterative refinement: the true residual in the precision
+ * of (p_hi, nz_hi) (FP64), corrections solved by PCG with (p_lo, nz_lo)
+ * (typically the FP32 form) and M.  From x (in: x0, out: x):
+ *   repeat  r = A_hi x - b (one A_hi apply per outer step, stop when every
+ *           column has ||r|| / ||b|| <= tol); solve A_lo e = r by mm_solve to
+ *           the relative accuracy the remaining gap needs, max(inner_tol,
+ *           tol / (2 max_c ||r_c|| / ||b_c||)) capped at 0.5 (at most
+ *           max_inner iterations); x -= e.
+ * It reaches residuals the FP32 PCG stalls above (its recursion drifts from
+ * the FP64 residual near 5e-8).  Both pointings must hold the same observed
+ * pixels and Stokes components (built from the same pix), both noise handles
+ * the same samples; b, x [device] f64 map layout, nrhs columns.
+ *   info [host] mm_refine_info or NULL.
+ * Returns MM_OK when every column reaches tol, MM_NOT_CONVERGED after
+ * max_outer steps; errors as mm_solve. */
+typedef struct {
+    int32_t outer;          /* outer steps (A_hi applies after the first) */
+    int32_t inner_iters;    /* PCG iterations summed over the outer steps (max over columns) */
+    int32_t converged;      /* 1 if every column reached tol */
+    int32_t pad;
+    double rel_res_true;    /* max over columns of ||b - A_hi x|| / ||b|| at exit */
+    double solve_seconds;
+} mm_refine_info;
+mm_status mm_solve_refined(mm_ctx *ctx, const mm_pointing *p_lo, const mm_noise *nz_lo,
+                           const mm_pointing *p_hi, const mm_noise *nz_hi, const mm_precond *M,
+                           int32_t nrhs, const double *b, double *x, double tol, double inner_tol,
+                           int32_t max_outer, int32_t max_inner, mm_refine_info *info);
+
 /* ------------------------------------------------- step-wise PCG sessions */
 
 /* A PCG session holds nrhs column slots that iterate in lockstep with the

@@ -1389,6 +1389,84 @@ extern "C" mm_status mm_solve(mm_ctx *ctx, const mm_pointing *p, const mm_noise 
     return result;
 }
 
+// ================================================ iterative refinement
+
+extern "C" mm_status mm_solve_refined(mm_ctx *ctx, const mm_pointing *p_lo, const mm_noise *nz_lo,
+                                      const mm_pointing *p_hi, const mm_noise *nz_hi,
+                                      const mm_precond *M, int32_t nrhs, const double *b,
+                                      double *x, double tol, double inner_tol, int32_t max_outer,
+                                      int32_t max_inner, mm_refine_info *info) {
+    if (!ctx) return MM_E_INVALID;
+    mm_status result = MM_OK;
+    API_BEGIN(ctx)
+    const auto t0 = std::chrono::steady_clock::now();
+    check_pair(p_lo, nz_lo);
+    check_pair(p_hi, nz_hi);
+    check_nrhs(nrhs);
+    MM_CHECK(p_lo->n_samp == p_hi->n_samp && p_lo->n_obs == p_hi->n_obs && p_lo->nc == p_hi->nc,
+             MM_E_INVALID, "refine: the two pointings differ in samples or observed pixels");
+    MM_CHECK(b && x && b != x, MM_E_INVALID, "refine: bad b/x");
+    MM_CHECK(tol > 0 && inner_tol > 0 && max_outer >= 1 && max_inner >= 1, MM_E_INVALID,
+             "refine: tol, inner_tol > 0 and max_outer, max_inner >= 1");
+    MM_CHECK(!M || (M->n_obs == p_hi->n_obs && M->nc == p_hi->nc), MM_E_INVALID,
+             "refine: preconditioner of another pointing");
+    hipStream_t s = ctx->stream;
+    const int64_t n = p_hi->n();
+    const int R = nrhs;
+    DBuf r, e, Ax, nb;
+    r.alloc(sizeof(double) * n * R);
+    e.alloc(sizeof(double) * n * R);
+    Ax.alloc(sizeof(double) * n * R);
+    nb.alloc(sizeof(double) * 2 * R);
+    std::vector<double> h(2 * R);
+    dot_cols(ctx, n, R, b, b, nb.as<double>());
+    std::vector<mm_solve_info> inner(R);
+    int outer = 0, inner_total = 0;
+    double worst = 0;
+    bool conv = false;
+    for (;;) {
+        // r = A_hi x - b and its norm
+        apply_A_impl(ctx, p_hi, nz_hi, R, x, Ax.as<double>());
+        axpby_cols(ctx, n, R, Ax.as<double>(), b, r.as<double>());
+        dot_cols(ctx, n, R, r.as<double>(), r.as<double>(), nb.as<double>() + R);
+        MM_HIP(hipMemcpyAsync(h.data(), nb.ptr, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, s));
+        MM_HIP(hipStreamSynchronize(s));
+        conv = true;
+        worst = 0;
+        for (int c = 0; c < R; ++c) {
+            const double rel = h[c] > 0 ? std::sqrt(std::max(h[R + c], 0.0) / h[c]) : 0.0;
+            worst = std::max(worst, rel);
+            conv &= rel <= tol;
+        }
+        if (conv || outer == max_outer) break;
+        // correction: A_lo e = r to the accuracy the remaining gap needs
+        // (tol / residual, halved; at least inner_tol, at most 0.5), then x -= e
+        const double itol = std::min(0.5, std::max(inner_tol, 0.5 * tol / worst));
+        MM_HIP(hipMemsetAsync(e.ptr, 0, sizeof(double) * n * R, s));
+        const mm_status st = mm_solve(ctx, p_lo, nz_lo, M, R, r.as<double>(), e.as<double>(),
+                                      itol, max_inner, 4u, nullptr, inner.data());
+        if (st < 0) throw Error(st, std::string("refine: inner solve: ") + ctx->last_error);
+        int it = 0;
+        for (int c = 0; c < R; ++c) it = std::max(it, inner[c].iters);
+        inner_total += it;
+        axpby_cols(ctx, n, R, x, e.as<double>(), Ax.as<double>());  // x - e
+        MM_HIP(hipMemcpyAsync(x, Ax.ptr, sizeof(double) * n * R, hipMemcpyDeviceToDevice, s));
+        ++outer;
+    }
+    if (info) {
+        info->outer = outer;
+        info->inner_iters = inner_total;
+        info->converged = conv ? 1 : 0;
+        info->pad = 0;
+        info->rel_res_true = worst;
+        info->solve_seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    result = conv ? MM_OK : MM_NOT_CONVERGED;
+    API_END
+    return result;
+}
+
 // ============================================================= block CG
 
 // Block PCG (O'Leary 1980) with A-orthonormal search blocks:

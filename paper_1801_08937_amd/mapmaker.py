@@ -49,6 +49,11 @@ class RequestInfo(C.Structure):
                 ("queue_seconds", C.c_double), ("latency_seconds", C.c_double)]
 
 
+class RefineInfo(C.Structure):
+    _fields_ = [("outer", C.c_int32), ("inner_iters", C.c_int32), ("converged", C.c_int32),
+                ("pad", C.c_int32), ("rel_res_true", C.c_double), ("solve_seconds", C.c_double)]
+
+
 class ArnoldiInfo(C.Structure):
     _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("h_last", C.c_double),
                 ("setup_seconds", C.c_double)]
@@ -99,6 +104,8 @@ def lib() -> C.CDLL:
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
             "mm_defl_transfer": (C.c_int, [P, P, P, P, P, P, PP]),
             "mm_noise_set_fft_block": (C.c_int, [P, P, I32]),
+            "mm_solve_refined": (C.c_int, [P, P, P, P, P, P, I32, P, P, D, D, I32, I32,
+                                           C.POINTER(RefineInfo)]),
             "mm_dense_gram": (C.c_int, [P, I64, I32, I32, P, I64, I64, P, I64, I64, P]),
             "mm_dense_tall": (C.c_int, [P, I64, I32, I32, P, P, P]),
             "mm_dense_rows": (C.c_int, [P, I64, I32, P, P, D, D, P]),
@@ -454,6 +461,22 @@ class Context:
         names = {0: "P", 1: "band_chunk", 2: "PT_order", 3: "fft_block"}
         return [(names[int(rep[3 * i])], int(rep[3 * i + 1]), float(rep[3 * i + 2]))
                 for i in range(n.value)]
+
+    def solve_refined(self, p_lo, nz_lo, p_hi, nz_hi, M, b, x=None, tol: float = 1e-8,
+                      inner_tol: float = 1e-5, max_outer: int = 20, max_inner: int = 2000,
+                      nrhs: int = 1):
+        """Iterative refinement: FP64 residual (p_hi, nz_hi), corrections by PCG
+        with (p_lo, nz_lo).  Returns (x, info dict)."""
+        import torch
+        _dev_check(b, torch.float64, p_hi.n * nrhs, "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        info = RefineInfo()
+        st = lib().mm_solve_refined(self.h, p_lo.h, nz_lo.h, p_hi.h, nz_hi.h,
+                                    M.h if M is not None else None, nrhs, _ptr(b), _ptr(x), tol,
+                                    inner_tol, max_outer, max_inner, C.byref(info))
+        self._check(st, "mm_solve_refined")
+        return x, {f: getattr(info, f) for f, _ in RefineInfo._fields_ if f != "pad"}
 
     # ---------------------------------------------- small dense products
     def dense_gram(self, X, Y):

@@ -267,6 +267,35 @@ def test_fp32_form_error_vs_fp64_oracle(ctx):
     assert err <= 2e-5
 
 
+def test_fp32_refined_to_fp64_residual(ctx):
+    """FP32 form with FP64-residual iterative refinement (one FP64 A apply per
+    outer step): the FP32 PCG alone stalls near a 5e-8 true residual, the
+    refined solve reaches 1e-10, and its map is within 1e-8 of the oracle's
+    1e-13 solution (the stored config-1 reference) with the FP64 residual
+    confirmed by the oracle's own A."""
+    import json
+    import os
+    p = synth.config1()
+    lp64, ln64, op, on = build_both(ctx, p)
+    lp32, ln32, _, _ = build_both(ctx, p, prec=1)
+    M = ctx.mbd(lp64, ln64)
+    b = ctx.rhs(lp64, ln64, dev(p.tod))
+    x, info = ctx.solve_refined(lp32, ln32, lp64, ln64, M, b, tol=1e-10, inner_tol=1e-5)
+    print(f"refined FP32: {info}")
+    assert info["converged"] and info["rel_res_true"] <= 1e-10 and info["outer"] >= 2
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config1_solution.json")) as f:
+        ref = np.array(json.load(f)["x"])
+    xg = host(x)
+    err = rel(xg, ref)
+    bo = O.rhs(op, on, p.tod)
+    res = float(np.linalg.norm(bo - O.apply_A(op, on, xg)) / np.linalg.norm(bo))
+    print(f"refined FP32 map error vs oracle {err:.2e}, oracle-A residual {res:.2e}")
+    assert err <= 1e-8 and res <= 1.5e-10
+    # the same call with both operators FP64 converges in one outer step
+    x2, i2 = ctx.solve_refined(lp64, ln64, lp64, ln64, M, b, tol=1e-8, inner_tol=1e-9)
+    assert i2["converged"] and i2["outer"] == 1
+
+
 def test_error_paths(ctx):
     import torch
     from paper_1801_08937_amd import mapmaker as mm

@@ -1023,3 +1023,18 @@ def test_pcg_lanczos_stops_at_tolerance():
     _, i1 = O.pcg(A, lambda v: O.mbd_apply(M, v), b, 1e-6, 1000)
     res = O.pcg_lanczos(A, lambda v: O.mbd_apply(M, v), b, 1000, tol=1e-6)
     assert res.m == i1.iters   # the prior solve's own iteration count
+
+
+def test_stored_config1_solution_is_the_oracles():
+    """tests/golden/config1_solution.json (the reference of the FP32 form's map
+    error) is what its committed script computes from the oracle now."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_config1_solution", os.path.join(GOLDEN, "make_config1_solution.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    x, b, info = mod.solve()
+    ref = _golden("config1_solution.json")
+    assert info.rel_res_true <= 1e-12
+    assert np.max(np.abs(np.array(ref["x"]) - x)) <= 1e-12 * np.max(np.abs(x))
+    assert abs(ref["b_norm"] - float(np.linalg.norm(b))) <= 1e-12 * ref["b_norm"]
