@@ -999,14 +999,26 @@ def _n1_size(mm, ctx, lams, n_samp, L, dev, ev):
     return rows
 
 
-def form_d1(mm, ctx, n_sub=8, full_m2l=2):
+def _stats(v):
+    """median, 16th and 84th percentiles and (p84 - p16) / 2 (the spread the
+    paper tabulates)."""
+    v = np.asarray(v, dtype=np.float64)
+    p16, p50, p84 = np.percentile(v, [16, 50, 84])
+    return {"median": float(p50), "p16": float(p16), "p84": float(p84),
+            "half_spread": float((p84 - p16) / 2), "n": int(v.size)}
+
+
+def form_d1(mm, ctx, n_sub=64, full_m2l=8):
     """Divide and conquer with the "simplified" two-level preconditioner
-    (Sect. 7.3): the config-2 scan split by detectors into n_sub subsets over
-    the same patch, each filtered as in form f1 (white noise, quadratic
-    polynomials per 256-sample subscan).  Z is built once, by Arnoldi on
-    subset 0, and reused on the others with AZ and E rebuilt per subset; each
-    subset is solved to 1e-8 with M_BD, with that transferred M_2l, and (for
-    the first full_m2l subsets) with its own M_2l."""
+    (Sect. 7.3, tab. stats and fig. histos2D on synthetic data): the config-2
+    scan split by detectors into n_sub subsets over the same patch (two
+    detectors, 2^21 samples each at n_sub = 64), each filtered as in form f1
+    (white noise, quadratic polynomials per 256-sample subscan).  Z (k = 32)
+    is built once, by Arnoldi on subset 0, and moved to every other subset
+    with A Z and E rebuilt there (mm_defl_transfer).  Every subset is solved
+    to 1e-8 with M_BD and with the transferred M_2l, and the first full_m2l
+    with their own M_2l; per solve the iterations to 1e-8 and the residual
+    after 100 iterations, then their statistics and histograms."""
     import torch
     import synth
     dev = torch.device("cuda", 0)
@@ -1030,9 +1042,11 @@ def form_d1(mm, ctx, n_sub=8, full_m2l=2):
 
         def run(M):
             ((_, info), t) = _wall(lambda: ctx.solve(lp, lf, M, b, tol=1e-8, max_iter=3000,
-                                                     check_every=4, history=False))
+                                                     check_every=1, history=True))
+            h = info["history"]
+            r100 = float(h[100]) if len(h) > 100 and h[100] >= 0 else float(info["rel_res_true"])
             return {"iters": info["iters"], "converged": info["converged"],
-                    "rel_res_true": info["rel_res_true"], "solve_s": t}
+                    "rel_res_true": info["rel_res_true"], "res_at_100": r100, "solve_s": t}
         row["mbd"] = run(Mbd)
         if k == 0:
             (M2, t) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=32, eps_arn=1e-8, m_max=256))
@@ -1043,64 +1057,117 @@ def form_d1(mm, ctx, n_sub=8, full_m2l=2):
             (Ms, t) = _wall(lambda: ctx.defl_transfer(src[0], src[1], lp, lf, Mbd))
             row["m2l_transferred"] = run(Ms)
             row["m2l_transferred"]["setup_s"] = t
-            if k <= full_m2l:
+            del Ms
+            if k < full_m2l:
                 (M2, t) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=32, eps_arn=1e-8,
                                                        m_max=256))
                 row["m2l_own"] = run(M2)
                 row["m2l_own"]["setup_s"] = t
+                del M2
         rows.append(row)
-        log(f"[bench] subset {k}: {row}")
-        del lp, lf, Mbd, b
-    it_bd = [r["mbd"]["iters"] for r in rows]
-    it_tr = [r["m2l_transferred"]["iters"] for r in rows if "m2l_transferred" in r]
+        log(f"[bench] subset {k}: " + json.dumps({kk: vv for kk, vv in row.items()}))
+        if k > 0:
+            del lp
+        del lf, Mbd, b
+    summary, hist = {}, {}
+    edges = [0, 20, 30, 40, 50, 60, 80, 100, 125, 150, 200, 300, 3000]
+    for name in ("mbd", "m2l_transferred", "m2l_own"):
+        its = [r[name]["iters"] for r in rows if name in r]
+        res = [r[name]["res_at_100"] for r in rows if name in r]
+        if not its:
+            continue
+        summary[name] = {"iters_to_1e-8": _stats(its), "residual_after_100": _stats(res),
+                         "all_converged": all(r[name]["converged"] for r in rows if name in r),
+                         "setup_s_median": float(np.median([r[name].get("setup_s", 0.0)
+                                                            for r in rows if name in r]))}
+        counts, _ = np.histogram(its, bins=edges)
+        hist[name] = {f"[{a},{b_})": int(c) for a, b_, c in zip(edges[:-1], edges[1:], counts)}
     return {"form": "d1", "workload": f"config-2 scan split by detectors into {n_sub} subsets "
-            "(16 detectors, 1.68e7 samples each), quadratic polynomial filter per 256-sample "
-            "subscan, white noise; Z (k = 32) from subset 0 reused on the others, tol 1e-8",
-            "summary": {"mbd_iters_mean": float(np.mean(it_bd)), "mbd_iters_max": int(max(it_bd)),
-                        "transferred_m2l_iters_mean": float(np.mean(it_tr)),
-                        "transferred_m2l_iters_max": int(max(it_tr))},
-            "subsets": rows}
+            f"({128 // n_sub} detectors, {per} samples each), quadratic polynomial filter per "
+            "256-sample subscan, white noise; Z (k = 32) from subset 0 moved to the others, "
+            "tol 1e-8", "summary": summary, "iteration_histograms": hist, "subsets": rows}
 
 
 def form_z1(mm, ctx):
-    """Deflation-space study on one filtered subset of form d1 (1.68e7 samples,
-    quadratic polynomials per subscan): iterations and times to 1e-8 against
-    dim Z (k) and the Arnoldi length m_max (our Arnoldi stops on
-    h_{j+1,j} <= eps_Arn or at m_max; on these scans h stays near 0.2, so
-    m_max plays the part of the paper's eps_Arn)."""
+    """The eps_Arn x dim Z study of Sect. 6 (figs. eigenspectrum, binned_ritz
+    and arntol_vs_dimZ) on a problem in the paper's regime: white noise and a
+    template filter with few templates -- linear polynomials per 8,192-sample
+    subscan, 256 templates on 2^20 samples over a 64 x 64 patch -- so that
+    M_BD A is the identity minus a perturbation of rank <= 256 and Arnoldi
+    from the initial residual of a random guess reaches numerical convergence (h_{j+1,j} falls by orders of
+    magnitude) within a few hundred steps.  One long Arnoldi run gives
+    h_{j+1,j} and the step at which each eps_Arn stops it; for each eps_Arn,
+    the Ritz values of H_m (the library's host eigensolver), binned, and the
+    PCG iterations to 1e-8 for several dim Z."""
     import torch
     import synth
     dev = torch.device("cuda", 0)
-    p = synth.config2()
-    per = p.n_samp // 8
-    ipd = p.n_intervals // 8
-    pix = torch.from_numpy(p.pix[:per]).to(dev)
-    psi = torch.from_numpy(p.psi[:per]).to(dev)
-    lp = ctx.pointing(pix, psi, p.n_pix_total, p.min_hits)
+    p = synth.config2(n_side=64, grid=(4, 4), samp_per_det=1 << 16, L=1 << 14, half_bw=10)
+    lp = ctx.pointing(torch.from_numpy(p.pix).to(dev), torch.from_numpy(p.psi).to(dev),
+                      p.n_pix_total, p.min_hits)
     lp.set_grid(p.n_side)
-    lf = ctx.polyfilter(lp, p.interval_start[:ipd + 1], np.ones(ipd),
-                        np.arange(0, per + 1, 256), 2)
-    d = synth.signal_tod(p.pix[:per], p.psi[:per], p.signal) + \
-        synth.rng_for(2, 10, synth.STREAM_NOISE).standard_normal(per)
+    sub_len, order = 8192, 1
+    lf = ctx.polyfilter(lp, p.interval_start, np.ones(p.n_intervals),
+                        np.arange(0, p.n_samp + 1, sub_len), order)
+    n_tmpl = (p.n_samp // sub_len) * (order + 1)
+    d = synth.signal_tod(p.pix, p.psi, p.signal) + \
+        synth.rng_for(2, 30, synth.STREAM_NOISE).standard_normal(p.n_samp)
     b = ctx.rhs(lp, lf, torch.from_numpy(d).to(dev))
     Mbd = ctx.mbd(lp, lf)
     ((_, i0), t0) = _wall(lambda: ctx.solve(lp, lf, Mbd, b, tol=1e-8, max_iter=3000,
                                            check_every=4, history=False))
-    grid = []
-    for m_max in (64, 128, 256):
-        for k in (4, 8, 16, 32, 48):
-            if k >= m_max:
+    m_max = 500
+    # Arnoldi starts from the initial residual r_0 = M_BD (b - A x_0) of a
+    # seeded random guess x_0: with x_0 = 0 on white noise, M_BD b lies almost
+    # wholly in the eigenvalue-1 eigenspace and h_21 is already below 1e-2
+    x0 = torch.from_numpy(synth.rng_for(2, 31, synth.STREAM_SIGNAL).standard_normal(lp.n)).to(dev)
+    seed = b - ctx.apply_A(lp, lf, x0)
+    del x0
+    # run to numerical convergence (h_{j+1,j} at the rounding level, 1e-14)
+    Mfull = ctx.defl_build(lp, lf, Mbd, seed, k=8, eps_arn=1e-14, m_max=m_max)
+    h = np.array(Mfull.h_history)
+    del Mfull
+    eps_list = (1e-1, 1e-2, 1e-3, 1e-4, 1e-6, 1e-8, 1e-10)
+    stops = {}
+    for eps in eps_list:
+        idx = np.flatnonzero(h <= eps)
+        stops[eps] = int(idx[0]) + 1 if idx.size else m_max
+    bins = np.array([0.0, 1e-3, 1e-2, 0.1, 0.3, 0.6, 0.9, 0.99, 1.01, 2.0, np.inf])
+    rows = []
+    for eps in eps_list:
+        row = {"eps_arn": eps, "arnoldi_steps": stops[eps]}
+        (M8, ts) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, seed, k=8, eps_arn=eps, m_max=m_max))
+        W, H = M8.arnoldi()
+        m = H.shape[1]
+        theta, _ = mm.hessenberg_eig(H[:m, :m])
+        th = np.sort(theta.real)
+        row["ritz_count"] = int(m)
+        row["ritz_smallest"] = [float(v) for v in th[:8]]
+        row["ritz_binned"] = {f"[{lo:g},{hi:g})": int(np.sum((th >= lo) & (th < hi)))
+                              for lo, hi in zip(bins[:-1], bins[1:])}
+        del W, M8
+        row["dimZ"] = {}
+        for k in (4, 8, 16, 24, 32, 48):
+            if k > m:
                 continue
-            (M2, ts) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, b, k=k, eps_arn=1e-8,
+            (M2, ts) = _wall(lambda: ctx.defl_build(lp, lf, Mbd, seed, k=k, eps_arn=eps,
                                                     m_max=m_max))
             ((_, info), t) = _wall(lambda: ctx.solve(lp, lf, M2, b, tol=1e-8, max_iter=3000,
                                                      check_every=4, history=False))
-            grid.append({"m_max": m_max, "k": k, "iters": info["iters"],
-                         "converged": info["converged"], "solve_s": t, "setup_s": ts})
-            log(f"[bench] z1 {grid[-1]}")
-    return {"form": "z1", "workload": "one detector subset of the config-2 scan (16 detectors, "
-            "1.68e7 samples), quadratic polynomial filter per 256-sample subscan, tol 1e-8",
-            "mbd": {"iters": i0["iters"], "solve_s": t0}, "grid": grid}
+            row["dimZ"][k] = {"iters": info["iters"], "converged": info["converged"],
+                              "solve_s": t, "setup_s": ts}
+            del M2
+        log(f"[bench] z1 {row}")
+        rows.append(row)
+    return {"form": "z1", "workload": f"64x64 patch, 16 detectors x 2^16 samples (2^20), white "
+            f"noise, linear polynomials per {sub_len}-sample subscan ({n_tmpl} templates), "
+            "tol 1e-8; Arnoldi from r_0 = M_BD (b - A x_0), x_0 seeded N(0,1), k smallest "
+            "Ritz vectors",
+            "n_unknowns": lp.n, "templates": n_tmpl,
+            "mbd": {"iters": i0["iters"], "solve_s": t0},
+            "h_history": {str(j): float(h[j - 1]) for j in (1, 10, 25, 50, 100, 150, 200, 250,
+                                                             300, 400, 500) if j <= len(h)},
+            "rows": rows}
 
 
 def form_c5(mm, ctx, n_requests=200, slots=1):

@@ -838,51 +838,6 @@ extern "C" mm_status mm_defl_transfer(mm_ctx *ctx, const mm_pointing *p_src,
     return MM_OK;
 }
 
-// Eigen-decomposition of a small symmetric matrix (cyclic Jacobi rotations):
-// A (n x n, row-major) is destroyed; w = eigenvalues, U column j = vector j.
-static void sym_eig_jacobi(int n, std::vector<double> &A, std::vector<double> &w,
-                           std::vector<double> &U) {
-    U.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0, tot = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                const double a = A[(size_t)i * n + j] * A[(size_t)i * n + j];
-                tot += a;
-                if (i != j) off += a;
-            }
-        if (off <= 1e-30 * tot) break;
-        for (int pq = 0; pq < n * n; ++pq) {
-            const int pi = pq / n, qi = pq % n;
-            if (qi <= pi) continue;
-            const double apq = A[(size_t)pi * n + qi];
-            if (apq == 0.0) continue;
-            const double app = A[(size_t)pi * n + pi], aqq = A[(size_t)qi * n + qi];
-            const double th = 0.5 * (aqq - app) / apq;
-            const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-            const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-            for (int r = 0; r < n; ++r) {  // A <- A J (columns pi, qi)
-                const double x = A[(size_t)r * n + pi], y = A[(size_t)r * n + qi];
-                A[(size_t)r * n + pi] = c * x - sn * y;
-                A[(size_t)r * n + qi] = sn * x + c * y;
-            }
-            for (int r = 0; r < n; ++r) {  // A <- J^T A (rows pi, qi)
-                const double x = A[(size_t)pi * n + r], y = A[(size_t)qi * n + r];
-                A[(size_t)pi * n + r] = c * x - sn * y;
-                A[(size_t)qi * n + r] = sn * x + c * y;
-            }
-            for (int r = 0; r < n; ++r) {  // U <- U J
-                const double x = U[(size_t)r * n + pi], y = U[(size_t)r * n + qi];
-                U[(size_t)r * n + pi] = c * x - sn * y;
-                U[(size_t)r * n + qi] = sn * x + c * y;
-            }
-        }
-    }
-    w.resize(n);
-    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
-}
-
 // Ritz pairs of the m x m projected matrix Hm (column-major; Arnoldi's
 // Hessenberg H_m or the Lanczos tridiagonal T_m), selection of the k smallest
 // past the null directions (or all with Re theta < eps_lambda), V = W Y and

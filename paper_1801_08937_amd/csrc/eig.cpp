@@ -66,10 +66,11 @@ void eig2(double a, double b, double c, double d, cd &e1, cd &e2) {
     const double mid = 0.5 * (a + d);
     if (disc >= 0) {
         const double sq = std::sqrt(disc);
-        // avoid cancellation: larger-magnitude root first
-        const double r1 = mid + (p >= 0 ? sq : -sq);
+        // avoid cancellation: the larger-magnitude root mid +- sq takes the
+        // sign of mid, the other one follows from the determinant
+        const double r1 = mid + (mid >= 0 ? sq : -sq);
         const double prod = a * d - b * c;
-        const double r2 = r1 != 0 ? prod / r1 : mid - (p >= 0 ? sq : -sq);
+        const double r2 = r1 != 0 ? prod / r1 : mid - (mid >= 0 ? sq : -sq);
         e1 = cd(r1, 0);
         e2 = cd(r2, 0);
     } else {
@@ -114,14 +115,23 @@ std::vector<cd> hqr_eigenvalues(Mat H) {
             iter = 0;
             continue;
         }
-        MM_CHECK(total < 60 * n, MM_E_DEVICE, "Hessenberg QR did not converge");
+        MM_CHECK(total < 30 * std::max(10, n) * 4, MM_E_DEVICE, "Hessenberg QR did not converge");
         ++iter;
         ++total;
         double s, t;
-        if (iter % 11 == 10) {  // exceptional shift
-            const double w = std::fabs(H(u, u - 1)) + std::fabs(H(u - 1, u - 2));
-            s = 1.5 * w;
-            t = w * w;
+        if (iter % 10 == 0) {
+            // exceptional shifts, centred on a diagonal entry of the window:
+            // the eigenvalues of [[a, -0.4375 w], [w, a]] with a = h + 0.75 w,
+            // w the size of two neighbouring subdiagonals -- alternately at the
+            // bottom (h = H(u,u)) and at the top (h = H(l,l)) of the window.
+            // They break the cycles the standard shifts can fall into on tight
+            // clusters of eigenvalues.
+            const bool top = (iter / 10) % 2 == 0;
+            const double w = top ? std::fabs(H(l + 1, l)) + std::fabs(H(l + 2, l + 1))
+                                 : std::fabs(H(u, u - 1)) + std::fabs(H(u - 1, u - 2));
+            const double a = (top ? H(l, l) : H(u, u)) + 0.75 * w;
+            s = 2.0 * a;
+            t = a * a + 0.4375 * w * w;
         } else {
             s = H(u - 1, u - 1) + H(u, u);
             t = H(u - 1, u - 1) * H(u, u) - H(u - 1, u) * H(u, u - 1);
@@ -179,6 +189,51 @@ void hess_solve(const Mat &H, cd theta, std::vector<cd> &b) {
 
 }  // namespace
 
+// Eigen-decomposition of a small symmetric matrix (cyclic Jacobi rotations):
+// A (n x n, row-major) is destroyed; w = eigenvalues, U column j = vector j.
+void sym_eig_jacobi(int n, std::vector<double> &A, std::vector<double> &w,
+                           std::vector<double> &U) {
+    U.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double a = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int pq = 0; pq < n * n; ++pq) {
+            const int pi = pq / n, qi = pq % n;
+            if (qi <= pi) continue;
+            const double apq = A[(size_t)pi * n + qi];
+            if (apq == 0.0) continue;
+            const double app = A[(size_t)pi * n + pi], aqq = A[(size_t)qi * n + qi];
+            const double th = 0.5 * (aqq - app) / apq;
+            const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+            const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+            for (int r = 0; r < n; ++r) {  // A <- A J (columns pi, qi)
+                const double x = A[(size_t)r * n + pi], y = A[(size_t)r * n + qi];
+                A[(size_t)r * n + pi] = c * x - sn * y;
+                A[(size_t)r * n + qi] = sn * x + c * y;
+            }
+            for (int r = 0; r < n; ++r) {  // A <- J^T A (rows pi, qi)
+                const double x = A[(size_t)pi * n + r], y = A[(size_t)qi * n + r];
+                A[(size_t)pi * n + r] = c * x - sn * y;
+                A[(size_t)qi * n + r] = sn * x + c * y;
+            }
+            for (int r = 0; r < n; ++r) {  // U <- U J
+                const double x = U[(size_t)r * n + pi], y = U[(size_t)r * n + qi];
+                U[(size_t)r * n + pi] = c * x - sn * y;
+                U[(size_t)r * n + qi] = sn * x + c * y;
+            }
+        }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
 void hessenberg_eig(int m, const double *Hcm, double *wr, double *wi, double *vr, double *vi) {
     Mat H{m, std::vector<double>((size_t)m * m)};
     double hnorm = 0;
@@ -187,7 +242,32 @@ void hessenberg_eig(int m, const double *Hcm, double *wr, double *wi, double *vr
             H(i, j) = (i <= j + 1) ? Hcm[(size_t)j * m + i] : 0.0;
             hnorm = std::max(hnorm, std::fabs(H(i, j)));
         }
-    std::vector<cd> ev = hqr_eigenvalues(H);
+    std::vector<cd> ev;
+    try {
+        ev = hqr_eigenvalues(H);
+    } catch (const Error &) {
+        // QR can stall on tight clusters of a symmetric matrix (a Lanczos
+        // tridiagonal whose converged Ritz values repeat): there the Jacobi
+        // rotations give eigenvalues and orthonormal eigenvectors directly
+        double asym = 0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < i; ++j) asym = std::max(asym, std::fabs(H(i, j) - H(j, i)));
+        if (!(asym <= 1e-12 * std::max(hnorm, 1e-300))) throw;
+        std::vector<double> A(H.a), w, U;
+        sym_eig_jacobi(m, A, w, U);
+        std::vector<int> order(m);
+        for (int i = 0; i < m; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int p, int q) { return w[p] < w[q]; });
+        for (int i = 0; i < m; ++i) {
+            wr[i] = w[order[i]];
+            wi[i] = 0.0;
+            for (int q = 0; q < m; ++q) {
+                vr[(size_t)i * m + q] = U[(size_t)q * m + order[i]];
+                vi[(size_t)i * m + q] = 0.0;
+            }
+        }
+        return;
+    }
     std::sort(ev.begin(), ev.end(), [](const cd &a, const cd &b) {
         return a.real() != b.real() ? a.real() < b.real() : a.imag() < b.imag();
     });

@@ -336,6 +336,9 @@ void copy_cols_masked(mm_ctx *ctx, int64_t n, int nrhs, const int *done, const d
 
 // host
 void hessenberg_eig(int m, const double *H, double *wr, double *wi, double *vr, double *vi);
+// Eigen-decomposition of a small symmetric matrix (cyclic Jacobi rotations):
+// A (n x n, row-major) is destroyed; w = eigenvalues, U column j = vector j.
+void sym_eig_jacobi(int n, std::vector<double> &A, std::vector<double> &w, std::vector<double> &U);
 
 template <typename T> struct Vec2T;
 template <> struct Vec2T<float> { using type = float2; };

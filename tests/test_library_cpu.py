@@ -79,3 +79,49 @@ def test_graft_entry_exposes_build_and_smoke(root_dir):
     ge = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(ge)
     assert callable(ge.build) and callable(ge.smoke)
+
+
+def test_hessenberg_eig_clustered_tridiagonals():
+    """Symmetric tridiagonals (Lanczos-like) with tight clusters of equal
+    diagonal entries and tiny couplings, where a QR iteration with shifts
+    that do not track the cluster stalls: eigenvalues against LAPACK's
+    eigvalsh, eigenpair residuals small."""
+    rng = np.random.default_rng(0)
+    for _ in range(120):
+        m = int(rng.integers(2, 160))
+        d = rng.choice([1.0, 2.0, 3.0], m) + rng.standard_normal(m) * 10.0 ** rng.integers(-16, 0)
+        e = rng.standard_normal(m - 1) * 10.0 ** rng.integers(-18, 0)
+        T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+        w, V = mm.hessenberg_eig(T)
+        ref = np.linalg.eigvalsh(T)
+        tn = np.abs(T).max()
+        assert np.max(np.abs(np.sort(w.real) - ref)) <= 1e-9 * tn
+        assert np.max(np.abs(w.imag)) <= 1e-9 * tn
+        for i in range(0, m, max(1, m // 8)):
+            v = V[:, i]
+            assert np.linalg.norm(T @ v - w[i] * v) <= 1e-7 * tn * np.linalg.norm(v)
+
+
+def test_hessenberg_eig_converged_arnoldi_with_template_filter():
+    """H from an Arnoldi run to numerical convergence on M_BD A with white
+    noise and few filter templates (M_BD A = I minus a low-rank term: most
+    Ritz values cluster at 1), the regime of the eps_Arn study."""
+    import oracle as O
+    import synth
+    p = synth.config2(n_side=32, grid=(4, 2), samp_per_det=1 << 12, L=1 << 11, half_bw=10)
+    op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    pf = O.polyfilter_build(op, p.interval_start, np.ones(p.n_intervals),
+                            np.arange(0, p.n_samp + 1, 512), 1)
+    M = O.mbd_build(op, pf)
+    u = np.random.default_rng(1).uniform(-1, 1, op.n)
+    res = O.arnoldi(lambda w: O.mbd_apply(M, O.apply_A(op, pf, w)),
+                    O.mbd_apply(M, O.apply_A(op, pf, u)), 200, 1e-14)
+    assert res.m < 200 and res.h_last <= 1e-14   # numerical convergence
+    for m in (res.m // 2, res.m - 5, res.m):
+        H = res.H[:m, :m]
+        w, V = mm.hessenberg_eig(H)
+        hn = np.abs(H).max()
+        ref = np.linalg.eigvals(H)
+        np.testing.assert_allclose(np.sort(w.real), np.sort(ref.real), atol=1e-7 * hn)
+        for i in range(m):
+            assert np.linalg.norm(H @ V[:, i] - w[i] * V[:, i]) <= 1e-7 * hn
