@@ -309,6 +309,16 @@ typedef struct {
     double setup_seconds; /* wall time of the whole build */
 } mm_arnoldi_info;
 
+/* Arnoldi stop rules (Appendix A; the paper stops once the error term of
+ * Eq. factoriz, h_{m+1,m} w_{m+1} e_m^T, falls below eps_Arn):
+ *   MM_ARN_STOP_H         h_{j+1,j} <= eps_arn, the test of the algorithm box;
+ *   MM_ARN_STOP_RESIDUAL  the error term applied to the Arnoldi solution of
+ *                         B x = r_0, h_{j+1,j} |(H_j^-1 e_1)_j|, relative to
+ *                         ||r_0||, <= eps_arn (the reading under which a lower
+ *                         eps_Arn solves the system to that residual, Sect. 6).
+ * Both also stop when h_{j+1,j} = 0 (an invariant Krylov space). */
+enum { MM_ARN_STOP_H = 0, MM_ARN_STOP_RESIDUAL = 1 };
+
 /* M_2l from Ritz vectors (Sect. 6, Appendix A): Arnoldi on B = M_BD A from
  * r_0 = M_BD b_seed, classical Gram-Schmidt applied twice, until
  * h_{j+1,j} <= eps_arn or m_max steps; eigenpairs of H_m ordered by real
@@ -324,6 +334,18 @@ mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
                         const mm_precond *mbd, const double *b_seed, int32_t k,
                         double eps_lambda, double eps_arn, int32_t m_max,
                         double *h_history, mm_arnoldi_info *info, mm_precond **out);
+/* mm_defl_build with a chosen Arnoldi stop rule (MM_ARN_STOP_*);
+ * mm_defl_build is this call with MM_ARN_STOP_H and res_history NULL.
+ *   b_seed      r_0 = M_BD b_seed: b for x_0 = 0, b - A x_0 for a guess x_0
+ *   res_history [host] f64[m_max] or NULL: the Arnoldi solution's relative
+ *               residual h_{j+1,j} |(H_j^-1 e_1)_j| per step (+inf where H_j is
+ *               singular), whichever rule stops the run
+ * Errors: as mm_defl_build; MM_E_INVALID for an unknown stop rule. */
+mm_status mm_defl_build_stop(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                             const mm_precond *mbd, const double *b_seed, int32_t k,
+                             double eps_lambda, double eps_arn, int32_t stop_rule, int32_t m_max,
+                             double *h_history, double *res_history, mm_arnoldi_info *info,
+                             mm_precond **out);
 /* M_2l from the Ritz vectors of a prior M_BD solve: PCG with M_BD on
  * A x = b from x_0 = 0 (Eq. pcg) until ||r||/||b|| <= tol or m_max
  * iterations, whose coefficients give the

@@ -19,8 +19,11 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
     diag(N^-1);
   * PCG uses beta = rho_new / rho for both preconditioners (M_2l is not
     symmetric; Sect. 3.2);
-  * Arnoldi starts from r_0 = M_BD b (x_0 = 0), orthogonalises by classical
-    Gram-Schmidt applied twice, stops when h_{j+1,j} <= eps_Arn or j = m_max;
+  * Arnoldi starts from r_0 = M_BD b_seed (b_seed = b - A x_0; b for
+    x_0 = 0), orthogonalises by classical Gram-Schmidt applied twice, stops
+    when h_{j+1,j} <= eps_Arn (the algorithm box) or, as a second reading of
+    the error term, when the Arnoldi solution's relative residual
+    h_{j+1,j} |(H_j^-1 e_1)_j| <= eps_Arn, or at j = m_max;
   * Ritz values are ordered by real part; a complex pair is never split; the
     real and imaginary parts of a pair's vector both enter Z.
 """
@@ -32,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "Pointing", "Noise", "OracleError", "pointing_build", "apply_P", "apply_PT",
-    "noise_build", "noise_apply_direct", "noise_apply_fft", "noise_apply",
+    "noise_build", "noise_apply_direct", "noise_apply_fft", "noise_apply", "fom_residual",
     "apply_A", "apply_A_pixels", "rhs", "Mbd", "mbd_build", "mbd_apply", "M2l", "m2l_from_Z",
     "m2l_apply", "arnoldi", "ritz_select", "defl_build", "pcg", "SolveInfo",
     "dense_P", "dense_Ninv", "PolyFilter", "polyfilter_build", "polyfilter_apply",
@@ -532,16 +535,45 @@ class ArnoldiResult:
     H: np.ndarray      # f64[m+1, m] Hessenberg matrix incl. h_{m+1,m}
     m: int
     h_last: float
+    res: np.ndarray | None = None   # f64[m] fom_residual after each step
 
 
-def arnoldi(apply_B, r0, m_max: int, eps_arn: float, reorth: bool = True) -> ArnoldiResult:
+def fom_residual(H: np.ndarray, j: int) -> float:
+    """||W~_j y_j|| / ||r_0|| for the Arnoldi (full orthogonalisation)
+    solution of B x = r_0 in the j-step Krylov space, y_j = H_j^-1 ||r_0|| e_1:
+    by Eq. factoriz the residual r_0 - B W_j y_j is -h_{j+1,j} (e_j^T y_j)
+    w_{j+1}, so its relative norm is h_{j+1,j} |(H_j^-1 e_1)_j|.  Infinite if
+    H_j is singular.  H holds at least j+1 rows and j columns."""
+    Hj = H[:j, :j]
+    e1 = np.zeros(j)
+    e1[0] = 1.0
+    try:
+        y = np.linalg.solve(Hj, e1)
+    except np.linalg.LinAlgError:
+        return float("inf")
+    return float(H[j, j - 1] * abs(y[j - 1]))
+
+
+def arnoldi(apply_B, r0, m_max: int, eps_arn: float, reorth: bool = True,
+            stop: str = "h") -> ArnoldiResult:
     """w_1 = r0/||r0||; for j: v = B w_j; h_ij = (v, w_i) for all i <= j from
     the same v (classical Gram-Schmidt); v -= sum h_ij w_i; with reorth the
     projection is repeated once and added into h (CGS2); h_{j+1,j} = ||v||;
-    stop when h_{j+1,j} <= eps_arn, else w_{j+1} = v / h_{j+1,j}."""
+    stop when the error term of Eq. factoriz falls to eps_arn, else
+    w_{j+1} = v / h_{j+1,j}.  Two readings of that test (App. A):
+    stop="h"        h_{j+1,j} <= eps_arn, as the algorithm box writes it
+                    (||W~_j|| = h_{j+1,j});
+    stop="residual" fom_residual(H, j) <= eps_arn, the error term applied to
+                    the Arnoldi solution of B x = r_0 (the reading under
+                    which tightening eps_Arn solves the system to that
+                    residual, as Sect. 6 says).
+    Either rule also stops on h_{j+1,j} = 0 (an invariant subspace)."""
+    if stop not in ("h", "residual"):
+        raise OracleError("INVALID", "stop rule is 'h' or 'residual'")
     n = r0.shape[0]
     W = np.zeros((n, m_max + 1))
     H = np.zeros((m_max + 1, m_max))
+    res = np.zeros(m_max)
     W[:, 0] = r0 / np.linalg.norm(r0)
     m = 0
     h_last = 0.0
@@ -558,10 +590,12 @@ def arnoldi(apply_B, r0, m_max: int, eps_arn: float, reorth: bool = True) -> Arn
         H[j + 1, j] = hn
         m = j + 1
         h_last = hn
-        if hn <= eps_arn:
+        res[j] = fom_residual(H, m)
+        test = hn if stop == "h" else res[j]
+        if test <= eps_arn or hn == 0.0:
             break
         W[:, j + 1] = v / hn
-    return ArnoldiResult(W[:, :m + 1], H[:m + 1, :m], m, h_last)
+    return ArnoldiResult(W[:, :m + 1], H[:m + 1, :m], m, h_last, res[:m].copy())
 
 
 NULL_RITZ_REL = 1e-10
@@ -608,13 +642,14 @@ def ritz_select(H_m: np.ndarray, k: int, eps_lambda: float = 0.0):
 
 def defl_build(pt: Pointing, nz: Noise, mbd: Mbd, b_seed, k: int, eps_arn: float,
                m_max: int, eps_lambda: float = 0.0, method: str = "direct",
-               reorth: bool = True):
+               reorth: bool = True, stop: str = "h"):
     """Deflation space from Ritz vectors of B = M_BD A (Sect. 6): Arnoldi from
-    r_0 = M_BD b_seed, Ritz selection, V = W_m Y, Z = Q of a Householder QR
-    of V (numpy's QR).  Returns (M2l, ArnoldiResult, theta)."""
+    r_0 = M_BD b_seed (stop rule as in arnoldi), Ritz selection, V = W_m Y,
+    Z = Q of a Householder QR of V (numpy's QR).
+    Returns (M2l, ArnoldiResult, theta)."""
     r0 = mbd_apply(mbd, b_seed)
     res = arnoldi(lambda w: mbd_apply(mbd, apply_A(pt, nz, w, method)), r0, m_max,
-                  eps_arn, reorth)
+                  eps_arn, reorth, stop)
     theta, Y = ritz_select(res.H[:res.m, :res.m], k, eps_lambda)
     V = res.W[:, :res.m] @ Y
     Z = np.linalg.qr(V)[0] if V.shape[1] else V

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -971,11 +972,22 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
                                    const mm_precond *mbd, const double *b_seed, int32_t k,
                                    double eps_lambda, double eps_arn, int32_t m_max,
                                    double *h_history, mm_arnoldi_info *info, mm_precond **out) {
+    return mm_defl_build_stop(ctx, p, nz, mbd, b_seed, k, eps_lambda, eps_arn, MM_ARN_STOP_H,
+                              m_max, h_history, nullptr, info, out);
+}
+
+extern "C" mm_status mm_defl_build_stop(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
+                                        const mm_precond *mbd, const double *b_seed, int32_t k,
+                                        double eps_lambda, double eps_arn, int32_t stop_rule,
+                                        int32_t m_max, double *h_history, double *res_history,
+                                        mm_arnoldi_info *info, mm_precond **out) {
     if (!ctx || !out) return MM_E_INVALID;
     *out = nullptr;
     API_BEGIN(ctx)
     auto t_start = std::chrono::steady_clock::now();
     check_pair(p, nz);
+    MM_CHECK(stop_rule == MM_ARN_STOP_H || stop_rule == MM_ARN_STOP_RESIDUAL, MM_E_INVALID,
+             "defl: unknown Arnoldi stop rule");
     MM_CHECK(mbd && mbd->kind == 0 && mbd->n_obs == p->n_obs && mbd->nc == p->nc, MM_E_INVALID,
              "defl: needs an M_BD handle of the same pointing");
     MM_CHECK(b_seed, MM_E_INVALID, "defl: null b_seed");
@@ -1012,6 +1024,14 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
         MM_HIP(hipMemcpyAsync(hd.as<double>() + 1, hp + 1, sizeof(double), hipMemcpyHostToDevice, s));
         scale_copy(ctx, n, v.as<double>(), hd.as<double>() + 1, W, 1);
         std::vector<double> H((size_t)(m_max + 1) * m_max, 0.0);
+        // Givens rotations reducing the (j+1) x j Hessenberg matrix to
+        // triangular form: the least-squares residual after step j is
+        // |gamma| = |s_1 ... s_j| (relative to ||r_0||) and the Arnoldi
+        // (Galerkin) solution's residual h_{j+1,j} |(H_j^-1 e_1)_j| equals
+        // |gamma| / |c_j| (Saad, Iterative Methods for Sparse Linear
+        // Systems, 2nd ed., Sect. 6.5.7), so each step costs O(j)
+        std::vector<double> gc(m_max), gs(m_max), col(m_max + 1);
+        double gamma = 1.0;
         int m = 0;
         double h_last = 0;
         for (int j = 0; j < m_max; ++j) {
@@ -1033,7 +1053,21 @@ extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_n
             if (h_history) h_history[j] = hn;
             m = j + 1;
             h_last = hn;
-            if (!(hn > eps_arn)) break;
+            for (int i = 0; i <= j + 1; ++i) col[i] = H[(size_t)j * (m_max + 1) + i];
+            for (int i = 0; i < j; ++i) {
+                const double a = col[i], b = col[i + 1];
+                col[i] = gc[i] * a + gs[i] * b;
+                col[i + 1] = -gs[i] * a + gc[i] * b;
+            }
+            const double d = std::hypot(col[j], col[j + 1]);
+            gc[j] = d > 0 ? col[j] / d : 1.0;
+            gs[j] = d > 0 ? col[j + 1] / d : 0.0;
+            gamma = -gs[j] * gamma;
+            const double res = gc[j] != 0 ? std::fabs(gamma) / std::fabs(gc[j])
+                                          : std::numeric_limits<double>::infinity();
+            if (res_history) res_history[j] = res;
+            const double test = stop_rule == MM_ARN_STOP_H ? hn : res;
+            if (!(test > eps_arn) || !(hn > 0)) break;
             hp[0] = hn;
             MM_HIP(hipMemcpyAsync(hd.ptr, hp, sizeof(double), hipMemcpyHostToDevice, s));
             scale_copy(ctx, n, v.as<double>(), hd.as<double>(), W + (int64_t)(j + 1) * n, 1);

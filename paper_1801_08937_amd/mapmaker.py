@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
             "mm_mbd_build": (C.c_int, [P, P, P, PP]),
             "mm_mbd_rcond": (C.c_int, [P, C.POINTER(D)]),
             "mm_defl_build": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, PP]),
+            "mm_defl_build_stop": (C.c_int, [P, P, P, P, P, I32, D, D, I32, I32, P, P, P, PP]),
             "mm_defl_build_pcg": (C.c_int, [P, P, P, P, P, I32, D, D, I32, P, P, P, PP]),
             "mm_defl_from_Z": (C.c_int, [P, P, P, P, I32, P, PP]),
             "mm_defl_transfer": (C.c_int, [P, P, P, P, P, P, PP]),
@@ -374,18 +375,27 @@ class Context:
         return Precond(self, h, p.n, 1)
 
     def defl_build(self, p, nz, mbd, b_seed, k: int = 32, eps_arn: float = 1e-8,
-                   m_max: int = 256, eps_lambda: float = 0.0):
+                   m_max: int = 256, eps_lambda: float = 0.0, stop: str = "h"):
+        """M_2l by Arnoldi from r_0 = M_BD b_seed.  stop: "h" (h_{j+1,j} <=
+        eps_arn) or "residual" (the Arnoldi solution's relative residual <=
+        eps_arn).  The handle carries .h_history and .res_history per step."""
         import torch
         _dev_check(b_seed, torch.float64, p.n, "b_seed")
+        rule = {"h": 0, "residual": 1}.get(stop)
+        if rule is None:
+            raise ValueError("stop is 'h' or 'residual'")
         hist = np.zeros(m_max)
+        res = np.zeros(m_max)
         info = ArnoldiInfo()
         h = C.c_void_p()
-        self._check(lib().mm_defl_build(self.h, p.h, nz.h, mbd.h, _ptr(b_seed), k, eps_lambda,
-                                        eps_arn, m_max, hist.ctypes.data, C.byref(info),
-                                        C.byref(h)), "mm_defl_build")
+        self._check(lib().mm_defl_build_stop(self.h, p.h, nz.h, mbd.h, _ptr(b_seed), k,
+                                             eps_lambda, eps_arn, rule, m_max,
+                                             hist.ctypes.data, res.ctypes.data, C.byref(info),
+                                             C.byref(h)), "mm_defl_build_stop")
         M = Precond(self, h, p.n, 1)
         M.arnoldi_info = info
         M.h_history = hist[: info.m].copy()
+        M.res_history = res[: info.m].copy()
         return M
 
     def defl_build_pcg(self, p, nz, mbd, b, k: int = 32, m_max: int = 256, tol: float = 0.0,

@@ -183,11 +183,15 @@ def straight_raster(n_side: int, n_det: int, n_samp_per_det: int) -> np.ndarray:
     return out
 
 
-def rotated_raster(n_side: int, grid: tuple[int, int], n_samp_per_det: int) -> np.ndarray:
+def rotated_raster(n_side: int, grid: tuple[int, int], n_samp_per_det: int,
+                   angles_deg=(0.0, 60.0, 120.0)) -> np.ndarray:
     """Cross-linked raster scans.  A pass is n_side sweeps of n_side samples;
-    pass m is rotated by (m mod 3)*60 degrees about the patch centre.  Detector
-    k sits at focal-plane offset (2(k mod gx)-(gx-1), 2(k div gx)-(gy-1)) px.
-    Samples falling off the patch get pixel -1 (flagged)."""
+    pass m is rotated by angles_deg[m mod len(angles_deg)] about the patch
+    centre (the default, three passes 60 degrees apart, cross-links every
+    pixel; a few degrees apart mimic the weak cross-linking of constant-
+    elevation scans).  Detector k sits at focal-plane offset
+    (2(k mod gx)-(gx-1), 2(k div gx)-(gy-1)) px.  Samples falling off the
+    patch get pixel -1 (flagged)."""
     gx, gy = grid
     n_det = gx * gy
     per_pass = n_side * n_side
@@ -199,8 +203,8 @@ def rotated_raster(n_side: int, grid: tuple[int, int], n_samp_per_det: int) -> n
     a = np.where(q % 2 == 0, u, n_side - 1 - u).astype(np.float64) + 0.5 - half
     b = q.astype(np.float64) + 0.5 - half
     rot = []
-    for o in range(3):
-        th = math.radians(60.0 * o)
+    for ang in angles_deg:
+        th = math.radians(ang)
         ct, st = math.cos(th), math.sin(th)
         rot.append((half + a * ct - b * st, half + a * st + b * ct))
     n_pass = n_samp_per_det // per_pass
@@ -209,7 +213,7 @@ def rotated_raster(n_side: int, grid: tuple[int, int], n_samp_per_det: int) -> n
         ox = 2 * (k % gx) - (gx - 1)
         oy = 2 * (k // gx) - (gy - 1)
         for m in range(n_pass):
-            x, y = rot[m % 3]
+            x, y = rot[m % len(rot)]
             ix = np.floor(x + ox).astype(np.int64)
             iy = np.floor(y + oy).astype(np.int64)
             ok = (ix >= 0) & (ix < n_side) & (iy >= 0) & (iy < n_side)
@@ -299,12 +303,12 @@ def config1(realization: int = 0, noiseless: bool = False) -> Problem:
 
 def config2(realization: int = 0, noiseless: bool = False, n_side: int = 256,
             grid=(16, 8), samp_per_det: int = 1 << 20, L: int = 1 << 16,
-            half_bw: int = 4096) -> Problem:
+            half_bw: int = 4096, angles_deg=(0.0, 60.0, 120.0)) -> Problem:
     """256x256 patch, 128 detectors x 2^20 samples of cross-linked rasters,
     f_knee ~ U[0.05, 1] Hz per detector, intervals of 2^16, lambda = 4,096.
     Smaller shapes of the same structure come from the keyword arguments."""
     n_det = grid[0] * grid[1]
-    pix = rotated_raster(n_side, grid, samp_per_det)
+    pix = rotated_raster(n_side, grid, samp_per_det, angles_deg)
     fk = rng_for(2, realization, STREAM_FKNEE).uniform(0.05, 1.0, n_det)
     p = _finish("c2", 2, realization, n_side, pix, L, half_bw, fk, samp_per_det, noiseless)
     return p

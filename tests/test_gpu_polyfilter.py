@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 import synth
-from gpu_util import dev, host, maxrel, rel
+from gpu_util import build_both, dev, host, maxrel, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -377,3 +377,50 @@ def test_filter_on_stokes_subset_pointing(ctx, stokes):
     assert maxrel(host(ctx.precond_apply(M, dev(x))), O.mbd_apply(O.mbd_build(op, of), x)) <= TOL_OP
     xs, info = ctx.solve(lp, lf, M, b, tol=1e-10, max_iter=3000)
     assert info["converged"] and info["rel_res_true"] <= 1e-9, info
+
+
+def test_arnoldi_residual_stop_rule_vs_oracle(ctx):
+    """Arnoldi under the residual stop rule (App. A: the error term of
+    Eq. factoriz applied to the Arnoldi solution of B x = r_0) on a weakly
+    cross-linked scan (passes 5 degrees apart) filtered by offset + slope per
+    sweep: the GPU and the oracle stop at the same step (a crossing within
+    1e-6 of eps may move it by one), their residual histories agree to 1e-6,
+    the library's stop is the first step at or below eps, and Z spans the
+    oracle's space.  The literal rule h_{j+1,j} <= eps does not stop on this
+    problem (h stays near 0.2)."""
+    import scipy.linalg
+    p = synth.config2(n_side=16, grid=(2, 2), samp_per_det=1536, L=768, half_bw=8,
+                      angles_deg=(0.0, 5.0, -5.0))
+    lp, _, op, _ = build_both(ctx, p)
+    sub = np.arange(0, p.n_samp + 1, 16)
+    w = np.ones(p.n_intervals)
+    lf = ctx.polyfilter(lp, p.interval_start, w, sub, 1)
+    of = O.polyfilter_build(op, p.interval_start, w, sub, 1)
+    M = ctx.mbd(lp, lf)
+    OM = O.mbd_build(op, of)
+    x0 = synth.rng_for(2, 31, synth.STREAM_SIGNAL).standard_normal(op.n_obs * op.nc)
+    b = O.rhs(op, of, p.tod) - O.apply_A(op, of, x0)
+    k = 10
+    for eps in (1e-3, 1e-6, 1e-9):
+        print(f"[residual rule] eps {eps:g}", flush=True)
+        M2 = ctx.defl_build(lp, lf, M, dev(b), k=k, eps_arn=eps, m_max=200, stop="residual")
+        OM2, res, theta = O.defl_build(op, of, OM, b, k, eps, 200, stop="residual")
+        m = M2.arnoldi_info.m
+        rg = M2.res_history
+        assert rg.shape[0] == m and rg[-1] <= eps and np.all(rg[:-1] > eps)
+        j = min(m, res.m)
+        np.testing.assert_allclose(rg[:j], res.res[:j], rtol=1e-6, atol=0)
+        if abs(res.res[res.m - 1] - eps) > 1e-6 * eps and \
+                (res.m < 2 or abs(res.res[res.m - 2] - eps) > 1e-6 * eps):
+            assert m == res.m, (eps, m, res.m)
+        else:
+            assert abs(m - res.m) <= 1
+        th = np.sort(theta.real)
+        Zg = host(M2.export()[0])
+        if m == res.m and th[k] - th[k - 1] > 1e-3 * th[k]:
+            s = scipy.linalg.subspace_angles(Zg, OM2.Z)
+            assert np.max(np.sin(s)) <= 1e-6, (eps, np.max(np.sin(s)))
+        del M2
+    Mh = ctx.defl_build(lp, lf, M, dev(b), k=k, eps_arn=1e-6, m_max=200, stop="h")
+    assert Mh.arnoldi_info.m == 200
+    np.testing.assert_allclose(Mh.res_history[:60], res.res[:60], rtol=1e-6, atol=0)

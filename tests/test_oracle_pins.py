@@ -386,6 +386,59 @@ def test_ritz_select_keeps_pairs():
     assert Y.shape[1] == 2
 
 
+def test_fom_residual_is_the_true_residual_of_the_arnoldi_solution():
+    """fom_residual (App. A, error term of Eq. factoriz applied to the
+    Arnoldi solution) against r_0 - B W_j y_j formed by applying B itself,
+    y_j = H_j^-1 ||r_0|| e_1, on a non-symmetric B, at every step."""
+    rng = np.random.default_rng(41)
+    n = 50
+    B = np.eye(n) + 0.4 * rng.standard_normal((n, n)) / np.sqrt(n)
+    r0 = rng.standard_normal(n)
+    res = O.arnoldi(lambda w: B @ w, r0, 30, 0.0)
+    beta = np.linalg.norm(r0)
+    for j in range(1, res.m + 1):
+        y = np.linalg.solve(res.H[:j, :j], beta * np.eye(j)[:, 0])
+        true = np.linalg.norm(r0 - B @ (res.W[:, :j] @ y)) / beta
+        assert abs(res.res[j - 1] - true) <= 1e-9 * max(true, 1e-6), (j, res.res[j - 1], true)
+    assert res.res[-1] < 1e-8 * res.res[0]
+
+
+def test_fom_residual_equals_cg_residual_on_spd():
+    """For symmetric positive definite B the Arnoldi (full orthogonalisation)
+    solution is the conjugate-gradient iterate, so the residual history of
+    the residual stop rule must be CG's ||r_j|| / ||r_0|| step by step."""
+    rng = np.random.default_rng(42)
+    n = 80
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    B = Q @ np.diag(np.geomspace(1e-2, 1.0, n)) @ Q.T
+    r0 = rng.standard_normal(n)
+    res = O.arnoldi(lambda w: B @ w, r0, 25, 0.0)
+    _, info = O.pcg(lambda x: B @ x, lambda r: r, r0, 0.0, 25)
+    np.testing.assert_allclose(res.res, info.history[1:26], rtol=1e-7)
+
+
+def test_arnoldi_residual_rule_stops_where_the_residual_falls():
+    """stop="residual" ends at the first step whose Arnoldi-solution residual
+    is <= eps_Arn; the Hessenberg entries up to there are those of the
+    unstopped run; stop="h" on the same B runs on while h_{j+1,j} stays
+    large (a spectrum spread over [0.01, 1] keeps h near 0.2)."""
+    rng = np.random.default_rng(43)
+    n = 120
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    B = Q @ np.diag(np.geomspace(1e-2, 1.0, n)) @ Q.T
+    r0 = rng.standard_normal(n)
+    full = O.arnoldi(lambda w: B @ w, r0, 100, 0.0)
+    for eps in (1e-2, 1e-4, 1e-6):
+        j = int(np.flatnonzero(full.res <= eps)[0]) + 1
+        st = O.arnoldi(lambda w: B @ w, r0, 100, eps, stop="residual")
+        assert st.m == j and st.res[-1] <= eps and np.all(st.res[:-1] > eps)
+        np.testing.assert_allclose(st.H, full.H[:j + 1, :j], rtol=0, atol=1e-12)
+        hs = O.arnoldi(lambda w: B @ w, r0, 100, eps, stop="h")
+        assert hs.m > j
+    with pytest.raises(O.OracleError):
+        O.arnoldi(lambda w: B @ w, r0, 10, 1e-3, stop="gmres")
+
+
 def _hessenberg_with_spectrum(eigs, seed, symmetric):
     """An upper Hessenberg matrix similar to diag(eigs) (scipy's Householder
     reduction of T D T^-1), and its eigenvectors as columns (U^T T)."""
