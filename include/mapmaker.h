@@ -41,6 +41,13 @@
  *    or 64.  Columns are processed independently and in a fixed order, so a
  *    column's result does not depend on the values in the other columns.
  *  - Not thread safe per context: calls on one context must not overlap.
+ *  - Sharing handles: a pointing, noise or preconditioner handle is read-only
+ *    once its set-up calls are done (the build that created it, then
+ *    mm_pointing_set_grid, mm_noise_set_fft_block, mm_autotune).  After that
+ *    several contexts, on one host thread or several, may use it at the same
+ *    time: every apply, solve and build reads it only, and each context
+ *    works in its own stream and scratch.  A set-up call must not overlap
+ *    any other use of the handle.  A PCG session belongs to its context.
  */
 #ifndef MAPMAKER_H
 #define MAPMAKER_H

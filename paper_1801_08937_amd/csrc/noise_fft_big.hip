@@ -15,7 +15,10 @@
 // (xor-swizzled) and the thread's other component stays in registers.  The
 // first forward pass reads global memory, the radix-RL passes run in
 // registers, the spectrum step reads each value's partner Z_{NC-k} through
-// the same LDS buffer, and the last inverse pass writes global memory.
+// the same LDS buffer, and the last inverse pass writes global memory.  The
+// block reads and writes global memory through raw buffer resources sized to
+// its window and to its valid outputs, so the interval clipping and the
+// overlap-save discard cost no per-element compares.
 #include <cmath>
 
 #include "fft_common.h"
@@ -35,6 +38,51 @@ template <int NC_> struct Geo {
 };
 constexpr int BIG_MAX_LAMBDA = 12288;  // 32,768-sample blocks: V = N - 2 lambda >= 8,192
 constexpr int MID_MAX_LAMBDA = 6144;   // 16,384-sample blocks: V >= 4,096
+
+// Raw buffer accesses (resource word of the gfx9 family, stride 0): a load
+// whose offset (VGPR part plus instruction offset) falls outside
+// [0, num_records) bytes returns 0 and such a store is dropped.  A block's
+// input resource covers its window clipped to the interval and its output
+// resource the block's valid outputs, which gives the overlap-save block its
+// zero padding and discards its edges with 32-bit offsets and no compares.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+// Two consecutive elements in one access (16 bytes FP64, 8 bytes FP32).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void buf_ld2(__amdgpu_buffer_rsrc_t r, int off, double &a, double &b) {
+    const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void buf_ld2(__amdgpu_buffer_rsrc_t r, int off, float &a, float &b) {
+    const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, int off, double a, double b) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, make_double2(a, b)), r, off,
+                                           0, 0);
+}
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, int off, float a, float b) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(a, b)), r, off, 0,
+                                          0);
+}
 
 // LDS index of element i: its low four bits xor-ed with the next four, a
 // bijection on [0, NC) that spreads the stride-16 accesses of the radix-16
@@ -201,15 +249,18 @@ __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T
     __syncthreads();
 }
 
-template <typename G, typename T>
+// RC = the column count when it is known at compile time (1), else 0 and the
+// column count is R.
+template <typename G, typename T, int RC>
 __global__ void __launch_bounds__(G::TH) __attribute__((amdgpu_waves_per_eu(4)))
     k_noise_fft_reg(const int64_t *__restrict__ blocks, const int64_t *__restrict__ istart,
                     const int32_t *__restrict__ fid,
                     const typename Vec2T<T>::type *__restrict__ ab,
                     const typename Vec2T<T>::type *__restrict__ tw,
-                    const typename Vec2T<T>::type *__restrict__ twN, int lam, int V, int R,
+                    const typename Vec2T<T>::type *__restrict__ twN, int lam, int V, int R_,
                     const T *__restrict__ y, T *__restrict__ z) {
     __shared__ T sh[G::NC];
+    const int R = RC > 0 ? RC : R_;
     const int tid = threadIdx.x;
     const int rr = blockIdx.y;
     const int64_t t0 = blocks[2 * blockIdx.x];
@@ -218,14 +269,32 @@ __global__ void __launch_bounds__(G::TH) __attribute__((amdgpu_waves_per_eu(4)))
     const int64_t base = t0 - lam;
     T re[16], im[16];
     // forward pass 1 from global: z_m = y_{base+2m} + i y_{base+2m+1}, m = tid + TH r.
-    // Block-uniform base pointer and bounds, 32-bit per-thread offsets.
-    const T *yb = y + base * R + rr;
-    const int lo = (int)(a - base), hi = (int)(e - base);  // valid offsets [lo, hi)
+    // The resource spans the window [base, base + 2 NC) clipped to the
+    // interval [a, e): samples outside it read as 0.
+    const int64_t w0 = base > a ? base : a;
+    const int64_t w1 = base + 2 * G::NC < e ? base + 2 * G::NC : e;
+    const auto ry = raw_rsrc(y + w0 * R, (w1 - w0) * R * (int64_t)sizeof(T));
+    const int off0 = ((int)(base - w0) * R + rr) * (int)sizeof(T);
+    // One column: each thread's pair (y_{2m}, y_{2m+1}) is one access when
+    // the window's ends fall on even offsets from base, so that no pair
+    // straddles them (block-uniform; false only for odd lambda or an odd
+    // interval end).  Otherwise, and for several columns, every access moves
+    // one element, wholly inside or outside the resource; the second
+    // element's offset is hidden from the optimiser there so that the two
+    // are never merged into one access across a resource end.
+    if (RC == 1 && (((w0 - base) | (w1 - base)) & 1) == 0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int u0 = 2 * (tid + G::TH * r);
-        re[r] = (u0 >= lo && u0 < hi) ? yb[u0 * R] : (T)0;
-        im[r] = (u0 + 1 >= lo && u0 + 1 < hi) ? yb[(u0 + 1) * R] : (T)0;
+        for (int r = 0; r < 16; ++r)
+            buf_ld2(ry, off0 + 2 * (tid + G::TH * r) * (int)sizeof(T), re[r], im[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int off = off0 + 2 * (tid + G::TH * r) * R * (int)sizeof(T);
+            int off1 = off + R * (int)sizeof(T);
+            asm volatile("" : "+v"(off1));
+            re[r] = buf_ld<T>(ry, off);
+            im[r] = buf_ld<T>(ry, off1);
+        }
     }
     dft16<T, -1>(re, im);
     passes_234<G, T, -1>(sh, re, im, tw, tid);
@@ -245,13 +314,25 @@ __global__ void __launch_bounds__(G::TH) __attribute__((amdgpu_waves_per_eu(4)))
     dft16<T, 1>(re, im);
     passes_234<G, T, 1>(sh, re, im, tw, tid_i);
     // registers hold z'_m, m = tid + TH q: outputs 2m and 2m + 1 of the block
-    const int nvalid = (int)(e - t0 < V ? e - t0 : V);
-    T *zb = z + t0 * R + rr;
+    // output 2m - lam of the block is valid in [0, nvalid): the resource
+    // spans exactly those outputs, the stores of the others are dropped
+    const int64_t nvalid = e - t0 < V ? e - t0 : V;
+    const auto rz = raw_rsrc(z + t0 * R, nvalid * R * (int64_t)sizeof(T));
+    // pairs as for the loads: the valid range [0, nvalid) starts lam before
+    // each pair's even offset 2m, so pairs are whole when lam and nvalid are even
+    if (RC == 1 && ((lam | (int)nvalid) & 1) == 0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int q0 = 2 * (tid_i + G::TH * q) - lam;
-        if (q0 >= 0 && q0 < nvalid) zb[q0 * R] = re[q];
-        if (q0 + 1 >= 0 && q0 + 1 < nvalid) zb[(q0 + 1) * R] = im[q];
+        for (int q = 0; q < 16; ++q)
+            buf_st2(rz, (2 * (tid_i + G::TH * q) - lam) * (int)sizeof(T), re[q], im[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int off = ((2 * (tid_i + G::TH * q) - lam) * R + rr) * (int)sizeof(T);
+            int off1 = off + R * (int)sizeof(T);
+            asm volatile("" : "+v"(off1));
+            buf_st(rz, off, re[q]);
+            buf_st(rz, off1, im[q]);
+        }
     }
 }
 
@@ -271,13 +352,15 @@ void noise_fft_reg_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const vo
         using G = decltype(GG);
         if (nz->prec == MM_F32) {
             const float2 *tw = nz->fft_tw.as<float2>();
-            k_noise_fft_reg<G, float><<<grid, G::TH, 0, ctx->stream>>>(
+            auto k = nrhs == 1 ? k_noise_fft_reg<G, float, 1> : k_noise_fft_reg<G, float, 0>;
+            k<<<grid, G::TH, 0, ctx->stream>>>(
                 nz->fft_blocks.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
                 nz->fft_spec.as<float2>(), tw, tw + G::NC, nz->half_bw, nz->fft_valid, nrhs,
                 static_cast<const float *>(y), static_cast<float *>(z));
         } else {
             const double2 *tw = nz->fft_tw.as<double2>();
-            k_noise_fft_reg<G, double><<<grid, G::TH, 0, ctx->stream>>>(
+            auto k = nrhs == 1 ? k_noise_fft_reg<G, double, 1> : k_noise_fft_reg<G, double, 0>;
+            k<<<grid, G::TH, 0, ctx->stream>>>(
                 nz->fft_blocks.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
                 nz->fft_spec.as<double2>(), tw, tw + G::NC, nz->half_bw, nz->fft_valid, nrhs,
                 static_cast<const double *>(y), static_cast<double *>(z));
