@@ -224,6 +224,7 @@ def main():
                     help="measure one form (latency, FP32, batched, serving) instead")
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
+    ap.add_argument("--rate", type=float, default=4.0, help="serving arrival rate (requests/s)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -258,7 +259,7 @@ def main():
               "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1, "h1": form_h1, "n1": form_n1,
               "mf": form_mf,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
-                                         slots=args.slots)}[args.form]
+                                         slots=args.slots, rate=args.rate)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
         ctx.close()
         return
@@ -1180,8 +1181,8 @@ def form_z1(mm, ctx):
             "rows": rows}
 
 
-def form_c5(mm, ctx, n_requests=200, slots=1):
-    """Serving: a Poisson trace (4 requests/s) over four recurring strategies
+def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0):
+    """Serving: a Poisson trace (`rate` requests/s) over four recurring strategies
     of uneven size (2^20 to 2^27 samples, lambda 1,024 to 8,192), tolerance
     1e-6 or 1e-8.  Served by mm_server_* (cached pointing, M_BD and M_2l per
     strategy, continuous batching over `slots` columns) and, as the baseline,
@@ -1192,7 +1193,7 @@ def form_c5(mm, ctx, n_requests=200, slots=1):
     import synth.gpu as sg
     from paper_1801_08937_amd import serving
     dev = torch.device("cuda", 0)
-    arrivals, strat, tol = synth.poisson_arrivals(n_requests, 4.0, seed=0)
+    arrivals, strat, tol = synth.poisson_arrivals(n_requests, rate, seed=0)
     S = []
     for s in range(4):
         t0 = time.perf_counter()
@@ -1314,7 +1315,7 @@ def form_c5(mm, ctx, n_requests=200, slots=1):
             "solves_per_s": n_requests / wall_b, "wall_s": wall_b,
             "iters_mean": float(np.mean(iters))}
     log(f"[bench] baseline: {base}")
-    return {"form": "c5", "workload": "Poisson 4 req/s, 4 strategies: 64^2/16 det x 2^16 "
+    return {"form": "c5", "workload": f"Poisson {rate:g} req/s, 4 strategies: 64^2/16 det x 2^16 "
             "(lambda 1024), 128^2/32 x 2^18 (2048), 256^2/64 x 2^20 (4096), 256^2/128 x 2^20 "
             "(8192); tol 1e-6 or 1e-8; slots %d" % slots, "served": served,
             "served_m2l_at_registration": served_pre,
