@@ -22,6 +22,7 @@
 #include <cmath>
 
 #include "fft_common.h"
+#include "xcd.h"
 
 namespace mm {
 namespace {
@@ -258,13 +259,26 @@ __global__ void __launch_bounds__(G::TH) __attribute__((amdgpu_waves_per_eu(4)))
                     const typename Vec2T<T>::type *__restrict__ ab,
                     const typename Vec2T<T>::type *__restrict__ tw,
                     const typename Vec2T<T>::type *__restrict__ twN, int lam, int V, int R_,
-                    const T *__restrict__ y, T *__restrict__ z) {
+                    int64_t n_blk, const T *__restrict__ y, T *__restrict__ z) {
     __shared__ T sh[G::NC];
     const int R = RC > 0 ? RC : R_;
     const int tid = threadIdx.x;
-    const int rr = blockIdx.y;
-    const int64_t t0 = blocks[2 * blockIdx.x];
-    const int64_t iv = blocks[2 * blockIdx.x + 1];
+    // Several columns: one flat grid of (block, column) pairs, padded to a
+    // multiple of 8 and remapped so that each XCD takes a contiguous run of
+    // them, in which the R columns of a block are neighbours: they read and
+    // write the same interleaved cache lines, which then meet in that XCD's
+    // L2 instead of coming from HBM once per column.  Padding blocks leave
+    // before any barrier.
+    int64_t bx = blockIdx.x;
+    int rr = 0;
+    if constexpr (RC != 1) {
+        const int64_t l = xcd_block(blockIdx.x, gridDim.x);
+        if (l >= n_blk * R) return;
+        bx = l / R;
+        rr = (int)(l % R);
+    }
+    const int64_t t0 = blocks[2 * bx];
+    const int64_t iv = blocks[2 * bx + 1];
     const int64_t a = istart[iv], e = istart[iv + 1];
     const int64_t base = t0 - lam;
     T re[16], im[16];
@@ -347,7 +361,10 @@ int noise_fft_mid_nc() { return Geo<8192>::NC; }
 // prepared for (nz->fft_n = 32,768 or 16,384).
 void noise_fft_reg_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z) {
     Scope sc(ctx->prof, ctx->stream, "Ninv_fft");
-    dim3 grid((unsigned)nz->n_fft_blocks, nrhs);
+    // one column: a block per overlap-save block; several: (block, column)
+    // pairs on a flat grid padded to a multiple of 8 (see the kernel)
+    const int64_t nb = nz->n_fft_blocks;
+    const dim3 grid(nrhs == 1 ? (unsigned)nb : (unsigned)((nb * nrhs + 7) / 8 * 8));
     auto go = [&](auto GG) {
         using G = decltype(GG);
         if (nz->prec == MM_F32) {
@@ -355,14 +372,14 @@ void noise_fft_reg_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const vo
             auto k = nrhs == 1 ? k_noise_fft_reg<G, float, 1> : k_noise_fft_reg<G, float, 0>;
             k<<<grid, G::TH, 0, ctx->stream>>>(
                 nz->fft_blocks.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
-                nz->fft_spec.as<float2>(), tw, tw + G::NC, nz->half_bw, nz->fft_valid, nrhs,
+                nz->fft_spec.as<float2>(), tw, tw + G::NC, nz->half_bw, nz->fft_valid, nrhs, nb,
                 static_cast<const float *>(y), static_cast<float *>(z));
         } else {
             const double2 *tw = nz->fft_tw.as<double2>();
             auto k = nrhs == 1 ? k_noise_fft_reg<G, double, 1> : k_noise_fft_reg<G, double, 0>;
             k<<<grid, G::TH, 0, ctx->stream>>>(
                 nz->fft_blocks.as<int64_t>(), nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
-                nz->fft_spec.as<double2>(), tw, tw + G::NC, nz->half_bw, nz->fft_valid, nrhs,
+                nz->fft_spec.as<double2>(), tw, tw + G::NC, nz->half_bw, nz->fft_valid, nrhs, nb,
                 static_cast<const double *>(y), static_cast<double *>(z));
         }
     };
