@@ -352,6 +352,29 @@ def main():
             "setup_steps": Mh.arnoldi_info.m, "total_s": t_h + el}
         log(f"[bench] solve m2l_from_mbd_solve: {solves['m2l_from_mbd_solve']}")
         del Mh, xh
+        # M_2l whose Arnoldi stops on the residual of its own solution of
+        # B x = r_0 (the second reading of the eps_Arn test): Arnoldi ends near
+        # the point where an M_BD-preconditioned Krylov solve would converge
+        for eps in (1e-8, 1e-10):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Mr = ctx.defl_build(lp, ln, Mbd, b, k=32, eps_arn=eps, m_max=args.m_max,
+                                stop="residual")
+            torch.cuda.synchronize()
+            t_r = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, info = ctx.solve(lp, ln, Mr, b, tol=1e-8, max_iter=3000, check_every=4,
+                                history=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            key = f"m2l_arnoldi_residual_rule_{eps:g}"
+            solves[key] = {
+                "iters": info["iters"], "converged": info["converged"],
+                "rel_res_true": info["rel_res_true"], "solve_s": el,
+                "s_per_iter": el / max(info["iters"], 1), "setup_s": t_r,
+                "setup_steps": Mr.arnoldi_info.m, "total_s": t_r + el}
+            log(f"[bench] solve {key}: {solves[key]}")
+            del Mr
 
     # pure A-apply rate
     x = torch.randn(lp.n, dtype=torch.float64, device=dev)
