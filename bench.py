@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="requests in the serving trace")
     ap.add_argument("--slots", type=int, default=1, help="columns per serving session")
     ap.add_argument("--rate", type=float, default=4.0, help="serving arrival rate (requests/s)")
+    ap.add_argument("--serve-stop", choices=["h", "residual"], default="h",
+                    help="Arnoldi stop rule of the serving engine's background M_2l build")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -259,7 +261,8 @@ def main():
               "z1": form_z1, "g1": lambda m, c: form_f1(m, c, ground=True), "p1": form_p1, "h1": form_h1, "n1": form_n1,
               "mf": form_mf,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
-                                         slots=args.slots, rate=args.rate)}[args.form]
+                                         slots=args.slots, rate=args.rate,
+                                         stop=args.serve_stop)}[args.form]
         print(json.dumps(fn(mm, ctx)), flush=True)
         ctx.close()
         return
@@ -1204,7 +1207,7 @@ def form_z1(mm, ctx):
             "rows": rows}
 
 
-def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0):
+def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0, stop="h"):
     """Serving: a Poisson trace (`rate` requests/s) over four recurring strategies
     of uneven size (2^20 to 2^27 samples, lambda 1,024 to 8,192), tolerance
     1e-6 or 1e-8.  Served by mm_server_* (cached pointing, M_BD and M_2l per
@@ -1246,7 +1249,8 @@ def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0):
         del lp
     def serve(prebuild):
         srv = mm.Server(0, hbm_budget_bytes=240 << 30, slots=slots, defl_k=32, iters_per_step=4,
-                        prebuild=prebuild)
+                        prebuild=prebuild,
+                        arnoldi=None if stop == "h" else ("residual", 1e-10, 256))
         t0 = time.perf_counter()
         for s in range(4):
             p = S[s]["p"]
@@ -1340,7 +1344,8 @@ def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0):
     log(f"[bench] baseline: {base}")
     return {"form": "c5", "workload": f"Poisson {rate:g} req/s, 4 strategies: 64^2/16 det x 2^16 "
             "(lambda 1024), 128^2/32 x 2^18 (2048), 256^2/64 x 2^20 (4096), 256^2/128 x 2^20 "
-            "(8192); tol 1e-6 or 1e-8; slots %d" % slots, "served": served,
+            "(8192); tol 1e-6 or 1e-8; slots %d; background Arnoldi stop rule %s" % (slots, stop),
+            "served": served,
             "served_m2l_at_registration": served_pre,
             "one_at_a_time_mbd_no_cache": base,
             "served_vs_baseline_map_rel_diff_first8": diffs}

@@ -575,6 +575,12 @@ mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots, 
  * registration takes that much longer.  Off (the default): M_2l is built in
  * the background from the first request's right-hand side. */
 mm_status mm_server_set_prebuild(mm_server *srv, int32_t on);
+/* Arnoldi of the background M_2l build (mm_defl_build_stop): stop rule
+ * MM_ARN_STOP_*, eps_arn >= 0, m_max in [1, 500].  The default is
+ * MM_ARN_STOP_H, 1e-8, 256.  Set before any strategy is registered (the
+ * registration charges the Arnoldi basis of m_max + 1 vectors).
+ * Errors: MM_E_INVALID (arguments, or strategies already registered). */
+mm_status mm_server_set_arnoldi(mm_server *srv, int32_t stop_rule, double eps_arn, int32_t m_max);
 /* Register a scan strategy; arguments as mm_pointing_build / mm_noise_build
  * (pix, psi [device] are read during the call only; grid_width as
  * mm_pointing_set_grid, 0 = none).  Errors: MM_E_BUSY if its estimated

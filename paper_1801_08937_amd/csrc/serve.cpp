@@ -121,6 +121,7 @@ struct mm_server {
     int32_t chunk = 4;
     int32_t m_max = 256;
     double eps_arn = 1e-8;
+    int32_t arn_stop = MM_ARN_STOP_H;  // stop rule of the background Arnoldi
     // build M_2l at registration (synchronously, on the strategy's stream)
     // from the Ritz vectors of an M_BD solve of A x = A u, u a fixed
     // pseudo-random map, instead of in the background from the first request
@@ -196,6 +197,21 @@ extern "C" mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int3
 extern "C" mm_status mm_server_set_prebuild(mm_server *srv, int32_t on) {
     if (!srv) return MM_E_INVALID;
     srv->prebuild = on != 0;
+    return MM_OK;
+}
+
+extern "C" mm_status mm_server_set_arnoldi(mm_server *srv, int32_t stop_rule, double eps_arn,
+                                           int32_t m_max) {
+    if (!srv) return MM_E_INVALID;
+    if (stop_rule != MM_ARN_STOP_H && stop_rule != MM_ARN_STOP_RESIDUAL) return MM_E_INVALID;
+    if (!(eps_arn >= 0) || m_max < 1 || m_max > 500) return MM_E_INVALID;
+    if (!srv->strat.empty()) {
+        srv->last_error = "server: the Arnoldi parameters are set before any strategy";
+        return MM_E_INVALID;
+    }
+    srv->arn_stop = stop_rule;
+    srv->eps_arn = eps_arn;
+    srv->m_max = m_max;
     return MM_OK;
 }
 
@@ -322,14 +338,15 @@ static void start_build(mm_server *srv, Strategy &st) {
     const int k = (int)std::min<int64_t>(srv->defl_k, st.n - 1);
     const int mmax = (int)std::min<int64_t>(srv->m_max, st.n);
     const double eps = srv->eps_arn;
+    const int32_t rule = srv->arn_stop;
     const int dev = srv->device;
     st.build = BUILD_RUNNING;
     Strategy *sp = &st;
-    st.builder = std::thread([sp, k, mmax, eps, dev]() {
+    st.builder = std::thread([sp, k, mmax, eps, rule, dev]() {
         mm_status s = MM_E_DEVICE;
         if (hipSetDevice(dev) == hipSuccess && mm_ctx_create(dev, nullptr, &sp->bctx) == MM_OK)
-            s = mm_defl_build(sp->bctx, sp->p, sp->nz, sp->mbd, sp->b_seed.as<double>(), k, 0.0,
-                              eps, mmax, nullptr, nullptr, &sp->m2l_new);
+            s = mm_defl_build_stop(sp->bctx, sp->p, sp->nz, sp->mbd, sp->b_seed.as<double>(), k,
+                                   0.0, eps, rule, mmax, nullptr, nullptr, nullptr, &sp->m2l_new);
         sp->build = s >= 0 ? BUILD_READY : BUILD_FAILED;
     });
 }

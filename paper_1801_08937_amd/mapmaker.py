@@ -121,6 +121,7 @@ def lib() -> C.CDLL:
             "mm_autotune": (C.c_int, [P, P, P, I32, I32, P, I32, C.POINTER(I32)]),
             "mm_server_create": (C.c_int, [C.c_int, I64, I32, I32, I32, PP]),
             "mm_server_set_prebuild": (C.c_int, [P, I32]),
+            "mm_server_set_arnoldi": (C.c_int, [P, I32, D, I32]),
             "mm_server_add_strategy": (C.c_int, [P, I32, I64, I32, P, P, I32, I32, I32, P, P, I32,
                                                  I32, P, C.c_int]),
             "mm_server_submit": (C.c_int, [P, I32, P, D, I32, P, C.POINTER(I64)]),
@@ -724,7 +725,10 @@ class Server:
     cached M_BD/M_2l, per-strategy streams, column slots admitted mid-flight."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 200 << 30, slots: int = 8,
-                 defl_k: int = 32, iters_per_step: int = 4, prebuild: bool = False):
+                 defl_k: int = 32, iters_per_step: int = 4, prebuild: bool = False,
+                 arnoldi=None):
+        """arnoldi: None (the library default) or (stop, eps_arn, m_max) for
+        the background M_2l build, stop "h" or "residual"."""
         h = C.c_void_p()
         st = lib().mm_server_create(device, hbm_budget_bytes, slots, defl_k, iters_per_step,
                                     C.byref(h))
@@ -733,6 +737,14 @@ class Server:
         self.h = h
         if prebuild:
             lib().mm_server_set_prebuild(h, 1)
+        if arnoldi is not None:
+            stop, eps, m_max = arnoldi
+            rule = {"h": 0, "residual": 1}[stop]
+            st = lib().mm_server_set_arnoldi(h, rule, eps, m_max)
+            if st != 0:
+                lib().mm_server_destroy(h)
+                self.h = None
+                raise MapmakerError(st, "mm_server_set_arnoldi failed")
         self.device = device
         self.n = {}
 

@@ -236,3 +236,33 @@ def test_server_admits_by_memory(mm):
     for oa, ob in zip(outs_a, outs_b):
         assert torch.equal(oa[0], ob[0])
     _check_vs_oracle(outs_b, infos_b, [t for _, _, t in reqs])
+
+
+def test_server_residual_rule_m2l(mm):
+    """The background M_2l built with the residual stop rule (App. A, second
+    reading of the eps_Arn test; mm_server_set_arnoldi): the cache is built,
+    the M_2l lane serves requests that meet the oracle bar, bitwise the same
+    alone and in a mix; setting the parameters after a strategy is
+    registered is refused."""
+    import torch
+    srv = mm.Server(0, hbm_budget_bytes=8 << 30, slots=4, defl_k=8, iters_per_step=3,
+                    arnoldi=("residual", 1e-10, 128))
+    for s in range(2):
+        p = _strategy(s, 0)
+        srv.add_strategy(s, dev(p.pix), dev(p.psi), p.n_pix_total, p.interval_start,
+                         p.filter_id, p.band, p.half_bw, grid_width=p.n_side)
+    from paper_1801_08937_amd.mapmaker import lib
+    assert lib().mm_server_set_arnoldi(srv.h, 1, 1e-10, 128) != 0
+    _warm(srv)
+    reqs = [(0, 21, 1e-8), (1, 22, 1e-8), (0, 23, 1e-6)]
+    infos_a, outs_a = _run_each_alone(srv, reqs)
+    infos_b, outs_b = _run(srv, reqs, join_after=1)
+    srv.close()
+    assert all(i["state"] == 2 and i["precond"] == 1 for i in infos_a + infos_b)
+    for ia, ib, oa, ob in zip(infos_a, infos_b, outs_a, outs_b):
+        assert ia["iters"] == ib["iters"]
+        assert torch.equal(oa[0], ob[0])
+    errs = _check_vs_oracle(outs_b, infos_b, [t for _, _, t in reqs])
+    print("residual-rule M_2l lane vs oracle (map error, true residual):", errs)
+    with pytest.raises(mm.MapmakerError):
+        mm.Server(0, hbm_budget_bytes=8 << 30, slots=4, defl_k=8, arnoldi=("residual", -1.0, 128))
