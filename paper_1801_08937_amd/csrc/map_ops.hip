@@ -552,14 +552,17 @@ __global__ void __launch_bounds__(BS) k_gemm_tall_small(int64_t n, int kin, int 
 // --------------------------------------------------------- MFMA Gram (FP64)
 //
 // C[a][b] = sum_i X(i, a) Y(i, b), X(i, a) = X[i*xr + a*xc], likewise Y.
-// Block = 4 waves; rows are staged through LDS 32 at a time (coalesced along
-// whichever dimension is contiguous) and fed to v_mfma_f64_16x16x4f64 in
-// K-steps of 4 rows.  Each block writes its partial KA x KB product; a second
+// Block = 4 waves over the block's rows; wave w owns the 16 x 16 output tiles
+// w, w + 4, ..., and walks the rows once per tile.  Each wave loads its
+// v_mfma_f64_16x16x4f64 operands straight from global memory (lane l feeds
+// row l/16 and column l%16 of the 16 x 4 A and B fragments), GR_KS K-steps
+// of 4 rows at a time in flight, with no LDS and no barriers.  Each block writes its partial KA x KB product; a second
 // kernel sums the partials in a fixed order.
 
 using d4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 
-constexpr int GR_ROWS = 32;
+constexpr int GR_KS = 8;                // K-steps of 4 rows in flight per group
+constexpr int GR_ROWS = 4 * GR_KS;      // rows per group
 
 __global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
                                                   const double *__restrict__ X, int64_t xr,
@@ -568,59 +571,45 @@ __global__ void __launch_bounds__(BS) k_gram_mfma(int64_t n, int ka, int kb,
                                                   double *__restrict__ partial,
                                                   int64_t rows_per_block) {
     const int KA = (ka + 15) & ~15, KB = (kb + 15) & ~15;  // <= 64 each
-    __shared__ double sx[GR_ROWS][64 + 1];
-    __shared__ double syy[GR_ROWS][64 + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int TA = KA / 16, TB = KB / 16, NT = TA * TB;
-    d4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+    const int m = lane & 15, kq = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
     int64_t i1 = i0 + rows_per_block;
     if (i1 > n) i1 = n;
-    for (int64_t rb = i0; rb < i1; rb += GR_ROWS) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < GR_ROWS * 64; e += BS) {
-            int rr, cc;
-            // choose the index order that walks memory contiguously
-            if (xr == 1) { rr = e % GR_ROWS; cc = e / GR_ROWS; } else { cc = e % 64; rr = e / 64; }
-            const int64_t i = rb + rr;
-            sx[rr][cc] = (i < i1 && cc < ka) ? X[i * xr + cc * xc] : 0.0;
-            if (yr == 1) { rr = e % GR_ROWS; cc = e / GR_ROWS; } else { cc = e % 64; rr = e / 64; }
-            const int64_t i2 = rb + rr;
-            syy[rr][cc] = (i2 < i1 && cc < kb) ? Y[i2 * yr + cc * yc] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < GR_ROWS; ks += 4) {
-            const int kk = ks + lane / 16;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int t = wv + 4 * q;
-                if (t < NT) {
-                    const int ta = t / TB, tb = t % TB;
-                    const double av = sx[kk][ta * 16 + (lane % 16)];
-                    const double bv = syy[kk][tb * 16 + (lane % 16)];
-                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
-                }
-            }
-        }
-    }
-    // D layout of v_mfma_f64_16x16x4f64 (checked on gfx950): item v of lane l
-    // holds row l/16 + 4 v, column l % 16.
-    // partials are stored element-major, partial[(row 64 + col) P + block]
+    const uint32_t uxr = (uint32_t)xr, uyr = (uint32_t)yr;
     const int64_t P = gridDim.x;
+    // the wave's tiles one after another: one accumulator live at a time
+    for (int t = wv; t < NT; t += 4) {
+        const int ta = t / TB, tb = t % TB;
+        const int a = ta * 16 + m, b = tb * 16 + m;
+        // this lane's column of A and of B as element offsets (32-bit: the
+        // host checks the index range); a padding column feeds 0
+        const bool xa = a < ka, yb = b < kb;
+        const uint32_t xo = xa ? (uint32_t)(a * xc) : 0u, yo = yb ? (uint32_t)(b * yc) : 0u;
+        d4 acc = d4{0, 0, 0, 0};
+        for (int64_t rb = i0; rb < i1; rb += GR_ROWS) {
+            double av[GR_KS], bv[GR_KS];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int t = wv + 4 * q;
-        if (t < NT) {
-            const int ta = t / TB, tb = t % TB;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = ta * 16 + (lane / 16) + 4 * v;
-                const int col = tb * 16 + (lane % 16);
-                partial[(int64_t)(row * 64 + col) * P + blockIdx.x] = acc[q][v];
+            for (int s = 0; s < GR_KS; ++s) {
+                const int64_t row = rb + 4 * s + kq;
+                const bool rok = row < i1;
+                const uint32_t ur = (uint32_t)row;
+                av[s] = (xa && rok) ? X[ur * uxr + xo] : 0.0;
+                bv[s] = (yb && rok) ? Y[ur * uyr + yo] : 0.0;
             }
+#pragma unroll
+            for (int s = 0; s < GR_KS; ++s)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+        }
+        // D layout of v_mfma_f64_16x16x4f64 (checked on gfx950): item v of
+        // lane l holds row l/16 + 4 v, column l % 16.  Partials are stored
+        // element-major, partial[(row 64 + col) P + block].
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = ta * 16 + (lane / 16) + 4 * v;
+            const int col = tb * 16 + (lane % 16);
+            partial[(int64_t)(row * 64 + col) * P + blockIdx.x] = acc[v];
         }
     }
 }
@@ -1266,6 +1255,11 @@ void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t 
                int64_t x_cs, const double *Y, int64_t y_rs, int64_t y_cs, double *C) {
     Scope sc(ctx->prof, ctx->stream, "gram_mfma");
     MM_CHECK(ka >= 1 && ka <= 64 && kb >= 1 && kb <= 64, MM_E_INVALID, "gram: sizes");
+    // the kernel indexes with 32-bit element offsets
+    MM_CHECK(n >= 1 && x_rs >= 0 && x_cs >= 0 && y_rs >= 0 && y_cs >= 0 &&
+                 (n - 1) * x_rs + (int64_t)(ka - 1) * x_cs < ((int64_t)1 << 32) &&
+                 (n - 1) * y_rs + (int64_t)(kb - 1) * y_cs < ((int64_t)1 << 32),
+             MM_E_INVALID, "gram: operands beyond 2^32 elements");
     // one 32-row chunk per block up to 1,024 blocks (small n: more blocks in
     // flight), then more chunks per block
     int64_t parts64 = (n + GR_ROWS - 1) / GR_ROWS;
