@@ -514,10 +514,13 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
             MM_CHECK(fft_ok, MM_E_INVALID, "FFT noise method unsupported for this bandwidth");
             nz->method = MM_NOISE_FFT;
         } else if (method == MM_NOISE_AUTO) {
-            // measured crossover (direct band vs overlap-save FFT, 2^20..2^27
-            // samples): the band wins up to lambda = 32, the FFT from 64 on
-            // streams of 2^22 samples and more, from 128 on shorter ones
-            const int cross = nz->n_samp >= ((int64_t)1 << 22) ? 64 : 128;
+            // measured crossover (direct band vs overlap-save FFT, FP64,
+            // 2^20..2^27 samples in 2^16-sample intervals): on streams of 2^22
+            // samples and more the FFT wins from lambda = 16 on (its time
+            // hardly depends on lambda, the band's grows with it); on shorter
+            // ones from 128.  FP32 keeps the earlier crossover at 64.
+            const bool long_stream = nz->n_samp >= ((int64_t)1 << 22);
+            const int cross = long_stream ? (prec == MM_F64 ? 16 : 64) : 128;
             nz->method = (fft_ok && half_bw >= cross) ? MM_NOISE_FFT : MM_NOISE_DIRECT;
         } else {
             nz->method = MM_NOISE_DIRECT;

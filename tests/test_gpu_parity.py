@@ -362,7 +362,8 @@ def _fft_problem(lam, L, n_int, seed, n_filters=3):
 
 @pytest.mark.parametrize("lam,L,n_int", [(300, 5000, 5), (1000, 20000, 3), (2048, 65536, 2),
                                          (4096, 65536, 3), (6000, 30000, 2), (9000, 40000, 2),
-                                         (301, 5001, 5), (4095, 30001, 3)])
+                                         (301, 5001, 5), (4095, 30001, 3), (16, 4000, 5),
+                                         (40, 9001, 3)])
 def test_noise_fft_parity(ctx, lam, L, n_int):
     """FFT form of N^-1 (overlap-save, partial last blocks, several filters)
     against the oracle's direct band, with each block length the lambda
