@@ -767,3 +767,25 @@ def test_graph_recaptured_after_workspace_growth(ctx):
         assert torch.equal(S.finish(0), x_ref)
     finally:
         c2.close()
+
+
+def test_pol_weights_against_numpy(ctx):
+    """The polarisation weights (cos 2psi, sin 2psi) the kernels form from
+    psi (Eq. datamodel) against numpy's cos and sin: every sample hits one
+    pixel and P applies to the maps (I, Q, U) = (0, 1, 0) and (0, 0, 1),
+    whose outputs are the weights themselves.  Angles uniform in [0, pi),
+    negative and large ones, points next to multiples of pi/4, and angles
+    beyond the range of the fast reduction (|2 psi| > 2^20)."""
+    rng = np.random.default_rng(5)
+    psi = np.concatenate([rng.uniform(0, np.pi, 200000), rng.uniform(-3e5, 3e5, 20000),
+                          np.arange(-40, 41) * np.pi / 8, np.arange(-8, 9) * np.pi / 4 + 1e-12,
+                          np.arange(-8, 9) * np.pi / 4 - 1e-12, [6e5, -6e5, 1e6, -3e6]])
+    pix = np.zeros(psi.size, dtype=np.int32)
+    lp = ctx.pointing(dev(pix), dev(psi), 1, 1)
+    assert lp.n_obs == 1
+    for a, ref in ((1, np.cos(2 * psi)), (2, np.sin(2 * psi))):
+        x = np.zeros(3)
+        x[a] = 1.0
+        y = host(ctx.apply_P(lp, dev(x)))
+        err = float(np.max(np.abs(y - ref)))
+        assert err <= 4e-16, (a, err)
