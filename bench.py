@@ -15,7 +15,15 @@ line also carries the pure A-apply rate, time to a 1e-8 residual for M_2l and
 M_BD (with setup costs), the roofline of the dominant kernel and the oracle
 timed on the host on a bounded sample.
 
+`--form NAME` measures one form or study instead and prints its own JSON
+line.  The latency (c1), batching (c4) and serving (c5) forms carry the
+FP64 oracle's timing of the same work as `cpu_baseline` (config 1's solves
+on one core; the 64 Monte Carlo solves on all host cores; the serving trace
+extrapolated per request from each strategy's measured costs); `--no-cpu`
+leaves it out.
+
     python bench.py [--steps K] [--warmup W] [--workload c2|c1] [--no-solves] [--no-cpu]
+    python bench.py --form c1|c3|c4|c5|f1|g1|d1|z1|p1|h1|n1|mf [--no-cpu]
 """
 from __future__ import annotations
 
@@ -207,6 +215,169 @@ def cpu_solve_estimates(cpu, n_samp, n_unknowns, solves, m_max, k):
     return res
 
 
+def _oracle_pcg_cols(rng):
+    """Oracle PCG to 1e-8 on the right-hand sides [c0, c1) of the batch held in
+    _CPU (a forked worker of oracle_c4): (iterations, true residual) each."""
+    import oracle as O
+    c0, c1 = rng
+    pt, nz, B, apply_M = _CPU["pt"], _CPU["nz"], _CPU["B"], _CPU["apply_M"]
+    out = []
+    for c in range(c0, c1):
+        _, info = O.pcg(lambda v: O.apply_A(pt, nz, v), apply_M, B[:, c], 1e-8, 3000)
+        out.append((int(info.iters), float(info.rel_res_true)))
+    return out
+
+
+def oracle_c1():
+    """Config 1 on the FP64 oracle, one host core: setup (pointing, noise
+    model, M_BD, b), the A apply, PCG to 1e-8 with M_BD, and with M_2l (k = 32,
+    Arnoldi with the literal stop rule at 1e-8 and at most 256 steps, as the
+    GPU form builds it)."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    import synth
+    p = synth.config1()
+    res = {"kind": "oracle", "cores": 1, "nproc": os.cpu_count(),
+           "sample": f"the whole config-1 problem ({p.n_samp} samples), numpy on one thread"}
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+        nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+        M = O.mbd_build(pt, nz)
+        b = O.rhs(pt, nz, p.tod)
+        res["setup_s"] = time.perf_counter() - t0
+
+        def A(v):
+            return O.apply_A(pt, nz, v)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            A(b)
+            ts.append(time.perf_counter() - t0)
+        res["a_apply_ms"] = 1e3 * float(np.median(ts))
+        t0 = time.perf_counter()
+        _, info = O.pcg(A, lambda v: O.mbd_apply(M, v), b, 1e-8, 2000)
+        res["mbd"] = {"iters": int(info.iters), "rel_res_true": float(info.rel_res_true),
+                      "solve_s": time.perf_counter() - t0}
+        t0 = time.perf_counter()
+        M2 = O.defl_build(pt, nz, M, b, 32, 1e-8, 256)[0]
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, info = O.pcg(A, lambda v: O.m2l_apply(M2, v), b, 1e-8, 2000)
+        res["m2l"] = {"iters": int(info.iters), "rel_res_true": float(info.rel_res_true),
+                      "solve_s": time.perf_counter() - t0, "setup_s": t_setup}
+    res["value"] = 1.0 / res["mbd"]["solve_s"]
+    res["unit"] = "M_BD solves/s"
+    return res
+
+
+def oracle_c4():
+    """The 64 Monte Carlo solves of the batching form on the FP64 oracle: one
+    M_BD solve and M_2l's setup (Z from realization 0, as the GPU form) on one
+    core, then the 64 M_BD and the 64 M_2l solves on all host cores (at most
+    16, the GPU's CPU share): a fixed partition of the realizations over
+    forked single-threaded workers.  Runs before the GPU is initialised."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    import synth
+    t_all = time.perf_counter()
+    reals = [synth.config4_realization(r) for r in range(64)]
+    p = reals[0]
+    with threadpool_limits(1):
+        pt = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+        nz = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+        M = O.mbd_build(pt, nz)
+        B = np.stack([O.rhs(pt, nz, q.tod) for q in reals], axis=1)
+        t0 = time.perf_counter()
+        O.pcg(lambda v: O.apply_A(pt, nz, v), lambda v: O.mbd_apply(M, v), B[:, 0], 1e-8, 3000)
+        t_one = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        M2 = O.defl_build(pt, nz, M, B[:, 0], 32, 1e-8, 256)[0]
+        t_m2l_setup = time.perf_counter() - t0
+    W = max(1, min(16, os.cpu_count() or 1))
+    bounds = np.linspace(0, 64, W + 1).round().astype(int)
+    parts = [(int(a), int(b_)) for a, b_ in zip(bounds[:-1], bounds[1:]) if b_ > a]
+    res = {"kind": "oracle", "cores": len(parts), "nproc": os.cpu_count(),
+           "sample": "all 64 realizations of config 4 in FP64; one forked single-threaded "
+                     "worker per slice of a fixed partition of the realizations",
+           "mbd_one_solve_single_core_s": t_one, "m2l_setup_single_core_s": t_m2l_setup}
+    for name, apply_M in (("mbd", lambda v: O.mbd_apply(M, v)),
+                          ("m2l", lambda v: O.m2l_apply(M2, v))):
+        _CPU.update(pt=pt, nz=nz, B=B, apply_M=apply_M)
+        with threadpool_limits(1), mp.get_context("fork").Pool(len(parts)) as pool:
+            t0 = time.perf_counter()
+            rs = pool.map(_oracle_pcg_cols, parts, chunksize=1)
+            t = time.perf_counter() - t0
+        its = [i for r in rs for (i, _) in r]
+        rr = [x for r in rs for (_, x) in r]
+        res[name] = {"solves_64_s": t, "max_iters": max(its), "mean_iters": float(np.mean(its)),
+                     "max_rel_res_true": max(rr)}
+    _CPU.clear()
+    res["value"] = 64 / res["mbd"]["solves_64_s"]
+    res["unit"] = "M_BD solves/s"
+    res["wall_s"] = time.perf_counter() - t_all
+    return res
+
+
+def oracle_strategy_costs(p):
+    """Costs of an oracle M_BD solve for one serving strategy, on one core,
+    measured on its first min(2^20, n) samples (whole intervals): the setup
+    (pointing, noise model, M_BD), the A apply (FFT path), the M_BD apply and
+    one iteration's vector work.  oracle_trace_estimate scales them to the
+    strategy's size."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    ns = min(1 << 20, p.n_samp)
+    n_int = int(np.searchsorted(p.interval_start, ns))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pt = O.pointing_build(p.pix[:ns], p.psi[:ns], p.n_pix_total, 1)
+        nz = O.noise_build(p.interval_start[: n_int + 1], p.filter_id[:n_int], p.band, p.half_bw)
+        M = O.mbd_build(pt, nz)
+        t_setup = time.perf_counter() - t0
+        x = np.random.default_rng(0).standard_normal(pt.n)
+        ts = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            y = O.apply_A(pt, nz, x, "fft")
+            ts.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            O.mbd_apply(M, x)
+        t_mbd = (time.perf_counter() - t0) / 5
+        t0 = time.perf_counter()
+        for _ in range(5):  # the vector work of one PCG iteration: 3 dots, 3 axpys
+            v = x + 0.5 * y
+            _ = float(v @ v) + float(x @ y) + float(y @ y)
+            v = y + 0.25 * v
+            v = v - 0.125 * x
+        t_vec = (time.perf_counter() - t0) / 5
+    return {"sample_samples": ns, "n_samp": p.n_samp, "sample_unknowns": pt.n,
+            "setup_s": t_setup, "a_apply_s": min(ts), "map_ops_s": t_mbd + t_vec}
+
+
+def oracle_trace_estimate(costs, n_obs, strat, iters):
+    """Single-core oracle time of the serving baseline (one request at a time,
+    M_BD, nothing cached), extrapolated per request: the strategy's setup and
+    A apply scaled by samples, its map-domain work by unknowns, times the
+    iteration count the GPU baseline took for that request."""
+    per = []
+    for s, c in enumerate(costs):
+        ss = c["n_samp"] / c["sample_samples"]
+        sn = n_obs[s] / max(c["sample_unknowns"], 1)
+        per.append({"setup_s": c["setup_s"] * ss,
+                    "per_iter_s": c["a_apply_s"] * ss + c["map_ops_s"] * sn,
+                    "a_apply_s": c["a_apply_s"] * ss})
+    t_req = [per[int(s)]["setup_s"] + it * per[int(s)]["per_iter_s"] for s, it in zip(strat, iters)]
+    total = float(np.sum(t_req))
+    return {"kind": "oracle", "cores": 1, "nproc": os.cpu_count(),
+            "method": "per-strategy costs measured on the first 2^20 samples (one core) and "
+                      "scaled; iteration counts from the GPU baseline",
+            "per_strategy": per, "trace_s": total, "value": len(t_req) / total,
+            "unit": "solves/s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +427,12 @@ def main():
     from paper_1801_08937_amd import mapmaker as mm
 
     if args.form:
+        # the oracle's legs of the latency and batching forms, before the GPU
+        # is initialised (the batching leg forks worker processes)
+        pre = None
+        if not args.no_cpu and args.form in ("c1", "c4"):
+            pre = (oracle_c1 if args.form == "c1" else oracle_c4)()
+            log(f"[bench] oracle: {pre}")
         torch.cuda.init()
         ctx = mm.Context(0)
         fn = {"c1": form_c1, "c3": form_c3, "c4": form_c4, "f1": form_f1, "d1": form_d1,
@@ -263,8 +440,11 @@ def main():
               "mf": form_mf,
               "c5": lambda m, c: form_c5(m, c, n_requests=args.requests,
                                          slots=args.slots, rate=args.rate,
-                                         stop=args.serve_stop)}[args.form]
-        print(json.dumps(fn(mm, ctx)), flush=True)
+                                         stop=args.serve_stop, cpu=not args.no_cpu)}[args.form]
+        res = fn(mm, ctx)
+        if pre is not None:
+            res["cpu_baseline"] = pre
+        print(json.dumps(res), flush=True)
         ctx.close()
         return
 
@@ -1210,7 +1390,7 @@ def form_z1(mm, ctx):
             "rows": rows}
 
 
-def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0, stop="h"):
+def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0, stop="h", cpu=True):
     """Serving: a Poisson trace (`rate` requests/s) over four recurring strategies
     of uneven size (2^20 to 2^27 samples, lambda 1,024 to 8,192), tolerance
     1e-6 or 1e-8.  Served by mm_server_* (cached pointing, M_BD and M_2l per
@@ -1231,6 +1411,8 @@ def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0, stop="h"):
         fk = synth.rng_for(50 + s, 0, synth.STREAM_FKNEE).uniform(0.05, 1.0, n_det)
         S.append({"p": p, "pix": torch.from_numpy(p.pix).to(dev),
                   "psi": torch.from_numpy(p.psi).to(dev), "fk": fk[p.filter_id]})
+        if cpu:
+            S[-1]["oracle"] = oracle_strategy_costs(p)
         p.pix = p.psi = p.tod = None
         log(f"[bench] strategy {s}: {S[-1]['pix'].numel()} samples "
             f"({time.perf_counter() - t0:.1f} s)")
@@ -1345,7 +1527,11 @@ def form_c5(mm, ctx, n_requests=200, slots=1, rate=4.0, stop="h"):
             "solves_per_s": n_requests / wall_b, "wall_s": wall_b,
             "iters_mean": float(np.mean(iters))}
     log(f"[bench] baseline: {base}")
-    return {"form": "c5", "workload": f"Poisson {rate:g} req/s, 4 strategies: 64^2/16 det x 2^16 "
+    extra = {}
+    if cpu:
+        extra["cpu_baseline"] = oracle_trace_estimate([st["oracle"] for st in S], n_obs, strat,
+                                                      iters)
+    return {**extra, "form": "c5", "workload": f"Poisson {rate:g} req/s, 4 strategies: 64^2/16 det x 2^16 "
             "(lambda 1024), 128^2/32 x 2^18 (2048), 256^2/64 x 2^20 (4096), 256^2/128 x 2^20 "
             "(8192); tol 1e-6 or 1e-8; slots %d; background Arnoldi stop rule %s" % (slots, stop),
             "served": served,

@@ -1276,8 +1276,8 @@ void gram_mfma(mm_ctx *ctx, int64_t n, int ka, int kb, const double *X, int64_t 
     MM_HIP(hipGetLastError());
 }
 
-void chol_small_dev(mm_ctx *ctx, int k, const double *E, double *Lc, int *flag) {
-    k_chol_small<<<1, 64, 0, ctx->stream>>>(k, const_cast<double *>(E), Lc, flag);
+void chol_small_dev(mm_ctx *ctx, int k, double *E, double *Lc, int *flag) {
+    k_chol_small<<<1, 64, 0, ctx->stream>>>(k, E, Lc, flag);
     MM_HIP(hipGetLastError());
 }
 

@@ -295,7 +295,8 @@ void scale_copy(mm_ctx *ctx, int64_t n, const double *src, const double *s_dev, 
                 int invert);
 void matmul_small_right(mm_ctx *ctx, int64_t n, int kin, int kout, const double *V,
                         const double *Y, double *Zout);  // Zout = V Y, col-major
-void chol_small_dev(mm_ctx *ctx, int k, const double *E, double *Lc, int *flag);
+// Cholesky factor Lc of the k x k matrix E; E is symmetrised in place first.
+void chol_small_dev(mm_ctx *ctx, int k, double *E, double *Lc, int *flag);
 void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
                    double *dot_partial, int n_part);
 void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c);
