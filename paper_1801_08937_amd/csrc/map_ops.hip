@@ -444,8 +444,32 @@ __global__ void __launch_bounds__(BS) k_gemv_t(int64_t n, const double *__restri
 // columns (Z^T v of M_2l): v is read once
 // per group of columns, and each thread keeps GT independent loads in
 // flight.  Each column sums a thread's rows in order, then the lanes of a
-// wave by a fixed butterfly, then the waves in order.
+// wave by a fixed transpose reduction (below), then the waves in order.
 constexpr int GT = 16;
+
+// Sums over the 64 lanes of a wave for the 16 values a[0..15] every lane
+// holds.  At the exchanges with lanes xor 32, 16, 8 and 4 a lane keeps half
+// of its remaining columns (the upper half when that lane bit is set) and
+// adds its partner's copy of them, so the columns left halve each time:
+// 8 + 4 + 2 + 1 exchanges, then two more (xor 2, xor 1) on the last value,
+// instead of six for each of the 16 columns.  Returns the total of column
+// (lane >> 2) & 15.  The order of the additions is fixed.
+__device__ __forceinline__ double wave_sum16_transposed(double (&a)[16], int lane) {
+#pragma unroll
+    for (int h = 8, d = 32; h >= 1; h >>= 1, d >>= 1) {
+        const bool up = (lane & d) != 0;
+#pragma unroll
+        for (int c = 0; c < h; ++c) {
+            const double send = up ? a[c] : a[c + h];
+            const double keep = up ? a[c + h] : a[c];
+            a[c] = keep + __shfl_xor(send, d);
+        }
+    }
+    double t = a[0];
+    t += __shfl_xor(t, 2);
+    t += __shfl_xor(t, 1);
+    return t;
+}
 __global__ void __launch_bounds__(BS) k_gemv_t_grp(int64_t n, const double *__restrict__ W,
                                                    const double *__restrict__ v,
                                                    double *__restrict__ partial, int64_t rows,
@@ -467,13 +491,8 @@ __global__ void __launch_bounds__(BS) k_gemv_t_grp(int64_t n, const double *__re
     }
     __shared__ double sm[BS / 64][GT];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < GT; ++c) {
-        double a = acc[c];
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d);
-        if (lane == 0) sm[wv][c] = a;
-    }
+    const double tot = wave_sum16_transposed(acc, lane);
+    if ((lane & 3) == 0) sm[wv][(lane >> 2) & 15] = tot;
     __syncthreads();
     if (threadIdx.x < nc) {
         double t = 0;
@@ -678,9 +697,21 @@ __global__ void k_chol_small(int k, double *__restrict__ E, double *__restrict__
 
 // c = E^-1 g per column: forward then backward substitution with Lc.
 // g[a * R + r] (k x R), c likewise.  One thread per column.
+// Lane j's value of v (j uniform across the wave), as two 32-bit reads.
+__device__ __forceinline__ double lane_value(double v, int j) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // c = E^-1 g for each column r (block r): forward then backward substitution
-// with the Cholesky factor staged in LDS.  Lane i holds y_i; each step's
-// inner product is a wave sum in a fixed butterfly order.
+// with the Cholesky factor L staged in LDS, column by column.  Lane i holds
+// y_i.  At step j, y_j is final: it is read from lane j, scaled by 1 / L_jj
+// (each lane forms the reciprocal of its own diagonal entry once), and every
+// lane still to be solved subtracts its multiple of it, so each y_i is
+// updated in the fixed order of j.  One broadcast and one FMA per step
+// instead of a wave reduction.
 __global__ void __launch_bounds__(64) k_coarse_solve(int k, int R, const double *__restrict__ Lc,
                                                      const double *__restrict__ g,
                                                      double *__restrict__ c) {
@@ -688,22 +719,20 @@ __global__ void __launch_bounds__(64) k_coarse_solve(int k, int R, const double 
     const int i = threadIdx.x, r = blockIdx.x;
     for (int e = i; e < k * k; e += 64) L[e / k][e % k] = Lc[e];
     __syncthreads();
-    double y = i < k ? g[i * R + r] : 0.0;
+    const bool on = i < k;
+    const double rd = on ? 1.0 / L[i][i] : 0.0;
+    double y = on ? g[i * R + r] : 0.0;
     for (int j = 0; j < k; ++j) {  // L y' = g
-        double t = (i < j) ? L[j][i] * y : 0.0;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
-        const double yj = (__shfl(y, j) - t) / L[j][j];
+        const double yj = lane_value(y, j) * lane_value(rd, j);
         if (i == j) y = yj;
+        else if (i > j && on) y = __builtin_fma(-L[i][j], yj, y);
     }
     for (int j = k - 1; j >= 0; --j) {  // L^T c = y'
-        double t = (i > j && i < k) ? L[i][j] * y : 0.0;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
-        const double cj = (__shfl(y, j) - t) / L[j][j];
+        const double cj = lane_value(y, j) * lane_value(rd, j);
         if (i == j) y = cj;
+        else if (i < j) y = __builtin_fma(-L[j][i], cj, y);
     }
-    if (i < k) c[i * R + r] = y;
+    if (on) c[i * R + r] = y;
 }
 
 // out = M_BD (v - AZ c) + Z c per pixel and column (Eq. m2l), with optional
@@ -1009,7 +1038,11 @@ int grid_for(int64_t n, int max_blocks = 4096) {
 // ----------------------------------------------------------------- launchers
 
 int reduction_parts(int64_t n_rows, int nrhs) {
-    int64_t p = (n_rows * nrhs + 1023) / 1024;
+    const int64_t m = n_rows * nrhs;
+    // up to 65,536 elements a block per 256 (one per thread), so that these
+    // latency-bound launches spread over more CUs; beyond, a block per 1,024,
+    // at most 512 blocks
+    int64_t p = m <= 65536 ? (m + 255) / 256 : (m + 1023) / 1024;
     if (p > 512) p = 512;
     return (int)(p < 1 ? 1 : p);
 }
