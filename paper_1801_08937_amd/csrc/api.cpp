@@ -145,7 +145,8 @@ void precond_rel_res(mm_ctx *ctx, const mm_precond *M, int64_t n, int R, const d
         out[c] = h[R + c] > 0 ? std::sqrt(std::max(h[c], 0.0) / h[R + c]) : 0.0;
 }
 
-// M_2l from Z (device, column-major n x k): AZ, E = Z^T AZ, Cholesky on device.
+// M_2l from Z (device, column-major n x k): AZ, E = Z^T AZ, its Cholesky
+// factor and from it E^-1, on device.
 void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M) {
     const int64_t n = p->n();
     const int k = M->k;
@@ -154,11 +155,14 @@ void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precon
         apply_A_impl(ctx, p, nz, 1, M->Z.as<double>() + (int64_t)c * n,
                      M->AZ.as<double>() + (int64_t)c * n);
     M->E.alloc(sizeof(double) * k * k);
-    M->Lc.alloc(sizeof(double) * k * k);
+    M->Einv.alloc(sizeof(double) * k * k);
     gram_mfma(ctx, n, k, k, M->Z.as<double>(), 1, n, M->AZ.as<double>(), 1, n, M->E.as<double>());
-    DBuf flag;
+    DBuf flag, Lc;
     flag.alloc(sizeof(int));
-    chol_small_dev(ctx, k, M->E.as<double>(), M->Lc.as<double>(), flag.as<int>());
+    Lc.alloc(sizeof(double) * k * k);
+    chol_small_dev(ctx, k, M->E.as<double>(), Lc.as<double>(), flag.as<int>());
+    // formed before the pivot check (one wait for both); not used if it fails
+    coarse_inverse_dev(ctx, k, Lc.as<double>(), M->Einv.as<double>());
     int hf = 0;
     MM_HIP(hipMemcpyAsync(&hf, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     MM_HIP(hipStreamSynchronize(ctx->stream));

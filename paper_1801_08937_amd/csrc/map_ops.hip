@@ -695,8 +695,6 @@ __global__ void k_chol_small(int k, double *__restrict__ E, double *__restrict__
     if (tid == 0) *flag = bad;
 }
 
-// c = E^-1 g per column: forward then backward substitution with Lc.
-// g[a * R + r] (k x R), c likewise.  One thread per column.
 // Lane j's value of v (j uniform across the wave), as two 32-bit reads.
 __device__ __forceinline__ double lane_value(double v, int j) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -705,24 +703,24 @@ __device__ __forceinline__ double lane_value(double v, int j) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// c = E^-1 g for each column r (block r): forward then backward substitution
-// with the Cholesky factor L staged in LDS, column by column.  Lane i holds
-// y_i.  At step j, y_j is final: it is read from lane j, scaled by 1 / L_jj
-// (each lane forms the reciprocal of its own diagonal entry once), and every
-// lane still to be solved subtracts its multiple of it, so each y_i is
-// updated in the fixed order of j.  One broadcast and one FMA per step
-// instead of a wave reduction.
-__global__ void __launch_bounds__(64) k_coarse_solve(int k, int R, const double *__restrict__ Lc,
-                                                     const double *__restrict__ g,
-                                                     double *__restrict__ c) {
+// Column r of E^-1 (block r) from the Cholesky factor L of E: forward then
+// backward substitution on e_r, column by column.  Lane i holds y_i.  At
+// step j, y_j is final: it is read from lane j, scaled by 1 / L_jj (each lane
+// forms the reciprocal of its own diagonal entry once), and every lane still
+// to be solved subtracts its multiple of it, so each y_i is updated in the
+// fixed order of j.  Column r is stored contiguously: Einv[r k + i] =
+// (E^-1)_{i r}.  Formed once per M_2l, so that its applies need no
+// substitution.
+__global__ void __launch_bounds__(64) k_coarse_inverse(int k, const double *__restrict__ Lc,
+                                                       double *__restrict__ Einv) {
     __shared__ double L[64][65];
     const int i = threadIdx.x, r = blockIdx.x;
     for (int e = i; e < k * k; e += 64) L[e / k][e % k] = Lc[e];
     __syncthreads();
     const bool on = i < k;
     const double rd = on ? 1.0 / L[i][i] : 0.0;
-    double y = on ? g[i * R + r] : 0.0;
-    for (int j = 0; j < k; ++j) {  // L y' = g
+    double y = i == r ? 1.0 : 0.0;
+    for (int j = 0; j < k; ++j) {  // L y' = e_r
         const double yj = lane_value(y, j) * lane_value(rd, j);
         if (i == j) y = yj;
         else if (i > j && on) y = __builtin_fma(-L[i][j], yj, y);
@@ -732,7 +730,31 @@ __global__ void __launch_bounds__(64) k_coarse_solve(int k, int R, const double 
         if (i == j) y = cj;
         else if (i < j) y = __builtin_fma(-L[j][i], cj, y);
     }
-    if (on) c[i * R + r] = y;
+    if (on) Einv[(int64_t)r * k + i] = y;
+}
+
+// c = E^-1 g for each column r (block r): lane i forms sum_j (E^-1)_{ij} g_j
+// in the order of j, with g staged in LDS and the loads of E^-1 issued
+// sixteen at a time.  g[a R + r] and c likewise (k x R).
+__global__ void __launch_bounds__(64) k_coarse_apply(int k, int R, const double *__restrict__ Einv,
+                                                     const double *__restrict__ g,
+                                                     double *__restrict__ c) {
+    __shared__ double gs[64];
+    const int i = threadIdx.x, r = blockIdx.x;
+    if (i < k) gs[i] = g[i * R + r];
+    __syncthreads();
+    if (i >= k) return;
+    double acc = 0.0;
+    int j = 0;
+    for (; j + 16 <= k; j += 16) {
+        double e[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) e[q] = Einv[(int64_t)(j + q) * k + i];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = __builtin_fma(e[q], gs[j + q], acc);
+    }
+    for (; j < k; ++j) acc = __builtin_fma(Einv[(int64_t)j * k + i], gs[j], acc);
+    c[i * R + r] = acc;
 }
 
 // out = M_BD (v - AZ c) + Z c per pixel and column (Eq. m2l), with optional
@@ -1314,6 +1336,11 @@ void chol_small_dev(mm_ctx *ctx, int k, double *E, double *Lc, int *flag) {
     MM_HIP(hipGetLastError());
 }
 
+void coarse_inverse_dev(mm_ctx *ctx, int k, const double *Lc, double *Einv) {
+    k_coarse_inverse<<<k, 64, 0, ctx->stream>>>(k, Lc, Einv);
+    MM_HIP(hipGetLastError());
+}
+
 void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c) {
     const int64_t n = M->n();
     const int k = M->k;
@@ -1325,7 +1352,7 @@ void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, d
         // g[a][r] = sum_i Z[a n + i] v[i R + r]   (Z^T V on MFMA)
         gram_mfma(ctx, n, k, nrhs, M->Z.as<double>(), 1, n, v, nrhs, 1, g);
     }
-    k_coarse_solve<<<nrhs, 64, 0, ctx->stream>>>(k, nrhs, M->Lc.as<double>(), g, c);
+    k_coarse_apply<<<nrhs, 64, 0, ctx->stream>>>(k, nrhs, M->Einv.as<double>(), g, c);
     MM_HIP(hipGetLastError());
 }
 

@@ -222,7 +222,8 @@ struct mm_precond {
     double rcond_min = 0;
     // M_2l
     int32_t k = 0;
-    mm::DBuf Z, AZ, E, Lc;  // Z, AZ: f64[k][n]; E, Lc: f64[k][k] (Lc lower, row-major)
+    // Z, AZ: f64[k][n]; E: f64[k][k]; Einv: E^-1, column r at Einv[r k]
+    mm::DBuf Z, AZ, E, Einv;
     // Arnoldi record
     int32_t arn_m = 0;
     mm::DBuf W;
@@ -297,6 +298,8 @@ void matmul_small_right(mm_ctx *ctx, int64_t n, int kin, int kout, const double 
                         const double *Y, double *Zout);  // Zout = V Y, col-major
 // Cholesky factor Lc of the k x k matrix E; E is symmetrised in place first.
 void chol_small_dev(mm_ctx *ctx, int k, double *E, double *Lc, int *flag);
+// E^-1 (column r at Einv[r k]) from the lower Cholesky factor Lc of E.
+void coarse_inverse_dev(mm_ctx *ctx, int k, const double *Lc, double *Einv);
 void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *out,
                    double *dot_partial, int n_part);
 void m2l_coef_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, double *c);
