@@ -485,9 +485,14 @@ __global__ void __launch_bounds__(BS) k_gemv_t_grp(int64_t n, const double *__re
     const double *w = W + (int64_t)c0 * n;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += BS) {
         const double vi = v[i];
+        // every column's load is issued unconditionally (columns past nc
+        // re-read the last one and are not accumulated), so the GT loads are
+        // in flight together instead of one branch and wait each
+        double x[GT];
 #pragma unroll
-        for (int c = 0; c < GT; ++c)
-            if (c < nc) acc[c] += w[(int64_t)c * n + i] * vi;
+        for (int c = 0; c < GT; ++c) x[c] = w[(int64_t)(c < nc ? c : nc - 1) * n + i];
+#pragma unroll
+        for (int c = 0; c < GT; ++c) acc[c] = c < nc ? acc[c] + x[c] * vi : acc[c];
     }
     __shared__ double sm[BS / 64][GT];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -810,7 +815,32 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
         // whole lines of Z and AZ at once (each sum still runs over q in order)
         double u[3], zc[3], s_az[3] = {0, 0, 0};
         zc[0] = zc[1] = zc[2] = 0;
-        for (int q = 0; q < k; ++q) {
+        int q = 0;
+        // eight columns' loads issued before their sums, so that they are in
+        // flight together (k = 32: four round trips)
+        for (; q + 8 <= k; q += 8) {
+            double az8[8][3], z8[8][3];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double *azq = AZ + (int64_t)(q + t) * n + 3 * j;
+                const double *zq = Z + (int64_t)(q + t) * n + 3 * j;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    az8[t][a] = azq[a];
+                    z8[t][a] = zq[a];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double cq = sc[(q + t) * R + r];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    s_az[a] += az8[t][a] * cq;
+                    zc[a] += z8[t][a] * cq;
+                }
+            }
+        }
+        for (; q < k; ++q) {
             const double cq = sc[q * R + r];
             const double *azq = AZ + (int64_t)q * n + 3 * j;
             const double *zq = Z + (int64_t)q * n + 3 * j;
