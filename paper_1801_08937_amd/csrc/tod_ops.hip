@@ -455,13 +455,45 @@ __global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ p
     for (int d0 = 0; d0 < nf_pad; d0 += CLa) {
         const int cl = nf_pad - d0 < CLa ? nf_pad - d0 : CLa;
         __syncthreads();  // the previous chunk's reads are done
-        for (int k = threadIdx.x; k < cl; k += BS) {
+        // The staging loads are issued eight per thread at a time: each
+        // address is clamped to a valid element (tap 0, or the interval's
+        // first sample) and the value zeroed where it falls outside, so no
+        // load waits behind a branch.  The staged values are the same.
+        int k = threadIdx.x;
+        for (; k + 7 * BS < cl; k += 8 * BS) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int ku = k + u * BS;
+                const int d = d0 + ku - lam;
+                const bool in = d0 + ku < nf;
+                v[u] = c[in ? (d < 0 ? -d : d) : 0];
+                v[u] = in ? v[u] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sf[k + u * BS] = v[u];
+        }
+        for (; k < cl; k += BS) {
             const int d = d0 + k - lam;
             sf[k] = d0 + k < nf ? c[d < 0 ? -d : d] : (T)0;
         }
         const int rows = TL + cl - 1;
         const int64_t w0 = t0 - lam + d0;
-        for (int e = threadIdx.x; e < rows * R; e += BS) {
+        int e = threadIdx.x;
+        for (; e + 7 * BS < rows * R; e += 8 * BS) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int eu = e + u * BS;
+                const int64_t t = w0 + eu / R;
+                const bool in = t >= a && t < b;
+                v[u] = y[(in ? t : a) * R + eu % R];
+                v[u] = in ? v[u] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) sy[e + u * BS] = v[u];
+        }
+        for (; e < rows * R; e += BS) {
             const int64_t t = w0 + e / R;
             sy[e] = (t >= a && t < b) ? y[t * R + e % R] : (T)0;
         }
