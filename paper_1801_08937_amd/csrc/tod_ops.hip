@@ -25,12 +25,21 @@ namespace {
 
 constexpr int BS = 256;
 
+template <typename T>
+__global__ void __launch_bounds__(BS) k_zero(int64_t n, T *__restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n; e += (int64_t)gridDim.x * BS)
+        y[e] = (T)0;
+}
+
 template <typename T, int R>
 __device__ __forceinline__ T p_gather(int32_t j, typename Vec2<T>::type ww,
                                       const double *__restrict__ x, int r) {
-    if (j < 0) return (T)0;
-    const double *xp = x + (int64_t)3 * j * R + r;
-    return (T)xp[0] + ww.x * (T)xp[R] + ww.y * (T)xp[2 * R];
+    // branch-free: an unobserved sample (j < 0) reads pixel 0 and yields 0,
+    // so the gathers of several samples are in flight together (the map is
+    // never empty here)
+    const double *xp = x + (int64_t)3 * (j < 0 ? 0 : j) * R + r;
+    const T v = (T)xp[0] + ww.x * (T)xp[R] + ww.y * (T)xp[2 * R];
+    return j < 0 ? (T)0 : v;
 }
 
 // y = P x.  Each wave step covers G = 64/R consecutive samples x R columns;
@@ -85,10 +94,11 @@ __global__ void __launch_bounds__(BS) k_pack_map(const double *__restrict__ x, i
 template <typename T>
 __device__ __forceinline__ T p_gather4(int32_t j, typename Vec2<T>::type ww,
                                        const double2 *__restrict__ x4) {
-    if (j < 0) return (T)0;
-    const double2 iq = x4[2 * (int64_t)j];
-    const double u = x4[2 * (int64_t)j + 1].x;
-    return (T)iq.x + ww.x * (T)iq.y + ww.y * (T)u;
+    const int64_t jj = j < 0 ? 0 : j;  // branch-free, as p_gather
+    const double2 iq = x4[2 * jj];
+    const double u = x4[2 * jj + 1].x;
+    const T v = (T)iq.x + ww.x * (T)iq.y + ww.y * (T)u;
+    return j < 0 ? (T)0 : v;
 }
 
 template <typename T>
@@ -140,11 +150,13 @@ __global__ void __launch_bounds__(BS) k_pack_map_split(const double *__restrict_
 __device__ __forceinline__ double p_gather_psi(int32_t j, double psi,
                                                const double *__restrict__ xi,
                                                const double2 *__restrict__ xqu) {
-    if (j < 0) return 0.0;
+    const int32_t jj = j < 0 ? 0 : j;  // branch-free, as p_gather
+    const double i0 = xi[jj];
+    const double2 qu = xqu[jj];
     double c, s;
     pol_weights(psi, c, s);
-    const double2 qu = xqu[j];
-    return xi[j] + c * qu.x + s * qu.y;
+    const double v = i0 + c * qu.x + s * qu.y;
+    return j < 0 ? 0.0 : v;
 }
 
 __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__ jpix,
@@ -155,17 +167,31 @@ __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__
     const int64_t step = (int64_t)gridDim.x * BS;
     int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
     // eight samples in flight per thread (measured: 0.70 ms against 0.73 with
-    // four at 1.34e8 samples; sixteen gave no more)
+    // four at 1.34e8 samples; sixteen gave no more): their slots and angles,
+    // then their eight map gathers (from slot 0 where the sample is
+    // unobserved, so that no gather waits behind a branch), then the weights
     for (; t + 7 * step < n; t += 8 * step) {
         int32_t j[8];
-        double a[8];
+        double a[8], i8[8];
+        double2 qu8[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             j[q] = jpix[t + q * step];
             a[q] = psi[t + q * step];
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) y[t + q * step] = p_gather_psi(j[q], a[q], xi, xqu);
+        for (int q = 0; q < 8; ++q) {
+            const int32_t jj = j[q] < 0 ? 0 : j[q];
+            i8[q] = xi[jj];
+            qu8[q] = xqu[jj];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double c, s;
+            pol_weights(a[q], c, s);
+            const double v = i8[q] + c * qu8[q].x + s * qu8[q].y;
+            y[t + q * step] = j[q] < 0 ? 0.0 : v;
+        }
     }
     for (; t < n; t += step) y[t] = p_gather_psi(jpix[t], psi[t], xi, xqu);
 }
@@ -284,7 +310,10 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             ww[q] = wp[64 * (k + q)];
-            zz[q] = tt[q] >= 0 ? z[tt[q]] : (T)0;
+            // a padding entry (-1) reads sample 0 and adds 0: no branch
+            // between the eight gathers
+            const T zq = z[tt[q] < 0 ? 0 : tt[q]];
+            zz[q] = tt[q] >= 0 ? zq : (T)0;
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -564,6 +593,17 @@ void apply_P_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const double *x, v
                  char *scratch) {
     Scope sc(ctx->prof, ctx->stream, "P");
     const int64_t n = p->n_samp;
+    if (p->n_obs == 0) {  // no observed pixel: y = 0 (the gathers assume a pixel 0)
+        const int64_t ne = n * nrhs;
+        if (ne > 0) {
+            if (p->prec == MM_F32)
+                k_zero<float><<<grid_for(ne), BS, 0, ctx->stream>>>(ne, static_cast<float *>(y));
+            else
+                k_zero<double><<<grid_for(ne), BS, 0, ctx->stream>>>(ne, static_cast<double *>(y));
+            MM_HIP(hipGetLastError());
+        }
+        return;
+    }
     if (p->nc != 3) {
         dispatch_r(nrhs, [&](auto RR) {
             constexpr int R = decltype(RR)::value;
