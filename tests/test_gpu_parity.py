@@ -789,3 +789,27 @@ def test_pol_weights_against_numpy(ctx):
         y = host(ctx.apply_P(lp, dev(x)))
         err = float(np.max(np.abs(y - ref)))
         assert err <= 4e-16, (a, err)
+
+
+def test_empty_map_P_writes_zeros(ctx):
+    """No pixel reaches min_hits: the map is empty (n_obs = 0) and P x = 0
+    for every sample (all are unobserved); P^T and A leave nothing to write.
+    The map pointer is valid but addresses no element, as a C caller may pass
+    it."""
+    import torch
+    pix = np.array([0, 1, 2, 3, 0, 1], dtype=np.int32)
+    psi = np.linspace(0.0, 1.0, pix.size)
+    lp = ctx.pointing(dev(pix), dev(psi), 4, 3)
+    assert lp.n == 0
+    from paper_1801_08937_amd.mapmaker import lib
+    buf = torch.zeros(8, dtype=torch.float64, device="cuda")
+    y = torch.full((pix.size,), float("nan"), dtype=torch.float64, device="cuda")
+    # torch gives a zero-element tensor a null pointer, so call the C ABI with
+    # a real buffer of which no element is read
+    assert lib().mm_apply_P(ctx.h, lp.h, 1, buf.data_ptr(), y.data_ptr()) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(y.cpu(), torch.zeros(pix.size, dtype=torch.float64))
+    ln = ctx.noise([0, pix.size], [0], [[1.0, 0.25]], 1)
+    assert lib().mm_apply_A(ctx.h, lp.h, ln.h, 1, buf.data_ptr(), buf.data_ptr() + 32) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(buf.cpu(), torch.zeros(8, dtype=torch.float64))
