@@ -590,9 +590,11 @@ extern "C" mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int3
              "polyfilter: subscans must tile [0, n_samp)");
     std::vector<double> om((size_t)n_subscans);
     int iv = 0;
+    int64_t max_len = 0;
     for (int64_t s2 = 0; s2 < n_subscans; ++s2) {
         const int64_t a = subscan_start[s2], b = subscan_start[s2 + 1];
         MM_CHECK(b > a, MM_E_INVALID, "polyfilter: subscans must be strictly increasing");
+        max_len = std::max(max_len, b - a);
         while (interval_start[iv + 1] <= a) ++iv;
         MM_CHECK(b <= interval_start[iv + 1], MM_E_INVALID,
                  "polyfilter: a subscan crosses an interval boundary");
@@ -606,6 +608,7 @@ extern "C" mm_status mm_polyfilter_build(mm_ctx *ctx, const mm_pointing *p, int3
         nz->half_bw = 0;
         nz->prec = p->prec;
         nz->method = MM_NOISE_POLY;
+        nz->pf_max_len = max_len;
         nz->h_istart.assign(interval_start, interval_start + n_intervals + 1);
         nz->h_fid.resize(n_intervals);
         std::iota(nz->h_fid.begin(), nz->h_fid.end(), 0);

@@ -201,6 +201,7 @@ struct mm_noise {
     // zeros for a subscan fitted exactly) and the flag mask as bits
     int32_t pf_order = 0;
     int64_t pf_n_sub = 0;
+    int64_t pf_max_len = 0;  // longest subscan (picks the apply's register cache)
     mm::DBuf pf_sub, pf_omega, pf_ginv, pf_mask;
     // ground templates (pf_nb bins, 0 = none): each sample's bin, 1 / sum of
     // w per bin, and the bin-sorted samples and weights interleaved per wave

@@ -296,6 +296,38 @@ def test_ground_filter_apply_parity(ctx, order, n_bins):
     np.testing.assert_array_equal(Z[:, 1], z)
 
 
+@pytest.mark.parametrize("lo,hi,n_bins", [(5, 250, 0), (200, 500, 0), (400, 1500, 0),
+                                          (5, 250, 5), (400, 1500, 5)])
+def test_polyfilter_subscan_lengths(ctx, lo, hi, n_bins):
+    """The apply keeps a lane's samples in registers when the longest subscan
+    has at most 256 (4 per lane) or 512 (8 per lane) samples, and streams them
+    otherwise: each regime, with and without ground templates, against the
+    oracle, and a column of a 4-column apply bitwise equal to the single one."""
+    p = synth.random_problem(31, n_side=12, n_samp=30011, n_int=5, half_bw=5, n_filters=2,
+                             flag_frac=0.1)
+    lp = ctx.pointing(dev(p.pix), dev(p.psi), p.n_pix_total, p.min_hits)
+    op = O.pointing_build(p.pix, p.psi, p.n_pix_total, p.min_hits)
+    sub = _subscans(p, lo + hi, lo, hi)
+    assert (np.diff(sub).max() > 256) == (hi > 256)
+    assert (np.diff(sub).max() > 512) == (hi > 512)
+    w = np.random.default_rng(32).uniform(0.5, 2.0, p.n_intervals)
+    if n_bins:
+        gb = _ground_bins(p, 33, n_bins)
+        lf = ctx.polyfilter(lp, p.interval_start, w, sub, 2, dev(gb), n_bins)
+        of = O.polyfilter_build(op, p.interval_start, w, sub, 2, gb, n_bins)
+    else:
+        lf = ctx.polyfilter(lp, p.interval_start, w, sub, 2)
+        of = O.polyfilter_build(op, p.interval_start, w, sub, 2)
+    y = np.random.default_rng(34).standard_normal(p.n_samp)
+    z = host(ctx.noise_apply(lf, dev(y)))
+    ref = O.polyfilter_apply(of, y)
+    assert maxrel(z, ref) <= TOL_OP, maxrel(z, ref)
+    Y = np.random.default_rng(35).standard_normal((p.n_samp, 4))
+    Y[:, 3] = y
+    Z = host(ctx.noise_apply(lf, dev(Y.reshape(-1)), nrhs=4)).reshape(-1, 4)
+    np.testing.assert_array_equal(Z[:, 3], z)
+
+
 def test_ground_filter_operators_mbd_and_fp32(ctx):
     p = synth.random_problem(24, n_side=10, n_samp=20011, n_int=4, half_bw=5, n_filters=2,
                              flag_frac=0.05)
