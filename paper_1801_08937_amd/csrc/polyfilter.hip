@@ -385,15 +385,25 @@ __global__ void __launch_bounds__(BS) k_gb_part(const int64_t *__restrict__ base
     const double *wp = sw + b0 + lane;
     T acc = 0;
     int64_t i = 0;
-    for (; i + 3 < W; i += 4) {
-        int32_t t[4];
-        T v[4];
+    // eight entries in flight: their samples and weights together, then the
+    // eight gathers (a padding entry, -1, reads sample 0 and adds 0, so no
+    // gather waits behind a branch), summed in entry order
+    for (; i + 7 < W; i += 8) {
+        int32_t t[8];
+        double wv[8];
+        T v[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) t[q] = pp[64 * (i + q)];
+        for (int q = 0; q < 8; ++q) {
+            t[q] = pp[64 * (i + q)];
+            wv[q] = wp[64 * (i + q)];
+        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = t[q] >= 0 ? y1[(int64_t)t[q] * R + r] : (T)0;
+        for (int q = 0; q < 8; ++q) {
+            const T g = y1[(int64_t)(t[q] < 0 ? 0 : t[q]) * R + r];
+            v[q] = t[q] >= 0 ? g : (T)0;
+        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc += (T)wp[64 * (i + q)] * v[q];
+        for (int q = 0; q < 8; ++q) acc += (T)wv[q] * v[q];
     }
     for (; i < W; ++i) {
         const int32_t t = pp[64 * i];
