@@ -333,6 +333,9 @@ enum { MM_ARN_STOP_H = 0, MM_ARN_STOP_RESIDUAL = 1 };
  * part; keep the k smallest (k+1 rather than split a complex pair) or, if
  * eps_lambda > 0, all with Re(theta) < eps_lambda; Z = orthonormalised
  * W_m [Re y | Im y]; E = Z^T A Z (FP64 MFMA), Cholesky-factorised on device.
+ * A Z comes from the Arnoldi factorisation B W_m = W_{m+1} Hbar_m (Eq.
+ * factoriz), A W_m = M_BD^-1 W_{m+1} Hbar_m, instead of k applies of A: the
+ * same matrix up to rounding.
  *   mbd       an M_BD handle built for the same pointing and noise
  *   b_seed    [device] f64[n] start vector seed (typically b)
  *   h_history [host] f64[m_max] or NULL: h_{j+1,j} per step

@@ -145,15 +145,10 @@ void precond_rel_res(mm_ctx *ctx, const mm_precond *M, int64_t n, int R, const d
         out[c] = h[R + c] > 0 ? std::sqrt(std::max(h[c], 0.0) / h[R + c]) : 0.0;
 }
 
-// M_2l from Z (device, column-major n x k): AZ, E = Z^T AZ, its Cholesky
-// factor and from it E^-1, on device.
-void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M) {
-    const int64_t n = p->n();
+// The coarse part of M_2l once Z and AZ are on the device (column-major
+// n x k): E = Z^T AZ, its Cholesky factor and from it E^-1.
+static void finish_coarse(mm_ctx *ctx, int64_t n, mm_precond *M) {
     const int k = M->k;
-    M->AZ.alloc(sizeof(double) * n * k);
-    for (int c = 0; c < k; ++c)
-        apply_A_impl(ctx, p, nz, 1, M->Z.as<double>() + (int64_t)c * n,
-                     M->AZ.as<double>() + (int64_t)c * n);
     M->E.alloc(sizeof(double) * k * k);
     M->Einv.alloc(sizeof(double) * k * k);
     gram_mfma(ctx, n, k, k, M->Z.as<double>(), 1, n, M->AZ.as<double>(), 1, n, M->E.as<double>());
@@ -167,6 +162,18 @@ void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precon
     MM_HIP(hipMemcpyAsync(&hf, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     MM_HIP(hipStreamSynchronize(ctx->stream));
     MM_CHECK(!hf, MM_E_COARSE_NOT_SPD, "coarse matrix E = Z^T A Z is not positive definite");
+}
+
+// M_2l from Z (device, column-major n x k): AZ by k applies of A, then the
+// coarse part.
+void finish_m2l(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M) {
+    const int64_t n = p->n();
+    const int k = M->k;
+    M->AZ.alloc(sizeof(double) * n * k);
+    for (int c = 0; c < k; ++c)
+        apply_A_impl(ctx, p, nz, 1, M->Z.as<double>() + (int64_t)c * n,
+                     M->AZ.as<double>() + (int64_t)c * n);
+    finish_coarse(ctx, n, M);
 }
 
 // Device vectors and scalars of a column-batched PCG (Eq. pcg).
@@ -857,9 +864,50 @@ extern "C" mm_status mm_defl_transfer(mm_ctx *ctx, const mm_pointing *p_src,
 // eigenvalue of V^T V below 1e-12 of the largest; finite-precision Lanczos
 // repeats converged Ritz values) are left out before the Cholesky-QR, and kk
 // shrinks accordingly; otherwise a dependent V is an error.
+// AZ from the Arnoldi factorisation (App. A, Eq. factoriz) instead of k
+// applies of A.  With B = M_BD A, B W_m = W_m H_m + r e_m^T, where r =
+// h_{m+1,m} w_{m+1} is the last orthogonalised vector before normalisation,
+// so A W_m = M_BD^-1 (W_m H_m + r e_m^T).  Z = W_m Y T (Y the selected Ritz
+// vectors of H_m, T the orthonormalisation), hence
+//   AZ = M_BD^-1 (W_m (H_m Y T) + r (e_m^T Y T)),
+// one m x k product on the tall basis and, per column, M_BD^-1: the
+// assembled 3 x 3 (or smaller) blocks blk.  Hbar is the (m+1) x m Hessenberg
+// matrix (column-major), YT = Y T (m x k, column-major).
+static void az_from_arnoldi(mm_ctx *ctx, mm_precond *M, const double *W, int m,
+                            const std::vector<double> &Hbar, const std::vector<double> &YT,
+                            int kk, const double *r, const double *blk) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = M->n();
+    std::vector<double> G((size_t)m * kk), g((size_t)kk);
+    for (int c = 0; c < kk; ++c) {
+        for (int i = 0; i < m; ++i) {
+            double acc = 0;
+            for (int j = 0; j < m; ++j) acc += Hbar[(size_t)j * (m + 1) + i] * YT[(size_t)c * m + j];
+            G[(size_t)c * m + i] = acc;
+        }
+        g[(size_t)c] = YT[(size_t)c * m + (m - 1)];
+    }
+    DBuf Gd, gd, U;
+    Gd.alloc(sizeof(double) * G.size());
+    gd.alloc(sizeof(double) * g.size());
+    MM_HIP(hipMemcpyAsync(Gd.ptr, G.data(), sizeof(double) * G.size(), hipMemcpyHostToDevice, s));
+    MM_HIP(hipMemcpyAsync(gd.ptr, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, s));
+    U.alloc(sizeof(double) * n * kk);
+    matmul_small_right(ctx, n, m, kk, W, Gd.as<double>(), U.as<double>());
+    rank1_add(ctx, n, kk, r, gd.as<double>(), U.as<double>());
+    M->AZ.alloc(sizeof(double) * n * kk);
+    for (int c = 0; c < kk; ++c)
+        mbd_apply_dev(ctx, blk, M->n_obs, M->nc, 1, U.as<double>() + (int64_t)c * n,
+                      M->AZ.as<double>() + (int64_t)c * n, nullptr, nullptr, 0);
+    MM_HIP(hipStreamSynchronize(s));  // G and g are host vectors of this frame
+}
+
+// arn_res and blk given (an Arnoldi build): AZ from the factorisation
+// (az_from_arnoldi); otherwise by applies of A.
 static void z_from_ritz(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_precond *M,
                         const double *W, int m, std::vector<double> &Hm, int k,
-                        double eps_lambda, double *theta_out, bool drop_dependent = false) {
+                        double eps_lambda, double *theta_out, bool drop_dependent = false,
+                        const double *arn_res = nullptr, const double *blk = nullptr) {
     hipStream_t s = ctx->stream;
     const int64_t n = p->n();
     std::vector<double> wr(m), wi(m), vr((size_t)m * m), vi((size_t)m * m);
@@ -899,6 +947,20 @@ static void z_from_ritz(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, m
         }
     }
     MM_CHECK(kk >= 1, MM_E_INVALID, "defl: no Ritz vector selected");
+    // T (column-major, kk0 x kk): Z = W_m Y T, accumulated over the steps below
+    const int kk0 = kk;
+    std::vector<double> T((size_t)kk0 * kk0, 0.0);
+    for (int i = 0; i < kk0; ++i) T[(size_t)i * kk0 + i] = 1.0;
+    auto t_times = [&](const std::vector<double> &Rm, int kin, int kout) {
+        std::vector<double> nt((size_t)kk0 * kout, 0.0);
+        for (int c = 0; c < kout; ++c)
+            for (int q = 0; q < kin; ++q) {
+                const double f = Rm[(size_t)c * kin + q];
+                if (f == 0) continue;
+                for (int r2 = 0; r2 < kk0; ++r2) nt[(size_t)c * kk0 + r2] += T[(size_t)q * kk0 + r2] * f;
+            }
+        T.swap(nt);
+    };
     // V = W_m Y, then Cholesky-QR applied twice for an orthonormal Z
     DBuf Yd, V, G;
     Yd.alloc(sizeof(double) * Y.size());
@@ -935,6 +997,7 @@ static void z_from_ritz(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, m
         matmul_small_right(ctx, n, kk, kk2, V.as<double>(), Sd.as<double>(), M->Z.as<double>());
         MM_HIP(hipMemcpyAsync(V.ptr, M->Z.ptr, sizeof(double) * n * kk2, hipMemcpyDeviceToDevice, s));
         MM_HIP(hipStreamSynchronize(s));
+        t_times(S, kk, kk2);
         kk = kk2;
     }
     std::vector<double> g((size_t)kk * kk), rinv((size_t)kk * kk);
@@ -971,11 +1034,23 @@ static void z_from_ritz(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, m
         MM_HIP(hipMemcpyAsync(G.ptr, rinv.data(), sizeof(double) * kk * kk, hipMemcpyHostToDevice, s));
         matmul_small_right(ctx, n, kk, kk, src, G.as<double>(), dst);
         MM_HIP(hipStreamSynchronize(s));
+        t_times(rinv, kk, kk);
     }
     // after two passes the orthonormal basis is in V
     std::swap(M->Z, V);
     M->k = kk;
-    finish_m2l(ctx, p, nz, M);
+    if (arn_res && blk) {
+        std::vector<double> YT((size_t)m * kk, 0.0);
+        for (int c = 0; c < kk; ++c)
+            for (int q = 0; q < kk0; ++q) {
+                const double f = T[(size_t)c * kk0 + q];
+                for (int r2 = 0; r2 < m; ++r2) YT[(size_t)c * m + r2] += Y[(size_t)q * m + r2] * f;
+            }
+        az_from_arnoldi(ctx, M, W, m, M->H, YT, kk, arn_res, blk);
+        finish_coarse(ctx, n, M);
+    } else {
+        finish_m2l(ctx, p, nz, M);
+    }
 }
 
 extern "C" mm_status mm_defl_build(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz,
@@ -1090,7 +1165,8 @@ extern "C" mm_status mm_defl_build_stop(mm_ctx *ctx, const mm_pointing *p, const
         std::vector<double> Hm((size_t)m * m);
         for (int j = 0; j < m; ++j)
             for (int i = 0; i < m; ++i) Hm[(size_t)j * m + i] = H[(size_t)j * (m_max + 1) + i];
-        z_from_ritz(ctx, p, nz, M, W, m, Hm, k, eps_lambda, nullptr);
+        z_from_ritz(ctx, p, nz, M, W, m, Hm, k, eps_lambda, nullptr, false, v.as<double>(),
+                    mbd->blk.ptr ? mbd->blk.as<double>() : nullptr);
         const int kk = M->k;
         if (info) {
             info->m = m;

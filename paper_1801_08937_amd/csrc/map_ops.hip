@@ -40,6 +40,7 @@ __global__ void __launch_bounds__(BS) k_mbd_build(const int32_t *__restrict__ of
                                                   const int32_t *__restrict__ fid,
                                                   const double *__restrict__ band64, int lam,
                                                   int32_t n_obs, double *__restrict__ inv,
+                                                  double *__restrict__ blk,
                                                   double *__restrict__ rcond,
                                                   int *__restrict__ n_bad) {
     const int lane = threadIdx.x & 63;
@@ -97,6 +98,8 @@ __global__ void __launch_bounds__(BS) k_mbd_build(const int32_t *__restrict__ of
     rcond[j] = ok ? rc : 0.0;
     double *o = inv + 6 * j;
     o[0] = i00; o[1] = i01; o[2] = i02; o[3] = i11; o[4] = i12; o[5] = i22;
+    double *q = blk + 6 * j;
+    q[0] = b00; q[1] = b01; q[2] = b02; q[3] = b11; q[4] = b12; q[5] = b22;
 }
 
 // I (NC = 1: B_j = sum c0) and QU (NC = 2: B_j = sum c0 (c, s)(c, s)^T)
@@ -110,6 +113,7 @@ __global__ void __launch_bounds__(BS) k_mbd_build_nc(const int32_t *__restrict__
                                                      const int32_t *__restrict__ fid,
                                                      const double *__restrict__ band64, int lam,
                                                      int32_t n_obs, double *__restrict__ inv,
+                                                     double *__restrict__ blk,
                                                      double *__restrict__ rcond,
                                                      int *__restrict__ n_bad) {
     const int lane = threadIdx.x & 63;
@@ -140,6 +144,7 @@ __global__ void __launch_bounds__(BS) k_mbd_build_nc(const int32_t *__restrict__
     if constexpr (NC == 1) {
         ok = s[0] > 0;
         inv[j] = ok ? 1.0 / s[0] : 0.0;
+        blk[j] = s[0];
         rc = ok ? 1.0 : 0.0;
     } else {
         // Cholesky of [[b00, b01], [b01, b11]], then the inverse
@@ -158,6 +163,10 @@ __global__ void __launch_bounds__(BS) k_mbd_build_nc(const int32_t *__restrict__
         o[0] = i00;
         o[1] = i01;
         o[2] = i11;
+        double *q = blk + 3 * j;
+        q[0] = b00;
+        q[1] = b01;
+        q[2] = b11;
     }
     if (!(rc >= 1e-12)) {
         atomicAdd(n_bad, 1);
@@ -700,6 +709,18 @@ __global__ void k_chol_small(int k, double *__restrict__ E, double *__restrict__
     if (tid == 0) *flag = bad;
 }
 
+// U[c n + i] += g[c] r[i]: a rank-one update of the column-major n x k U.
+__global__ void __launch_bounds__(BS) k_rank1_add(int64_t n, int k, const double *__restrict__ r,
+                                                  const double *__restrict__ g,
+                                                  double *__restrict__ U) {
+    const int64_t tot = n * k;
+    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * BS) {
+        const int64_t c = e / n;
+        U[e] += g[c] * r[e - c * n];
+    }
+}
+
 // Lane j's value of v (j uniform across the wave), as two 32-bit reads.
 __device__ __forceinline__ double lane_value(double v, int j) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -1106,6 +1127,7 @@ void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_pre
     hipStream_t s = ctx->stream;
     const int32_t n_obs = p->n_obs;
     M->inv.alloc(sizeof(double) * packed_sym(p->nc) * (n_obs > 0 ? n_obs : 1));
+    M->blk.alloc(sizeof(double) * packed_sym(p->nc) * (n_obs > 0 ? n_obs : 1));
     DBuf rc, bad, mn;
     rc.alloc(sizeof(double) * (n_obs > 0 ? n_obs : 1));
     bad.alloc(sizeof(int));
@@ -1120,8 +1142,8 @@ void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_pre
                 p->off.as<int32_t>(), p->perm.as<int32_t>(),
                 NC == 2 ? static_cast<const typename Vec2w<T>::type *>(p->ws.ptr) : nullptr,
                 nz->istart.as<int64_t>(), nz->n_int, nz->fid.as<int32_t>(),
-                nz->band64.as<double>(), nz->half_bw, n_obs, M->inv.as<double>(), rc.as<double>(),
-                bad.as<int>());
+                nz->band64.as<double>(), nz->half_bw, n_obs, M->inv.as<double>(),
+                M->blk.as<double>(), rc.as<double>(), bad.as<int>());
         };
         if (p->nc == 1)
             nc_build(0.0, std::integral_constant<int, 1>());
@@ -1134,15 +1156,15 @@ void mbd_build_dev(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, mm_pre
                                                  p->ws.as<float2>(), nz->istart.as<int64_t>(),
                                                  nz->n_int, nz->fid.as<int32_t>(),
                                                  nz->band64.as<double>(), nz->half_bw, n_obs,
-                                                 M->inv.as<double>(), rc.as<double>(),
-                                                 bad.as<int>());
+                                                 M->inv.as<double>(), M->blk.as<double>(),
+                                                 rc.as<double>(), bad.as<int>());
         else
             k_mbd_build<double><<<nb, BS, 0, s>>>(p->off.as<int32_t>(), p->perm.as<int32_t>(),
                                                   p->ws.as<double2>(), nz->istart.as<int64_t>(),
                                                   nz->n_int, nz->fid.as<int32_t>(),
                                                   nz->band64.as<double>(), nz->half_bw, n_obs,
-                                                  M->inv.as<double>(), rc.as<double>(),
-                                                  bad.as<int>());
+                                                  M->inv.as<double>(), M->blk.as<double>(),
+                                                  rc.as<double>(), bad.as<int>());
         k_min_reduce<<<1, BS, 0, s>>>(rc.as<double>(), n_obs, mn.as<double>());
         MM_HIP(hipGetLastError());
     }
@@ -1318,6 +1340,11 @@ void gemv_n_sub(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double 
     Scope sc(ctx->prof, ctx->stream, "gemv");
     MM_CHECK(ncol <= 512, MM_E_INVALID, "gemv: too many columns");
     k_gemv_n_sub<<<grid_for(n, 2048), BS, 0, ctx->stream>>>(n, ncol, W, h, v);
+    MM_HIP(hipGetLastError());
+}
+
+void rank1_add(mm_ctx *ctx, int64_t n, int k, const double *r, const double *g, double *U) {
+    k_rank1_add<<<grid_for(n * k), BS, 0, ctx->stream>>>(n, k, r, g, U);
     MM_HIP(hipGetLastError());
 }
 

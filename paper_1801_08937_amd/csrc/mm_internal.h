@@ -218,8 +218,10 @@ struct mm_precond {
     int32_t nc = 3;  // map components per pixel (the pointing's)
     int64_t n() const { return (int64_t)nc * n_obs; }
     // f64[n_obs][nc (nc + 1) / 2] packed symmetric B_j^-1: (00, 01, 02, 11,
-    // 12, 22) for IQU, (00, 01, 11) for QU, (00) for I
-    mm::DBuf inv;
+    // 12, 22) for IQU, (00, 01, 11) for QU, (00) for I; for M_BD also the
+    // assembled blocks B_j themselves, packed the same way (M_BD^-1, used to
+    // form A Z from the Arnoldi factorisation)
+    mm::DBuf inv, blk;
     double rcond_min = 0;
     // M_2l
     int32_t k = 0;
@@ -295,6 +297,8 @@ void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, 
 void gemv_n_sub(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *h, double *v);
 void scale_copy(mm_ctx *ctx, int64_t n, const double *src, const double *s_dev, double *dst,
                 int invert);
+// U[c n + i] += g[c] r[i] (U column-major n x k; g on the device).
+void rank1_add(mm_ctx *ctx, int64_t n, int k, const double *r, const double *g, double *U);
 void matmul_small_right(mm_ctx *ctx, int64_t n, int kin, int kout, const double *V,
                         const double *Y, double *Zout);  // Zout = V Y, col-major
 // Cholesky factor Lc of the k x k matrix E; E is symmetrised in place first.

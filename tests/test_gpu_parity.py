@@ -813,3 +813,41 @@ def test_empty_map_P_writes_zeros(ctx):
     assert lib().mm_apply_A(ctx.h, lp.h, ln.h, 1, buf.data_ptr(), buf.data_ptr() + 32) == 0
     torch.cuda.synchronize()
     assert torch.equal(buf.cpu(), torch.zeros(8, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("case", ["iqu", "qu", "i", "poly"])
+def test_defl_build_az_from_arnoldi_factorisation(ctx, case):
+    """mm_defl_build forms AZ from its Arnoldi factorisation (App. A, Eq.
+    factoriz: A W_m = M_BD^-1 W_{m+1} Hbar_m) instead of k applies of A.
+    Against the oracle on the exported Z: AZ equals A Z applied directly,
+    E equals Z^T (A Z), the M_2l apply equals the oracle's M_2l built from
+    that Z, and Eq. ident holds (IQU, QU and I pointings; a band weight and
+    the template filter, whose M_BD blocks are not those of A)."""
+    p = synth.config2(n_side=16, grid=(2, 2), samp_per_det=1 << 10, L=1 << 9, half_bw=32)
+    if case in ("iqu", "poly"):
+        lp, ln, op, on = build_both(ctx, p)
+        if case == "poly":
+            sub = np.arange(0, p.n_samp + 1, 32, dtype=np.int64)
+            w = np.ones(p.n_intervals)
+            ln = ctx.polyfilter(lp, p.interval_start, w, sub, 2)
+            on = O.polyfilter_build(op, p.interval_start, w, sub, 2)
+    else:
+        stokes = case.upper()
+        psi = None if stokes == "I" else p.psi
+        lp = ctx.pointing(dev(p.pix), None if psi is None else dev(psi), p.n_pix_total,
+                          p.min_hits, stokes=stokes)
+        ln = ctx.noise(p.interval_start, p.filter_id, p.band, p.half_bw)
+        op = O.pointing_build(p.pix, psi, p.n_pix_total, p.min_hits, stokes)
+        on = O.noise_build(p.interval_start, p.filter_id, p.band, p.half_bw)
+    M = ctx.mbd(lp, ln)
+    b = np.random.default_rng(61).standard_normal(op.n)
+    M2 = ctx.defl_build(lp, ln, M, dev(b), k=8, eps_arn=1e-10, m_max=60)
+    Z, AZ, E = (host(t) for t in M2.export())
+    AZo = np.stack([O.apply_A(op, on, Z[:, c]) for c in range(Z.shape[1])], axis=1)
+    assert maxrel(AZ, AZo) <= 1e-10, maxrel(AZ, AZo)
+    assert maxrel(E, Z.T @ AZo) <= 1e-10, maxrel(E, Z.T @ AZo)
+    OM2 = O.m2l_from_Z(op, on, O.mbd_build(op, on), Z)
+    v = np.random.default_rng(62).standard_normal(op.n)
+    assert maxrel(host(ctx.precond_apply(M2, dev(v))), O.m2l_apply(OM2, v)) <= 1e-9
+    # Eq. ident: M_2l A Z = Z, with A Z applied directly
+    assert rel(host(ctx.precond_apply(M2, dev(AZo[:, 0].copy()))), Z[:, 0]) <= 1e-9
