@@ -78,7 +78,7 @@ typedef enum {
 typedef enum { MM_F64 = 0, MM_F32 = 1 } mm_precision;
 
 /* How N^-1 is applied: AUTO picks the FFT when the bandwidth allows it and
- * half_bw >= 16 (FP64 streams of 2^22 samples or more), >= 64 (FP32 streams
+ * half_bw >= 32 (FP64 streams of 2^22 samples or more), >= 64 (FP32 streams
  * of that length) or >= 128 (shorter streams), the measured crossovers with
  * the direct band; else the direct band.  MM_NOISE_POLY marks a
  * weight built by mm_polyfilter_build (a template filter, not a band). */

@@ -527,11 +527,11 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
         } else if (method == MM_NOISE_AUTO) {
             // measured crossover (direct band vs overlap-save FFT, FP64,
             // 2^20..2^27 samples in 2^16-sample intervals): on streams of 2^22
-            // samples and more the FFT wins from lambda = 16 on (its time
+            // samples and more the FFT wins from lambda = 32 on (its time
             // hardly depends on lambda, the band's grows with it); on shorter
             // ones from 128.  FP32 keeps the earlier crossover at 64.
             const bool long_stream = nz->n_samp >= ((int64_t)1 << 22);
-            const int cross = long_stream ? (prec == MM_F64 ? 16 : 64) : 128;
+            const int cross = long_stream ? (prec == MM_F64 ? 32 : 64) : 128;
             nz->method = (fft_ok && half_bw >= cross) ? MM_NOISE_FFT : MM_NOISE_DIRECT;
         } else {
             nz->method = MM_NOISE_DIRECT;
