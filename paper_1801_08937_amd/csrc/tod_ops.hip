@@ -341,13 +341,22 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
     o[2] = (double)s2;
 }
 
-// x[e] = part[0][e] + part[1][e] + ... in segment order.
+// x[e] = part[0][e] + part[1][e] + ... in segment order; the partials' loads
+// are issued eight at a time (a runtime-length loop would wait for each).
 __global__ void __launch_bounds__(BS) k_pt_sum_parts(const double *__restrict__ part, int32_t S,
                                                      int64_t n3, double *__restrict__ x) {
     for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < n3;
          e += (int64_t)gridDim.x * BS) {
         double acc = part[e];
-        for (int32_t sg = 1; sg < S; ++sg) acc += part[sg * n3 + e];
+        int32_t sg = 1;
+        for (; sg + 7 < S; sg += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = part[(sg + q) * n3 + e];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += v[q];
+        }
+        for (; sg < S; ++sg) acc += part[sg * n3 + e];
         x[e] = acc;
     }
 }
