@@ -271,6 +271,36 @@ def _small_c1_like():
     return p, pt, nz
 
 
+def test_arnoldi_factorisation_gives_AZ():
+    """App. A, Eq. factoriz with B = M_BD A: B W_m = W_{m+1} Hbar_m, so
+    A W_m = M_BD^-1 W_{m+1} Hbar_m with M_BD^-1 the assembled blocks B_j.  For
+    Z = W_m Y R^-1 (Ritz vectors, orthonormalised) A Z then follows from the
+    factorisation alone and equals A Z applied directly: the reading by which
+    AZ of an Arnoldi-built M_2l is formed (R26).  A sign or index slip in the
+    Hessenberg matrix or the basis breaks the first identity."""
+    p, pt, nz = _small_c1_like()
+    M = O.mbd_build(pt, nz)
+    nc = M.blocks.shape[1]
+    b = np.random.default_rng(11).standard_normal(pt.n)
+    res = O.arnoldi(lambda w: O.mbd_apply(M, O.apply_A(pt, nz, w)), O.mbd_apply(M, b), 40, 1e-300)
+    m, W, H = res.m, res.W, res.H
+    assert m == 40 and W.shape[1] == m + 1
+
+    def blocks_apply(V):
+        V = V.reshape(-1, nc, V.shape[-1])
+        return np.einsum("jab,jbk->jak", M.blocks, V).reshape(-1, V.shape[-1])
+    AW = np.stack([O.apply_A(pt, nz, W[:, j]) for j in range(m)], axis=1)
+    AW_fact = blocks_apply(W[:, :m + 1] @ H[:m + 1, :m])
+    assert np.max(np.abs(AW_fact - AW)) <= 1e-10 * np.max(np.abs(AW))
+    theta, Y = O.ritz_select(H[:m, :m], 8)
+    V = W[:, :m] @ Y
+    Z, R = np.linalg.qr(V)
+    YT = Y @ np.linalg.inv(R)
+    AZ_fact = blocks_apply(W[:, :m + 1] @ (H[:m + 1, :m] @ YT))
+    AZ = np.stack([O.apply_A(pt, nz, Z[:, c]) for c in range(Z.shape[1])], axis=1)
+    assert np.max(np.abs(AZ_fact - AZ)) <= 1e-10 * np.max(np.abs(AZ))
+
+
 def test_m2l_identities():
     p, pt, nz = _small_c1_like()
     M = O.mbd_build(pt, nz)
