@@ -154,13 +154,14 @@ static void check(mm_status st, mm_ctx *ctx, const char *what) {
 // Resident footprint of a strategy: per sample, the pointing (compact pixel,
 // weights, permutation, sorted weights, the angle in the FP64 form, the
 // sliced P^T entries with ~10 % padding, P's map-copy slot with a grid);
-// per unknown, M_BD, b and the M_2l reserve (Z, AZ, the Arnoldi basis); and
-// the single-column TOD workspaces of the M_2l builder's context.
+// per unknown, M_BD (its inverse blocks and its assembled blocks), b and the
+// M_2l reserve (Z, AZ, the Arnoldi basis); and the single-column TOD
+// workspaces of the M_2l builder's context.
 static int64_t resident_bytes(const mm_server *srv, int64_t n_samp, int64_t est_n, int64_t te,
                               bool grid) {
     const int64_t per_samp = 4 + 2 * 2 * te + 4 + (te == 4 ? 0 : 8) + 14 + (grid ? 4 : 0);
     return n_samp * per_samp + 2 * n_samp * te +
-           est_n * 8 * (4 + 2 * srv->defl_k + srv->m_max + 2);
+           est_n * 8 * (6 + 2 * srv->defl_k + srv->m_max + 2);
 }
 
 // One lane session of `slots` columns: the session's column vectors (x, r,
