@@ -557,7 +557,9 @@ extern "C" mm_status mm_noise_build(mm_ctx *ctx, int32_t n_intervals,
                                   hipMemcpyHostToDevice, s));
         }
         // direct-band tile counts for every column count, built here so that
-        // applies never modify the handle
+        // applies never modify the handle; one column on a short stream is
+        // cut into small tiles so that it still fills the CUs
+        nz->band_small = nz->n_samp <= (int64_t(1) << 20);
         build_band_tiles(ctx, nz);
         if (nz->method == MM_NOISE_FFT) noise_fft_prepare(ctx, nz, 0);
     } catch (...) {

@@ -189,6 +189,7 @@ struct mm_noise {
     mm::DBuf tile_pref;
     std::vector<int64_t> h_tile_pref;
     int32_t band_cl[7] = {0, 0, 0, 0, 0, 0, 0};  // tuned taps per LDS chunk per log2(nrhs); 0 = default
+    bool band_small = false;  // one column in 512-sample tiles of 64 threads (short streams)
     // FFT: per-filter packed spectrum and block table
     int32_t fft_n = 0;       // real block length
     int32_t fft_valid = 0;   // valid outputs per block
@@ -259,7 +260,7 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
                   char *scratch = nullptr);
 void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z,
                      char *scratch = nullptr);
-int band_tile_len(int nrhs);
+int band_tile_len(int nrhs, bool small);
 void mask_tod_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *tod_rm, void *y,
                   int *nonfinite_flag);
 void pair_sum_diff_dev(mm_ctx *ctx, int64_t n, mm_precision prec, const void *a, const void *b,

@@ -458,15 +458,19 @@ __global__ void __launch_bounds__(BS) k_sum_diff(int64_t n, const T *a, const T 
 // exactly +0.
 constexpr int BT_OPT = 8;
 constexpr int BT_LDS = 65536;  // bytes of LDS per block
+// One column on a short stream (nz->band_small): blocks of 64 threads, tiles
+// of 512 outputs, so that the few tiles of such a stream still spread over
+// the CUs (config 1's 131,072 samples: 256 blocks instead of 64).
+constexpr int BAND_SMALL_NT = 64;
 
-template <typename T, int R>
-__global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ pref, int n_int,
+template <typename T, int R, int NT = BS>
+__global__ void __launch_bounds__(NT) k_band_tiled(const int64_t *__restrict__ pref, int n_int,
                                                    const int64_t *__restrict__ istart,
                                                    const int32_t *__restrict__ fid,
                                                    const T *__restrict__ band, int lam, int CL,
                                                    const T *__restrict__ y, T *__restrict__ z) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int TL = (BS / R) * BT_OPT;
+    constexpr int TL = (NT / R) * BT_OPT;
     const int nf = 2 * lam + 1;
     const int nf_pad = (nf + BT_OPT - 1) / BT_OPT * BT_OPT;
     // CL is a multiple of BT_OPT; rounding it here lets the compiler see
@@ -498,40 +502,40 @@ __global__ void __launch_bounds__(BS) k_band_tiled(const int64_t *__restrict__ p
         // first sample) and the value zeroed where it falls outside, so no
         // load waits behind a branch.  The staged values are the same.
         int k = threadIdx.x;
-        for (; k + 7 * BS < cl; k += 8 * BS) {
+        for (; k + 7 * NT < cl; k += 8 * NT) {
             T v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int ku = k + u * BS;
+                const int ku = k + u * NT;
                 const int d = d0 + ku - lam;
                 const bool in = d0 + ku < nf;
                 v[u] = c[in ? (d < 0 ? -d : d) : 0];
                 v[u] = in ? v[u] : (T)0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) sf[k + u * BS] = v[u];
+            for (int u = 0; u < 8; ++u) sf[k + u * NT] = v[u];
         }
-        for (; k < cl; k += BS) {
+        for (; k < cl; k += NT) {
             const int d = d0 + k - lam;
             sf[k] = d0 + k < nf ? c[d < 0 ? -d : d] : (T)0;
         }
         const int rows = TL + cl - 1;
         const int64_t w0 = t0 - lam + d0;
         int e = threadIdx.x;
-        for (; e + 7 * BS < rows * R; e += 8 * BS) {
+        for (; e + 7 * NT < rows * R; e += 8 * NT) {
             T v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int eu = e + u * BS;
+                const int eu = e + u * NT;
                 const int64_t t = w0 + eu / R;
                 const bool in = t >= a && t < b;
                 v[u] = y[(in ? t : a) * R + eu % R];
                 v[u] = in ? v[u] : (T)0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) sy[e + u * BS] = v[u];
+            for (int u = 0; u < 8; ++u) sy[e + u * NT] = v[u];
         }
-        for (; e < rows * R; e += BS) {
+        for (; e < rows * R; e += NT) {
             const int64_t t = w0 + e / R;
             sy[e] = (t >= a && t < b) ? y[t * R + e % R] : (T)0;
         }
@@ -776,13 +780,15 @@ void apply_PT_dev(mm_ctx *ctx, const mm_pointing *p, int nrhs, const void *z, do
 void noise_fft_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, void *z);
 
 // Tile length of the direct band for R columns.
-int band_tile_len(int nrhs) { return (BS / nrhs) * BT_OPT; }
+int band_tile_len(int nrhs, bool small) {
+    return nrhs == 1 && small ? BAND_SMALL_NT * BT_OPT : (BS / nrhs) * BT_OPT;
+}
 
 // Taps per LDS chunk of the direct band: taps + window rows of R values fit
 // in BT_LDS bytes; a multiple of BT_OPT, at most the padded filter length.
-static int band_chunk(int lam, int R, mm_precision prec) {
+static int band_chunk(int lam, int R, mm_precision prec, bool small) {
     const size_t te = prec == MM_F32 ? sizeof(float) : sizeof(double);
-    const int tl = band_tile_len(R);
+    const int tl = band_tile_len(R, small);
     const int nf_pad = (2 * lam + 1 + BT_OPT - 1) / BT_OPT * BT_OPT;
     int cl = (int)(((int64_t)(BT_LDS / te) - (int64_t)(tl - 1) * R) / (R + 1));
     cl = cl / BT_OPT * BT_OPT;
@@ -805,15 +811,30 @@ void noise_apply_dev(mm_ctx *ctx, const mm_noise *nz, int nrhs, const void *y, v
     }
     Scope sc(ctx->prof, ctx->stream, "Ninv_band");
     const int lam = nz->half_bw;
-    const int tl = band_tile_len(nrhs);
+    const int tl = band_tile_len(nrhs, nz->band_small);
     // tile counts for every column count are built with the noise handle, so
     // an apply never modifies it (handles may be shared across contexts)
     const int li = log2i(nrhs);
     const int64_t *pref = nz->tile_pref.as<int64_t>() + (int64_t)li * (nz->n_int + 1);
     const unsigned n_tiles = (unsigned)nz->h_tile_pref[(size_t)li * (nz->n_int + 1) + nz->n_int];
-    const int cl = nz->band_cl[li] > 0 ? nz->band_cl[li] : band_chunk(lam, nrhs, nz->prec);
+    const int cl =
+        nz->band_cl[li] > 0 ? nz->band_cl[li] : band_chunk(lam, nrhs, nz->prec, nz->band_small);
     const size_t te = nz->prec == MM_F32 ? sizeof(float) : sizeof(double);
     const size_t sm = te * ((size_t)cl + (size_t)(tl + cl - 1) * nrhs);
+    if (nrhs == 1 && nz->band_small) {  // short single streams: 64-thread blocks
+        if (nz->prec == MM_F32)
+            k_band_tiled<float, 1, BAND_SMALL_NT><<<n_tiles, BAND_SMALL_NT, sm, ctx->stream>>>(
+                pref, nz->n_int, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+                nz->band.as<float>(), lam, cl, static_cast<const float *>(y),
+                static_cast<float *>(z));
+        else
+            k_band_tiled<double, 1, BAND_SMALL_NT><<<n_tiles, BAND_SMALL_NT, sm, ctx->stream>>>(
+                pref, nz->n_int, nz->istart.as<int64_t>(), nz->fid.as<int32_t>(),
+                nz->band.as<double>(), lam, cl, static_cast<const double *>(y),
+                static_cast<double *>(z));
+        MM_HIP(hipGetLastError());
+        return;
+    }
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
         if (nz->prec == MM_F32)
@@ -870,7 +891,7 @@ void build_band_tiles(mm_ctx *ctx, mm_noise *nz) {
     const size_t np = (size_t)nz->n_int + 1;
     nz->h_tile_pref.assign(7 * np, 0);
     for (int li = 0; li < 7; ++li) {
-        const int64_t tl = band_tile_len(1 << li);
+        const int64_t tl = band_tile_len(1 << li, nz->band_small);
         int64_t *pr = nz->h_tile_pref.data() + li * np;
         for (int i = 0; i < nz->n_int; ++i)
             pr[i + 1] = pr[i] + (nz->h_istart[i + 1] - nz->h_istart[i] + tl - 1) / tl;
@@ -943,7 +964,7 @@ void autotune(mm_ctx *ctx, mm_pointing *p, mm_noise *nz, int nrhs, int flags, do
         }
         // stage 1: taps per LDS chunk of the direct band
         if (nz->method == MM_NOISE_DIRECT) {
-            const int def = band_chunk(nz->half_bw, nrhs, nz->prec);
+            const int def = band_chunk(nz->half_bw, nrhs, nz->prec, nz->band_small);
             double best = 1e30;
             int best_c = 0;
             for (int div : {1, 2, 4, 8}) {
