@@ -181,7 +181,7 @@ struct PcgWork {
     int R = 1;
     int64_t n = 0;
     int n_part = 1;
-    DBuf r, z, pv, q, part, sc;
+    DBuf r, z, pv, q, part, part2, sc;  // part2: the ||r||^2 partials of an iteration
     PcgDev sd{};
     bool flexible = false;  // Polak-Ribiere beta (sd.rzo holds r'.z_old)
     void alloc(int64_t n_, int R_) {
@@ -194,6 +194,7 @@ struct PcgWork {
         pv.alloc(vb);
         q.alloc(vb);
         part.alloc(sizeof(double) * n_part * R);
+        part2.alloc(sizeof(double) * n_part * R);
         sc.alloc(sizeof(double) * 8 * 64 + sizeof(int) * 3 * 64);
         double *sb = sc.as<double>();
         sd.rho = sb; sd.pq = sb + 64; sd.alpha = sb + 128; sd.beta = sb + 192;
@@ -241,23 +242,23 @@ void pcg_apply_M(mm_ctx *ctx, const mm_precond *M, PcgWork &w, const double *in,
 // One lockstep iteration over the live columns:
 //   q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q; ||r||^2;
 //   z = M r; rho' = r.z; beta = rho'/rho; p = z + beta p.
+// alpha is taken inside the x, r update, and the ||r||^2 test together with
+// rho' and beta in one small launch after z = M r (its partials kept apart).
 void pcg_iteration(mm_ctx *ctx, const mm_pointing *p, const mm_noise *nz, const mm_precond *M,
                    PcgWork &w, double *x) {
     const int R = w.R;
     apply_A_impl(ctx, p, nz, R, w.pv.as<double>(), w.q.as<double>());
     dot_partial_cols(ctx, w.n, R, w.pv.as<double>(), w.q.as<double>(), w.part.as<double>(),
                      w.n_part);
-    pcg_after_pq(ctx, R, w.sd, w.part.as<double>(), w.n_part);
-    pcg_update_xr(ctx, w.n, R, w.sd, w.pv.as<double>(), w.q.as<double>(), x, w.r.as<double>(),
-                  w.part.as<double>(), w.n_part);
-    pcg_after_rn(ctx, R, w.sd, w.part.as<double>(), w.n_part, 1);
+    pcg_update_xr(ctx, w.n, R, w.sd, w.part.as<double>(), w.pv.as<double>(), w.q.as<double>(), x,
+                  w.r.as<double>(), w.part2.as<double>(), w.n_part);
     if (w.flexible) {  // r'.z_old before z is overwritten
         dot_partial_cols(ctx, w.n, R, w.r.as<double>(), w.z.as<double>(), w.part.as<double>(),
                          w.n_part);
         pcg_store_rzo(ctx, R, w.sd, w.part.as<double>(), w.n_part);
     }
     pcg_apply_M(ctx, M, w, w.r.as<double>(), w.z.as<double>());
-    pcg_after_rz(ctx, R, w.sd, w.part.as<double>(), w.n_part, 0);
+    pcg_after_rnrz(ctx, R, w.sd, w.part2.as<double>(), w.part.as<double>(), w.n_part);
     pcg_update_p(ctx, w.n, R, w.sd, w.z.as<double>(), w.pv.as<double>());
 }
 

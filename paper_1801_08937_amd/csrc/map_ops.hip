@@ -322,33 +322,41 @@ __global__ void __launch_bounds__(BS) k_axpby(int64_t n, const double *__restric
         out[e] = b[e] - ax[e];
 }
 
-// alpha = rho / p.q, breakdown if p.q <= 0
-__global__ void k_pcg_alpha(const double *__restrict__ partial, int n_part, int R, PcgDev s) {
-    const int r = blockIdx.x;
-    const double pq = wave_sum_parts(partial, n_part, R, r);
-    if ((threadIdx.x & 63) != 0) return;
-    s.pq[r] = pq;
-    if (s.done[r]) return;
-    if (!(pq > 0.0)) {
-        s.brk[r] = 1;
-        s.done[r] = 1;
-        s.alpha[r] = 0;
-        return;
-    }
-    s.alpha[r] = s.rho[r] / pq;
-}
-
-// x += alpha p; r -= alpha q (live columns); partial ||r||^2
+// alpha = rho / p.q, then x += alpha p; r -= alpha q (live columns);
+// partial ||r||^2.  Every block sums the p.q partials itself, in the same
+// order, so all take the same alpha; block 0 records p.q and alpha.  A column
+// whose p.q is not positive (breakdown) is left as it is here and flagged by
+// k_pcg_rnrz, so that no block reads a flag another block of this launch
+// writes.
 template <int R>
-__global__ void __launch_bounds__(BS) k_pcg_xr(int64_t n, PcgDev s, const double *__restrict__ p,
+__global__ void __launch_bounds__(BS) k_pcg_xr(int64_t n, PcgDev s,
+                                               const double *__restrict__ pq_part, int n_part,
+                                               const double *__restrict__ p,
                                                const double *__restrict__ q,
                                                double *__restrict__ x, double *__restrict__ rr,
                                                double *__restrict__ partial,
                                                int64_t rows_per_block) {
     constexpr int NG = BS / R;
+    __shared__ double s_al[R];
+    __shared__ int s_live[R];
+    for (int c = threadIdx.x >> 6; c < R; c += BS / 64) {
+        const double pq = wave_sum_parts(pq_part, n_part, R, c);
+        if ((threadIdx.x & 63) == 0) {
+            const bool was_done = s.done[c] != 0;
+            const bool lv = !was_done && pq > 0.0;
+            const double al = lv ? s.rho[c] / pq : 0.0;
+            s_al[c] = al;
+            s_live[c] = lv;
+            if (blockIdx.x == 0) {
+                s.pq[c] = pq;
+                if (!was_done) s.alpha[c] = al;
+            }
+        }
+    }
+    __syncthreads();
     const int r = threadIdx.x % R, rg = threadIdx.x / R;
-    const bool live = !s.done[r];
-    const double al = s.alpha[r];
+    const bool live = s_live[r] != 0;
+    const double al = s_al[r];
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
     int64_t i1 = i0 + rows_per_block;
     if (i1 > n) i1 = n;
@@ -393,6 +401,34 @@ __global__ void k_pcg_rz(const double *__restrict__ partial, int n_part, int R, 
         return;
     }
     if (s.done[r]) return;
+    s.beta[r] = s.rzo ? (rz - s.rzo[r]) / s.rho[r] : rz / s.rho[r];
+    s.rho[r] = rz;
+}
+
+// The two scalar steps between the x, r update and the p update of one
+// iteration, in one launch: a breakdown of this iteration's p.q ends the
+// column (its alpha was taken as 0); otherwise ||r||^2 counts the iteration
+// and tests convergence; a live column then takes rho' = r.z and
+// beta = rho'/rho (Polak-Ribiere with r'.z_old when that is kept).
+__global__ void k_pcg_rnrz(const double *__restrict__ part_rn, const double *__restrict__ part_rz,
+                           int n_part, int R, PcgDev s) {
+    const int r = blockIdx.x;
+    const double rn = wave_sum_parts(part_rn, n_part, R, r);
+    const double rz = wave_sum_parts(part_rz, n_part, R, r);
+    if ((threadIdx.x & 63) != 0) return;
+    if (s.done[r]) return;
+    if (!(s.pq[r] > 0.0)) {
+        s.brk[r] = 1;
+        s.done[r] = 1;
+        return;
+    }
+    s.iters[r] += 1;
+    s.rn2[r] = rn;
+    if (s.hist && s.iters[r] < s.hist_len) s.hist[(int64_t)s.iters[r] * R + r] = rn;
+    if (rn <= s.tol2[r] * s.bn2[r]) {
+        s.done[r] = 1;
+        return;
+    }
     s.beta[r] = s.rzo ? (rz - s.rzo[r]) / s.rho[r] : rz / s.rho[r];
     s.rho[r] = rz;
 }
@@ -1233,18 +1269,21 @@ void axpby_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *b, const double 
     MM_HIP(hipGetLastError());
 }
 
-void pcg_after_pq(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part) {
-    k_pcg_alpha<<<nrhs, 64, 0, ctx->stream>>>(partial, n_part, nrhs, s);
+void pcg_after_rnrz(mm_ctx *ctx, int nrhs, PcgDev s, const double *part_rn,
+                    const double *part_rz, int n_part) {
+    k_pcg_rnrz<<<nrhs, 64, 0, ctx->stream>>>(part_rn, part_rz, n_part, nrhs, s);
     MM_HIP(hipGetLastError());
 }
 
-void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *p, const double *q,
-                   double *x, double *r, double *partial, int n_part) {
+void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *pq_part,
+                   const double *p, const double *q, double *x, double *r, double *partial,
+                   int n_part) {
     Scope sc(ctx->prof, ctx->stream, "vec");
     const int64_t rpb = rows_per(n, n_part);
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        k_pcg_xr<R><<<n_part, BS, 0, ctx->stream>>>(n, s, p, q, x, r, partial, rpb);
+        k_pcg_xr<R><<<n_part, BS, 0, ctx->stream>>>(n, s, pq_part, n_part, p, q, x, r, partial,
+                                                    rpb);
     });
     MM_HIP(hipGetLastError());
 }

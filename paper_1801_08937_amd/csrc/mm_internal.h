@@ -320,9 +320,14 @@ struct PcgDev {
 };
 void pcg_init_scalars(mm_ctx *ctx, int nrhs, PcgDev s, double tol);
 void axpby_cols(mm_ctx *ctx, int64_t n, int nrhs, const double *b, const double *Ax, double *r);
-void pcg_after_pq(mm_ctx *ctx, int nrhs, PcgDev s, const double *pq_partial, int n_part);
-void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *p, const double *q,
-                   double *x, double *r, double *partial, int n_part);
+// alpha from the p.q partials, then x += alpha p, r -= alpha q with the
+// ||r||^2 partials (into a buffer other than pq_part)
+void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *pq_part,
+                   const double *p, const double *q, double *x, double *r, double *partial,
+                   int n_part);
+// breakdown flag, iteration count and convergence from ||r||^2, then rho', beta
+void pcg_after_rnrz(mm_ctx *ctx, int nrhs, PcgDev s, const double *part_rn,
+                    const double *part_rz, int n_part);
 void pcg_after_rn(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part,
                   int count_iter);
 void pcg_after_rz(mm_ctx *ctx, int nrhs, PcgDev s, const double *partial, int n_part, int init);

@@ -165,13 +165,14 @@ static int64_t resident_bytes(const mm_server *srv, int64_t n_samp, int64_t est_
 }
 
 // One lane session of `slots` columns: the session's column vectors (x, r,
-// z, p, q) and its single-column buffer, the strategy context's TOD
+// z, p, q) and its single-column buffer, its two sets of per-block partial
+// sums (at most 512 blocks per column), the strategy context's TOD
 // workspaces for `slots` columns, and the sliced P^T's partial maps of the
 // right-hand side.
 static int64_t session_bytes(const mm_server *srv, int64_t n_samp, int64_t n, int64_t n_obs,
                              int64_t te) {
-    return 8 * n * (5 * (int64_t)srv->slots + 1) + 2 * n_samp * te * srv->slots +
-           8 * 3 * n_obs * 64;
+    return 8 * n * (5 * (int64_t)srv->slots + 1) + 2 * 8 * 512 * (int64_t)srv->slots +
+           2 * n_samp * te * srv->slots + 8 * 3 * n_obs * 64;
 }
 
 extern "C" mm_status mm_server_create(int device, int64_t hbm_budget_bytes, int32_t slots,
