@@ -322,12 +322,31 @@ __global__ void __launch_bounds__(BS) k_axpby(int64_t n, const double *__restric
         out[e] = b[e] - ax[e];
 }
 
-// alpha = rho / p.q, then x += alpha p; r -= alpha q (live columns);
-// partial ||r||^2.  Every block sums the p.q partials itself, in the same
-// order, so all take the same alpha; block 0 records p.q and alpha.  A column
-// whose p.q is not positive (breakdown) is left as it is here and flagged by
-// k_pcg_rnrz, so that no block reads a flag another block of this launch
-// writes.
+// Several columns: alpha = rho / p.q in a launch of its own, breakdown if
+// p.q <= 0
+__global__ void k_pcg_alpha(const double *__restrict__ partial, int n_part, int R, PcgDev s) {
+    const int r = blockIdx.x;
+    const double pq = wave_sum_parts(partial, n_part, R, r);
+    if ((threadIdx.x & 63) != 0) return;
+    s.pq[r] = pq;
+    if (s.done[r]) return;
+    if (!(pq > 0.0)) {
+        s.brk[r] = 1;
+        s.done[r] = 1;
+        s.alpha[r] = 0;
+        return;
+    }
+    s.alpha[r] = s.rho[r] / pq;
+}
+
+// x += alpha p; r -= alpha q (live columns); partial ||r||^2.
+// One column (pq_part given): alpha = rho / p.q is taken here.  Every block
+// sums the p.q partials itself, in the same order, so all take the same
+// alpha; block 0 records p.q and alpha.  A column whose p.q is not positive
+// (breakdown) is left as it is and flagged by k_pcg_rnrz, so that no block
+// reads a flag another block of this launch writes.  Several columns
+// (pq_part null): alpha and the flags come from k_pcg_alpha, since 64 such
+// sums per block cost more than the launch they save.
 template <int R>
 __global__ void __launch_bounds__(BS) k_pcg_xr(int64_t n, PcgDev s,
                                                const double *__restrict__ pq_part, int n_part,
@@ -337,26 +356,33 @@ __global__ void __launch_bounds__(BS) k_pcg_xr(int64_t n, PcgDev s,
                                                double *__restrict__ partial,
                                                int64_t rows_per_block) {
     constexpr int NG = BS / R;
-    __shared__ double s_al[R];
-    __shared__ int s_live[R];
-    for (int c = threadIdx.x >> 6; c < R; c += BS / 64) {
-        const double pq = wave_sum_parts(pq_part, n_part, R, c);
-        if ((threadIdx.x & 63) == 0) {
-            const bool was_done = s.done[c] != 0;
-            const bool lv = !was_done && pq > 0.0;
-            const double al = lv ? s.rho[c] / pq : 0.0;
-            s_al[c] = al;
-            s_live[c] = lv;
-            if (blockIdx.x == 0) {
-                s.pq[c] = pq;
-                if (!was_done) s.alpha[c] = al;
+    const int r = threadIdx.x % R, rg = threadIdx.x / R;
+    bool live;
+    double al;
+    if (R == 1 && pq_part) {
+        __shared__ double s_al;
+        __shared__ int s_live;
+        if (threadIdx.x < 64) {
+            const double pq = wave_sum_parts(pq_part, n_part, 1, 0);
+            if (threadIdx.x == 0) {
+                const bool was_done = s.done[0] != 0;
+                const bool lv = !was_done && pq > 0.0;
+                const double a = lv ? s.rho[0] / pq : 0.0;
+                s_al = a;
+                s_live = lv;
+                if (blockIdx.x == 0) {
+                    s.pq[0] = pq;
+                    if (!was_done) s.alpha[0] = a;
+                }
             }
         }
+        __syncthreads();
+        live = s_live != 0;
+        al = s_al;
+    } else {
+        live = !s.done[r];
+        al = s.alpha[r];
     }
-    __syncthreads();
-    const int r = threadIdx.x % R, rg = threadIdx.x / R;
-    const bool live = s_live[r] != 0;
-    const double al = s_al[r];
     const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
     int64_t i1 = i0 + rows_per_block;
     if (i1 > n) i1 = n;
@@ -1280,10 +1306,14 @@ void pcg_update_xr(mm_ctx *ctx, int64_t n, int nrhs, PcgDev s, const double *pq_
                    int n_part) {
     Scope sc(ctx->prof, ctx->stream, "vec");
     const int64_t rpb = rows_per(n, n_part);
+    if (nrhs > 1) {
+        k_pcg_alpha<<<nrhs, 64, 0, ctx->stream>>>(pq_part, n_part, nrhs, s);
+        MM_HIP(hipGetLastError());
+    }
     dispatch_r(nrhs, [&](auto RR) {
         constexpr int R = decltype(RR)::value;
-        k_pcg_xr<R><<<n_part, BS, 0, ctx->stream>>>(n, s, pq_part, n_part, p, q, x, r, partial,
-                                                    rpb);
+        k_pcg_xr<R><<<n_part, BS, 0, ctx->stream>>>(n, s, nrhs == 1 ? pq_part : nullptr, n_part,
+                                                    p, q, x, r, partial, rpb);
     });
     MM_HIP(hipGetLastError());
 }
