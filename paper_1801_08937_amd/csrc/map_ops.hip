@@ -847,11 +847,17 @@ __global__ void __launch_bounds__(64) k_coarse_apply(int k, int R, const double 
 
 // out = M_BD (v - AZ c) + Z c per pixel and column (Eq. m2l), with optional
 // partial sums of dot_with . out.  Z, AZ are column-major n x k, c is k x R.
+// One column with g_part given: each block first forms c = E^-1 Z^T v itself
+// from the partial sums of Z^T v (g_part[b k + a], b < g_parts), summing each
+// column and then forming E^-1 g exactly as k_dot_final and k_coarse_apply
+// do, so every block holds the same c, bitwise that of those two launches.
 template <int R, int NC>
 __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv, int32_t n_obs,
                                                   int k, int64_t n, const double *__restrict__ Z,
                                                   const double *__restrict__ AZ,
                                                   const double *__restrict__ cc,
+                                                  const double *__restrict__ g_part, int g_parts,
+                                                  const double *__restrict__ Einv,
                                                   const double *__restrict__ v,
                                                   double *__restrict__ out,
                                                   const double *__restrict__ dot_with,
@@ -859,7 +865,52 @@ __global__ void __launch_bounds__(BS) k_m2l_final(const double *__restrict__ inv
                                                   int64_t pix_per_block) {
     constexpr int NG = BS / R;
     __shared__ double sc[64 * 64];
-    for (int e = threadIdx.x; e < k * R; e += BS) sc[e] = cc[e];
+    if (R == 1 && g_part) {
+        __shared__ double gs[64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        // wave wv sums columns wv + 4t, eight at a time with their loads in
+        // flight together; each column in the order of wave_sum_parts
+        for (int a0 = wv; a0 < k; a0 += 4 * 8) {
+            double s8[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s8[t] = 0;
+            for (int b = lane; b < g_parts; b += 64) {
+                double x8[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int a = a0 + 4 * t;
+                    x8[t] = g_part[(int64_t)b * k + (a < k ? a : k - 1)];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) s8[t] += x8[t];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                double sm = s8[t];
+#pragma unroll
+                for (int m = 32; m >= 1; m >>= 1) sm += __shfl_xor(sm, m);
+                const int a = a0 + 4 * t;
+                if (lane == 0 && a < k) gs[a] = sm;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < k) {  // c_i = sum_j (E^-1)_{ij} g_j, in the order of j
+            const int i = threadIdx.x;
+            double acc = 0.0;
+            int j = 0;
+            for (; j + 16 <= k; j += 16) {
+                double e[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) e[q] = Einv[(int64_t)(j + q) * k + i];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc = __builtin_fma(e[q], gs[j + q], acc);
+            }
+            for (; j < k; ++j) acc = __builtin_fma(Einv[(int64_t)j * k + i], gs[j], acc);
+            sc[i] = acc;
+        }
+    } else {
+        for (int e = threadIdx.x; e < k * R; e += BS) sc[e] = cc[e];
+    }
     __syncthreads();
     const int r = threadIdx.x % R, rg = threadIdx.x / R;
     const int64_t p0 = (int64_t)blockIdx.x * pix_per_block;
@@ -1389,8 +1440,9 @@ void slot_ctl(mm_ctx *ctx, PcgDev s, int slot, int mode, double tol) {
     MM_HIP(hipGetLastError());
 }
 
-void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, double *h) {
-    Scope sc(ctx->prof, ctx->stream, "gemv");
+// The partial sums of W^T v, ctx->red[b ncol + col] for b < the returned
+// count of row chunks.
+static int gemv_t_parts(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v) {
     const int parts = reduction_parts(n);
     ws_alloc(ctx, ctx->red, sizeof(double) * parts * (ncol > 64 ? ncol : 64));
     // grouped columns measured faster for k = 32 (M_2l), one column per
@@ -1401,6 +1453,13 @@ void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, 
     else
         k_gemv_t<<<dim3(parts, ncol), BS, 0, ctx->stream>>>(n, W, v, ctx->red.as<double>(),
                                                              rows_per(n, parts), ncol);
+    MM_HIP(hipGetLastError());
+    return parts;
+}
+
+void gemv_t(mm_ctx *ctx, int64_t n, int ncol, const double *W, const double *v, double *h) {
+    Scope sc(ctx->prof, ctx->stream, "gemv");
+    const int parts = gemv_t_parts(ctx, n, ncol, W, v);
     k_dot_final<<<ncol, 64, 0, ctx->stream>>>(ctx->red.as<double>(), parts, ncol, h);
     MM_HIP(hipGetLastError());
 }
@@ -1489,7 +1548,17 @@ void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, 
     const int k = M->k;
     ws_alloc(ctx, ctx->scal, sizeof(double) * 64 * 64 + 4096);
     double *c = ctx->scal.as<double>();
-    m2l_coef_dev(ctx, M, nrhs, v, c);
+    // one column: the Z^T v partial sums go straight to the final kernel,
+    // whose blocks each form c = E^-1 Z^T v (two launches fewer)
+    const double *g_part = nullptr;
+    int g_parts = 0;
+    if (nrhs == 1) {
+        Scope sg(ctx->prof, ctx->stream, "gemv");
+        g_parts = gemv_t_parts(ctx, n, k, M->Z.as<double>(), v);
+        g_part = ctx->red.as<double>();
+    } else {
+        m2l_coef_dev(ctx, M, nrhs, v, c);
+    }
     const int parts = partial ? n_part : reduction_parts(n, nrhs);
     const int64_t ppb = rows_per(M->n_obs, parts);
     dispatch_r(nrhs, [&](auto RR) {
@@ -1497,8 +1566,9 @@ void m2l_apply_dev(mm_ctx *ctx, const mm_precond *M, int nrhs, const double *v, 
         auto go = [&](auto NN) {
             constexpr int NC = decltype(NN)::value;
             k_m2l_final<R, NC><<<parts, BS, 0, ctx->stream>>>(
-                M->inv.as<double>(), M->n_obs, k, n, M->Z.as<double>(), M->AZ.as<double>(), c, v,
-                out, partial ? v : nullptr, partial, ppb);
+                M->inv.as<double>(), M->n_obs, k, n, M->Z.as<double>(), M->AZ.as<double>(), c,
+                g_part, g_parts, M->Einv.as<double>(), v, out, partial ? v : nullptr, partial,
+                ppb);
         };
         if (M->nc == 1) go(std::integral_constant<int, 1>());
         else if (M->nc == 2) go(std::integral_constant<int, 2>());
