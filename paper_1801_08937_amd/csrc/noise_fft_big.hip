@@ -106,15 +106,19 @@ __device__ __forceinline__ void twiddle_seq(T (&re)[R], T (&im)[R], T w1r, T w1i
 }
 
 // Store component v (value r at LDS index out(r)), then load v[q] from
-// index tid + TH q.
-template <typename G, typename T, typename F>
+// index tid + TH q.  The barrier that protects the LDS from being
+// overwritten while other threads still read it sits before the stores
+// (PRE), not after the loads, so that a wave goes on to its arithmetic as
+// soon as its own loads are done; the first exchange of a block, with no
+// earlier LDS use, has none.
+template <typename G, typename T, bool PRE = true, typename F>
 __device__ __forceinline__ void exchange(T *__restrict__ sh, T (&v)[16], const F &out, int tid) {
+    if (PRE) __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) sh[padb(out(r, tid))] = v[r];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = sh[padb(tid + G::TH * q)];
-    __syncthreads();
 }
 
 // Radix-16 pass at sub-transform size NS on the thread's butterfly j = tid,
@@ -172,12 +176,14 @@ __device__ __forceinline__ void r_last(T (&re)[16], T (&im)[16],
     }
 }
 
-template <typename G, typename T, int DIR>
+// FIRST_PRE: whether the LDS may still be read by an earlier phase (the
+// inverse transform, after the spectrum step) when the first exchange starts.
+template <typename G, typename T, int DIR, bool FIRST_PRE>
 __device__ __forceinline__ void passes_234(T *__restrict__ sh, T (&re)[16], T (&im)[16],
                                            const typename Vec2T<T>::type *__restrict__ tw,
                                            int tid) {
     // after pass 1 the registers hold outputs for index tid*16 + r
-    exchange<G>(sh, re, R16Out<1>(), tid);
+    exchange<G, T, FIRST_PRE>(sh, re, R16Out<1>(), tid);
     exchange<G>(sh, im, R16Out<1>(), tid);
     r16<G, T, 16, DIR>(re, im, tw, tid);
     exchange<G>(sh, re, R16Out<16>(), tid);
@@ -218,6 +224,7 @@ __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T
                                               int tid) {
     constexpr int H = G::NC / 2;
     T *shr = sh, *shi = sh + H;
+    __syncthreads();  // the forward transform's last LDS loads are done
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         shr[tid + G::TH * q] = re[8 + q];
@@ -247,7 +254,7 @@ __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T
         re[8 + q] = shr[tid + G::TH * q];
         im[8 + q] = shi[tid + G::TH * q];
     }
-    __syncthreads();
+    // the inverse transform's first exchange waits for these loads
 }
 
 // RC = the column count when it is known at compile time (1), else 0 and the
@@ -312,7 +319,7 @@ __global__ void __launch_bounds__(G::TH) __attribute__((amdgpu_waves_per_eu(4)))
         }
     }
     dft16<T, -1>(re, im);
-    passes_234<G, T, -1>(sh, re, im, tw, tid);
+    passes_234<G, T, -1, false>(sh, re, im, tw, tid);
 
     // spectrum: Z'_k = A_k Z_k + B_k (W^k O_k + i W^-k E_k), with the partner
     // Z_{NC-k} exchanged through LDS.  Each phase below works from its own
@@ -327,7 +334,7 @@ __global__ void __launch_bounds__(G::TH) __attribute__((amdgpu_waves_per_eu(4)))
     int tid_i = tid;
     asm volatile("" : "+v"(tid_i));
     dft16<T, 1>(re, im);
-    passes_234<G, T, 1>(sh, re, im, tw, tid_i);
+    passes_234<G, T, 1, true>(sh, re, im, tw, tid_i);
     // registers hold z'_m, m = tid + TH q: outputs 2m and 2m + 1 of the block
     // output 2m - lam of the block is valid in [0, nvalid): the resource
     // spans exactly those outputs, the stores of the others are dropped
