@@ -215,7 +215,7 @@ __device__ __forceinline__ void spectrum_one(T zr, T zi, T pr, T pi,
 // computes both outputs of the pair. It keeps Z'_k and writes Z'_{NC-k} over
 // the partner's slot, which no other thread reads. Then every thread reads
 // its upper half back.  Thread 0's q = 0 takes k = 0 and k = NC/2 (slot 0),
-// each paired with itself.  Half the LDS traffic and three barriers, where
+// each paired with itself.  Half the LDS traffic and two barriers, where
 // moving both components to a pair layout and back takes eight.
 template <typename G, typename T>
 __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T (&im)[16],
@@ -224,11 +224,15 @@ __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T
                                               int tid) {
     constexpr int H = G::NC / 2;
     T *shr = sh, *shi = sh + H;
-    __syncthreads();  // the forward transform's last LDS loads are done
+    // Element u of each half sits at padb(u).  Since H is a power of two
+    // above the swizzle's bits, H + padb(u) = padb(H + u): a thread's stores
+    // go to exactly the LDS words it loaded itself in the forward transform's
+    // last exchange (indices tid + TH q, q < 16), so no barrier is needed
+    // before them.
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        shr[tid + G::TH * q] = re[8 + q];
-        shi[tid + G::TH * q] = im[8 + q];
+        shr[padb(tid + G::TH * q)] = re[8 + q];
+        shi[padb(tid + G::TH * q)] = im[8 + q];
     }
     __syncthreads();
 #pragma unroll
@@ -238,12 +242,12 @@ __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T
         const int k2 = self ? H : G::NC - k1;
         const int u2 = k2 - H;  // LDS slot of k2
         const T z1r = re[q], z1i = im[q];
-        const T z2r = shr[u2], z2i = shi[u2];
+        const T z2r = shr[padb(u2)], z2i = shi[padb(u2)];
         T o1r, o1i, o2r, o2i;
         spectrum_one<T>(z1r, z1i, self ? z1r : z2r, self ? z1i : z2i, twN[k1], abf[k1], o1r, o1i);
         spectrum_one<T>(z2r, z2i, self ? z2r : z1r, self ? z2i : z1i, twN[k2], abf[k2], o2r, o2i);
-        shr[u2] = o2r;
-        shi[u2] = o2i;
+        shr[padb(u2)] = o2r;
+        shi[padb(u2)] = o2i;
         re[q] = o1r;
         im[q] = o1i;
         __builtin_amdgcn_sched_barrier(0);  // keep the table loads of one pair at a time
@@ -251,8 +255,8 @@ __device__ __forceinline__ void spectrum_step(T *__restrict__ sh, T (&re)[16], T
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        re[8 + q] = shr[tid + G::TH * q];
-        im[8 + q] = shi[tid + G::TH * q];
+        re[8 + q] = shr[padb(tid + G::TH * q)];
+        im[8 + q] = shi[padb(tid + G::TH * q)];
     }
     // the inverse transform's first exchange waits for these loads
 }
