@@ -9,6 +9,7 @@
 // rows.  Each column is computed with the same arithmetic and order whatever
 // the other columns hold.
 #include <functional>
+#include <type_traits>
 
 #include "mm_internal.h"
 #include "pol_weights.h"
@@ -305,11 +306,16 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
         int32_t tt[8];
         typename SlRec<T>::type ww[8];
         T zz[8];
+        // the sample indices and weights are read once: non-temporal, so
+        // that they do not push the gathered z lines out of the L2
 #pragma unroll
-        for (int q = 0; q < 8; ++q) tt[q] = pp[64 * (k + q)];
+        for (int q = 0; q < 8; ++q) tt[q] = __builtin_nontemporal_load(pp + 64 * (k + q));
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            ww[q] = wp[64 * (k + q)];
+            if constexpr (std::is_same<T, double>::value)
+                ww[q] = __builtin_nontemporal_load(wp + 64 * (k + q));
+            else
+                ww[q] = wp[64 * (k + q)];
             // a padding entry (-1) reads sample 0 and adds 0: no branch
             // between the eight gathers
             const T zq = z[tt[q] < 0 ? 0 : tt[q]];
