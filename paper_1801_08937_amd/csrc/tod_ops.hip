@@ -175,10 +175,12 @@ __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__
         int32_t j[8];
         double a[8], i8[8];
         double2 qu8[8];
+        // slots and angles are read once, and y written once: non-temporal,
+        // so that they do not push the gathered map lines out of the L2
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            j[q] = jpix[t + q * step];
-            a[q] = psi[t + q * step];
+            j[q] = __builtin_nontemporal_load(jpix + t + q * step);
+            a[q] = __builtin_nontemporal_load(psi + t + q * step);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(BS) k_apply_P1_psi(const int32_t *__restrict__
             double c, s;
             pol_weights(a[q], c, s);
             const double v = i8[q] + c * qu8[q].x + s * qu8[q].y;
-            y[t + q * step] = j[q] < 0 ? 0.0 : v;
+            __builtin_nontemporal_store(j[q] < 0 ? 0.0 : v, y + t + q * step);
         }
     }
     for (; t < n; t += step) y[t] = p_gather_psi(jpix[t], psi[t], xi, xqu);
