@@ -102,6 +102,17 @@ __device__ __forceinline__ T p_gather4(int32_t j, typename Vec2<T>::type ww,
     return j < 0 ? (T)0 : v;
 }
 
+// A once-read stream element loaded with the non-temporal cache policy: a
+// double, or a float2 moved as one 64-bit word.
+__device__ __forceinline__ double nt_load_w(const double *p) {
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ float2 nt_load_w(const float2 *p) {
+    return __builtin_bit_cast(
+        float2, __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p)));
+}
+__device__ __forceinline__ double2 nt_load_w(const double2 *p) { return *p; }
+
 template <typename T>
 __global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpix,
                                                  const typename Vec2<T>::type *__restrict__ w,
@@ -112,13 +123,16 @@ __global__ void __launch_bounds__(BS) k_apply_P1(const int32_t *__restrict__ jpi
     for (; t + 7 * step < n; t += 8 * step) {
         int32_t j[8];
         typename Vec2<T>::type ww[8];
+        // slots and weights are read once, and y written once: non-temporal,
+        // so that they do not push the gathered map lines out of the L2
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            j[q] = jpix[t + q * step];
-            ww[q] = w[t + q * step];
+            j[q] = __builtin_nontemporal_load(jpix + t + q * step);
+            ww[q] = nt_load_w(w + t + q * step);
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) y[t + q * step] = p_gather4<T>(j[q], ww[q], x4);
+        for (int q = 0; q < 8; ++q)
+            __builtin_nontemporal_store(p_gather4<T>(j[q], ww[q], x4), y + t + q * step);
     }
     for (; t < n; t += step) y[t] = p_gather4<T>(jpix[t], w[t], x4);
 }
@@ -314,10 +328,7 @@ __global__ void __launch_bounds__(BS) k_apply_PT_sl(const int64_t *__restrict__ 
         for (int q = 0; q < 8; ++q) tt[q] = __builtin_nontemporal_load(pp + 64 * (k + q));
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            if constexpr (std::is_same<T, double>::value)
-                ww[q] = __builtin_nontemporal_load(wp + 64 * (k + q));
-            else
-                ww[q] = wp[64 * (k + q)];
+            ww[q] = nt_load_w(wp + 64 * (k + q));
             // a padding entry (-1) reads sample 0 and adds 0: no branch
             // between the eight gathers
             const T zq = z[tt[q] < 0 ? 0 : tt[q]];
